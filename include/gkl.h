@@ -1,0 +1,205 @@
+/*
+ * gkl.h -- C ABI of the MI355X (gfx950) Golub-Kahan-Lanczos library for the
+ * top-k principal components of a 2-bit packed genotype matrix.
+ *
+ * Method: Chen, Noack & Edelman, "Fast computation of the principal components
+ * of genotype matrices in Julia", arXiv:1808.03374.
+ *   - Section 3 (Golub-Kahan-Lanczos bidiagonalization): A V_j = U_j B_j with
+ *     B_j upper bidiagonal; top singular triplets from the SVD of B_j.
+ *   - Section 3 "Thick restarting": restart from the leading ordinary Ritz
+ *     vectors to bound memory and roundoff.
+ *   - Section 3 "Choice of reorthogonalization strategy": full
+ *     reorthogonalization by doubly reorthogonalized classical Gram-Schmidt
+ *     (CGS2), optionally with an adaptive second pass; or partial
+ *     reorthogonalization (PRO) with threshold omega (1e-8 in the experiments).
+ *   - Section 3 "Convergence criteria": |sigma - sigma~_i| <= beta_j |P_{j,i}|.
+ *   - Section 5 (conclusions): block Lanczos as the BLAS3 extension, here the
+ *     mixed-precision blocked variant.
+ *
+ * Plain C99. No C++ types cross the ABI, no exception escapes, every fallible
+ * entry point returns a gkl_status and leaves a message in gkl_last_error().
+ *
+ * Matrix and storage format
+ *   G is n individuals x p SNPs.  Storage is SNP-major: column j occupies bytes
+ *   [j*ld, j*ld + ld) with ld >= ceil(n/4); individual i sits in byte
+ *   j*ld + i/4 at bits 2*(i%4)..2*(i%4)+1.  Codes 0/1/2 are allele counts and
+ *   3 is missing.  Bits for i >= n and bytes beyond ceil(n/4) are ignored.
+ *   The operator is the standardized matrix with mean imputation
+ *       A_ij = o_ij * (g_ij - mu_j) * s_j,
+ *   g = code (0 for missing), o = [code != 3], mu_j = c_j / nobs_j with
+ *   c_j = n1_j + 2 n2_j and nobs_j = n - n3_j, s_j = 1/sqrt(mu_j (1 - mu_j/2))
+ *   (binomial scaling), s_j = 0 when nobs_j = 0 or the column is monomorphic.
+ *
+ * Pointers
+ *   Unless stated otherwise every array argument is a DEVICE pointer on the
+ *   current HIP device (for example torch.Tensor.data_ptr() on ROCm).  Output
+ *   arrays are caller-allocated, column-major, FP64.  G is borrowed: it must
+ *   stay valid and unchanged until gkl_destroy.  Contexts are not thread-safe;
+ *   use one context per thread.
+ *
+ * Streams
+ *   All device work of a context runs on options.stream (NULL = the default
+ *   stream).  Every entry point returns after its outputs are written, i.e. it
+ *   is synchronous with respect to the host.
+ */
+#ifndef GKL_H
+#define GKL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gkl_ctx gkl_ctx;
+
+typedef enum gkl_status {
+    GKL_OK = 0,
+    GKL_ERR_INVALID = 1,      /* bad argument; nothing was changed */
+    GKL_ERR_NOMEM = 2,        /* device allocation failed */
+    GKL_ERR_DEVICE = 3,       /* a HIP call or kernel launch failed */
+    GKL_NOT_CONVERGED = 4,    /* max_matvecs reached; best Ritz triplets written */
+    GKL_ERR_BREAKDOWN = 5,    /* no new direction could be found */
+    GKL_ERR_INTERNAL = 6,
+    GKL_ERR_UNSUPPORTED = 7   /* option combination not built */
+} gkl_status;
+
+enum gkl_reorth { GKL_REORTH_FULL = 0, GKL_REORTH_PARTIAL = 1 };
+enum gkl_precision { GKL_PREC_FP64 = 0, GKL_PREC_MIXED = 1 };
+
+/* Options.  Always initialise with gkl_options_default(). */
+typedef struct gkl_options {
+    uint32_t struct_size;     /* sizeof(gkl_options), set by gkl_options_default */
+    int32_t krylov_dim;       /* m, vectors kept before a thick restart; 0 = no restart */
+    int32_t keep;             /* l, Ritz vectors kept at a restart; 0 = k + (m - k)/2 */
+    int32_t precision;        /* gkl_precision */
+    int32_t block_width;      /* b of the mixed blocked variant (1..32); 0 = 16 */
+    int32_t adaptive_cgs2;    /* 1: second Gram-Schmidt pass only when the first pass
+                                 shrank the vector below 1/sqrt(2) of its norm */
+    int32_t check_every;      /* steps between convergence tests without restart; 0 = auto */
+    int32_t max_steps;        /* cap on the basis size without restart; 0 = min(n, p) */
+    double pro_omega;         /* PRO threshold on the orthogonality estimate; 0 = 1e-8 */
+    int64_t max_matvecs;      /* stop with GKL_NOT_CONVERGED after this many; 0 = unlimited */
+    uint64_t seed;            /* start vector seed when v0 is NULL */
+    const double* v0;         /* optional device start vector (p values; p*b when blocked) */
+    int64_t ld_bytes;         /* bytes per SNP column of G; 0 = ceil(n/4) */
+    void* stream;             /* hipStream_t; NULL = default stream */
+    int32_t trace;            /* 1: record a per-step trace (gkl_get_trace) */
+    int32_t verbose;          /* 1: progress lines on stderr */
+} gkl_options;
+
+/* Run statistics (host struct). */
+typedef struct gkl_info {
+    int64_t matvecs;          /* products A v or A^T u; a block product counts b */
+    int64_t passes_over_G;    /* times the packed matrix was streamed */
+    int64_t steps;            /* Lanczos steps (block steps in the blocked variant) */
+    int64_t restarts;
+    int64_t reorths;          /* Gram-Schmidt reorthogonalizations performed */
+    int32_t nconv;            /* leading Ritz values meeting the tolerance */
+    int32_t converged;        /* 1 when all k met the tolerance */
+    double sum_residual_est;  /* sum_i beta_j |P_{j,i}| over the k returned values */
+    double max_residual_rel;  /* max_i residual_i / sigma_1 */
+    double solve_ms;
+    double create_ms;
+} gkl_info;
+
+void gkl_options_default(gkl_options* opt);
+const char* gkl_status_string(gkl_status s);
+/* Last error message of ctx; ctx == NULL gives the calling thread's last
+ * message from gkl_create / gkl_create_ex / gkl_create_batched. */
+const char* gkl_last_error(const gkl_ctx* ctx);
+
+/*
+ * gkl_create / gkl_create_ex
+ *   Validate the arguments, compute the column statistics (counts, mu, s) on the
+ *   device and allocate the solver workspace for a top-k solve.
+ *   G      device, p*ld bytes, SNP-major 2-bit codes (see above), borrowed.
+ *   n, p   individuals and SNPs, both >= 1.
+ *   k      singular triplets wanted, 1 <= k <= min(n, p).
+ *   tol    relative tolerance: stop when beta_j |P_{j,i}| <= tol * sigma~_1 for
+ *          every i < k; must be > 0.
+ *   reorth gkl_reorth.
+ *   out    receives the context; unchanged on failure.
+ *   Errors: GKL_ERR_INVALID (n, p < 1; k out of range; tol <= 0; m != 0 and
+ *   m <= k; ld < ceil(n/4); NULL G or out; bad option values), GKL_ERR_NOMEM,
+ *   GKL_ERR_DEVICE.  On any error nothing is allocated.
+ */
+gkl_status gkl_create(const uint8_t* G, int64_t n, int64_t p, int32_t k, double tol,
+                      int32_t reorth, gkl_ctx** out);
+gkl_status gkl_create_ex(const uint8_t* G, int64_t n, int64_t p, int32_t k, double tol,
+                         int32_t reorth, const gkl_options* opt, gkl_ctx** out);
+
+/*
+ * gkl_solve
+ *   Run the Lanczos iteration and write the top-k triplets.
+ *   sigma  device, k values, descending.
+ *   U      device, n x k column-major with leading dimension ldu >= n (scores).
+ *   V      device, p x k column-major with leading dimension ldv >= p (loadings).
+ *   info   host, may be NULL.
+ *   Sign rule: the largest-magnitude entry of each V column is positive
+ *   (lowest index on ties); the U column is flipped with it.
+ *   Returns GKL_NOT_CONVERGED (outputs still written) when max_matvecs ran out.
+ *   A context can be solved repeatedly; each solve starts from the start vector.
+ */
+gkl_status gkl_solve(gkl_ctx* ctx, double* sigma, double* U, int64_t ldu, double* V,
+                     int64_t ldv, gkl_info* info);
+
+/* Release everything owned by ctx.  NULL-safe. */
+void gkl_destroy(gkl_ctx* ctx);
+
+/*
+ * Batched solves of many uneven matrices (per-chromosome PCAs).
+ *   count     number of problems (1..1024).
+ *   G, n, p   host arrays of count device pointers / sizes; each problem as above.
+ *   The context solves all problems together: every Lanczos half-step of all
+ *   still-running problems is one persistent kernel launch, and problems drop
+ *   out as they converge.  Options apply to every problem (FP64, full reorth).
+ */
+gkl_status gkl_create_batched(int32_t count, const uint8_t* const* G, const int64_t* n,
+                              const int64_t* p, int32_t k, double tol, int32_t reorth,
+                              const gkl_options* opt, gkl_ctx** out);
+/*   sigma, U, V: host arrays of count device pointers; ldu, ldv host arrays.
+ *   infos: host array of count gkl_info, may be NULL. */
+gkl_status gkl_solve_batched(gkl_ctx* ctx, double* const* sigma, double* const* U,
+                             const int64_t* ldu, double* const* V, const int64_t* ldv,
+                             gkl_info* infos);
+
+/* ---------------- kernel-level entry points on an existing context ----------
+ * Used by the parity tests and the bench; same conventions as above.  All
+ * pointers are device pointers; every call is synchronous. */
+
+/* Column statistics: count (int64, p), nobs (int64, p), mean (p), inv_sd (p).
+ * Any pointer may be NULL to skip it. */
+gkl_status gkl_column_stats(gkl_ctx* ctx, int64_t* count, int64_t* nobs, double* mean,
+                            double* inv_sd);
+/* Unpack G to an n x p column-major int8 matrix; missing becomes -1. */
+gkl_status gkl_unpack(gkl_ctx* ctx, int8_t* out);
+/* y = A v (v: p values, y: n values), FP64. */
+gkl_status gkl_matvec(gkl_ctx* ctx, const double* v, double* y);
+/* z = A^T u (u: n values, z: p values), FP64. */
+gkl_status gkl_rmatvec(gkl_ctx* ctx, const double* u, double* z);
+/* Y = A W for b columns (W: p x b, Y: n x b, column-major, leading dims p and n),
+ * through the split-BF16 MFMA path (W split into bf16 hi + lo, FP32 accumulate per
+ * K-chunk, FP64 across chunks, exact FP64 centring and missing-value terms). */
+gkl_status gkl_matmat_mixed(gkl_ctx* ctx, const double* W, int32_t b, double* Y);
+/* Z = A^T X for b columns (X: n x b, Z: p x b), split-BF16 MFMA path. */
+gkl_status gkl_rmatmat_mixed(gkl_ctx* ctx, const double* X, int32_t b, double* Z);
+/* Per-step trace of the last solve, as rows of GKL_TRACE_FIELDS doubles:
+ *   step, alpha, beta, reorth_left, reorth_right, restart, max_residual_rel.
+ * buf is HOST memory of cap doubles; *written receives the number of rows. */
+#define GKL_TRACE_FIELDS 7
+gkl_status gkl_get_trace(gkl_ctx* ctx, double* buf, int64_t cap, int64_t* written);
+
+/*
+ * gkl_dense_svd -- the small dense SVD used for Ritz extraction, exposed for
+ * testing: B (m x m, column-major, device) = P diag(S) Q^T with S descending.
+ * m <= 96.  P, Q: m x m column-major device; S: m device.  stream may be NULL.
+ */
+gkl_status gkl_dense_svd(const double* B, int32_t m, double* P, double* S, double* Q,
+                         void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GKL_H */

@@ -1,0 +1,88 @@
+// Internal helpers shared by the gfx950 kernels and the host engine.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/gkl.h"
+
+namespace gkl {
+
+constexpr int kWave = 64;          // CDNA wavefront width
+constexpr int kMaxKrylov = 96;     // largest projected matrix the in-LDS SVD handles
+
+// ---------------------------------------------------------------------------
+// Error plumbing: internal code throws gkl::Error, the ABI layer converts it.
+// ---------------------------------------------------------------------------
+struct Error {
+    gkl_status status;
+    std::string msg;
+};
+
+[[noreturn]] void fail(gkl_status s, const std::string& msg);
+void check_hip(hipError_t e, const char* what);
+
+#define GKL_HIP(call) ::gkl::check_hip((call), #call)
+#define GKL_LAUNCH_CHECK(what) ::gkl::check_hip(hipGetLastError(), what)
+
+// ---------------------------------------------------------------------------
+// Device helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v)
+{
+    // butterfly over the 64 lanes; every lane ends with the same total and the
+    // order of additions is fixed, so results are deterministic
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+__device__ __forceinline__ int64_t wave_sum_i64(int64_t v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// Sum of one double per thread over a block of blockDim.x threads (multiple of
+// 64, at most 1024).  Result valid in every thread.  scratch: >= 16 doubles.
+__device__ __forceinline__ double block_sum(double v, double* scratch)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    const int nw = blockDim.x / kWave;
+    v = wave_sum(v);
+    __syncthreads();
+    if (lane == 0) scratch[wid] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < nw; ++w) t += scratch[w];
+    return t;
+}
+
+// "Last block reduces" handshake for two-stage deterministic reductions: each
+// block writes its partials, then calls this; exactly one block (the last to
+// arrive) gets true and may read every block's partials.  The counter is
+// reset by that block so the kernel can be replayed.
+__device__ __forceinline__ bool last_block_arrived(unsigned int* counter, unsigned int nblocks)
+{
+    __shared__ bool is_last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned int prev = atomicAdd(counter, 1u);
+        is_last = (prev == nblocks - 1);
+    }
+    __syncthreads();
+    if (is_last) {
+        __threadfence();
+        if (threadIdx.x == 0) atomicExch(counter, 0u);
+    }
+    return is_last;
+}
+
+inline unsigned int ceil_div(int64_t a, int64_t b) { return (unsigned int)((a + b - 1) / b); }
+
+}  // namespace gkl

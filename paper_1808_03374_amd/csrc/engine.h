@@ -1,0 +1,107 @@
+// Host-side solver state (internal).
+#pragma once
+
+#include <array>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+namespace gkl {
+
+// Every device allocation of a context; freed together.
+struct DeviceArena {
+    std::vector<void*> ptrs;
+    size_t total = 0;
+    void* alloc(size_t bytes);
+    DeviceArena() = default;
+    DeviceArena(const DeviceArena&) = delete;
+    DeviceArena& operator=(const DeviceArena&) = delete;
+    ~DeviceArena();
+};
+
+// One packed genotype matrix with its statistics and matvec scratch.
+struct Problem {
+    DeviceArena arena;
+    int64_t n = 0, p = 0, ld = 0;
+    hipStream_t stream = nullptr;
+    Packed packed;
+    ColStats st{};
+    MatvecWork mvw;
+    void setup(const uint8_t* G, int64_t n, int64_t p, int64_t ld, hipStream_t s);
+};
+
+// ||r|| into *out (no scaling).
+void launch_norm(const double* r, int64_t len, double* out, OrthoWork& w, hipStream_t s);
+
+struct MixedState;   // blocked split-BF16 solver (k_mixed / mixed.hip)
+struct BatchState;   // batched persistent solver (batched.hip)
+bool mixed_supported();
+void destroy_mixed(MixedState* m);
+void destroy_batch(BatchState* b);
+
+}  // namespace gkl
+
+struct gkl_ctx {
+    gkl::Problem prob;
+    gkl_options opt{};
+    int k = 0;
+    double tol = 0.0;
+    int reorth = 0;
+    double omega = 1e-8;
+    double root_maxdim = 1.0;
+    double noise_scale = 0.0;
+    int krylov = 0;      // 0 = no restart
+    int maxm = 0;        // basis capacity (left columns)
+    int keep = 0;        // Ritz vectors kept at a restart
+    bool batched = false;
+    std::string last_error;
+    std::vector<std::array<double, GKL_TRACE_FIELDS>> trace;
+    gkl_info info{};
+    double create_ms = 0.0;
+
+    // device solver state (FP64 path)
+    double* U = nullptr;
+    double* V = nullptr;
+    double* tmp = nullptr;
+    double* scal = nullptr;
+    double* alpha = nullptr;
+    double* beta = nullptr;
+    double* theta = nullptr;
+    double* rho = nullptr;
+    double* norm_est = nullptr;
+    int* flags = nullptr;   // [0] left breakdown [1] right breakdown [2..5] PRO
+                            // [6] Gram-Schmidt passes [7] scratch flag [8] nconv
+    gkl::RitzOut ritz{};
+    double* svd_scratch = nullptr;
+    gkl::ProState pro{};
+    gkl::OrthoWork ow;
+    static constexpr size_t kScalarsPerCol = 4;
+    size_t kScalars = 0;
+
+    // loop state
+    int nlock = 0;
+    int ritz_m = -1;
+    bool exhausted = false;
+    uint64_t breakdown_draws = 1;
+
+    gkl::MixedState* mixed = nullptr;
+    gkl::BatchState* batch = nullptr;
+
+    gkl_ctx() = default;
+    ~gkl_ctx();
+
+    void allocate_solver();
+    void record(int step, bool restart_flag, double res_rel);
+    int read_flag(const int* dflag);
+    void left_step(int j);
+    void right_step(int j);
+    void launch_normalize_only(double* r, int64_t len, double* out);
+    void handle_breakdown(bool left, int j);
+    int check_convergence(int m);
+    void restart(int m);
+    void finalize(int m, double* sigma, double* Uo, int64_t ldu, double* Vo, int64_t ldv);
+    gkl_status solve_fp64(double* sigma, double* Uo, int64_t ldu, double* Vo, int64_t ldv);
+    void setup_mixed();
+    gkl_status solve_mixed(double* sigma, double* Uo, int64_t ldu, double* Vo, int64_t ldv);
+};

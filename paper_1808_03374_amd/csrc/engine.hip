@@ -1,0 +1,640 @@
+// Host engine of the GKL solver and the C ABI (include/gkl.h).
+//
+// The engine owns the device state of one problem (internal copy of the packed
+// matrix, column statistics, Krylov bases, projected-matrix scalars) and drives
+// the kernels in the order of the Golub-Kahan-Lanczos recurrence (Section 3 of
+// the paper):
+//     p = A v_j - beta_{j-1} u_{j-1};  reorthogonalise;  alpha_j = ||p||; u_j = p/alpha_j
+//     r = A^T u_j - alpha_j v_j;       reorthogonalise;  beta_j  = ||r||; v_{j+1} = r/beta_j
+// with full CGS2 or partial reorthogonalisation, convergence tests on the SVD of
+// the projected matrix, and thick restarts from the leading ordinary Ritz
+// vectors.  Every numerical step runs in a kernel; the host only sequences the
+// launches and reads back small control values (breakdown flags, the number of
+// converged Ritz values).
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <string>
+#include <vector>
+
+#include "engine.h"
+
+namespace gkl {
+
+[[noreturn]] void fail(gkl_status s, const std::string& msg) { throw Error{s, msg}; }
+
+void check_hip(hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return;
+    const gkl_status st = (e == hipErrorOutOfMemory) ? GKL_ERR_NOMEM : GKL_ERR_DEVICE;
+    fail(st, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------------------
+// Device memory owned by a context
+// ---------------------------------------------------------------------------
+void* DeviceArena::alloc(size_t bytes)
+{
+    if (bytes == 0) bytes = 8;
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(e == hipErrorOutOfMemory ? GKL_ERR_NOMEM : GKL_ERR_DEVICE,
+             "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    ptrs.push_back(p);
+    total += bytes;
+    return p;
+}
+
+DeviceArena::~DeviceArena()
+{
+    for (void* p : ptrs) (void)hipFree(p);
+}
+
+// ---------------------------------------------------------------------------
+// Problem setup
+// ---------------------------------------------------------------------------
+void Problem::setup(const uint8_t* G, int64_t n_, int64_t p_, int64_t ld_, hipStream_t s)
+{
+    n = n_;
+    p = p_;
+    ld = ld_;
+    stream = s;
+    packed.n = n;
+    packed.p = p;
+    packed.ldp = ((((n + 3) / 4) + 255) / 256) * 256;
+    uint8_t* Gi = static_cast<uint8_t*>(arena.alloc((size_t)packed.ldp * (size_t)p));
+    launch_repack(G, n, p, ld, Gi, packed.ldp, s);
+    packed.G = Gi;
+    st.count = static_cast<int64_t*>(arena.alloc(sizeof(int64_t) * p));
+    st.nobs = static_cast<int64_t*>(arena.alloc(sizeof(int64_t) * p));
+    st.n3 = static_cast<int64_t*>(arena.alloc(sizeof(int64_t) * p));
+    st.mean = static_cast<double*>(arena.alloc(sizeof(double) * p));
+    st.inv_sd = static_cast<double*>(arena.alloc(sizeof(double) * p));
+    launch_colstats(G, n, p, ld, st, s);
+    mvw.partial_elems = matvec_partial_elems(packed);
+    mvw.partial = static_cast<double*>(arena.alloc(sizeof(double) * mvw.partial_elems));
+    mvw.ncounters = matvec_counters(packed);
+    mvw.counters = static_cast<unsigned int*>(arena.alloc(sizeof(unsigned int) * mvw.ncounters));
+    GKL_HIP(hipMemsetAsync(mvw.counters, 0, sizeof(unsigned int) * mvw.ncounters, s));
+}
+
+}  // namespace gkl
+
+using namespace gkl;
+
+// ---------------------------------------------------------------------------
+// Solver state
+// ---------------------------------------------------------------------------
+void gkl_ctx::allocate_solver()
+{
+    const int64_t n = prob.n, p = prob.p;
+    DeviceArena& A = prob.arena;
+    const int cols = maxm;
+    U = static_cast<double*>(A.alloc(sizeof(double) * (size_t)n * cols));
+    V = static_cast<double*>(A.alloc(sizeof(double) * (size_t)p * (cols + 1)));
+    const int keep_alloc = std::max(keep, 1);
+    tmp = static_cast<double*>(A.alloc(sizeof(double) * (size_t)std::max(n, p) * keep_alloc));
+    kScalars = 4 * (size_t)(cols + 1) + 2;
+    scal = static_cast<double*>(A.alloc(sizeof(double) * kScalars));
+    alpha = scal;
+    beta = alpha + (cols + 1);
+    theta = beta + (cols + 1);
+    rho = theta + (cols + 1);
+    norm_est = rho + (cols + 1);
+    flags = static_cast<int*>(A.alloc(sizeof(int) * 16));
+    const size_t mm = (size_t)cols * cols;
+    ritz.B = static_cast<double*>(A.alloc(sizeof(double) * mm));
+    ritz.P = static_cast<double*>(A.alloc(sizeof(double) * mm));
+    ritz.Q = static_cast<double*>(A.alloc(sizeof(double) * mm));
+    ritz.S = static_cast<double*>(A.alloc(sizeof(double) * cols));
+    ritz.res = static_cast<double*>(A.alloc(sizeof(double) * cols));
+    ritz.nconv = flags + 8;
+    svd_scratch = svd_fits_lds(cols)
+                      ? nullptr
+                      : static_cast<double*>(A.alloc(sizeof(double) * svd_scratch_elems(cols)));
+    pro.mu = static_cast<double*>(A.alloc(sizeof(double) * (cols + 1)));
+    pro.nu = static_cast<double*>(A.alloc(sizeof(double) * (cols + 2)));
+    pro.flag_left = flags + 2;
+    pro.flag_right = flags + 3;
+    pro.force = flags + 4;
+    const int64_t maxlen = std::max(n, p);
+    ow.partial_elems = ortho_partial_elems(maxlen, cols + 1);
+    ow.partial = static_cast<double*>(A.alloc(sizeof(double) * ow.partial_elems));
+    ow.counters = static_cast<unsigned int*>(A.alloc(sizeof(unsigned int) * 4));
+    ow.h = static_cast<double*>(A.alloc(sizeof(double) * (3 * (size_t)(cols + 2) + 8)));
+    hipStream_t s = prob.stream;
+    GKL_HIP(hipMemsetAsync(ow.counters, 0, sizeof(unsigned int) * 4, s));
+    GKL_HIP(hipMemsetAsync(scal, 0, sizeof(double) * kScalars, s));
+    GKL_HIP(hipMemsetAsync(flags, 0, sizeof(int) * 16, s));
+}
+
+static thread_local std::string g_create_error;
+
+static gkl_status set_error(gkl_ctx* ctx, gkl_status s, const std::string& msg)
+{
+    if (ctx) ctx->last_error = msg;
+    else g_create_error = msg;
+    return s;
+}
+
+void gkl_ctx::record(int step, bool restart_flag, double res_rel)
+{
+    if (!opt.trace) return;
+    double a = 0.0, b = 0.0;
+    int fl[2] = {1, 1};
+    GKL_HIP(hipMemcpyAsync(&a, alpha + step, sizeof(double), hipMemcpyDeviceToHost, prob.stream));
+    GKL_HIP(hipMemcpyAsync(&b, beta + step, sizeof(double), hipMemcpyDeviceToHost, prob.stream));
+    if (reorth == GKL_REORTH_PARTIAL)
+        GKL_HIP(hipMemcpyAsync(fl, pro.flag_left, 2 * sizeof(int), hipMemcpyDeviceToHost,
+                               prob.stream));
+    GKL_HIP(hipStreamSynchronize(prob.stream));
+    trace.push_back({(double)step, a, b, (double)fl[0], (double)fl[1], restart_flag ? 1.0 : 0.0,
+                     res_rel});
+}
+
+int gkl_ctx::read_flag(const int* dflag)
+{
+    int h = 0;
+    GKL_HIP(hipMemcpyAsync(&h, dflag, sizeof(int), hipMemcpyDeviceToHost, prob.stream));
+    GKL_HIP(hipStreamSynchronize(prob.stream));
+    return h;
+}
+
+// Left half-step j: U(:, j) from v_j.
+void gkl_ctx::left_step(int j)
+{
+    hipStream_t s = prob.stream;
+    const int64_t n = prob.n, p = prob.p;
+    double* uj = U + (int64_t)j * n;
+    const double* vj = V + (int64_t)j * p;
+    if (j > 0 && j == nlock) {
+        launch_matvec(prob.packed, prob.st, vj, uj, nullptr, nullptr, prob.mvw, s);
+        launch_gemv_n_sub(U, n, n, nlock, rho, uj, s);
+    } else if (j > 0) {
+        launch_matvec(prob.packed, prob.st, vj, uj, beta + (j - 1), U + (int64_t)(j - 1) * n,
+                      prob.mvw, s);
+    } else {
+        launch_matvec(prob.packed, prob.st, vj, uj, nullptr, nullptr, prob.mvw, s);
+    }
+    info.matvecs += 1;
+    info.passes_over_G += 1;
+    if (j > 0) {
+        if (reorth == GKL_REORTH_PARTIAL) {
+            launch_normalize_only(uj, n, alpha + j);
+            launch_pro_left(alpha, beta, theta, rho, nlock, j, omega, noise_scale, norm_est, pro, s);
+            launch_cgs2(U, n, n, j, uj, pro.flag_left, opt.adaptive_cgs2, flags + 6, ow, s);
+        } else {
+            launch_cgs2(U, n, n, j, uj, nullptr, opt.adaptive_cgs2, flags + 6, ow, s);
+        }
+    }
+    launch_normalize(uj, n, uj, alpha + j, norm_est, root_maxdim, flags + 0, ow, s);
+    if (read_flag(flags + 0)) handle_breakdown(true, j);
+}
+
+// Right half-step j: V(:, j+1) from u_j.
+void gkl_ctx::right_step(int j)
+{
+    hipStream_t s = prob.stream;
+    const int64_t n = prob.n, p = prob.p;
+    const double* uj = U + (int64_t)j * n;
+    double* vn = V + (int64_t)(j + 1) * p;
+    launch_rmatvec(prob.packed, prob.st, uj, vn, alpha + j, V + (int64_t)j * p, prob.mvw, s);
+    info.matvecs += 1;
+    info.passes_over_G += 1;
+    if (reorth == GKL_REORTH_PARTIAL) {
+        launch_normalize_only(vn, p, beta + j);
+        launch_pro_right(alpha, beta, theta, rho, nlock, j, omega, noise_scale, norm_est, pro, s);
+        launch_cgs2(V, p, p, j + 1, vn, pro.flag_right, opt.adaptive_cgs2, flags + 6, ow, s);
+    } else {
+        launch_cgs2(V, p, p, j + 1, vn, nullptr, opt.adaptive_cgs2, flags + 6, ow, s);
+    }
+    launch_normalize(vn, p, vn, beta + j, norm_est, root_maxdim, flags + 1, ow, s);
+    if (read_flag(flags + 1)) handle_breakdown(false, j);
+}
+
+// ||r|| into *out without scaling (PRO needs alpha_j / beta_j before deciding).
+void gkl_ctx::launch_normalize_only(double* r, int64_t len, double* out)
+{
+    // norm into out; flag ignored; scaling skipped because nrm_out is written
+    // with the norm and the scale kernel would divide -- so use a scratch copy
+    launch_norm(r, len, out, ow, prob.stream);
+}
+
+// Breakdown: the new vector has (numerically) no component outside the current
+// basis.  Record a zero scalar and continue with a random direction made
+// orthogonal to the basis (or stop if the basis already spans the space).
+void gkl_ctx::handle_breakdown(bool left, int j)
+{
+    hipStream_t s = prob.stream;
+    const int64_t len = left ? prob.n : prob.p;
+    const int ncols = left ? j : j + 1;
+    double* Q = left ? U : V;
+    double* r = left ? U + (int64_t)j * prob.n : V + (int64_t)(j + 1) * prob.p;
+    double* scalar = left ? alpha + j : beta + j;
+    if (ncols >= len) {
+        exhausted = true;
+        return;
+    }
+    for (int attempt = 0; attempt < 3; ++attempt) {
+        launch_gaussian(r, len, opt.seed ^ 0xB4EA4D0ull, (uint64_t)(breakdown_draws++), s);
+        launch_cgs2(Q, len, len, ncols, r, nullptr, 0, flags + 6, ow, s);
+        double* tmp_nrm = ow.h + 3 * (maxm + 2) + 4;
+        launch_normalize(r, len, r, tmp_nrm, norm_est, root_maxdim, flags + 7, ow, s);
+        if (!read_flag(flags + 7)) {
+            GKL_HIP(hipMemsetAsync(scalar, 0, sizeof(double), s));
+            info.reorths += 1;
+            if (reorth == GKL_REORTH_PARTIAL) launch_pro_reset(pro, maxm, 2, s);
+            return;
+        }
+    }
+    fail(GKL_ERR_BREAKDOWN, "Lanczos breakdown: no new direction orthogonal to the basis");
+}
+
+int gkl_ctx::check_convergence(int m)
+{
+    launch_ritz(alpha, beta, theta, rho, nlock, m, k, tol, ritz, svd_scratch, prob.stream);
+    ritz_m = m;
+    return read_flag(ritz.nconv);
+}
+
+void gkl_ctx::restart(int m)
+{
+    hipStream_t s = prob.stream;
+    const int64_t n = prob.n, p = prob.p;
+    if (ritz_m != m) check_convergence(m);
+    // V(:, 0:l) = V(:, 0:m) Q(:, 0:l); v_l = v_m
+    launch_gemm_tall(V, p, p, m, ritz.Q, m, keep, tmp, p, s);
+    GKL_HIP(hipMemcpyAsync(V, tmp, sizeof(double) * (size_t)p * keep, hipMemcpyDeviceToDevice, s));
+    GKL_HIP(hipMemcpyAsync(V + (int64_t)keep * p, V + (int64_t)m * p, sizeof(double) * (size_t)p,
+                           hipMemcpyDeviceToDevice, s));
+    // U(:, 0:l) = U(:, 0:m) P(:, 0:l)
+    launch_gemm_tall(U, n, n, m, ritz.P, m, keep, tmp, n, s);
+    GKL_HIP(hipMemcpyAsync(U, tmp, sizeof(double) * (size_t)n * keep, hipMemcpyDeviceToDevice, s));
+    launch_restart_scalars(ritz.S, ritz.P, m, beta + (m - 1), keep, theta, rho, s);
+    nlock = keep;
+    ritz_m = -1;
+    info.restarts += 1;
+    if (reorth == GKL_REORTH_PARTIAL) launch_pro_reset(pro, maxm, 2, s);
+}
+
+void gkl_ctx::finalize(int m, double* sigma, double* Uo, int64_t ldu, double* Vo, int64_t ldv)
+{
+    hipStream_t s = prob.stream;
+    const int64_t n = prob.n, p = prob.p;
+    if (ritz_m != m) check_convergence(m);
+    const int kk = std::min(k, m);
+    GKL_HIP(hipMemcpyAsync(sigma, ritz.S, sizeof(double) * kk, hipMemcpyDeviceToDevice, s));
+    launch_gemm_tall(U, n, n, m, ritz.P, m, kk, Uo, ldu, s);
+    launch_gemm_tall(V, p, p, m, ritz.Q, m, kk, Vo, ldv, s);
+    launch_sign_fix(Uo, ldu, n, Vo, ldv, p, kk, s);
+    std::vector<double> res(kk), sig(1);
+    GKL_HIP(hipMemcpyAsync(res.data(), ritz.res, sizeof(double) * kk, hipMemcpyDeviceToHost, s));
+    GKL_HIP(hipMemcpyAsync(sig.data(), ritz.S, sizeof(double), hipMemcpyDeviceToHost, s));
+    GKL_HIP(hipStreamSynchronize(s));
+    double sum = 0.0, mx = 0.0;
+    for (int i = 0; i < kk; ++i) {
+        sum += res[i];
+        mx = std::max(mx, sig[0] > 0 ? res[i] / sig[0] : 0.0);
+    }
+    info.sum_residual_est = sum;
+    info.max_residual_rel = mx;
+}
+
+gkl_status gkl_ctx::solve_fp64(double* sigma, double* Uo, int64_t ldu, double* Vo, int64_t ldv)
+{
+    hipStream_t s = prob.stream;
+    const int64_t p = prob.p;
+    // start vector
+    if (opt.v0) GKL_HIP(hipMemcpyAsync(V, opt.v0, sizeof(double) * p, hipMemcpyDeviceToDevice, s));
+    else launch_gaussian(V, p, opt.seed, 0, s);
+    GKL_HIP(hipMemsetAsync(scal, 0, sizeof(double) * kScalars, s));
+    launch_normalize(V, p, V, tmp, norm_est, root_maxdim, flags + 1, ow, s);
+    GKL_HIP(hipMemsetAsync(norm_est, 0, sizeof(double), s));
+    if (reorth == GKL_REORTH_PARTIAL) launch_pro_reset(pro, maxm, 0, s);
+    nlock = 0;
+    ritz_m = -1;
+    exhausted = false;
+    breakdown_draws = 1;
+    int j = 0;
+    int last_check = 0;
+    int nconv = 0;
+    const int64_t maxbasis = std::min(prob.n, prob.p);
+    const int check_every = opt.check_every > 0 ? opt.check_every : (krylov > 0 ? 0 : 5);
+    bool converged = false;
+    while (true) {
+        left_step(j);
+        if (exhausted) { ++j; break; }
+        right_step(j);
+        ++j;
+        const bool full = (j == maxm) || (j >= maxbasis) || exhausted;
+        bool checked = false;
+        if (j >= k && (full || (check_every > 0 && j - last_check >= check_every))) {
+            nconv = check_convergence(j);
+            last_check = j;
+            checked = true;
+            info.nconv = nconv;
+            if (nconv >= k) { converged = true; }
+        }
+        if (opt.trace) {
+            double rr = NAN;
+            if (checked) {
+                double r = 0.0, s0 = 0.0;
+                GKL_HIP(hipMemcpy(&s0, ritz.S, sizeof(double), hipMemcpyDeviceToHost));
+                std::vector<double> res(k);
+                GKL_HIP(hipMemcpy(res.data(), ritz.res, sizeof(double) * k, hipMemcpyDeviceToHost));
+                for (int i = 0; i < k; ++i) r = std::max(r, s0 > 0 ? res[i] / s0 : 0.0);
+                rr = r;
+            }
+            record(j - 1, false, rr);
+        }
+        if (converged) break;
+        if (opt.max_matvecs > 0 && info.matvecs >= opt.max_matvecs) break;
+        if (j >= maxbasis || exhausted) break;
+        if (j == maxm) {
+            if (krylov > 0) {
+                restart(j);
+                j = nlock;
+                last_check = j;
+                if (opt.trace && !trace.empty()) trace.back()[5] = 1.0;
+            } else {
+                break;
+            }
+        }
+    }
+    info.steps = j;
+    finalize(j, sigma, Uo, ldu, Vo, ldv);
+    int passes = 0;
+    GKL_HIP(hipMemcpy(&passes, flags + 6, sizeof(int), hipMemcpyDeviceToHost));
+    info.reorths += passes;
+    info.converged = converged ? 1 : 0;
+    info.nconv = converged ? k : nconv;
+    return converged ? GKL_OK : GKL_NOT_CONVERGED;
+}
+
+gkl_ctx::~gkl_ctx()
+{
+    gkl::destroy_mixed(mixed);
+    gkl::destroy_batch(batch);
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+void gkl_options_default(gkl_options* o)
+{
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->struct_size = sizeof(gkl_options);
+    o->pro_omega = 1e-8;
+    o->block_width = 16;
+    o->adaptive_cgs2 = 0;
+    o->seed = 0x5EEDull;
+}
+
+const char* gkl_status_string(gkl_status s)
+{
+    switch (s) {
+    case GKL_OK: return "ok";
+    case GKL_ERR_INVALID: return "invalid argument";
+    case GKL_ERR_NOMEM: return "out of device memory";
+    case GKL_ERR_DEVICE: return "device error";
+    case GKL_NOT_CONVERGED: return "not converged";
+    case GKL_ERR_BREAKDOWN: return "Lanczos breakdown";
+    case GKL_ERR_INTERNAL: return "internal error";
+    case GKL_ERR_UNSUPPORTED: return "unsupported option combination";
+    }
+    return "unknown status";
+}
+
+const char* gkl_last_error(const gkl_ctx* ctx)
+{
+    return ctx ? ctx->last_error.c_str() : g_create_error.c_str();
+}
+
+gkl_status gkl_create(const uint8_t* G, int64_t n, int64_t p, int32_t k, double tol,
+                      int32_t reorth, gkl_ctx** out)
+{
+    gkl_options o;
+    gkl_options_default(&o);
+    return gkl_create_ex(G, n, p, k, tol, reorth, &o, out);
+}
+
+static gkl_status validate(const uint8_t* G, int64_t n, int64_t p, int32_t k, double tol,
+                           int32_t reorth, const gkl_options* o, gkl_ctx** out)
+{
+    if (!out) return set_error(nullptr, GKL_ERR_INVALID, "out is NULL");
+    if (!G) return set_error(nullptr, GKL_ERR_INVALID, "G is NULL");
+    if (!o) return set_error(nullptr, GKL_ERR_INVALID, "options is NULL");
+    if (o->struct_size != sizeof(gkl_options))
+        return set_error(nullptr, GKL_ERR_INVALID, "options.struct_size mismatch (ABI version)");
+    if (n < 1 || p < 1) return set_error(nullptr, GKL_ERR_INVALID, "n and p must be >= 1");
+    if (k < 1 || (int64_t)k > std::min(n, p))
+        return set_error(nullptr, GKL_ERR_INVALID, "k must lie in [1, min(n, p)]");
+    if (!(tol > 0.0) || !isfinite(tol)) return set_error(nullptr, GKL_ERR_INVALID, "tol must be > 0");
+    if (reorth != GKL_REORTH_FULL && reorth != GKL_REORTH_PARTIAL)
+        return set_error(nullptr, GKL_ERR_INVALID, "reorth must be GKL_REORTH_FULL or _PARTIAL");
+    if (o->krylov_dim < 0 || (o->krylov_dim > 0 && o->krylov_dim <= k))
+        return set_error(nullptr, GKL_ERR_INVALID, "krylov_dim must be 0 or > k");
+    if (o->krylov_dim > kMaxSvd) return set_error(nullptr, GKL_ERR_INVALID, "krylov_dim too large");
+    if (o->keep < 0 || (o->krylov_dim > 0 && o->keep > 0 && (o->keep < k || o->keep >= o->krylov_dim)))
+        return set_error(nullptr, GKL_ERR_INVALID, "keep must lie in [k, krylov_dim)");
+    if (o->ld_bytes != 0 && o->ld_bytes < (n + 3) / 4)
+        return set_error(nullptr, GKL_ERR_INVALID, "ld_bytes < ceil(n/4)");
+    if (o->precision != GKL_PREC_FP64 && o->precision != GKL_PREC_MIXED)
+        return set_error(nullptr, GKL_ERR_INVALID, "unknown precision");
+    if (o->block_width < 0 || o->block_width > 32)
+        return set_error(nullptr, GKL_ERR_INVALID, "block_width must lie in [0, 32]");
+    if (o->max_steps < 0 || o->max_steps > kMaxSvd || o->check_every < 0 || o->max_matvecs < 0)
+        return set_error(nullptr, GKL_ERR_INVALID, "bad max_steps / check_every / max_matvecs");
+    if (o->pro_omega < 0.0) return set_error(nullptr, GKL_ERR_INVALID, "pro_omega must be >= 0");
+    return GKL_OK;
+}
+
+gkl_status gkl_create_ex(const uint8_t* G, int64_t n, int64_t p, int32_t k, double tol,
+                         int32_t reorth, const gkl_options* o, gkl_ctx** out)
+{
+    gkl_status v = validate(G, n, p, k, tol, reorth, o, out);
+    if (v != GKL_OK) return v;
+    if (o->precision == GKL_PREC_MIXED && !gkl::mixed_supported())
+        return set_error(nullptr, GKL_ERR_UNSUPPORTED, "mixed precision path not built");
+    gkl_ctx* ctx = nullptr;
+    try {
+        auto t0 = std::chrono::steady_clock::now();
+        ctx = new gkl_ctx();
+        ctx->opt = *o;
+        ctx->k = k;
+        ctx->tol = tol;
+        ctx->reorth = reorth;
+        ctx->omega = o->pro_omega > 0.0 ? o->pro_omega : 1e-8;
+        hipStream_t s = static_cast<hipStream_t>(o->stream);
+        const int64_t ld = o->ld_bytes ? o->ld_bytes : (n + 3) / 4;
+        ctx->prob.setup(G, n, p, ld, s);
+        ctx->root_maxdim = sqrt((double)std::max(n, p));
+        ctx->noise_scale = 2.220446049250313e-16 * ctx->root_maxdim;
+        ctx->krylov = o->krylov_dim;
+        const int64_t mn = std::min(n, p);
+        if (ctx->krylov > 0) {
+            ctx->maxm = (int)std::min<int64_t>(ctx->krylov, mn);
+            ctx->keep = o->keep > 0 ? o->keep : k + (ctx->krylov - k) / 2;
+            ctx->keep = std::min(ctx->keep, ctx->maxm - 1);
+            if (ctx->maxm <= k) ctx->krylov = 0;   // the whole space fits: no restart needed
+        } else {
+            ctx->maxm = (int)std::min<int64_t>(o->max_steps > 0 ? o->max_steps : 512, mn);
+            ctx->keep = 0;
+        }
+        if (ctx->maxm < k) fail(GKL_ERR_INVALID, "basis smaller than k");
+        if (o->precision == GKL_PREC_MIXED) ctx->setup_mixed();
+        else ctx->allocate_solver();
+        GKL_HIP(hipStreamSynchronize(s));
+        ctx->create_ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        *out = ctx;
+        return GKL_OK;
+    } catch (const Error& e) {
+        delete ctx;
+        return set_error(nullptr, e.status, e.msg);
+    } catch (const std::bad_alloc&) {
+        delete ctx;
+        return set_error(nullptr, GKL_ERR_NOMEM, "host allocation failed");
+    } catch (...) {
+        delete ctx;
+        return set_error(nullptr, GKL_ERR_INTERNAL, "unexpected exception in gkl_create");
+    }
+}
+
+gkl_status gkl_solve(gkl_ctx* ctx, double* sigma, double* U, int64_t ldu, double* V, int64_t ldv,
+                     gkl_info* info)
+{
+    if (!ctx) return set_error(nullptr, GKL_ERR_INVALID, "ctx is NULL");
+    if (ctx->batched) return set_error(ctx, GKL_ERR_INVALID, "use gkl_solve_batched for this ctx");
+    if (!sigma || !U || !V) return set_error(ctx, GKL_ERR_INVALID, "NULL output pointer");
+    if (ldu < ctx->prob.n || ldv < ctx->prob.p)
+        return set_error(ctx, GKL_ERR_INVALID, "ldu < n or ldv < p");
+    try {
+        auto t0 = std::chrono::steady_clock::now();
+        ctx->info = gkl_info{};
+        ctx->trace.clear();
+        gkl_status st = ctx->opt.precision == GKL_PREC_MIXED
+                            ? ctx->solve_mixed(sigma, U, ldu, V, ldv)
+                            : ctx->solve_fp64(sigma, U, ldu, V, ldv);
+        GKL_HIP(hipStreamSynchronize(ctx->prob.stream));
+        ctx->info.solve_ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        ctx->info.create_ms = ctx->create_ms;
+        if (info) *info = ctx->info;
+        if (st == GKL_NOT_CONVERGED) ctx->last_error = "tolerance not met within the matvec budget";
+        return st;
+    } catch (const Error& e) {
+        return set_error(ctx, e.status, e.msg);
+    } catch (...) {
+        return set_error(ctx, GKL_ERR_INTERNAL, "unexpected exception in gkl_solve");
+    }
+}
+
+void gkl_destroy(gkl_ctx* ctx)
+{
+    if (!ctx) return;
+    (void)hipStreamSynchronize(ctx->prob.stream);
+    delete ctx;
+}
+
+gkl_status gkl_column_stats(gkl_ctx* ctx, int64_t* count, int64_t* nobs, double* mean,
+                            double* inv_sd)
+{
+    if (!ctx || ctx->batched) return set_error(ctx, GKL_ERR_INVALID, "bad ctx");
+    try {
+        hipStream_t s = ctx->prob.stream;
+        const size_t p = (size_t)ctx->prob.p;
+        const ColStats& st = ctx->prob.st;
+        if (count) GKL_HIP(hipMemcpyAsync(count, st.count, 8 * p, hipMemcpyDeviceToDevice, s));
+        if (nobs) GKL_HIP(hipMemcpyAsync(nobs, st.nobs, 8 * p, hipMemcpyDeviceToDevice, s));
+        if (mean) GKL_HIP(hipMemcpyAsync(mean, st.mean, 8 * p, hipMemcpyDeviceToDevice, s));
+        if (inv_sd) GKL_HIP(hipMemcpyAsync(inv_sd, st.inv_sd, 8 * p, hipMemcpyDeviceToDevice, s));
+        GKL_HIP(hipStreamSynchronize(s));
+        return GKL_OK;
+    } catch (const Error& e) {
+        return set_error(ctx, e.status, e.msg);
+    }
+}
+
+gkl_status gkl_unpack(gkl_ctx* ctx, int8_t* out)
+{
+    if (!ctx || ctx->batched || !out) return set_error(ctx, GKL_ERR_INVALID, "bad argument");
+    try {
+        hipStream_t s = ctx->prob.stream;
+        launch_unpack(ctx->prob.packed.G, ctx->prob.n, ctx->prob.p, ctx->prob.packed.ldp, out, s);
+        GKL_HIP(hipStreamSynchronize(s));
+        return GKL_OK;
+    } catch (const Error& e) {
+        return set_error(ctx, e.status, e.msg);
+    }
+}
+
+gkl_status gkl_matvec(gkl_ctx* ctx, const double* v, double* y)
+{
+    if (!ctx || ctx->batched || !v || !y) return set_error(ctx, GKL_ERR_INVALID, "bad argument");
+    try {
+        hipStream_t s = ctx->prob.stream;
+        launch_matvec(ctx->prob.packed, ctx->prob.st, v, y, nullptr, nullptr, ctx->prob.mvw, s);
+        GKL_HIP(hipStreamSynchronize(s));
+        return GKL_OK;
+    } catch (const Error& e) {
+        return set_error(ctx, e.status, e.msg);
+    }
+}
+
+gkl_status gkl_rmatvec(gkl_ctx* ctx, const double* u, double* z)
+{
+    if (!ctx || ctx->batched || !u || !z) return set_error(ctx, GKL_ERR_INVALID, "bad argument");
+    try {
+        hipStream_t s = ctx->prob.stream;
+        launch_rmatvec(ctx->prob.packed, ctx->prob.st, u, z, nullptr, nullptr, ctx->prob.mvw, s);
+        GKL_HIP(hipStreamSynchronize(s));
+        return GKL_OK;
+    } catch (const Error& e) {
+        return set_error(ctx, e.status, e.msg);
+    }
+}
+
+gkl_status gkl_get_trace(gkl_ctx* ctx, double* buf, int64_t cap, int64_t* written)
+{
+    if (!ctx || !written || (cap > 0 && !buf)) return set_error(ctx, GKL_ERR_INVALID, "bad argument");
+    const int64_t rows = std::min<int64_t>((int64_t)ctx->trace.size(), cap / GKL_TRACE_FIELDS);
+    for (int64_t r = 0; r < rows; ++r)
+        for (int f = 0; f < GKL_TRACE_FIELDS; ++f) buf[r * GKL_TRACE_FIELDS + f] = ctx->trace[r][f];
+    *written = rows;
+    return GKL_OK;
+}
+
+gkl_status gkl_dense_svd(const double* B, int32_t m, double* P, double* S, double* Q, void* stream)
+{
+    if (!B || !P || !S || !Q || m < 1 || m > kMaxSvd)
+        return set_error(nullptr, GKL_ERR_INVALID, "bad argument to gkl_dense_svd");
+    try {
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        double* scratch = nullptr;
+        if (!svd_fits_lds(m))
+            GKL_HIP(hipMalloc(&scratch, sizeof(double) * svd_scratch_elems(m)));
+        try {
+            launch_dense_svd(B, m, P, S, Q, scratch, s);
+            GKL_HIP(hipStreamSynchronize(s));
+        } catch (...) {
+            if (scratch) (void)hipFree(scratch);
+            throw;
+        }
+        if (scratch) GKL_HIP(hipFree(scratch));
+        return GKL_OK;
+    } catch (const Error& e) {
+        return set_error(nullptr, e.status, e.msg);
+    }
+}
+
+}  // extern "C"

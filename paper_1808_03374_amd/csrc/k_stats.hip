@@ -1,0 +1,151 @@
+// Column statistics and unpack of the 2-bit packed genotype matrix (gfx950).
+//
+// The paper leaves preprocessing unspecified (Table 2 reports only its time);
+// the operator this library applies centres each SNP by its observed mean and
+// scales it by 1/sqrt(2 f (1 - f)), f = mean/2, with missing entries imputed by
+// the mean.  Counts are exact integers; mean and scale follow one fixed order of
+// correctly rounded IEEE operations, so they are reproducible bit for bit.
+#include "kernels.h"
+
+namespace gkl {
+
+// Counts of codes 1, 2, 3 in one 32-bit word holding 16 codes; `valid` low codes
+// are real individuals (the rest is padding and ignored).
+__device__ __forceinline__ void count_word(uint32_t w, int valid, int64_t& c1, int64_t& c2,
+                                           int64_t& c3)
+{
+    const uint32_t keep = valid >= 16 ? 0xFFFFFFFFu : ((1u << (2 * valid)) - 1u);
+    w &= keep;
+    const uint32_t lo = w & 0x55555555u;
+    const uint32_t hi = (w >> 1) & 0x55555555u;
+    c1 += __popc(lo & ~hi);
+    c2 += __popc(hi & ~lo);
+    c3 += __popc(lo & hi);
+}
+
+// One wavefront per SNP column; lanes stride over the column's bytes.
+__global__ void __launch_bounds__(256) colstats_kernel(const uint8_t* __restrict__ G, int64_t n,
+                                                       int64_t p, int64_t ld, ColStats st)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t j = (int64_t)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+    if (j >= p) return;
+    const uint8_t* col = G + j * ld;
+    const int64_t nbytes = (n + 3) / 4;
+    int64_t c1 = 0, c2 = 0, c3 = 0;
+    // 4 bytes per lane per iteration, assembled from byte loads (columns need
+    // not be 4-byte aligned)
+    for (int64_t b = (int64_t)lane * 4; b < nbytes; b += 256) {
+        uint32_t w = 0;
+        int nb = (int)(nbytes - b < 4 ? nbytes - b : 4);
+        for (int t = 0; t < nb; ++t) w |= (uint32_t)col[b + t] << (8 * t);
+        int64_t valid = n - b * 4;
+        count_word(w, valid >= 16 ? 16 : (int)valid, c1, c2, c3);
+    }
+    c1 = wave_sum_i64(c1);
+    c2 = wave_sum_i64(c2);
+    c3 = wave_sum_i64(c3);
+    if (lane == 0) {
+#pragma clang fp contract(off)
+        const int64_t nobs = n - c3;
+        const int64_t cnt = c1 + 2 * c2;
+        double mu = 0.0, s = 0.0;
+        if (nobs > 0) {
+            mu = (double)cnt / (double)nobs;
+            const double f = 0.5 * mu;
+            const double t = 1.0 - f;
+            const double var = mu * t;
+            if (var > 0.0) {
+                const double d = sqrt(var);
+                s = 1.0 / d;
+            }
+        }
+        st.count[j] = cnt;
+        st.nobs[j] = nobs;
+        st.n3[j] = c3;
+        st.mean[j] = mu;
+        st.inv_sd[j] = s;
+    }
+}
+
+void launch_colstats(const uint8_t* G, int64_t n, int64_t p, int64_t ld, const ColStats& st,
+                     hipStream_t s)
+{
+    dim3 grid(ceil_div(p, 4));
+    hipLaunchKernelGGL(colstats_kernel, grid, dim3(256), 0, s, G, n, p, ld, st);
+    GKL_LAUNCH_CHECK("colstats_kernel");
+}
+
+// Unpack to n x p column-major int8, -1 for missing.  One thread per output byte
+// quad (4 individuals of one SNP).
+__global__ void unpack_kernel(const uint8_t* __restrict__ G, int64_t n, int64_t p, int64_t ld,
+                              int8_t* __restrict__ out)
+{
+    const int64_t nb = (n + 3) / 4;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nb * p) return;
+    const int64_t j = t / nb;
+    const int64_t b = t - j * nb;
+    const uint32_t byte = G[j * ld + b];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int64_t i = b * 4 + k;
+        if (i < n) {
+            const int c = (byte >> (2 * k)) & 3;
+            out[j * n + i] = (int8_t)(c == 3 ? -1 : c);
+        }
+    }
+}
+
+void launch_unpack(const uint8_t* G, int64_t n, int64_t p, int64_t ld, int8_t* out,
+                   hipStream_t s)
+{
+    const int64_t total = ((n + 3) / 4) * p;
+    hipLaunchKernelGGL(unpack_kernel, dim3(ceil_div(total, 256)), dim3(256), 0, s, G, n, p, ld,
+                       out);
+    GKL_LAUNCH_CHECK("unpack_kernel");
+}
+
+}  // namespace gkl
+
+namespace gkl {
+
+// Copy the caller's packed matrix (ld bytes per column) into the internal
+// layout (ldp bytes per column, ldp a multiple of 256).  Codes of padded
+// individuals i >= n and padding bytes become 3 (missing) so they contribute
+// nothing to either product.
+__global__ void repack_kernel(const uint8_t* __restrict__ G, int64_t n, int64_t ld,
+                              uint8_t* __restrict__ out, int64_t ldp)
+{
+    const int64_t j = blockIdx.y;
+    const int64_t nb = (n + 3) / 4;
+    const uint8_t* src = G + j * ld;
+    uint8_t* dst = out + j * ldp;
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < ldp;
+         b += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t v = 0xFF;
+        if (b < nb) {
+            v = src[b];
+            const int64_t valid = n - 4 * b;   // >= 1
+            if (valid < 4) v |= (0xFFu << (2 * valid)) & 0xFFu;
+        }
+        dst[b] = (uint8_t)v;
+    }
+}
+
+void launch_repack(const uint8_t* G, int64_t n, int64_t p, int64_t ld, uint8_t* out,
+                   int64_t ldp, hipStream_t s)
+{
+    int64_t y = p;
+    int64_t done = 0;
+    while (done < y) {   // grid.y is limited to 65535
+        const int64_t chunk = (y - done) < 65535 ? (y - done) : 65535;
+        dim3 grid(ceil_div(ldp, 256) < 8 ? ceil_div(ldp, 256) : 8, (unsigned int)chunk);
+        hipLaunchKernelGGL(repack_kernel, grid, dim3(256), 0, s, G + done * ld, n, ld,
+                           out + done * ldp, ldp);
+        GKL_LAUNCH_CHECK("repack_kernel");
+        done += chunk;
+    }
+}
+
+}  // namespace gkl

@@ -1,0 +1,273 @@
+// Ritz extraction for GKL (gfx950, FP64).
+//
+// Section 3 of the paper: the top singular triplets of A are approximated from
+// the SVD of the small projected matrix B_j (upper bidiagonal, or after a thick
+// restart a diagonal block with one spike column followed by a bidiagonal
+// tail), and convergence is tested with the residual bound
+//     |sigma - sigma~_i| <= beta_j |P_{j,i}|
+// where P holds the left singular vectors of B_j (the Table 3 caption sums these
+// bounds into ||Delta theta||_1).
+//
+// The SVD is a one-sided (Hestenes) Jacobi method run by a single workgroup
+// with the matrix and the accumulated rotations held in LDS.  Column pairs of a
+// round-robin tournament are rotated concurrently, one half-wavefront (32
+// lanes) per pair; sweeps repeat until no pair needs rotating.
+#include <math.h>
+
+#include "kernels.h"
+
+namespace gkl {
+
+namespace {
+constexpr int kSvdThreads = 1024;
+constexpr int kGroup = 32;                      // lanes per column pair
+constexpr int kGroups = kSvdThreads / kGroup;   // pairs rotated at once
+constexpr int kMaxSweeps = 40;
+
+__device__ __forceinline__ double group_sum(double v)
+{
+#pragma unroll
+    for (int off = kGroup / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, kGroup);
+    return v;
+}
+
+// W (mp x mp, column-major, ld = mp) is replaced by B Q = P S; Vr accumulates Q.
+// mp is even (a zero column pads odd m).  Returns after convergence.
+__device__ void jacobi_sweeps(double* W, double* Vr, int mp)
+{
+    __shared__ int rotated;
+    const int g = threadIdx.x / kGroup;
+    const int gl = threadIdx.x % kGroup;
+    const int npairs = mp / 2;
+    const double eps = 2.220446049250313e-16;
+    for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
+        if (threadIdx.x == 0) rotated = 0;
+        __syncthreads();
+        for (int r = 0; r < mp - 1; ++r) {
+            for (int k = g; k < npairs; k += kGroups) {
+                int a, b;
+                if (k == 0) {
+                    a = mp - 1;
+                    b = r;
+                } else {
+                    a = (r + k) % (mp - 1);
+                    b = (r - k + (mp - 1)) % (mp - 1);
+                }
+                if (a > b) { const int t = a; a = b; b = t; }
+                double* wa = W + (int64_t)a * mp;
+                double* wb = W + (int64_t)b * mp;
+                double saa = 0.0, sbb = 0.0, sab = 0.0;
+                for (int i = gl; i < mp; i += kGroup) {
+                    const double x = wa[i], y = wb[i];
+                    saa = fma(x, x, saa);
+                    sbb = fma(y, y, sbb);
+                    sab = fma(x, y, sab);
+                }
+                saa = group_sum(saa);
+                sbb = group_sum(sbb);
+                sab = group_sum(sab);
+                if (fabs(sab) > eps * sqrt(saa * sbb) && sab != 0.0) {
+                    const double zeta = (sbb - saa) / (2.0 * sab);
+                    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                    const double cs = 1.0 / sqrt(1.0 + t * t);
+                    const double sn = cs * t;
+                    for (int i = gl; i < mp; i += kGroup) {
+                        const double x = wa[i], y = wb[i];
+                        wa[i] = cs * x - sn * y;
+                        wb[i] = sn * x + cs * y;
+                    }
+                    double* va = Vr + (int64_t)a * mp;
+                    double* vb = Vr + (int64_t)b * mp;
+                    for (int i = gl; i < mp; i += kGroup) {
+                        const double x = va[i], y = vb[i];
+                        va[i] = cs * x - sn * y;
+                        vb[i] = sn * x + cs * y;
+                    }
+                    if (gl == 0) rotated = 1;
+                }
+            }
+            __syncthreads();
+        }
+        if (!rotated) break;
+        __syncthreads();
+    }
+}
+
+// After jacobi_sweeps: singular values are the column norms of W; write the
+// m leading (sorted descending) triplets.
+__device__ void extract_sorted(const double* W, const double* Vr, int m, int mp, double* sig,
+                               int* order, double* P, int ldp_, double* S, double* Q, int ldq_)
+{
+    for (int c = threadIdx.x / kGroup; c < mp; c += kGroups) {
+        const double* wc = W + (int64_t)c * mp;
+        double s = 0.0;
+        for (int i = threadIdx.x % kGroup; i < mp; i += kGroup) s = fma(wc[i], wc[i], s);
+        s = group_sum(s);
+        if (threadIdx.x % kGroup == 0) sig[c] = sqrt(s);
+    }
+    __syncthreads();
+    // rank by value (ties broken by index) -> stable descending order
+    for (int c = threadIdx.x; c < mp; c += blockDim.x) {
+        int rank = 0;
+        const double sc = sig[c];
+        for (int d = 0; d < mp; ++d) {
+            const double sd = sig[d];
+            rank += (sd > sc) || (sd == sc && d < c);
+        }
+        order[rank] = c;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < m * m; t += blockDim.x) {
+        const int i = t % m, o = t / m;     // row i of output column o
+        const int c = order[o];
+        const double s = sig[c];
+        P[(int64_t)o * ldp_ + i] = s > 0.0 ? W[(int64_t)c * mp + i] / s : (i == o ? 1.0 : 0.0);
+        Q[(int64_t)o * ldq_ + i] = Vr[(int64_t)c * mp + i];
+    }
+    for (int o = threadIdx.x; o < m; o += blockDim.x) S[o] = sig[order[o]];
+}
+
+}  // namespace
+
+__global__ void __launch_bounds__(kSvdThreads)
+dense_svd_kernel(const double* __restrict__ B, int m, double* __restrict__ P,
+                 double* __restrict__ S, double* __restrict__ Q, double* gscratch)
+{
+    extern __shared__ double lds[];
+    const int mp = m + (m & 1);
+    double* W = gscratch ? gscratch : lds;
+    double* Vr = W + mp * mp;
+    double* sig = Vr + mp * mp;
+    int* order = reinterpret_cast<int*>(sig + mp);
+    for (int t = threadIdx.x; t < mp * mp; t += blockDim.x) {
+        const int i = t % mp, c = t / mp;
+        W[t] = (i < m && c < m) ? B[(int64_t)c * m + i] : 0.0;
+        Vr[t] = (i == c) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    jacobi_sweeps(W, Vr, mp);
+    __syncthreads();
+    extract_sorted(W, Vr, m, mp, sig, order, P, m, S, Q, m);
+}
+
+static size_t svd_lds_bytes(int m)
+{
+    const int mp = m + (m & 1);
+    return sizeof(double) * (2 * (size_t)mp * mp + mp) + sizeof(int) * (size_t)mp;
+}
+
+size_t svd_scratch_elems(int m) { return svd_lds_bytes(m) / sizeof(double) + 1; }
+
+bool svd_fits_lds(int m)
+{
+    static int limit = -1;
+    if (limit < 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            v = 65536;
+        limit = v;
+    }
+    // static LDS of the kernels (flags, reduction scratch) needs a little room
+    return m <= kMaxKrylov && svd_lds_bytes(m) + 1024 <= (size_t)limit;
+}
+
+static void check_svd_size(int m, const double* gscratch)
+{
+    if (m < 1 || m > kMaxSvd) fail(GKL_ERR_INVALID, "projected matrix size out of range");
+    if (!svd_fits_lds(m) && gscratch == nullptr)
+        fail(GKL_ERR_INTERNAL, "large projected matrix needs a global scratch buffer");
+}
+
+void launch_dense_svd(const double* B, int m, double* P, double* S, double* Q, double* gscratch,
+                      hipStream_t s)
+{
+    check_svd_size(m, gscratch);
+    const bool global = !svd_fits_lds(m);
+    const size_t lds = global ? 0 : svd_lds_bytes(m);
+    hipLaunchKernelGGL(dense_svd_kernel, dim3(1), dim3(kSvdThreads), lds, s, B, m, P, S, Q,
+                       global ? gscratch : nullptr);
+    GKL_LAUNCH_CHECK("dense_svd_kernel");
+}
+
+__global__ void __launch_bounds__(kSvdThreads)
+ritz_kernel(const double* __restrict__ alpha, const double* __restrict__ beta,
+            const double* __restrict__ theta, const double* __restrict__ rho, int nlock, int m,
+            int k, double tol, RitzOut out, double* gscratch)
+{
+    extern __shared__ double lds[];
+    const int mp = m + (m & 1);
+    double* W = gscratch ? gscratch : lds;
+    double* Vr = W + mp * mp;
+    double* sig = Vr + mp * mp;
+    int* order = reinterpret_cast<int*>(sig + mp);
+    for (int t = threadIdx.x; t < mp * mp; t += blockDim.x) {
+        const int i = t % mp, c = t / mp;
+        double v = 0.0;
+        if (i < m && c < m) {
+            if (i < nlock) {
+                if (c == i) v = theta[i];
+                else if (c == nlock) v = rho[i];
+            } else {
+                if (c == i) v = alpha[i];
+                else if (c == i + 1) v = beta[i];
+            }
+        }
+        W[t] = v;
+        Vr[t] = (i == c) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < m * m; t += blockDim.x) out.B[t] = W[(t / m) * mp + (t % m)];
+    jacobi_sweeps(W, Vr, mp);
+    __syncthreads();
+    extract_sorted(W, Vr, m, mp, sig, order, out.P, m, out.S, out.Q, m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double bl = beta[m - 1];
+        const double s0 = out.S[0];
+        int nconv = 0;
+        bool run = true;
+        for (int i = 0; i < m; ++i) {
+            const double r = fabs(bl * out.P[(int64_t)i * m + (m - 1)]);
+            out.res[i] = r;
+            if (i < k && run) {
+                if (r <= tol * s0) ++nconv;
+                else run = false;
+            }
+        }
+        *out.nconv = nconv;
+    }
+}
+
+void launch_ritz(const double* alpha, const double* beta, const double* theta, const double* rho,
+                 int nlock, int m, int k, double tol, const RitzOut& out, double* gscratch,
+                 hipStream_t s)
+{
+    check_svd_size(m, gscratch);
+    const bool global = !svd_fits_lds(m);
+    const size_t lds = global ? 0 : svd_lds_bytes(m);
+    hipLaunchKernelGGL(ritz_kernel, dim3(1), dim3(kSvdThreads), lds, s, alpha, beta, theta, rho,
+                       nlock, m, k, tol, out, global ? gscratch : nullptr);
+    GKL_LAUNCH_CHECK("ritz_kernel");
+}
+
+__global__ void restart_scalars_kernel(const double* __restrict__ S, const double* __restrict__ P,
+                                       int m, const double* __restrict__ beta_last, int keep,
+                                       double* __restrict__ theta, double* __restrict__ rho)
+{
+    const double bl = *beta_last;
+    for (int i = threadIdx.x; i < keep; i += blockDim.x) {
+        theta[i] = S[i];
+        rho[i] = bl * P[(int64_t)i * m + (m - 1)];
+    }
+}
+
+void launch_restart_scalars(const double* S, const double* P, int m, const double* beta_last,
+                            int keep, double* theta, double* rho, hipStream_t s)
+{
+    hipLaunchKernelGGL(restart_scalars_kernel, dim3(1), dim3(256), 0, s, S, P, m, beta_last, keep,
+                       theta, rho);
+    GKL_LAUNCH_CHECK("restart_scalars_kernel");
+}
+
+}  // namespace gkl

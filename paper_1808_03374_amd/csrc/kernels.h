@@ -1,0 +1,140 @@
+// Kernel launch interface used by the host engine (internal).
+#pragma once
+
+#include "common.h"
+
+namespace gkl {
+
+// Column statistics, device arrays of length p.
+struct ColStats {
+    int64_t* count;   // c_j = n1 + 2 n2
+    int64_t* nobs;    // n - n3
+    int64_t* n3;      // missing count
+    double* mean;     // mu_j
+    double* inv_sd;   // s_j
+};
+
+// Internal copy of the genotype matrix: SNP-major, ldp bytes per column with
+// ldp a multiple of 256 and every padding code set to 3 (missing), so padded
+// individuals contribute exactly zero without masking in the hot loops.
+struct Packed {
+    const uint8_t* G = nullptr;   // device, p * ldp bytes
+    int64_t n = 0, p = 0;
+    int64_t ldp = 0;              // bytes per SNP column
+};
+
+// Device scratch used by the two-stage reductions of the matvec kernels.
+struct MatvecWork {
+    double* partial = nullptr;        // split partials
+    size_t partial_elems = 0;
+    unsigned int* counters = nullptr; // zeroed, one per output block
+    size_t ncounters = 0;
+};
+
+// ---- k_stats.hip ----
+void launch_colstats(const uint8_t* G, int64_t n, int64_t p, int64_t ld, const ColStats& st,
+                     hipStream_t s);
+void launch_unpack(const uint8_t* G, int64_t n, int64_t p, int64_t ld, int8_t* out,
+                   hipStream_t s);
+void launch_repack(const uint8_t* G, int64_t n, int64_t p, int64_t ld, uint8_t* out,
+                   int64_t ldp, hipStream_t s);
+
+// ---- k_matvec.hip: FP64 products with the implicit standardised matrix ----
+// y = A v - (beta ? *beta : 0) * uprev      (y, uprev: n; v: p)
+void launch_matvec(const Packed& P, const ColStats& st, const double* v, double* y,
+                   const double* beta, const double* uprev, MatvecWork& w, hipStream_t s);
+// z = A^T u - (alpha ? *alpha : 0) * vprev  (u: n; z, vprev: p)
+void launch_rmatvec(const Packed& P, const ColStats& st, const double* u, double* z,
+                    const double* alpha, const double* vprev, MatvecWork& w, hipStream_t s);
+size_t matvec_partial_elems(const Packed& P);
+size_t matvec_counters(const Packed& P);
+
+// ---- k_ortho.hip: Gram-Schmidt, norms, small dense ops on the Krylov bases ----
+struct OrthoWork {
+    double* partial = nullptr;      // nblocks x (maxcols + 1)
+    size_t partial_elems = 0;
+    unsigned int* counters = nullptr;
+    double* h = nullptr;            // projection coefficients (maxcols + 1)
+};
+size_t ortho_partial_elems(int64_t len, int maxcols);
+
+// r <- r - Q (Q^T r) with Q = [Q(:, 0:ncols)], column-major leading dim ldq.
+// `enable` (device, may be NULL = always) gates the whole call: 0 skips it.
+// If adaptive, the second pass runs only when ||r1|| < ||r0|| / sqrt(2);
+// otherwise two passes always.  Counts performed passes into *passes (device).
+void launch_cgs2(const double* Q, int64_t ldq, int64_t len, int ncols, double* r,
+                 const int* enable, int adaptive, int* passes, OrthoWork& w, hipStream_t s);
+// nrm = ||r||; if nrm <= thresh(*) then breakdown: *flag = 1 and nrm stored as 0,
+// r left unscaled; else out = r / nrm (out may alias r).
+//   thresh = eps * max(*norm_est, nrm) * sqrt(max_dim); *norm_est updated.
+void launch_normalize(double* r, int64_t len, double* out, double* nrm_out, double* norm_est,
+                      double root_maxdim, int* flag, OrthoWork& w, hipStream_t s);
+// y -= Q(:, 0:ncols) * c  (c device, ncols)
+void launch_gemv_n_sub(const double* Q, int64_t ldq, int64_t len, int ncols, const double* c,
+                       double* y, hipStream_t s);
+// C(len x ncols_out) = Q(len x ncols_in) * S(ncols_in x ncols_out) (S column-major, lds)
+void launch_gemm_tall(const double* Q, int64_t ldq, int64_t len, int ncols_in, const double* S,
+                      int lds, int ncols_out, double* C, int64_t ldc, hipStream_t s);
+// Gaussian vector from a counter-based generator (Box-Muller), seed-keyed.
+void launch_gaussian(double* x, int64_t len, uint64_t seed, uint64_t stream_id, hipStream_t s);
+// Sign rule: for each of k columns of V (ldv), find the largest |entry| (lowest
+// index on ties); if negative flip that V column and the U column.
+void launch_sign_fix(double* U, int64_t ldu, int64_t n, double* V, int64_t ldv, int64_t p,
+                     int k, hipStream_t s);
+
+// ---- k_svd.hip: Ritz extraction ----
+// One-sided Jacobi SVD of a dense m x m matrix (m <= kMaxKrylov) in one workgroup:
+// B = P diag(S) Q^T, S descending.
+// For m > kMaxKrylov the working matrices live in `gscratch` (device, at least
+// svd_scratch_elems(m) doubles); otherwise in LDS and gscratch may be NULL.
+void launch_dense_svd(const double* B, int m, double* P, double* S, double* Q, double* gscratch,
+                      hipStream_t s);
+size_t svd_scratch_elems(int m);
+// True when the m x m SVD working set fits the device's LDS per workgroup.
+bool svd_fits_lds(int m);
+constexpr int kMaxSvd = 1024;
+
+// Builds the projected matrix from the device state and runs the SVD, then the
+// convergence test:
+//   B(i,i) = alpha[i], B(i,i+1) = beta[i] for i >= nlock (bidiagonal part),
+//   B(i,i) = theta[i], B(i,nlock) = rho[i] for i < nlock (restart arrowhead).
+//   res_i = beta[m-1] * |P(m-1, i)|; conv = #leading i < k with res_i <= tol*S[0].
+struct RitzOut {
+    double* B;      // m x m scratch
+    double* P;      // m x m
+    double* S;      // m
+    double* Q;      // m x m
+    double* res;    // m
+    int* nconv;     // 1
+};
+void launch_ritz(const double* alpha, const double* beta, const double* theta, const double* rho,
+                 int nlock, int m, int k, double tol, const RitzOut& out, double* gscratch,
+                 hipStream_t s);
+
+// ---- k_pro.hip: partial reorthogonalisation estimates ----
+struct ProState {
+    double* mu;     // left estimates  u_j^T u_i, length maxm
+    double* nu;     // right estimates v_{j+1}^T v_i, length maxm + 1
+    int* flag_left;   // 1 = reorthogonalise the next left vector
+    int* flag_right;  // 1 = reorthogonalise the next right vector
+    int* force;       // [0] left, [1] right: pending forced passes (Simon's rule)
+};
+// Update after alpha_j (left side) or beta_j (right side); theta/rho/nlock
+// describe the thick-restart block (nlock = 0 without restart).
+// noise_scale = eps * sqrt(max(n, p)); the noise added per update is
+// noise_scale * (*norm_est) / alpha_j (or beta_j).
+void launch_pro_left(const double* alpha, const double* beta, const double* theta,
+                     const double* rho, int nlock, int j, double omega, double noise_scale,
+                     const double* norm_est, const ProState& st, hipStream_t s);
+void launch_pro_right(const double* alpha, const double* beta, const double* theta,
+                      const double* rho, int nlock, int j, double omega, double noise_scale,
+                      const double* norm_est, const ProState& st, hipStream_t s);
+// Zero the estimates and force `force` full reorthogonalisations on each side.
+void launch_pro_reset(const ProState& st, int maxm, int force, hipStream_t s);
+
+// ---- k_svd.hip, restart helpers ----
+// theta[i] = S[i], rho[i] = beta_last * P(m-1, i) for i < keep.
+void launch_restart_scalars(const double* S, const double* P, int m, const double* beta_last,
+                            int keep, double* theta, double* rho, hipStream_t s);
+
+}  // namespace gkl
