@@ -1,0 +1,225 @@
+#!/usr/bin/env python3
+"""Bench: top-k principal components of a packed genotype matrix on one MI355X.
+
+Workload (default): 10,000 individuals x 100,000 SNPs, five Balding-Nichols
+subpopulations (F 0.005..0.02), 2% of individuals in related pairs, MAF ~
+U(0.01, 0.5), 1% missing, 2-bit packed (250 MB); top k = 20 by FP64 GKL with
+partial reorthogonalisation (omega = 1e-8) and thick restart (basis 60).
+
+A step is one pass of the hot path: gkl_create (device column statistics and
+internal layout) + gkl_solve (the Lanczos iteration to tolerance, Ritz
+extraction, output) + gkl_destroy, with the packed matrix already in HBM.
+Prints one JSON line.  `value` is seconds per step (lower is better).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "top-k PC solve time + matvec HBM GB/s, split-BF16 blocked vs FP64 GKL"
+HBM_PEAK_GBPS = 8000.0
+
+WORKLOADS = {
+    "c2": dict(name="c2", k=20, tol=1e-10, reorth="partial", krylov_dim=60,
+               desc="10,000 x 100,000 genotypes, 5 subpopulations + related pairs, 1% missing; "
+                    "k=20, FP64 GKL, PRO omega=1e-8, thick restart m=60"),
+    "c1": dict(name="c1", k=10, tol=1e-10, reorth="full", krylov_dim=0,
+               desc="1,000 x 5,000 genotypes, 2 subpopulations, 1% missing; k=10, FP64 GKL, "
+                    "full CGS2, no restart"),
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None
+    when the kernel source changed since the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", f"{workload}_fp64_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    src = os.path.join(ROOT, rec["kernel_source"])
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
+        return None
+    k = rec["per_launch_bytes"].get(kernel)
+    return None if k is None else int(k["fetch"] + k["write"])
+
+
+def cpu_baseline(g, gpu_matvecs, seconds):
+    """Time the oracle (plain FP64 CPU GKL, full CGS2) on the same matrix for a
+    bounded number of steps and scale its per-product time to the GPU solve's
+    product count."""
+    import numpy as np
+
+    import oracle
+    import synth
+    cores = len(os.sched_getaffinity(0))
+    threads = int(os.environ.get("OMP_NUM_THREADS", cores))
+    op = oracle.PackedOperator(g.packed, g.n, g.p)
+    v0 = synth.start_vector(g.p, 1)
+    t0 = time.perf_counter()
+    oracle.gkl_svd(op, 1, tol=-1.0, v0=v0, max_steps=1)
+    t1 = time.perf_counter() - t0
+    steps = max(2, min(200, int(seconds / max(t1, 1e-6))))
+    op.matvecs = 0
+    t0 = time.perf_counter()
+    res = oracle.gkl_svd(op, 1, tol=-1.0, v0=v0, max_steps=steps)
+    t = time.perf_counter() - t0
+    per_mvp = t / res.matvecs
+    return {
+        "value": per_mvp * gpu_matvecs,
+        "unit": "s",
+        "cores": min(threads, cores),
+        "kind": "oracle",
+        "sample": (f"oracle plain GKL (full CGS2, no restart) on the full matrix: first {steps} "
+                   f"steps = {res.matvecs} products in {t:.1f} s ({per_mvp * 1e3:.1f} ms per "
+                   f"product incl. its CGS2), scaled to the GPU solve's {gpu_matvecs} products"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="after the timed steps, copy BYTES bytes device-to-device 3 times "
+                         "(reference dispatch for the HBM traffic counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_1808_03374_amd as gk
+
+    wl = WORKLOADS[args.workload]
+    log(f"[bench] generating workload {wl['name']}")
+    g = synth.config(wl["name"])
+    n, p, k = g.n, g.p, wl["k"]
+    G = torch.from_numpy(g.packed).cuda()
+    v0 = torch.from_numpy(synth.start_vector(p, 1)).cuda()
+    stream = torch.cuda.current_stream().cuda_stream
+    reorth = gk.GKL_REORTH_PARTIAL if wl["reorth"] == "partial" else gk.GKL_REORTH_FULL
+    opts = dict(v0=v0, krylov_dim=wl["krylov_dim"], timing=1, stream=stream)
+    sigma = torch.empty(k, dtype=torch.float64, device="cuda")
+    U = torch.empty((k, n), dtype=torch.float64, device="cuda")
+    V = torch.empty((k, p), dtype=torch.float64, device="cuda")
+
+    def one_step():
+        ctx = gk.Context(G, n, p, k, wl["tol"], reorth, **opts)
+        try:
+            st, info = gk.gkl_solve(ctx.ctx, sigma, U, n, V, p)
+        finally:
+            ctx.close()
+        return st, info
+
+    for w in range(args.warmup):
+        st, info = one_step()
+        log(f"[bench] warmup {w}: status {st} solve {info.solve_ms:.1f} ms matvecs {info.matvecs}")
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        st, info = one_step()
+        infos.append(info)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    for s, info in enumerate(infos):
+        log(f"[bench] step {s}: solve {info.solve_ms:.1f} ms create {info.create_ms:.1f} ms "
+            f"matvecs {info.matvecs} restarts {info.restarts} conv {info.converged}")
+    sec_per_step = elapsed / args.steps
+
+    # dominant product kernel: average duration from the HIP events taken on the
+    # library's stream during the timed steps
+    mv_ms = sum(i.matvec_kernel_ms for i in infos)
+    rmv_ms = sum(i.rmatvec_kernel_ms for i in infos)
+    mv_n = sum(i.timed_matvecs for i in infos)
+    rmv_n = sum(i.timed_rmatvecs for i in infos)
+    bytes_per_product = ((n + 3) // 4) * p + 16 * p + 16 * n
+    mv_avg = mv_ms / max(mv_n, 1)
+    rmv_avg = rmv_ms / max(rmv_n, 1)
+    kernels = {"matvec_kernel (A v)": (mv_ms, mv_avg), "rmatvec_kernel (A^T u)": (rmv_ms, rmv_avg)}
+    dom = max(kernels, key=lambda key: kernels[key][0])
+    dom_avg = kernels[dom][1]
+    achieved = bytes_per_product / (dom_avg * 1e-3) / 1e9
+    other = [key for key in kernels if key != dom][0]
+    other_avg = kernels[other][1]
+    solve_s = float(np.mean([i.solve_ms for i in infos])) / 1e3
+    create_s = float(np.mean([i.create_ms for i in infos])) / 1e3
+    last = infos[-1]
+    line = {
+        "metric": METRIC,
+        "value": sec_per_step,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec_per_step * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl["desc"], "n": n, "p": p, "k": k, "tol": wl["tol"],
+                   "reorth": wl["reorth"], "krylov_dim": wl["krylov_dim"],
+                   "packed_bytes": int(g.nbytes)},
+        "solve_s": solve_s,
+        "create_s": create_s,
+        "matvecs": int(last.matvecs),
+        "restarts": int(last.restarts),
+        "reorth_passes": int(last.reorths),
+        "converged": int(last.converged),
+        "max_residual_rel": last.max_residual_rel,
+        "matvec_GBps": bytes_per_product / (mv_avg * 1e-3) / 1e9,
+        "rmatvec_GBps": bytes_per_product / (rmv_avg * 1e-3) / 1e9,
+        "roofline": {
+            "kernel": dom,
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBPS,
+            "traffic": measured_traffic(wl["name"], dom),
+            "avg_launch_ms": dom_avg,
+            "launches": int(mv_n if dom.startswith("matvec") else rmv_n),
+            "algorithmic_bytes_per_launch": int(bytes_per_product),
+            "other_kernel": {"kernel": other, "avg_launch_ms": other_avg,
+                             "achieved_GBps": bytes_per_product / (other_avg * 1e-3) / 1e9},
+        },
+    }
+    if args.copy_calibration > 0:
+        src = torch.empty(args.copy_calibration, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        line["copy_calibration_bytes"] = args.copy_calibration
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a bounded sample")
+        line["cpu_baseline"] = cpu_baseline(g, int(last.matvecs), args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

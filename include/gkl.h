@@ -86,6 +86,8 @@ typedef struct gkl_options {
     void* stream;             /* hipStream_t; NULL = default stream */
     int32_t trace;            /* 1: record a per-step trace (gkl_get_trace) */
     int32_t verbose;          /* 1: progress lines on stderr */
+    int32_t timing;           /* 1: bracket every product launch with HIP events and
+                                 report the kernel time in gkl_info */
 } gkl_options;
 
 /* Run statistics (host struct). */
@@ -101,6 +103,10 @@ typedef struct gkl_info {
     double max_residual_rel;  /* max_i residual_i / sigma_1 */
     double solve_ms;
     double create_ms;
+    double matvec_kernel_ms;  /* with options.timing: summed A v kernel time */
+    double rmatvec_kernel_ms; /* with options.timing: summed A^T u kernel time */
+    int64_t timed_matvecs;    /* launches behind matvec_kernel_ms */
+    int64_t timed_rmatvecs;   /* launches behind rmatvec_kernel_ms */
 } gkl_info;
 
 void gkl_options_default(gkl_options* opt);

@@ -42,6 +42,7 @@ class gkl_options(ctypes.Structure):
         ("stream", ctypes.c_void_p),
         ("trace", ctypes.c_int32),
         ("verbose", ctypes.c_int32),
+        ("timing", ctypes.c_int32),
     ]
 
 
@@ -58,6 +59,10 @@ class gkl_info(ctypes.Structure):
         ("max_residual_rel", ctypes.c_double),
         ("solve_ms", ctypes.c_double),
         ("create_ms", ctypes.c_double),
+        ("matvec_kernel_ms", ctypes.c_double),
+        ("rmatvec_kernel_ms", ctypes.c_double),
+        ("timed_matvecs", ctypes.c_int64),
+        ("timed_rmatvecs", ctypes.c_int64),
     ]
 
     def as_dict(self):

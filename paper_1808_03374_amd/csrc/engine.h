@@ -72,6 +72,7 @@ struct gkl_ctx {
     double* norm_est = nullptr;
     int* flags = nullptr;   // [0] left breakdown [1] right breakdown [2..5] PRO
                             // [6] Gram-Schmidt passes [7] scratch flag [8] nconv
+                            // [9] first breakdown half-step (-1 = none)
     gkl::RitzOut ritz{};
     double* svd_scratch = nullptr;
     gkl::ProState pro{};
@@ -84,6 +85,16 @@ struct gkl_ctx {
     int ritz_m = -1;
     bool exhausted = false;
     uint64_t breakdown_draws = 1;
+    int last_breakdown = -1;
+    static constexpr int kOrthoCounters = 128;
+
+    // optional kernel timing (options.timing)
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, int>> ev_mv, ev_rmv;   // (start, stop) indices
+    int ev_next = 0;
+    int timing_begin();
+    void timing_end(int start, bool right);
+    void timing_collect();
 
     gkl::MixedState* mixed = nullptr;
     gkl::BatchState* batch = nullptr;
@@ -94,6 +105,7 @@ struct gkl_ctx {
     void allocate_solver();
     void record(int step, bool restart_flag, double res_rel);
     int read_flag(const int* dflag);
+    void sync_state(int* nconv, int* breakdown);
     void left_step(int j);
     void right_step(int j);
     void launch_normalize_only(double* r, int64_t len, double* out);

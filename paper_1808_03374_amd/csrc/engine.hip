@@ -65,12 +65,10 @@ void Problem::setup(const uint8_t* G, int64_t n_, int64_t p_, int64_t ld_, hipSt
     p = p_;
     ld = ld_;
     stream = s;
-    packed.n = n;
-    packed.p = p;
-    packed.ldp = ((((n + 3) / 4) + 255) / 256) * 256;
-    uint8_t* Gi = static_cast<uint8_t*>(arena.alloc((size_t)packed.ldp * (size_t)p));
-    launch_repack(G, n, p, ld, Gi, packed.ldp, s);
-    packed.G = Gi;
+    layout_shape(n, p, packed);
+    packed.T = static_cast<uint8_t*>(arena.alloc(layout_T_bytes(packed)));
+    packed.P = static_cast<uint8_t*>(arena.alloc(layout_P_bytes(packed)));
+    build_layouts(G, ld, packed, s);
     st.count = static_cast<int64_t*>(arena.alloc(sizeof(int64_t) * p));
     st.nobs = static_cast<int64_t*>(arena.alloc(sizeof(int64_t) * p));
     st.n3 = static_cast<int64_t*>(arena.alloc(sizeof(int64_t) * p));
@@ -126,10 +124,10 @@ void gkl_ctx::allocate_solver()
     const int64_t maxlen = std::max(n, p);
     ow.partial_elems = ortho_partial_elems(maxlen, cols + 1);
     ow.partial = static_cast<double*>(A.alloc(sizeof(double) * ow.partial_elems));
-    ow.counters = static_cast<unsigned int*>(A.alloc(sizeof(unsigned int) * 4));
+    ow.counters = static_cast<unsigned int*>(A.alloc(sizeof(unsigned int) * kOrthoCounters));
     ow.h = static_cast<double*>(A.alloc(sizeof(double) * (3 * (size_t)(cols + 2) + 8)));
     hipStream_t s = prob.stream;
-    GKL_HIP(hipMemsetAsync(ow.counters, 0, sizeof(unsigned int) * 4, s));
+    GKL_HIP(hipMemsetAsync(ow.counters, 0, sizeof(unsigned int) * kOrthoCounters, s));
     GKL_HIP(hipMemsetAsync(scal, 0, sizeof(double) * kScalars, s));
     GKL_HIP(hipMemsetAsync(flags, 0, sizeof(int) * 16, s));
 }
@@ -166,21 +164,76 @@ int gkl_ctx::read_flag(const int* dflag)
     return h;
 }
 
-// Left half-step j: U(:, j) from v_j.
+// Kernel timing: events are taken from a pool that grows on demand and is
+// reused across solves; durations are summed after the solve.
+int gkl_ctx::timing_begin()
+{
+    if (!opt.timing) return -1;
+    if (ev_next + 2 > (int)ev_pool.size()) {
+        for (int t = 0; t < 64; ++t) {
+            hipEvent_t e;
+            GKL_HIP(hipEventCreate(&e));
+            ev_pool.push_back(e);
+        }
+    }
+    const int i = ev_next;
+    ev_next += 2;
+    GKL_HIP(hipEventRecord(ev_pool[i], prob.stream));
+    return i;
+}
+
+void gkl_ctx::timing_end(int start, bool right)
+{
+    if (start < 0) return;
+    GKL_HIP(hipEventRecord(ev_pool[start + 1], prob.stream));
+    (right ? ev_rmv : ev_mv).push_back({start, start + 1});
+}
+
+void gkl_ctx::timing_collect()
+{
+    if (!opt.timing) return;
+    GKL_HIP(hipStreamSynchronize(prob.stream));
+    double a = 0.0, b = 0.0;
+    for (auto& pr : ev_mv) {
+        float ms = 0.f;
+        GKL_HIP(hipEventElapsedTime(&ms, ev_pool[pr.first], ev_pool[pr.second]));
+        a += ms;
+    }
+    for (auto& pr : ev_rmv) {
+        float ms = 0.f;
+        GKL_HIP(hipEventElapsedTime(&ms, ev_pool[pr.first], ev_pool[pr.second]));
+        b += ms;
+    }
+    info.matvec_kernel_ms = a;
+    info.rmatvec_kernel_ms = b;
+    info.timed_matvecs = (int64_t)ev_mv.size();
+    info.timed_rmatvecs = (int64_t)ev_rmv.size();
+    ev_mv.clear();
+    ev_rmv.clear();
+    ev_next = 0;
+}
+
+// Left half-step j: U(:, j) from v_j.  Nothing is read back: a breakdown is
+// recorded on the device (first half-step index) and handled at the next
+// synchronisation point.
 void gkl_ctx::left_step(int j)
 {
     hipStream_t s = prob.stream;
     const int64_t n = prob.n, p = prob.p;
     double* uj = U + (int64_t)j * n;
     const double* vj = V + (int64_t)j * p;
+    const int ev = timing_begin();
     if (j > 0 && j == nlock) {
         launch_matvec(prob.packed, prob.st, vj, uj, nullptr, nullptr, prob.mvw, s);
+        timing_end(ev, false);
         launch_gemv_n_sub(U, n, n, nlock, rho, uj, s);
     } else if (j > 0) {
         launch_matvec(prob.packed, prob.st, vj, uj, beta + (j - 1), U + (int64_t)(j - 1) * n,
                       prob.mvw, s);
+        timing_end(ev, false);
     } else {
         launch_matvec(prob.packed, prob.st, vj, uj, nullptr, nullptr, prob.mvw, s);
+        timing_end(ev, false);
     }
     info.matvecs += 1;
     info.passes_over_G += 1;
@@ -193,8 +246,8 @@ void gkl_ctx::left_step(int j)
             launch_cgs2(U, n, n, j, uj, nullptr, opt.adaptive_cgs2, flags + 6, ow, s);
         }
     }
-    launch_normalize(uj, n, uj, alpha + j, norm_est, root_maxdim, flags + 0, ow, s);
-    if (read_flag(flags + 0)) handle_breakdown(true, j);
+    launch_normalize(uj, n, uj, alpha + j, norm_est, root_maxdim, flags + 0, ow, s, flags + 9,
+                     2 * j);
 }
 
 // Right half-step j: V(:, j+1) from u_j.
@@ -204,7 +257,9 @@ void gkl_ctx::right_step(int j)
     const int64_t n = prob.n, p = prob.p;
     const double* uj = U + (int64_t)j * n;
     double* vn = V + (int64_t)(j + 1) * p;
+    const int ev = timing_begin();
     launch_rmatvec(prob.packed, prob.st, uj, vn, alpha + j, V + (int64_t)j * p, prob.mvw, s);
+    timing_end(ev, true);
     info.matvecs += 1;
     info.passes_over_G += 1;
     if (reorth == GKL_REORTH_PARTIAL) {
@@ -214,8 +269,19 @@ void gkl_ctx::right_step(int j)
     } else {
         launch_cgs2(V, p, p, j + 1, vn, nullptr, opt.adaptive_cgs2, flags + 6, ow, s);
     }
-    launch_normalize(vn, p, vn, beta + j, norm_est, root_maxdim, flags + 1, ow, s);
-    if (read_flag(flags + 1)) handle_breakdown(false, j);
+    launch_normalize(vn, p, vn, beta + j, norm_est, root_maxdim, flags + 1, ow, s, flags + 9,
+                     2 * j + 1);
+}
+
+// Reads the number of converged Ritz values and the first breakdown half-step
+// (-1 if none) in one copy.
+void gkl_ctx::sync_state(int* nconv, int* breakdown)
+{
+    int h[2] = {0, -1};
+    GKL_HIP(hipMemcpyAsync(h, flags + 8, 2 * sizeof(int), hipMemcpyDeviceToHost, prob.stream));
+    GKL_HIP(hipStreamSynchronize(prob.stream));
+    *nconv = h[0];
+    *breakdown = h[1];
 }
 
 // ||r|| into *out without scaling (PRO needs alpha_j / beta_j before deciding).
@@ -260,7 +326,10 @@ int gkl_ctx::check_convergence(int m)
 {
     launch_ritz(alpha, beta, theta, rho, nlock, m, k, tol, ritz, svd_scratch, prob.stream);
     ritz_m = m;
-    return read_flag(ritz.nconv);
+    int nconv = 0, bd = -1;
+    sync_state(&nconv, &bd);
+    last_breakdown = bd;
+    return nconv;
 }
 
 void gkl_ctx::restart(int m)
@@ -314,6 +383,7 @@ gkl_status gkl_ctx::solve_fp64(double* sigma, double* Uo, int64_t ldu, double* V
     if (opt.v0) GKL_HIP(hipMemcpyAsync(V, opt.v0, sizeof(double) * p, hipMemcpyDeviceToDevice, s));
     else launch_gaussian(V, p, opt.seed, 0, s);
     GKL_HIP(hipMemsetAsync(scal, 0, sizeof(double) * kScalars, s));
+    GKL_HIP(hipMemsetAsync(flags + 9, 0xFF, sizeof(int), s));   // first breakdown = -1
     launch_normalize(V, p, V, tmp, norm_est, root_maxdim, flags + 1, ow, s);
     GKL_HIP(hipMemsetAsync(norm_est, 0, sizeof(double), s));
     if (reorth == GKL_REORTH_PARTIAL) launch_pro_reset(pro, maxm, 0, s);
@@ -321,6 +391,7 @@ gkl_status gkl_ctx::solve_fp64(double* sigma, double* Uo, int64_t ldu, double* V
     ritz_m = -1;
     exhausted = false;
     breakdown_draws = 1;
+    last_breakdown = -1;
     int j = 0;
     int last_check = 0;
     int nconv = 0;
@@ -329,33 +400,54 @@ gkl_status gkl_ctx::solve_fp64(double* sigma, double* Uo, int64_t ldu, double* V
     bool converged = false;
     while (true) {
         left_step(j);
-        if (exhausted) { ++j; break; }
         right_step(j);
         ++j;
-        const bool full = (j == maxm) || (j >= maxbasis) || exhausted;
-        bool checked = false;
-        if (j >= k && (full || (check_every > 0 && j - last_check >= check_every))) {
-            nconv = check_convergence(j);
-            last_check = j;
-            checked = true;
-            info.nconv = nconv;
-            if (nconv >= k) { converged = true; }
+        const bool budget = opt.max_matvecs > 0 && info.matvecs >= opt.max_matvecs;
+        const bool full = (j == maxm) || (j >= maxbasis);
+        const bool due = j >= k && (full || (check_every > 0 && j - last_check >= check_every));
+        if (opt.trace) record(j - 1, false, NAN);
+        if (!(due || budget || full)) continue;
+        nconv = j >= k ? check_convergence(j) : 0;
+        if (j < k) {
+            int dummy = 0;
+            sync_state(&dummy, &last_breakdown);
         }
-        if (opt.trace) {
-            double rr = NAN;
-            if (checked) {
-                double r = 0.0, s0 = 0.0;
-                GKL_HIP(hipMemcpy(&s0, ritz.S, sizeof(double), hipMemcpyDeviceToHost));
-                std::vector<double> res(k);
-                GKL_HIP(hipMemcpy(res.data(), ritz.res, sizeof(double) * k, hipMemcpyDeviceToHost));
-                for (int i = 0; i < k; ++i) r = std::max(r, s0 > 0 ? res[i] / s0 : 0.0);
-                rr = r;
+        last_check = j;
+        if (last_breakdown >= 0) {
+            // roll back to the half-step that broke down and continue from there
+            const int hb = last_breakdown;
+            const int jb = hb / 2;
+            GKL_HIP(hipMemsetAsync(flags + 9, 0xFF, sizeof(int), s));
+            last_breakdown = -1;
+            ritz_m = -1;
+            if (hb % 2 == 0) {
+                handle_breakdown(true, jb);
+                if (exhausted) { j = jb; break; }
+                right_step(jb);
+            } else {
+                handle_breakdown(false, jb);
+                if (exhausted) { j = jb + 1; break; }
             }
-            record(j - 1, false, rr);
+            j = jb + 1;
+            last_check = std::min(last_check, j);
+            if (opt.trace) {
+                while (!trace.empty() && trace.back()[0] >= jb) trace.pop_back();
+                record(jb, false, NAN);
+            }
+            continue;
         }
-        if (converged) break;
-        if (opt.max_matvecs > 0 && info.matvecs >= opt.max_matvecs) break;
-        if (j >= maxbasis || exhausted) break;
+        info.nconv = nconv;
+        if (opt.trace && j >= k && !trace.empty()) {
+            double s0 = 0.0;
+            std::vector<double> res(k);
+            GKL_HIP(hipMemcpy(&s0, ritz.S, sizeof(double), hipMemcpyDeviceToHost));
+            GKL_HIP(hipMemcpy(res.data(), ritz.res, sizeof(double) * k, hipMemcpyDeviceToHost));
+            double r = 0.0;
+            for (int i = 0; i < k; ++i) r = std::max(r, s0 > 0 ? res[i] / s0 : 0.0);
+            trace.back()[6] = r;
+        }
+        if (nconv >= k) { converged = true; break; }
+        if (budget || j >= maxbasis) break;
         if (j == maxm) {
             if (krylov > 0) {
                 restart(j);
@@ -529,6 +621,7 @@ gkl_status gkl_solve(gkl_ctx* ctx, double* sigma, double* U, int64_t ldu, double
         ctx->info.solve_ms =
             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         ctx->info.create_ms = ctx->create_ms;
+        ctx->timing_collect();
         if (info) *info = ctx->info;
         if (st == GKL_NOT_CONVERGED) ctx->last_error = "tolerance not met within the matvec budget";
         return st;
@@ -543,6 +636,7 @@ void gkl_destroy(gkl_ctx* ctx)
 {
     if (!ctx) return;
     (void)hipStreamSynchronize(ctx->prob.stream);
+    for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     delete ctx;
 }
 
@@ -570,7 +664,7 @@ gkl_status gkl_unpack(gkl_ctx* ctx, int8_t* out)
     if (!ctx || ctx->batched || !out) return set_error(ctx, GKL_ERR_INVALID, "bad argument");
     try {
         hipStream_t s = ctx->prob.stream;
-        launch_unpack(ctx->prob.packed.G, ctx->prob.n, ctx->prob.p, ctx->prob.packed.ldp, out, s);
+        launch_unpack_layout(ctx->prob.packed, out, s);
         GKL_HIP(hipStreamSynchronize(s));
         return GKL_OK;
     } catch (const Error& e) {
@@ -583,7 +677,9 @@ gkl_status gkl_matvec(gkl_ctx* ctx, const double* v, double* y)
     if (!ctx || ctx->batched || !v || !y) return set_error(ctx, GKL_ERR_INVALID, "bad argument");
     try {
         hipStream_t s = ctx->prob.stream;
+        const int ev = ctx->timing_begin();
         launch_matvec(ctx->prob.packed, ctx->prob.st, v, y, nullptr, nullptr, ctx->prob.mvw, s);
+        ctx->timing_end(ev, false);
         GKL_HIP(hipStreamSynchronize(s));
         return GKL_OK;
     } catch (const Error& e) {
@@ -596,7 +692,9 @@ gkl_status gkl_rmatvec(gkl_ctx* ctx, const double* u, double* z)
     if (!ctx || ctx->batched || !u || !z) return set_error(ctx, GKL_ERR_INVALID, "bad argument");
     try {
         hipStream_t s = ctx->prob.stream;
+        const int ev = ctx->timing_begin();
         launch_rmatvec(ctx->prob.packed, ctx->prob.st, u, z, nullptr, nullptr, ctx->prob.mvw, s);
+        ctx->timing_end(ev, true);
         GKL_HIP(hipStreamSynchronize(s));
         return GKL_OK;
     } catch (const Error& e) {

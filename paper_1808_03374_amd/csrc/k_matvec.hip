@@ -4,189 +4,446 @@
 //   (A^T u)_j = s_j ( sum_i g_ij u_i - mu_j sum_i o_ij u_i )
 //
 // Section 3 of the paper: each Lanczos step applies A once and A^T once; these
-// two products are where the iteration spends its time.  Genotypes stay in
-// their 2-bit packed form in HBM and are decoded in registers; the dense
-// standardised matrix is never formed.
+// two products are where the iteration spends its time.  Genotypes stay 2-bit
+// packed in HBM; the dense standardised matrix is never formed.
 //
-// Both kernels stream the internal SNP-major layout (ldp bytes per column,
-// ldp % 256 == 0, padding codes = 3).  A lane owns 16 individuals (one 32-bit
-// word per column), so a wavefront reads 256 contiguous bytes per column.
-// Partial sums over column splits (A v) or individual chunks (A^T u) are
-// combined by the last block to arrive, in a fixed order (deterministic).
+// Both products use lookup tables in LDS so that one byte of four packed codes
+// costs one table read and one FP64 add:
+//   A v   -- layout T: byte (quad J, individual i) holds the codes of SNPs
+//            4J..4J+3 of individual i; for each quad J the 256-entry table
+//            L_J[b] = sum_k t_{4J+k}(code_k(b)), t_j(c) = (c - mu_j) s_j v_j for
+//            c < 3 and 0 for missing, is built in LDS and every lane adds
+//            L_J[byte] into the accumulator of its individual.
+//   A^T u -- layout P: byte (individual quad I, SNP j) holds the codes of
+//            individuals 4I..4I+3 of SNP j; for each quad I the table entry is the
+//            pair (sum_k g(c_k) u_{4I+k}, sum_k o(c_k) u_{4I+k}) and every lane adds
+//            it into the accumulators of its SNPs.
+// Tables of a quad are built from two 16-entry pair tables (one add per entry).
+// Wavefronts read 512 B or 1 KB contiguous per quad row.  Partial sums of the
+// K-splits go to a scratch buffer and a second kernel adds them in a fixed
+// order (deterministic, no atomics).
 #include "kernels.h"
 
 namespace gkl {
 
 namespace {
-
-constexpr int kThreads = 256;
-constexpr int kIndPerThread = 16;
-constexpr int kIndPerBlock = kThreads * kIndPerThread;   // 4096
-
-struct MvGrid {
-    unsigned int gx, gy;
-    int64_t cols_per_split;
-};
-
-MvGrid matvec_grid(const Packed& P)
-{
-    MvGrid g;
-    g.gx = ceil_div(P.ldp * 4, kIndPerBlock);
-    // aim for >= 2048 blocks so the 256 CUs stay busy
-    int64_t splits = (2048 + g.gx - 1) / g.gx;
-    if (splits > P.p) splits = P.p;
-    if (splits < 1) splits = 1;
-    g.cols_per_split = (P.p + splits - 1) / splits;
-    g.gy = (unsigned int)((P.p + g.cols_per_split - 1) / g.cols_per_split);
-    return g;
-}
-
-constexpr int64_t kRCols = 128;   // columns per block in A^T u
-
+constexpr int kMvThreads = 256;
+constexpr int kIPT = 16;                          // A v: individuals per thread (uint4)
+constexpr int kRowsPerWave = kWave * kIPT;        // 1024
+constexpr int kRowsPerBlock = kMvThreads * kIPT;  // 4096
+constexpr int kQCH = 16;                          // A v: SNP quads per table chunk
+constexpr int kSPT = 8;                           // A^T u: SNPs per thread (uint2)
+constexpr int kColsPerBlock = kMvThreads * kSPT;  // 2048
+constexpr int kQI = 8;                            // A^T u: individual quads per chunk
 }  // namespace
 
-size_t matvec_partial_elems(const Packed& P)
+int64_t layout_T_rows(int64_t n) { return ((n + kRowsPerWave - 1) / kRowsPerWave) * kRowsPerWave; }
+int64_t layout_P_cols(int64_t p) { return ((p + kColsPerBlock - 1) / kColsPerBlock) * kColsPerBlock; }
+
+// ---------------------------------------------------------------------------
+// Layout builders (create time)
+// ---------------------------------------------------------------------------
+
+// T[J * nT + i] = codes of SNPs 4J..4J+3 of individual i (2 bits each, SNP 4J in
+// the low bits); padding individuals and SNPs get code 3.  One thread makes the
+// 4 bytes of individuals 4I..4I+3 for quad J (a 4 x 4 transpose of 2-bit fields).
+__global__ void build_T_kernel(const uint8_t* __restrict__ G, int64_t n, int64_t p, int64_t ld,
+                               uint8_t* __restrict__ T, int64_t nT, int64_t Pq)
 {
-    MvGrid g = matvec_grid(P);
-    const size_t a = (size_t)g.gy * (size_t)g.gx * kIndPerBlock;       // A v partials
-    const size_t nchunks = (size_t)ceil_div(P.ldp * 4, kWave * kIndPerThread);
-    const size_t b = nchunks * (size_t)P.p * 2;                          // A^T u partials
-    return a > b ? a : b;
+    const int64_t nbT = nT / 4;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nbT * Pq) return;
+    const int64_t J = t / nbT;
+    const int64_t I = t - J * nbT;
+    const int64_t nb = (n + 3) / 4;
+    uint32_t in[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int64_t j = 4 * J + k;
+        uint32_t b = 0xFF;
+        if (j < p && I < nb) {
+            b = G[j * ld + I];
+            const int64_t valid = n - 4 * I;
+            if (valid < 4) b |= (0xFFu << (2 * valid)) & 0xFFu;
+        }
+        in[k] = b;
+    }
+    uint32_t out = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        uint32_t byte = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) byte |= ((in[k] >> (2 * r)) & 3u) << (2 * k);
+        out |= byte << (8 * r);
+    }
+    *reinterpret_cast<uint32_t*>(T + J * nT + 4 * I) = out;
 }
 
-size_t matvec_counters(const Packed& P)
+// P[I * pP + j] = byte I of SNP j (codes of individuals 4I..4I+3); padding is
+// code 3.  64 x 64 byte tiles transposed through LDS.
+__global__ void build_P_kernel(const uint8_t* __restrict__ G, int64_t n, int64_t p, int64_t ld,
+                               uint8_t* __restrict__ P, int64_t pP, int64_t nqP)
 {
-    MvGrid g = matvec_grid(P);
-    const size_t a = g.gx;
-    const size_t b = ceil_div(P.p, kRCols);
-    return a > b ? a : b;
+    __shared__ uint8_t tile[64][65];
+    const int64_t j0 = (int64_t)blockIdx.x * 64;     // SNPs
+    const int64_t I0 = (int64_t)blockIdx.y * 64;     // individual quads
+    const int64_t nb = (n + 3) / 4;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;   // 64 x 4
+    for (int r = ty; r < 64; r += 4) {
+        const int64_t j = j0 + r, I = I0 + tx;
+        uint32_t b = 0xFF;
+        if (j < p && I < nb) {
+            b = G[j * ld + I];
+            const int64_t valid = n - 4 * I;
+            if (valid < 4) b |= (0xFFu << (2 * valid)) & 0xFFu;
+        }
+        tile[r][tx] = (uint8_t)b;
+    }
+    __syncthreads();
+    for (int r = ty; r < 64; r += 4) {
+        const int64_t I = I0 + r, j = j0 + tx;
+        if (I < nqP && j < pP) P[I * pP + j] = tile[tx][r];
+    }
+}
+
+void layout_shape(int64_t n, int64_t p, Packed& L)
+{
+    L.n = n;
+    L.p = p;
+    L.nT = layout_T_rows(n);
+    L.Pq = (p + 3) / 4;
+    L.pP = layout_P_cols(p);
+    L.nq = (n + 3) / 4;
+    L.nqP = ((L.nq + kQI - 1) / kQI) * kQI;
+}
+
+size_t layout_T_bytes(const Packed& L) { return (size_t)L.nT * (size_t)L.Pq; }
+size_t layout_P_bytes(const Packed& L) { return (size_t)L.nqP * (size_t)L.pP; }
+
+void build_layouts(const uint8_t* G, int64_t ld, const Packed& L, hipStream_t s)
+{
+    const int64_t n = L.n, p = L.p;
+    uint8_t* T = const_cast<uint8_t*>(L.T);
+    uint8_t* P = const_cast<uint8_t*>(L.P);
+    const int64_t tT = (L.nT / 4) * L.Pq;
+    hipLaunchKernelGGL(build_T_kernel, dim3(ceil_div(tT, 256)), dim3(256), 0, s, G, n, p, ld, T,
+                       L.nT, L.Pq);
+    GKL_LAUNCH_CHECK("build_T_kernel");
+    int64_t done = 0;
+    const int64_t ytiles = (L.nqP + 63) / 64;
+    while (done < ytiles) {   // grid.y <= 65535
+        const int64_t chunk = ytiles - done < 65535 ? ytiles - done : 65535;
+        hipLaunchKernelGGL(build_P_kernel, dim3(ceil_div(L.pP, 64), (unsigned int)chunk),
+                           dim3(256), 0, s, G + done * 64, n - done * 256, p, ld,
+                           P + done * 64 * L.pP, L.pP, L.nqP - done * 64);
+        GKL_LAUNCH_CHECK("build_P_kernel");
+        done += chunk;
+    }
 }
 
 // ---------------------------------------------------------------------------
-// y = A v - beta * uprev
+// A v: partial[split][i] over the split's SNP quads
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kThreads)
-matvec_kernel(const uint32_t* __restrict__ G, int64_t n, int64_t p, int64_t ldw,
-              const double* __restrict__ mean, const double* __restrict__ inv_sd,
-              const double* __restrict__ v, int64_t cols_per_split, double* __restrict__ partial,
-              unsigned int* __restrict__ counters, double* __restrict__ y,
-              const double* __restrict__ beta, const double* __restrict__ uprev)
+__global__ void __launch_bounds__(kMvThreads)
+matvec_lut_kernel(const uint8_t* __restrict__ T, int64_t nT, int64_t p, int64_t Pq,
+                  const double* __restrict__ mean, const double* __restrict__ inv_sd,
+                  const double* __restrict__ v, int64_t quads_per_split,
+                  double* __restrict__ partial)
 {
-    const int64_t dw = (int64_t)blockIdx.x * kThreads + threadIdx.x;   // word within a column
-    const int64_t j0 = (int64_t)blockIdx.y * cols_per_split;
-    const int64_t j1 = j0 + cols_per_split < p ? j0 + cols_per_split : p;
-    double acc[kIndPerThread];
+    __shared__ double tv[kQCH * 4 * 4];          // t value per (SNP, code)
+    __shared__ double pairs[kQCH * 2 * 16];      // per quad: codes of SNPs (0,1) and (2,3)
+    __shared__ double lut[kQCH * 256];           // 32 KB
+    const int64_t row0 = (int64_t)blockIdx.x * kRowsPerBlock + (int64_t)threadIdx.x * kIPT;
+    const bool active = row0 < nT;
+    const int64_t Jb = (int64_t)blockIdx.y * quads_per_split;
+    const int64_t Je = Jb + quads_per_split < Pq ? Jb + quads_per_split : Pq;
+    double acc[kIPT];
 #pragma unroll
-    for (int k = 0; k < kIndPerThread; ++k) acc[k] = 0.0;
-    if (dw < ldw) {
-        const uint32_t* col = G + j0 * ldw + dw;
-        for (int64_t j = j0; j < j1; ++j, col += ldw) {
-            const double w = inv_sd[j] * v[j];
-            const double x = mean[j] * w;
-            const uint32_t word = *col;
+    for (int r = 0; r < kIPT; ++r) acc[r] = 0.0;
+
+    for (int64_t J0 = Jb; J0 < Je; J0 += kQCH) {
+        const int nq = (int)(Je - J0 < kQCH ? Je - J0 : kQCH);
+        uint4 d[kQCH];
 #pragma unroll
-            for (int k = 0; k < kIndPerThread; ++k) {
-                const uint32_t c = (word >> (2 * k)) & 3u;
-                const double t = fma((double)c, w, -x);
-                acc[k] += (c == 3u) ? 0.0 : t;
+        for (int q = 0; q < kQCH; ++q) {
+            if (active && q < nq) d[q] = *reinterpret_cast<const uint4*>(T + (J0 + q) * nT + row0);
+            else d[q] = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
+        }
+        {
+            const int s = threadIdx.x;               // 64 SNPs x 4 codes = 256 entries
+            const int64_t j = 4 * J0 + (s >> 2);
+            const int c = s & 3;
+            double val = 0.0;
+            if (j < p && c < 3 && (s >> 4) < nq) val = ((double)c - mean[j]) * inv_sd[j] * v[j];
+            tv[s] = val;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < kQCH * 32; e += kMvThreads) {
+            const int q = e >> 5, h = (e >> 4) & 1, x = e & 15;
+            const int sa = 4 * q + 2 * h;
+            pairs[e] = tv[sa * 4 + (x & 3)] + tv[(sa + 1) * 4 + (x >> 2)];
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < kQCH * 256; e += kMvThreads) {
+            const int q = e >> 8, b = e & 255;
+            lut[e] = pairs[q * 32 + (b & 15)] + pairs[q * 32 + 16 + (b >> 4)];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kQCH; ++q) {
+            const double* L = lut + q * 256;
+            const uint32_t w[4] = {d[q].x, d[q].y, d[q].z, d[q].w};
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) acc[4 * t + k] += L[(w[t] >> (8 * k)) & 0xFFu];
             }
         }
+        __syncthreads();
     }
-    const int64_t ind_per_split = (int64_t)gridDim.x * kIndPerBlock;
-    double* my = partial + (int64_t)blockIdx.y * ind_per_split + (int64_t)blockIdx.x * kIndPerBlock;
+    if (active) {
+        double* out = partial + (int64_t)blockIdx.y * nT + row0;
 #pragma unroll
-    for (int k = 0; k < kIndPerThread; ++k) my[threadIdx.x * kIndPerThread + k] = acc[k];
+        for (int r = 0; r < kIPT; r += 2)
+            *reinterpret_cast<double2*>(out + r) = make_double2(acc[r], acc[r + 1]);
+    }
+}
 
-    if (!last_block_arrived(&counters[blockIdx.x], gridDim.y)) return;
-    const double b = beta ? *beta : 0.0;
-    for (int t = threadIdx.x; t < kIndPerBlock; t += kThreads) {
-        const int64_t i = (int64_t)blockIdx.x * kIndPerBlock + t;
-        if (i >= n) break;
+// y[i] = sum over splits (fixed order within each of 8 split groups, then the
+// groups in order) - beta uprev[i]; 32 rows x 8 split groups per block.
+constexpr int kRedRows = 32;
+constexpr int kRedGroups = 8;
+
+__global__ void __launch_bounds__(kRedRows * kRedGroups)
+matvec_reduce_kernel(const double* __restrict__ partial, int64_t nT, int nsplit, int64_t n,
+                     double* __restrict__ y, const double* __restrict__ beta,
+                     const double* __restrict__ uprev)
+{
+    __shared__ double sh[kRedGroups][kRedRows];
+    const int r = threadIdx.x % kRedRows, g = threadIdx.x / kRedRows;
+    const int64_t i = (int64_t)blockIdx.x * kRedRows + r;
+    double a = 0.0;
+    if (i < n) {
+        int sp = g;
+        for (; sp + 3 * kRedGroups < nsplit; sp += 4 * kRedGroups) {
+            const double x0 = partial[(int64_t)sp * nT + i];
+            const double x1 = partial[(int64_t)(sp + kRedGroups) * nT + i];
+            const double x2 = partial[(int64_t)(sp + 2 * kRedGroups) * nT + i];
+            const double x3 = partial[(int64_t)(sp + 3 * kRedGroups) * nT + i];
+            a += x0;
+            a += x1;
+            a += x2;
+            a += x3;
+        }
+        for (; sp < nsplit; sp += kRedGroups) a += partial[(int64_t)sp * nT + i];
+    }
+    sh[g][r] = a;
+    __syncthreads();
+    if (g == 0 && i < n) {
         double s = 0.0;
-        for (unsigned int sp = 0; sp < gridDim.y; ++sp)
-            s += partial[(int64_t)sp * ind_per_split + (int64_t)blockIdx.x * kIndPerBlock + t];
-        if (uprev) s -= b * uprev[i];
+        for (int t = 0; t < kRedGroups; ++t) s += sh[t][r];
+        if (uprev) s -= (beta ? *beta : 0.0) * uprev[i];
         y[i] = s;
     }
 }
 
-void launch_matvec(const Packed& P, const ColStats& st, const double* v, double* y,
-                   const double* beta, const double* uprev, MatvecWork& w, hipStream_t s)
+// ---------------------------------------------------------------------------
+// A^T u: partial[split][j] = sum_i g u - mu_j sum_i o u over the split's quads
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kMvThreads)
+rmatvec_lut_kernel(const uint8_t* __restrict__ P, int64_t pP, int64_t n, int64_t nq, int64_t p,
+                   const double* __restrict__ u, const double* __restrict__ mean,
+                   int64_t iq_per_split, double* __restrict__ partial)
 {
-    MvGrid g = matvec_grid(P);
-    hipLaunchKernelGGL(matvec_kernel, dim3(g.gx, g.gy), dim3(kThreads), 0, s,
-                       reinterpret_cast<const uint32_t*>(P.G), P.n, P.p, P.ldp / 4, st.mean,
-                       st.inv_sd, v, g.cols_per_split, w.partial, w.counters, y, beta, uprev);
-    GKL_LAUNCH_CHECK("matvec_kernel");
+    __shared__ double uq[kQI * 4];
+    __shared__ double2 pairs[kQI * 2 * 16];
+    __shared__ double2 lut[kQI * 256];           // 32 KB
+    const int64_t col0 = (int64_t)blockIdx.x * kColsPerBlock + (int64_t)threadIdx.x * kSPT;
+    const int64_t Ib = (int64_t)blockIdx.y * iq_per_split;
+    const int64_t Ie = Ib + iq_per_split < nq ? Ib + iq_per_split : nq;
+    double sg[kSPT], so[kSPT];
+#pragma unroll
+    for (int k = 0; k < kSPT; ++k) { sg[k] = 0.0; so[k] = 0.0; }
+
+    for (int64_t I0 = Ib; I0 < Ie; I0 += kQI) {
+        const int nqc = (int)(Ie - I0 < kQI ? Ie - I0 : kQI);
+        uint2 d[kQI];
+#pragma unroll
+        for (int q = 0; q < kQI; ++q) {
+            if (q < nqc) d[q] = *reinterpret_cast<const uint2*>(P + (I0 + q) * pP + col0);
+            else d[q] = make_uint2(0xFFFFFFFFu, 0xFFFFFFFFu);
+        }
+        if (threadIdx.x < kQI * 4) {
+            const int64_t i = 4 * I0 + threadIdx.x;
+            uq[threadIdx.x] = (i < n && (int)(threadIdx.x >> 2) < nqc) ? u[i] : 0.0;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < kQI * 32; e += kMvThreads) {
+            const int q = e >> 5, h = (e >> 4) & 1, x = e & 15;
+            const int c0 = x & 3, c1 = x >> 2;
+            const double u0 = uq[4 * q + 2 * h], u1 = uq[4 * q + 2 * h + 1];
+            const double g0 = c0 == 3 ? 0.0 : (double)c0, g1 = c1 == 3 ? 0.0 : (double)c1;
+            const double o0 = c0 == 3 ? 0.0 : 1.0, o1 = c1 == 3 ? 0.0 : 1.0;
+            pairs[e] = make_double2(g0 * u0 + g1 * u1, o0 * u0 + o1 * u1);
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < kQI * 256; e += kMvThreads) {
+            const int q = e >> 8, b = e & 255;
+            const double2 lo = pairs[q * 32 + (b & 15)], hi = pairs[q * 32 + 16 + (b >> 4)];
+            lut[e] = make_double2(lo.x + hi.x, lo.y + hi.y);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kQI; ++q) {
+            const double2* L = lut + q * 256;
+            const uint32_t w[2] = {d[q].x, d[q].y};
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const double2 e = L[(w[t] >> (8 * k)) & 0xFFu];
+                    sg[4 * t + k] += e.x;
+                    so[4 * t + k] += e.y;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    double* out = partial + (int64_t)blockIdx.y * pP + col0;
+#pragma unroll
+    for (int k = 0; k < kSPT; k += 2) {
+        const int64_t j = col0 + k;
+        const double m0 = j < p ? mean[j] : 0.0;
+        const double m1 = j + 1 < p ? mean[j + 1] : 0.0;
+        *reinterpret_cast<double2*>(out + k) =
+            make_double2(sg[k] - m0 * so[k], sg[k + 1] - m1 * so[k + 1]);
+    }
 }
 
-// ---------------------------------------------------------------------------
-// z = A^T u - alpha * vprev
-// Block = 4 wavefronts; wavefront w of block x owns individual chunk 4x + w
-// (1024 individuals) and keeps its u values in registers across all columns
-// of the block's column group.
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kThreads)
-rmatvec_kernel(const uint32_t* __restrict__ G, int64_t n, int64_t p, int64_t ldw,
-               const double* __restrict__ mean, const double* __restrict__ inv_sd,
-               const double* __restrict__ u, int64_t nchunks, double* __restrict__ partial,
-               unsigned int* __restrict__ counters, double* __restrict__ z,
-               const double* __restrict__ alpha, const double* __restrict__ vprev)
+__global__ void rmatvec_reduce_kernel(const double* __restrict__ partial, int64_t pP, int nsplit,
+                                      int64_t p, const double* __restrict__ inv_sd,
+                                      double* __restrict__ z, const double* __restrict__ alpha,
+                                      const double* __restrict__ vprev)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t chunk = (int64_t)blockIdx.x * (kThreads / kWave) + threadIdx.x / kWave;
-    const int64_t dw = chunk * kWave + lane;
-    const int64_t j0 = (int64_t)blockIdx.y * kRCols;
-    const int64_t j1 = j0 + kRCols < p ? j0 + kRCols : p;
-    if (chunk < nchunks) {
-        double uu[kIndPerThread];
-#pragma unroll
-        for (int k = 0; k < kIndPerThread; ++k) {
-            const int64_t i = dw * kIndPerThread + k;
-            uu[k] = (dw < ldw && i < n) ? u[i] : 0.0;
-        }
-        for (int64_t j = j0; j < j1; ++j) {
-            const uint32_t word = dw < ldw ? G[j * ldw + dw] : 0xFFFFFFFFu;
-            double sg = 0.0, so = 0.0;
-#pragma unroll
-            for (int k = 0; k < kIndPerThread; ++k) {
-                const uint32_t c = (word >> (2 * k)) & 3u;
-                const bool obs = c != 3u;
-                sg = fma(obs ? (double)c : 0.0, uu[k], sg);
-                so += obs ? uu[k] : 0.0;
-            }
-            sg = wave_sum(sg);
-            so = wave_sum(so);
-            if (lane == 0) {
-                partial[(chunk * p + j) * 2 + 0] = sg;
-                partial[(chunk * p + j) * 2 + 1] = so;
-            }
-        }
-    }
-    if (!last_block_arrived(&counters[blockIdx.y], gridDim.x)) return;
     const double a = alpha ? *alpha : 0.0;
-    for (int64_t j = j0 + threadIdx.x; j < j1; j += kThreads) {
-        double sg = 0.0, so = 0.0;
-        for (int64_t c = 0; c < nchunks; ++c) {
-            sg += partial[(c * p + j) * 2 + 0];
-            so += partial[(c * p + j) * 2 + 1];
-        }
-        double r = inv_sd[j] * (sg - mean[j] * so);
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < p;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int sp = 0; sp < nsplit; ++sp) s += partial[(int64_t)sp * pP + j];
+        double r = inv_sd[j] * s;
         if (vprev) r -= a * vprev[j];
         z[j] = r;
     }
 }
 
-void launch_rmatvec(const Packed& P, const ColStats& st, const double* u, double* z,
+// ---------------------------------------------------------------------------
+// Launch geometry
+// ---------------------------------------------------------------------------
+namespace {
+struct Split {
+    int64_t per_split;
+    int nsplit;
+};
+
+// Split K (the contraction range, in quads) so that the grid has about `target`
+// blocks without making the partial-sum traffic a large share of the stream.
+Split choose_split(int64_t kquads, int64_t other_blocks, int64_t chunk, int64_t target,
+                   int64_t max_split)
+{
+    int64_t ns = (target + other_blocks - 1) / other_blocks;
+    if (ns > max_split) ns = max_split;
+    const int64_t max_by_chunk = (kquads + chunk - 1) / chunk;
+    if (ns > max_by_chunk) ns = max_by_chunk;
+    if (ns < 1) ns = 1;
+    int64_t per = (kquads + ns - 1) / ns;
+    per = ((per + chunk - 1) / chunk) * chunk;
+    Split s;
+    s.per_split = per;
+    s.nsplit = (int)((kquads + per - 1) / per);
+    return s;
+}
+
+Split mv_split(const Packed& L)
+{
+    const int64_t rowblocks = (L.nT + kRowsPerBlock - 1) / kRowsPerBlock;
+    // partial traffic nsplit * nT * 8 B kept near 5% of the packed bytes
+    int64_t cap = (L.Pq * 4) / 400;
+    if (cap < 1) cap = 1;
+    return choose_split(L.Pq, rowblocks, kQCH, 1536, cap);
+}
+
+Split rmv_split(const Packed& L)
+{
+    const int64_t colblocks = L.pP / kColsPerBlock;
+    int64_t cap = (L.nq * 4) / 640;
+    if (cap < 1) cap = 1;
+    return choose_split(L.nq, colblocks, kQI, 1536, cap);
+}
+}  // namespace
+
+size_t matvec_partial_elems(const Packed& L)
+{
+    const size_t a = (size_t)mv_split(L).nsplit * (size_t)L.nT;
+    const size_t b = (size_t)rmv_split(L).nsplit * (size_t)L.pP;
+    return a > b ? a : b;
+}
+
+size_t matvec_counters(const Packed&) { return 1; }
+
+void launch_matvec(const Packed& L, const ColStats& st, const double* v, double* y,
+                   const double* beta, const double* uprev, MatvecWork& w, hipStream_t s)
+{
+    const Split sp = mv_split(L);
+    dim3 grid((unsigned int)((L.nT + kRowsPerBlock - 1) / kRowsPerBlock), (unsigned int)sp.nsplit);
+    hipLaunchKernelGGL(matvec_lut_kernel, grid, dim3(kMvThreads), 0, s, L.T, L.nT, L.p, L.Pq,
+                       st.mean, st.inv_sd, v, sp.per_split, w.partial);
+    GKL_LAUNCH_CHECK("matvec_lut_kernel");
+    hipLaunchKernelGGL(matvec_reduce_kernel, dim3(ceil_div(L.n, kRedRows)),
+                       dim3(kRedRows * kRedGroups), 0, s, w.partial, L.nT, sp.nsplit, L.n, y, beta,
+                       uprev);
+    GKL_LAUNCH_CHECK("matvec_reduce_kernel");
+}
+
+void launch_rmatvec(const Packed& L, const ColStats& st, const double* u, double* z,
                     const double* alpha, const double* vprev, MatvecWork& w, hipStream_t s)
 {
-    const int64_t ldw = P.ldp / 4;
-    const int64_t nchunks = (ldw + kWave - 1) / kWave;
-    dim3 grid(ceil_div(nchunks, kThreads / kWave), ceil_div(P.p, kRCols));
-    hipLaunchKernelGGL(rmatvec_kernel, grid, dim3(kThreads), 0, s,
-                       reinterpret_cast<const uint32_t*>(P.G), P.n, P.p, ldw, st.mean, st.inv_sd,
-                       u, nchunks, w.partial, w.counters, z, alpha, vprev);
-    GKL_LAUNCH_CHECK("rmatvec_kernel");
+    const Split sp = rmv_split(L);
+    dim3 grid((unsigned int)(L.pP / kColsPerBlock), (unsigned int)sp.nsplit);
+    hipLaunchKernelGGL(rmatvec_lut_kernel, grid, dim3(kMvThreads), 0, s, L.P, L.pP, L.n, L.nq, L.p,
+                       u, st.mean, sp.per_split, w.partial);
+    GKL_LAUNCH_CHECK("rmatvec_lut_kernel");
+    unsigned int nb = ceil_div(L.p, 256);
+    if (nb > 2048) nb = 2048;
+    hipLaunchKernelGGL(rmatvec_reduce_kernel, dim3(nb), dim3(256), 0, s, w.partial, L.pP,
+                       sp.nsplit, L.p, st.inv_sd, z, alpha, vprev);
+    GKL_LAUNCH_CHECK("rmatvec_reduce_kernel");
+}
+
+// Unpack from layout T to n x p column-major int8 (-1 = missing).
+__global__ void unpack_T_kernel(const uint8_t* __restrict__ T, int64_t nT, int64_t n, int64_t p,
+                                int64_t Pq, int8_t* __restrict__ out)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * Pq) return;
+    const int64_t J = t / n;
+    const int64_t i = t - J * n;
+    const uint32_t b = T[J * nT + i];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int64_t j = 4 * J + k;
+        if (j < p) {
+            const int c = (b >> (2 * k)) & 3;
+            out[j * n + i] = (int8_t)(c == 3 ? -1 : c);
+        }
+    }
+}
+
+void launch_unpack_layout(const Packed& L, int8_t* out, hipStream_t s)
+{
+    const int64_t total = L.n * L.Pq;
+    hipLaunchKernelGGL(unpack_T_kernel, dim3(ceil_div(total, 256)), dim3(256), 0, s, L.T, L.nT, L.n,
+                       L.p, L.Pq, out);
+    GKL_LAUNCH_CHECK("unpack_T_kernel");
 }
 
 }  // namespace gkl

@@ -17,133 +17,195 @@
 namespace gkl {
 
 namespace {
-constexpr int kOT = 256;     // threads per block
-constexpr int kORows = 2;    // rows per thread
-constexpr int kORowsPerBlock = kOT * kORows;
+constexpr int kOT = 256;      // threads per block
+constexpr int kPC = 16;       // projection: columns per block
+constexpr int kPR = 4;        // projection: rows per thread
+constexpr int kPRows = kOT * kPR;
+constexpr int kNR = 4;        // norm / update: rows per thread
+constexpr int kNRows = kOT * kNR;
 }  // namespace
 
 size_t ortho_partial_elems(int64_t len, int maxcols)
 {
-    return (size_t)ceil_div(len, kORowsPerBlock) * (size_t)(maxcols + 2);
+    const size_t rb = (size_t)ceil_div(len, kPRows);
+    const size_t a = rb * (size_t)(((maxcols + kPC - 1) / kPC) * kPC);
+    const size_t b = (size_t)ceil_div(len, kNRows) + 1;
+    return a > b ? a : b;
 }
 
-// One pass over the rows of r:
-//   if hin:        r <- r - Q hin      (hin: ncols, skipped when *skip != 0)
-//   if hout:       partials of Q^T r   -> hout (ncols) by the last block
-//   if nrm2_out:   partial of ||r||^2  -> *nrm2_out by the last block
-// After the reduction the last block may apply the adaptive test: when
-// adapt_ref (||r_before||^2) is given and ||r||^2 >= adapt_ref / 2 it sets
-// *skip_next = 1 (no second pass), else 0 and counts a pass.
+// h = Q^T r for the 16 columns of blockIdx.y; blocks over rows write partials,
+// the last block of each column group sums them in row-block order.
 __global__ void __launch_bounds__(kOT)
-ortho_pass_kernel(const double* __restrict__ Q, int64_t ldq, int64_t len, int ncols,
-                  double* __restrict__ r, const int* __restrict__ enable,
-                  const double* __restrict__ hin, const int* __restrict__ skip,
-                  double* __restrict__ hout, double* __restrict__ nrm2_out,
-                  const double* __restrict__ adapt_ref, int* __restrict__ skip_next,
-                  int* __restrict__ passes, double* __restrict__ partial,
-                  unsigned int* __restrict__ counter)
+proj_kernel(const double* __restrict__ Q, int64_t ldq, int64_t len, int ncols,
+            const double* __restrict__ r, const int* __restrict__ enable,
+            const int* __restrict__ skip, double* __restrict__ h, double* __restrict__ partial,
+            unsigned int* __restrict__ counters)
 {
     if (enable && *enable == 0) return;
-    extern __shared__ double sh[];          // ncols (hin) + 4 * (ncols + 1) wave partials
-    double* hs = sh;
-    double* wp = sh + ncols;
-    const int lane = threadIdx.x & 63;
-    const int wid = threadIdx.x >> 6;
-    const int64_t row0 = (int64_t)blockIdx.x * kORowsPerBlock + threadIdx.x;
-    double rv[kORows];
+    if (skip && *skip) return;
+    __shared__ double red[kOT / 64][kPC];
+    const int c0 = blockIdx.y * kPC;
+    const int nc = ncols - c0 < kPC ? ncols - c0 : kPC;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    double rv[kPR];
+    int64_t rows[kPR];
 #pragma unroll
-    for (int t = 0; t < kORows; ++t) {
-        const int64_t row = row0 + t * kOT;
-        rv[t] = row < len ? r[row] : 0.0;
+    for (int t = 0; t < kPR; ++t) {
+        rows[t] = (int64_t)blockIdx.x * kPRows + t * kOT + threadIdx.x;
+        rv[t] = rows[t] < len ? r[rows[t]] : 0.0;
     }
-    const bool do_update = hin != nullptr && !(skip && *skip);
-    if (do_update) {
-        for (int c = threadIdx.x; c < ncols; c += kOT) hs[c] = hin[c];
-        __syncthreads();
-        for (int c = 0; c < ncols; ++c) {
-            const double hc = hs[c];
-            const double* qc = Q + (int64_t)c * ldq;
+    double acc[kPC];
 #pragma unroll
-            for (int t = 0; t < kORows; ++t) {
-                const int64_t row = row0 + t * kOT;
-                if (row < len) rv[t] = fma(-qc[row], hc, rv[t]);
-            }
-        }
-#pragma unroll
-        for (int t = 0; t < kORows; ++t) {
-            const int64_t row = row0 + t * kOT;
-            if (row < len) r[row] = rv[t];
-        }
-    }
-    const int nout = (hout ? ncols : 0) + (nrm2_out ? 1 : 0);
-    if (nout == 0) return;
-    if (hout) {
-        for (int c = 0; c < ncols; ++c) {
-            const double* qc = Q + (int64_t)c * ldq;
-            double a = 0.0;
-#pragma unroll
-            for (int t = 0; t < kORows; ++t) {
-                const int64_t row = row0 + t * kOT;
-                if (row < len) a = fma(qc[row], rv[t], a);
-            }
-            a = wave_sum(a);
-            if (lane == 0) wp[wid * (ncols + 1) + c] = a;
-        }
-    }
-    if (nrm2_out) {
+    for (int c = 0; c < kPC; ++c) {
         double a = 0.0;
+        if (c < nc) {
+            const double* qc = Q + (int64_t)(c0 + c) * ldq;
 #pragma unroll
-        for (int t = 0; t < kORows; ++t) a = fma(rv[t], rv[t], a);
-        a = wave_sum(a);
-        if (lane == 0) wp[wid * (ncols + 1) + ncols] = a;
+            for (int t = 0; t < kPR; ++t)
+                if (rows[t] < len) a = fma(qc[rows[t]], rv[t], a);
+        }
+        acc[c] = a;
+    }
+#pragma unroll
+    for (int c = 0; c < kPC; ++c) {
+        const double a = wave_sum(acc[c]);
+        if (lane == 0) red[wid][c] = a;
     }
     __syncthreads();
-    const int stride = ncols + 1;
-    for (int c = threadIdx.x; c < stride; c += kOT) {
-        if (c < ncols && !hout) continue;
-        if (c == ncols && !nrm2_out) continue;
+    const int64_t stride = (int64_t)gridDim.y * kPC;
+    if (threadIdx.x < kPC) {
         double a = 0.0;
-        for (int w = 0; w < kOT / 64; ++w) a += wp[w * stride + c];
-        partial[(int64_t)blockIdx.x * stride + c] = a;
+        for (int w = 0; w < kOT / 64; ++w) a += red[w][threadIdx.x];
+        partial[(int64_t)blockIdx.x * stride + c0 + threadIdx.x] = a;
     }
-    if (!last_block_arrived(counter, gridDim.x)) return;
-    for (int c = threadIdx.x; c < stride; c += kOT) {
-        if (c < ncols && !hout) continue;
-        if (c == ncols && !nrm2_out) continue;
+    if (!last_block_arrived(&counters[blockIdx.y], gridDim.x)) return;
+    // final sum over row blocks: 16 groups of threads per column, fixed order
+    __shared__ double fin[kOT / kPC][kPC];
+    {
+        const int col = threadIdx.x % kPC, grp = threadIdx.x / kPC;
         double a = 0.0;
-        for (unsigned int b = 0; b < gridDim.x; ++b) a += partial[(int64_t)b * stride + c];
-        if (c < ncols) hout[c] = a;
-        else *nrm2_out = a;
-    }
-    if (threadIdx.x == 0 && skip_next) {
-        // nrm2_out holds ||r after first pass||^2 here; adapt_ref the norm before it
-        __threadfence_block();
+        for (unsigned int b = grp; b < gridDim.x; b += kOT / kPC)
+            a += partial[(int64_t)b * stride + c0 + col];
+        fin[grp][col] = a;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        if (skip_next && adapt_ref && nrm2_out) {
-            const double after = *nrm2_out;
-            const int sk = (after >= 0.5 * (*adapt_ref)) ? 1 : 0;
-            *skip_next = sk;
-            if (passes) *passes += sk ? 1 : 2;
-        } else if (passes && hin == nullptr && hout) {
-            // non-adaptive: counted once per CGS2 call by the first pass
-            *passes += 2;
-        }
+    if (threadIdx.x < nc) {
+        double a = 0.0;
+        for (int g = 0; g < kOT / kPC; ++g) a += fin[g][threadIdx.x];
+        h[c0 + threadIdx.x] = a;
     }
 }
 
-static void ortho_pass(const double* Q, int64_t ldq, int64_t len, int ncols, double* r,
-                       const int* enable, const double* hin, const int* skip, double* hout,
-                       double* nrm2_out, const double* adapt_ref, int* skip_next, int* passes,
-                       OrthoWork& w, hipStream_t s)
+// r <- r - Q h (all columns); optional partial ||r||^2 reduced by the last block.
+__global__ void __launch_bounds__(kOT)
+update_kernel(const double* __restrict__ Q, int64_t ldq, int64_t len, int ncols,
+              double* __restrict__ r, const double* __restrict__ h, const int* __restrict__ enable,
+              const int* __restrict__ skip)
 {
-    const unsigned int nb = ceil_div(len, kORowsPerBlock);
-    const size_t shmem = sizeof(double) * ((size_t)ncols + 4 * ((size_t)ncols + 1));
-    hipLaunchKernelGGL(ortho_pass_kernel, dim3(nb), dim3(kOT), shmem, s, Q, ldq, len, ncols, r,
-                       enable, hin, skip, hout, nrm2_out, adapt_ref, skip_next, passes, w.partial,
-                       w.counters);
-    GKL_LAUNCH_CHECK("ortho_pass_kernel");
+    if (enable && *enable == 0) return;
+    if (skip && *skip) return;
+    extern __shared__ double hs[];
+    for (int c = threadIdx.x; c < ncols; c += kOT) hs[c] = h[c];
+    __syncthreads();
+    const int64_t row = (int64_t)blockIdx.x * kOT + threadIdx.x;
+    if (row >= len) return;
+    double a = r[row];
+    int c = 0;
+    for (; c + 8 <= ncols; c += 8) {
+        double q[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) q[t] = Q[(int64_t)(c + t) * ldq + row];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) a = fma(-q[t], hs[c + t], a);
+    }
+    for (; c < ncols; ++c) a = fma(-Q[(int64_t)c * ldq + row], hs[c], a);
+    r[row] = a;
+}
+
+// ||r||^2 by blocks, the last block finishes: nrm = sqrt; breakdown test against
+// eps * max(norm_est, nrm) * root_maxdim; writes *nrm_out (0 on breakdown), the
+// flag, and updates norm_est.  With decide == 0 it only writes sqrt into nrm_out.
+__global__ void __launch_bounds__(kOT)
+norm_kernel(const double* __restrict__ r, int64_t len, double* __restrict__ nrm_out,
+            double* __restrict__ norm_est, double root_maxdim, int* __restrict__ flag,
+            int* __restrict__ first_breakdown, int step, int decide, double* __restrict__ partial,
+            unsigned int* __restrict__ counter)
+{
+    __shared__ double sh[16];
+    double a = 0.0;
+#pragma unroll
+    for (int t = 0; t < kNR; ++t) {
+        const int64_t row = (int64_t)blockIdx.x * kNRows + t * kOT + threadIdx.x;
+        if (row < len) {
+            const double x = r[row];
+            a = fma(x, x, a);
+        }
+    }
+    a = block_sum(a, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = a;
+    if (!last_block_arrived(counter, gridDim.x)) return;
+    double t2 = 0.0;
+    for (unsigned int b = threadIdx.x; b < gridDim.x; b += kOT) t2 += partial[b];
+    t2 = block_sum(t2, sh);
+    if (threadIdx.x == 0) {
+        const double nrm = sqrt(t2);
+        if (!decide) {
+            *nrm_out = nrm;
+            return;
+        }
+        double est = *norm_est;
+        if (nrm > est) est = nrm;
+        const double thresh = 2.220446049250313e-16 * est * root_maxdim;
+        if (nrm <= thresh) {
+            *nrm_out = 0.0;
+            *flag = 1;
+            if (first_breakdown && *first_breakdown < 0) *first_breakdown = step;
+        } else {
+            *nrm_out = nrm;
+            *flag = 0;
+        }
+        *norm_est = est;
+    }
+}
+
+static void launch_proj(const double* Q, int64_t ldq, int64_t len, int ncols, const double* r,
+                        const int* enable, const int* skip, double* h, OrthoWork& w, hipStream_t s)
+{
+    dim3 grid(ceil_div(len, kPRows), ceil_div(ncols, kPC));
+    hipLaunchKernelGGL(proj_kernel, grid, dim3(kOT), 0, s, Q, ldq, len, ncols, r, enable, skip, h,
+                       w.partial, w.counters);
+    GKL_LAUNCH_CHECK("proj_kernel");
+}
+
+static void launch_update(const double* Q, int64_t ldq, int64_t len, int ncols, double* r,
+                          const double* h, const int* enable, const int* skip, hipStream_t s)
+{
+    hipLaunchKernelGGL(update_kernel, dim3(ceil_div(len, kOT)), dim3(kOT),
+                       sizeof(double) * (size_t)ncols, s, Q, ldq, len, ncols, r, h, enable, skip);
+    GKL_LAUNCH_CHECK("update_kernel");
+}
+
+__global__ void adapt_decide_kernel(const double* __restrict__ n0, const double* __restrict__ n1,
+                                    int* __restrict__ skip, int* __restrict__ passes,
+                                    const int* __restrict__ enable)
+{
+    if (enable && *enable == 0) return;
+    const int sk = (*n1) >= 0.7071067811865476 * (*n0) ? 1 : 0;
+    *skip = sk;
+    if (passes) *passes += sk ? 1 : 2;
+}
+
+__global__ void count_passes_kernel(int* __restrict__ passes, const int* __restrict__ enable)
+{
+    if (enable && *enable == 0) return;
+    *passes += 2;
+}
+
+void launch_norm_raw(const double* r, int64_t len, double* out, OrthoWork& w, hipStream_t s)
+{
+    hipLaunchKernelGGL(norm_kernel, dim3(ceil_div(len, kNRows)), dim3(kOT), 0, s, r, len, out,
+                       nullptr, 1.0, nullptr, nullptr, 0, 0, w.partial, w.counters + 1);
+    GKL_LAUNCH_CHECK("norm_kernel");
 }
 
 void launch_cgs2(const double* Q, int64_t ldq, int64_t len, int ncols, double* r,
@@ -151,50 +213,33 @@ void launch_cgs2(const double* Q, int64_t ldq, int64_t len, int ncols, double* r
 {
     if (ncols <= 0) return;
     double* h1 = w.h;
-    double* h2 = w.h + (ncols + 1);
-    double* n0 = w.h + 2 * (ncols + 1);
+    double* n0 = w.h + (ncols + 1);
     double* n1 = n0 + 1;
     int* skip = reinterpret_cast<int*>(n0 + 2);
     if (adaptive) {
-        // pass 1: h1 = Q^T r, ||r||^2
-        ortho_pass(Q, ldq, len, ncols, r, enable, nullptr, nullptr, h1, n0, nullptr, nullptr,
-                   nullptr, w, s);
-        // pass 2: r -= Q h1; h2 = Q^T r; ||r||^2; decide whether a second update is needed
-        ortho_pass(Q, ldq, len, ncols, r, enable, h1, nullptr, h2, n1, n0, skip, passes, w, s);
-        // pass 3: r -= Q h2 unless skipped
-        ortho_pass(Q, ldq, len, ncols, r, enable, h2, skip, nullptr, nullptr, nullptr, nullptr,
-                   nullptr, w, s);
+        launch_norm_raw(r, len, n0, w, s);
+        launch_proj(Q, ldq, len, ncols, r, enable, nullptr, h1, w, s);
+        launch_update(Q, ldq, len, ncols, r, h1, enable, nullptr, s);
+        launch_norm_raw(r, len, n1, w, s);
+        hipLaunchKernelGGL(adapt_decide_kernel, dim3(1), dim3(1), 0, s, n0, n1, skip, passes, enable);
+        GKL_LAUNCH_CHECK("adapt_decide_kernel");
+        launch_proj(Q, ldq, len, ncols, r, enable, skip, h1, w, s);
+        launch_update(Q, ldq, len, ncols, r, h1, enable, skip, s);
     } else {
-        ortho_pass(Q, ldq, len, ncols, r, enable, nullptr, nullptr, h1, nullptr, nullptr,
-                   nullptr, passes, w, s);
-        ortho_pass(Q, ldq, len, ncols, r, enable, h1, nullptr, h2, nullptr, nullptr, nullptr,
-                   nullptr, w, s);
-        ortho_pass(Q, ldq, len, ncols, r, enable, h2, nullptr, nullptr, nullptr, nullptr,
-                   nullptr, nullptr, w, s);
+        launch_proj(Q, ldq, len, ncols, r, enable, nullptr, h1, w, s);
+        launch_update(Q, ldq, len, ncols, r, h1, enable, nullptr, s);
+        launch_proj(Q, ldq, len, ncols, r, enable, nullptr, h1, w, s);
+        launch_update(Q, ldq, len, ncols, r, h1, enable, nullptr, s);
+        if (passes) {
+            hipLaunchKernelGGL(count_passes_kernel, dim3(1), dim3(1), 0, s, passes, enable);
+            GKL_LAUNCH_CHECK("count_passes_kernel");
+        }
     }
 }
 
 // ---------------------------------------------------------------------------
 // Normalisation with breakdown test
 // ---------------------------------------------------------------------------
-__global__ void normalize_decide_kernel(const double* __restrict__ nrm2, double* __restrict__ nrm_out,
-                                        double* __restrict__ norm_est, double root_maxdim,
-                                        int* __restrict__ flag)
-{
-    const double nrm = sqrt(*nrm2);
-    double est = *norm_est;
-    if (nrm > est) est = nrm;
-    const double thresh = 2.220446049250313e-16 * est * root_maxdim;
-    if (nrm <= thresh) {
-        *nrm_out = 0.0;
-        *flag = 1;
-    } else {
-        *nrm_out = nrm;
-        *flag = 0;
-    }
-    *norm_est = est;
-}
-
 __global__ void scale_kernel(const double* __restrict__ r, int64_t len, double* __restrict__ out,
                              const double* __restrict__ nrm)
 {
@@ -206,29 +251,19 @@ __global__ void scale_kernel(const double* __restrict__ r, int64_t len, double* 
         out[i] = r[i] * inv;
 }
 
-__global__ void sqrt_kernel(const double* __restrict__ a, double* __restrict__ out)
-{
-    *out = sqrt(*a);
-}
-
 void launch_norm(const double* r, int64_t len, double* out, OrthoWork& w, hipStream_t s)
 {
-    double* n2 = w.h + 1;
-    ortho_pass(nullptr, 0, len, 0, const_cast<double*>(r), nullptr, nullptr, nullptr, nullptr, n2,
-               nullptr, nullptr, nullptr, w, s);
-    hipLaunchKernelGGL(sqrt_kernel, dim3(1), dim3(1), 0, s, n2, out);
-    GKL_LAUNCH_CHECK("sqrt_kernel");
+    launch_norm_raw(r, len, out, w, s);
 }
 
 void launch_normalize(double* r, int64_t len, double* out, double* nrm_out, double* norm_est,
-                      double root_maxdim, int* flag, OrthoWork& w, hipStream_t s)
+                      double root_maxdim, int* flag, OrthoWork& w, hipStream_t s,
+                      int* first_breakdown, int step)
 {
-    double* n2 = w.h + 0;
-    ortho_pass(nullptr, 0, len, 0, r, nullptr, nullptr, nullptr, nullptr, n2, nullptr, nullptr,
-               nullptr, w, s);
-    hipLaunchKernelGGL(normalize_decide_kernel, dim3(1), dim3(1), 0, s, n2, nrm_out, norm_est,
-                       root_maxdim, flag);
-    GKL_LAUNCH_CHECK("normalize_decide_kernel");
+    hipLaunchKernelGGL(norm_kernel, dim3(ceil_div(len, kNRows)), dim3(kOT), 0, s, r, len, nrm_out,
+                       norm_est, root_maxdim, flag, first_breakdown, step, 1, w.partial,
+                       w.counters + 1);
+    GKL_LAUNCH_CHECK("norm_kernel");
     unsigned int nb = ceil_div(len, 256);
     if (nb > 2048) nb = 2048;
     hipLaunchKernelGGL(scale_kernel, dim3(nb), dim3(256), 0, s, r, len, out, nrm_out);

@@ -108,44 +108,3 @@ void launch_unpack(const uint8_t* G, int64_t n, int64_t p, int64_t ld, int8_t* o
 
 }  // namespace gkl
 
-namespace gkl {
-
-// Copy the caller's packed matrix (ld bytes per column) into the internal
-// layout (ldp bytes per column, ldp a multiple of 256).  Codes of padded
-// individuals i >= n and padding bytes become 3 (missing) so they contribute
-// nothing to either product.
-__global__ void repack_kernel(const uint8_t* __restrict__ G, int64_t n, int64_t ld,
-                              uint8_t* __restrict__ out, int64_t ldp)
-{
-    const int64_t j = blockIdx.y;
-    const int64_t nb = (n + 3) / 4;
-    const uint8_t* src = G + j * ld;
-    uint8_t* dst = out + j * ldp;
-    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < ldp;
-         b += (int64_t)gridDim.x * blockDim.x) {
-        uint32_t v = 0xFF;
-        if (b < nb) {
-            v = src[b];
-            const int64_t valid = n - 4 * b;   // >= 1
-            if (valid < 4) v |= (0xFFu << (2 * valid)) & 0xFFu;
-        }
-        dst[b] = (uint8_t)v;
-    }
-}
-
-void launch_repack(const uint8_t* G, int64_t n, int64_t p, int64_t ld, uint8_t* out,
-                   int64_t ldp, hipStream_t s)
-{
-    int64_t y = p;
-    int64_t done = 0;
-    while (done < y) {   // grid.y is limited to 65535
-        const int64_t chunk = (y - done) < 65535 ? (y - done) : 65535;
-        dim3 grid(ceil_div(ldp, 256) < 8 ? ceil_div(ldp, 256) : 8, (unsigned int)chunk);
-        hipLaunchKernelGGL(repack_kernel, grid, dim3(256), 0, s, G + done * ld, n, ld,
-                           out + done * ldp, ldp);
-        GKL_LAUNCH_CHECK("repack_kernel");
-        done += chunk;
-    }
-}
-
-}  // namespace gkl

@@ -14,13 +14,19 @@ struct ColStats {
     double* inv_sd;   // s_j
 };
 
-// Internal copy of the genotype matrix: SNP-major, ldp bytes per column with
-// ldp a multiple of 256 and every padding code set to 3 (missing), so padded
-// individuals contribute exactly zero without masking in the hot loops.
+// Internal copies of the genotype matrix, built once at create.  Padding codes
+// are 3 (missing), so padded individuals and SNPs contribute exactly zero
+// without masking in the hot loops.
+//   T: nT x Pq bytes; T[J * nT + i] = codes of SNPs 4J..4J+3 of individual i
+//      (feeds A v: one byte = four SNPs of one individual)
+//   P: nqP x pP bytes; P[I * pP + j] = codes of individuals 4I..4I+3 of SNP j
+//      (feeds A^T u: one byte = four individuals of one SNP)
 struct Packed {
-    const uint8_t* G = nullptr;   // device, p * ldp bytes
+    const uint8_t* T = nullptr;
+    const uint8_t* P = nullptr;
     int64_t n = 0, p = 0;
-    int64_t ldp = 0;              // bytes per SNP column
+    int64_t nT = 0, Pq = 0;       // rows (padded individuals), SNP quads of T
+    int64_t pP = 0, nq = 0, nqP = 0;  // padded SNPs, individual quads (real, padded) of P
 };
 
 // Device scratch used by the two-stage reductions of the matvec kernels.
@@ -36,8 +42,13 @@ void launch_colstats(const uint8_t* G, int64_t n, int64_t p, int64_t ld, const C
                      hipStream_t s);
 void launch_unpack(const uint8_t* G, int64_t n, int64_t p, int64_t ld, int8_t* out,
                    hipStream_t s);
-void launch_repack(const uint8_t* G, int64_t n, int64_t p, int64_t ld, uint8_t* out,
-                   int64_t ldp, hipStream_t s);
+// Layout shapes, sizes and the builders (from the caller's SNP-major G).
+void layout_shape(int64_t n, int64_t p, Packed& L);
+size_t layout_T_bytes(const Packed& L);
+size_t layout_P_bytes(const Packed& L);
+void build_layouts(const uint8_t* G, int64_t ld, const Packed& L, hipStream_t s);
+// Unpack from the internal layout to n x p column-major int8, -1 = missing.
+void launch_unpack_layout(const Packed& L, int8_t* out, hipStream_t s);
 
 // ---- k_matvec.hip: FP64 products with the implicit standardised matrix ----
 // y = A v - (beta ? *beta : 0) * uprev      (y, uprev: n; v: p)
@@ -67,8 +78,10 @@ void launch_cgs2(const double* Q, int64_t ldq, int64_t len, int ncols, double* r
 // nrm = ||r||; if nrm <= thresh(*) then breakdown: *flag = 1 and nrm stored as 0,
 // r left unscaled; else out = r / nrm (out may alias r).
 //   thresh = eps * max(*norm_est, nrm) * sqrt(max_dim); *norm_est updated.
+// On breakdown, *first_breakdown (if not NULL and still < 0) receives `step`.
 void launch_normalize(double* r, int64_t len, double* out, double* nrm_out, double* norm_est,
-                      double root_maxdim, int* flag, OrthoWork& w, hipStream_t s);
+                      double root_maxdim, int* flag, OrthoWork& w, hipStream_t s,
+                      int* first_breakdown = nullptr, int step = 0);
 // y -= Q(:, 0:ncols) * c  (c device, ncols)
 void launch_gemv_n_sub(const double* Q, int64_t ldq, int64_t len, int ncols, const double* c,
                        double* y, hipStream_t s);
