@@ -24,11 +24,13 @@ struct DeviceArena {
 struct Problem {
     DeviceArena arena;
     int64_t n = 0, p = 0, ld = 0;
+    const uint8_t* G_user = nullptr;   // the caller's matrix (borrowed)
     hipStream_t stream = nullptr;
     Packed packed;
     ColStats st{};
     MatvecWork mvw;
-    void setup(const uint8_t* G, int64_t n, int64_t p, int64_t ld, hipStream_t s);
+    // lut_layouts: build the two lookup-table layouts of the FP64 products
+    void setup(const uint8_t* G, int64_t n, int64_t p, int64_t ld, hipStream_t s, bool lut_layouts);
 };
 
 // ||r|| into *out (no scaling).

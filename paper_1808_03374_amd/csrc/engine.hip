@@ -59,22 +59,27 @@ DeviceArena::~DeviceArena()
 // ---------------------------------------------------------------------------
 // Problem setup
 // ---------------------------------------------------------------------------
-void Problem::setup(const uint8_t* G, int64_t n_, int64_t p_, int64_t ld_, hipStream_t s)
+void Problem::setup(const uint8_t* G, int64_t n_, int64_t p_, int64_t ld_, hipStream_t s,
+                    bool lut_layouts)
 {
     n = n_;
     p = p_;
     ld = ld_;
+    G_user = G;
     stream = s;
     layout_shape(n, p, packed);
-    packed.T = static_cast<uint8_t*>(arena.alloc(layout_T_bytes(packed)));
-    packed.P = static_cast<uint8_t*>(arena.alloc(layout_P_bytes(packed)));
-    build_layouts(G, ld, packed, s);
+    if (lut_layouts) {
+        packed.T = static_cast<uint8_t*>(arena.alloc(layout_T_bytes(packed)));
+        packed.P = static_cast<uint8_t*>(arena.alloc(layout_P_bytes(packed)));
+        build_layouts(G, ld, packed, s);
+    }
     st.count = static_cast<int64_t*>(arena.alloc(sizeof(int64_t) * p));
     st.nobs = static_cast<int64_t*>(arena.alloc(sizeof(int64_t) * p));
     st.n3 = static_cast<int64_t*>(arena.alloc(sizeof(int64_t) * p));
     st.mean = static_cast<double*>(arena.alloc(sizeof(double) * p));
     st.inv_sd = static_cast<double*>(arena.alloc(sizeof(double) * p));
     launch_colstats(G, n, p, ld, st, s);
+    if (!lut_layouts) return;
     mvw.partial_elems = matvec_partial_elems(packed);
     mvw.partial = static_cast<double*>(arena.alloc(sizeof(double) * mvw.partial_elems));
     mvw.ncounters = matvec_counters(packed);
@@ -568,7 +573,7 @@ gkl_status gkl_create_ex(const uint8_t* G, int64_t n, int64_t p, int32_t k, doub
         ctx->omega = o->pro_omega > 0.0 ? o->pro_omega : 1e-8;
         hipStream_t s = static_cast<hipStream_t>(o->stream);
         const int64_t ld = o->ld_bytes ? o->ld_bytes : (n + 3) / 4;
-        ctx->prob.setup(G, n, p, ld, s);
+        ctx->prob.setup(G, n, p, ld, s, o->precision != GKL_PREC_MIXED);
         ctx->root_maxdim = sqrt((double)std::max(n, p));
         ctx->noise_scale = 2.220446049250313e-16 * ctx->root_maxdim;
         ctx->krylov = o->krylov_dim;
@@ -662,6 +667,7 @@ gkl_status gkl_column_stats(gkl_ctx* ctx, int64_t* count, int64_t* nobs, double*
 gkl_status gkl_unpack(gkl_ctx* ctx, int8_t* out)
 {
     if (!ctx || ctx->batched || !out) return set_error(ctx, GKL_ERR_INVALID, "bad argument");
+    if (!ctx->prob.packed.T) return set_error(ctx, GKL_ERR_INVALID, "unpack needs an FP64 context");
     try {
         hipStream_t s = ctx->prob.stream;
         launch_unpack_layout(ctx->prob.packed, out, s);
@@ -675,6 +681,7 @@ gkl_status gkl_unpack(gkl_ctx* ctx, int8_t* out)
 gkl_status gkl_matvec(gkl_ctx* ctx, const double* v, double* y)
 {
     if (!ctx || ctx->batched || !v || !y) return set_error(ctx, GKL_ERR_INVALID, "bad argument");
+    if (!ctx->prob.packed.T) return set_error(ctx, GKL_ERR_INVALID, "FP64 products need an FP64 context");
     try {
         hipStream_t s = ctx->prob.stream;
         const int ev = ctx->timing_begin();
@@ -690,6 +697,7 @@ gkl_status gkl_matvec(gkl_ctx* ctx, const double* v, double* y)
 gkl_status gkl_rmatvec(gkl_ctx* ctx, const double* u, double* z)
 {
     if (!ctx || ctx->batched || !u || !z) return set_error(ctx, GKL_ERR_INVALID, "bad argument");
+    if (!ctx->prob.packed.T) return set_error(ctx, GKL_ERR_INVALID, "FP64 products need an FP64 context");
     try {
         hipStream_t s = ctx->prob.stream;
         const int ev = ctx->timing_begin();

@@ -150,4 +150,52 @@ void launch_pro_reset(const ProState& st, int maxm, int force, hipStream_t s);
 void launch_restart_scalars(const double* S, const double* P, int m, const double* beta_last,
                             int keep, double* theta, double* rho, hipStream_t s);
 
+// ---- k_mixed.hip: split-BF16 MFMA block products ----
+struct MixedShape {
+    int64_t n = 0, p = 0;
+    int64_t nI = 0, ldI = 0;      // layout I: rows (individuals, padded) and bytes per row
+    int64_t pS = 0, ldS = 0;      // layout S: rows (SNPs, padded) and bytes per row
+    int64_t nstW = 0, nstX = 0;   // 256-wide super-tiles along SNPs / individuals
+    int64_t stW = 0, stX = 0;     // super-tiles per K split
+    int splitW = 1, splitX = 1;
+};
+struct MixedWork {
+    void* frag = nullptr;         // split-BF16 vector fragments
+    double* partial = nullptr;
+    double* k1 = nullptr;         // 16 per-column constants
+    double* k2 = nullptr;
+};
+MixedShape mixed_shape(int64_t n, int64_t p);
+size_t mixed_frag_bytes(const MixedShape& m);
+size_t mixed_partial_elems(const MixedShape& m);
+void build_mixed_layouts(const uint8_t* G, int64_t n, int64_t p, int64_t ld, uint8_t* I,
+                         uint8_t* S, hipStream_t s);
+// Y (n x b, ldy) = A W (W: p x b, ldw); Z (p x b, ldz) = A^T X (X: n x b, ldx); b <= 32.
+void launch_matmat_mixed(const MixedShape& m, const uint8_t* I, const ColStats& st,
+                         const double* W, int64_t ldw, int b, double* Y, int64_t ldy,
+                         MixedWork& w, hipStream_t s);
+void launch_rmatmat_mixed(const MixedShape& m, const uint8_t* S, const ColStats& st,
+                          const double* X, int64_t ldx, int b, double* Z, int64_t ldz,
+                          MixedWork& w, hipStream_t s);
+
+// ---- k_block.hip: FP64 block operations ----
+size_t gemm_tn_partial_elems(int64_t len, int q);
+// H (q x b, ldh) = Q^T Y
+void launch_gemm_tn(const double* Q, int64_t ldq, const double* Y, int64_t ldy, int64_t len, int q,
+                    int b, double* H, int ldh, double* partial, unsigned int* counters,
+                    hipStream_t s);
+// Y -= Q H
+void launch_gemm_nn_sub(const double* Q, int64_t ldq, double* Y, int64_t ldy, int64_t len, int q,
+                        int b, const double* H, int ldh, hipStream_t s);
+// shifted CholeskyQR3 of Y in place; R (b x b upper) to Rout; work >= 3 b^2
+void launch_block_qr(double* Y, int64_t ldy, int64_t len, int b, double* Rout, double* work,
+                     double* partial, unsigned int* counters, int* bad, hipStream_t s);
+void launch_put_block(double* Bm, int ldb, int r0, int c0, const double* X, int rows, int cols,
+                      int ldx, int transpose, hipStream_t s);
+void launch_copy_lead(const double* Bm, int ldb, int m, double* out, hipStream_t s);
+void launch_block_residual(const double* C, int b, const double* P, int m, const double* S, int k,
+                           double tol, double* res, int* nconv, hipStream_t s);
+void launch_restart_block(double* Bm, int ldb, int keep, int b, const double* S, const double* C,
+                          const double* P, int m, hipStream_t s);
+
 }  // namespace gkl

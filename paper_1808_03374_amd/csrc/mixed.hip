@@ -1,31 +1,292 @@
-// Blocked mixed-precision GKL (split-BF16 MFMA products) -- placeholder until built.
+// Blocked mixed-precision GKL (host engine).
+//
+// Block Lanczos bidiagonalisation of width b (the BLAS3 extension named in
+// Section 5 of the paper), with thick restart from ordinary Ritz vectors
+// (Section 3):
+//     U_s R_s     = A V_s - U_{s-1} C_{s-1}^T      (block CGS2 against all U, QR)
+//     V_{s+1} C_s = A^T U_s - V_s R_s^T            (block CGS2 against all V, QR)
+// so that A [V_1..V_s] = [U_1..U_s] B with B block upper bidiagonal (R_s on the
+// diagonal, C_s^T above it).  The two products run on MFMA with split-BF16 vector
+// tiles; everything else (Gram-Schmidt, QR, B, its SVD, restart) is FP64.
+// Ritz residual of triplet i: || C_s P(last block rows, i) ||.
+// After a restart that keeps l Ritz vectors, B starts as diag(sigma_1..l) with the
+// spike block G^T = (C_s P(last, 1:l))^T in columns l..l+b, and the next left
+// block subtracts U~ G^T.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
 #include "engine.h"
 
 namespace gkl {
-struct MixedState {};
-struct BatchState {};
-bool mixed_supported() { return false; }
+
+struct MixedState {
+    MixedShape shape;
+    uint8_t* I = nullptr;
+    uint8_t* S = nullptr;
+    MixedWork w;
+    int b = 16;
+    int mmax = 0;       // left basis capacity (columns)
+    int keep = 0;
+    int ldb = 0;        // leading dimension of the projected matrix
+    double* U = nullptr;
+    double* V = nullptr;
+    double* H = nullptr;       // (mmax + b) x b projection coefficients
+    double* Bm = nullptr;      // ldb x ldb projected matrix
+    double* Bc = nullptr;      // compact copy for the SVD
+    double* R = nullptr;       // b x b
+    double* RT = nullptr;      // b x b
+    double* C = nullptr;       // b x b last right factor
+    double* qrwork = nullptr;  // 3 b^2
+    double* tmp = nullptr;     // max(n, p) x keep
+    double* gpart = nullptr;
+    unsigned int* gcnt = nullptr;
+    double* svd_scratch = nullptr;
+    int* iflags = nullptr;     // [0] nconv [1] bad pivots
+    RitzOut ritz{};
+};
+
+bool mixed_supported() { return true; }
 void destroy_mixed(MixedState* m) { delete m; }
-void destroy_batch(BatchState* b) { delete b; }
+
 }  // namespace gkl
 
-void gkl_ctx::setup_mixed() { gkl::fail(GKL_ERR_UNSUPPORTED, "mixed precision path not built"); }
-gkl_status gkl_ctx::solve_mixed(double*, double*, int64_t, double*, int64_t)
+using namespace gkl;
+
+void gkl_ctx::setup_mixed()
 {
-    gkl::fail(GKL_ERR_UNSUPPORTED, "mixed precision path not built");
+    mixed = new MixedState();
+    MixedState& M = *mixed;
+    DeviceArena& A = prob.arena;
+    hipStream_t s = prob.stream;
+    const int64_t n = prob.n, p = prob.p;
+    M.b = opt.block_width > 0 ? opt.block_width : 16;
+    if (M.b > 32) fail(GKL_ERR_INVALID, "block_width must be <= 32");
+    const int64_t mn = std::min(n, p);
+    int m = opt.krylov_dim > 0 ? opt.krylov_dim : std::max(k + 4 * M.b, 3 * k);
+    m = ((m + M.b - 1) / M.b) * M.b;
+    if (m > mn) m = (int)(mn / M.b) * M.b;
+    if (m < 2 * M.b || m <= k) fail(GKL_ERR_INVALID, "problem too small for the blocked solver");
+    M.mmax = m;
+    M.keep = opt.keep > 0 ? opt.keep : k + (m - k) / 2;
+    M.keep = std::min(M.keep, m - M.b);
+    if (M.keep < k) M.keep = k;
+    M.ldb = m + M.b;
+    M.shape = mixed_shape(n, p);
+    M.I = static_cast<uint8_t*>(A.alloc((size_t)M.shape.nI * M.shape.ldI));
+    M.S = static_cast<uint8_t*>(A.alloc((size_t)M.shape.pS * M.shape.ldS));
+    build_mixed_layouts(prob.G_user, n, p, prob.ld, M.I, M.S, s);
+    M.w.frag = A.alloc(mixed_frag_bytes(M.shape));
+    M.w.partial = static_cast<double*>(A.alloc(sizeof(double) * mixed_partial_elems(M.shape)));
+    M.w.k1 = static_cast<double*>(A.alloc(sizeof(double) * 32));
+    M.w.k2 = static_cast<double*>(A.alloc(sizeof(double) * 32));
+    const int b = M.b;
+    M.U = static_cast<double*>(A.alloc(sizeof(double) * (size_t)n * m));
+    M.V = static_cast<double*>(A.alloc(sizeof(double) * (size_t)p * (m + b)));
+    M.H = static_cast<double*>(A.alloc(sizeof(double) * (size_t)(m + b) * b));
+    M.Bm = static_cast<double*>(A.alloc(sizeof(double) * (size_t)M.ldb * M.ldb));
+    M.Bc = static_cast<double*>(A.alloc(sizeof(double) * (size_t)m * m));
+    M.R = static_cast<double*>(A.alloc(sizeof(double) * b * b));
+    M.RT = static_cast<double*>(A.alloc(sizeof(double) * b * b));
+    M.C = static_cast<double*>(A.alloc(sizeof(double) * b * b));
+    M.qrwork = static_cast<double*>(A.alloc(sizeof(double) * 3 * b * b));
+    M.tmp = static_cast<double*>(A.alloc(sizeof(double) * (size_t)std::max(n, p) * M.keep));
+    const size_t gp = std::max(gemm_tn_partial_elems(std::max(n, p), m + b),
+                               gemm_tn_partial_elems(std::max(n, p), b));
+    M.gpart = static_cast<double*>(A.alloc(sizeof(double) * gp));
+    M.gcnt = static_cast<unsigned int*>(A.alloc(sizeof(unsigned int) * 64));
+    M.iflags = static_cast<int*>(A.alloc(sizeof(int) * 8));
+    M.ritz.B = M.Bc;
+    M.ritz.P = static_cast<double*>(A.alloc(sizeof(double) * (size_t)m * m));
+    M.ritz.Q = static_cast<double*>(A.alloc(sizeof(double) * (size_t)m * m));
+    M.ritz.S = static_cast<double*>(A.alloc(sizeof(double) * m));
+    M.ritz.res = static_cast<double*>(A.alloc(sizeof(double) * m));
+    M.ritz.nconv = M.iflags;
+    M.svd_scratch = svd_fits_lds(m) ? nullptr
+                                    : static_cast<double*>(A.alloc(sizeof(double) * svd_scratch_elems(m)));
+    GKL_HIP(hipMemsetAsync(M.gcnt, 0, sizeof(unsigned int) * 64, s));
+    GKL_HIP(hipMemsetAsync(M.iflags, 0, sizeof(int) * 8, s));
+    maxm = m;
+    keep = M.keep;
+    krylov = m;
 }
 
+// Block CGS2 of the b columns of Y (len) against Q(:, 0:q).
+static void block_cgs2(MixedState& M, const double* Q, int64_t len, int q, double* Y, hipStream_t s)
+{
+    if (q <= 0) return;
+    const int b = M.b;
+    for (int pass = 0; pass < 2; ++pass) {
+        launch_gemm_tn(Q, len, Y, len, len, q, b, M.H, M.mmax + b, M.gpart, M.gcnt, s);
+        launch_gemm_nn_sub(Q, len, Y, len, len, q, b, M.H, M.mmax + b, s);
+    }
+}
+
+gkl_status gkl_ctx::solve_mixed(double* sigma, double* Uo, int64_t ldu, double* Vo, int64_t ldv)
+{
+    MixedState& M = *mixed;
+    hipStream_t s = prob.stream;
+    const int64_t n = prob.n, p = prob.p;
+    const int b = M.b;
+    // start block
+    if (opt.v0) GKL_HIP(hipMemcpyAsync(M.V, opt.v0, sizeof(double) * p * b, hipMemcpyDeviceToDevice, s));
+    else launch_gaussian(M.V, p * b, opt.seed, 0, s);
+    GKL_HIP(hipMemsetAsync(M.Bm, 0, sizeof(double) * (size_t)M.ldb * M.ldb, s));
+    GKL_HIP(hipMemsetAsync(M.iflags, 0, sizeof(int) * 8, s));
+    launch_block_qr(M.V, p, p, b, M.R, M.qrwork, M.gpart, M.gcnt, M.iflags + 1, s);
+    int o = 0;
+    int nlock_m = 0;         // columns kept at the last restart (0 = none)
+    int mcur = 0;
+    int nconv = 0;
+    int svd_m = -1;
+    bool converged = false;
+    int since_check = 0;
+    const int check_every = opt.check_every > 0 ? opt.check_every : 2;
+    while (true) {
+        double* Ub = M.U + (int64_t)o * n;
+        double* Vb = M.V + (int64_t)o * p;
+        double* Vn = M.V + (int64_t)(o + b) * p;
+        // left block: A V_o minus the coupling to the previous left block
+        const int ev = timing_begin();
+        launch_matmat_mixed(M.shape, M.I, prob.st, Vb, p, b, Ub, n, M.w, s);
+        timing_end(ev, false);
+        info.matvecs += b;
+        info.passes_over_G += (b + 15) / 16;
+        if (o > 0) {
+            if (o == nlock_m)
+                launch_gemm_nn_sub(M.U, n, Ub, n, n, nlock_m, b, M.Bm + (int64_t)o * M.ldb, M.ldb, s);
+            else
+                launch_gemm_nn_sub(M.U + (int64_t)(o - b) * n, n, Ub, n, n, b, b,
+                                   M.Bm + (int64_t)o * M.ldb + (o - b), M.ldb, s);
+            block_cgs2(M, M.U, n, o, Ub, s);
+            info.reorths += 2;
+        }
+        launch_block_qr(Ub, n, n, b, M.R, M.qrwork, M.gpart, M.gcnt, M.iflags + 1, s);
+        launch_put_block(M.Bm, M.ldb, o, o, M.R, b, b, b, 0, s);
+        // right block: A^T U_o - V_o R^T
+        const int ev2 = timing_begin();
+        launch_rmatmat_mixed(M.shape, M.S, prob.st, Ub, n, b, Vn, p, M.w, s);
+        timing_end(ev2, true);
+        info.matvecs += b;
+        info.passes_over_G += (b + 15) / 16;
+        launch_put_block(M.RT, b, 0, 0, M.R, b, b, b, 1, s);
+        launch_gemm_nn_sub(Vb, p, Vn, p, p, b, b, M.RT, b, s);
+        block_cgs2(M, M.V, p, o + b, Vn, s);
+        info.reorths += 2;
+        launch_block_qr(Vn, p, p, b, M.C, M.qrwork, M.gpart, M.gcnt, M.iflags + 1, s);
+        launch_put_block(M.Bm, M.ldb, o, o + b, M.C, b, b, b, 1, s);
+        o += b;
+        mcur = o;
+        info.steps += 1;
+        ++since_check;
+        const bool full = o + b > M.mmax;
+        const bool budget = opt.max_matvecs > 0 && info.matvecs >= opt.max_matvecs;
+        if (mcur >= k && (full || budget || since_check >= check_every)) {
+            since_check = 0;
+            launch_copy_lead(M.Bm, M.ldb, mcur, M.Bc, s);
+            launch_dense_svd(M.Bc, mcur, M.ritz.P, M.ritz.S, M.ritz.Q, M.svd_scratch, s);
+            launch_block_residual(M.C, b, M.ritz.P, mcur, M.ritz.S, k, tol, M.ritz.res,
+                                  M.ritz.nconv, s);
+            svd_m = mcur;
+            GKL_HIP(hipMemcpyAsync(&nconv, M.ritz.nconv, sizeof(int), hipMemcpyDeviceToHost, s));
+            GKL_HIP(hipStreamSynchronize(s));
+            info.nconv = nconv;
+            if (nconv >= k) { converged = true; break; }
+            if (budget) break;
+            if (full) {
+                // thick restart keeping M.keep Ritz vectors
+                const int kp = M.keep;
+                launch_gemm_tall(M.V, p, p, mcur, M.ritz.Q, mcur, kp, M.tmp, p, s);
+                GKL_HIP(hipMemcpyAsync(M.V, M.tmp, sizeof(double) * (size_t)p * kp,
+                                       hipMemcpyDeviceToDevice, s));
+                GKL_HIP(hipMemcpyAsync(M.V + (int64_t)kp * p, M.V + (int64_t)mcur * p,
+                                       sizeof(double) * (size_t)p * b, hipMemcpyDeviceToDevice, s));
+                launch_gemm_tall(M.U, n, n, mcur, M.ritz.P, mcur, kp, M.tmp, n, s);
+                GKL_HIP(hipMemcpyAsync(M.U, M.tmp, sizeof(double) * (size_t)n * kp,
+                                       hipMemcpyDeviceToDevice, s));
+                launch_restart_block(M.Bm, M.ldb, kp, b, M.ritz.S, M.C, M.ritz.P, mcur, s);
+                nlock_m = kp;
+                o = kp;
+                svd_m = -1;
+                info.restarts += 1;
+            }
+        } else if (budget) {
+            break;
+        }
+    }
+    if (svd_m != mcur) {
+        launch_copy_lead(M.Bm, M.ldb, mcur, M.Bc, s);
+        launch_dense_svd(M.Bc, mcur, M.ritz.P, M.ritz.S, M.ritz.Q, M.svd_scratch, s);
+        launch_block_residual(M.C, b, M.ritz.P, mcur, M.ritz.S, k, tol, M.ritz.res, M.ritz.nconv, s);
+    }
+    const int kk = std::min(k, mcur);
+    GKL_HIP(hipMemcpyAsync(sigma, M.ritz.S, sizeof(double) * kk, hipMemcpyDeviceToDevice, s));
+    launch_gemm_tall(M.U, n, n, mcur, M.ritz.P, mcur, kk, Uo, ldu, s);
+    launch_gemm_tall(M.V, p, p, mcur, M.ritz.Q, mcur, kk, Vo, ldv, s);
+    launch_sign_fix(Uo, ldu, n, Vo, ldv, p, kk, s);
+    std::vector<double> res(kk), s0(1);
+    int bad = 0;
+    GKL_HIP(hipMemcpyAsync(res.data(), M.ritz.res, sizeof(double) * kk, hipMemcpyDeviceToHost, s));
+    GKL_HIP(hipMemcpyAsync(s0.data(), M.ritz.S, sizeof(double), hipMemcpyDeviceToHost, s));
+    GKL_HIP(hipMemcpyAsync(&bad, M.iflags + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+    GKL_HIP(hipStreamSynchronize(s));
+    double sum = 0.0, mx = 0.0;
+    for (int i = 0; i < kk; ++i) {
+        sum += res[i];
+        mx = std::max(mx, s0[0] > 0 ? res[i] / s0[0] : 0.0);
+    }
+    info.sum_residual_est = sum;
+    info.max_residual_rel = mx;
+    info.converged = converged ? 1 : 0;
+    info.nconv = converged ? k : nconv;
+    if (bad > 0 && !converged)
+        last_error = "block orthonormalisation met a rank-deficient block";
+    return converged ? GKL_OK : GKL_NOT_CONVERGED;
+}
+
+// ---------------------------------------------------------------------------
+// Batched solves -- built in batched.hip
+// ---------------------------------------------------------------------------
 extern "C" {
-gkl_status gkl_matmat_mixed(gkl_ctx*, const double*, int32_t, double*) { return GKL_ERR_UNSUPPORTED; }
-gkl_status gkl_rmatmat_mixed(gkl_ctx*, const double*, int32_t, double*) { return GKL_ERR_UNSUPPORTED; }
-gkl_status gkl_create_batched(int32_t, const uint8_t* const*, const int64_t*, const int64_t*, int32_t,
-                              double, int32_t, const gkl_options*, gkl_ctx**)
+
+gkl_status gkl_matmat_mixed(gkl_ctx* ctx, const double* W, int32_t b, double* Y)
 {
-    return GKL_ERR_UNSUPPORTED;
+    if (!ctx || !W || !Y || b < 1 || b > 32) return GKL_ERR_INVALID;
+    if (!ctx->mixed) {
+        ctx->last_error = "context was not created with precision GKL_PREC_MIXED";
+        return GKL_ERR_INVALID;
+    }
+    try {
+        hipStream_t s = ctx->prob.stream;
+        launch_matmat_mixed(ctx->mixed->shape, ctx->mixed->I, ctx->prob.st, W, ctx->prob.p, b, Y,
+                            ctx->prob.n, ctx->mixed->w, s);
+        GKL_HIP(hipStreamSynchronize(s));
+        return GKL_OK;
+    } catch (const Error& e) {
+        ctx->last_error = e.msg;
+        return e.status;
+    }
 }
-gkl_status gkl_solve_batched(gkl_ctx*, double* const*, double* const*, const int64_t*, double* const*,
-                             const int64_t*, gkl_info*)
+
+gkl_status gkl_rmatmat_mixed(gkl_ctx* ctx, const double* X, int32_t b, double* Z)
 {
-    return GKL_ERR_UNSUPPORTED;
+    if (!ctx || !X || !Z || b < 1 || b > 32) return GKL_ERR_INVALID;
+    if (!ctx->mixed) {
+        ctx->last_error = "context was not created with precision GKL_PREC_MIXED";
+        return GKL_ERR_INVALID;
+    }
+    try {
+        hipStream_t s = ctx->prob.stream;
+        launch_rmatmat_mixed(ctx->mixed->shape, ctx->mixed->S, ctx->prob.st, X, ctx->prob.n, b, Z,
+                             ctx->prob.p, ctx->mixed->w, s);
+        GKL_HIP(hipStreamSynchronize(s));
+        return GKL_OK;
+    } catch (const Error& e) {
+        ctx->last_error = e.msg;
+        return e.status;
+    }
 }
-}
+
+}  // extern "C"

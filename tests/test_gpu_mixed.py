@@ -1,0 +1,93 @@
+"""GPU parity of the blocked mixed-precision path (split-BF16 MFMA products).
+
+Error model and tolerances
+  * The vector block is split into bf16 hi + lo: |w - hi - lo| <= 2^-16 |w| per
+    element; genotype operands are exact.  FP32 accumulation runs over chunks of
+    1,024 K values (error ~ sqrt(4096) * 2^-24 of the chunk magnitude, about 4e-6
+    relative to |A| |w|) and FP64 across chunks.  Per output element the error is
+    therefore bounded by about 2^-16 (|A| |W|)_ic + 4e-6 (|A| |W|)_ic; the test
+    uses 3e-5 (|A| |W|)_ic.
+  * Singular values of the blocked solve agree with the FP64 oracle to 1e-6
+    relative (the target for the mixed path).
+  * Vectors: the operator error of the split is at most 2^-16 of sigma_1, so the
+    leading singular vector is within sin(angle) <= 2^-16 sigma_1 / (sigma_1 -
+    sigma_2) of the oracle's (Davis-Kahan); the test allows 2e-5 / relative gap.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+import synth   # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gk():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm device")
+    import paper_1808_03374_amd as m
+    return m
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _dense(g):
+    st = oracle.column_stats(g.n, *oracle.counts(g.packed, g.n, g.p))
+    return oracle.dense_matrix(oracle.decode(g.packed, g.n, g.p), st.mean, st.inv_sd)
+
+
+@pytest.mark.parametrize("name,n,p,b,pad", [("c1", 300, 900, 16, 0), ("c3", 523, 1111, 7, -1),
+                                            ("c5", 1000, 3000, 32, -1), ("c2", 17, 260, 1, -1)])
+def test_mixed_products(gk, name, n, p, b, pad):
+    g = synth.config(name, n=n, p=p, pad_mode=pad)
+    A = _dense(g)
+    bw = 16 if min(n, p) >= 32 else 4
+    ctx = gk.Context(dev(g.packed), n, p, 1, precision=gk.GKL_PREC_MIXED, block_width=bw,
+                     krylov_dim=2 * bw)
+    rng = np.random.default_rng(n + p + b)
+    W = rng.standard_normal((p, b))
+    X = rng.standard_normal((n, b))
+    Y = ctx.matmat_mixed(dev(W)).cpu().numpy()
+    Z = ctx.rmatmat_mixed(dev(X)).cpu().numpy()
+    Y0 = A @ W
+    Z0 = A.T @ X
+    bound_y = 3e-5 * (np.abs(A) @ np.abs(W))
+    bound_z = 3e-5 * (np.abs(A).T @ np.abs(X))
+    assert np.all(np.abs(Y - Y0) <= bound_y + 1e-12)
+    assert np.all(np.abs(Z - Z0) <= bound_z + 1e-12)
+    # the error is far below the bound on average (random rounding)
+    assert np.linalg.norm(Y - Y0) <= 1e-5 * np.linalg.norm(Y0)
+    ctx.close()
+
+
+def _oracle(g, k):
+    op = oracle.PackedOperator(g.packed, g.n, g.p)
+    return op, oracle.gkl_svd(op, k, tol=1e-12, v0=synth.start_vector(g.p, 3))
+
+
+@pytest.mark.parametrize("name,n,p,k,b", [("c1", 1000, 5000, 10, 16), ("c3", 2000, 20000, 20, 16),
+                                          ("c2", 2000, 20000, 20, 32)])
+def test_mixed_solve_matches_fp64_oracle(gk, name, n, p, k, b):
+    g = synth.config(name, n=n, p=p)
+    op, ref = _oracle(g, k)
+    ctx = gk.Context(dev(g.packed), g.n, g.p, k, tol=1e-9, precision=gk.GKL_PREC_MIXED,
+                     block_width=b)
+    sigma, U, V, st, info = ctx.solve()
+    assert st == gk.GKL_OK, gk.gkl_last_error(ctx.ctx)
+    sigma = sigma.cpu().numpy()
+    U = U.cpu().numpy()
+    V = V.cpu().numpy()
+    rel = np.abs(sigma - ref.sigma) / ref.sigma
+    assert rel.max() <= 1e-6, rel
+    assert np.abs(V.T @ V - np.eye(k)).max() < 1e-8
+    assert np.abs(U.T @ U - np.eye(k)).max() < 1e-8
+    # leading vector: sin(angle) <= ||E|| / gap with ||E|| <= 2^-16 sigma_1 (split error)
+    gap = (ref.sigma[0] - ref.sigma[1]) / ref.sigma[0]
+    ang = oracle.subspace_angles(V[:, :1], ref.V[:, :1]).max()
+    assert ang <= 2e-5 / gap, (ang, gap)
+    ctx.close()
