@@ -90,6 +90,66 @@ def cpu_baseline(g, gpu_matvecs, seconds):
     }
 
 
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+
+
+def run_mixed(gk, torch, G, n, p, k, args, sigma_fp64, stream):
+    """The same top-k solve by the blocked split-BF16 path; timed like the FP64 steps."""
+    import numpy as np
+    import synth
+    b = args.block_width
+    v0 = torch.from_numpy(np.ascontiguousarray(
+        np.random.default_rng([1, 0x6D6978]).standard_normal((b, p)))).cuda()
+    opts = dict(v0=v0, precision=gk.GKL_PREC_MIXED, block_width=b, timing=1, stream=stream)
+    sig = torch.empty(k, dtype=torch.float64, device="cuda")
+    U = torch.empty((k, n), dtype=torch.float64, device="cuda")
+    V = torch.empty((k, p), dtype=torch.float64, device="cuda")
+    tol = 1e-8
+
+    def one():
+        ctx = gk.Context(G, n, p, k, tol, gk.GKL_REORTH_FULL, **opts)
+        try:
+            return gk.gkl_solve(ctx.ctx, sig, U, n, V, p)
+        finally:
+            ctx.close()
+
+    for _ in range(args.warmup):
+        one()
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st, info = one()
+        infos.append(info)
+    torch.cuda.synchronize()
+    step_s = (time.perf_counter() - t0) / args.steps
+    s_mixed = sig.cpu().numpy()
+    rel = np.abs(s_mixed - sigma_fp64) / sigma_fp64
+    mv_ms = sum(i.matvec_kernel_ms for i in infos)
+    rmv_ms = sum(i.rmatvec_kernel_ms for i in infos)
+    mv_n = sum(i.timed_matvecs for i in infos)
+    rmv_n = sum(i.timed_rmatvecs for i in infos)
+    last = infos[-1]
+    alg_bytes = ((n + 3) // 4) * p + b * (4 * p + 8 * n)
+    exec_flop = 8.0 * n * p * b           # g and m operands, each hi + lo
+    out = {"block_width": b, "tol": tol, "value_s_per_step": step_s,
+           "solve_s": float(np.mean([i.solve_ms for i in infos])) / 1e3,
+           "create_s": float(np.mean([i.create_ms for i in infos])) / 1e3,
+           "converged": int(last.converged), "matvecs": int(last.matvecs),
+           "block_steps": int(last.steps), "restarts": int(last.restarts),
+           "sigma_max_rel_err_vs_fp64": float(rel.max()),
+           "sigma_rel_err_vs_fp64": [float(x) for x in rel]}
+    for name, ms, cnt in (("matmat_mixed (A W)", mv_ms, mv_n), ("rmatmat_mixed (A^T X)", rmv_ms, rmv_n)):
+        avg = ms / max(cnt, 1)
+        out[name] = {"avg_launch_ms": avg, "launches": int(cnt),
+                     "algorithmic_bytes_per_launch": int(alg_bytes),
+                     "achieved_GBps": alg_bytes / (avg * 1e-3) / 1e9,
+                     "hbm_frac": alg_bytes / (avg * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+                     "mfma_executed_TFLOPs": exec_flop / (avg * 1e-3) / 1e12,
+                     "mfma_frac": exec_flop / (avg * 1e-3) / 1e12 / MFMA_BF16_PEAK_TFLOPS}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +158,9 @@ def main():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the blocked split-BF16 solve of the same workload")
+    ap.add_argument("--block-width", type=int, default=16)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="after the timed steps, copy BYTES bytes device-to-device 3 times "
                          "(reference dispatch for the HBM traffic counters)")
@@ -208,6 +271,8 @@ def main():
                              "achieved_GBps": bytes_per_product / (other_avg * 1e-3) / 1e9},
         },
     }
+    if not args.no_mixed:
+        line["mixed"] = run_mixed(gk, torch, G, n, p, k, args, sigma.cpu().numpy(), stream)
     if args.copy_calibration > 0:
         src = torch.empty(args.copy_calibration, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)

@@ -80,6 +80,15 @@ if not os.path.exists(library_path):
         f"{library_path} is missing: build it with paper_1808_03374_amd/build.py "
         "(or __graft_entry__.build()); there is no non-HIP fallback")
 
+# torch ships its own HIP runtime whose file name differs from the soname that
+# libgkl.so records.  Loading libgkl.so first would pull in a second HIP/HSA
+# runtime, and whichever initialises second finds no device.  Importing torch
+# first makes libgkl.so bind to the runtime torch already holds.
+try:
+    import torch  # noqa: F401
+except ImportError:
+    torch = None
+
 lib = ctypes.CDLL(library_path)
 
 _vp = ctypes.c_void_p

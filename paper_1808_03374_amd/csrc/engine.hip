@@ -44,7 +44,7 @@ void* DeviceArena::alloc(size_t bytes)
     if (e != hipSuccess) {
         (void)hipGetLastError();
         fail(e == hipErrorOutOfMemory ? GKL_ERR_NOMEM : GKL_ERR_DEVICE,
-             "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+             "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
     }
     ptrs.push_back(p);
     total += bytes;

@@ -20,7 +20,7 @@ namespace gkl {
 
 namespace {
 constexpr int kSvdThreads = 1024;
-constexpr int kGroup = 32;                      // lanes per column pair
+constexpr int kGroup = 16;                      // lanes per column pair
 constexpr int kGroups = kSvdThreads / kGroup;   // pairs rotated at once
 constexpr int kMaxSweeps = 40;
 
@@ -32,15 +32,26 @@ __device__ __forceinline__ double group_sum(double v)
 }
 
 // W (mp x mp, column-major, ld = mp) is replaced by B Q = P S; Vr accumulates Q.
-// mp is even (a zero column pads odd m).  Returns after convergence.
+// mp is even (a zero column pads odd m).  Column norms are computed once per
+// sweep and updated after each rotation (d_p -= t c, d_q += t c), so a pair needs
+// one reduction (its inner product).  Returns after a sweep without rotations.
 __device__ void jacobi_sweeps(double* W, double* Vr, int mp)
 {
     __shared__ int rotated;
+    __shared__ double dn[kMaxSvd + 2];
     const int g = threadIdx.x / kGroup;
     const int gl = threadIdx.x % kGroup;
     const int npairs = mp / 2;
-    const double eps = 2.220446049250313e-16;
+    // rotation threshold sqrt(m) * eps (the usual one-sided Jacobi test)
+    const double tol = 2.220446049250313e-16 * sqrt((double)mp);
     for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
+        for (int c = g; c < mp; c += kGroups) {
+            const double* wc = W + (int64_t)c * mp;
+            double a = 0.0;
+            for (int i = gl; i < mp; i += kGroup) a = fma(wc[i], wc[i], a);
+            a = group_sum(a);
+            if (gl == 0) dn[c] = a;
+        }
         if (threadIdx.x == 0) rotated = 0;
         __syncthreads();
         for (int r = 0; r < mp - 1; ++r) {
@@ -56,17 +67,11 @@ __device__ void jacobi_sweeps(double* W, double* Vr, int mp)
                 if (a > b) { const int t = a; a = b; b = t; }
                 double* wa = W + (int64_t)a * mp;
                 double* wb = W + (int64_t)b * mp;
-                double saa = 0.0, sbb = 0.0, sab = 0.0;
-                for (int i = gl; i < mp; i += kGroup) {
-                    const double x = wa[i], y = wb[i];
-                    saa = fma(x, x, saa);
-                    sbb = fma(y, y, sbb);
-                    sab = fma(x, y, sab);
-                }
-                saa = group_sum(saa);
-                sbb = group_sum(sbb);
+                double sab = 0.0;
+                for (int i = gl; i < mp; i += kGroup) sab = fma(wa[i], wb[i], sab);
                 sab = group_sum(sab);
-                if (fabs(sab) > eps * sqrt(saa * sbb) && sab != 0.0) {
+                const double saa = dn[a], sbb = dn[b];
+                if (sab != 0.0 && fabs(sab) > tol * sqrt(saa * sbb)) {
                     const double zeta = (sbb - saa) / (2.0 * sab);
                     const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
                     const double cs = 1.0 / sqrt(1.0 + t * t);
@@ -83,7 +88,11 @@ __device__ void jacobi_sweeps(double* W, double* Vr, int mp)
                         va[i] = cs * x - sn * y;
                         vb[i] = sn * x + cs * y;
                     }
-                    if (gl == 0) rotated = 1;
+                    if (gl == 0) {
+                        dn[a] = saa - t * sab;
+                        dn[b] = sbb + t * sab;
+                        rotated = 1;
+                    }
                 }
             }
             __syncthreads();
