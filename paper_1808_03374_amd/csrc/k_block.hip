@@ -4,14 +4,19 @@
 // recurrence scalars, the Gram-Schmidt reorthogonalisation and the projected
 // matrix in FP64; only the two products with the genotype matrix use the
 // split-BF16 MFMA path.  This file holds the FP64 pieces:
-//   * H = Q^T Y for tall Q (len x q) and Y (len x b): LDS-tiled, partials per row
-//     block, summed by the last block in a fixed order;
-//   * Y -= Q H;
+//   * H = Q^T Y for tall Q (len x q) and Y (len x b) on the FP64 matrix cores:
+//     one partial per workgroup, summed in a fixed order by a second kernel;
+//   * Out -= Q H and Out = Q H (also in place, for Y <- Y R^-1), FP64 MFMA;
 //   * block orthonormalisation by shifted Cholesky QR applied three times
 //     (shifted CholeskyQR3, Fukaya, Kannan, Nakatsukasa, Yamamoto & Yanagisawa,
 //     SIAM J. Sci. Comput. 2020): Gram matrix, Cholesky in one workgroup,
 //     triangular solve applied to every row, R accumulated;
 //   * Ritz residuals of the block-bidiagonal projected matrix.
+//
+// v_mfma_f64_16x16x4f64 (one wave): lane l supplies A(l % 16, l / 16) and
+// B(l / 16, l % 16); element e of the lane's result is D(l / 16 + 4 e, l % 16)
+// (rows interleaved by four, unlike the FP32-output 16x16 forms).
+// The contraction index may be permuted freely as long as A and B agree.
 #include <math.h>
 
 #include "kernels.h"
@@ -19,230 +24,332 @@
 namespace gkl {
 
 namespace {
-constexpr int kTR = 32;       // rows per LDS tile
-constexpr int kQC = 96;       // Q columns per block (grid.y covers more)
 constexpr int kBmax = 32;     // block width limit
-}  // namespace
+constexpr int kTnQ = 64;      // Q columns per workgroup in Q^T Y (4 tiles of 16)
+constexpr int kTnPart = kTnQ * kBmax;
+typedef double v4d __attribute__((ext_vector_type(4)));
 
-// H(q x b, ldh) = Q(len x q)^T Y(len x b); grid (row chunks, q chunks of 96).
-// Thread t computes outputs (qcol = t / 16 * 6 + 0..5 within the chunk, ycol =
-// t % 16 and t % 16 + 16 when b > 16) over the chunk's rows.
-__global__ void __launch_bounds__(256)
-gemm_tn_kernel(const double* __restrict__ Q, int64_t ldq, const double* __restrict__ Y,
-               int64_t ldy, int64_t len, int q, int b, int64_t rows_per_block,
-               double* __restrict__ H, int ldh, double* __restrict__ partial,
-               unsigned int* __restrict__ counters)
+__device__ __forceinline__ v4d mfma64(double a, double b, v4d c)
 {
-    __shared__ double qs[kTR][kQC + 1];
-    __shared__ double ys[kTR][kBmax + 1];
-    const int q0 = blockIdx.y * kQC;
-    const int qn = q - q0 < kQC ? q - q0 : kQC;
-    const int tq = (threadIdx.x >> 4) * 6;          // 16 groups x 6 = 96 columns
-    const int ty = threadIdx.x & 15;
-    double acc[2][6];
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-        for (int v = 0; v < 6; ++v) acc[u][v] = 0.0;
-    const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
-    const int64_t r1 = r0 + rows_per_block < len ? r0 + rows_per_block : len;
-    for (int64_t rt = r0; rt < r1; rt += kTR) {
-        const int nr = (int)(r1 - rt < kTR ? r1 - rt : kTR);
-        for (int e = threadIdx.x; e < kTR * kQC; e += 256) {
-            const int rr = e % kTR, c = e / kTR;
-            qs[rr][c] = (rr < nr && c < qn) ? Q[(int64_t)(q0 + c) * ldq + rt + rr] : 0.0;
-        }
-        for (int e = threadIdx.x; e < kTR * kBmax; e += 256) {
-            const int rr = e % kTR, c = e / kTR;
-            ys[rr][c] = (rr < nr && c < b) ? Y[(int64_t)c * ldy + rt + rr] : 0.0;
-        }
-        __syncthreads();
-        for (int rr = 0; rr < nr; ++rr) {
-            const double y0 = ys[rr][ty], y1 = ys[rr][ty + 16];
-#pragma unroll
-            for (int v = 0; v < 6; ++v) {
-                const double qv = qs[rr][tq + v];
-                acc[0][v] = fma(qv, y0, acc[0][v]);
-                acc[1][v] = fma(qv, y1, acc[1][v]);
-            }
-        }
-        __syncthreads();
-    }
-    // partial[block][96][32]
-    const int64_t pstride = (int64_t)kQC * kBmax;
-    double* my = partial + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * pstride;
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-        for (int v = 0; v < 6; ++v) my[(tq + v) * kBmax + ty + 16 * u] = acc[u][v];
-    if (!last_block_arrived(&counters[blockIdx.y], gridDim.x)) return;
-    for (int e = threadIdx.x; e < qn * b; e += 256) {
-        const int c = e / b, yc = e % b;
-        double s = 0.0;
-        for (unsigned int bx = 0; bx < gridDim.x; ++bx)
-            s += partial[((int64_t)blockIdx.y * gridDim.x + bx) * pstride + c * kBmax + yc];
-        H[(int64_t)yc * ldh + q0 + c] = s;
-    }
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-size_t gemm_tn_partial_elems(int64_t len, int q)
+// Rows per workgroup (a multiple of 128) and workgroup count for Q^T Y.
+void tn_plan(int64_t len, int64_t* rows_per_wg, int* nwg)
 {
-    const int64_t rb = len / 2048 + 1 < 512 ? len / 2048 + 1 : 512;
-    return (size_t)rb * (size_t)((q + kQC - 1) / kQC) * kQC * kBmax;
+    int64_t r = ceil_div(len, (int64_t)256);
+    r = (r + 127) / 128 * 128;
+    *rows_per_wg = r;
+    *nwg = (int)ceil_div(len, r);
+}
+}  // namespace
+
+// Partial Q^T Y of one workgroup: rows [r0, r0 + rows_per_wg), Q columns [q0,
+// q0 + 64).  Each wave walks steps of 32 rows; in a step, lane group g holds rows
+// 8g .. 8g + 7 of its column and MFMA t contracts row 8g + t of every group.
+// The four waves are summed through LDS in a fixed order.
+__global__ void __launch_bounds__(256)
+gemm_tn_kernel(const double* __restrict__ Q, int64_t ldq, const double* __restrict__ Y,
+               int64_t ldy, int64_t len, int q, int b, int64_t rows_per_wg,
+               double* __restrict__ partial)
+{
+    __shared__ double red[2][kTnPart];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, g = lane >> 4;
+    const int q0 = blockIdx.y * kTnQ;
+    const int nqt = (q - q0 + 15) / 16 < 4 ? (q - q0 + 15) / 16 : 4;
+    const int nbt = (b + 15) / 16;
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg;
+    const int64_t r1 = r0 + rows_per_wg < len ? r0 + rows_per_wg : len;
+    const double* qp[4];
+    bool qok[4];
+#pragma unroll
+    for (int qt = 0; qt < 4; ++qt) {
+        const int c = q0 + qt * 16 + col;
+        qok[qt] = c < q;
+        qp[qt] = Q + (int64_t)(qok[qt] ? c : 0) * ldq;
+    }
+    const double* yp[2];
+    bool yok[2];
+#pragma unroll
+    for (int bt = 0; bt < 2; ++bt) {
+        const int c = bt * 16 + col;
+        yok[bt] = c < b;
+        yp[bt] = Y + (int64_t)(yok[bt] ? c : 0) * ldy;
+    }
+    v4d acc[4][2];
+#pragma unroll
+    for (int qt = 0; qt < 4; ++qt)
+#pragma unroll
+        for (int bt = 0; bt < 2; ++bt) acc[qt][bt] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int64_t rs = r0 + wave * 32; rs < r1; rs += 128) {
+        const int64_t rb = rs + 8 * g;
+        double qv[4][8], yv[2][8];
+        const bool full = rb + 8 <= r1;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const bool ok = full || rb + t < r1;
+#pragma unroll
+            for (int bt = 0; bt < 2; ++bt) yv[bt][t] = (ok && yok[bt]) ? yp[bt][rb + t] : 0.0;
+#pragma unroll
+            for (int qt = 0; qt < 4; ++qt) qv[qt][t] = (ok && qok[qt]) ? qp[qt][rb + t] : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+#pragma unroll
+            for (int qt = 0; qt < 4; ++qt) {
+                if (qt >= nqt) continue;
+                acc[qt][0] = mfma64(qv[qt][t], yv[0][t], acc[qt][0]);
+                if (nbt > 1) acc[qt][1] = mfma64(qv[qt][t], yv[1][t], acc[qt][1]);
+            }
+    }
+    // lane's element e of tile (qt, bt) is H(q0 + qt*16 + g + 4e, bt*16 + col)
+    if (wave < 2) {
+#pragma unroll
+        for (int qt = 0; qt < 4; ++qt)
+#pragma unroll
+            for (int bt = 0; bt < 2; ++bt)
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    red[wave][(qt * 16 + g + 4 * e) * kBmax + bt * 16 + col] = acc[qt][bt][e];
+    }
+    __syncthreads();
+    if (wave >= 2) {
+#pragma unroll
+        for (int qt = 0; qt < 4; ++qt)
+#pragma unroll
+            for (int bt = 0; bt < 2; ++bt)
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    red[wave - 2][(qt * 16 + g + 4 * e) * kBmax + bt * 16 + col] += acc[qt][bt][e];
+    }
+    __syncthreads();
+    double* my = partial + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * kTnPart;
+    for (int e = threadIdx.x; e < kTnPart; e += 256) my[e] = red[0][e] + red[1][e];
+}
+
+// H(qc, j) = sum over workgroups of the partials: 16 lanes per output, lane r
+// adding workgroups r, r + 16, ... in order, then a fixed butterfly.
+__global__ void __launch_bounds__(256)
+gemm_tn_reduce_kernel(const double* __restrict__ partial, int nwg, int q, int b,
+                      double* __restrict__ H, int ldh)
+{
+    const int t = blockIdx.x * 16 + (threadIdx.x >> 4);
+    const int r = threadIdx.x & 15;
+    const bool live = t < q * b;
+    const int qc = live ? t / b : 0, j = live ? t % b : 0;
+    const double* src =
+        partial + (int64_t)(qc / kTnQ) * nwg * kTnPart + (qc % kTnQ) * kBmax + j;
+    double s = 0.0;
+    if (live)
+        for (int x = r; x < nwg; x += 16) s += src[(int64_t)x * kTnPart];
+#pragma unroll
+    for (int off = 8; off >= 1; off >>= 1) s += __shfl_xor(s, off, 16);
+    if (live && r == 0) H[(int64_t)j * ldh + qc] = s;
+}
+
+// Partial buffer for any len: tn_plan never uses more than 256 workgroups.
+size_t gemm_tn_partial_elems(int64_t, int q)
+{
+    return (size_t)256 * (size_t)ceil_div(q < 1 ? 1 : q, kTnQ) * kTnPart;
 }
 
 void launch_gemm_tn(const double* Q, int64_t ldq, const double* Y, int64_t ldy, int64_t len, int q,
-                    int b, double* H, int ldh, double* partial, unsigned int* counters,
-                    hipStream_t s)
+                    int b, double* H, int ldh, double* partial, hipStream_t s)
 {
-    if (q <= 0 || b <= 0) return;
+    if (q <= 0 || b <= 0 || len <= 0) return;
     if (b > kBmax) fail(GKL_ERR_INVALID, "block width above 32");
-    int64_t rb = len / 2048 + 1;
-    if (rb > 512) rb = 512;
-    const int64_t rpb = ((len + rb - 1) / rb + kTR - 1) / kTR * kTR;
-    rb = (len + rpb - 1) / rpb;
-    if (rb < 1) rb = 1;
-    dim3 grid((unsigned int)rb, (unsigned int)((q + kQC - 1) / kQC));
-    hipLaunchKernelGGL(gemm_tn_kernel, grid, dim3(256), 0, s, Q, ldq, Y, ldy, len, q, b, rpb, H,
-                       ldh, partial, counters);
+    int64_t rpw;
+    int nwg;
+    tn_plan(len, &rpw, &nwg);
+    if (nwg > 256) fail(GKL_ERR_INTERNAL, "gemm_tn plan exceeds its partial buffer");
+    dim3 grid((unsigned int)nwg, (unsigned int)ceil_div(q, kTnQ));
+    hipLaunchKernelGGL(gemm_tn_kernel, grid, dim3(256), 0, s, Q, ldq, Y, ldy, len, q, b, rpw,
+                       partial);
     GKL_LAUNCH_CHECK("gemm_tn_kernel");
+    hipLaunchKernelGGL(gemm_tn_reduce_kernel, dim3(ceil_div(q * b, 16)), dim3(256), 0, s, partial,
+                       nwg, q, b, H, ldh);
+    GKL_LAUNCH_CHECK("gemm_tn_reduce_kernel");
 }
 
-// Y(len x b) -= Q(len x q) H(q x b); one row per thread, H in LDS.
+// Out(len x nc) = Q(len x q) H(q x nc)  (subtract == 0), or Out -= Q H.  Each wave
+// owns 64 rows (four row tiles) and 32 output columns (grid.y covers more); the
+// contraction runs over q in steps of 4.  Q and Out may be the same matrix when
+// nc <= 32: a wave reads all of its rows before it writes them.
 __global__ void __launch_bounds__(256)
-gemm_nn_sub_kernel(const double* __restrict__ Q, int64_t ldq, double* __restrict__ Y, int64_t ldy,
-                   int64_t len, int q, int b, const double* __restrict__ H, int ldh)
+gemm_nn_kernel(const double* Q, int64_t ldq, int q, const double* __restrict__ H, int ldh,
+               double* Out, int64_t ldo, int64_t len, int nc, int subtract)
 {
-    extern __shared__ double hs[];   // q x b
-    for (int e = threadIdx.x; e < q * b; e += 256) hs[e] = H[(int64_t)(e / q) * ldh + (e % q)];
-    __syncthreads();
-    const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (row >= len) return;
-    double acc[kBmax];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, g = lane >> 4;
+    const int64_t r0 = ((int64_t)blockIdx.x * 4 + wave) * 64;
+    if (r0 >= len) return;
+    const int c0 = blockIdx.y * 32;
+    const int nbt = nc - c0 > 16 ? 2 : 1;
+    bool rok[4];
 #pragma unroll
-    for (int c = 0; c < kBmax; ++c) acc[c] = 0.0;
-    for (int k = 0; k < q; ++k) {
-        const double qv = Q[(int64_t)k * ldq + row];
+    for (int rt = 0; rt < 4; ++rt) rok[rt] = r0 + rt * 16 + col < len;
+    bool hok[2];
+    int hc[2];
 #pragma unroll
-        for (int c = 0; c < kBmax; ++c)
-            if (c < b) acc[c] = fma(qv, hs[c * q + k], acc[c]);
+    for (int bt = 0; bt < 2; ++bt) {
+        hc[bt] = c0 + bt * 16 + col;
+        hok[bt] = hc[bt] < nc;
+        if (!hok[bt]) hc[bt] = 0;
     }
+    v4d acc[4][2];
 #pragma unroll
-    for (int c = 0; c < kBmax; ++c)
-        if (c < b) Y[(int64_t)c * ldy + row] -= acc[c];
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+        for (int bt = 0; bt < 2; ++bt) acc[rt][bt] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < q; k += 4) {
+        const int kk = k + g;
+        const bool kok = kk < q;
+        const double* qc = Q + (int64_t)(kok ? kk : 0) * ldq + r0 + col;
+        double a[4], hb[2];
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) a[rt] = (kok && rok[rt]) ? qc[rt * 16] : 0.0;
+#pragma unroll
+        for (int bt = 0; bt < 2; ++bt)
+            hb[bt] = (kok && hok[bt]) ? H[(int64_t)hc[bt] * ldh + kk] : 0.0;
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) {
+            acc[rt][0] = mfma64(a[rt], hb[0], acc[rt][0]);
+            if (nbt > 1) acc[rt][1] = mfma64(a[rt], hb[1], acc[rt][1]);
+        }
+    }
+    // element e of tile (rt, bt): Out(r0 + rt*16 + g + 4e, c0 + bt*16 + col)
+#pragma unroll
+    for (int bt = 0; bt < 2; ++bt) {
+        const int c = c0 + bt * 16 + col;
+        if (c >= nc) continue;
+        double* oc = Out + (int64_t)c * ldo;
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t row = r0 + rt * 16 + g + 4 * e;
+                if (row < len) oc[row] = subtract ? oc[row] - acc[rt][bt][e] : acc[rt][bt][e];
+            }
+    }
+}
+
+void launch_gemm_nn(const double* Q, int64_t ldq, int q, const double* H, int ldh, double* Out,
+                    int64_t ldo, int64_t len, int nc, int subtract, hipStream_t s)
+{
+    if (nc <= 0 || len <= 0) return;
+    if (q <= 0) {
+        if (subtract) return;
+        fail(GKL_ERR_INTERNAL, "gemm_nn with an empty contraction");
+    }
+    if ((const double*)Out == Q && nc > 32)
+        fail(GKL_ERR_INTERNAL, "in-place gemm_nn needs at most 32 output columns");
+    dim3 grid((unsigned int)ceil_div(len, (int64_t)256), (unsigned int)ceil_div(nc, 32));
+    hipLaunchKernelGGL(gemm_nn_kernel, grid, dim3(256), 0, s, Q, ldq, q, H, ldh, Out, ldo, len, nc,
+                       subtract);
+    GKL_LAUNCH_CHECK("gemm_nn_kernel");
 }
 
 void launch_gemm_nn_sub(const double* Q, int64_t ldq, double* Y, int64_t ldy, int64_t len, int q,
                         int b, const double* H, int ldh, hipStream_t s)
 {
-    if (q <= 0 || b <= 0) return;
-    hipLaunchKernelGGL(gemm_nn_sub_kernel, dim3(ceil_div(len, 256)), dim3(256),
-                       sizeof(double) * (size_t)q * b, s, Q, ldq, Y, ldy, len, q, b, H, ldh);
-    GKL_LAUNCH_CHECK("gemm_nn_sub_kernel");
+    launch_gemm_nn(Q, ldq, q, H, ldh, Y, ldy, len, b, 1, s);
 }
 
 // Cholesky of the b x b Gram matrix (column-major, ld b) in one workgroup, with an
-// optional shift added to the diagonal; writes the upper factor Rn (G + shift I =
-// Rn^T Rn), its inverse Ri, and R <- Rn R (accumulated; R = I on the first pass
-// when first != 0).  Non-positive pivots are replaced by a tiny positive value and
-// counted in *bad.
-__global__ void chol_kernel(const double* __restrict__ Gm, int b, double shift_rel,
-                            double* __restrict__ R, double* __restrict__ Ri, int first,
-                            int* __restrict__ bad)
+// optional shift (shift_rel times the trace) added to the diagonal; writes the
+// upper factor Rn (G + shift I = Rn^T Rn), its inverse Ri, and R <- Rn R
+// (accumulated; R = I on the first pass when first != 0).  Non-positive pivots
+// are replaced by a tiny positive value and counted in *bad.  Right-looking
+// factorisation and a row-oriented back substitution, one barrier per stage.
+__global__ void __launch_bounds__(256)
+chol_kernel(const double* __restrict__ Gm, int b, double shift_rel, double* __restrict__ R,
+            double* __restrict__ Ri, int first, int* __restrict__ bad)
 {
-    __shared__ double A[kBmax][kBmax + 1];
-    __shared__ double L[kBmax][kBmax + 1];      // upper factor Rn
-    __shared__ double Iv[kBmax][kBmax + 1];     // inverse of Rn
+    __shared__ double A[kBmax][kBmax + 1];      // becomes the upper factor Rn
+    __shared__ double Xr[kBmax][kBmax + 1];     // inverse of Rn
     __shared__ double Rold[kBmax][kBmax + 1];
+    __shared__ double trace;
+    __shared__ int nbad;
     const int t = threadIdx.x;
     for (int e = t; e < b * b; e += blockDim.x) {
         const int i = e % b, j = e / b;
         A[i][j] = Gm[e];
         Rold[i][j] = first ? (i == j ? 1.0 : 0.0) : R[e];
+        Xr[i][j] = i == j ? 1.0 : 0.0;
     }
     __syncthreads();
     if (t == 0) {
         double tr = 0.0;
         for (int i = 0; i < b; ++i) tr += A[i][i];
+        trace = tr;
+        nbad = 0;
         const double sh = shift_rel * tr;
         for (int i = 0; i < b; ++i) A[i][i] += sh;
-        // column Cholesky, upper factor: A = L^T L with L upper triangular
-        for (int j = 0; j < b; ++j) {
-            double d = A[j][j];
-            for (int k = 0; k < j; ++k) d -= L[k][j] * L[k][j];
-            if (!(d > 1e-300)) {
-                d = 1e-300 + 1e-30 * (tr > 0 ? tr : 1.0);
-                if (bad) *bad += 1;
-            }
-            const double l = sqrt(d);
-            L[j][j] = l;
-            for (int i = j + 1; i < b; ++i) {
-                double s = A[j][i];
-                for (int k = 0; k < j; ++k) s -= L[k][j] * L[k][i];
-                L[j][i] = s / l;
-            }
-            for (int i = 0; i < j; ++i) L[j][i] = 0.0;
-        }
-        // inverse of the upper triangular L
-        for (int j = b - 1; j >= 0; --j) {
-            Iv[j][j] = 1.0 / L[j][j];
-            for (int i = j - 1; i >= 0; --i) {
-                double s = 0.0;
-                for (int k = i + 1; k <= j; ++k) s += L[i][k] * Iv[k][j];
-                Iv[i][j] = -s / L[i][i];
-            }
-            for (int i = j + 1; i < b; ++i) Iv[i][j] = 0.0;
-        }
     }
     __syncthreads();
+    for (int j = 0; j < b; ++j) {
+        if (t == 0) {
+            double d = A[j][j];
+            if (!(d > 1e-300)) {
+                d = 1e-300 + 1e-30 * (trace > 0 ? trace : 1.0);
+                ++nbad;
+            }
+            A[j][j] = sqrt(d);
+        }
+        __syncthreads();
+        const double l = A[j][j];
+        for (int i = j + 1 + t; i < b; i += blockDim.x) A[j][i] /= l;
+        __syncthreads();
+        const int w = b - j - 1;
+        for (int e = t; e < w * w; e += blockDim.x) {
+            const int i = j + 1 + e / w, i2 = j + 1 + e % w;
+            A[i][i2] -= A[j][i] * A[j][i2];
+        }
+        __syncthreads();
+    }
     for (int e = t; e < b * b; e += blockDim.x) {
         const int i = e % b, j = e / b;
-        Ri[e] = Iv[i][j];
+        if (i > j) A[i][j] = 0.0;
+    }
+    __syncthreads();
+    // Rn X = I, X upper: rows from the bottom, each finished row updating those above
+    for (int i = b - 1; i >= 0; --i) {
+        const double d = A[i][i];
+        for (int j = i + t; j < b; j += blockDim.x) Xr[i][j] /= d;
+        __syncthreads();
+        const int w = b - i;
+        for (int e = t; e < i * w; e += blockDim.x) {
+            const int k = e / w, j = i + e % w;
+            Xr[k][j] -= A[k][i] * Xr[i][j];
+        }
+        __syncthreads();
+    }
+    for (int e = t; e < b * b; e += blockDim.x) {
+        const int i = e % b, j = e / b;
+        Ri[e] = j >= i ? Xr[i][j] : 0.0;
         double s = 0.0;
-        for (int k = 0; k < b; ++k) s += L[i][k] * Rold[k][j];
+        for (int k = i; k < b; ++k) s += A[i][k] * Rold[k][j];
         R[e] = s;
     }
-}
-
-// Y(len x b) <- Y Ri (Ri upper triangular b x b).
-__global__ void __launch_bounds__(256)
-trmm_right_kernel(double* __restrict__ Y, int64_t ldy, int64_t len, int b,
-                  const double* __restrict__ Ri)
-{
-    __shared__ double rs[kBmax * kBmax];
-    for (int e = threadIdx.x; e < b * b; e += 256) rs[e] = Ri[e];
-    __syncthreads();
-    const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (row >= len) return;
-    double y[kBmax];
-#pragma unroll
-    for (int c = 0; c < kBmax; ++c) y[c] = c < b ? Y[(int64_t)c * ldy + row] : 0.0;
-#pragma unroll
-    for (int j = 0; j < kBmax; ++j) {
-        if (j >= b) break;
-        double s = 0.0;
-        for (int k = 0; k <= j; ++k) s = fma(y[k], rs[j * b + k], s);
-        Y[(int64_t)j * ldy + row] = s;
-    }
+    if (t == 0 && bad && nbad) *bad += nbad;
 }
 
 // Shifted CholeskyQR3: Y (len x b) -> Q R with Q overwriting Y, R (b x b upper,
 // column-major) written to Rout.  work: >= 3 b*b doubles.
 void launch_block_qr(double* Y, int64_t ldy, int64_t len, int b, double* Rout, double* work,
-                     double* partial, unsigned int* counters, int* bad, hipStream_t s)
+                     double* partial, int* bad, hipStream_t s)
 {
     double* Gm = work;
     double* Ri = work + b * b;
     const double u = 1.1102230246251565e-16;
     const double shift = 11.0 * ((double)len * b + (double)b * (b + 1)) * u;
     for (int pass = 0; pass < 3; ++pass) {
-        launch_gemm_tn(Y, ldy, Y, ldy, len, b, b, Gm, b, partial, counters, s);
-        hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(64), 0, s, Gm, b, pass == 0 ? shift : 0.0,
+        launch_gemm_tn(Y, ldy, Y, ldy, len, b, b, Gm, b, partial, s);
+        hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(256), 0, s, Gm, b, pass == 0 ? shift : 0.0,
                            Rout, Ri, pass == 0 ? 1 : 0, pass == 2 ? bad : nullptr);
         GKL_LAUNCH_CHECK("chol_kernel");
-        hipLaunchKernelGGL(trmm_right_kernel, dim3(ceil_div(len, 256)), dim3(256), 0, s, Y, ldy,
-                           len, b, Ri);
-        GKL_LAUNCH_CHECK("trmm_right_kernel");
+        launch_gemm_nn(Y, ldy, b, Ri, b, Y, ldy, len, b, 0, s);
     }
 }
 

@@ -181,18 +181,37 @@ __global__ void split_W_kernel(const double* __restrict__ W, int64_t ldw, int b,
 }
 
 // Per column c: K2_c = sum_j mu_j s_j W_jc (FP64, fixed order; one block per column).
+// Column sums over len rows: out[c] = sum_j f_j X(j, c), with f_j = mean_j inv_sd_j
+// when mean != NULL (the product mean_j (inv_sd_j x) is formed in that order)
+// and f_j = 1 otherwise.  grid (kCsSplit, columns): each block sums one chunk of
+// rows; the last block of a column adds the chunk sums in chunk order.
+constexpr int kCsSplit = 64;   // == wavefront size (final sum is one wave)
+
 __global__ void __launch_bounds__(256)
-consts_W_kernel(const double* __restrict__ W, int64_t ldw, int64_t p,
-                const double* __restrict__ mean, const double* __restrict__ inv_sd,
-                double* __restrict__ K2)
+colsum_kernel(const double* __restrict__ X, int64_t ldx, int64_t len,
+              const double* __restrict__ mean, const double* __restrict__ inv_sd,
+              double* __restrict__ cpart, unsigned int* __restrict__ counters,
+              double* __restrict__ out)
 {
     __shared__ double sh[16];
-    const int c = blockIdx.x;
-    double a2 = 0.0;
-    for (int64_t j = threadIdx.x; j < p; j += blockDim.x)
-        a2 += mean[j] * (inv_sd[j] * W[(int64_t)c * ldw + j]);
-    a2 = block_sum(a2, sh);
-    if (threadIdx.x == 0) K2[c] = a2;
+    const int c = blockIdx.y;
+    const int64_t chunk = (len + kCsSplit - 1) / kCsSplit;
+    const int64_t j0 = (int64_t)blockIdx.x * chunk;
+    const int64_t j1 = j0 + chunk < len ? j0 + chunk : len;
+    const double* xc = X + (int64_t)c * ldx;
+    double a = 0.0;
+    if (mean) {
+        for (int64_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) a += mean[j] * (inv_sd[j] * xc[j]);
+    } else {
+        for (int64_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) a += xc[j];
+    }
+    a = block_sum(a, sh);
+    if (threadIdx.x == 0) cpart[c * kCsSplit + blockIdx.x] = a;
+    if (!last_block_arrived(&counters[c], kCsSplit)) return;
+    if (threadIdx.x < 64) {      // one wave: kCsSplit == 64 chunk sums, fixed butterfly
+        const double t = wave_sum(cpart[c * kCsSplit + threadIdx.x]);
+        if (threadIdx.x == 0) out[c] = t;
+    }
 }
 
 // A^T X operands: frag[((st*8 + t)*2 + op)*64 + lane][e], ops 0..1 = Xhi, Xlo.
@@ -221,17 +240,6 @@ __global__ void split_X_kernel(const double* __restrict__ X, int64_t ldx, int b,
 }
 
 // T_c = sum_i X_ic (FP64, fixed order; one block per column).
-__global__ void __launch_bounds__(256)
-consts_X_kernel(const double* __restrict__ X, int64_t ldx, int64_t n, double* __restrict__ T)
-{
-    __shared__ double sh[16];
-    const int c = blockIdx.x;
-    double a1 = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) a1 += X[(int64_t)c * ldx + i];
-    a1 = block_sum(a1, sh);
-    if (threadIdx.x == 0) T[c] = a1;
-}
-
 // ---------------------------------------------------------------------------
 // A W main kernel: block = 4 waves x 8 row tiles x 16 rows = 512 rows, K split in
 // super-tiles; partial[split][row][16] FP64.
@@ -491,9 +499,10 @@ void launch_matmat_mixed(const MixedShape& m, const uint8_t* I, const ColStats& 
                            col0, m.p, st.mean, st.inv_sd, m.nstW,
                            reinterpret_cast<bf16x8*>(w.frag));
         GKL_LAUNCH_CHECK("split_W_kernel");
-        hipLaunchKernelGGL(consts_W_kernel, dim3(nb), dim3(256), 0, s, W + (int64_t)col0 * ldw,
-                           ldw, m.p, st.mean, st.inv_sd, w.k2);
-        GKL_LAUNCH_CHECK("consts_W_kernel");
+        hipLaunchKernelGGL(colsum_kernel, dim3(kCsSplit, nb), dim3(256), 0, s,
+                           W + (int64_t)col0 * ldw, ldw, m.p, st.mean, st.inv_sd, w.cpart,
+                           w.counters, w.k2);
+        GKL_LAUNCH_CHECK("colsum_kernel");
         dim3 grid((unsigned int)(m.nI / (kMxWaves * kRTw * 16)), (unsigned int)m.splitW);
         hipLaunchKernelGGL(matmat_bf16_kernel, grid, dim3(256), 0, s, I, m.ldI, m.nI,
                            reinterpret_cast<const bf16x8*>(w.frag), m.nstW, m.stW, w.partial);
@@ -515,9 +524,10 @@ void launch_rmatmat_mixed(const MixedShape& m, const uint8_t* S, const ColStats&
         hipLaunchKernelGGL(split_X_kernel, dim3(ceil_div(nthr, 256)), dim3(256), 0, s, X, ldx, b,
                            col0, m.n, m.nstX, reinterpret_cast<bf16x8*>(w.frag));
         GKL_LAUNCH_CHECK("split_X_kernel");
-        hipLaunchKernelGGL(consts_X_kernel, dim3(nb), dim3(256), 0, s, X + (int64_t)col0 * ldx,
-                           ldx, m.n, w.k1);
-        GKL_LAUNCH_CHECK("consts_X_kernel");
+        hipLaunchKernelGGL(colsum_kernel, dim3(kCsSplit, nb), dim3(256), 0, s,
+                           X + (int64_t)col0 * ldx, ldx, m.n, nullptr, nullptr, w.cpart,
+                           w.counters, w.k1);
+        GKL_LAUNCH_CHECK("colsum_kernel");
         dim3 grid((unsigned int)(m.pS / (kMxWaves * kRTr * 16)), (unsigned int)m.splitX);
         hipLaunchKernelGGL(rmatmat_bf16_kernel, grid, dim3(256), 0, s, S, m.ldS, m.pS,
                            reinterpret_cast<const bf16x8*>(w.frag), m.nstX, m.stX, w.partial);

@@ -9,9 +9,10 @@
 // bounds into ||Delta theta||_1).
 //
 // The SVD is a one-sided (Hestenes) Jacobi method run by a single workgroup
-// with the matrix and the accumulated rotations held in LDS.  Column pairs of a
-// round-robin tournament are rotated concurrently, one half-wavefront (32
-// lanes) per pair; sweeps repeat until no pair needs rotating.
+// with the matrix and the accumulated rotations held in LDS (global scratch for
+// matrices too large for it).  Column pairs of a round-robin tournament are
+// rotated concurrently, 16 lanes per pair, with the pair's columns held in
+// registers while they are rotated; sweeps repeat until no pair needs rotating.
 #include <math.h>
 
 #include "kernels.h"
@@ -31,11 +32,66 @@ __device__ __forceinline__ double group_sum(double v)
     return v;
 }
 
+constexpr int kRegs = 8;   // column elements per lane kept in registers (mp <= 128)
+
+// Rotate columns a and b of X (ld mp) by (cs, sn): x_a <- cs x_a - sn x_b,
+// x_b <- sn x_a + cs x_b.
+__device__ __forceinline__ void rotate_pair(double* X, int mp, int a, int b, double cs, double sn,
+                                            int gl)
+{
+    double* xa = X + (int64_t)a * mp;
+    double* xb = X + (int64_t)b * mp;
+    if (mp <= kRegs * kGroup) {
+        double u[kRegs], v[kRegs];
+#pragma unroll
+        for (int j = 0; j < kRegs; ++j) {
+            const int i = gl + j * kGroup;
+            u[j] = i < mp ? xa[i] : 0.0;
+            v[j] = i < mp ? xb[i] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < kRegs; ++j) {
+            const int i = gl + j * kGroup;
+            if (i < mp) {
+                xa[i] = cs * u[j] - sn * v[j];
+                xb[i] = sn * u[j] + cs * v[j];
+            }
+        }
+    } else {
+        for (int i = gl; i < mp; i += kGroup) {
+            const double x = xa[i], y = xb[i];
+            xa[i] = cs * x - sn * y;
+            xb[i] = sn * x + cs * y;
+        }
+    }
+}
+
+__device__ __forceinline__ double pair_dot(const double* X, int mp, int a, int b, int gl)
+{
+    const double* xa = X + (int64_t)a * mp;
+    const double* xb = X + (int64_t)b * mp;
+    double s = 0.0;
+    if (mp <= kRegs * kGroup) {
+        double u[kRegs], v[kRegs];
+#pragma unroll
+        for (int j = 0; j < kRegs; ++j) {
+            const int i = gl + j * kGroup;
+            u[j] = i < mp ? xa[i] : 0.0;
+            v[j] = i < mp ? xb[i] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < kRegs; ++j) s = fma(u[j], v[j], s);
+    } else {
+        for (int i = gl; i < mp; i += kGroup) s = fma(xa[i], xb[i], s);
+    }
+    return group_sum(s);
+}
+
 // W (mp x mp, column-major, ld = mp) is replaced by B Q = P S; Vr accumulates Q.
 // mp is even (a zero column pads odd m).  Column norms are computed once per
 // sweep and updated after each rotation (d_p -= t c, d_q += t c), so a pair needs
 // one reduction (its inner product).  Returns after a sweep without rotations.
-__device__ void jacobi_sweeps(double* W, double* Vr, int mp)
+__device__ __forceinline__ void jacobi_sweeps(double* W, double* Vr, int mp)
 {
     __shared__ int rotated;
     __shared__ double dn[kMaxSvd + 2];
@@ -65,29 +121,15 @@ __device__ void jacobi_sweeps(double* W, double* Vr, int mp)
                     b = (r - k + (mp - 1)) % (mp - 1);
                 }
                 if (a > b) { const int t = a; a = b; b = t; }
-                double* wa = W + (int64_t)a * mp;
-                double* wb = W + (int64_t)b * mp;
-                double sab = 0.0;
-                for (int i = gl; i < mp; i += kGroup) sab = fma(wa[i], wb[i], sab);
-                sab = group_sum(sab);
+                const double sab = pair_dot(W, mp, a, b, gl);
                 const double saa = dn[a], sbb = dn[b];
                 if (sab != 0.0 && fabs(sab) > tol * sqrt(saa * sbb)) {
                     const double zeta = (sbb - saa) / (2.0 * sab);
                     const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
                     const double cs = 1.0 / sqrt(1.0 + t * t);
                     const double sn = cs * t;
-                    for (int i = gl; i < mp; i += kGroup) {
-                        const double x = wa[i], y = wb[i];
-                        wa[i] = cs * x - sn * y;
-                        wb[i] = sn * x + cs * y;
-                    }
-                    double* va = Vr + (int64_t)a * mp;
-                    double* vb = Vr + (int64_t)b * mp;
-                    for (int i = gl; i < mp; i += kGroup) {
-                        const double x = va[i], y = vb[i];
-                        va[i] = cs * x - sn * y;
-                        vb[i] = sn * x + cs * y;
-                    }
+                    rotate_pair(W, mp, a, b, cs, sn, gl);
+                    rotate_pair(Vr, mp, a, b, cs, sn, gl);
                     if (gl == 0) {
                         dn[a] = saa - t * sab;
                         dn[b] = sbb + t * sab;
@@ -104,7 +146,7 @@ __device__ void jacobi_sweeps(double* W, double* Vr, int mp)
 
 // After jacobi_sweeps: singular values are the column norms of W; write the
 // m leading (sorted descending) triplets.
-__device__ void extract_sorted(const double* W, const double* Vr, int m, int mp, double* sig,
+__device__ __forceinline__ void extract_sorted(const double* W, const double* Vr, int m, int mp, double* sig,
                                int* order, double* P, int ldp_, double* S, double* Q, int ldq_)
 {
     for (int c = threadIdx.x / kGroup; c < mp; c += kGroups) {
@@ -115,12 +157,13 @@ __device__ void extract_sorted(const double* W, const double* Vr, int m, int mp,
         if (threadIdx.x % kGroup == 0) sig[c] = sqrt(s);
     }
     __syncthreads();
-    // rank by value (ties broken by index) -> stable descending order
+    // rank by value (ties broken by index) -> stable descending order.  A NaN
+    // norm ranks as -1 so that the ranks stay a permutation whatever the input.
     for (int c = threadIdx.x; c < mp; c += blockDim.x) {
         int rank = 0;
-        const double sc = sig[c];
+        const double sc = isnan(sig[c]) ? -1.0 : sig[c];
         for (int d = 0; d < mp; ++d) {
-            const double sd = sig[d];
+            const double sd = isnan(sig[d]) ? -1.0 : sig[d];
             rank += (sd > sc) || (sd == sc && d < c);
         }
         order[rank] = c;
@@ -138,13 +181,16 @@ __device__ void extract_sorted(const double* W, const double* Vr, int m, int mp,
 
 }  // namespace
 
+// kLds: the working arrays live in LDS (the compiler then emits LDS
+// instructions); otherwise in gscratch.
+template <bool kLds>
 __global__ void __launch_bounds__(kSvdThreads)
 dense_svd_kernel(const double* __restrict__ B, int m, double* __restrict__ P,
                  double* __restrict__ S, double* __restrict__ Q, double* gscratch)
 {
     extern __shared__ double lds[];
     const int mp = m + (m & 1);
-    double* W = gscratch ? gscratch : lds;
+    double* W = kLds ? lds : gscratch;
     double* Vr = W + mp * mp;
     double* sig = Vr + mp * mp;
     int* order = reinterpret_cast<int*>(sig + mp);
@@ -177,8 +223,8 @@ bool svd_fits_lds(int m)
             v = 65536;
         limit = v;
     }
-    // static LDS of the kernels (flags, reduction scratch) needs a little room
-    return m <= kMaxKrylov && svd_lds_bytes(m) + 1024 <= (size_t)limit;
+    // the kernels' static LDS (column norms, flags) needs room beside the arrays
+    return m <= kMaxKrylov && svd_lds_bytes(m) + sizeof(double) * (kMaxSvd + 2) + 256 <= (size_t)limit;
 }
 
 static void check_svd_size(int m, const double* gscratch)
@@ -194,11 +240,16 @@ void launch_dense_svd(const double* B, int m, double* P, double* S, double* Q, d
     check_svd_size(m, gscratch);
     const bool global = !svd_fits_lds(m);
     const size_t lds = global ? 0 : svd_lds_bytes(m);
-    hipLaunchKernelGGL(dense_svd_kernel, dim3(1), dim3(kSvdThreads), lds, s, B, m, P, S, Q,
-                       global ? gscratch : nullptr);
+    if (global)
+        hipLaunchKernelGGL(dense_svd_kernel<false>, dim3(1), dim3(kSvdThreads), 0, s, B, m, P, S,
+                           Q, gscratch);
+    else
+        hipLaunchKernelGGL(dense_svd_kernel<true>, dim3(1), dim3(kSvdThreads), lds, s, B, m, P, S,
+                           Q, nullptr);
     GKL_LAUNCH_CHECK("dense_svd_kernel");
 }
 
+template <bool kLds>
 __global__ void __launch_bounds__(kSvdThreads)
 ritz_kernel(const double* __restrict__ alpha, const double* __restrict__ beta,
             const double* __restrict__ theta, const double* __restrict__ rho, int nlock, int m,
@@ -206,7 +257,7 @@ ritz_kernel(const double* __restrict__ alpha, const double* __restrict__ beta,
 {
     extern __shared__ double lds[];
     const int mp = m + (m & 1);
-    double* W = gscratch ? gscratch : lds;
+    double* W = kLds ? lds : gscratch;
     double* Vr = W + mp * mp;
     double* sig = Vr + mp * mp;
     int* order = reinterpret_cast<int*>(sig + mp);
@@ -255,8 +306,12 @@ void launch_ritz(const double* alpha, const double* beta, const double* theta, c
     check_svd_size(m, gscratch);
     const bool global = !svd_fits_lds(m);
     const size_t lds = global ? 0 : svd_lds_bytes(m);
-    hipLaunchKernelGGL(ritz_kernel, dim3(1), dim3(kSvdThreads), lds, s, alpha, beta, theta, rho,
-                       nlock, m, k, tol, out, global ? gscratch : nullptr);
+    if (global)
+        hipLaunchKernelGGL(ritz_kernel<false>, dim3(1), dim3(kSvdThreads), 0, s, alpha, beta, theta,
+                           rho, nlock, m, k, tol, out, gscratch);
+    else
+        hipLaunchKernelGGL(ritz_kernel<true>, dim3(1), dim3(kSvdThreads), lds, s, alpha, beta,
+                           theta, rho, nlock, m, k, tol, out, nullptr);
     GKL_LAUNCH_CHECK("ritz_kernel");
 }
 

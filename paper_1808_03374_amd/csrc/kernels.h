@@ -164,6 +164,8 @@ struct MixedWork {
     double* partial = nullptr;
     double* k1 = nullptr;         // 16 per-column constants
     double* k2 = nullptr;
+    double* cpart = nullptr;      // 16 x 64 column-sum partials
+    unsigned int* counters = nullptr;   // 16, zero between launches
 };
 MixedShape mixed_shape(int64_t n, int64_t p);
 size_t mixed_frag_bytes(const MixedShape& m);
@@ -182,14 +184,16 @@ void launch_rmatmat_mixed(const MixedShape& m, const uint8_t* S, const ColStats&
 size_t gemm_tn_partial_elems(int64_t len, int q);
 // H (q x b, ldh) = Q^T Y
 void launch_gemm_tn(const double* Q, int64_t ldq, const double* Y, int64_t ldy, int64_t len, int q,
-                    int b, double* H, int ldh, double* partial, unsigned int* counters,
-                    hipStream_t s);
+                    int b, double* H, int ldh, double* partial, hipStream_t s);
+// Out (len x nc) = Q H (subtract == 0) or Out -= Q H; Q (len x q), H (q x nc, ldh)
+void launch_gemm_nn(const double* Q, int64_t ldq, int q, const double* H, int ldh, double* Out,
+                    int64_t ldo, int64_t len, int nc, int subtract, hipStream_t s);
 // Y -= Q H
 void launch_gemm_nn_sub(const double* Q, int64_t ldq, double* Y, int64_t ldy, int64_t len, int q,
                         int b, const double* H, int ldh, hipStream_t s);
 // shifted CholeskyQR3 of Y in place; R (b x b upper) to Rout; work >= 3 b^2
 void launch_block_qr(double* Y, int64_t ldy, int64_t len, int b, double* Rout, double* work,
-                     double* partial, unsigned int* counters, int* bad, hipStream_t s);
+                     double* partial, int* bad, hipStream_t s);
 void launch_put_block(double* Bm, int ldb, int r0, int c0, const double* X, int rows, int cols,
                       int ldx, int transpose, hipStream_t s);
 void launch_copy_lead(const double* Bm, int ldb, int m, double* out, hipStream_t s);

@@ -42,7 +42,6 @@ struct MixedState {
     double* qrwork = nullptr;  // 3 b^2
     double* tmp = nullptr;     // max(n, p) x keep
     double* gpart = nullptr;
-    unsigned int* gcnt = nullptr;
     double* svd_scratch = nullptr;
     int* iflags = nullptr;     // [0] nconv [1] bad pivots
     RitzOut ritz{};
@@ -82,6 +81,9 @@ void gkl_ctx::setup_mixed()
     M.w.partial = static_cast<double*>(A.alloc(sizeof(double) * mixed_partial_elems(M.shape)));
     M.w.k1 = static_cast<double*>(A.alloc(sizeof(double) * 32));
     M.w.k2 = static_cast<double*>(A.alloc(sizeof(double) * 32));
+    M.w.cpart = static_cast<double*>(A.alloc(sizeof(double) * 16 * 64));
+    M.w.counters = static_cast<unsigned int*>(A.alloc(sizeof(unsigned int) * 16));
+    GKL_HIP(hipMemsetAsync(M.w.counters, 0, sizeof(unsigned int) * 16, s));
     const int b = M.b;
     M.U = static_cast<double*>(A.alloc(sizeof(double) * (size_t)n * m));
     M.V = static_cast<double*>(A.alloc(sizeof(double) * (size_t)p * (m + b)));
@@ -96,7 +98,6 @@ void gkl_ctx::setup_mixed()
     const size_t gp = std::max(gemm_tn_partial_elems(std::max(n, p), m + b),
                                gemm_tn_partial_elems(std::max(n, p), b));
     M.gpart = static_cast<double*>(A.alloc(sizeof(double) * gp));
-    M.gcnt = static_cast<unsigned int*>(A.alloc(sizeof(unsigned int) * 64));
     M.iflags = static_cast<int*>(A.alloc(sizeof(int) * 8));
     M.ritz.B = M.Bc;
     M.ritz.P = static_cast<double*>(A.alloc(sizeof(double) * (size_t)m * m));
@@ -106,7 +107,6 @@ void gkl_ctx::setup_mixed()
     M.ritz.nconv = M.iflags;
     M.svd_scratch = svd_fits_lds(m) ? nullptr
                                     : static_cast<double*>(A.alloc(sizeof(double) * svd_scratch_elems(m)));
-    GKL_HIP(hipMemsetAsync(M.gcnt, 0, sizeof(unsigned int) * 64, s));
     GKL_HIP(hipMemsetAsync(M.iflags, 0, sizeof(int) * 8, s));
     maxm = m;
     keep = M.keep;
@@ -119,7 +119,7 @@ static void block_cgs2(MixedState& M, const double* Q, int64_t len, int q, doubl
     if (q <= 0) return;
     const int b = M.b;
     for (int pass = 0; pass < 2; ++pass) {
-        launch_gemm_tn(Q, len, Y, len, len, q, b, M.H, M.mmax + b, M.gpart, M.gcnt, s);
+        launch_gemm_tn(Q, len, Y, len, len, q, b, M.H, M.mmax + b, M.gpart, s);
         launch_gemm_nn_sub(Q, len, Y, len, len, q, b, M.H, M.mmax + b, s);
     }
 }
@@ -135,7 +135,7 @@ gkl_status gkl_ctx::solve_mixed(double* sigma, double* Uo, int64_t ldu, double* 
     else launch_gaussian(M.V, p * b, opt.seed, 0, s);
     GKL_HIP(hipMemsetAsync(M.Bm, 0, sizeof(double) * (size_t)M.ldb * M.ldb, s));
     GKL_HIP(hipMemsetAsync(M.iflags, 0, sizeof(int) * 8, s));
-    launch_block_qr(M.V, p, p, b, M.R, M.qrwork, M.gpart, M.gcnt, M.iflags + 1, s);
+    launch_block_qr(M.V, p, p, b, M.R, M.qrwork, M.gpart, M.iflags + 1, s);
     int o = 0;
     int nlock_m = 0;         // columns kept at the last restart (0 = none)
     int mcur = 0;
@@ -163,7 +163,7 @@ gkl_status gkl_ctx::solve_mixed(double* sigma, double* Uo, int64_t ldu, double* 
             block_cgs2(M, M.U, n, o, Ub, s);
             info.reorths += 2;
         }
-        launch_block_qr(Ub, n, n, b, M.R, M.qrwork, M.gpart, M.gcnt, M.iflags + 1, s);
+        launch_block_qr(Ub, n, n, b, M.R, M.qrwork, M.gpart, M.iflags + 1, s);
         launch_put_block(M.Bm, M.ldb, o, o, M.R, b, b, b, 0, s);
         // right block: A^T U_o - V_o R^T
         const int ev2 = timing_begin();
@@ -175,7 +175,7 @@ gkl_status gkl_ctx::solve_mixed(double* sigma, double* Uo, int64_t ldu, double* 
         launch_gemm_nn_sub(Vb, p, Vn, p, p, b, b, M.RT, b, s);
         block_cgs2(M, M.V, p, o + b, Vn, s);
         info.reorths += 2;
-        launch_block_qr(Vn, p, p, b, M.C, M.qrwork, M.gpart, M.gcnt, M.iflags + 1, s);
+        launch_block_qr(Vn, p, p, b, M.C, M.qrwork, M.gpart, M.iflags + 1, s);
         launch_put_block(M.Bm, M.ldb, o, o + b, M.C, b, b, b, 1, s);
         o += b;
         mcur = o;
@@ -198,12 +198,12 @@ gkl_status gkl_ctx::solve_mixed(double* sigma, double* Uo, int64_t ldu, double* 
             if (full) {
                 // thick restart keeping M.keep Ritz vectors
                 const int kp = M.keep;
-                launch_gemm_tall(M.V, p, p, mcur, M.ritz.Q, mcur, kp, M.tmp, p, s);
+                launch_gemm_nn(M.V, p, mcur, M.ritz.Q, mcur, M.tmp, p, p, kp, 0, s);
                 GKL_HIP(hipMemcpyAsync(M.V, M.tmp, sizeof(double) * (size_t)p * kp,
                                        hipMemcpyDeviceToDevice, s));
                 GKL_HIP(hipMemcpyAsync(M.V + (int64_t)kp * p, M.V + (int64_t)mcur * p,
                                        sizeof(double) * (size_t)p * b, hipMemcpyDeviceToDevice, s));
-                launch_gemm_tall(M.U, n, n, mcur, M.ritz.P, mcur, kp, M.tmp, n, s);
+                launch_gemm_nn(M.U, n, mcur, M.ritz.P, mcur, M.tmp, n, n, kp, 0, s);
                 GKL_HIP(hipMemcpyAsync(M.U, M.tmp, sizeof(double) * (size_t)n * kp,
                                        hipMemcpyDeviceToDevice, s));
                 launch_restart_block(M.Bm, M.ldb, kp, b, M.ritz.S, M.C, M.ritz.P, mcur, s);
@@ -223,8 +223,8 @@ gkl_status gkl_ctx::solve_mixed(double* sigma, double* Uo, int64_t ldu, double* 
     }
     const int kk = std::min(k, mcur);
     GKL_HIP(hipMemcpyAsync(sigma, M.ritz.S, sizeof(double) * kk, hipMemcpyDeviceToDevice, s));
-    launch_gemm_tall(M.U, n, n, mcur, M.ritz.P, mcur, kk, Uo, ldu, s);
-    launch_gemm_tall(M.V, p, p, mcur, M.ritz.Q, mcur, kk, Vo, ldv, s);
+    launch_gemm_nn(M.U, n, mcur, M.ritz.P, mcur, Uo, ldu, n, kk, 0, s);
+    launch_gemm_nn(M.V, p, mcur, M.ritz.Q, mcur, Vo, ldv, p, kk, 0, s);
     launch_sign_fix(Uo, ldu, n, Vo, ldv, p, kk, s);
     std::vector<double> res(kk), s0(1);
     int bad = 0;
