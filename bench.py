@@ -160,7 +160,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the blocked split-BF16 solve of the same workload")
-    ap.add_argument("--block-width", type=int, default=16)
+    ap.add_argument("--block-width", type=int, default=8)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="after the timed steps, copy BYTES bytes device-to-device 3 times "
                          "(reference dispatch for the HBM traffic counters)")

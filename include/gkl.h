@@ -70,13 +70,16 @@ enum gkl_precision { GKL_PREC_FP64 = 0, GKL_PREC_MIXED = 1 };
 /* Options.  Always initialise with gkl_options_default(). */
 typedef struct gkl_options {
     uint32_t struct_size;     /* sizeof(gkl_options), set by gkl_options_default */
-    int32_t krylov_dim;       /* m, vectors kept before a thick restart; 0 = no restart */
-    int32_t keep;             /* l, Ritz vectors kept at a restart; 0 = k + (m - k)/2 */
+    int32_t krylov_dim;       /* m, vectors kept before a thick restart; 0 = no restart
+                                 (FP64), or max(96, 3k + b) rounded to b (blocked) */
+    int32_t keep;             /* l, Ritz vectors kept at a restart; 0 = k + (m - k)/2
+                                 (FP64) or k + (m - k)/4 (blocked) */
     int32_t precision;        /* gkl_precision */
-    int32_t block_width;      /* b of the mixed blocked variant (1..32); 0 = 16 */
+    int32_t block_width;      /* b of the mixed blocked variant (1..32); 0 = 8 */
     int32_t adaptive_cgs2;    /* 1: second Gram-Schmidt pass only when the first pass
                                  shrank the vector below 1/sqrt(2) of its norm */
-    int32_t check_every;      /* steps between convergence tests without restart; 0 = auto */
+    int32_t check_every;      /* steps between convergence tests; 0 = auto (when the
+                                 basis is full if restarting, else every 5 steps) */
     int32_t max_steps;        /* cap on the basis size without restart; 0 = min(n, p) */
     double pro_omega;         /* PRO threshold on the orthogonality estimate; 0 = 1e-8 */
     int64_t max_matvecs;      /* stop with GKL_NOT_CONVERGED after this many; 0 = unlimited */
@@ -88,6 +91,10 @@ typedef struct gkl_options {
     int32_t verbose;          /* 1: progress lines on stderr */
     int32_t timing;           /* 1: bracket every product launch with HIP events and
                                  report the kernel time in gkl_info */
+    int32_t autotune;         /* batched: 1 = time candidate product geometries at
+                                 create and keep the fastest; 0 = fixed geometry */
+    int32_t graph;            /* batched: 1 (default) = each Lanczos step is one HIP
+                                 graph launch; 0 = the same kernels launched one by one */
 } gkl_options;
 
 /* Run statistics (host struct). */
@@ -169,6 +176,12 @@ gkl_status gkl_create_batched(int32_t count, const uint8_t* const* G, const int6
 gkl_status gkl_solve_batched(gkl_ctx* ctx, double* const* sigma, double* const* U,
                              const int64_t* ldu, double* const* V, const int64_t* ldv,
                              gkl_info* infos);
+/*   Product geometry of a batched context (after autotuning when options.autotune
+ *   was set): K-split target in workgroups per problem and persistent grid size
+ *   of the A v and A^T u launches, and their measured launch times in ms (0 when
+ *   not tuned).  Any pointer may be NULL. */
+gkl_status gkl_batched_plan(const gkl_ctx* ctx, int64_t* mv_target, int64_t* rmv_target,
+                            int32_t* grid_mv, int32_t* grid_rmv, double* mv_ms, double* rmv_ms);
 
 /* ---------------- kernel-level entry points on an existing context ----------
  * Used by the parity tests and the bench; same conventions as above.  All

@@ -43,6 +43,8 @@ class gkl_options(ctypes.Structure):
         ("trace", ctypes.c_int32),
         ("verbose", ctypes.c_int32),
         ("timing", ctypes.c_int32),
+        ("autotune", ctypes.c_int32),
+        ("graph", ctypes.c_int32),
     ]
 
 
@@ -110,6 +112,7 @@ _SIGS = {
     "gkl_create_batched": (_st, [_i32, _vp, _vp, _vp, _i32, _dbl, _i32,
                                  ctypes.POINTER(gkl_options), _ctx_pp]),
     "gkl_solve_batched": (_st, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "gkl_batched_plan": (_st, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "gkl_column_stats": (_st, [_vp, _vp, _vp, _vp, _vp]),
     "gkl_unpack": (_st, [_vp, _vp]),
     "gkl_matvec": (_st, [_vp, _vp, _vp]),
@@ -211,6 +214,16 @@ def gkl_solve_batched(ctx, sigmas, Us, ldus, Vs, ldvs):
     st = lib.gkl_solve_batched(ctx, SA, UA, LU, VA, LV, infos)
     _check(st, ctx, allow=(GKL_NOT_CONVERGED,))
     return st, list(infos)
+
+
+def gkl_batched_plan(ctx):
+    mt, rt = ctypes.c_int64(), ctypes.c_int64()
+    gm, gr = ctypes.c_int32(), ctypes.c_int32()
+    a, b = ctypes.c_double(), ctypes.c_double()
+    _check(lib.gkl_batched_plan(ctx, ctypes.byref(mt), ctypes.byref(rt), ctypes.byref(gm),
+                                ctypes.byref(gr), ctypes.byref(a), ctypes.byref(b)), ctx)
+    return {"mv_target": mt.value, "rmv_target": rt.value, "grid_mv": gm.value,
+            "grid_rmv": gr.value, "mv_ms": a.value, "rmv_ms": b.value}
 
 
 def gkl_column_stats(ctx, count, nobs, mean, inv_sd):
@@ -331,6 +344,55 @@ class Context:
 
     def trace(self):
         return gkl_get_trace(self.ctx)
+
+    def close(self):
+        if self.ctx:
+            gkl_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BatchedContext:
+    """Owns one batched gkl_ctx over a list of torch.uint8 CUDA tensors (p_q, ld_q)."""
+
+    def __init__(self, Gs, ns, ps, k, tol=1e-10, reorth=GKL_REORTH_FULL, **options):
+        import torch
+        self._torch = torch
+        self.Gs = list(Gs)
+        self.ns = [int(x) for x in ns]
+        self.ps = [int(x) for x in ps]
+        self.k = int(k)
+        opt = gkl_options_default()
+        self._v0 = None
+        for key, val in options.items():
+            if key == "v0":
+                if val is not None:
+                    self._v0 = val
+                    opt.v0 = val.data_ptr()
+            elif key == "stream":
+                opt.stream = val
+            else:
+                setattr(opt, key, val)
+        self.opt = opt
+        self.ctx = gkl_create_batched(self.Gs, self.ns, self.ps, self.k, tol, reorth, opt)
+
+    def solve(self):
+        """Returns (sigmas, Us, Vs, status, infos) as lists over the problems."""
+        torch = self._torch
+        dev = self.Gs[0].device
+        sig = [torch.empty(self.k, dtype=torch.float64, device=dev) for _ in self.ns]
+        Us = [torch.empty((self.k, n), dtype=torch.float64, device=dev) for n in self.ns]
+        Vs = [torch.empty((self.k, p), dtype=torch.float64, device=dev) for p in self.ps]
+        st, infos = gkl_solve_batched(self.ctx, sig, Us, self.ns, Vs, self.ps)
+        return sig, [u.T for u in Us], [v.T for v in Vs], st, infos
+
+    def plan(self):
+        return gkl_batched_plan(self.ctx)
 
     def close(self):
         if self.ctx:

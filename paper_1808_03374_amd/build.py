@@ -18,7 +18,7 @@ BUILD_DIR = os.path.join(HERE, "_build")
 ARCH = os.environ.get("GKL_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["engine.hip", "k_stats.hip", "k_matvec.hip", "k_ortho.hip", "k_svd.hip", "k_pro.hip",
-           "k_mixed.hip", "k_block.hip", "mixed.hip", "batched.hip"]
+           "k_mixed.hip", "k_block.hip", "k_batch.hip", "mixed.hip", "batched.hip"]
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # packed-FP32 instructions are disabled on purpose (see the design notes)

@@ -39,6 +39,8 @@ void launch_norm(const double* r, int64_t len, double* out, OrthoWork& w, hipStr
 struct MixedState;   // blocked split-BF16 solver (k_mixed / mixed.hip)
 struct BatchState;   // batched persistent solver (batched.hip)
 bool mixed_supported();
+// Message returned by gkl_last_error(NULL) (last failed create on this thread).
+void set_create_error(const std::string& msg);
 void destroy_mixed(MixedState* m);
 void destroy_batch(BatchState* b);
 

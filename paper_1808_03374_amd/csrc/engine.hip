@@ -139,6 +139,10 @@ void gkl_ctx::allocate_solver()
 
 static thread_local std::string g_create_error;
 
+namespace gkl {
+void set_create_error(const std::string& msg) { g_create_error = msg; }
+}  // namespace gkl
+
 static gkl_status set_error(gkl_ctx* ctx, gkl_status s, const std::string& msg)
 {
     if (ctx) ctx->last_error = msg;
@@ -491,8 +495,9 @@ void gkl_options_default(gkl_options* o)
     memset(o, 0, sizeof(*o));
     o->struct_size = sizeof(gkl_options);
     o->pro_omega = 1e-8;
-    o->block_width = 16;
+    o->block_width = 0;
     o->adaptive_cgs2 = 0;
+    o->graph = 1;
     o->seed = 0x5EEDull;
 }
 

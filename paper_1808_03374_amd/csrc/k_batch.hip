@@ -1,0 +1,255 @@
+// Batched Gram-Schmidt, norms and step bookkeeping for many problems (gfx950).
+//
+// The batched solver runs the FP64 GKL iteration of Section 3 of the paper on
+// many genotype matrices at once (one per chromosome, say).  All problems step
+// together; every kernel here covers every active problem in one launch
+// (grid.y = problem), so one Lanczos step is a fixed sequence of launches that
+// is captured once in a HIP graph and replayed.  The step index lives on the
+// device (state[0]) for the same reason.
+//
+// Full reorthogonalisation by classical Gram-Schmidt applied twice (CGS2): for
+// a new vector r and basis Q(:, 0:c), h = Q^T r, r <- r - Q h, twice; the norm
+// of the result (accumulated while the second update writes r) becomes alpha_j
+// or beta_j and r is scaled to unit length.  Sums over row chunks are added in
+// chunk order, so results do not depend on scheduling.
+#include <math.h>
+
+#include "kernels.h"
+
+namespace gkl {
+
+namespace {
+constexpr int kChunk = 2048;       // rows per workgroup in the Gram-Schmidt kernels
+constexpr int kPerLane = kChunk / kWave;
+
+struct Side {
+    int64_t len;
+    int ncols;
+    const double* Q;
+    double* r;
+    double* scalar;
+};
+
+__device__ __forceinline__ Side side_of(const BatchDesc& D, int j, int side)
+{
+    Side s;
+    if (side == 0) {
+        s.len = D.n;
+        s.ncols = j;
+        s.Q = D.U;
+        s.r = D.U + (int64_t)j * D.n;
+        s.scalar = D.alpha + j;
+    } else {
+        s.len = D.p;
+        s.ncols = j + 1;
+        s.Q = D.V;
+        s.r = D.V + (int64_t)(j + 1) * D.p;
+        s.scalar = D.beta + j;
+    }
+    return s;
+}
+}  // namespace
+
+size_t bortho_chunks(int64_t len) { return (size_t)((len + kChunk - 1) / kChunk); }
+
+// hpart[chunk][c] = sum over the chunk's rows of Q(row, c) r(row); each wave takes
+// columns wave, wave + 4, ... with the chunk of r held in registers.
+__global__ void __launch_bounds__(256)
+bproj_kernel(const BatchDesc* __restrict__ desc, const int* __restrict__ state, int side,
+             int hstride)
+{
+    const BatchDesc& D = desc[blockIdx.y];
+    if (!*D.active) return;
+    const Side S = side_of(D, state[0], side);
+    const int64_t r0 = (int64_t)blockIdx.x * kChunk;
+    if (r0 >= S.len || S.ncols == 0) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double rv[kPerLane];
+#pragma unroll
+    for (int t = 0; t < kPerLane; ++t) {
+        const int64_t row = r0 + lane + (int64_t)t * kWave;
+        rv[t] = row < S.len ? S.r[row] : 0.0;
+    }
+    for (int c = wave; c < S.ncols; c += 4) {
+        const double* qc = S.Q + (int64_t)c * S.len;
+        double a = 0.0;
+#pragma unroll
+        for (int t = 0; t < kPerLane; ++t) {
+            const int64_t row = r0 + lane + (int64_t)t * kWave;
+            if (row < S.len) a = fma(qc[row], rv[t], a);
+        }
+        a = wave_sum(a);
+        if (lane == 0) D.hpart[(int64_t)blockIdx.x * hstride + c] = a;
+    }
+}
+
+// h[c] = sum of hpart over the chunks, in chunk order.
+__global__ void __launch_bounds__(256)
+bproj_reduce_kernel(const BatchDesc* __restrict__ desc, const int* __restrict__ state, int side,
+                    int hstride)
+{
+    const BatchDesc& D = desc[blockIdx.x];
+    if (!*D.active) return;
+    const Side S = side_of(D, state[0], side);
+    const int nch = (int)((S.len + kChunk - 1) / kChunk);
+    for (int c = threadIdx.x; c < S.ncols; c += blockDim.x) {
+        double a = 0.0;
+        for (int ch = 0; ch < nch; ++ch) a += D.hpart[(int64_t)ch * hstride + c];
+        D.h[c] = a;
+    }
+}
+
+// r <- r - Q h over the chunk's rows; with norm != 0 the chunk's sum of squares
+// of the new r goes to npart[chunk].
+__global__ void __launch_bounds__(256)
+bupdate_kernel(const BatchDesc* __restrict__ desc, const int* __restrict__ state, int side,
+               int norm)
+{
+    __shared__ double hs[kMaxSvd + 2];
+    __shared__ double red[16];
+    const BatchDesc& D = desc[blockIdx.y];
+    if (!*D.active) return;
+    const Side S = side_of(D, state[0], side);
+    const int64_t r0 = (int64_t)blockIdx.x * kChunk;
+    if (r0 >= S.len) return;
+    for (int c = threadIdx.x; c < S.ncols; c += blockDim.x) hs[c] = D.h[c];
+    __syncthreads();
+    double ss = 0.0;
+    for (int t = 0; t < kChunk / 256; ++t) {
+        const int64_t row = r0 + threadIdx.x + (int64_t)t * 256;
+        if (row >= S.len) break;
+        double x = S.r[row];
+        for (int c = 0; c < S.ncols; ++c) x = fma(-S.Q[(int64_t)c * S.len + row], hs[c], x);
+        S.r[row] = x;
+        ss = fma(x, x, ss);
+    }
+    if (norm) {
+        ss = block_sum(ss, red);
+        if (threadIdx.x == 0) D.npart[blockIdx.x] = ss;
+    }
+}
+
+// alpha_j / beta_j = ||r|| from the chunk sums (one wave per problem).  A norm
+// at or below 2^-52 sqrt(len) times the largest scalar so far is a breakdown:
+// the problem stops (its scalar is 0 and the vector is left unscaled).
+__global__ void __launch_bounds__(64)
+bnorm_kernel(const BatchDesc* __restrict__ desc, const int* __restrict__ state, int side)
+{
+    const BatchDesc& D = desc[blockIdx.x];
+    if (!*D.active) return;
+    const Side S = side_of(D, state[0], side);
+    const int nch = (int)((S.len + kChunk - 1) / kChunk);
+    double a = 0.0;
+    for (int ch = threadIdx.x; ch < nch; ch += 64) a += D.npart[ch];
+    a = wave_sum(a);
+    if (threadIdx.x == 0) {
+        const double nrm = sqrt(a);
+        const double scale = *D.anorm;
+        if (!(nrm > 2.220446049250313e-16 * sqrt((double)S.len) * scale) || !(nrm > 0.0)) {
+            *S.scalar = 0.0;
+            *D.breakdown = 1;
+            *D.active = 0;
+        } else {
+            *S.scalar = nrm;
+            if (nrm > scale) *D.anorm = nrm;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256)
+bscale_kernel(const BatchDesc* __restrict__ desc, const int* __restrict__ state, int side)
+{
+    const BatchDesc& D = desc[blockIdx.y];
+    if (!*D.active) return;
+    const Side S = side_of(D, state[0], side);
+    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= S.len) return;
+    S.r[row] = S.r[row] / *S.scalar;
+}
+
+void launch_bortho(const BatchDesc* d, const int* state, int count, int side, int64_t max_len,
+                   int hstride, hipStream_t s)
+{
+    const dim3 gch((unsigned int)bortho_chunks(max_len), (unsigned int)count);
+    for (int pass = 0; pass < 2; ++pass) {
+        hipLaunchKernelGGL(bproj_kernel, gch, dim3(256), 0, s, d, state, side, hstride);
+        GKL_LAUNCH_CHECK("bproj_kernel");
+        hipLaunchKernelGGL(bproj_reduce_kernel, dim3(count), dim3(256), 0, s, d, state, side,
+                           hstride);
+        GKL_LAUNCH_CHECK("bproj_reduce_kernel");
+        hipLaunchKernelGGL(bupdate_kernel, gch, dim3(256), 0, s, d, state, side, pass == 1 ? 1 : 0);
+        GKL_LAUNCH_CHECK("bupdate_kernel");
+    }
+    hipLaunchKernelGGL(bnorm_kernel, dim3(count), dim3(64), 0, s, d, state, side);
+    GKL_LAUNCH_CHECK("bnorm_kernel");
+    hipLaunchKernelGGL(bscale_kernel, dim3(ceil_div(max_len, 256), count), dim3(256), 0, s, d, state,
+                       side);
+    GKL_LAUNCH_CHECK("bscale_kernel");
+}
+
+__global__ void bstep_kernel(int* state)
+{
+    if (threadIdx.x == 0) state[0] += 1;
+}
+
+void launch_bstep(int* state, hipStream_t s)
+{
+    hipLaunchKernelGGL(bstep_kernel, dim3(1), dim3(64), 0, s, state);
+    GKL_LAUNCH_CHECK("bstep_kernel");
+}
+
+// Start of a solve: v_0 <- v_0 / ||v_0|| for every active problem (the norm is
+// summed in chunk order by one wave per problem).
+__global__ void __launch_bounds__(256)
+bstart_norm_kernel(const BatchDesc* __restrict__ desc)
+{
+    __shared__ double red[16];
+    const BatchDesc& D = desc[blockIdx.y];
+    const int64_t r0 = (int64_t)blockIdx.x * kChunk;
+    if (r0 >= D.p) return;
+    double ss = 0.0;
+    for (int t = 0; t < kChunk / 256; ++t) {
+        const int64_t row = r0 + threadIdx.x + (int64_t)t * 256;
+        if (row < D.p) ss = fma(D.V[row], D.V[row], ss);
+    }
+    ss = block_sum(ss, red);
+    if (threadIdx.x == 0) D.npart[blockIdx.x] = ss;
+}
+
+__global__ void __launch_bounds__(64)
+bstart_sum_kernel(const BatchDesc* __restrict__ desc)
+{
+    const BatchDesc& D = desc[blockIdx.x];
+    const int nch = (int)((D.p + kChunk - 1) / kChunk);
+    double a = 0.0;
+    for (int ch = threadIdx.x; ch < nch; ch += 64) a += D.npart[ch];
+    a = wave_sum(a);
+    if (threadIdx.x == 0) {
+        D.h[0] = sqrt(a);
+        *D.anorm = 0.0;
+        *D.breakdown = 0;
+    }
+}
+
+__global__ void __launch_bounds__(256)
+bstart_scale_kernel(const BatchDesc* __restrict__ desc)
+{
+    const BatchDesc& D = desc[blockIdx.y];
+    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= D.p) return;
+    const double nrm = D.h[0];
+    D.V[row] = nrm > 0.0 ? D.V[row] / nrm : 0.0;
+}
+
+void launch_bstart(const BatchDesc* d, int count, int64_t max_p, int, hipStream_t s)
+{
+    hipLaunchKernelGGL(bstart_norm_kernel, dim3((unsigned int)bortho_chunks(max_p), count),
+                       dim3(256), 0, s, d);
+    GKL_LAUNCH_CHECK("bstart_norm_kernel");
+    hipLaunchKernelGGL(bstart_sum_kernel, dim3(count), dim3(64), 0, s, d);
+    GKL_LAUNCH_CHECK("bstart_sum_kernel");
+    hipLaunchKernelGGL(bstart_scale_kernel, dim3(ceil_div(max_p, 256), count), dim3(256), 0, s, d);
+    GKL_LAUNCH_CHECK("bstart_scale_kernel");
+}
+
+}  // namespace gkl

@@ -144,18 +144,22 @@ void build_layouts(const uint8_t* G, int64_t ld, const Packed& L, hipStream_t s)
 // ---------------------------------------------------------------------------
 // A v: partial[split][i] over the split's SNP quads
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kMvThreads)
-matvec_lut_kernel(const uint8_t* __restrict__ T, int64_t nT, int64_t p, int64_t Pq,
-                  const double* __restrict__ mean, const double* __restrict__ inv_sd,
-                  const double* __restrict__ v, int64_t quads_per_split,
-                  double* __restrict__ partial)
+// One tile of A v: rows of row block bx, SNP quads of split by.  Called by the
+// single-problem kernel (one tile per workgroup) and by the persistent batched
+// kernel (many tiles per workgroup; every thread of the workgroup runs the same
+// tiles, and a tile ends with a barrier, so the LDS tables can be reused).
+__device__ __forceinline__ void matvec_tile(const uint8_t* __restrict__ T, int64_t nT, int64_t p,
+                                            int64_t Pq, const double* __restrict__ mean,
+                                            const double* __restrict__ inv_sd,
+                                            const double* __restrict__ v, int64_t quads_per_split,
+                                            double* __restrict__ partial, int64_t bx, int64_t by)
 {
     __shared__ double tv[kQCH * 4 * 4];          // t value per (SNP, code)
     __shared__ double pairs[kQCH * 2 * 16];      // per quad: codes of SNPs (0,1) and (2,3)
     __shared__ double lut[kQCH * 256];           // 32 KB
-    const int64_t row0 = (int64_t)blockIdx.x * kRowsPerBlock + (int64_t)threadIdx.x * kIPT;
+    const int64_t row0 = bx * kRowsPerBlock + (int64_t)threadIdx.x * kIPT;
     const bool active = row0 < nT;
-    const int64_t Jb = (int64_t)blockIdx.y * quads_per_split;
+    const int64_t Jb = by * quads_per_split;
     const int64_t Je = Jb + quads_per_split < Pq ? Jb + quads_per_split : Pq;
     double acc[kIPT];
 #pragma unroll
@@ -202,11 +206,20 @@ matvec_lut_kernel(const uint8_t* __restrict__ T, int64_t nT, int64_t p, int64_t 
         __syncthreads();
     }
     if (active) {
-        double* out = partial + (int64_t)blockIdx.y * nT + row0;
+        double* out = partial + by * nT + row0;
 #pragma unroll
         for (int r = 0; r < kIPT; r += 2)
             *reinterpret_cast<double2*>(out + r) = make_double2(acc[r], acc[r + 1]);
     }
+}
+
+__global__ void __launch_bounds__(kMvThreads)
+matvec_lut_kernel(const uint8_t* __restrict__ T, int64_t nT, int64_t p, int64_t Pq,
+                  const double* __restrict__ mean, const double* __restrict__ inv_sd,
+                  const double* __restrict__ v, int64_t quads_per_split,
+                  double* __restrict__ partial)
+{
+    matvec_tile(T, nT, p, Pq, mean, inv_sd, v, quads_per_split, partial, blockIdx.x, blockIdx.y);
 }
 
 // y[i] = sum over splits (fixed order within each of 8 split groups, then the
@@ -250,16 +263,17 @@ matvec_reduce_kernel(const double* __restrict__ partial, int64_t nT, int nsplit,
 // ---------------------------------------------------------------------------
 // A^T u: partial[split][j] = sum_i g u - mu_j sum_i o u over the split's quads
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kMvThreads)
-rmatvec_lut_kernel(const uint8_t* __restrict__ P, int64_t pP, int64_t n, int64_t nq, int64_t p,
-                   const double* __restrict__ u, const double* __restrict__ mean,
-                   int64_t iq_per_split, double* __restrict__ partial)
+// One tile of A^T u: SNP block bx, individual quads of split by (see matvec_tile).
+__device__ __forceinline__ void rmatvec_tile(const uint8_t* __restrict__ P, int64_t pP, int64_t n,
+                                             int64_t nq, int64_t p, const double* __restrict__ u,
+                                             const double* __restrict__ mean, int64_t iq_per_split,
+                                             double* __restrict__ partial, int64_t bx, int64_t by)
 {
     __shared__ double uq[kQI * 4];
     __shared__ double2 pairs[kQI * 2 * 16];
     __shared__ double2 lut[kQI * 256];           // 32 KB
-    const int64_t col0 = (int64_t)blockIdx.x * kColsPerBlock + (int64_t)threadIdx.x * kSPT;
-    const int64_t Ib = (int64_t)blockIdx.y * iq_per_split;
+    const int64_t col0 = bx * kColsPerBlock + (int64_t)threadIdx.x * kSPT;
+    const int64_t Ib = by * iq_per_split;
     const int64_t Ie = Ib + iq_per_split < nq ? Ib + iq_per_split : nq;
     double sg[kSPT], so[kSPT];
 #pragma unroll
@@ -309,7 +323,7 @@ rmatvec_lut_kernel(const uint8_t* __restrict__ P, int64_t pP, int64_t n, int64_t
         }
         __syncthreads();
     }
-    double* out = partial + (int64_t)blockIdx.y * pP + col0;
+    double* out = partial + by * pP + col0;
 #pragma unroll
     for (int k = 0; k < kSPT; k += 2) {
         const int64_t j = col0 + k;
@@ -318,6 +332,14 @@ rmatvec_lut_kernel(const uint8_t* __restrict__ P, int64_t pP, int64_t n, int64_t
         *reinterpret_cast<double2*>(out + k) =
             make_double2(sg[k] - m0 * so[k], sg[k + 1] - m1 * so[k + 1]);
     }
+}
+
+__global__ void __launch_bounds__(kMvThreads)
+rmatvec_lut_kernel(const uint8_t* __restrict__ P, int64_t pP, int64_t n, int64_t nq, int64_t p,
+                   const double* __restrict__ u, const double* __restrict__ mean,
+                   int64_t iq_per_split, double* __restrict__ partial)
+{
+    rmatvec_tile(P, pP, n, nq, p, u, mean, iq_per_split, partial, blockIdx.x, blockIdx.y);
 }
 
 __global__ void rmatvec_reduce_kernel(const double* __restrict__ partial, int64_t pP, int nsplit,
@@ -363,21 +385,23 @@ Split choose_split(int64_t kquads, int64_t other_blocks, int64_t chunk, int64_t 
     return s;
 }
 
-Split mv_split(const Packed& L)
+constexpr int64_t kSplitTarget = 1536;   // blocks per single-problem launch
+
+Split mv_split(const Packed& L, int64_t target = kSplitTarget)
 {
     const int64_t rowblocks = (L.nT + kRowsPerBlock - 1) / kRowsPerBlock;
     // partial traffic nsplit * nT * 8 B kept near 5% of the packed bytes
     int64_t cap = (L.Pq * 4) / 400;
     if (cap < 1) cap = 1;
-    return choose_split(L.Pq, rowblocks, kQCH, 1536, cap);
+    return choose_split(L.Pq, rowblocks, kQCH, target, cap);
 }
 
-Split rmv_split(const Packed& L)
+Split rmv_split(const Packed& L, int64_t target = kSplitTarget)
 {
     const int64_t colblocks = L.pP / kColsPerBlock;
     int64_t cap = (L.nq * 4) / 640;
     if (cap < 1) cap = 1;
-    return choose_split(L.nq, colblocks, kQI, 1536, cap);
+    return choose_split(L.nq, colblocks, kQI, target, cap);
 }
 }  // namespace
 
@@ -417,6 +441,169 @@ void launch_rmatvec(const Packed& L, const ColStats& st, const double* u, double
     hipLaunchKernelGGL(rmatvec_reduce_kernel, dim3(nb), dim3(256), 0, s, w.partial, L.pP,
                        sp.nsplit, L.p, st.inv_sd, z, alpha, vprev);
     GKL_LAUNCH_CHECK("rmatvec_reduce_kernel");
+}
+
+// ---------------------------------------------------------------------------
+// Batched products: one persistent launch covers the tiles of every problem
+// ---------------------------------------------------------------------------
+ProductPlan product_plan(const Packed& L, int64_t mv_target, int64_t rmv_target)
+{
+    const Split a = mv_split(L, mv_target), b = rmv_split(L, rmv_target);
+    ProductPlan pl;
+    pl.mv_per_split = a.per_split;
+    pl.mv_nsplit = a.nsplit;
+    pl.mv_rowblocks = (int)((L.nT + kRowsPerBlock - 1) / kRowsPerBlock);
+    pl.rmv_per_split = b.per_split;
+    pl.rmv_nsplit = b.nsplit;
+    pl.rmv_colblocks = (int)(L.pP / kColsPerBlock);
+    return pl;
+}
+
+size_t product_plan_partial_elems(const Packed& L, const ProductPlan& pl)
+{
+    const size_t a = (size_t)pl.mv_nsplit * (size_t)L.nT;
+    const size_t b = (size_t)pl.rmv_nsplit * (size_t)L.pP;
+    return a > b ? a : b;
+}
+
+namespace {
+// Problem owning global tile t: the last q with tile0[q] <= t.
+__device__ __forceinline__ int owner(const int* tile0, int count, int t)
+{
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tile0[mid] <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+}  // namespace
+
+__global__ void __launch_bounds__(kMvThreads)
+bmatvec_kernel(const BatchDesc* __restrict__ desc, const int* __restrict__ tile0, int count,
+               const int* __restrict__ state)
+{
+    __shared__ int t0[kMaxBatch + 1];
+    for (int i = threadIdx.x; i <= count; i += blockDim.x) t0[i] = tile0[i];
+    __syncthreads();
+    const int total = t0[count];
+    const int64_t j = state[0];
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+        const int q = owner(t0, count, t);
+        const BatchDesc& D = desc[q];
+        if (!*D.active) continue;            // the same for the whole workgroup
+        const int l = t - t0[q];
+        matvec_tile(D.T, D.nT, D.p, D.Pq, D.mean, D.inv_sd, D.V + j * D.p, D.mv_per_split,
+                    D.partial, l % D.mv_rowblocks, l / D.mv_rowblocks);
+    }
+}
+
+__global__ void __launch_bounds__(kMvThreads)
+brmatvec_kernel(const BatchDesc* __restrict__ desc, const int* __restrict__ tile0, int count,
+                const int* __restrict__ state)
+{
+    __shared__ int t0[kMaxBatch + 1];
+    for (int i = threadIdx.x; i <= count; i += blockDim.x) t0[i] = tile0[i];
+    __syncthreads();
+    const int total = t0[count];
+    const int64_t j = state[0];
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+        const int q = owner(t0, count, t);
+        const BatchDesc& D = desc[q];
+        if (!*D.active) continue;
+        const int l = t - t0[q];
+        rmatvec_tile(D.P, D.pP, D.n, D.nq, D.p, D.U + j * D.n, D.mean, D.rmv_per_split, D.partial,
+                     l % D.rmv_colblocks, l / D.rmv_colblocks);
+    }
+}
+
+// grid (row chunks of the largest n, problems); same summation order as
+// matvec_reduce_kernel.
+__global__ void __launch_bounds__(kRedRows * kRedGroups)
+bmatvec_reduce_kernel(const BatchDesc* __restrict__ desc, const int* __restrict__ state)
+{
+    __shared__ double sh[kRedGroups][kRedRows];
+    const BatchDesc& D = desc[blockIdx.y];
+    if (!*D.active || (int64_t)blockIdx.x * kRedRows >= D.n) return;   // whole workgroup
+    const int r = threadIdx.x % kRedRows, g = threadIdx.x / kRedRows;
+    const int64_t i = (int64_t)blockIdx.x * kRedRows + r;
+    const int64_t n = D.n, nT = D.nT;
+    const int nsplit = D.mv_nsplit;
+    const double* partial = D.partial;
+    double a = 0.0;
+    if (i < n) {
+        int sp = g;
+        for (; sp + 3 * kRedGroups < nsplit; sp += 4 * kRedGroups) {
+            const double x0 = partial[(int64_t)sp * nT + i];
+            const double x1 = partial[(int64_t)(sp + kRedGroups) * nT + i];
+            const double x2 = partial[(int64_t)(sp + 2 * kRedGroups) * nT + i];
+            const double x3 = partial[(int64_t)(sp + 3 * kRedGroups) * nT + i];
+            a += x0;
+            a += x1;
+            a += x2;
+            a += x3;
+        }
+        for (; sp < nsplit; sp += kRedGroups) a += partial[(int64_t)sp * nT + i];
+    }
+    sh[g][r] = a;
+    __syncthreads();
+    if (g == 0 && i < n) {
+        double s = 0.0;
+        for (int t = 0; t < kRedGroups; ++t) s += sh[t][r];
+        const int j = state[0], nlock = state[1];
+        if (j > 0 && j == nlock) {
+            for (int c = 0; c < nlock; ++c) s -= D.rho[c] * D.U[(int64_t)c * n + i];
+        } else if (j > 0) {
+            s -= D.beta[j - 1] * D.U[(int64_t)(j - 1) * n + i];
+        }
+        D.U[(int64_t)j * n + i] = s;
+    }
+}
+
+__global__ void __launch_bounds__(256)
+brmatvec_reduce_kernel(const BatchDesc* __restrict__ desc, const int* __restrict__ state)
+{
+    const BatchDesc& D = desc[blockIdx.y];
+    if (!*D.active) return;
+    const int64_t jj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (jj >= D.p) return;
+    const int j = state[0];
+    double s = 0.0;
+    for (int sp = 0; sp < D.rmv_nsplit; ++sp) s += D.partial[(int64_t)sp * D.pP + jj];
+    double r = D.inv_sd[jj] * s;
+    r -= D.alpha[j] * D.V[(int64_t)j * D.p + jj];
+    D.V[(int64_t)(j + 1) * D.p + jj] = r;
+}
+
+void launch_bmatvec(const BatchDesc* d, const int* tile0, int count, const int* state, int grid,
+                    hipStream_t s)
+{
+    hipLaunchKernelGGL(bmatvec_kernel, dim3(grid), dim3(kMvThreads), 0, s, d, tile0, count, state);
+    GKL_LAUNCH_CHECK("bmatvec_kernel");
+}
+
+void launch_brmatvec(const BatchDesc* d, const int* tile0, int count, const int* state, int grid,
+                     hipStream_t s)
+{
+    hipLaunchKernelGGL(brmatvec_kernel, dim3(grid), dim3(kMvThreads), 0, s, d, tile0, count, state);
+    GKL_LAUNCH_CHECK("brmatvec_kernel");
+}
+
+void launch_bmatvec_reduce(const BatchDesc* d, const int* state, int count, int64_t max_n,
+                           hipStream_t s)
+{
+    hipLaunchKernelGGL(bmatvec_reduce_kernel, dim3(ceil_div(max_n, kRedRows), count),
+                       dim3(kRedRows * kRedGroups), 0, s, d, state);
+    GKL_LAUNCH_CHECK("bmatvec_reduce_kernel");
+}
+
+void launch_brmatvec_reduce(const BatchDesc* d, const int* state, int count, int64_t max_p,
+                            hipStream_t s)
+{
+    hipLaunchKernelGGL(brmatvec_reduce_kernel, dim3(ceil_div(max_p, 256), count), dim3(256), 0, s,
+                       d, state);
+    GKL_LAUNCH_CHECK("brmatvec_reduce_kernel");
 }
 
 // Unpack from layout T to n x p column-major int8 (-1 = missing).

@@ -249,18 +249,16 @@ void launch_dense_svd(const double* B, int m, double* P, double* S, double* Q, d
     GKL_LAUNCH_CHECK("dense_svd_kernel");
 }
 
-template <bool kLds>
-__global__ void __launch_bounds__(kSvdThreads)
-ritz_kernel(const double* __restrict__ alpha, const double* __restrict__ beta,
-            const double* __restrict__ theta, const double* __restrict__ rho, int nlock, int m,
-            int k, double tol, RitzOut out, double* gscratch)
+// Projected matrix from the recurrence scalars, its SVD and the residual test
+// (one workgroup; W, Vr, sig, order are the working arrays).
+__device__ __forceinline__ void ritz_body(const double* __restrict__ alpha,
+                                          const double* __restrict__ beta,
+                                          const double* __restrict__ theta,
+                                          const double* __restrict__ rho, int nlock, int m, int k,
+                                          double tol, const RitzOut& out, double* W, double* Vr,
+                                          double* sig, int* order)
 {
-    extern __shared__ double lds[];
     const int mp = m + (m & 1);
-    double* W = kLds ? lds : gscratch;
-    double* Vr = W + mp * mp;
-    double* sig = Vr + mp * mp;
-    int* order = reinterpret_cast<int*>(sig + mp);
     for (int t = threadIdx.x; t < mp * mp; t += blockDim.x) {
         const int i = t % mp, c = t / mp;
         double v = 0.0;
@@ -299,6 +297,38 @@ ritz_kernel(const double* __restrict__ alpha, const double* __restrict__ beta,
     }
 }
 
+template <bool kLds>
+__global__ void __launch_bounds__(kSvdThreads)
+ritz_kernel(const double* __restrict__ alpha, const double* __restrict__ beta,
+            const double* __restrict__ theta, const double* __restrict__ rho, int nlock, int m,
+            int k, double tol, RitzOut out, double* gscratch)
+{
+    extern __shared__ double lds[];
+    const int mp = m + (m & 1);
+    double* W = kLds ? lds : gscratch;
+    double* Vr = W + mp * mp;
+    double* sig = Vr + mp * mp;
+    int* order = reinterpret_cast<int*>(sig + mp);
+    ritz_body(alpha, beta, theta, rho, nlock, m, k, tol, out, W, Vr, sig, order);
+}
+
+// One workgroup per problem of a batch.
+template <bool kLds>
+__global__ void __launch_bounds__(kSvdThreads)
+ritz_batched_kernel(const BatchRitzArgs* __restrict__ args, int nlock, int m, int k, double tol,
+                    double* gscratch, int64_t gstride)
+{
+    extern __shared__ double lds[];
+    const BatchRitzArgs& a = args[blockIdx.x];
+    if (!a.run) return;
+    const int mp = m + (m & 1);
+    double* W = kLds ? lds : gscratch + (int64_t)blockIdx.x * gstride;
+    double* Vr = W + mp * mp;
+    double* sig = Vr + mp * mp;
+    int* order = reinterpret_cast<int*>(sig + mp);
+    ritz_body(a.alpha, a.beta, a.theta, a.rho, nlock, m, k, tol, a.out, W, Vr, sig, order);
+}
+
 void launch_ritz(const double* alpha, const double* beta, const double* theta, const double* rho,
                  int nlock, int m, int k, double tol, const RitzOut& out, double* gscratch,
                  hipStream_t s)
@@ -313,6 +343,20 @@ void launch_ritz(const double* alpha, const double* beta, const double* theta, c
         hipLaunchKernelGGL(ritz_kernel<true>, dim3(1), dim3(kSvdThreads), lds, s, alpha, beta,
                            theta, rho, nlock, m, k, tol, out, nullptr);
     GKL_LAUNCH_CHECK("ritz_kernel");
+}
+
+void launch_ritz_batched(const BatchRitzArgs* args, int count, int nlock, int m, int k, double tol,
+                         double* gscratch, hipStream_t s)
+{
+    check_svd_size(m, gscratch);
+    const bool global = !svd_fits_lds(m);
+    if (global)
+        hipLaunchKernelGGL(ritz_batched_kernel<false>, dim3(count), dim3(kSvdThreads), 0, s, args,
+                           nlock, m, k, tol, gscratch, (int64_t)svd_scratch_elems(m));
+    else
+        hipLaunchKernelGGL(ritz_batched_kernel<true>, dim3(count), dim3(kSvdThreads),
+                           svd_lds_bytes(m), s, args, nlock, m, k, tol, nullptr, (int64_t)0);
+    GKL_LAUNCH_CHECK("ritz_batched_kernel");
 }
 
 __global__ void restart_scalars_kernel(const double* __restrict__ S, const double* __restrict__ P,

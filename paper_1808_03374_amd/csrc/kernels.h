@@ -60,6 +60,66 @@ void launch_rmatvec(const Packed& P, const ColStats& st, const double* u, double
 size_t matvec_partial_elems(const Packed& P);
 size_t matvec_counters(const Packed& P);
 
+// ---- batched solver: many problems stepped together ----
+constexpr int kMaxBatch = 1024;
+// Per-problem view read by the batched kernels (device array, one per problem).
+// Every Lanczos quantity has the same meaning as in the single-problem solver;
+// state[0] = current step j and state[1] = nlock (Ritz vectors kept at the last
+// restart), shared by all problems because they step in lockstep.
+struct BatchDesc {
+    const uint8_t* T;
+    const uint8_t* P;
+    int64_t n, p, nT, Pq, pP, nq;
+    const double* mean;
+    const double* inv_sd;
+    int64_t mv_per_split, rmv_per_split;
+    int32_t mv_nsplit, rmv_nsplit, mv_rowblocks, rmv_colblocks;
+    double* partial;                 // product split partials
+    double* U;                       // n x maxm
+    double* V;                       // p x (maxm + 1)
+    double* alpha;
+    double* beta;
+    double* theta;
+    double* rho;
+    double* hpart;                   // Gram-Schmidt partials, chunks x hstride
+    double* h;                       // projection coefficients, hstride
+    double* npart;                   // norm partials, chunks
+    double* anorm;                   // running max of the alphas and betas
+    int32_t* active;                 // 0 once converged or stopped
+    int32_t* breakdown;              // set when a new vector had no new direction
+};
+
+// Product geometry of one problem for the given split targets (blocks per launch).
+struct ProductPlan {
+    int64_t mv_per_split = 0, rmv_per_split = 0;
+    int mv_nsplit = 1, rmv_nsplit = 1, mv_rowblocks = 1, rmv_colblocks = 1;
+};
+ProductPlan product_plan(const Packed& L, int64_t mv_target, int64_t rmv_target);
+size_t product_plan_partial_elems(const Packed& L, const ProductPlan& pl);
+// Persistent products over the tiles of every active problem: tile0[q] is the
+// first tile of problem q (tile0[count] = total), `grid` workgroups stride over
+// the tiles.  Left: partial of A v_j.  Right: partial of A^T u_j.
+void launch_bmatvec(const BatchDesc* d, const int* tile0, int count, const int* state, int grid,
+                    hipStream_t s);
+void launch_brmatvec(const BatchDesc* d, const int* tile0, int count, const int* state, int grid,
+                     hipStream_t s);
+// u_j = sum of partials - beta_{j-1} u_{j-1} (or - U(:, 0:nlock) rho right after a
+// restart); v_{j+1} = s o (sum of partials) - alpha_j v_j.
+void launch_bmatvec_reduce(const BatchDesc* d, const int* state, int count, int64_t max_n,
+                           hipStream_t s);
+void launch_brmatvec_reduce(const BatchDesc* d, const int* state, int count, int64_t max_p,
+                            hipStream_t s);
+// ---- k_batch.hip ----
+// Full CGS2 of the new vector of every active problem (side 0: u_j against
+// U(:, 0:j); side 1: v_{j+1} against V(:, 0:j+1)), then its norm into alpha_j /
+// beta_j and the scaling.  hstride >= maxm + 2.
+void launch_bortho(const BatchDesc* d, const int* state, int count, int side, int64_t max_len,
+                   int hstride, hipStream_t s);
+size_t bortho_chunks(int64_t len);
+void launch_bstep(int* state, hipStream_t s);
+// v_0 of every problem scaled to unit norm (start of a solve).
+void launch_bstart(const BatchDesc* d, int count, int64_t max_p, int hstride, hipStream_t s);
+
 // ---- k_ortho.hip: Gram-Schmidt, norms, small dense ops on the Krylov bases ----
 struct OrthoWork {
     double* partial = nullptr;      // nblocks x (maxcols + 1)
@@ -123,6 +183,19 @@ struct RitzOut {
 void launch_ritz(const double* alpha, const double* beta, const double* theta, const double* rho,
                  int nlock, int m, int k, double tol, const RitzOut& out, double* gscratch,
                  hipStream_t s);
+// The same for many problems at once (one workgroup each); problems with
+// run == 0 are skipped.  gscratch: count * svd_scratch_elems(m) doubles when
+// the matrix does not fit LDS.
+struct BatchRitzArgs {
+    const double* alpha;
+    const double* beta;
+    const double* theta;
+    const double* rho;
+    RitzOut out;
+    int32_t run;
+};
+void launch_ritz_batched(const BatchRitzArgs* args, int count, int nlock, int m, int k, double tol,
+                         double* gscratch, hipStream_t s);
 
 // ---- k_pro.hip: partial reorthogonalisation estimates ----
 struct ProState {

@@ -78,3 +78,41 @@ def test_null_safe_destroy_and_solve():
     assert gk.lib.gkl_solve(None, None, None, 0, None, 0, ctypes.byref(info)) == gk.GKL_ERR_INVALID
     assert gk.lib.gkl_dense_svd(None, 4, None, None, None, None) == gk.GKL_ERR_INVALID
     assert gk.lib.gkl_dense_svd(FAKE, 0, FAKE, FAKE, FAKE, None) == gk.GKL_ERR_INVALID
+
+
+def _batched(count, ns, ps, k=2, tol=1e-8, reorth=0, **fields):
+    o = gk.gkl_options_default()
+    for key, val in fields.items():
+        setattr(o, key, val)
+    G = (ctypes.c_void_p * max(count, 1))(*([FAKE] * max(count, 1)))
+    N = (ctypes.c_int64 * max(count, 1))(*ns)
+    P = (ctypes.c_int64 * max(count, 1))(*ps)
+    ctx = ctypes.c_void_p(777)
+    st = gk.lib.gkl_create_batched(count, G, N, P, k, tol, reorth, ctypes.byref(o), ctypes.byref(ctx))
+    assert ctx.value == 777               # untouched on failure
+    return st, gk.gkl_last_error(None)
+
+
+@pytest.mark.parametrize("args,fields,status,msg", [
+    ((0, [10], [10]), {}, gk.GKL_ERR_INVALID, "count"),
+    ((1025, [10] * 1025, [10] * 1025), {}, gk.GKL_ERR_INVALID, "count"),
+    ((2, [10, 0], [10, 10]), {}, gk.GKL_ERR_INVALID, "n and p"),
+    ((2, [10, 10], [10, 3]), {}, gk.GKL_ERR_INVALID, "k must"),
+    ((1, [10], [10]), {"krylov_dim": 2}, gk.GKL_ERR_INVALID, "krylov_dim"),
+    ((1, [10], [10]), {"precision": 1}, gk.GKL_ERR_UNSUPPORTED, "FP64"),
+])
+def test_create_batched_rejects_bad_arguments(args, fields, status, msg):
+    count, ns, ps = args
+    k = 4 if msg == "k must" else 2
+    st, err = _batched(count, ns, ps, k=k, **fields)
+    assert st == status and msg in err
+
+
+def test_create_batched_partial_reorth_is_unsupported():
+    st, err = _batched(1, [10], [10], reorth=1)
+    assert st == gk.GKL_ERR_UNSUPPORTED and "full" in err
+
+
+def test_batched_entry_points_reject_null():
+    assert gk.lib.gkl_solve_batched(None, None, None, None, None, None, None) == gk.GKL_ERR_INVALID
+    assert gk.lib.gkl_batched_plan(None, None, None, None, None, None, None) == gk.GKL_ERR_INVALID
