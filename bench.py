@@ -150,6 +150,117 @@ def run_mixed(gk, torch, G, n, p, k, args, sigma_fp64, stream):
     return out
 
 
+def run_batched(gk, torch, args):
+    """22 chromosome blocks (20,000 individuals, 8,000..80,000 SNPs, 700,000 in all)
+    solved together by the batched path (persistent products, one HIP graph per
+    Lanczos step, autotuned product geometry), beside the same 22 problems
+    solved one after another through the single-problem entry points."""
+    import numpy as np
+    import synth
+    log("[bench] batched: generating 22 chromosome blocks")
+    gs = [synth.config("c4", chrom=c) for c in range(1, 23)]
+    Gs = [torch.from_numpy(g.packed).cuda() for g in gs]
+    ns = [g.n for g in gs]
+    ps = [g.p for g in gs]
+    k, tol, m = 10, 1e-10, 40
+    v0s = [synth.start_vector(g.p, 100 + q) for q, g in enumerate(gs)]
+    v0 = torch.from_numpy(np.concatenate(v0s)).cuda()
+    t0 = time.perf_counter()
+    ctx = gk.BatchedContext(Gs, ns, ps, k, tol=tol, v0=v0, krylov_dim=m, autotune=1, graph=1)
+    create_s = time.perf_counter() - t0
+    try:
+        ctx.solve()                     # warmup (captures the step graph)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(max(1, args.batched_steps)):
+            t0 = time.perf_counter()
+            sig, Us, Vs, st, infos = ctx.solve()
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        plan = ctx.plan()
+    finally:
+        ctx.close()
+    batch_s = float(np.mean(times))
+    log(f"[bench] batched: {batch_s * 1e3:.1f} ms per solve, status {st}")
+    bytes_pass = sum(((g.n + 3) // 4) * g.p + 16 * g.p + 16 * g.n for g in gs)
+    t0 = time.perf_counter()
+    seq_mv = 0
+    for q, g in enumerate(gs):
+        c1 = gk.Context(Gs[q], g.n, g.p, k, tol=tol, reorth=gk.GKL_REORTH_FULL,
+                        v0=v0[sum(ps[:q]):sum(ps[:q + 1])], krylov_dim=m)
+        try:
+            _, _, _, _, info = c1.solve()
+            seq_mv += info.matvecs
+        finally:
+            c1.close()
+    torch.cuda.synchronize()
+    seq_s = time.perf_counter() - t0
+    out = {"workload": "22 chromosome blocks of 20,000 individuals x 8,000..80,000 SNPs "
+                       "(701,314 in all), 4 subpopulations, 1% missing; k=10 each, FP64 GKL, "
+                       "full CGS2, thick restart m=40",
+           "problems": len(gs), "total_snps": int(sum(ps)), "packed_bytes": int(sum(g.nbytes for g in gs)),
+           "k": k, "tol": tol, "krylov_dim": m, "status": int(st),
+           "value_s_per_solve": batch_s, "create_s_incl_autotune": create_s,
+           "converged": int(sum(i.converged for i in infos)),
+           "steps_max": int(max(i.steps for i in infos)), "steps_min": int(min(i.steps for i in infos)),
+           "restarts_max": int(max(i.restarts for i in infos)),
+           "matvecs_total": int(sum(i.matvecs for i in infos)),
+           "plan": plan,
+           "sequential_single_solves_s": seq_s, "sequential_matvecs_total": int(seq_mv),
+           "speedup_vs_sequential": seq_s / batch_s}
+    for name, ms in (("batched_matvec (A v, all 22)", plan["mv_ms"]),
+                     ("batched_rmatvec (A^T u, all 22)", plan["rmv_ms"])):
+        if ms > 0:
+            out[name] = {"avg_launch_ms": ms, "algorithmic_bytes_per_launch": int(bytes_pass),
+                         "achieved_GBps": bytes_pass / (ms * 1e-3) / 1e9,
+                         "hbm_frac": bytes_pass / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS}
+    return out
+
+
+def run_c3(gk, torch, args):
+    """50,000 x 500,000 (6.25 GB packed): FP64 GKL (PRO, thick restart m=60) and the
+    blocked split-BF16 solve (block width 8), one solve each after a warmup."""
+    import numpy as np
+    import synth
+    log("[bench] c3: generating 50,000 x 500,000")
+    g = synth.config("c3")
+    n, p, k = g.n, g.p, 20
+    G = torch.from_numpy(g.packed).cuda()
+    sig = torch.empty(k, dtype=torch.float64, device="cuda")
+    U = torch.empty((k, n), dtype=torch.float64, device="cuda")
+    V = torch.empty((k, p), dtype=torch.float64, device="cuda")
+    out = {"workload": "50,000 x 500,000 genotypes, 10 subpopulations + 20% admixed, 1% missing; k=20"}
+    res = {}
+    for label, tol, opts in (
+            ("fp64", 1e-10, dict(v0=torch.from_numpy(synth.start_vector(p, 1)).cuda(),
+                                 krylov_dim=60, reorth=gk.GKL_REORTH_PARTIAL)),
+            ("mixed", 1e-8, dict(v0=torch.from_numpy(np.ascontiguousarray(
+                np.random.default_rng([1, 0x6D6978]).standard_normal((8, p)))).cuda(),
+                precision=gk.GKL_PREC_MIXED, block_width=8, reorth=gk.GKL_REORTH_FULL))):
+        reorth = opts.pop("reorth")
+        for rep in range(2):
+            ctx = gk.Context(G, n, p, k, tol, reorth, timing=1, **opts)
+            try:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st, info = gk.gkl_solve(ctx.ctx, sig, U, n, V, p)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+            finally:
+                ctx.close()
+        res[label] = sig.cpu().numpy().copy()
+        mv = info.matvec_kernel_ms / max(info.timed_matvecs, 1)
+        rmv = info.rmatvec_kernel_ms / max(info.timed_rmatvecs, 1)
+        out[label] = {"solve_s": dt, "status": int(st), "matvecs": int(info.matvecs),
+                      "passes_over_G": int(info.passes_over_G), "restarts": int(info.restarts),
+                      "avg_product_ms": [mv, rmv]}
+        log(f"[bench] c3 {label}: {dt:.2f} s, {info.matvecs} matvecs")
+    rel = np.abs(res["mixed"] - res["fp64"]) / res["fp64"]
+    out["mixed"]["sigma_max_rel_err_vs_fp64"] = float(rel.max())
+    out["mixed_speedup_vs_fp64"] = out["fp64"]["solve_s"] / out["mixed"]["solve_s"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -161,6 +272,11 @@ def main():
     ap.add_argument("--no-mixed", action="store_true",
                     help="skip the blocked split-BF16 solve of the same workload")
     ap.add_argument("--block-width", type=int, default=8)
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched solve of the 22 chromosome blocks")
+    ap.add_argument("--batched-steps", type=int, default=2)
+    ap.add_argument("--c3", action="store_true",
+                    help="also compare FP64 and mixed at 50,000 x 500,000 (adds about a minute)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="after the timed steps, copy BYTES bytes device-to-device 3 times "
                          "(reference dispatch for the HBM traffic counters)")
@@ -273,6 +389,10 @@ def main():
     }
     if not args.no_mixed:
         line["mixed"] = run_mixed(gk, torch, G, n, p, k, args, sigma.cpu().numpy(), stream)
+    if not args.no_batched:
+        line["batched"] = run_batched(gk, torch, args)
+    if args.c3:
+        line["c3"] = run_c3(gk, torch, args)
     if args.copy_calibration > 0:
         src = torch.empty(args.copy_calibration, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)

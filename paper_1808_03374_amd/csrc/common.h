@@ -85,4 +85,15 @@ __device__ __forceinline__ bool last_block_arrived(unsigned int* counter, unsign
 
 inline unsigned int ceil_div(int64_t a, int64_t b) { return (unsigned int)((a + b - 1) / b); }
 
+// Workgroups for a grid-stride loop over `total` items with `block` threads per
+// workgroup.  A HIP launch counts its work-items in 32 bits (workgroups times
+// workgroup size), so any kernel whose item count can exceed that loops instead
+// of launching one thread per item.
+inline unsigned int stride_grid(int64_t total, int block)
+{
+    const int64_t g = (total + block - 1) / block;
+    const int64_t cap = (int64_t)1 << 20;
+    return (unsigned int)(g < 1 ? 1 : (g > cap ? cap : g));
+}
+
 }  // namespace gkl

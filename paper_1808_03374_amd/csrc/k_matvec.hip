@@ -51,32 +51,33 @@ __global__ void build_T_kernel(const uint8_t* __restrict__ G, int64_t n, int64_t
                                uint8_t* __restrict__ T, int64_t nT, int64_t Pq)
 {
     const int64_t nbT = nT / 4;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nbT * Pq) return;
-    const int64_t J = t / nbT;
-    const int64_t I = t - J * nbT;
     const int64_t nb = (n + 3) / 4;
-    uint32_t in[4];
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nbT * Pq;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t J = t / nbT;
+        const int64_t I = t - J * nbT;
+        uint32_t in[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int64_t j = 4 * J + k;
-        uint32_t b = 0xFF;
-        if (j < p && I < nb) {
-            b = G[j * ld + I];
-            const int64_t valid = n - 4 * I;
-            if (valid < 4) b |= (0xFFu << (2 * valid)) & 0xFFu;
+        for (int k = 0; k < 4; ++k) {
+            const int64_t j = 4 * J + k;
+            uint32_t b = 0xFF;
+            if (j < p && I < nb) {
+                b = G[j * ld + I];
+                const int64_t valid = n - 4 * I;
+                if (valid < 4) b |= (0xFFu << (2 * valid)) & 0xFFu;
+            }
+            in[k] = b;
         }
-        in[k] = b;
-    }
-    uint32_t out = 0;
+        uint32_t out = 0;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        uint32_t byte = 0;
+        for (int r = 0; r < 4; ++r) {
+            uint32_t byte = 0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) byte |= ((in[k] >> (2 * r)) & 3u) << (2 * k);
-        out |= byte << (8 * r);
+            for (int k = 0; k < 4; ++k) byte |= ((in[k] >> (2 * r)) & 3u) << (2 * k);
+            out |= byte << (8 * r);
+        }
+        *reinterpret_cast<uint32_t*>(T + J * nT + 4 * I) = out;
     }
-    *reinterpret_cast<uint32_t*>(T + J * nT + 4 * I) = out;
 }
 
 // P[I * pP + j] = byte I of SNP j (codes of individuals 4I..4I+3); padding is
@@ -126,7 +127,7 @@ void build_layouts(const uint8_t* G, int64_t ld, const Packed& L, hipStream_t s)
     uint8_t* T = const_cast<uint8_t*>(L.T);
     uint8_t* P = const_cast<uint8_t*>(L.P);
     const int64_t tT = (L.nT / 4) * L.Pq;
-    hipLaunchKernelGGL(build_T_kernel, dim3(ceil_div(tT, 256)), dim3(256), 0, s, G, n, p, ld, T,
+    hipLaunchKernelGGL(build_T_kernel, dim3(stride_grid(tT, 256)), dim3(256), 0, s, G, n, p, ld, T,
                        L.nT, L.Pq);
     GKL_LAUNCH_CHECK("build_T_kernel");
     int64_t done = 0;
@@ -610,17 +611,18 @@ void launch_brmatvec_reduce(const BatchDesc* d, const int* state, int count, int
 __global__ void unpack_T_kernel(const uint8_t* __restrict__ T, int64_t nT, int64_t n, int64_t p,
                                 int64_t Pq, int8_t* __restrict__ out)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n * Pq) return;
-    const int64_t J = t / n;
-    const int64_t i = t - J * n;
-    const uint32_t b = T[J * nT + i];
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n * Pq;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t J = t / n;
+        const int64_t i = t - J * n;
+        const uint32_t b = T[J * nT + i];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int64_t j = 4 * J + k;
-        if (j < p) {
-            const int c = (b >> (2 * k)) & 3;
-            out[j * n + i] = (int8_t)(c == 3 ? -1 : c);
+        for (int k = 0; k < 4; ++k) {
+            const int64_t j = 4 * J + k;
+            if (j < p) {
+                const int c = (b >> (2 * k)) & 3;
+                out[j * n + i] = (int8_t)(c == 3 ? -1 : c);
+            }
         }
     }
 }
@@ -628,7 +630,7 @@ __global__ void unpack_T_kernel(const uint8_t* __restrict__ T, int64_t nT, int64
 void launch_unpack_layout(const Packed& L, int8_t* out, hipStream_t s)
 {
     const int64_t total = L.n * L.Pq;
-    hipLaunchKernelGGL(unpack_T_kernel, dim3(ceil_div(total, 256)), dim3(256), 0, s, L.T, L.nT, L.n,
+    hipLaunchKernelGGL(unpack_T_kernel, dim3(stride_grid(total, 256)), dim3(256), 0, s, L.T, L.nT, L.n,
                        L.p, L.Pq, out);
     GKL_LAUNCH_CHECK("unpack_T_kernel");
 }

@@ -54,29 +54,31 @@ __global__ void build_I_kernel(const uint8_t* __restrict__ G, int64_t n, int64_t
                                uint8_t* __restrict__ I, int64_t nI, int64_t ldI)
 {
     const int64_t nb = (n + 3) / 4;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // (row quad, J)
     const int64_t nrq = nI / 4;
-    if (t >= nrq * ldI) return;
-    const int64_t J = t / nrq;
-    const int64_t Iq = t - J * nrq;                                       // individual quad
-    uint32_t in[4];
+    // t = (SNP quad J, individual quad Iq)
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nrq * ldI;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t J = t / nrq;
+        const int64_t Iq = t - J * nrq;
+        uint32_t in[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int64_t j = 4 * J + k;
-        uint32_t b = 0xFF;
-        if (j < p && Iq < nb) {
-            b = G[j * ld + Iq];
-            const int64_t valid = n - 4 * Iq;
-            if (valid < 4) b |= (0xFFu << (2 * valid)) & 0xFFu;
+        for (int k = 0; k < 4; ++k) {
+            const int64_t j = 4 * J + k;
+            uint32_t b = 0xFF;
+            if (j < p && Iq < nb) {
+                b = G[j * ld + Iq];
+                const int64_t valid = n - 4 * Iq;
+                if (valid < 4) b |= (0xFFu << (2 * valid)) & 0xFFu;
+            }
+            in[k] = b;
         }
-        in[k] = b;
-    }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        uint32_t byte = 0;
+        for (int r = 0; r < 4; ++r) {
+            uint32_t byte = 0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) byte |= ((in[k] >> (2 * r)) & 3u) << (2 * k);
-        I[(4 * Iq + r) * ldI + J] = (uint8_t)byte;
+            for (int k = 0; k < 4; ++k) byte |= ((in[k] >> (2 * r)) & 3u) << (2 * k);
+            I[(4 * Iq + r) * ldI + J] = (uint8_t)byte;
+        }
     }
 }
 
@@ -85,17 +87,18 @@ __global__ void build_S_kernel(const uint8_t* __restrict__ G, int64_t n, int64_t
                                uint8_t* __restrict__ S, int64_t pS, int64_t ldS)
 {
     const int64_t nb = (n + 3) / 4;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= pS * ldS) return;
-    const int64_t j = t / ldS;
-    const int64_t Iq = t - j * ldS;
-    uint32_t b = 0xFF;
-    if (j < p && Iq < nb) {
-        b = G[j * ld + Iq];
-        const int64_t valid = n - 4 * Iq;
-        if (valid < 4) b |= (0xFFu << (2 * valid)) & 0xFFu;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < pS * ldS;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = t / ldS;
+        const int64_t Iq = t - j * ldS;
+        uint32_t b = 0xFF;
+        if (j < p && Iq < nb) {
+            b = G[j * ld + Iq];
+            const int64_t valid = n - 4 * Iq;
+            if (valid < 4) b |= (0xFFu << (2 * valid)) & 0xFFu;
+        }
+        S[t] = (uint8_t)b;
     }
-    S[t] = (uint8_t)b;
 }
 
 void build_mixed_layouts(const uint8_t* G, int64_t n, int64_t p, int64_t ld, uint8_t* I,
@@ -104,11 +107,11 @@ void build_mixed_layouts(const uint8_t* G, int64_t n, int64_t p, int64_t ld, uin
     const int64_t nI = mixed_rows_I(n), ldI = mixed_ld_I(p);
     const int64_t pS = mixed_rows_S(p), ldS = mixed_ld_S(n);
     const int64_t tI = (nI / 4) * ldI;
-    hipLaunchKernelGGL(build_I_kernel, dim3(ceil_div(tI, 256)), dim3(256), 0, s, G, n, p, ld, I,
+    hipLaunchKernelGGL(build_I_kernel, dim3(stride_grid(tI, 256)), dim3(256), 0, s, G, n, p, ld, I,
                        nI, ldI);
     GKL_LAUNCH_CHECK("build_I_kernel");
     const int64_t tS = pS * ldS;
-    hipLaunchKernelGGL(build_S_kernel, dim3(ceil_div(tS, 256)), dim3(256), 0, s, G, n, p, ld, S,
+    hipLaunchKernelGGL(build_S_kernel, dim3(stride_grid(tS, 256)), dim3(256), 0, s, G, n, p, ld, S,
                        pS, ldS);
     GKL_LAUNCH_CHECK("build_S_kernel");
 }

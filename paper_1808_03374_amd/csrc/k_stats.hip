@@ -82,17 +82,18 @@ __global__ void unpack_kernel(const uint8_t* __restrict__ G, int64_t n, int64_t 
                               int8_t* __restrict__ out)
 {
     const int64_t nb = (n + 3) / 4;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nb * p) return;
-    const int64_t j = t / nb;
-    const int64_t b = t - j * nb;
-    const uint32_t byte = G[j * ld + b];
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nb * p;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = t / nb;
+        const int64_t b = t - j * nb;
+        const uint32_t byte = G[j * ld + b];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int64_t i = b * 4 + k;
-        if (i < n) {
-            const int c = (byte >> (2 * k)) & 3;
-            out[j * n + i] = (int8_t)(c == 3 ? -1 : c);
+        for (int k = 0; k < 4; ++k) {
+            const int64_t i = b * 4 + k;
+            if (i < n) {
+                const int c = (byte >> (2 * k)) & 3;
+                out[j * n + i] = (int8_t)(c == 3 ? -1 : c);
+            }
         }
     }
 }
@@ -101,7 +102,7 @@ void launch_unpack(const uint8_t* G, int64_t n, int64_t p, int64_t ld, int8_t* o
                    hipStream_t s)
 {
     const int64_t total = ((n + 3) / 4) * p;
-    hipLaunchKernelGGL(unpack_kernel, dim3(ceil_div(total, 256)), dim3(256), 0, s, G, n, p, ld,
+    hipLaunchKernelGGL(unpack_kernel, dim3(stride_grid(total, 256)), dim3(256), 0, s, G, n, p, ld,
                        out);
     GKL_LAUNCH_CHECK("unpack_kernel");
 }

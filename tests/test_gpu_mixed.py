@@ -91,3 +91,30 @@ def test_mixed_solve_matches_fp64_oracle(gk, name, n, p, k, b):
     ang = oracle.subspace_angles(V[:, :1], ref.V[:, :1]).max()
     assert ang <= 2e-5 / gap, (ang, gap)
     ctx.close()
+
+
+def test_mixed_products_layouts_beyond_4GiB(gk):
+    # 50,000 x 350,000: both internal layouts of the block products hold more than
+    # 2^32 bytes, so byte offsets and the layout builders' work-item counts exceed
+    # 32 bits.  Checked on sampled rows and columns against the oracle, including
+    # rows and SNPs whose offsets lie beyond 2^32.
+    n, p = 50000, 350000
+    ld = (n + 3) // 4
+    rng = np.random.default_rng(11)
+    block = rng.integers(0, 256, size=(1000, ld), dtype=np.uint8)
+    packed = np.tile(block, (p // 1000, 1))
+    op = oracle.PackedOperator(packed, n, p)
+    ctx = gk.Context(dev(packed), n, p, 1, precision=gk.GKL_PREC_MIXED, block_width=8,
+                     krylov_dim=32)
+    W = rng.standard_normal((p, 8)) / np.sqrt(p)
+    X = rng.standard_normal((n, 8)) / np.sqrt(n)
+    Y = ctx.matmat_mixed(dev(W)).cpu().numpy()
+    Z = ctx.rmatmat_mixed(dev(X)).cpu().numpy()
+    ctx.close()
+    rows = np.concatenate([[0, n - 1, n - 2], rng.choice(n, 13, replace=False)])
+    cols = np.concatenate([[0, p - 1, 345000, 349000], rng.choice(p, 12, replace=False)])
+    for c in (0, 7):
+        yr = op.matvec_rows(W[:, c], rows)
+        zr = op.rmatvec_cols(X[:, c], cols)
+        assert np.max(np.abs(Y[rows, c] - yr)) <= 1e-4 * np.max(np.abs(yr))
+        assert np.max(np.abs(Z[cols, c] - zr)) <= 1e-4 * np.max(np.abs(zr))
