@@ -148,8 +148,12 @@ __device__ __forceinline__ __bf16 to_bf16(double v) { return (__bf16)(float)v; }
 // ---------------------------------------------------------------------------
 // Vector fragments
 // ---------------------------------------------------------------------------
-// A W operands: frag[((st*8 + t)*4 + op)*64 + lane][e], ops 0..3 = W'hi, W'lo, X'hi,
-// X'lo for the 16 columns starting at col0.
+// A W operands.  kPack == false: frag[((st*8 + t)*4 + op)*64 + lane][e], ops
+// 0..3 = W'hi, W'lo, X'hi, X'lo for the 16 columns starting at col0.
+// kPack == true (b <= 8): two operands whose 16 columns hold the hi parts of the
+// b columns in 0..7 and their lo parts in 8..15: op 0 = [W'hi | W'lo], op 1 =
+// [X'hi | X'lo]; one MFMA per operand then covers both halves of the split.
+template <bool kPack>
 __global__ void split_W_kernel(const double* __restrict__ W, int64_t ldw, int b, int col0,
                                int64_t p, const double* __restrict__ mean,
                                const double* __restrict__ inv_sd, int64_t nst,
@@ -160,7 +164,9 @@ __global__ void split_W_kernel(const double* __restrict__ W, int64_t ldw, int b,
     const int lane = (int)(t & 63);
     const int ks = (int)((t >> 6) % kKSteps);
     const int64_t st = t / (64 * kKSteps);
-    const int g = lane >> 4, col = col0 + (lane & 15);
+    const int g = lane >> 4;
+    const int col = kPack ? (lane & 7) : col0 + (lane & 15);
+    const bool hi_half = !kPack || (lane & 15) < 8;
     bf16x8 whi, wlo, zhi, zlo;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
@@ -171,16 +177,23 @@ __global__ void split_W_kernel(const double* __restrict__ W, int64_t ldw, int b,
             z = mean[j] * w;
         }
         const __bf16 h1 = to_bf16(w), h2 = to_bf16(z);
-        whi[e] = h1;
-        wlo[e] = to_bf16(w - (double)(float)h1);
-        zhi[e] = h2;
-        zlo[e] = to_bf16(z - (double)(float)h2);
+        const __bf16 l1 = to_bf16(w - (double)(float)h1), l2 = to_bf16(z - (double)(float)h2);
+        whi[e] = hi_half ? h1 : l1;
+        zhi[e] = hi_half ? h2 : l2;
+        wlo[e] = l1;
+        zlo[e] = l2;
     }
-    bf16x8* f = frag + (((st * kKSteps + ks) * 4) * 64) + lane;
-    f[0 * 64] = whi;
-    f[1 * 64] = wlo;
-    f[2 * 64] = zhi;
-    f[3 * 64] = zlo;
+    if (kPack) {
+        bf16x8* f = frag + (((st * kKSteps + ks) * 2) * 64) + lane;
+        f[0 * 64] = whi;
+        f[1 * 64] = zhi;
+    } else {
+        bf16x8* f = frag + (((st * kKSteps + ks) * 4) * 64) + lane;
+        f[0 * 64] = whi;
+        f[1 * 64] = wlo;
+        f[2 * 64] = zhi;
+        f[3 * 64] = zlo;
+    }
 }
 
 // Per column c: K2_c = sum_j mu_j s_j W_jc (FP64, fixed order; one block per column).
@@ -217,7 +230,10 @@ colsum_kernel(const double* __restrict__ X, int64_t ldx, int64_t len,
     }
 }
 
-// A^T X operands: frag[((st*8 + t)*2 + op)*64 + lane][e], ops 0..1 = Xhi, Xlo.
+// A^T X operands.  kPack == false: frag[((st*8 + t)*2 + op)*64 + lane][e], ops
+// 0..1 = Xhi, Xlo.  kPack == true (b <= 8): one operand [Xhi | Xlo] (hi parts in
+// columns 0..7, lo parts in 8..15), frag[(st*8 + t)*64 + lane].
+template <bool kPack>
 __global__ void split_X_kernel(const double* __restrict__ X, int64_t ldx, int b, int col0,
                                int64_t n, int64_t nst, bf16x8* __restrict__ frag)
 {
@@ -226,7 +242,9 @@ __global__ void split_X_kernel(const double* __restrict__ X, int64_t ldx, int b,
     const int lane = (int)(t & 63);
     const int ks = (int)((t >> 6) % kKSteps);
     const int64_t st = t / (64 * kKSteps);
-    const int g = lane >> 4, col = col0 + (lane & 15);
+    const int g = lane >> 4;
+    const int col = kPack ? (lane & 7) : col0 + (lane & 15);
+    const bool hi_half = !kPack || (lane & 15) < 8;
     bf16x8 xhi, xlo;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
@@ -234,25 +252,31 @@ __global__ void split_X_kernel(const double* __restrict__ X, int64_t ldx, int b,
         double x = 0.0;
         if (i < n && col < b) x = X[(int64_t)col * ldx + i];
         const __bf16 h = to_bf16(x);
-        xhi[e] = h;
-        xlo[e] = to_bf16(x - (double)(float)h);
+        const __bf16 l = to_bf16(x - (double)(float)h);
+        xhi[e] = hi_half ? h : l;
+        xlo[e] = l;
     }
-    bf16x8* f = frag + (((st * kKSteps + ks) * 2) * 64) + lane;
-    f[0] = xhi;
-    f[64] = xlo;
+    if (kPack) {
+        frag[(st * kKSteps + ks) * 64 + lane] = xhi;
+    } else {
+        bf16x8* f = frag + (((st * kKSteps + ks) * 2) * 64) + lane;
+        f[0] = xhi;
+        f[64] = xlo;
+    }
 }
 
-// T_c = sum_i X_ic (FP64, fixed order; one block per column).
 // ---------------------------------------------------------------------------
 // A W main kernel: block = 4 waves x 8 row tiles x 16 rows = 512 rows, K split in
 // super-tiles; partial[split][row][16] FP64.
 // ---------------------------------------------------------------------------
+template <bool kPack>
 __global__ void __launch_bounds__(256)
 matmat_bf16_kernel(const uint8_t* __restrict__ I, int64_t ldI, int64_t nI,
                    const bf16x8* __restrict__ frag, int64_t nst, int64_t st_per_split,
                    double* __restrict__ partial)
 {
-    __shared__ bf16x8 bs[kKSteps * 4 * 64];         // 32 KB: one super-tile of 4 operands
+    constexpr int kOps = kPack ? 2 : 4;
+    __shared__ bf16x8 bs[kKSteps * kOps * 64];      // one super-tile of the operands
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = lane >> 4, r = lane & 15;
     const int64_t row_base = (int64_t)blockIdx.x * (kMxWaves * kRTw * 16) + wave * (kRTw * 16);
@@ -272,19 +296,24 @@ matmat_bf16_kernel(const uint8_t* __restrict__ I, int64_t ldI, int64_t nI,
 #pragma unroll
         for (int t = 0; t < kRTw; ++t)
             a[t] = *reinterpret_cast<const uint4*>(I + (row_base + 16 * t + r) * ldI + st * 64 + 16 * g);
-        const bf16x8* src = frag + st * (kKSteps * 4 * 64);
-        for (int q = threadIdx.x; q < kKSteps * 4 * 64; q += 256) bs[q] = src[q];
+        const bf16x8* src = frag + st * (kKSteps * kOps * 64);
+        for (int q = threadIdx.x; q < kKSteps * kOps * 64; q += 256) bs[q] = src[q];
         __syncthreads();
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
-            bf16x8 bw0[2], bw1[2], bz0[2], bz1[2];   // W'hi, W'lo, X'hi, X'lo
+            bf16x8 bw0[2], bw1[2], bz0[2], bz1[2];   // W'hi, W'lo, X'hi, X'lo (packed: 0 only)
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const int ks = 2 * w + h;
-                bw0[h] = bs[(ks * 4 + 0) * 64 + lane];
-                bw1[h] = bs[(ks * 4 + 1) * 64 + lane];
-                bz0[h] = bs[(ks * 4 + 2) * 64 + lane];
-                bz1[h] = bs[(ks * 4 + 3) * 64 + lane];
+                if (kPack) {
+                    bw0[h] = bs[(ks * 2 + 0) * 64 + lane];
+                    bz0[h] = bs[(ks * 2 + 1) * 64 + lane];
+                } else {
+                    bw0[h] = bs[(ks * 4 + 0) * 64 + lane];
+                    bw1[h] = bs[(ks * 4 + 1) * 64 + lane];
+                    bz0[h] = bs[(ks * 4 + 2) * 64 + lane];
+                    bz1[h] = bs[(ks * 4 + 3) * 64 + lane];
+                }
             }
 #pragma unroll
             for (int t = 0; t < kRTw; ++t) {
@@ -296,9 +325,11 @@ matmat_bf16_kernel(const uint8_t* __restrict__ I, int64_t ldI, int64_t nI,
                     const bf16x8 ca = pack4(C[4 * h], C[4 * h + 1], C[4 * h + 2], C[4 * h + 3]);
                     const bf16x8 ma = pack4(M[4 * h], M[4 * h + 1], M[4 * h + 2], M[4 * h + 3]);
                     acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ca, bw0[h], acc[t], 0, 0, 0);
-                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ca, bw1[h], acc[t], 0, 0, 0);
+                    if (!kPack)
+                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ca, bw1[h], acc[t], 0, 0, 0);
                     acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ma, bz0[h], acc[t], 0, 0, 0);
-                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ma, bz1[h], acc[t], 0, 0, 0);
+                    if (!kPack)
+                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ma, bz1[h], acc[t], 0, 0, 0);
                 }
             }
         }
@@ -324,7 +355,9 @@ matmat_bf16_kernel(const uint8_t* __restrict__ I, int64_t ldI, int64_t nI,
     }
 }
 
-// Y[i + c*ldy] = sum_split partial - K2_c for i < n, c < nb (col0 offset).
+// Y[i + c*ldy] = sum_split partial - K2_c for i < n, c < nb (col0 offset); packed:
+// the hi (column c) and lo (column c + 8) partials of each split are added first.
+template <bool kPack>
 __global__ void matmat_reduce_kernel(const double* __restrict__ partial, int nsplit, int64_t nI,
                                      int64_t n, int nb, const double* __restrict__ K2,
                                      double* __restrict__ Y, int64_t ldy)
@@ -335,7 +368,10 @@ __global__ void matmat_reduce_kernel(const double* __restrict__ partial, int nsp
     const int c = (int)(t & 15);
     if (c >= nb) return;
     double s = 0.0;
-    for (int sp = 0; sp < nsplit; ++sp) s += partial[((int64_t)sp * nI + i) * 16 + c];
+    for (int sp = 0; sp < nsplit; ++sp) {
+        const double* pr = partial + ((int64_t)sp * nI + i) * 16;
+        s += kPack ? pr[c] + pr[c + 8] : pr[c];
+    }
     Y[(int64_t)c * ldy + i] = s - K2[c];
 }
 
@@ -343,12 +379,14 @@ __global__ void matmat_reduce_kernel(const double* __restrict__ partial, int nsp
 // A^T X main kernel: block = 4 waves x 4 SNP tiles x 16 = 256 SNPs; K = individuals.
 // partial[split][2][row][16]: sums with the code operand and the missing operand.
 // ---------------------------------------------------------------------------
+template <bool kPack>
 __global__ void __launch_bounds__(256)
 rmatmat_bf16_kernel(const uint8_t* __restrict__ S, int64_t ldS, int64_t pS,
                     const bf16x8* __restrict__ frag, int64_t nst, int64_t st_per_split,
                     double* __restrict__ partial)
 {
-    __shared__ bf16x8 bs[kKSteps * 2 * 64];         // 16 KB
+    constexpr int kOps = kPack ? 1 : 2;
+    __shared__ bf16x8 bs[kKSteps * kOps * 64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = lane >> 4, r = lane & 15;
     const int64_t row_base = (int64_t)blockIdx.x * (kMxWaves * kRTr * 16) + wave * (kRTr * 16);
@@ -369,8 +407,8 @@ rmatmat_bf16_kernel(const uint8_t* __restrict__ S, int64_t ldS, int64_t pS,
 #pragma unroll
         for (int t = 0; t < kRTr; ++t)
             a[t] = *reinterpret_cast<const uint4*>(S + (row_base + 16 * t + r) * ldS + st * 64 + 16 * g);
-        const bf16x8* src = frag + st * (kKSteps * 2 * 64);
-        for (int q = threadIdx.x; q < kKSteps * 2 * 64; q += 256) bs[q] = src[q];
+        const bf16x8* src = frag + st * (kKSteps * kOps * 64);
+        for (int q = threadIdx.x; q < kKSteps * kOps * 64; q += 256) bs[q] = src[q];
         __syncthreads();
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
@@ -378,8 +416,12 @@ rmatmat_bf16_kernel(const uint8_t* __restrict__ S, int64_t ldS, int64_t pS,
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const int ks = 2 * w + h;
-                x0[h] = bs[(ks * 2 + 0) * 64 + lane];
-                x1[h] = bs[(ks * 2 + 1) * 64 + lane];
+                if (kPack) {
+                    x0[h] = bs[ks * 64 + lane];
+                } else {
+                    x0[h] = bs[(ks * 2 + 0) * 64 + lane];
+                    x1[h] = bs[(ks * 2 + 1) * 64 + lane];
+                }
             }
 #pragma unroll
             for (int t = 0; t < kRTr; ++t) {
@@ -391,9 +433,11 @@ rmatmat_bf16_kernel(const uint8_t* __restrict__ S, int64_t ldS, int64_t pS,
                     const bf16x8 ca = pack4(C[4 * h], C[4 * h + 1], C[4 * h + 2], C[4 * h + 3]);
                     const bf16x8 ma = pack4(M[4 * h], M[4 * h + 1], M[4 * h + 2], M[4 * h + 3]);
                     accC[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ca, x0[h], accC[t], 0, 0, 0);
-                    accC[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ca, x1[h], accC[t], 0, 0, 0);
+                    if (!kPack)
+                        accC[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ca, x1[h], accC[t], 0, 0, 0);
                     accM[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ma, x0[h], accM[t], 0, 0, 0);
-                    accM[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ma, x1[h], accM[t], 0, 0, 0);
+                    if (!kPack)
+                        accM[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ma, x1[h], accM[t], 0, 0, 0);
                 }
             }
         }
@@ -425,6 +469,7 @@ rmatmat_bf16_kernel(const uint8_t* __restrict__ S, int64_t ldS, int64_t pS,
 }
 
 // Z[j + c*ldz] = s_j ( SG - mu_j T_c + mu_j SM )
+template <bool kPack>
 __global__ void rmatmat_reduce_kernel(const double* __restrict__ partial, int nsplit, int64_t pS,
                                       int64_t p, int nb, const double* __restrict__ T,
                                       const double* __restrict__ mean,
@@ -438,8 +483,10 @@ __global__ void rmatmat_reduce_kernel(const double* __restrict__ partial, int ns
     if (c >= nb) return;
     double sc = 0.0, sm = 0.0;
     for (int sp = 0; sp < nsplit; ++sp) {
-        sc += partial[((int64_t)sp * 2 * pS + j) * 16 + c];
-        sm += partial[((int64_t)sp * 2 * pS + pS + j) * 16 + c];
+        const double* pc = partial + ((int64_t)sp * 2 * pS + j) * 16;
+        const double* pm = partial + ((int64_t)sp * 2 * pS + pS + j) * 16;
+        sc += kPack ? pc[c] + pc[c + 8] : pc[c];
+        sm += kPack ? pm[c] + pm[c + 8] : pm[c];
     }
     const double mu = mean[j];
     Z[(int64_t)c * ldz + j] = inv_sd[j] * (sc - mu * T[c] + mu * sm);
@@ -495,24 +542,37 @@ void launch_matmat_mixed(const MixedShape& m, const uint8_t* I, const ColStats& 
                          const double* W, int64_t ldw, int b, double* Y, int64_t ldy,
                          MixedWork& w, hipStream_t s)
 {
+    const bool pack = b <= 8;
     for (int col0 = 0; col0 < b; col0 += 16) {
         const int nb = b - col0 < 16 ? b - col0 : 16;
         const int64_t nthr = m.nstW * kKSteps * 64;
-        hipLaunchKernelGGL(split_W_kernel, dim3(ceil_div(nthr, 256)), dim3(256), 0, s, W, ldw, b,
-                           col0, m.p, st.mean, st.inv_sd, m.nstW,
-                           reinterpret_cast<bf16x8*>(w.frag));
+        const dim3 gsplit(ceil_div(nthr, 256));
+        if (pack)
+            hipLaunchKernelGGL(split_W_kernel<true>, gsplit, dim3(256), 0, s, W, ldw, b, col0, m.p,
+                               st.mean, st.inv_sd, m.nstW, reinterpret_cast<bf16x8*>(w.frag));
+        else
+            hipLaunchKernelGGL(split_W_kernel<false>, gsplit, dim3(256), 0, s, W, ldw, b, col0, m.p,
+                               st.mean, st.inv_sd, m.nstW, reinterpret_cast<bf16x8*>(w.frag));
         GKL_LAUNCH_CHECK("split_W_kernel");
         hipLaunchKernelGGL(colsum_kernel, dim3(kCsSplit, nb), dim3(256), 0, s,
                            W + (int64_t)col0 * ldw, ldw, m.p, st.mean, st.inv_sd, w.cpart,
                            w.counters, w.k2);
         GKL_LAUNCH_CHECK("colsum_kernel");
         dim3 grid((unsigned int)(m.nI / (kMxWaves * kRTw * 16)), (unsigned int)m.splitW);
-        hipLaunchKernelGGL(matmat_bf16_kernel, grid, dim3(256), 0, s, I, m.ldI, m.nI,
-                           reinterpret_cast<const bf16x8*>(w.frag), m.nstW, m.stW, w.partial);
+        if (pack)
+            hipLaunchKernelGGL(matmat_bf16_kernel<true>, grid, dim3(256), 0, s, I, m.ldI, m.nI,
+                               reinterpret_cast<const bf16x8*>(w.frag), m.nstW, m.stW, w.partial);
+        else
+            hipLaunchKernelGGL(matmat_bf16_kernel<false>, grid, dim3(256), 0, s, I, m.ldI, m.nI,
+                               reinterpret_cast<const bf16x8*>(w.frag), m.nstW, m.stW, w.partial);
         GKL_LAUNCH_CHECK("matmat_bf16_kernel");
-        hipLaunchKernelGGL(matmat_reduce_kernel, dim3(ceil_div(m.n * 16, 256)), dim3(256), 0, s,
-                           w.partial, m.splitW, m.nI, m.n, nb, w.k2, Y + (int64_t)col0 * ldy,
-                           ldy);
+        const dim3 gred(ceil_div(m.n * 16, 256));
+        if (pack)
+            hipLaunchKernelGGL(matmat_reduce_kernel<true>, gred, dim3(256), 0, s, w.partial,
+                               m.splitW, m.nI, m.n, nb, w.k2, Y + (int64_t)col0 * ldy, ldy);
+        else
+            hipLaunchKernelGGL(matmat_reduce_kernel<false>, gred, dim3(256), 0, s, w.partial,
+                               m.splitW, m.nI, m.n, nb, w.k2, Y + (int64_t)col0 * ldy, ldy);
         GKL_LAUNCH_CHECK("matmat_reduce_kernel");
     }
 }
@@ -521,23 +581,39 @@ void launch_rmatmat_mixed(const MixedShape& m, const uint8_t* S, const ColStats&
                           const double* X, int64_t ldx, int b, double* Z, int64_t ldz,
                           MixedWork& w, hipStream_t s)
 {
+    const bool pack = b <= 8;
     for (int col0 = 0; col0 < b; col0 += 16) {
         const int nb = b - col0 < 16 ? b - col0 : 16;
         const int64_t nthr = m.nstX * kKSteps * 64;
-        hipLaunchKernelGGL(split_X_kernel, dim3(ceil_div(nthr, 256)), dim3(256), 0, s, X, ldx, b,
-                           col0, m.n, m.nstX, reinterpret_cast<bf16x8*>(w.frag));
+        const dim3 gsplit(ceil_div(nthr, 256));
+        if (pack)
+            hipLaunchKernelGGL(split_X_kernel<true>, gsplit, dim3(256), 0, s, X, ldx, b, col0, m.n,
+                               m.nstX, reinterpret_cast<bf16x8*>(w.frag));
+        else
+            hipLaunchKernelGGL(split_X_kernel<false>, gsplit, dim3(256), 0, s, X, ldx, b, col0, m.n,
+                               m.nstX, reinterpret_cast<bf16x8*>(w.frag));
         GKL_LAUNCH_CHECK("split_X_kernel");
         hipLaunchKernelGGL(colsum_kernel, dim3(kCsSplit, nb), dim3(256), 0, s,
                            X + (int64_t)col0 * ldx, ldx, m.n, nullptr, nullptr, w.cpart,
                            w.counters, w.k1);
         GKL_LAUNCH_CHECK("colsum_kernel");
         dim3 grid((unsigned int)(m.pS / (kMxWaves * kRTr * 16)), (unsigned int)m.splitX);
-        hipLaunchKernelGGL(rmatmat_bf16_kernel, grid, dim3(256), 0, s, S, m.ldS, m.pS,
-                           reinterpret_cast<const bf16x8*>(w.frag), m.nstX, m.stX, w.partial);
+        if (pack)
+            hipLaunchKernelGGL(rmatmat_bf16_kernel<true>, grid, dim3(256), 0, s, S, m.ldS, m.pS,
+                               reinterpret_cast<const bf16x8*>(w.frag), m.nstX, m.stX, w.partial);
+        else
+            hipLaunchKernelGGL(rmatmat_bf16_kernel<false>, grid, dim3(256), 0, s, S, m.ldS, m.pS,
+                               reinterpret_cast<const bf16x8*>(w.frag), m.nstX, m.stX, w.partial);
         GKL_LAUNCH_CHECK("rmatmat_bf16_kernel");
-        hipLaunchKernelGGL(rmatmat_reduce_kernel, dim3(ceil_div(m.p * 16, 256)), dim3(256), 0, s,
-                           w.partial, m.splitX, m.pS, m.p, nb, w.k1, st.mean, st.inv_sd,
-                           Z + (int64_t)col0 * ldz, ldz);
+        const dim3 gred(ceil_div(m.p * 16, 256));
+        if (pack)
+            hipLaunchKernelGGL(rmatmat_reduce_kernel<true>, gred, dim3(256), 0, s, w.partial,
+                               m.splitX, m.pS, m.p, nb, w.k1, st.mean, st.inv_sd,
+                               Z + (int64_t)col0 * ldz, ldz);
+        else
+            hipLaunchKernelGGL(rmatmat_reduce_kernel<false>, gred, dim3(256), 0, s, w.partial,
+                               m.splitX, m.pS, m.p, nb, w.k1, st.mean, st.inv_sd,
+                               Z + (int64_t)col0 * ldz, ldz);
         GKL_LAUNCH_CHECK("rmatmat_reduce_kernel");
     }
 }

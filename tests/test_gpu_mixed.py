@@ -71,7 +71,8 @@ def _oracle(g, k):
 
 
 @pytest.mark.parametrize("name,n,p,k,b", [("c1", 1000, 5000, 10, 16), ("c3", 2000, 20000, 20, 16),
-                                          ("c2", 2000, 20000, 20, 32)])
+                                          ("c2", 2000, 20000, 20, 32), ("c3", 3000, 30000, 20, 8),
+                                          ("c1", 1000, 5000, 10, 5)])
 def test_mixed_solve_matches_fp64_oracle(gk, name, n, p, k, b):
     g = synth.config(name, n=n, p=p)
     op, ref = _oracle(g, k)
