@@ -49,7 +49,17 @@ int64_t mixed_ld_S(int64_t n) { return (((n + 3) / 4 + 63) / 64) * 64; }
 // ---------------------------------------------------------------------------
 // Layouts
 // ---------------------------------------------------------------------------
-// I[i * ldI + J] = codes of SNPs 4J..4J+3 of individual i; padding = code 3.
+// Both layouts are stored in 1 KB tiles of 16 rows x 64 bytes, tile (rt, st) at
+// byte (rt * (ld / 64) + st) * 1024 and row r of the tile at + r * 64, so that one
+// wave's 16-byte-per-lane load of a tile reads 1 KB of consecutive bytes and a
+// wave walking along K streams through consecutive tiles.
+__host__ __device__ __forceinline__ int64_t tiled_offset(int64_t row, int64_t byte, int64_t ld)
+{
+    return ((row >> 4) * (ld >> 6) + (byte >> 6)) * 1024 + (row & 15) * 64 + (byte & 63);
+}
+
+// I: byte J of individual i = codes of SNPs 4J..4J+3 of individual i (tiled, ld
+// = ldI); padding = code 3.
 __global__ void build_I_kernel(const uint8_t* __restrict__ G, int64_t n, int64_t p, int64_t ld,
                                uint8_t* __restrict__ I, int64_t nI, int64_t ldI)
 {
@@ -77,12 +87,13 @@ __global__ void build_I_kernel(const uint8_t* __restrict__ G, int64_t n, int64_t
             uint32_t byte = 0;
 #pragma unroll
             for (int k = 0; k < 4; ++k) byte |= ((in[k] >> (2 * r)) & 3u) << (2 * k);
-            I[(4 * Iq + r) * ldI + J] = (uint8_t)byte;
+            I[tiled_offset(4 * Iq + r, J, ldI)] = (uint8_t)byte;
         }
     }
 }
 
-// S[j * ldS + Iq] = byte Iq of SNP j (individuals 4Iq..4Iq+3); padding = code 3.
+// S: byte Iq of SNP j = codes of individuals 4Iq..4Iq+3 (tiled, ld = ldS);
+// padding = code 3.
 __global__ void build_S_kernel(const uint8_t* __restrict__ G, int64_t n, int64_t p, int64_t ld,
                                uint8_t* __restrict__ S, int64_t pS, int64_t ldS)
 {
@@ -97,7 +108,7 @@ __global__ void build_S_kernel(const uint8_t* __restrict__ G, int64_t n, int64_t
             const int64_t valid = n - 4 * Iq;
             if (valid < 4) b |= (0xFFu << (2 * valid)) & 0xFFu;
         }
-        S[t] = (uint8_t)b;
+        S[tiled_offset(j, Iq, ldS)] = (uint8_t)b;
     }
 }
 
@@ -295,7 +306,7 @@ matmat_bf16_kernel(const uint8_t* __restrict__ I, int64_t ldI, int64_t nI,
         uint4 a[kRTw];
 #pragma unroll
         for (int t = 0; t < kRTw; ++t)
-            a[t] = *reinterpret_cast<const uint4*>(I + (row_base + 16 * t + r) * ldI + st * 64 + 16 * g);
+            a[t] = *reinterpret_cast<const uint4*>(I + tiled_offset(row_base + 16 * t + r, st * 64 + 16 * g, ldI));
         const bf16x8* src = frag + st * (kKSteps * kOps * 64);
         for (int q = threadIdx.x; q < kKSteps * kOps * 64; q += 256) bs[q] = src[q];
         __syncthreads();
@@ -406,7 +417,7 @@ rmatmat_bf16_kernel(const uint8_t* __restrict__ S, int64_t ldS, int64_t pS,
         uint4 a[kRTr];
 #pragma unroll
         for (int t = 0; t < kRTr; ++t)
-            a[t] = *reinterpret_cast<const uint4*>(S + (row_base + 16 * t + r) * ldS + st * 64 + 16 * g);
+            a[t] = *reinterpret_cast<const uint4*>(S + tiled_offset(row_base + 16 * t + r, st * 64 + 16 * g, ldS));
         const bf16x8* src = frag + st * (kKSteps * kOps * 64);
         for (int q = threadIdx.x; q < kKSteps * kOps * 64; q += 256) bs[q] = src[q];
         __syncthreads();
