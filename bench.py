@@ -261,6 +261,63 @@ def run_c3(gk, torch, args):
     return out
 
 
+def run_c5(gk, torch, args):
+    """100,000 x 1,000,000 (25 GB packed), a pure noise bulk with ten planted spikes at
+    1.5..20 times the bulk edge: the blocked split-BF16 solve (k = 10, b = 8) and the
+    FP64 solve (PRO, m = 30), each once after nothing else has touched the matrix;
+    reports the spike recovery against the planted ratios."""
+    import numpy as np
+    import synth
+    log("[bench] c5: generating 100,000 x 1,000,000")
+    g = synth.config("c5", progress=log)
+    n, p, k = g.n, g.p, 10
+    log("[bench] c5: copying 25 GB to the device")
+    G = torch.from_numpy(g.packed).cuda()
+    torch.cuda.synchronize()
+    edge = g.meta["edge"]
+    ratios = np.sort(np.array(g.meta["spike_ratios"]))[::-1]
+    sig = torch.empty(k, dtype=torch.float64, device="cuda")
+    U = torch.empty((k, n), dtype=torch.float64, device="cuda")
+    V = torch.empty((k, p), dtype=torch.float64, device="cuda")
+    out = {"workload": "100,000 x 1,000,000 genotypes, MAF ~ Beta(0.5,0.5) folded, 3% missing, "
+                       "10 planted spikes at 1.5..20x the bulk edge; k=10",
+           "packed_bytes": int(g.nbytes), "bulk_edge": edge, "planted_ratios": ratios.tolist()}
+    res = {}
+    for label, tol, opts, reorth in (
+            ("mixed", 1e-8, dict(precision=gk.GKL_PREC_MIXED, block_width=8), gk.GKL_REORTH_FULL),
+            ("fp64", 1e-10, dict(v0=torch.from_numpy(synth.start_vector(p, 1)).cuda(), krylov_dim=30),
+             gk.GKL_REORTH_PARTIAL)):
+        log(f"[bench] c5: {label} create")
+        t0 = time.perf_counter()
+        ctx = gk.Context(G, n, p, k, tol, reorth, timing=1, **opts)
+        torch.cuda.synchronize()
+        create_s = time.perf_counter() - t0
+        try:
+            log(f"[bench] c5: {label} solve")
+            t0 = time.perf_counter()
+            st, info = gk.gkl_solve(ctx.ctx, sig, U, n, V, p)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        finally:
+            ctx.close()
+        torch.cuda.empty_cache()
+        s = sig.cpu().numpy().copy()
+        res[label] = s
+        mv = info.matvec_kernel_ms / max(info.timed_matvecs, 1)
+        rmv = info.rmatvec_kernel_ms / max(info.timed_rmatvecs, 1)
+        out[label] = {"solve_s": dt, "create_s": create_s, "status": int(st),
+                      "matvecs": int(info.matvecs), "passes_over_G": int(info.passes_over_G),
+                      "restarts": int(info.restarts), "avg_product_ms": [mv, rmv],
+                      "sigma_over_edge": (s / edge).tolist(),
+                      "sigma_vs_planted_ratio": (s / (ratios * edge) - 1.0).tolist()}
+        log(f"[bench] c5 {label}: {dt:.2f} s, {info.matvecs} matvecs, status {st}")
+    rel = np.abs(res["mixed"] - res["fp64"]) / res["fp64"]
+    out["mixed"]["sigma_max_rel_err_vs_fp64"] = float(rel.max())
+    out["mixed_speedup_vs_fp64"] = out["fp64"]["solve_s"] / out["mixed"]["solve_s"]
+    out["outliers_above_1.05_edge"] = int(np.sum(res["fp64"] > 1.05 * edge))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -277,6 +334,8 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=2)
     ap.add_argument("--c3", action="store_true",
                     help="also compare FP64 and mixed at 50,000 x 500,000 (adds about a minute)")
+    ap.add_argument("--c5", action="store_true",
+                    help="also solve 100,000 x 1,000,000 (25 GB) by both paths (adds a few minutes)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="after the timed steps, copy BYTES bytes device-to-device 3 times "
                          "(reference dispatch for the HBM traffic counters)")
@@ -393,6 +452,8 @@ def main():
         line["batched"] = run_batched(gk, torch, args)
     if args.c3:
         line["c3"] = run_c3(gk, torch, args)
+    if args.c5:
+        line["c5"] = run_c5(gk, torch, args)
     if args.copy_calibration > 0:
         src = torch.empty(args.copy_calibration, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)

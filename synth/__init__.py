@@ -46,6 +46,9 @@ def _load():
                                       ctypes.c_void_p, ctypes.c_double)
             lib.synth_genotypes.argtypes = [i64, i64, i64, u64, vp, i64, vp, vp, vp, dbl, i32, vp]
             lib.synth_genotypes.restype = ctypes.c_int
+            lib.synth_genotypes_range.argtypes = [i64, i64, i64, i64, i64, u64, vp, i64, vp, vp, vp,
+                                                  dbl, i32, vp]
+            lib.synth_genotypes_range.restype = ctypes.c_int
             lib.synth_pack.argtypes = [i64, i64, i64, vp, i32, vp]
             lib.synth_pack.restype = ctypes.c_int
             _lib = lib
@@ -87,10 +90,15 @@ def pack_codes(codes: np.ndarray, ld: int | None = None, pad_mode: int = 0) -> n
     return out
 
 
+PROGRESS_COLUMNS = 50000     # SNP columns per reported range
+
+
 def generate(n: int, p: int, seed: int, base: np.ndarray, A: np.ndarray | None = None,
              B: np.ndarray | None = None, hap0_src: np.ndarray | None = None,
-             miss_rate: float = 0.0, ld: int | None = None, pad_mode: int = 0) -> np.ndarray:
-    """Bulk draw of a packed (p, ld) genotype matrix; see gen.c for the model."""
+             miss_rate: float = 0.0, ld: int | None = None, pad_mode: int = 0,
+             progress=None) -> np.ndarray:
+    """Bulk draw of a packed (p, ld) genotype matrix; see gen.c for the model.  With a
+    `progress` callable the columns are drawn in ranges and each range is reported."""
     ld = default_ld(n) if ld is None else int(ld)
     base = np.ascontiguousarray(base, dtype=np.float64)
     assert base.shape == (p,)
@@ -104,10 +112,16 @@ def generate(n: int, p: int, seed: int, base: np.ndarray, A: np.ndarray | None =
         hap0_src = np.ascontiguousarray(hap0_src, dtype=np.int32)
         assert hap0_src.shape == (n,)
     out = np.empty((p, ld), dtype=np.uint8)
-    rc = _load().synth_genotypes(n, p, ld, seed & 0xFFFFFFFFFFFFFFFF, _ptr(base), L, _ptr(A),
-                                 _ptr(B), _ptr(hap0_src), float(miss_rate), pad_mode, _ptr(out))
-    if rc != 0:
-        raise ValueError("synth_genotypes rejected its arguments")
+    chunk = p if progress is None else max(1, min(p, PROGRESS_COLUMNS))
+    for j0 in range(0, p, chunk):
+        j1 = min(p, j0 + chunk)
+        rc = _load().synth_genotypes_range(n, p, j0, j1, ld, seed & 0xFFFFFFFFFFFFFFFF, _ptr(base),
+                                           L, _ptr(A), _ptr(B), _ptr(hap0_src), float(miss_rate),
+                                           pad_mode, _ptr(out[j0:j1]))
+        if rc != 0:
+            raise ValueError("synth_genotypes_range rejected its arguments")
+        if progress is not None:
+            progress(f"[synth] {j1:,} of {p:,} SNP columns drawn")
     return out
 
 
@@ -171,7 +185,8 @@ FULL_SIZES = {"c1": (1000, 5000), "c2": (10000, 100000), "c3": (50000, 500000),
 
 
 def config(name: str, seed: int | None = None, n: int | None = None, p: int | None = None,
-           chrom: int | None = None, ld: int | None = None, pad_mode: int = 0) -> Genotypes:
+           chrom: int | None = None, ld: int | None = None, pad_mode: int = 0,
+           progress=None) -> Genotypes:
     """Generate one workload.
 
     c1: 2 subpopulations (Balding-Nichols F = 0.01), f ~ U(0.05, 0.5), 1% missing.
@@ -256,7 +271,8 @@ def config(name: str, seed: int | None = None, n: int | None = None, p: int | No
         meta.update(spike_ratios=ratios.tolist(), theta=theta.tolist(),
                     edge=mp_edge(n, p, miss))
     meta["miss_rate"] = miss
-    packed = generate(n, p, seed, base, A, B, hap0, miss, ld=ld, pad_mode=pad_mode)
+    packed = generate(n, p, seed, base, A, B, hap0, miss, ld=ld, pad_mode=pad_mode,
+                      progress=progress)
     return Genotypes(packed, n, p, packed.shape[1], meta)
 
 

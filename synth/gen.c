@@ -55,25 +55,29 @@ static inline double prob_of(const double* base, const double* A, const double* 
 
 #define U21(x) (((double)((x) & 0x1FFFFFull) + 0.5) * (1.0 / 2097152.0))
 
-/* Returns 0 on success, -1 on bad arguments. */
-int synth_genotypes(int64_t n, int64_t p, int64_t ld, uint64_t seed,
-                    const double* base,      /* p */
-                    int64_t L,
-                    const double* A,         /* n x L row-major, may be NULL if L == 0 */
-                    const double* B,         /* L x p row-major, may be NULL if L == 0 */
-                    const int32_t* hap0_src, /* n, may be NULL (identity) */
-                    double miss_rate,
-                    int32_t pad_mode,
-                    uint8_t* out)            /* p * ld bytes */
+/* Columns j0 <= j < j1 of the p-column matrix into out (column j at
+ * out + (j - j0) * ld).  Drawing a matrix in column ranges gives the same bytes
+ * as drawing it at once.  Returns 0 on success, -1 on bad arguments. */
+int synth_genotypes_range(int64_t n, int64_t p, int64_t j0, int64_t j1, int64_t ld,
+                          uint64_t seed,
+                          const double* base,      /* p */
+                          int64_t L,
+                          const double* A,         /* n x L row-major, may be NULL if L == 0 */
+                          const double* B,         /* L x p row-major, may be NULL if L == 0 */
+                          const int32_t* hap0_src, /* n, may be NULL (identity) */
+                          double miss_rate,
+                          int32_t pad_mode,
+                          uint8_t* out)            /* (j1 - j0) * ld bytes */
 {
     if (n <= 0 || p <= 0 || ld < (n + 3) / 4 || !base || !out) return -1;
+    if (j0 < 0 || j1 > p || j0 >= j1) return -1;
     if (L > 0 && (!A || !B)) return -1;
     const int64_t nb = (n + 3) / 4;
     const uint64_t miss_thr = (uint64_t)(miss_rate * 4194304.0); /* 22-bit threshold */
 #pragma omp parallel for schedule(dynamic, 64)
-    for (int64_t j = 0; j < p; ++j) {
+    for (int64_t j = j0; j < j1; ++j) {
         const uint64_t key = column_key(seed, j);
-        uint8_t* col = out + j * ld;
+        uint8_t* col = out + (j - j0) * ld;
         memset(col, 0, (size_t)ld);
         for (int64_t i = 0; i < n; ++i) {
             const uint64_t r = splitmix_out(key + (uint64_t)i);
@@ -107,6 +111,15 @@ int synth_genotypes(int64_t n, int64_t p, int64_t ld, uint64_t seed,
         }
     }
     return 0;
+}
+
+/* The whole matrix (p * ld bytes). */
+int synth_genotypes(int64_t n, int64_t p, int64_t ld, uint64_t seed, const double* base,
+                    int64_t L, const double* A, const double* B, const int32_t* hap0_src,
+                    double miss_rate, int32_t pad_mode, uint8_t* out)
+{
+    return synth_genotypes_range(n, p, 0, p, ld, seed, base, L, A, B, hap0_src, miss_rate,
+                                 pad_mode, out);
 }
 
 /* Pack an explicit code matrix (n x p, column-major int8, values 0..3) into the
