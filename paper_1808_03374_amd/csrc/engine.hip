@@ -131,6 +131,7 @@ void gkl_ctx::allocate_solver()
     ow.partial = static_cast<double*>(A.alloc(sizeof(double) * ow.partial_elems));
     ow.counters = static_cast<unsigned int*>(A.alloc(sizeof(unsigned int) * kOrthoCounters));
     ow.h = static_cast<double*>(A.alloc(sizeof(double) * (3 * (size_t)(cols + 2) + 8)));
+    ow.tn_partial = static_cast<double*>(A.alloc(sizeof(double) * gemm_tn_partial_elems(maxlen, cols + 1)));
     hipStream_t s = prob.stream;
     GKL_HIP(hipMemsetAsync(ow.counters, 0, sizeof(unsigned int) * kOrthoCounters, s));
     GKL_HIP(hipMemsetAsync(scal, 0, sizeof(double) * kScalars, s));

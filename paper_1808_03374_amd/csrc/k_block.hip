@@ -51,8 +51,10 @@ void tn_plan(int64_t len, int64_t* rows_per_wg, int* nwg)
 __global__ void __launch_bounds__(256)
 gemm_tn_kernel(const double* __restrict__ Q, int64_t ldq, const double* __restrict__ Y,
                int64_t ldy, int64_t len, int q, int b, int64_t rows_per_wg,
-               double* __restrict__ partial)
+               double* __restrict__ partial, const int* __restrict__ enable,
+               const int* __restrict__ skip)
 {
+    if ((enable && *enable == 0) || (skip && *skip)) return;   // the same for every thread
     __shared__ double red[2][kTnPart];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int col = lane & 15, g = lane >> 4;
@@ -132,8 +134,10 @@ gemm_tn_kernel(const double* __restrict__ Q, int64_t ldq, const double* __restri
 // adding workgroups r, r + 16, ... in order, then a fixed butterfly.
 __global__ void __launch_bounds__(256)
 gemm_tn_reduce_kernel(const double* __restrict__ partial, int nwg, int q, int b,
-                      double* __restrict__ H, int ldh)
+                      double* __restrict__ H, int ldh, const int* __restrict__ enable,
+                      const int* __restrict__ skip)
 {
+    if ((enable && *enable == 0) || (skip && *skip)) return;
     const int t = blockIdx.x * 16 + (threadIdx.x >> 4);
     const int r = threadIdx.x & 15;
     const bool live = t < q * b;
@@ -157,6 +161,13 @@ size_t gemm_tn_partial_elems(int64_t, int q)
 void launch_gemm_tn(const double* Q, int64_t ldq, const double* Y, int64_t ldy, int64_t len, int q,
                     int b, double* H, int ldh, double* partial, hipStream_t s)
 {
+    launch_gemm_tn_gated(Q, ldq, Y, ldy, len, q, b, H, ldh, partial, nullptr, nullptr, s);
+}
+
+void launch_gemm_tn_gated(const double* Q, int64_t ldq, const double* Y, int64_t ldy, int64_t len,
+                          int q, int b, double* H, int ldh, double* partial, const int* enable,
+                          const int* skip, hipStream_t s)
+{
     if (q <= 0 || b <= 0 || len <= 0) return;
     if (b > kBmax) fail(GKL_ERR_INVALID, "block width above 32");
     int64_t rpw;
@@ -165,10 +176,10 @@ void launch_gemm_tn(const double* Q, int64_t ldq, const double* Y, int64_t ldy, 
     if (nwg > 256) fail(GKL_ERR_INTERNAL, "gemm_tn plan exceeds its partial buffer");
     dim3 grid((unsigned int)nwg, (unsigned int)ceil_div(q, kTnQ));
     hipLaunchKernelGGL(gemm_tn_kernel, grid, dim3(256), 0, s, Q, ldq, Y, ldy, len, q, b, rpw,
-                       partial);
+                       partial, enable, skip);
     GKL_LAUNCH_CHECK("gemm_tn_kernel");
     hipLaunchKernelGGL(gemm_tn_reduce_kernel, dim3(ceil_div(q * b, 16)), dim3(256), 0, s, partial,
-                       nwg, q, b, H, ldh);
+                       nwg, q, b, H, ldh, enable, skip);
     GKL_LAUNCH_CHECK("gemm_tn_reduce_kernel");
 }
 

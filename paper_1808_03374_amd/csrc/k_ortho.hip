@@ -8,8 +8,10 @@
 // is at least 1/sqrt(2) of the norm before the pass).
 //
 // The bases are column-major (length x columns), so every pass streams
-// contiguous rows; reductions over rows are two-stage with a fixed order (block
-// partials, then the last block to arrive sums them), hence deterministic.
+// contiguous rows.  The projection h = Q^T r runs on the FP64 matrix cores (the
+// tall-skinny Q^T Y kernel with one vector); norms are two-stage reductions with
+// a fixed order (block partials, then the last block to arrive sums them).  All
+// results are deterministic.
 #include <math.h>
 
 #include "engine.h"
@@ -18,82 +20,13 @@ namespace gkl {
 
 namespace {
 constexpr int kOT = 256;      // threads per block
-constexpr int kPC = 16;       // projection: columns per block
-constexpr int kPR = 4;        // projection: rows per thread
-constexpr int kPRows = kOT * kPR;
 constexpr int kNR = 4;        // norm / update: rows per thread
 constexpr int kNRows = kOT * kNR;
 }  // namespace
 
-size_t ortho_partial_elems(int64_t len, int maxcols)
+size_t ortho_partial_elems(int64_t len, int)
 {
-    const size_t rb = (size_t)ceil_div(len, kPRows);
-    const size_t a = rb * (size_t)(((maxcols + kPC - 1) / kPC) * kPC);
-    const size_t b = (size_t)ceil_div(len, kNRows) + 1;
-    return a > b ? a : b;
-}
-
-// h = Q^T r for the 16 columns of blockIdx.y; blocks over rows write partials,
-// the last block of each column group sums them in row-block order.
-__global__ void __launch_bounds__(kOT)
-proj_kernel(const double* __restrict__ Q, int64_t ldq, int64_t len, int ncols,
-            const double* __restrict__ r, const int* __restrict__ enable,
-            const int* __restrict__ skip, double* __restrict__ h, double* __restrict__ partial,
-            unsigned int* __restrict__ counters)
-{
-    if (enable && *enable == 0) return;
-    if (skip && *skip) return;
-    __shared__ double red[kOT / 64][kPC];
-    const int c0 = blockIdx.y * kPC;
-    const int nc = ncols - c0 < kPC ? ncols - c0 : kPC;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    double rv[kPR];
-    int64_t rows[kPR];
-#pragma unroll
-    for (int t = 0; t < kPR; ++t) {
-        rows[t] = (int64_t)blockIdx.x * kPRows + t * kOT + threadIdx.x;
-        rv[t] = rows[t] < len ? r[rows[t]] : 0.0;
-    }
-    double acc[kPC];
-#pragma unroll
-    for (int c = 0; c < kPC; ++c) {
-        double a = 0.0;
-        if (c < nc) {
-            const double* qc = Q + (int64_t)(c0 + c) * ldq;
-#pragma unroll
-            for (int t = 0; t < kPR; ++t)
-                if (rows[t] < len) a = fma(qc[rows[t]], rv[t], a);
-        }
-        acc[c] = a;
-    }
-#pragma unroll
-    for (int c = 0; c < kPC; ++c) {
-        const double a = wave_sum(acc[c]);
-        if (lane == 0) red[wid][c] = a;
-    }
-    __syncthreads();
-    const int64_t stride = (int64_t)gridDim.y * kPC;
-    if (threadIdx.x < kPC) {
-        double a = 0.0;
-        for (int w = 0; w < kOT / 64; ++w) a += red[w][threadIdx.x];
-        partial[(int64_t)blockIdx.x * stride + c0 + threadIdx.x] = a;
-    }
-    if (!last_block_arrived(&counters[blockIdx.y], gridDim.x)) return;
-    // final sum over row blocks: 16 groups of threads per column, fixed order
-    __shared__ double fin[kOT / kPC][kPC];
-    {
-        const int col = threadIdx.x % kPC, grp = threadIdx.x / kPC;
-        double a = 0.0;
-        for (unsigned int b = grp; b < gridDim.x; b += kOT / kPC)
-            a += partial[(int64_t)b * stride + c0 + col];
-        fin[grp][col] = a;
-    }
-    __syncthreads();
-    if (threadIdx.x < nc) {
-        double a = 0.0;
-        for (int g = 0; g < kOT / kPC; ++g) a += fin[g][threadIdx.x];
-        h[c0 + threadIdx.x] = a;
-    }
+    return (size_t)ceil_div(len, kNRows) + 1;   // norm partials (projections use tn_partial)
 }
 
 // r <- r - Q h (all columns); optional partial ||r||^2 reduced by the last block.
@@ -168,15 +101,6 @@ norm_kernel(const double* __restrict__ r, int64_t len, double* __restrict__ nrm_
     }
 }
 
-static void launch_proj(const double* Q, int64_t ldq, int64_t len, int ncols, const double* r,
-                        const int* enable, const int* skip, double* h, OrthoWork& w, hipStream_t s)
-{
-    dim3 grid(ceil_div(len, kPRows), ceil_div(ncols, kPC));
-    hipLaunchKernelGGL(proj_kernel, grid, dim3(kOT), 0, s, Q, ldq, len, ncols, r, enable, skip, h,
-                       w.partial, w.counters);
-    GKL_LAUNCH_CHECK("proj_kernel");
-}
-
 static void launch_update(const double* Q, int64_t ldq, int64_t len, int ncols, double* r,
                           const double* h, const int* enable, const int* skip, hipStream_t s)
 {
@@ -216,19 +140,23 @@ void launch_cgs2(const double* Q, int64_t ldq, int64_t len, int ncols, double* r
     double* n0 = w.h + (ncols + 1);
     double* n1 = n0 + 1;
     int* skip = reinterpret_cast<int*>(n0 + 2);
+    // h = Q^T r on the FP64 matrix cores (one column of the 16-wide B operand used)
+    auto proj = [&](const int* sk) {
+        launch_gemm_tn_gated(Q, ldq, r, len, len, ncols, 1, h1, ncols, w.tn_partial, enable, sk, s);
+    };
     if (adaptive) {
         launch_norm_raw(r, len, n0, w, s);
-        launch_proj(Q, ldq, len, ncols, r, enable, nullptr, h1, w, s);
+        proj(nullptr);
         launch_update(Q, ldq, len, ncols, r, h1, enable, nullptr, s);
         launch_norm_raw(r, len, n1, w, s);
         hipLaunchKernelGGL(adapt_decide_kernel, dim3(1), dim3(1), 0, s, n0, n1, skip, passes, enable);
         GKL_LAUNCH_CHECK("adapt_decide_kernel");
-        launch_proj(Q, ldq, len, ncols, r, enable, skip, h1, w, s);
+        proj(skip);
         launch_update(Q, ldq, len, ncols, r, h1, enable, skip, s);
     } else {
-        launch_proj(Q, ldq, len, ncols, r, enable, nullptr, h1, w, s);
+        proj(nullptr);
         launch_update(Q, ldq, len, ncols, r, h1, enable, nullptr, s);
-        launch_proj(Q, ldq, len, ncols, r, enable, nullptr, h1, w, s);
+        proj(nullptr);
         launch_update(Q, ldq, len, ncols, r, h1, enable, nullptr, s);
         if (passes) {
             hipLaunchKernelGGL(count_passes_kernel, dim3(1), dim3(1), 0, s, passes, enable);

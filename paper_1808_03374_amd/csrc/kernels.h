@@ -126,6 +126,7 @@ struct OrthoWork {
     size_t partial_elems = 0;
     unsigned int* counters = nullptr;
     double* h = nullptr;            // projection coefficients (maxcols + 1)
+    double* tn_partial = nullptr;   // Q^T r partials (gemm_tn_partial_elems)
 };
 size_t ortho_partial_elems(int64_t len, int maxcols);
 
@@ -258,6 +259,10 @@ size_t gemm_tn_partial_elems(int64_t len, int q);
 // H (q x b, ldh) = Q^T Y
 void launch_gemm_tn(const double* Q, int64_t ldq, const double* Y, int64_t ldy, int64_t len, int q,
                     int b, double* H, int ldh, double* partial, hipStream_t s);
+// The same, skipped on the device when *enable == 0 or *skip != 0 (either may be NULL).
+void launch_gemm_tn_gated(const double* Q, int64_t ldq, const double* Y, int64_t ldy, int64_t len,
+                          int q, int b, double* H, int ldh, double* partial, const int* enable,
+                          const int* skip, hipStream_t s);
 // Out (len x nc) = Q H (subtract == 0) or Out -= Q H; Q (len x q), H (q x nc, ldh)
 void launch_gemm_nn(const double* Q, int64_t ldq, int q, const double* H, int ldh, double* Out,
                     int64_t ldo, int64_t len, int nc, int subtract, hipStream_t s);
