@@ -132,6 +132,7 @@ void gkl_ctx::allocate_solver()
     ow.counters = static_cast<unsigned int*>(A.alloc(sizeof(unsigned int) * kOrthoCounters));
     ow.h = static_cast<double*>(A.alloc(sizeof(double) * (3 * (size_t)(cols + 2) + 8)));
     ow.tn_partial = static_cast<double*>(A.alloc(sizeof(double) * gemm_tn_partial_elems(maxlen, cols + 1)));
+    ow.npart = static_cast<double*>(A.alloc(sizeof(double) * (ceil_div(maxlen, 256) + 1)));
     hipStream_t s = prob.stream;
     GKL_HIP(hipMemsetAsync(ow.counters, 0, sizeof(unsigned int) * kOrthoCounters, s));
     GKL_HIP(hipMemsetAsync(scal, 0, sizeof(double) * kScalars, s));
@@ -247,17 +248,21 @@ void gkl_ctx::left_step(int j)
     }
     info.matvecs += 1;
     info.passes_over_G += 1;
+    const int* gate = nullptr;
     if (j > 0) {
         if (reorth == GKL_REORTH_PARTIAL) {
             launch_normalize_only(uj, n, alpha + j);
             launch_pro_left(alpha, beta, theta, rho, nlock, j, omega, noise_scale, norm_est, pro, s);
-            launch_cgs2(U, n, n, j, uj, pro.flag_left, opt.adaptive_cgs2, flags + 6, ow, s);
-        } else {
-            launch_cgs2(U, n, n, j, uj, nullptr, opt.adaptive_cgs2, flags + 6, ow, s);
+            gate = pro.flag_left;
         }
+        launch_cgs2(U, n, n, j, uj, gate, opt.adaptive_cgs2, flags + 6, ow, s);
     }
-    launch_normalize(uj, n, uj, alpha + j, norm_est, root_maxdim, flags + 0, ow, s, flags + 9,
-                     2 * j);
+    if (j > 0 && !opt.adaptive_cgs2)
+        launch_normalize_after_cgs2(uj, n, alpha + j, norm_est, root_maxdim, flags + 0, gate, ow, s,
+                                    flags + 9, 2 * j);
+    else
+        launch_normalize(uj, n, uj, alpha + j, norm_est, root_maxdim, flags + 0, ow, s, flags + 9,
+                         2 * j);
 }
 
 // Right half-step j: V(:, j+1) from u_j.
@@ -272,15 +277,19 @@ void gkl_ctx::right_step(int j)
     timing_end(ev, true);
     info.matvecs += 1;
     info.passes_over_G += 1;
+    const int* gate = nullptr;
     if (reorth == GKL_REORTH_PARTIAL) {
         launch_normalize_only(vn, p, beta + j);
         launch_pro_right(alpha, beta, theta, rho, nlock, j, omega, noise_scale, norm_est, pro, s);
-        launch_cgs2(V, p, p, j + 1, vn, pro.flag_right, opt.adaptive_cgs2, flags + 6, ow, s);
-    } else {
-        launch_cgs2(V, p, p, j + 1, vn, nullptr, opt.adaptive_cgs2, flags + 6, ow, s);
+        gate = pro.flag_right;
     }
-    launch_normalize(vn, p, vn, beta + j, norm_est, root_maxdim, flags + 1, ow, s, flags + 9,
-                     2 * j + 1);
+    launch_cgs2(V, p, p, j + 1, vn, gate, opt.adaptive_cgs2, flags + 6, ow, s);
+    if (!opt.adaptive_cgs2)
+        launch_normalize_after_cgs2(vn, p, beta + j, norm_est, root_maxdim, flags + 1, gate, ow, s,
+                                    flags + 9, 2 * j + 1);
+    else
+        launch_normalize(vn, p, vn, beta + j, norm_est, root_maxdim, flags + 1, ow, s, flags + 9,
+                         2 * j + 1);
 }
 
 // Reads the number of converged Ritz values and the first breakdown half-step

@@ -29,30 +29,40 @@ size_t ortho_partial_elems(int64_t len, int)
     return (size_t)ceil_div(len, kNRows) + 1;   // norm partials (projections use tn_partial)
 }
 
-// r <- r - Q h (all columns); optional partial ||r||^2 reduced by the last block.
+// r <- r - Q h (all columns).  With npart != NULL each block also writes the sum
+// of squares of its updated rows to npart[block] (the norm that follows needs no
+// second pass over r), and block 0 adds 2 to *passes when passes != NULL.
 __global__ void __launch_bounds__(kOT)
 update_kernel(const double* __restrict__ Q, int64_t ldq, int64_t len, int ncols,
               double* __restrict__ r, const double* __restrict__ h, const int* __restrict__ enable,
-              const int* __restrict__ skip)
+              const int* __restrict__ skip, double* __restrict__ npart, int* __restrict__ passes)
 {
     if (enable && *enable == 0) return;
     if (skip && *skip) return;
     extern __shared__ double hs[];
+    __shared__ double red[16];
     for (int c = threadIdx.x; c < ncols; c += kOT) hs[c] = h[c];
     __syncthreads();
     const int64_t row = (int64_t)blockIdx.x * kOT + threadIdx.x;
-    if (row >= len) return;
-    double a = r[row];
-    int c = 0;
-    for (; c + 8 <= ncols; c += 8) {
-        double q[8];
+    double a = 0.0;
+    if (row < len) {
+        a = r[row];
+        int c = 0;
+        for (; c + 8 <= ncols; c += 8) {
+            double q[8];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) q[t] = Q[(int64_t)(c + t) * ldq + row];
+            for (int t = 0; t < 8; ++t) q[t] = Q[(int64_t)(c + t) * ldq + row];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) a = fma(-q[t], hs[c + t], a);
+            for (int t = 0; t < 8; ++t) a = fma(-q[t], hs[c + t], a);
+        }
+        for (; c < ncols; ++c) a = fma(-Q[(int64_t)c * ldq + row], hs[c], a);
+        r[row] = a;
     }
-    for (; c < ncols; ++c) a = fma(-Q[(int64_t)c * ldq + row], hs[c], a);
-    r[row] = a;
+    if (npart) {
+        const double ss = block_sum(a * a, red);
+        if (threadIdx.x == 0) npart[blockIdx.x] = ss;
+    }
+    if (passes && blockIdx.x == 0 && threadIdx.x == 0) *passes += 2;
 }
 
 // ||r||^2 by blocks, the last block finishes: nrm = sqrt; breakdown test against
@@ -102,10 +112,12 @@ norm_kernel(const double* __restrict__ r, int64_t len, double* __restrict__ nrm_
 }
 
 static void launch_update(const double* Q, int64_t ldq, int64_t len, int ncols, double* r,
-                          const double* h, const int* enable, const int* skip, hipStream_t s)
+                          const double* h, const int* enable, const int* skip, hipStream_t s,
+                          double* npart = nullptr, int* passes = nullptr)
 {
     hipLaunchKernelGGL(update_kernel, dim3(ceil_div(len, kOT)), dim3(kOT),
-                       sizeof(double) * (size_t)ncols, s, Q, ldq, len, ncols, r, h, enable, skip);
+                       sizeof(double) * (size_t)ncols, s, Q, ldq, len, ncols, r, h, enable, skip,
+                       npart, passes);
     GKL_LAUNCH_CHECK("update_kernel");
 }
 
@@ -117,12 +129,6 @@ __global__ void adapt_decide_kernel(const double* __restrict__ n0, const double*
     const int sk = (*n1) >= 0.7071067811865476 * (*n0) ? 1 : 0;
     *skip = sk;
     if (passes) *passes += sk ? 1 : 2;
-}
-
-__global__ void count_passes_kernel(int* __restrict__ passes, const int* __restrict__ enable)
-{
-    if (enable && *enable == 0) return;
-    *passes += 2;
 }
 
 void launch_norm_raw(const double* r, int64_t len, double* out, OrthoWork& w, hipStream_t s)
@@ -157,11 +163,8 @@ void launch_cgs2(const double* Q, int64_t ldq, int64_t len, int ncols, double* r
         proj(nullptr);
         launch_update(Q, ldq, len, ncols, r, h1, enable, nullptr, s);
         proj(nullptr);
-        launch_update(Q, ldq, len, ncols, r, h1, enable, nullptr, s);
-        if (passes) {
-            hipLaunchKernelGGL(count_passes_kernel, dim3(1), dim3(1), 0, s, passes, enable);
-            GKL_LAUNCH_CHECK("count_passes_kernel");
-        }
+        // the second update also leaves the partial sums of ||r||^2 in w.npart
+        launch_update(Q, ldq, len, ncols, r, h1, enable, nullptr, s, w.npart, passes);
     }
 }
 
@@ -182,6 +185,57 @@ __global__ void scale_kernel(const double* __restrict__ r, int64_t len, double* 
 void launch_norm(const double* r, int64_t len, double* out, OrthoWork& w, hipStream_t s)
 {
     launch_norm_raw(r, len, out, w, s);
+}
+
+// Normalisation right after a non-adaptive CGS2 whose second update left the
+// partial sums of ||r||^2 in npart (one per 256 rows).  Every block adds the
+// partials in the same order, applies the breakdown test of norm_kernel and
+// scales its rows; block 0 records the results.  When *enable == 0 the CGS2 was
+// skipped and *nrm_out already holds ||r|| (computed before it).  Blocks may see
+// *norm_est before or after block 0 updates it: est = max(est, nrm) is the same
+// either way, and so is *nrm_out (unchanged, or 0 exactly when all blocks found
+// a breakdown).
+__global__ void __launch_bounds__(kOT)
+normalize_fused_kernel(double* __restrict__ r, int64_t len, double* nrm_out, double* norm_est,
+                       double root_maxdim, int* __restrict__ flag, int* __restrict__ first_breakdown,
+                       int step, const double* __restrict__ npart, int nparts,
+                       const int* __restrict__ enable)
+{
+    __shared__ double sh[16];
+    double nrm;
+    if (enable && *enable == 0) {
+        nrm = *nrm_out;
+    } else {
+        double t = 0.0;
+        for (int b = threadIdx.x; b < nparts; b += kOT) t += npart[b];
+        nrm = sqrt(block_sum(t, sh));
+    }
+    double est = *norm_est;
+    if (nrm > est) est = nrm;
+    const bool bd = nrm <= 2.220446049250313e-16 * est * root_maxdim;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *nrm_out = bd ? 0.0 : nrm;
+        *flag = bd ? 1 : 0;
+        if (bd && first_breakdown && *first_breakdown < 0) *first_breakdown = step;
+        *norm_est = est;
+    }
+    if (bd) return;
+    const double inv = 1.0 / nrm;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len;
+         i += (int64_t)gridDim.x * blockDim.x)
+        r[i] = r[i] * inv;
+}
+
+void launch_normalize_after_cgs2(double* r, int64_t len, double* nrm_out, double* norm_est,
+                                 double root_maxdim, int* flag, const int* enable, OrthoWork& w,
+                                 hipStream_t s, int* first_breakdown, int step)
+{
+    unsigned int nb = ceil_div(len, 4 * kOT);
+    if (nb > 1024) nb = 1024;
+    hipLaunchKernelGGL(normalize_fused_kernel, dim3(nb), dim3(kOT), 0, s, r, len, nrm_out, norm_est,
+                       root_maxdim, flag, first_breakdown, step, w.npart, (int)ceil_div(len, kOT),
+                       enable);
+    GKL_LAUNCH_CHECK("normalize_fused_kernel");
 }
 
 void launch_normalize(double* r, int64_t len, double* out, double* nrm_out, double* norm_est,

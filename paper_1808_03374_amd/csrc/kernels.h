@@ -127,6 +127,7 @@ struct OrthoWork {
     unsigned int* counters = nullptr;
     double* h = nullptr;            // projection coefficients (maxcols + 1)
     double* tn_partial = nullptr;   // Q^T r partials (gemm_tn_partial_elems)
+    double* npart = nullptr;        // ||r||^2 partials of the last CGS2 update, ceil(len/256)
 };
 size_t ortho_partial_elems(int64_t len, int maxcols);
 
@@ -140,6 +141,13 @@ void launch_cgs2(const double* Q, int64_t ldq, int64_t len, int ncols, double* r
 // r left unscaled; else out = r / nrm (out may alias r).
 //   thresh = eps * max(*norm_est, nrm) * sqrt(max_dim); *norm_est updated.
 // On breakdown, *first_breakdown (if not NULL and still < 0) receives `step`.
+// Scale r to unit length right after a non-adaptive launch_cgs2 on the same r
+// (uses the norm partials that CGS2 left in w.npart); with *enable == 0 (CGS2
+// skipped) *nrm_out must already hold ||r||.  Same breakdown test and outputs as
+// launch_normalize.
+void launch_normalize_after_cgs2(double* r, int64_t len, double* nrm_out, double* norm_est,
+                                 double root_maxdim, int* flag, const int* enable, OrthoWork& w,
+                                 hipStream_t s, int* first_breakdown, int step);
 void launch_normalize(double* r, int64_t len, double* out, double* nrm_out, double* norm_est,
                       double root_maxdim, int* flag, OrthoWork& w, hipStream_t s,
                       int* first_breakdown = nullptr, int step = 0);
