@@ -15,9 +15,12 @@
 //            c < 3 and 0 for missing, is built in LDS and every lane adds
 //            L_J[byte] into the accumulator of its individual.
 //   A^T u -- layout P: byte (individual quad I, SNP j) holds the codes of
-//            individuals 4I..4I+3 of SNP j; for each quad I the table entry is the
-//            pair (sum_k g(c_k) u_{4I+k}, sum_k o(c_k) u_{4I+k}) and every lane adds
-//            it into the accumulators of its SNPs.
+//            individuals 4I..4I+3 of SNP j; for each quad I the table entry is
+//            sum_k g(c_k) u_{4I+k} and every lane adds it into the accumulators of
+//            its SNPs.  The centring term needs sum_i o_ij u_i = sum_i u_i - sum of u
+//            over the missing individuals of SNP j; the first is common to all SNPs,
+//            the second comes from per-SNP lists built at create time (missing
+//            codes are rare), added by the reduce kernel.
 // Tables of a quad are built from two 16-entry pair tables (one add per entry).
 // Wavefronts read 512 B or 1 KB contiguous per quad row.  Partial sums of the
 // K-splits go to a scratch buffer and a second kernel adds them in a fixed
@@ -265,20 +268,25 @@ matvec_reduce_kernel(const double* __restrict__ partial, int64_t nT, int nsplit,
 // A^T u: partial[split][j] = sum_i g u - mu_j sum_i o u over the split's quads
 // ---------------------------------------------------------------------------
 // One tile of A^T u: SNP block bx, individual quads of split by (see matvec_tile).
+// The tile forms, for each of its SNPs j, sum_i g_ij u_i - mu_j sum_i u_i over
+// its individuals (missing codes count as g = 0 here); the reduce kernel adds
+// mu_j u_i back for each missing individual of SNP j, which turns the second sum
+// into sum_i o_ij u_i.  So one byte costs one 8-byte table read.
 __device__ __forceinline__ void rmatvec_tile(const uint8_t* __restrict__ P, int64_t pP, int64_t n,
                                              int64_t nq, int64_t p, const double* __restrict__ u,
                                              const double* __restrict__ mean, int64_t iq_per_split,
                                              double* __restrict__ partial, int64_t bx, int64_t by)
 {
     __shared__ double uq[kQI * 4];
-    __shared__ double2 pairs[kQI * 2 * 16];
-    __shared__ double2 lut[kQI * 256];           // 32 KB
+    __shared__ double pairs[kQI * 2 * 16];
+    __shared__ double lut[kQI * 256];            // 16 KB
     const int64_t col0 = bx * kColsPerBlock + (int64_t)threadIdx.x * kSPT;
     const int64_t Ib = by * iq_per_split;
     const int64_t Ie = Ib + iq_per_split < nq ? Ib + iq_per_split : nq;
-    double sg[kSPT], so[kSPT];
+    double sg[kSPT];
 #pragma unroll
-    for (int k = 0; k < kSPT; ++k) { sg[k] = 0.0; so[k] = 0.0; }
+    for (int k = 0; k < kSPT; ++k) sg[k] = 0.0;
+    double su = 0.0;
 
     for (int64_t I0 = Ib; I0 < Ie; I0 += kQI) {
         const int nqc = (int)(Ie - I0 < kQI ? Ie - I0 : kQI);
@@ -298,28 +306,23 @@ __device__ __forceinline__ void rmatvec_tile(const uint8_t* __restrict__ P, int6
             const int c0 = x & 3, c1 = x >> 2;
             const double u0 = uq[4 * q + 2 * h], u1 = uq[4 * q + 2 * h + 1];
             const double g0 = c0 == 3 ? 0.0 : (double)c0, g1 = c1 == 3 ? 0.0 : (double)c1;
-            const double o0 = c0 == 3 ? 0.0 : 1.0, o1 = c1 == 3 ? 0.0 : 1.0;
-            pairs[e] = make_double2(g0 * u0 + g1 * u1, o0 * u0 + o1 * u1);
+            pairs[e] = g0 * u0 + g1 * u1;
         }
         __syncthreads();
         for (int e = threadIdx.x; e < kQI * 256; e += kMvThreads) {
             const int q = e >> 8, b = e & 255;
-            const double2 lo = pairs[q * 32 + (b & 15)], hi = pairs[q * 32 + 16 + (b >> 4)];
-            lut[e] = make_double2(lo.x + hi.x, lo.y + hi.y);
+            lut[e] = pairs[q * 32 + (b & 15)] + pairs[q * 32 + 16 + (b >> 4)];
         }
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < kQI; ++q) {
-            const double2* L = lut + q * 256;
+            const double* L = lut + q * 256;
+            su += L[0x55];                           // all four codes 1: the quad's sum of u
             const uint32_t w[2] = {d[q].x, d[q].y};
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const double2 e = L[(w[t] >> (8 * k)) & 0xFFu];
-                    sg[4 * t + k] += e.x;
-                    so[4 * t + k] += e.y;
-                }
+                for (int k = 0; k < 4; ++k) sg[4 * t + k] += L[(w[t] >> (8 * k)) & 0xFFu];
             }
         }
         __syncthreads();
@@ -330,8 +333,7 @@ __device__ __forceinline__ void rmatvec_tile(const uint8_t* __restrict__ P, int6
         const int64_t j = col0 + k;
         const double m0 = j < p ? mean[j] : 0.0;
         const double m1 = j + 1 < p ? mean[j + 1] : 0.0;
-        *reinterpret_cast<double2*>(out + k) =
-            make_double2(sg[k] - m0 * so[k], sg[k + 1] - m1 * so[k + 1]);
+        *reinterpret_cast<double2*>(out + k) = make_double2(sg[k] - m0 * su, sg[k + 1] - m1 * su);
     }
 }
 
@@ -343,9 +345,33 @@ rmatvec_lut_kernel(const uint8_t* __restrict__ P, int64_t pP, int64_t n, int64_t
     rmatvec_tile(P, pP, n, nq, p, u, mean, iq_per_split, partial, blockIdx.x, blockIdx.y);
 }
 
+// corr[j] = sum of u over the missing individuals of SNP j: one wave per SNP,
+// lane l adding entries l, l + 64, ... of the list, then a fixed butterfly.
+__device__ __forceinline__ void missing_sums(const int64_t* __restrict__ mptr,
+                                             const int32_t* __restrict__ midx,
+                                             const double* __restrict__ u, int64_t p,
+                                             double* __restrict__ corr, int64_t wave_id)
+{
+    if (wave_id >= p) return;
+    const int lane = threadIdx.x & 63;
+    double m = 0.0;
+    for (int64_t t = mptr[wave_id] + lane; t < mptr[wave_id + 1]; t += 64) m += u[midx[t]];
+    m = wave_sum(m);
+    if (lane == 0) corr[wave_id] = m;
+}
+
+__global__ void __launch_bounds__(256)
+missing_sums_kernel(const int64_t* __restrict__ mptr, const int32_t* __restrict__ midx,
+                    const double* __restrict__ u, int64_t p, double* __restrict__ corr)
+{
+    missing_sums(mptr, midx, u, p, corr, (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6));
+}
+
 __global__ void rmatvec_reduce_kernel(const double* __restrict__ partial, int64_t pP, int nsplit,
                                       int64_t p, const double* __restrict__ inv_sd,
-                                      double* __restrict__ z, const double* __restrict__ alpha,
+                                      const double* __restrict__ mean,
+                                      const double* __restrict__ corr, double* __restrict__ z,
+                                      const double* __restrict__ alpha,
                                       const double* __restrict__ vprev)
 {
     const double a = alpha ? *alpha : 0.0;
@@ -353,6 +379,7 @@ __global__ void rmatvec_reduce_kernel(const double* __restrict__ partial, int64_
          j += (int64_t)gridDim.x * blockDim.x) {
         double s = 0.0;
         for (int sp = 0; sp < nsplit; ++sp) s += partial[(int64_t)sp * pP + j];
+        s += mean[j] * corr[j];
         double r = inv_sd[j] * s;
         if (vprev) r -= a * vprev[j];
         z[j] = r;
@@ -439,8 +466,11 @@ void launch_rmatvec(const Packed& L, const ColStats& st, const double* u, double
     GKL_LAUNCH_CHECK("rmatvec_lut_kernel");
     unsigned int nb = ceil_div(L.p, 256);
     if (nb > 2048) nb = 2048;
+    hipLaunchKernelGGL(missing_sums_kernel, dim3(ceil_div(L.p, 4)), dim3(256), 0, s, L.miss_ptr,
+                       L.miss_idx, u, L.p, w.corr);
+    GKL_LAUNCH_CHECK("missing_sums_kernel");
     hipLaunchKernelGGL(rmatvec_reduce_kernel, dim3(nb), dim3(256), 0, s, w.partial, L.pP,
-                       sp.nsplit, L.p, st.inv_sd, z, alpha, vprev);
+                       sp.nsplit, L.p, st.inv_sd, st.mean, w.corr, z, alpha, vprev);
     GKL_LAUNCH_CHECK("rmatvec_reduce_kernel");
 }
 
@@ -572,9 +602,20 @@ brmatvec_reduce_kernel(const BatchDesc* __restrict__ desc, const int* __restrict
     const int j = state[0];
     double s = 0.0;
     for (int sp = 0; sp < D.rmv_nsplit; ++sp) s += D.partial[(int64_t)sp * D.pP + jj];
+    s += D.mean[jj] * D.corr[jj];
     double r = D.inv_sd[jj] * s;
     r -= D.alpha[j] * D.V[(int64_t)j * D.p + jj];
     D.V[(int64_t)(j + 1) * D.p + jj] = r;
+}
+
+// grid (SNP groups of 4 over the largest p, problems)
+__global__ void __launch_bounds__(256)
+bmissing_sums_kernel(const BatchDesc* __restrict__ desc, const int* __restrict__ state)
+{
+    const BatchDesc& D = desc[blockIdx.y];
+    if (!*D.active) return;
+    missing_sums(D.miss_ptr, D.miss_idx, D.U + (int64_t)state[0] * D.n, D.p, D.corr,
+                 (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6));
 }
 
 void launch_bmatvec(const BatchDesc* d, const int* tile0, int count, const int* state, int grid,
@@ -602,6 +643,9 @@ void launch_bmatvec_reduce(const BatchDesc* d, const int* state, int count, int6
 void launch_brmatvec_reduce(const BatchDesc* d, const int* state, int count, int64_t max_p,
                             hipStream_t s)
 {
+    hipLaunchKernelGGL(bmissing_sums_kernel, dim3(ceil_div(max_p, 4), count), dim3(256), 0, s, d,
+                       state);
+    GKL_LAUNCH_CHECK("bmissing_sums_kernel");
     hipLaunchKernelGGL(brmatvec_reduce_kernel, dim3(ceil_div(max_p, 256), count), dim3(256), 0, s,
                        d, state);
     GKL_LAUNCH_CHECK("brmatvec_reduce_kernel");
