@@ -345,26 +345,36 @@ rmatvec_lut_kernel(const uint8_t* __restrict__ P, int64_t pP, int64_t n, int64_t
     rmatvec_tile(P, pP, n, nq, p, u, mean, iq_per_split, partial, blockIdx.x, blockIdx.y);
 }
 
-// corr[j] = sum of u over the missing individuals of SNP j: one wave per SNP,
-// lane l adding entries l, l + 64, ... of the list, then a fixed butterfly.
+// corr[j] = sum of u over the missing individuals of SNP j: 16 lanes per SNP (4
+// SNPs per wave, so each wave keeps several gathers in flight), lane l adding
+// entries l, l + 16, ... of the list, then a fixed 16-lane butterfly.
 __device__ __forceinline__ void missing_sums(const int64_t* __restrict__ mptr,
                                              const int32_t* __restrict__ midx,
                                              const double* __restrict__ u, int64_t p,
-                                             double* __restrict__ corr, int64_t wave_id)
+                                             double* __restrict__ corr, int64_t snp)
 {
-    if (wave_id >= p) return;
-    const int lane = threadIdx.x & 63;
+    const int sl = threadIdx.x & 15;
     double m = 0.0;
-    for (int64_t t = mptr[wave_id] + lane; t < mptr[wave_id + 1]; t += 64) m += u[midx[t]];
-    m = wave_sum(m);
-    if (lane == 0) corr[wave_id] = m;
+    if (snp < p) {
+        const int64_t t1 = mptr[snp + 1];
+        int64_t t = mptr[snp] + sl;
+        for (; t + 16 < t1; t += 32) {
+            const int32_t i0 = midx[t], i1 = midx[t + 16];
+            m += u[i0];
+            m += u[i1];
+        }
+        if (t < t1) m += u[midx[t]];
+    }
+#pragma unroll
+    for (int off = 8; off >= 1; off >>= 1) m += __shfl_xor(m, off, 16);
+    if (snp < p && sl == 0) corr[snp] = m;
 }
 
 __global__ void __launch_bounds__(256)
 missing_sums_kernel(const int64_t* __restrict__ mptr, const int32_t* __restrict__ midx,
                     const double* __restrict__ u, int64_t p, double* __restrict__ corr)
 {
-    missing_sums(mptr, midx, u, p, corr, (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6));
+    missing_sums(mptr, midx, u, p, corr, (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4));
 }
 
 __global__ void rmatvec_reduce_kernel(const double* __restrict__ partial, int64_t pP, int nsplit,
@@ -466,7 +476,7 @@ void launch_rmatvec(const Packed& L, const ColStats& st, const double* u, double
     GKL_LAUNCH_CHECK("rmatvec_lut_kernel");
     unsigned int nb = ceil_div(L.p, 256);
     if (nb > 2048) nb = 2048;
-    hipLaunchKernelGGL(missing_sums_kernel, dim3(ceil_div(L.p, 4)), dim3(256), 0, s, L.miss_ptr,
+    hipLaunchKernelGGL(missing_sums_kernel, dim3(ceil_div(L.p, 16)), dim3(256), 0, s, L.miss_ptr,
                        L.miss_idx, u, L.p, w.corr);
     GKL_LAUNCH_CHECK("missing_sums_kernel");
     hipLaunchKernelGGL(rmatvec_reduce_kernel, dim3(nb), dim3(256), 0, s, w.partial, L.pP,
@@ -608,14 +618,14 @@ brmatvec_reduce_kernel(const BatchDesc* __restrict__ desc, const int* __restrict
     D.V[(int64_t)(j + 1) * D.p + jj] = r;
 }
 
-// grid (SNP groups of 4 over the largest p, problems)
+// grid (SNP groups of 16 over the largest p, problems)
 __global__ void __launch_bounds__(256)
 bmissing_sums_kernel(const BatchDesc* __restrict__ desc, const int* __restrict__ state)
 {
     const BatchDesc& D = desc[blockIdx.y];
     if (!*D.active) return;
     missing_sums(D.miss_ptr, D.miss_idx, D.U + (int64_t)state[0] * D.n, D.p, D.corr,
-                 (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6));
+                 (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4));
 }
 
 void launch_bmatvec(const BatchDesc* d, const int* tile0, int count, const int* state, int grid,
@@ -643,7 +653,7 @@ void launch_bmatvec_reduce(const BatchDesc* d, const int* state, int count, int6
 void launch_brmatvec_reduce(const BatchDesc* d, const int* state, int count, int64_t max_p,
                             hipStream_t s)
 {
-    hipLaunchKernelGGL(bmissing_sums_kernel, dim3(ceil_div(max_p, 4), count), dim3(256), 0, s, d,
+    hipLaunchKernelGGL(bmissing_sums_kernel, dim3(ceil_div(max_p, 16), count), dim3(256), 0, s, d,
                        state);
     GKL_LAUNCH_CHECK("bmissing_sums_kernel");
     hipLaunchKernelGGL(brmatvec_reduce_kernel, dim3(ceil_div(max_p, 256), count), dim3(256), 0, s,
