@@ -129,9 +129,6 @@ struct BatchState {
             d.h = P.h;
             d.npart = P.npart;
             d.anorm = P.anorm;
-            d.miss_ptr = L.miss_ptr;
-            d.miss_idx = L.miss_idx;
-            d.corr = P.prob.mvw.corr;
             d.active = d_active + q;
             d.breakdown = d_breakdown + q;
         }

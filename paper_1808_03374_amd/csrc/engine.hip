@@ -80,19 +80,8 @@ void Problem::setup(const uint8_t* G, int64_t n_, int64_t p_, int64_t ld_, hipSt
     st.inv_sd = static_cast<double*>(arena.alloc(sizeof(double) * p));
     launch_colstats(G, n, p, ld, st, s);
     if (!lut_layouts) return;
-    // per-SNP lists of missing individuals (A^T u adds their u back in)
-    int64_t* mptr = static_cast<int64_t*>(arena.alloc(sizeof(int64_t) * (p + 1)));
-    launch_missing_offsets(st.n3, p, mptr, s);
-    int64_t total = 0;
-    GKL_HIP(hipMemcpyAsync(&total, mptr + p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    GKL_HIP(hipStreamSynchronize(s));
-    int32_t* midx = static_cast<int32_t*>(arena.alloc(sizeof(int32_t) * (size_t)(total > 0 ? total : 1)));
-    launch_missing_lists(G, ld, n, p, mptr, midx, s);
-    packed.miss_ptr = mptr;
-    packed.miss_idx = midx;
     mvw.partial_elems = matvec_partial_elems(packed);
     mvw.partial = static_cast<double*>(arena.alloc(sizeof(double) * mvw.partial_elems));
-    mvw.corr = static_cast<double*>(arena.alloc(sizeof(double) * p));
     mvw.ncounters = matvec_counters(packed);
     mvw.counters = static_cast<unsigned int*>(arena.alloc(sizeof(unsigned int) * mvw.ncounters));
     GKL_HIP(hipMemsetAsync(mvw.counters, 0, sizeof(unsigned int) * mvw.ncounters, s));

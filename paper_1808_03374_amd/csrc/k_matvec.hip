@@ -15,12 +15,10 @@
 //            c < 3 and 0 for missing, is built in LDS and every lane adds
 //            L_J[byte] into the accumulator of its individual.
 //   A^T u -- layout P: byte (individual quad I, SNP j) holds the codes of
-//            individuals 4I..4I+3 of SNP j; for each quad I the table entry is
-//            sum_k g(c_k) u_{4I+k} and every lane adds it into the accumulators of
-//            its SNPs.  The centring term needs sum_i o_ij u_i = sum_i u_i - sum of u
-//            over the missing individuals of SNP j; the first is common to all SNPs,
-//            the second comes from per-SNP lists built at create time (missing
-//            codes are rare), added by the reduce kernel.
+//            individuals 4I..4I+3 of SNP j; for each quad I one table holds
+//            sum_k g(c_k) u_{4I+k} per byte value and a second, indexed by the
+//            byte's missing-code bits, the sum of u over the quad's missing
+//            individuals; sum_i o_ij u_i = sum_i u_i - that sum.
 // Tables of a quad are built from two 16-entry pair tables (one add per entry).
 // Wavefronts read 512 B or 1 KB contiguous per quad row.  Partial sums of the
 // K-splits go to a scratch buffer and a second kernel adds them in a fixed
@@ -268,10 +266,15 @@ matvec_reduce_kernel(const double* __restrict__ partial, int64_t nT, int nsplit,
 // A^T u: partial[split][j] = sum_i g u - mu_j sum_i o u over the split's quads
 // ---------------------------------------------------------------------------
 // One tile of A^T u: SNP block bx, individual quads of split by (see matvec_tile).
-// The tile forms, for each of its SNPs j, sum_i g_ij u_i - mu_j sum_i u_i over
-// its individuals (missing codes count as g = 0 here); the reduce kernel adds
-// mu_j u_i back for each missing individual of SNP j, which turns the second sum
-// into sum_i o_ij u_i.  So one byte costs one 8-byte table read.
+// Per SNP j the tile forms sum_i g_ij u_i - mu_j sum_i o_ij u_i over its
+// individuals.  Each byte costs one read of the quad's genotype table (indexed
+// by the byte) and one read of its missing table, indexed by the byte's
+// missing-code bits x = byte & (byte >> 1) & 0x55 (bit 2k set when individual k
+// of the quad is missing).  x is 0 for almost every byte, so the second read is
+// nearly always the same entry for all lanes.  sum_i o_ij u_i is then
+// sum_i u_i - sum_i m_ij u_i, with sum_i u_i read from the all-ones entry.
+constexpr int kMT = 88;   // missing-table entries per quad (x <= 0x55)
+
 __device__ __forceinline__ void rmatvec_tile(const uint8_t* __restrict__ P, int64_t pP, int64_t n,
                                              int64_t nq, int64_t p, const double* __restrict__ u,
                                              const double* __restrict__ mean, int64_t iq_per_split,
@@ -280,12 +283,13 @@ __device__ __forceinline__ void rmatvec_tile(const uint8_t* __restrict__ P, int6
     __shared__ double uq[kQI * 4];
     __shared__ double pairs[kQI * 2 * 16];
     __shared__ double lut[kQI * 256];            // 16 KB
+    __shared__ double mtab[kQI * kMT];           // 5.5 KB
     const int64_t col0 = bx * kColsPerBlock + (int64_t)threadIdx.x * kSPT;
     const int64_t Ib = by * iq_per_split;
     const int64_t Ie = Ib + iq_per_split < nq ? Ib + iq_per_split : nq;
-    double sg[kSPT];
+    double sg[kSPT], sm[kSPT];
 #pragma unroll
-    for (int k = 0; k < kSPT; ++k) sg[k] = 0.0;
+    for (int k = 0; k < kSPT; ++k) { sg[k] = 0.0; sm[k] = 0.0; }
     double su = 0.0;
 
     for (int64_t I0 = Ib; I0 < Ie; I0 += kQI) {
@@ -308,6 +312,14 @@ __device__ __forceinline__ void rmatvec_tile(const uint8_t* __restrict__ P, int6
             const double g0 = c0 == 3 ? 0.0 : (double)c0, g1 = c1 == 3 ? 0.0 : (double)c1;
             pairs[e] = g0 * u0 + g1 * u1;
         }
+        for (int e = threadIdx.x; e < kQI * kMT; e += kMvThreads) {
+            const int q = e / kMT, x = e - q * kMT;
+            double v = 0.0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if ((x >> (2 * k)) & 1) v += uq[4 * q + k];
+            mtab[e] = v;
+        }
         __syncthreads();
         for (int e = threadIdx.x; e < kQI * 256; e += kMvThreads) {
             const int q = e >> 8, b = e & 255;
@@ -317,12 +329,17 @@ __device__ __forceinline__ void rmatvec_tile(const uint8_t* __restrict__ P, int6
 #pragma unroll
         for (int q = 0; q < kQI; ++q) {
             const double* L = lut + q * 256;
+            const double* M = mtab + q * kMT;
             su += L[0x55];                           // all four codes 1: the quad's sum of u
             const uint32_t w[2] = {d[q].x, d[q].y};
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
+                const uint32_t mw = w[t] & (w[t] >> 1) & 0x55555555u;
 #pragma unroll
-                for (int k = 0; k < 4; ++k) sg[4 * t + k] += L[(w[t] >> (8 * k)) & 0xFFu];
+                for (int k = 0; k < 4; ++k) {
+                    sg[4 * t + k] += L[(w[t] >> (8 * k)) & 0xFFu];
+                    sm[4 * t + k] += M[(mw >> (8 * k)) & 0xFFu];
+                }
             }
         }
         __syncthreads();
@@ -333,7 +350,8 @@ __device__ __forceinline__ void rmatvec_tile(const uint8_t* __restrict__ P, int6
         const int64_t j = col0 + k;
         const double m0 = j < p ? mean[j] : 0.0;
         const double m1 = j + 1 < p ? mean[j + 1] : 0.0;
-        *reinterpret_cast<double2*>(out + k) = make_double2(sg[k] - m0 * su, sg[k + 1] - m1 * su);
+        *reinterpret_cast<double2*>(out + k) =
+            make_double2(sg[k] - m0 * (su - sm[k]), sg[k + 1] - m1 * (su - sm[k + 1]));
     }
 }
 
@@ -345,42 +363,9 @@ rmatvec_lut_kernel(const uint8_t* __restrict__ P, int64_t pP, int64_t n, int64_t
     rmatvec_tile(P, pP, n, nq, p, u, mean, iq_per_split, partial, blockIdx.x, blockIdx.y);
 }
 
-// corr[j] = sum of u over the missing individuals of SNP j: 16 lanes per SNP (4
-// SNPs per wave, so each wave keeps several gathers in flight), lane l adding
-// entries l, l + 16, ... of the list, then a fixed 16-lane butterfly.
-__device__ __forceinline__ void missing_sums(const int64_t* __restrict__ mptr,
-                                             const int32_t* __restrict__ midx,
-                                             const double* __restrict__ u, int64_t p,
-                                             double* __restrict__ corr, int64_t snp)
-{
-    const int sl = threadIdx.x & 15;
-    double m = 0.0;
-    if (snp < p) {
-        const int64_t t1 = mptr[snp + 1];
-        int64_t t = mptr[snp] + sl;
-        for (; t + 16 < t1; t += 32) {
-            const int32_t i0 = midx[t], i1 = midx[t + 16];
-            m += u[i0];
-            m += u[i1];
-        }
-        if (t < t1) m += u[midx[t]];
-    }
-#pragma unroll
-    for (int off = 8; off >= 1; off >>= 1) m += __shfl_xor(m, off, 16);
-    if (snp < p && sl == 0) corr[snp] = m;
-}
-
-__global__ void __launch_bounds__(256)
-missing_sums_kernel(const int64_t* __restrict__ mptr, const int32_t* __restrict__ midx,
-                    const double* __restrict__ u, int64_t p, double* __restrict__ corr)
-{
-    missing_sums(mptr, midx, u, p, corr, (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4));
-}
-
 __global__ void rmatvec_reduce_kernel(const double* __restrict__ partial, int64_t pP, int nsplit,
                                       int64_t p, const double* __restrict__ inv_sd,
-                                      const double* __restrict__ mean,
-                                      const double* __restrict__ corr, double* __restrict__ z,
+                                      double* __restrict__ z,
                                       const double* __restrict__ alpha,
                                       const double* __restrict__ vprev)
 {
@@ -389,7 +374,6 @@ __global__ void rmatvec_reduce_kernel(const double* __restrict__ partial, int64_
          j += (int64_t)gridDim.x * blockDim.x) {
         double s = 0.0;
         for (int sp = 0; sp < nsplit; ++sp) s += partial[(int64_t)sp * pP + j];
-        s += mean[j] * corr[j];
         double r = inv_sd[j] * s;
         if (vprev) r -= a * vprev[j];
         z[j] = r;
@@ -476,11 +460,8 @@ void launch_rmatvec(const Packed& L, const ColStats& st, const double* u, double
     GKL_LAUNCH_CHECK("rmatvec_lut_kernel");
     unsigned int nb = ceil_div(L.p, 256);
     if (nb > 2048) nb = 2048;
-    hipLaunchKernelGGL(missing_sums_kernel, dim3(ceil_div(L.p, 16)), dim3(256), 0, s, L.miss_ptr,
-                       L.miss_idx, u, L.p, w.corr);
-    GKL_LAUNCH_CHECK("missing_sums_kernel");
     hipLaunchKernelGGL(rmatvec_reduce_kernel, dim3(nb), dim3(256), 0, s, w.partial, L.pP,
-                       sp.nsplit, L.p, st.inv_sd, st.mean, w.corr, z, alpha, vprev);
+                       sp.nsplit, L.p, st.inv_sd, z, alpha, vprev);
     GKL_LAUNCH_CHECK("rmatvec_reduce_kernel");
 }
 
@@ -612,20 +593,9 @@ brmatvec_reduce_kernel(const BatchDesc* __restrict__ desc, const int* __restrict
     const int j = state[0];
     double s = 0.0;
     for (int sp = 0; sp < D.rmv_nsplit; ++sp) s += D.partial[(int64_t)sp * D.pP + jj];
-    s += D.mean[jj] * D.corr[jj];
     double r = D.inv_sd[jj] * s;
     r -= D.alpha[j] * D.V[(int64_t)j * D.p + jj];
     D.V[(int64_t)(j + 1) * D.p + jj] = r;
-}
-
-// grid (SNP groups of 16 over the largest p, problems)
-__global__ void __launch_bounds__(256)
-bmissing_sums_kernel(const BatchDesc* __restrict__ desc, const int* __restrict__ state)
-{
-    const BatchDesc& D = desc[blockIdx.y];
-    if (!*D.active) return;
-    missing_sums(D.miss_ptr, D.miss_idx, D.U + (int64_t)state[0] * D.n, D.p, D.corr,
-                 (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4));
 }
 
 void launch_bmatvec(const BatchDesc* d, const int* tile0, int count, const int* state, int grid,
@@ -653,9 +623,6 @@ void launch_bmatvec_reduce(const BatchDesc* d, const int* state, int count, int6
 void launch_brmatvec_reduce(const BatchDesc* d, const int* state, int count, int64_t max_p,
                             hipStream_t s)
 {
-    hipLaunchKernelGGL(bmissing_sums_kernel, dim3(ceil_div(max_p, 16), count), dim3(256), 0, s, d,
-                       state);
-    GKL_LAUNCH_CHECK("bmissing_sums_kernel");
     hipLaunchKernelGGL(brmatvec_reduce_kernel, dim3(ceil_div(max_p, 256), count), dim3(256), 0, s,
                        d, state);
     GKL_LAUNCH_CHECK("brmatvec_reduce_kernel");

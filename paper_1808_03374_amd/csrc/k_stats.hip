@@ -107,77 +107,5 @@ void launch_unpack(const uint8_t* G, int64_t n, int64_t p, int64_t ld, int8_t* o
     GKL_LAUNCH_CHECK("unpack_kernel");
 }
 
-// ---------------------------------------------------------------------------
-// Per-SNP lists of individuals with a missing code (create time)
-// ---------------------------------------------------------------------------
-// Exclusive prefix sum of n3 in one workgroup: each thread sums a contiguous
-// chunk, thread 0 scans the 1,024 chunk totals, each thread writes its chunk.
-__global__ void __launch_bounds__(1024)
-missing_offsets_kernel(const int64_t* __restrict__ n3, int64_t p, int64_t* __restrict__ ptr)
-{
-    __shared__ int64_t tot[1024];
-    const int64_t chunk = (p + 1023) / 1024;
-    const int64_t j0 = (int64_t)threadIdx.x * chunk;
-    const int64_t j1 = j0 + chunk < p ? j0 + chunk : p;
-    int64_t a = 0;
-    for (int64_t j = j0; j < j1; ++j) a += n3[j];
-    tot[threadIdx.x] = a;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int64_t run = 0;
-        for (int t = 0; t < 1024; ++t) {
-            const int64_t x = tot[t];
-            tot[t] = run;
-            run += x;
-        }
-        ptr[p] = run;
-    }
-    __syncthreads();
-    int64_t run = tot[threadIdx.x];
-    for (int64_t j = j0; j < j1; ++j) {
-        ptr[j] = run;
-        run += n3[j];
-    }
-}
-
-void launch_missing_offsets(const int64_t* n3, int64_t p, int64_t* miss_ptr, hipStream_t s)
-{
-    hipLaunchKernelGGL(missing_offsets_kernel, dim3(1), dim3(1024), 0, s, n3, p, miss_ptr);
-    GKL_LAUNCH_CHECK("missing_offsets_kernel");
-}
-
-// One thread per SNP scans its column and writes the missing individuals in
-// increasing order.
-__global__ void missing_lists_kernel(const uint8_t* __restrict__ G, int64_t ld, int64_t n,
-                                     int64_t p, const int64_t* __restrict__ ptr,
-                                     int32_t* __restrict__ idx)
-{
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < p;
-         j += (int64_t)gridDim.x * blockDim.x) {
-        const uint8_t* col = G + j * ld;
-        int64_t o = ptr[j];
-        const int64_t end = ptr[j + 1];   // the counts come from the same codes; the
-                                          // bound keeps every write inside the list
-        const int64_t nb = (n + 3) / 4;
-        for (int64_t b = 0; b < nb; ++b) {
-            const uint32_t byte = col[b];
-            if ((byte & (byte >> 1) & 0x55u) == 0) continue;   // no code 3 in this byte
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int64_t i = 4 * b + k;
-                if (i < n && ((byte >> (2 * k)) & 3u) == 3u && o < end) idx[o++] = (int32_t)i;
-            }
-        }
-    }
-}
-
-void launch_missing_lists(const uint8_t* G, int64_t ld, int64_t n, int64_t p,
-                          const int64_t* miss_ptr, int32_t* miss_idx, hipStream_t s)
-{
-    hipLaunchKernelGGL(missing_lists_kernel, dim3(stride_grid(p, 256)), dim3(256), 0, s, G, ld, n, p,
-                       miss_ptr, miss_idx);
-    GKL_LAUNCH_CHECK("missing_lists_kernel");
-}
-
 }  // namespace gkl
 

@@ -21,24 +21,18 @@ struct ColStats {
 //      (feeds A v: one byte = four SNPs of one individual)
 //   P: nqP x pP bytes; P[I * pP + j] = codes of individuals 4I..4I+3 of SNP j
 //      (feeds A^T u: one byte = four individuals of one SNP)
-//   miss_ptr / miss_idx: per SNP j, the individuals with a missing code,
-//      miss_idx[miss_ptr[j] .. miss_ptr[j+1]) in increasing order (feeds the
-//      missing-data correction of A^T u).
 struct Packed {
     const uint8_t* T = nullptr;
     const uint8_t* P = nullptr;
     int64_t n = 0, p = 0;
     int64_t nT = 0, Pq = 0;       // rows (padded individuals), SNP quads of T
     int64_t pP = 0, nq = 0, nqP = 0;  // padded SNPs, individual quads (real, padded) of P
-    const int64_t* miss_ptr = nullptr;   // p + 1
-    const int32_t* miss_idx = nullptr;
 };
 
 // Device scratch used by the two-stage reductions of the matvec kernels.
 struct MatvecWork {
     double* partial = nullptr;        // split partials
     size_t partial_elems = 0;
-    double* corr = nullptr;           // p: sum of u over each SNP's missing individuals
     unsigned int* counters = nullptr; // zeroed, one per output block
     size_t ncounters = 0;
 };
@@ -53,11 +47,7 @@ void layout_shape(int64_t n, int64_t p, Packed& L);
 size_t layout_T_bytes(const Packed& L);
 size_t layout_P_bytes(const Packed& L);
 void build_layouts(const uint8_t* G, int64_t ld, const Packed& L, hipStream_t s);
-// miss_ptr = exclusive prefix sum of the per-SNP missing counts n3 (p + 1 entries).
-void launch_missing_offsets(const int64_t* n3, int64_t p, int64_t* miss_ptr, hipStream_t s);
-// Fills miss_idx from the caller's matrix (needs miss_ptr).
-void launch_missing_lists(const uint8_t* G, int64_t ld, int64_t n, int64_t p,
-                          const int64_t* miss_ptr, int32_t* miss_idx, hipStream_t s);
+
 // Unpack from the internal layout to n x p column-major int8, -1 = missing.
 void launch_unpack_layout(const Packed& L, int8_t* out, hipStream_t s);
 
@@ -96,9 +86,6 @@ struct BatchDesc {
     double* h;                       // projection coefficients, hstride
     double* npart;                   // norm partials, chunks
     double* anorm;                   // running max of the alphas and betas
-    const int64_t* miss_ptr;         // missing-code lists (see Packed)
-    const int32_t* miss_idx;
-    double* corr;                    // p: missing-data sums of the current A^T u
     int32_t* active;                 // 0 once converged or stopped
     int32_t* breakdown;              // set when a new vector had no new direction
 };
