@@ -49,6 +49,7 @@ struct BatchProblem {
     double* anorm = nullptr;
     double* tmp = nullptr;      // restart scratch, max(n, p) x keep
     RitzOut ritz{};
+    int64_t cap = 0;            // min(n, p): the largest Krylov basis of this problem
     // per-solve results
     int final_m = 0;
     bool converged = false;
@@ -297,13 +298,14 @@ gkl_status gkl_create_batched(int32_t count, const uint8_t* const* G, const int6
                            "batched solves use full reorthogonalisation (GKL_REORTH_FULL)");
     if (o->precision != GKL_PREC_FP64)
         return batch_error(nullptr, GKL_ERR_UNSUPPORTED, "batched solves run in FP64");
-    int64_t mn = INT64_MAX;
+    int64_t mn = INT64_MAX, mx = 0;
     for (int q = 0; q < count; ++q) {
         if (!G[q]) return batch_error(nullptr, GKL_ERR_INVALID, "G[q] is NULL");
         if (n[q] < 1 || p[q] < 1) return batch_error(nullptr, GKL_ERR_INVALID, "n and p must be >= 1");
         if (o->ld_bytes != 0 && o->ld_bytes < (n[q] + 3) / 4)
             return batch_error(nullptr, GKL_ERR_INVALID, "ld_bytes < ceil(n/4)");
         mn = std::min(mn, std::min(n[q], p[q]));
+        mx = std::max(mx, std::min(n[q], p[q]));
     }
     if (k < 1 || (int64_t)k > mn)
         return batch_error(nullptr, GKL_ERR_INVALID, "k must lie in [1, min(n, p)] of every problem");
@@ -338,14 +340,16 @@ gkl_status gkl_create_batched(int32_t count, const uint8_t* const* G, const int6
             B.own_stream = true;
         }
         hipStream_t s = B.stream;
+        // The basis capacity is shared (problems step together); a problem whose own
+        // min(n, p) is smaller leaves the batch when its Krylov space is complete.
         if (o->krylov_dim > 0) {
             B.krylov = o->krylov_dim;
-            B.maxm = (int)std::min<int64_t>(o->krylov_dim, mn);
+            B.maxm = (int)std::min<int64_t>(o->krylov_dim, mx);
             B.keep = o->keep > 0 ? o->keep : k + (B.krylov - k) / 2;
             B.keep = std::min(B.keep, B.maxm - 1);
             if (B.maxm <= k) B.krylov = 0;
         } else {
-            B.maxm = (int)std::min<int64_t>(o->max_steps > 0 ? o->max_steps : 512, mn);
+            B.maxm = (int)std::min<int64_t>(o->max_steps > 0 ? o->max_steps : 512, mx);
         }
         const int m = B.maxm;
         B.hstride = m + 2;
@@ -355,6 +359,7 @@ gkl_status gkl_create_batched(int32_t count, const uint8_t* const* G, const int6
             BatchProblem& P = *B.probs.back();
             const int64_t ld = o->ld_bytes ? o->ld_bytes : (n[q] + 3) / 4;
             P.prob.setup(G[q], n[q], p[q], ld, s, true);
+            P.cap = std::min(n[q], p[q]);
             B.max_n = std::max(B.max_n, n[q]);
             B.max_p = std::max(B.max_p, p[q]);
             size_t pe = 0;
@@ -479,7 +484,10 @@ gkl_status gkl_solve_batched(gkl_ctx* ctx, double* const* sigma, double* const* 
                 }
             const bool full = j >= B.maxm;
             const bool budget = o.max_matvecs > 0 && 2 * total_steps >= o.max_matvecs;
-            const bool due = j >= k && (full || budget || (check_every > 0 && j - last_check >= check_every));
+            bool complete = false;   // some active problem has a complete Krylov space
+            for (auto& P : B.probs) complete = complete || (P->active && j >= P->cap);
+            const bool due = (j >= k && (full || budget || (check_every > 0 && j - last_check >= check_every))) ||
+                             complete;
             if (!due) continue;
             last_check = j;
             for (int q = 0; q < count; ++q) {
@@ -498,11 +506,14 @@ gkl_status gkl_solve_batched(gkl_ctx* ctx, double* const* sigma, double* const* 
             for (int q = 0; q < count; ++q) {
                 BatchProblem& P = *B.probs[q];
                 if (!P.active) continue;
-                if (brk[q]) {
+                // a breakdown on the last vector a complete Krylov space can hold is
+                // the end of that space, not a failure: its Ritz values are exact
+                const bool exhausted = brk[q] && (brk[q] - 1) / 2 + 1 >= P.cap;
+                if (brk[q] && !exhausted) {
                     P.broke = true;
                 } else if (nconv[q] >= k) {
                     P.converged = true;
-                } else if (!(budget || (full && B.krylov == 0))) {
+                } else if (!(budget || (full && B.krylov == 0) || j >= P.cap)) {
                     continue;
                 }
                 P.active = false;

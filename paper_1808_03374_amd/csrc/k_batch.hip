@@ -131,7 +131,8 @@ bupdate_kernel(const BatchDesc* __restrict__ desc, const int* __restrict__ state
 
 // alpha_j / beta_j = ||r|| from the chunk sums (one wave per problem).  A norm
 // at or below 2^-52 sqrt(len) times the largest scalar so far is a breakdown:
-// the problem stops (its scalar is 0 and the vector is left unscaled).
+// the problem stops (its scalar is 0, the vector is left unscaled and
+// *breakdown records the half-step 2j + side, plus one).
 __global__ void __launch_bounds__(64)
 bnorm_kernel(const BatchDesc* __restrict__ desc, const int* __restrict__ state, int side)
 {
@@ -147,7 +148,7 @@ bnorm_kernel(const BatchDesc* __restrict__ desc, const int* __restrict__ state, 
         const double scale = *D.anorm;
         if (!(nrm > 2.220446049250313e-16 * sqrt((double)S.len) * scale) || !(nrm > 0.0)) {
             *S.scalar = 0.0;
-            *D.breakdown = 1;
+            *D.breakdown = 1 + 2 * state[0] + side;   // the half-step, plus one
             *D.active = 0;
         } else {
             *S.scalar = nrm;

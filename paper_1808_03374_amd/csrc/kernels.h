@@ -87,7 +87,7 @@ struct BatchDesc {
     double* npart;                   // norm partials, chunks
     double* anorm;                   // running max of the alphas and betas
     int32_t* active;                 // 0 once converged or stopped
-    int32_t* breakdown;              // set when a new vector had no new direction
+    int32_t* breakdown;              // 1 + half-step (2j + side) of a breakdown, else 0
 };
 
 // Product geometry of one problem for the given split targets (blocks per launch).

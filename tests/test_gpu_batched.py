@@ -139,3 +139,52 @@ def test_autotuned_geometry(gk):
     for q in range(len(gs)):
         s0, s1 = a[0][q].cpu().numpy(), b[0][q].cpu().numpy()
         assert np.all(np.abs(s0 - s1) <= 1e-10 * s0)
+
+
+def test_problems_of_different_sizes_and_a_single_problem(gk):
+    # individuals differ between problems too; and a batch of one
+    sizes = [(300, 1500, 5), (900, 700, 9), (520, 2600, 13)]
+    gs = [synth.config("c4", n=n, p=p, chrom=c) for n, p, c in sizes]
+    Gs = [dev(g.packed) for g in gs]
+    k = 4
+    v0s = start_vectors(gs)
+    refs = oracle_solutions(gs, k, v0s)
+    sig, Us, Vs, st, infos, _ = run_batch(gk, Gs, gs, k, v0s, krylov_dim=16)
+    assert st == gk.GKL_OK
+    for q, (op, ref) in enumerate(refs):
+        check_against_oracle(sig[q], Us[q], Vs[q], op, ref, k)
+    sig1, Us1, Vs1, st1, _, _ = run_batch(gk, Gs[1:2], gs[1:2], k, v0s[1:2], krylov_dim=16)
+    assert st1 == gk.GKL_OK
+    check_against_oracle(sig1[0], Us1[0], Vs1[0], refs[1][0], refs[1][1], k)
+
+
+def test_rank_deficient_problem_reports_breakdown(gk):
+    # a two-group matrix has rank one: asking for three triplets breaks the
+    # Lanczos recurrence on that problem; the other problem still converges
+    n, p = 40, 30
+    codes = np.zeros((n, p), dtype=np.int64)
+    codes[n // 2:] = 2
+    g0 = synth.Genotypes(synth.pack_codes(codes), n, p, (n + 3) // 4, {})
+    g1 = synth.config("c4", n=300, p=900, chrom=4)
+    gs = [g0, g1]
+    Gs = [dev(g.packed) for g in gs]
+    k = 3
+    v0s = start_vectors(gs)
+    v0 = dev(np.concatenate(v0s))
+    ctx = gk.BatchedContext(Gs, [g.n for g in gs], [g.p for g in gs], k, tol=1e-11,
+                            reorth=gk.GKL_REORTH_FULL, v0=v0)
+    SA = [torch.empty(k, dtype=torch.float64, device="cuda") for _ in gs]
+    UA = [torch.empty((k, g.n), dtype=torch.float64, device="cuda") for g in gs]
+    VA = [torch.empty((k, g.p), dtype=torch.float64, device="cuda") for g in gs]
+    infos = (gk.gkl_info * 2)()
+    import ctypes
+    arr = lambda xs: (ctypes.c_void_p * 2)(*[x.data_ptr() for x in xs])
+    st = gk.lib.gkl_solve_batched(ctypes.c_void_p(ctx.ctx), arr(SA), arr(UA),
+                                  (ctypes.c_int64 * 2)(*[g.n for g in gs]), arr(VA),
+                                  (ctypes.c_int64 * 2)(*[g.p for g in gs]), infos)
+    assert st == gk.GKL_ERR_BREAKDOWN
+    assert "broke down" in gk.gkl_last_error(ctx.ctx)
+    assert infos[0].converged == 0 and infos[1].converged == 1
+    op, ref = oracle_solutions([g1], k, v0s[1:])[0]
+    check_against_oracle(SA[1], UA[1].T, VA[1].T, op, ref, k)
+    ctx.close()
