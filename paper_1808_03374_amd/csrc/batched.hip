@@ -43,7 +43,7 @@ struct BatchProblem {
     double* beta = nullptr;
     double* theta = nullptr;
     double* rho = nullptr;
-    double* hpart = nullptr;
+    double* tnpart = nullptr;
     double* h = nullptr;
     double* npart = nullptr;
     double* anorm = nullptr;
@@ -126,7 +126,7 @@ struct BatchState {
             d.beta = P.beta;
             d.theta = P.theta;
             d.rho = P.rho;
-            d.hpart = P.hpart;
+            d.tnpart = P.tnpart;
             d.h = P.h;
             d.npart = P.npart;
             d.anorm = P.anorm;
@@ -377,7 +377,7 @@ gkl_status gkl_create_batched(int32_t count, const uint8_t* const* G, const int6
             P.theta = sc + 2 * (m + 2);
             P.rho = sc + 3 * (m + 2);
             const size_t ch = bortho_chunks(std::max(n[q], p[q]));
-            P.hpart = static_cast<double*>(A.alloc(sizeof(double) * ch * B.hstride));
+            P.tnpart = static_cast<double*>(A.alloc(sizeof(double) * batch_tn_partial_elems(B.hstride)));
             P.h = static_cast<double*>(A.alloc(sizeof(double) * B.hstride));
             P.npart = static_cast<double*>(A.alloc(sizeof(double) * ch));
             P.anorm = static_cast<double*>(A.alloc(sizeof(double)));

@@ -8,7 +8,8 @@
 // device (state[0]) for the same reason.
 //
 // Full reorthogonalisation by classical Gram-Schmidt applied twice (CGS2): for
-// a new vector r and basis Q(:, 0:c), h = Q^T r, r <- r - Q h, twice; the norm
+// a new vector r and basis Q(:, 0:c), h = Q^T r (on the FP64 matrix cores, see
+// launch_batch_proj), r <- r - Q h, twice; the norm
 // of the result (accumulated while the second update writes r) becomes alpha_j
 // or beta_j and r is scaled to unit length.  Sums over row chunks are added in
 // chunk order, so results do not depend on scheduling.
@@ -51,53 +52,6 @@ __device__ __forceinline__ Side side_of(const BatchDesc& D, int j, int side)
 }  // namespace
 
 size_t bortho_chunks(int64_t len) { return (size_t)((len + kChunk - 1) / kChunk); }
-
-// hpart[chunk][c] = sum over the chunk's rows of Q(row, c) r(row); each wave takes
-// columns wave, wave + 4, ... with the chunk of r held in registers.
-__global__ void __launch_bounds__(256)
-bproj_kernel(const BatchDesc* __restrict__ desc, const int* __restrict__ state, int side,
-             int hstride)
-{
-    const BatchDesc& D = desc[blockIdx.y];
-    if (!*D.active) return;
-    const Side S = side_of(D, state[0], side);
-    const int64_t r0 = (int64_t)blockIdx.x * kChunk;
-    if (r0 >= S.len || S.ncols == 0) return;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    double rv[kPerLane];
-#pragma unroll
-    for (int t = 0; t < kPerLane; ++t) {
-        const int64_t row = r0 + lane + (int64_t)t * kWave;
-        rv[t] = row < S.len ? S.r[row] : 0.0;
-    }
-    for (int c = wave; c < S.ncols; c += 4) {
-        const double* qc = S.Q + (int64_t)c * S.len;
-        double a = 0.0;
-#pragma unroll
-        for (int t = 0; t < kPerLane; ++t) {
-            const int64_t row = r0 + lane + (int64_t)t * kWave;
-            if (row < S.len) a = fma(qc[row], rv[t], a);
-        }
-        a = wave_sum(a);
-        if (lane == 0) D.hpart[(int64_t)blockIdx.x * hstride + c] = a;
-    }
-}
-
-// h[c] = sum of hpart over the chunks, in chunk order.
-__global__ void __launch_bounds__(256)
-bproj_reduce_kernel(const BatchDesc* __restrict__ desc, const int* __restrict__ state, int side,
-                    int hstride)
-{
-    const BatchDesc& D = desc[blockIdx.x];
-    if (!*D.active) return;
-    const Side S = side_of(D, state[0], side);
-    const int nch = (int)((S.len + kChunk - 1) / kChunk);
-    for (int c = threadIdx.x; c < S.ncols; c += blockDim.x) {
-        double a = 0.0;
-        for (int ch = 0; ch < nch; ++ch) a += D.hpart[(int64_t)ch * hstride + c];
-        D.h[c] = a;
-    }
-}
 
 // r <- r - Q h over the chunk's rows; with norm != 0 the chunk's sum of squares
 // of the new r goes to npart[chunk].
@@ -173,11 +127,7 @@ void launch_bortho(const BatchDesc* d, const int* state, int count, int side, in
 {
     const dim3 gch((unsigned int)bortho_chunks(max_len), (unsigned int)count);
     for (int pass = 0; pass < 2; ++pass) {
-        hipLaunchKernelGGL(bproj_kernel, gch, dim3(256), 0, s, d, state, side, hstride);
-        GKL_LAUNCH_CHECK("bproj_kernel");
-        hipLaunchKernelGGL(bproj_reduce_kernel, dim3(count), dim3(256), 0, s, d, state, side,
-                           hstride);
-        GKL_LAUNCH_CHECK("bproj_reduce_kernel");
+        launch_batch_proj(d, state, count, side, hstride, s);
         hipLaunchKernelGGL(bupdate_kernel, gch, dim3(256), 0, s, d, state, side, pass == 1 ? 1 : 0);
         GKL_LAUNCH_CHECK("bupdate_kernel");
     }

@@ -35,12 +35,12 @@ __device__ __forceinline__ v4d mfma64(double a, double b, v4d c)
 }
 
 // Rows per workgroup (a multiple of 128) and workgroup count for Q^T Y.
-void tn_plan(int64_t len, int64_t* rows_per_wg, int* nwg)
+__host__ __device__ inline void tn_plan(int64_t len, int64_t* rows_per_wg, int* nwg)
 {
-    int64_t r = ceil_div(len, (int64_t)256);
+    int64_t r = (len + 255) / 256;
     r = (r + 127) / 128 * 128;
     *rows_per_wg = r;
-    *nwg = (int)ceil_div(len, r);
+    *nwg = (int)((len + r - 1) / r);
 }
 }  // namespace
 
@@ -48,20 +48,18 @@ void tn_plan(int64_t len, int64_t* rows_per_wg, int* nwg)
 // q0 + 64).  Each wave walks steps of 32 rows; in a step, lane group g holds rows
 // 8g .. 8g + 7 of its column and MFMA t contracts row 8g + t of every group.
 // The four waves are summed through LDS in a fixed order.
-__global__ void __launch_bounds__(256)
-gemm_tn_kernel(const double* __restrict__ Q, int64_t ldq, const double* __restrict__ Y,
-               int64_t ldy, int64_t len, int q, int b, int64_t rows_per_wg,
-               double* __restrict__ partial, const int* __restrict__ enable,
-               const int* __restrict__ skip)
+__device__ __forceinline__ void tn_body(const double* __restrict__ Q, int64_t ldq,
+                                        const double* __restrict__ Y, int64_t ldy, int64_t len,
+                                        int q, int b, int64_t rows_per_wg, double* __restrict__ my,
+                                        int bx, int by)
 {
-    if ((enable && *enable == 0) || (skip && *skip)) return;   // the same for every thread
     __shared__ double red[2][kTnPart];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int col = lane & 15, g = lane >> 4;
-    const int q0 = blockIdx.y * kTnQ;
+    const int q0 = by * kTnQ;
     const int nqt = (q - q0 + 15) / 16 < 4 ? (q - q0 + 15) / 16 : 4;
     const int nbt = (b + 15) / 16;
-    const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg;
+    const int64_t r0 = (int64_t)bx * rows_per_wg;
     const int64_t r1 = r0 + rows_per_wg < len ? r0 + rows_per_wg : len;
     const double* qp[4];
     bool qok[4];
@@ -126,8 +124,19 @@ gemm_tn_kernel(const double* __restrict__ Q, int64_t ldq, const double* __restri
                     red[wave - 2][(qt * 16 + g + 4 * e) * kBmax + bt * 16 + col] += acc[qt][bt][e];
     }
     __syncthreads();
-    double* my = partial + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * kTnPart;
     for (int e = threadIdx.x; e < kTnPart; e += 256) my[e] = red[0][e] + red[1][e];
+}
+
+__global__ void __launch_bounds__(256)
+gemm_tn_kernel(const double* __restrict__ Q, int64_t ldq, const double* __restrict__ Y,
+               int64_t ldy, int64_t len, int q, int b, int64_t rows_per_wg,
+               double* __restrict__ partial, const int* __restrict__ enable,
+               const int* __restrict__ skip)
+{
+    if ((enable && *enable == 0) || (skip && *skip)) return;   // the same for every thread
+    tn_body(Q, ldq, Y, ldy, len, q, b, rows_per_wg,
+            partial + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * kTnPart, blockIdx.x,
+            blockIdx.y);
 }
 
 // H(qc, j) = sum over workgroups of the partials: 16 lanes per output, lane r
@@ -265,6 +274,88 @@ void launch_gemm_nn_sub(const double* Q, int64_t ldq, double* Y, int64_t ldy, in
                         int b, const double* H, int ldh, hipStream_t s)
 {
     launch_gemm_nn(Q, ldq, q, H, ldh, Y, ldy, len, b, 1, s);
+}
+
+// ---------------------------------------------------------------------------
+// Batched projections h = Q^T r of every active problem (grid.z = problem)
+// ---------------------------------------------------------------------------
+size_t batch_tn_partial_elems(int hstride)
+{
+    return (size_t)256 * (size_t)ceil_div(hstride, kTnQ) * kTnPart;
+}
+
+namespace {
+struct ProjSide {
+    int64_t len;
+    int ncols;
+    const double* Q;
+    const double* r;
+};
+__device__ __forceinline__ ProjSide proj_side(const BatchDesc& D, int j, int side)
+{
+    ProjSide s;
+    if (side == 0) {
+        s.len = D.n;
+        s.ncols = j;
+        s.Q = D.U;
+        s.r = D.U + (int64_t)j * D.n;
+    } else {
+        s.len = D.p;
+        s.ncols = j + 1;
+        s.Q = D.V;
+        s.r = D.V + (int64_t)(j + 1) * D.p;
+    }
+    return s;
+}
+}  // namespace
+
+// Partials of one problem live at tnpart + (chunk * 256 + workgroup) * kTnPart.
+__global__ void __launch_bounds__(256)
+batch_tn_kernel(const BatchDesc* __restrict__ desc, const int* __restrict__ state, int side)
+{
+    const BatchDesc& D = desc[blockIdx.z];
+    if (!*D.active) return;
+    const ProjSide S = proj_side(D, state[0], side);
+    int64_t rpw;
+    int nwg;
+    tn_plan(S.len, &rpw, &nwg);
+    if ((int)blockIdx.x >= nwg || (int)blockIdx.y * kTnQ >= S.ncols) return;   // whole workgroup
+    tn_body(S.Q, S.len, S.r, S.len, S.len, S.ncols, 1, rpw,
+            D.tnpart + ((int64_t)blockIdx.y * 256 + blockIdx.x) * kTnPart, blockIdx.x, blockIdx.y);
+}
+
+// h[c] = sum of the problem's workgroup partials, 16 lanes per column.
+__global__ void __launch_bounds__(256)
+batch_tn_reduce_kernel(const BatchDesc* __restrict__ desc, const int* __restrict__ state, int side)
+{
+    const BatchDesc& D = desc[blockIdx.y];
+    if (!*D.active) return;
+    const ProjSide S = proj_side(D, state[0], side);
+    int64_t rpw;
+    int nwg;
+    tn_plan(S.len, &rpw, &nwg);
+    const int t = blockIdx.x * 16 + (threadIdx.x >> 4);
+    const int r = threadIdx.x & 15;
+    const bool live = t < S.ncols;
+    const double* src =
+        D.tnpart + (int64_t)(live ? t / kTnQ : 0) * 256 * kTnPart + (live ? t % kTnQ : 0) * kBmax;
+    double s = 0.0;
+    if (live)
+        for (int x = r; x < nwg; x += 16) s += src[(int64_t)x * kTnPart];
+#pragma unroll
+    for (int off = 8; off >= 1; off >>= 1) s += __shfl_xor(s, off, 16);
+    if (live && r == 0) D.h[t] = s;
+}
+
+void launch_batch_proj(const BatchDesc* d, const int* state, int count, int side, int hstride,
+                       hipStream_t s)
+{
+    hipLaunchKernelGGL(batch_tn_kernel, dim3(256, ceil_div(hstride, kTnQ), count), dim3(256), 0, s,
+                       d, state, side);
+    GKL_LAUNCH_CHECK("batch_tn_kernel");
+    hipLaunchKernelGGL(batch_tn_reduce_kernel, dim3(ceil_div(hstride, 16), count), dim3(256), 0, s,
+                       d, state, side);
+    GKL_LAUNCH_CHECK("batch_tn_reduce_kernel");
 }
 
 // Cholesky of the b x b Gram matrix (column-major, ld b) in one workgroup, with an

@@ -82,7 +82,7 @@ struct BatchDesc {
     double* beta;
     double* theta;
     double* rho;
-    double* hpart;                   // Gram-Schmidt partials, chunks x hstride
+    double* tnpart;                  // projection partials (batch_tn_partial_elems)
     double* h;                       // projection coefficients, hstride
     double* npart;                   // norm partials, chunks
     double* anorm;                   // running max of the alphas and betas
@@ -117,6 +117,10 @@ void launch_brmatvec_reduce(const BatchDesc* d, const int* state, int count, int
 void launch_bortho(const BatchDesc* d, const int* state, int count, int side, int64_t max_len,
                    int hstride, hipStream_t s);
 size_t bortho_chunks(int64_t len);
+// h = Q^T r of every active problem on the FP64 matrix cores (k_block.hip).
+size_t batch_tn_partial_elems(int hstride);
+void launch_batch_proj(const BatchDesc* d, const int* state, int count, int side, int hstride,
+                       hipStream_t s);
 void launch_bstep(int* state, hipStream_t s);
 // v_0 of every problem scaled to unit norm (start of a solve).
 void launch_bstart(const BatchDesc* d, int count, int64_t max_p, int hstride, hipStream_t s);
