@@ -113,6 +113,8 @@ struct gkl_ctx {
     void left_step(int j);
     void right_step(int j);
     void launch_normalize_only(double* r, int64_t len, double* out);
+    gkl::ProArgs pro_args(int j) const;
+    gkl::NormTail pro_tail(double* nrm_out, int side, int j) const;
     void handle_breakdown(bool left, int j);
     int check_convergence(int m);
     void restart(int m);

@@ -84,6 +84,7 @@ void Problem::setup(const uint8_t* G, int64_t n_, int64_t p_, int64_t ld_, hipSt
     mvw.partial = static_cast<double*>(arena.alloc(sizeof(double) * mvw.partial_elems));
     mvw.ncounters = matvec_counters(packed);
     mvw.counters = static_cast<unsigned int*>(arena.alloc(sizeof(unsigned int) * mvw.ncounters));
+    mvw.npart = static_cast<double*>(arena.alloc(sizeof(double) * matvec_norm_partials(packed)));
     GKL_HIP(hipMemsetAsync(mvw.counters, 0, sizeof(unsigned int) * mvw.ncounters, s));
 }
 
@@ -234,14 +235,19 @@ void gkl_ctx::left_step(int j)
     double* uj = U + (int64_t)j * n;
     const double* vj = V + (int64_t)j * p;
     const int ev = timing_begin();
+    const bool pro_on = j > 0 && reorth == GKL_REORTH_PARTIAL;
+    bool pro_done = false;
     if (j > 0 && j == nlock) {
         launch_matvec(prob.packed, prob.st, vj, uj, nullptr, nullptr, prob.mvw, s);
         timing_end(ev, false);
         launch_gemv_n_sub(U, n, n, nlock, rho, uj, s);
     } else if (j > 0) {
+        // alpha_j and the PRO update come with the product
+        const NormTail tail = pro_tail(alpha + j, 1, j);
         launch_matvec(prob.packed, prob.st, vj, uj, beta + (j - 1), U + (int64_t)(j - 1) * n,
-                      prob.mvw, s);
+                      prob.mvw, s, pro_on ? &tail : nullptr);
         timing_end(ev, false);
+        pro_done = pro_on;
     } else {
         launch_matvec(prob.packed, prob.st, vj, uj, nullptr, nullptr, prob.mvw, s);
         timing_end(ev, false);
@@ -250,9 +256,11 @@ void gkl_ctx::left_step(int j)
     info.passes_over_G += 1;
     const int* gate = nullptr;
     if (j > 0) {
-        if (reorth == GKL_REORTH_PARTIAL) {
-            launch_normalize_only(uj, n, alpha + j);
-            launch_pro_left(alpha, beta, theta, rho, nlock, j, omega, noise_scale, norm_est, pro, s);
+        if (pro_on) {
+            if (!pro_done) {
+                launch_normalize_only(uj, n, alpha + j);
+                launch_pro_left(pro_args(j), s);
+            }
             gate = pro.flag_left;
         }
         launch_cgs2(U, n, n, j, uj, gate, opt.adaptive_cgs2, flags + 6, ow, s);
@@ -273,16 +281,14 @@ void gkl_ctx::right_step(int j)
     const double* uj = U + (int64_t)j * n;
     double* vn = V + (int64_t)(j + 1) * p;
     const int ev = timing_begin();
-    launch_rmatvec(prob.packed, prob.st, uj, vn, alpha + j, V + (int64_t)j * p, prob.mvw, s);
+    const bool pro_on = reorth == GKL_REORTH_PARTIAL;
+    const NormTail tail = pro_tail(beta + j, 2, j);   // beta_j and the PRO update
+    launch_rmatvec(prob.packed, prob.st, uj, vn, alpha + j, V + (int64_t)j * p, prob.mvw, s,
+                   pro_on ? &tail : nullptr);
     timing_end(ev, true);
     info.matvecs += 1;
     info.passes_over_G += 1;
-    const int* gate = nullptr;
-    if (reorth == GKL_REORTH_PARTIAL) {
-        launch_normalize_only(vn, p, beta + j);
-        launch_pro_right(alpha, beta, theta, rho, nlock, j, omega, noise_scale, norm_est, pro, s);
-        gate = pro.flag_right;
-    }
+    const int* gate = pro_on ? pro.flag_right : nullptr;
     launch_cgs2(V, p, p, j + 1, vn, gate, opt.adaptive_cgs2, flags + 6, ow, s);
     if (!opt.adaptive_cgs2)
         launch_normalize_after_cgs2(vn, p, beta + j, norm_est, root_maxdim, flags + 1, gate, ow, s,
@@ -290,6 +296,31 @@ void gkl_ctx::right_step(int j)
     else
         launch_normalize(vn, p, vn, beta + j, norm_est, root_maxdim, flags + 1, ow, s, flags + 9,
                          2 * j + 1);
+}
+
+ProArgs gkl_ctx::pro_args(int j) const
+{
+    ProArgs a;
+    a.alpha = alpha;
+    a.beta = beta;
+    a.theta = theta;
+    a.rho = rho;
+    a.nlock = nlock;
+    a.j = j;
+    a.omega = omega;
+    a.noise_scale = noise_scale;
+    a.norm_est = norm_est;
+    a.st = pro;
+    return a;
+}
+
+NormTail gkl_ctx::pro_tail(double* nrm_out, int side, int j) const
+{
+    NormTail t{};
+    t.nrm_out = nrm_out;
+    t.pro = side;
+    t.pa = pro_args(j);
+    return t;
 }
 
 // Reads the number of converged Ritz values and the first breakdown half-step

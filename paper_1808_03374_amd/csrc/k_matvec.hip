@@ -7,23 +7,26 @@
 // two products are where the iteration spends its time.  Genotypes stay 2-bit
 // packed in HBM; the dense standardised matrix is never formed.
 //
-// Both products use lookup tables in LDS so that one byte of four packed codes
-// costs one table read and one FP64 add:
+// Both products use lookup tables in LDS, so that one byte of four packed codes
+// costs a few table reads and FP64 adds:
 //   A v   -- layout T: byte (quad J, individual i) holds the codes of SNPs
-//            4J..4J+3 of individual i; for each quad J the 256-entry table
-//            L_J[b] = sum_k t_{4J+k}(code_k(b)), t_j(c) = (c - mu_j) s_j v_j for
-//            c < 3 and 0 for missing, is built in LDS and every lane adds
-//            L_J[byte] into the accumulator of its individual.
+//            4J..4J+3 of individual i; with t_j(c) = (c - mu_j) s_j v_j for
+//            c < 3 and 0 for missing, the quad's contribution to individual i
+//            is L_J[b] = sum_k t_{4J+k}(code_k(b)); it is read as the sum of
+//            two 16-entry pair tables (SNPs 4J, 4J+1 by the byte's low nibble,
+//            4J+2, 4J+3 by its high nibble), which is cheaper than filling a
+//            256-entry table per quad and keeps LDS use small.
 //   A^T u -- layout P: byte (individual quad I, SNP j) holds the codes of
 //            individuals 4I..4I+3 of SNP j; for each quad I one table holds
 //            sum_k g(c_k) u_{4I+k} per byte value and a second, indexed by the
 //            byte's missing-code bits, the sum of u over the quad's missing
 //            individuals; sum_i o_ij u_i = sum_i u_i - that sum.
-// Tables of a quad are built from two 16-entry pair tables (one add per entry).
+// The A^T u table of a quad is filled from two 16-entry pair tables (one add
+// per entry); there the full table is faster than two reads per byte.
 // Wavefronts read 512 B or 1 KB contiguous per quad row.  Partial sums of the
 // K-splits go to a scratch buffer and a second kernel adds them in a fixed
 // order (deterministic, no atomics).
-#include "kernels.h"
+#include "pro.h"
 
 namespace gkl {
 
@@ -158,7 +161,6 @@ __device__ __forceinline__ void matvec_tile(const uint8_t* __restrict__ T, int64
 {
     __shared__ double tv[kQCH * 4 * 4];          // t value per (SNP, code)
     __shared__ double pairs[kQCH * 2 * 16];      // per quad: codes of SNPs (0,1) and (2,3)
-    __shared__ double lut[kQCH * 256];           // 32 KB
     const int64_t row0 = bx * kRowsPerBlock + (int64_t)threadIdx.x * kIPT;
     const bool active = row0 < nT;
     const int64_t Jb = by * quads_per_split;
@@ -190,19 +192,22 @@ __device__ __forceinline__ void matvec_tile(const uint8_t* __restrict__ T, int64
             pairs[e] = tv[sa * 4 + (x & 3)] + tv[(sa + 1) * 4 + (x >> 2)];
         }
         __syncthreads();
-        for (int e = threadIdx.x; e < kQCH * 256; e += kMvThreads) {
-            const int q = e >> 8, b = e & 255;
-            lut[e] = pairs[q * 32 + (b & 15)] + pairs[q * 32 + 16 + (b >> 4)];
-        }
-        __syncthreads();
+        // nT is a multiple of the rows of a wave, so `active` is the same for
+        // every lane of a wave: padding waves skip the table reads
+        if (active) {
 #pragma unroll
-        for (int q = 0; q < kQCH; ++q) {
-            const double* L = lut + q * 256;
-            const uint32_t w[4] = {d[q].x, d[q].y, d[q].z, d[q].w};
+            for (int q = 0; q < kQCH; ++q) {
+                const double* Lo = pairs + q * 32;
+                const double* Hi = Lo + 16;
+                const uint32_t w[4] = {d[q].x, d[q].y, d[q].z, d[q].w};
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
+                for (int t = 0; t < 4; ++t) {
 #pragma unroll
-                for (int k = 0; k < 4; ++k) acc[4 * t + k] += L[(w[t] >> (8 * k)) & 0xFFu];
+                    for (int k = 0; k < 4; ++k) {
+                        const uint32_t b = (w[t] >> (8 * k)) & 0xFFu;
+                        acc[4 * t + k] += Lo[b & 15] + Hi[b >> 4];
+                    }
+                }
             }
         }
         __syncthreads();
@@ -232,7 +237,7 @@ constexpr int kRedGroups = 8;
 __global__ void __launch_bounds__(kRedRows * kRedGroups)
 matvec_reduce_kernel(const double* __restrict__ partial, int64_t nT, int nsplit, int64_t n,
                      double* __restrict__ y, const double* __restrict__ beta,
-                     const double* __restrict__ uprev)
+                     const double* __restrict__ uprev, double* __restrict__ npart)
 {
     __shared__ double sh[kRedGroups][kRedRows];
     const int r = threadIdx.x % kRedRows, g = threadIdx.x / kRedRows;
@@ -254,11 +259,17 @@ matvec_reduce_kernel(const double* __restrict__ partial, int64_t nT, int nsplit,
     }
     sh[g][r] = a;
     __syncthreads();
+    double ss = 0.0;
     if (g == 0 && i < n) {
         double s = 0.0;
         for (int t = 0; t < kRedGroups; ++t) s += sh[t][r];
         if (uprev) s -= (beta ? *beta : 0.0) * uprev[i];
         y[i] = s;
+        ss = s * s;
+    }
+    if (npart) {
+        ss = block_sum(ss, sh[0]);
+        if (threadIdx.x == 0) npart[blockIdx.x] = ss;
     }
 }
 
@@ -367,9 +378,11 @@ __global__ void rmatvec_reduce_kernel(const double* __restrict__ partial, int64_
                                       int64_t p, const double* __restrict__ inv_sd,
                                       double* __restrict__ z,
                                       const double* __restrict__ alpha,
-                                      const double* __restrict__ vprev)
+                                      const double* __restrict__ vprev,
+                                      double* __restrict__ npart)
 {
     const double a = alpha ? *alpha : 0.0;
+    double ss = 0.0;
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < p;
          j += (int64_t)gridDim.x * blockDim.x) {
         double s = 0.0;
@@ -377,7 +390,27 @@ __global__ void rmatvec_reduce_kernel(const double* __restrict__ partial, int64_
         double r = inv_sd[j] * s;
         if (vprev) r -= a * vprev[j];
         z[j] = r;
+        ss = fma(r, r, ss);
     }
+    if (npart) {
+        __shared__ double red[16];
+        ss = block_sum(ss, red);
+        if (threadIdx.x == 0) npart[blockIdx.x] = ss;
+    }
+}
+
+// The norm (and PRO update) after a reduce kernel that left sums of squares.
+__global__ void __launch_bounds__(256) norm_pro_kernel(NormTail t, int nparts)
+{
+    norm_pro_body(t, nparts);
+}
+
+static void launch_norm_pro(const NormTail* t, const MatvecWork& w, int nparts, hipStream_t s)
+{
+    NormTail x = *t;
+    x.npart = w.npart;
+    hipLaunchKernelGGL(norm_pro_kernel, dim3(1), dim3(256), 0, s, x, nparts);
+    GKL_LAUNCH_CHECK("norm_pro_kernel");
 }
 
 // ---------------------------------------------------------------------------
@@ -436,8 +469,21 @@ size_t matvec_partial_elems(const Packed& L)
 
 size_t matvec_counters(const Packed&) { return 1; }
 
+namespace {
+constexpr int64_t kRmvReduceBlocks = 2048;
+}
+
+size_t matvec_norm_partials(const Packed& L)
+{
+    const int64_t a = ceil_div(L.n, kRedRows);
+    int64_t b = ceil_div(L.p, 256);
+    if (b > kRmvReduceBlocks) b = kRmvReduceBlocks;
+    return (size_t)(a > b ? a : b);
+}
+
 void launch_matvec(const Packed& L, const ColStats& st, const double* v, double* y,
-                   const double* beta, const double* uprev, MatvecWork& w, hipStream_t s)
+                   const double* beta, const double* uprev, MatvecWork& w, hipStream_t s,
+                   const NormTail* tail)
 {
     const Split sp = mv_split(L);
     dim3 grid((unsigned int)((L.nT + kRowsPerBlock - 1) / kRowsPerBlock), (unsigned int)sp.nsplit);
@@ -446,12 +492,14 @@ void launch_matvec(const Packed& L, const ColStats& st, const double* v, double*
     GKL_LAUNCH_CHECK("matvec_lut_kernel");
     hipLaunchKernelGGL(matvec_reduce_kernel, dim3(ceil_div(L.n, kRedRows)),
                        dim3(kRedRows * kRedGroups), 0, s, w.partial, L.nT, sp.nsplit, L.n, y, beta,
-                       uprev);
+                       uprev, tail ? w.npart : nullptr);
     GKL_LAUNCH_CHECK("matvec_reduce_kernel");
+    if (tail) launch_norm_pro(tail, w, (int)ceil_div(L.n, kRedRows), s);
 }
 
 void launch_rmatvec(const Packed& L, const ColStats& st, const double* u, double* z,
-                    const double* alpha, const double* vprev, MatvecWork& w, hipStream_t s)
+                    const double* alpha, const double* vprev, MatvecWork& w, hipStream_t s,
+                    const NormTail* tail)
 {
     const Split sp = rmv_split(L);
     dim3 grid((unsigned int)(L.pP / kColsPerBlock), (unsigned int)sp.nsplit);
@@ -459,10 +507,11 @@ void launch_rmatvec(const Packed& L, const ColStats& st, const double* u, double
                        u, st.mean, sp.per_split, w.partial);
     GKL_LAUNCH_CHECK("rmatvec_lut_kernel");
     unsigned int nb = ceil_div(L.p, 256);
-    if (nb > 2048) nb = 2048;
+    if (nb > kRmvReduceBlocks) nb = kRmvReduceBlocks;
     hipLaunchKernelGGL(rmatvec_reduce_kernel, dim3(nb), dim3(256), 0, s, w.partial, L.pP,
-                       sp.nsplit, L.p, st.inv_sd, z, alpha, vprev);
+                       sp.nsplit, L.p, st.inv_sd, z, alpha, vprev, tail ? w.npart : nullptr);
     GKL_LAUNCH_CHECK("rmatvec_reduce_kernel");
+    if (tail) launch_norm_pro(tail, w, (int)nb, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -35,7 +35,10 @@ struct MatvecWork {
     size_t partial_elems = 0;
     unsigned int* counters = nullptr; // zeroed, one per output block
     size_t ncounters = 0;
+    double* npart = nullptr;          // per-block sums of squares for a NormTail
 };
+
+struct NormTail;
 
 // ---- k_stats.hip ----
 void launch_colstats(const uint8_t* G, int64_t n, int64_t p, int64_t ld, const ColStats& st,
@@ -53,11 +56,17 @@ void launch_unpack_layout(const Packed& L, int8_t* out, hipStream_t s);
 
 // ---- k_matvec.hip: FP64 products with the implicit standardised matrix ----
 // y = A v - (beta ? *beta : 0) * uprev      (y, uprev: n; v: p)
+// With a tail, ||y|| also goes to tail->nrm_out (and the PRO update runs);
+// the tail's npart is taken from w.
 void launch_matvec(const Packed& P, const ColStats& st, const double* v, double* y,
-                   const double* beta, const double* uprev, MatvecWork& w, hipStream_t s);
+                   const double* beta, const double* uprev, MatvecWork& w, hipStream_t s,
+                   const NormTail* tail = nullptr);
 // z = A^T u - (alpha ? *alpha : 0) * vprev  (u: n; z, vprev: p)
 void launch_rmatvec(const Packed& P, const ColStats& st, const double* u, double* z,
-                    const double* alpha, const double* vprev, MatvecWork& w, hipStream_t s);
+                    const double* alpha, const double* vprev, MatvecWork& w, hipStream_t s,
+                    const NormTail* tail = nullptr);
+// Length of MatvecWork::npart.
+size_t matvec_norm_partials(const Packed& P);
 size_t matvec_partial_elems(const Packed& P);
 size_t matvec_counters(const Packed& P);
 
@@ -219,16 +228,36 @@ struct ProState {
     int* flag_right;  // 1 = reorthogonalise the next right vector
     int* force;       // [0] left, [1] right: pending forced passes (Simon's rule)
 };
-// Update after alpha_j (left side) or beta_j (right side); theta/rho/nlock
-// describe the thick-restart block (nlock = 0 without restart).
-// noise_scale = eps * sqrt(max(n, p)); the noise added per update is
-// noise_scale * (*norm_est) / alpha_j (or beta_j).
-void launch_pro_left(const double* alpha, const double* beta, const double* theta,
-                     const double* rho, int nlock, int j, double omega, double noise_scale,
-                     const double* norm_est, const ProState& st, hipStream_t s);
-void launch_pro_right(const double* alpha, const double* beta, const double* theta,
-                      const double* rho, int nlock, int j, double omega, double noise_scale,
-                      const double* norm_est, const ProState& st, hipStream_t s);
+// Everything one PRO update reads besides the new norm: the update follows
+// alpha_j (left side) or beta_j (right side); theta/rho/nlock describe the
+// thick-restart block (nlock = 0 without restart); noise_scale = eps *
+// sqrt(max(n, p)), and the noise added per update is noise_scale * (*norm_est)
+// / alpha_j (or beta_j).
+struct ProArgs {
+    const double* alpha;
+    const double* beta;
+    const double* theta;
+    const double* rho;
+    int nlock;
+    int j;
+    double omega;
+    double noise_scale;
+    const double* norm_est;
+    ProState st;
+};
+// PRO update after alpha_j (left) or beta_j (right) is in memory.
+void launch_pro_left(const ProArgs& a, hipStream_t s);
+void launch_pro_right(const ProArgs& a, hipStream_t s);
+// Norm (and PRO update) of a product's output, requested from launch_matvec /
+// launch_rmatvec: their reduce kernel leaves per-workgroup sums of squares in
+// npart and one more small kernel finishes (pro.h).  pro = 0 norm only, 1 left
+// update, 2 right update.
+struct NormTail {
+    double* npart;
+    double* nrm_out;
+    int pro;
+    ProArgs pa;
+};
 // Zero the estimates and force `force` full reorthogonalisations on each side.
 void launch_pro_reset(const ProState& st, int maxm, int force, hipStream_t s);
 
