@@ -25,66 +25,65 @@ constexpr int kGroup = 16;                      // lanes per column pair
 constexpr int kGroups = kSvdThreads / kGroup;   // pairs rotated at once
 constexpr int kMaxSweeps = 40;
 
+// One 64-bit DPP move (two 32-bit halves) with a constant lane pattern.
+template <int kCtrl>
+__device__ __forceinline__ double dpp_move(double v)
+{
+    const long long x = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(x & 0xffffffff), kCtrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(x >> 32), kCtrl, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the 16 lanes of a group (a DPP row).  Partners are symmetric at
+// every level -- lane i with i^1, i^2 (quad permutes), 7-i within each half
+// row, 15-i within the row -- so every lane ends with the same bits.
 __device__ __forceinline__ double group_sum(double v)
 {
-#pragma unroll
-    for (int off = kGroup / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, kGroup);
+    static_assert(kGroup == 16, "group_sum covers one DPP row");
+    v += dpp_move<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_move<0x4E>(v);    // quad_perm [2,3,0,1]
+    v += dpp_move<0x141>(v);   // row_half_mirror
+    v += dpp_move<0x140>(v);   // row_mirror
     return v;
 }
 
 constexpr int kRegs = 8;   // column elements per lane kept in registers (mp <= 128)
 
-// Rotate columns a and b of X (ld mp) by (cs, sn): x_a <- cs x_a - sn x_b,
-// x_b <- sn x_a + cs x_b.
-__device__ __forceinline__ void rotate_pair(double* X, int mp, int a, int b, double cs, double sn,
-                                            int gl)
+// 1/x and 1/sqrt(x) from the hardware estimates, each refined by two Newton
+// steps.
+__device__ __forceinline__ double rcp_refined(double x)
 {
-    double* xa = X + (int64_t)a * mp;
-    double* xb = X + (int64_t)b * mp;
-    if (mp <= kRegs * kGroup) {
-        double u[kRegs], v[kRegs];
-#pragma unroll
-        for (int j = 0; j < kRegs; ++j) {
-            const int i = gl + j * kGroup;
-            u[j] = i < mp ? xa[i] : 0.0;
-            v[j] = i < mp ? xb[i] : 0.0;
-        }
-#pragma unroll
-        for (int j = 0; j < kRegs; ++j) {
-            const int i = gl + j * kGroup;
-            if (i < mp) {
-                xa[i] = cs * u[j] - sn * v[j];
-                xb[i] = sn * u[j] + cs * v[j];
-            }
-        }
-    } else {
-        for (int i = gl; i < mp; i += kGroup) {
-            const double x = xa[i], y = xb[i];
-            xa[i] = cs * x - sn * y;
-            xb[i] = sn * x + cs * y;
-        }
-    }
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
 }
 
-__device__ __forceinline__ double pair_dot(const double* X, int mp, int a, int b, int gl)
+__device__ __forceinline__ double rsq_refined(double x)
 {
-    const double* xa = X + (int64_t)a * mp;
-    const double* xb = X + (int64_t)b * mp;
-    double s = 0.0;
-    if (mp <= kRegs * kGroup) {
-        double u[kRegs], v[kRegs];
-#pragma unroll
-        for (int j = 0; j < kRegs; ++j) {
-            const int i = gl + j * kGroup;
-            u[j] = i < mp ? xa[i] : 0.0;
-            v[j] = i < mp ? xb[i] : 0.0;
-        }
-#pragma unroll
-        for (int j = 0; j < kRegs; ++j) s = fma(u[j], v[j], s);
-    } else {
-        for (int i = gl; i < mp; i += kGroup) s = fma(xa[i], xb[i], s);
-    }
-    return group_sum(s);
+    double y = __builtin_amdgcn_rsq(x);
+    y = y * fma(-0.5 * (x * y), y, 1.5);
+    return y * fma(-0.5 * (x * y), y, 1.5);
+}
+
+// Rotation of a column pair with inner product sab and squared norms saa, sbb
+// (Rutishauser's formulas): zeta = (sbb - saa) / (2 sab), t = sign(zeta) /
+// (|zeta| + sqrt(1 + zeta^2)), cs = 1 / sqrt(1 + t^2), sn = cs t.  Returns
+// false when the pair needs no rotation: sab is negligible against the norms
+// (|sab| <= tol sqrt(saa sbb), tested squared), or zeta is so large (or not a
+// number, from a vanishing sab) that the angle, about 1/(2 zeta), would not
+// change either column.
+__device__ __forceinline__ bool jacobi_rotation(double sab, double saa, double sbb, double tol,
+                                                double& t, double& cs, double& sn)
+{
+    if (!(sab != 0.0 && sab * sab > (tol * tol) * (saa * sbb))) return false;
+    const double z = (sbb - saa) * (0.5 * rcp_refined(sab));
+    if (!(fabs(z) < 1e150)) return false;
+    const double w = fma(z, z, 1.0);
+    t = (z >= 0.0 ? 1.0 : -1.0) * rcp_refined(fabs(z) + w * rsq_refined(w));
+    cs = rsq_refined(fma(t, t, 1.0));
+    sn = cs * t;
+    return true;
 }
 
 // W (mp x mp, column-major, ld = mp) is replaced by B Q = P S; Vr accumulates Q.
@@ -98,8 +97,10 @@ __device__ __forceinline__ void jacobi_sweeps(double* W, double* Vr, int mp)
     const int g = threadIdx.x / kGroup;
     const int gl = threadIdx.x % kGroup;
     const int npairs = mp / 2;
+    const int ring = mp - 1;
     // rotation threshold sqrt(m) * eps (the usual one-sided Jacobi test)
     const double tol = 2.220446049250313e-16 * sqrt((double)mp);
+    const bool in_regs = mp <= kRegs * kGroup;
     for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
         for (int c = g; c < mp; c += kGroups) {
             const double* wc = W + (int64_t)c * mp;
@@ -110,26 +111,72 @@ __device__ __forceinline__ void jacobi_sweeps(double* W, double* Vr, int mp)
         }
         if (threadIdx.x == 0) rotated = 0;
         __syncthreads();
-        for (int r = 0; r < mp - 1; ++r) {
+        for (int r = 0; r < ring; ++r) {
             for (int k = g; k < npairs; k += kGroups) {
+                // round-robin tournament: pair k of round r
                 int a, b;
                 if (k == 0) {
-                    a = mp - 1;
+                    a = ring;
                     b = r;
                 } else {
-                    a = (r + k) % (mp - 1);
-                    b = (r - k + (mp - 1)) % (mp - 1);
+                    a = r + k;
+                    if (a >= ring) a -= ring;
+                    b = r - k;
+                    if (b < 0) b += ring;
                 }
-                if (a > b) { const int t = a; a = b; b = t; }
-                const double sab = pair_dot(W, mp, a, b, gl);
+                if (a > b) { const int tmp = a; a = b; b = tmp; }
+                double* xa = W + (int64_t)a * mp;
+                double* xb = W + (int64_t)b * mp;
+                double* ya = Vr + (int64_t)a * mp;
+                double* yb = Vr + (int64_t)b * mp;
                 const double saa = dn[a], sbb = dn[b];
-                if (sab != 0.0 && fabs(sab) > tol * sqrt(saa * sbb)) {
-                    const double zeta = (sbb - saa) / (2.0 * sab);
-                    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                    const double cs = 1.0 / sqrt(1.0 + t * t);
-                    const double sn = cs * t;
-                    rotate_pair(W, mp, a, b, cs, sn, gl);
-                    rotate_pair(Vr, mp, a, b, cs, sn, gl);
+                double t, cs, sn;
+                if (in_regs) {
+                    // both pairs of columns are read once; the rotation is
+                    // applied from registers
+                    double u[kRegs], v[kRegs], pa[kRegs], pb[kRegs];
+#pragma unroll
+                    for (int j = 0; j < kRegs; ++j) {
+                        const int i = gl + j * kGroup;
+                        const bool ok = i < mp;
+                        u[j] = ok ? xa[i] : 0.0;
+                        v[j] = ok ? xb[i] : 0.0;
+                        pa[j] = ok ? ya[i] : 0.0;
+                        pb[j] = ok ? yb[i] : 0.0;
+                    }
+                    double sab = 0.0;
+#pragma unroll
+                    for (int j = 0; j < kRegs; ++j) sab = fma(u[j], v[j], sab);
+                    sab = group_sum(sab);
+                    if (!jacobi_rotation(sab, saa, sbb, tol, t, cs, sn)) continue;
+#pragma unroll
+                    for (int j = 0; j < kRegs; ++j) {
+                        const int i = gl + j * kGroup;
+                        if (i < mp) {
+                            xa[i] = cs * u[j] - sn * v[j];
+                            xb[i] = sn * u[j] + cs * v[j];
+                            ya[i] = cs * pa[j] - sn * pb[j];
+                            yb[i] = sn * pa[j] + cs * pb[j];
+                        }
+                    }
+                    if (gl == 0) {
+                        dn[a] = saa - t * sab;
+                        dn[b] = sbb + t * sab;
+                        rotated = 1;
+                    }
+                } else {
+                    double sab = 0.0;
+                    for (int i = gl; i < mp; i += kGroup) sab = fma(xa[i], xb[i], sab);
+                    sab = group_sum(sab);
+                    if (!jacobi_rotation(sab, saa, sbb, tol, t, cs, sn)) continue;
+                    for (int i = gl; i < mp; i += kGroup) {
+                        const double x = xa[i], y = xb[i];
+                        xa[i] = cs * x - sn * y;
+                        xb[i] = sn * x + cs * y;
+                        const double p = ya[i], q = yb[i];
+                        ya[i] = cs * p - sn * q;
+                        yb[i] = sn * p + cs * q;
+                    }
                     if (gl == 0) {
                         dn[a] = saa - t * sab;
                         dn[b] = sbb + t * sab;
