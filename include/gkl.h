@@ -89,8 +89,10 @@ typedef struct gkl_options {
     void* stream;             /* hipStream_t; NULL = default stream */
     int32_t trace;            /* 1: record a per-step trace (gkl_get_trace) */
     int32_t verbose;          /* 1: progress lines on stderr */
-    int32_t timing;           /* 1: bracket every product launch with HIP events and
-                                 report the kernel time in gkl_info */
+    int32_t timing;           /* t > 0: bracket the first of every t product launches
+                                 (1 = every launch) with HIP events and report the
+                                 product kernel time in gkl_info; each bracket
+                                 costs the stream a few microseconds */
     int32_t autotune;         /* batched: 1 = time candidate product geometries at
                                  create and keep the fastest; 0 = fixed geometry */
     int32_t graph;            /* batched: 1 (default) = each Lanczos step is one HIP

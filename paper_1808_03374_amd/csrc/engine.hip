@@ -177,10 +177,13 @@ int gkl_ctx::read_flag(const int* dflag)
 }
 
 // Kernel timing: events are taken from a pool that grows on demand and is
-// reused across solves; durations are summed after the solve.
-int gkl_ctx::timing_begin()
+// reused across solves; durations are summed after the solve.  With
+// options.timing = t, the first of every t launches of each product is
+// bracketed (a recorded event costs the stream a few microseconds).
+int gkl_ctx::timing_slot(bool right)
 {
-    if (!opt.timing) return -1;
+    if (opt.timing <= 0) return -1;
+    if (ev_calls[right ? 1 : 0]++ % opt.timing != 0) return -1;
     if (ev_next + 2 > (int)ev_pool.size()) {
         for (int t = 0; t < 64; ++t) {
             hipEvent_t e;
@@ -190,7 +193,23 @@ int gkl_ctx::timing_begin()
     }
     const int i = ev_next;
     ev_next += 2;
-    GKL_HIP(hipEventRecord(ev_pool[i], prob.stream));
+    return i;
+}
+
+const hipEvent_t* gkl_ctx::timing_events(int slot)
+{
+    return slot < 0 ? nullptr : &ev_pool[slot];
+}
+
+void gkl_ctx::timing_note(int slot, bool right)
+{
+    if (slot >= 0) (right ? ev_rmv : ev_mv).push_back({slot, slot + 1});
+}
+
+int gkl_ctx::timing_begin(bool right)
+{
+    const int i = timing_slot(right);
+    if (i >= 0) GKL_HIP(hipEventRecord(ev_pool[i], prob.stream));
     return i;
 }
 
@@ -198,7 +217,7 @@ void gkl_ctx::timing_end(int start, bool right)
 {
     if (start < 0) return;
     GKL_HIP(hipEventRecord(ev_pool[start + 1], prob.stream));
-    (right ? ev_rmv : ev_mv).push_back({start, start + 1});
+    timing_note(start, right);
 }
 
 void gkl_ctx::timing_collect()
@@ -223,6 +242,7 @@ void gkl_ctx::timing_collect()
     ev_mv.clear();
     ev_rmv.clear();
     ev_next = 0;
+    ev_calls[0] = ev_calls[1] = 0;
 }
 
 // Left half-step j: U(:, j) from v_j.  Nothing is read back: a breakdown is
@@ -234,24 +254,23 @@ void gkl_ctx::left_step(int j)
     const int64_t n = prob.n, p = prob.p;
     double* uj = U + (int64_t)j * n;
     const double* vj = V + (int64_t)j * p;
-    const int ev = timing_begin();
+    const int ev = timing_slot(false);
+    const hipEvent_t* evs = timing_events(ev);
     const bool pro_on = j > 0 && reorth == GKL_REORTH_PARTIAL;
     bool pro_done = false;
     if (j > 0 && j == nlock) {
-        launch_matvec(prob.packed, prob.st, vj, uj, nullptr, nullptr, prob.mvw, s);
-        timing_end(ev, false);
+        launch_matvec(prob.packed, prob.st, vj, uj, nullptr, nullptr, prob.mvw, s, nullptr, evs);
         launch_gemv_n_sub(U, n, n, nlock, rho, uj, s);
     } else if (j > 0) {
         // alpha_j and the PRO update come with the product
         const NormTail tail = pro_tail(alpha + j, 1, j);
         launch_matvec(prob.packed, prob.st, vj, uj, beta + (j - 1), U + (int64_t)(j - 1) * n,
-                      prob.mvw, s, pro_on ? &tail : nullptr);
-        timing_end(ev, false);
+                      prob.mvw, s, pro_on ? &tail : nullptr, evs);
         pro_done = pro_on;
     } else {
-        launch_matvec(prob.packed, prob.st, vj, uj, nullptr, nullptr, prob.mvw, s);
-        timing_end(ev, false);
+        launch_matvec(prob.packed, prob.st, vj, uj, nullptr, nullptr, prob.mvw, s, nullptr, evs);
     }
+    timing_note(ev, false);
     info.matvecs += 1;
     info.passes_over_G += 1;
     const int* gate = nullptr;
@@ -280,12 +299,12 @@ void gkl_ctx::right_step(int j)
     const int64_t n = prob.n, p = prob.p;
     const double* uj = U + (int64_t)j * n;
     double* vn = V + (int64_t)(j + 1) * p;
-    const int ev = timing_begin();
+    const int ev = timing_slot(true);
     const bool pro_on = reorth == GKL_REORTH_PARTIAL;
     const NormTail tail = pro_tail(beta + j, 2, j);   // beta_j and the PRO update
     launch_rmatvec(prob.packed, prob.st, uj, vn, alpha + j, V + (int64_t)j * p, prob.mvw, s,
-                   pro_on ? &tail : nullptr);
-    timing_end(ev, true);
+                   pro_on ? &tail : nullptr, timing_events(ev));
+    timing_note(ev, true);
     info.matvecs += 1;
     info.passes_over_G += 1;
     const int* gate = pro_on ? pro.flag_right : nullptr;
@@ -730,9 +749,10 @@ gkl_status gkl_matvec(gkl_ctx* ctx, const double* v, double* y)
     if (!ctx->prob.packed.T) return set_error(ctx, GKL_ERR_INVALID, "FP64 products need an FP64 context");
     try {
         hipStream_t s = ctx->prob.stream;
-        const int ev = ctx->timing_begin();
-        launch_matvec(ctx->prob.packed, ctx->prob.st, v, y, nullptr, nullptr, ctx->prob.mvw, s);
-        ctx->timing_end(ev, false);
+        const int ev = ctx->timing_slot(false);
+        launch_matvec(ctx->prob.packed, ctx->prob.st, v, y, nullptr, nullptr, ctx->prob.mvw, s,
+                      nullptr, ctx->timing_events(ev));
+        ctx->timing_note(ev, false);
         GKL_HIP(hipStreamSynchronize(s));
         return GKL_OK;
     } catch (const Error& e) {
@@ -746,9 +766,10 @@ gkl_status gkl_rmatvec(gkl_ctx* ctx, const double* u, double* z)
     if (!ctx->prob.packed.T) return set_error(ctx, GKL_ERR_INVALID, "FP64 products need an FP64 context");
     try {
         hipStream_t s = ctx->prob.stream;
-        const int ev = ctx->timing_begin();
-        launch_rmatvec(ctx->prob.packed, ctx->prob.st, u, z, nullptr, nullptr, ctx->prob.mvw, s);
-        ctx->timing_end(ev, true);
+        const int ev = ctx->timing_slot(true);
+        launch_rmatvec(ctx->prob.packed, ctx->prob.st, u, z, nullptr, nullptr, ctx->prob.mvw, s,
+                       nullptr, ctx->timing_events(ev));
+        ctx->timing_note(ev, true);
         GKL_HIP(hipStreamSynchronize(s));
         return GKL_OK;
     } catch (const Error& e) {

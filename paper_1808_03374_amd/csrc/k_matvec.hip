@@ -483,13 +483,15 @@ size_t matvec_norm_partials(const Packed& L)
 
 void launch_matvec(const Packed& L, const ColStats& st, const double* v, double* y,
                    const double* beta, const double* uprev, MatvecWork& w, hipStream_t s,
-                   const NormTail* tail)
+                   const NormTail* tail, const hipEvent_t* ev)
 {
     const Split sp = mv_split(L);
     dim3 grid((unsigned int)((L.nT + kRowsPerBlock - 1) / kRowsPerBlock), (unsigned int)sp.nsplit);
+    if (ev) GKL_HIP(hipEventRecord(ev[0], s));
     hipLaunchKernelGGL(matvec_lut_kernel, grid, dim3(kMvThreads), 0, s, L.T, L.nT, L.p, L.Pq,
                        st.mean, st.inv_sd, v, sp.per_split, w.partial);
     GKL_LAUNCH_CHECK("matvec_lut_kernel");
+    if (ev) GKL_HIP(hipEventRecord(ev[1], s));
     hipLaunchKernelGGL(matvec_reduce_kernel, dim3(ceil_div(L.n, kRedRows)),
                        dim3(kRedRows * kRedGroups), 0, s, w.partial, L.nT, sp.nsplit, L.n, y, beta,
                        uprev, tail ? w.npart : nullptr);
@@ -499,13 +501,15 @@ void launch_matvec(const Packed& L, const ColStats& st, const double* v, double*
 
 void launch_rmatvec(const Packed& L, const ColStats& st, const double* u, double* z,
                     const double* alpha, const double* vprev, MatvecWork& w, hipStream_t s,
-                    const NormTail* tail)
+                    const NormTail* tail, const hipEvent_t* ev)
 {
     const Split sp = rmv_split(L);
     dim3 grid((unsigned int)(L.pP / kColsPerBlock), (unsigned int)sp.nsplit);
+    if (ev) GKL_HIP(hipEventRecord(ev[0], s));
     hipLaunchKernelGGL(rmatvec_lut_kernel, grid, dim3(kMvThreads), 0, s, L.P, L.pP, L.n, L.nq, L.p,
                        u, st.mean, sp.per_split, w.partial);
     GKL_LAUNCH_CHECK("rmatvec_lut_kernel");
+    if (ev) GKL_HIP(hipEventRecord(ev[1], s));
     unsigned int nb = ceil_div(L.p, 256);
     if (nb > kRmvReduceBlocks) nb = kRmvReduceBlocks;
     hipLaunchKernelGGL(rmatvec_reduce_kernel, dim3(nb), dim3(256), 0, s, w.partial, L.pP,

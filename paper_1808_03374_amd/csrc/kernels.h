@@ -57,14 +57,15 @@ void launch_unpack_layout(const Packed& L, int8_t* out, hipStream_t s);
 // ---- k_matvec.hip: FP64 products with the implicit standardised matrix ----
 // y = A v - (beta ? *beta : 0) * uprev      (y, uprev: n; v: p)
 // With a tail, ||y|| also goes to tail->nrm_out (and the PRO update runs);
-// the tail's npart is taken from w.
+// the tail's npart is taken from w.  With ev, ev[0] and ev[1] are recorded
+// right before and after the product kernel (not its reduce).
 void launch_matvec(const Packed& P, const ColStats& st, const double* v, double* y,
                    const double* beta, const double* uprev, MatvecWork& w, hipStream_t s,
-                   const NormTail* tail = nullptr);
+                   const NormTail* tail = nullptr, const hipEvent_t* ev = nullptr);
 // z = A^T u - (alpha ? *alpha : 0) * vprev  (u: n; z, vprev: p)
 void launch_rmatvec(const Packed& P, const ColStats& st, const double* u, double* z,
                     const double* alpha, const double* vprev, MatvecWork& w, hipStream_t s,
-                    const NormTail* tail = nullptr);
+                    const NormTail* tail = nullptr, const hipEvent_t* ev = nullptr);
 // Length of MatvecWork::npart.
 size_t matvec_norm_partials(const Packed& P);
 size_t matvec_partial_elems(const Packed& P);

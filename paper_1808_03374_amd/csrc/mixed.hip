@@ -153,7 +153,7 @@ gkl_status gkl_ctx::solve_mixed(double* sigma, double* Uo, int64_t ldu, double* 
         double* Vb = M.V + (int64_t)o * p;
         double* Vn = M.V + (int64_t)(o + b) * p;
         // left block: A V_o minus the coupling to the previous left block
-        const int ev = timing_begin();
+        const int ev = timing_begin(false);
         launch_matmat_mixed(M.shape, M.I, prob.st, Vb, p, b, Ub, n, M.w, s);
         timing_end(ev, false);
         info.matvecs += b;
@@ -170,7 +170,7 @@ gkl_status gkl_ctx::solve_mixed(double* sigma, double* Uo, int64_t ldu, double* 
         launch_block_qr(Ub, n, n, b, M.R, M.qrwork, M.gpart, M.iflags + 1, s);
         launch_put_block(M.Bm, M.ldb, o, o, M.R, b, b, b, 0, s);
         // right block: A^T U_o - V_o R^T
-        const int ev2 = timing_begin();
+        const int ev2 = timing_begin(true);
         launch_rmatmat_mixed(M.shape, M.S, prob.st, Ub, n, b, Vn, p, M.w, s);
         timing_end(ev2, true);
         info.matvecs += b;

@@ -240,3 +240,24 @@ def test_solve_is_deterministic(gk):
     for x, y in zip(a, b):
         assert np.array_equal(x.view(np.uint64), y.view(np.uint64))
     ctx.close()
+
+
+@pytest.mark.parametrize("stride", [1, 3])
+def test_product_timing_sampling(gk, stride):
+    # options.timing = t brackets the first of every t launches of each product;
+    # the results do not depend on it
+    g, Gd = gen("c2", 700, 3000)
+    base = gk.Context(Gd, g.n, g.p, 6, tol=1e-10, krylov_dim=24, reorth=gk.GKL_REORTH_PARTIAL)
+    s0, _, _, _, i0 = base.solve()
+    base.close()
+    ctx = gk.Context(Gd, g.n, g.p, 6, tol=1e-10, krylov_dim=24, reorth=gk.GKL_REORTH_PARTIAL,
+                     timing=stride)
+    s1, _, _, _, i1 = ctx.solve()
+    ctx.close()
+    assert torch.equal(s0, s1)
+    n_mv = i1.matvecs // 2 + i1.matvecs % 2    # A v comes first in every step
+    n_rmv = i1.matvecs // 2
+    assert i1.timed_matvecs == -(-n_mv // stride)
+    assert i1.timed_rmatvecs == -(-n_rmv // stride)
+    assert i0.timed_matvecs == 0 and i0.matvec_kernel_ms == 0.0
+    assert i1.matvec_kernel_ms > 0.0 and i1.rmatvec_kernel_ms > 0.0
