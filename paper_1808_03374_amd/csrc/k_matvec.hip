@@ -37,7 +37,9 @@ constexpr int kRowsPerWave = kWave * kIPT;        // 1024
 constexpr int kRowsPerBlock = kMvThreads * kIPT;  // 4096
 constexpr int kQCH = 16;                          // A v: SNP quads per table chunk
 constexpr int kSPT = 8;                           // A^T u: SNPs per thread (uint2)
-constexpr int kColsPerBlock = kMvThreads * kSPT;  // 2048
+constexpr int kColsPerBlock = kMvThreads * kSPT;  // 2048: padding unit of layout P
+constexpr int kRmvThreads = 512;                  // A^T u workgroup: one table build serves
+constexpr int kRmvCols = kRmvThreads * kSPT;      // 4096 SNPs
 constexpr int kQI = 8;                            // A^T u: individual quads per chunk
 }  // namespace
 
@@ -286,6 +288,10 @@ matvec_reduce_kernel(const double* __restrict__ partial, int64_t nT, int nsplit,
 // sum_i u_i - sum_i m_ij u_i, with sum_i u_i read from the all-ones entry.
 constexpr int kMT = 88;   // missing-table entries per quad (x <= 0x55)
 
+// A workgroup of kRmvThreads threads covers kRmvCols SNPs, so one table build
+// serves 4096 SNPs.  pP (a multiple of 2048) need not be a multiple of 4096:
+// threads past pP -- whole waves, as a wave covers 512 SNPs -- only help
+// build the tables.
 __device__ __forceinline__ void rmatvec_tile(const uint8_t* __restrict__ P, int64_t pP, int64_t n,
                                              int64_t nq, int64_t p, const double* __restrict__ u,
                                              const double* __restrict__ mean, int64_t iq_per_split,
@@ -295,7 +301,8 @@ __device__ __forceinline__ void rmatvec_tile(const uint8_t* __restrict__ P, int6
     __shared__ double pairs[kQI * 2 * 16];
     __shared__ double lut[kQI * 256];            // 16 KB
     __shared__ double mtab[kQI * kMT];           // 5.5 KB
-    const int64_t col0 = bx * kColsPerBlock + (int64_t)threadIdx.x * kSPT;
+    const int64_t col0 = bx * kRmvCols + (int64_t)threadIdx.x * kSPT;
+    const bool live = col0 < pP;
     const int64_t Ib = by * iq_per_split;
     const int64_t Ie = Ib + iq_per_split < nq ? Ib + iq_per_split : nq;
     double sg[kSPT], sm[kSPT];
@@ -308,7 +315,7 @@ __device__ __forceinline__ void rmatvec_tile(const uint8_t* __restrict__ P, int6
         uint2 d[kQI];
 #pragma unroll
         for (int q = 0; q < kQI; ++q) {
-            if (q < nqc) d[q] = *reinterpret_cast<const uint2*>(P + (I0 + q) * pP + col0);
+            if (live && q < nqc) d[q] = *reinterpret_cast<const uint2*>(P + (I0 + q) * pP + col0);
             else d[q] = make_uint2(0xFFFFFFFFu, 0xFFFFFFFFu);
         }
         if (threadIdx.x < kQI * 4) {
@@ -316,14 +323,14 @@ __device__ __forceinline__ void rmatvec_tile(const uint8_t* __restrict__ P, int6
             uq[threadIdx.x] = (i < n && (int)(threadIdx.x >> 2) < nqc) ? u[i] : 0.0;
         }
         __syncthreads();
-        for (int e = threadIdx.x; e < kQI * 32; e += kMvThreads) {
+        for (int e = threadIdx.x; e < kQI * 32; e += kRmvThreads) {
             const int q = e >> 5, h = (e >> 4) & 1, x = e & 15;
             const int c0 = x & 3, c1 = x >> 2;
             const double u0 = uq[4 * q + 2 * h], u1 = uq[4 * q + 2 * h + 1];
             const double g0 = c0 == 3 ? 0.0 : (double)c0, g1 = c1 == 3 ? 0.0 : (double)c1;
             pairs[e] = g0 * u0 + g1 * u1;
         }
-        for (int e = threadIdx.x; e < kQI * kMT; e += kMvThreads) {
+        for (int e = threadIdx.x; e < kQI * kMT; e += kRmvThreads) {
             const int q = e / kMT, x = e - q * kMT;
             double v = 0.0;
 #pragma unroll
@@ -332,29 +339,32 @@ __device__ __forceinline__ void rmatvec_tile(const uint8_t* __restrict__ P, int6
             mtab[e] = v;
         }
         __syncthreads();
-        for (int e = threadIdx.x; e < kQI * 256; e += kMvThreads) {
+        for (int e = threadIdx.x; e < kQI * 256; e += kRmvThreads) {
             const int q = e >> 8, b = e & 255;
             lut[e] = pairs[q * 32 + (b & 15)] + pairs[q * 32 + 16 + (b >> 4)];
         }
         __syncthreads();
+        if (live) {
 #pragma unroll
-        for (int q = 0; q < kQI; ++q) {
-            const double* L = lut + q * 256;
-            const double* M = mtab + q * kMT;
-            su += L[0x55];                           // all four codes 1: the quad's sum of u
-            const uint32_t w[2] = {d[q].x, d[q].y};
+            for (int q = 0; q < kQI; ++q) {
+                const double* L = lut + q * 256;
+                const double* M = mtab + q * kMT;
+                su += L[0x55];                       // all four codes 1: the quad's sum of u
+                const uint32_t w[2] = {d[q].x, d[q].y};
 #pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                const uint32_t mw = w[t] & (w[t] >> 1) & 0x55555555u;
+                for (int t = 0; t < 2; ++t) {
+                    const uint32_t mw = w[t] & (w[t] >> 1) & 0x55555555u;
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    sg[4 * t + k] += L[(w[t] >> (8 * k)) & 0xFFu];
-                    sm[4 * t + k] += M[(mw >> (8 * k)) & 0xFFu];
+                    for (int k = 0; k < 4; ++k) {
+                        sg[4 * t + k] += L[(w[t] >> (8 * k)) & 0xFFu];
+                        sm[4 * t + k] += M[(mw >> (8 * k)) & 0xFFu];
+                    }
                 }
             }
         }
         __syncthreads();
     }
+    if (!live) return;
     double* out = partial + by * pP + col0;
 #pragma unroll
     for (int k = 0; k < kSPT; k += 2) {
@@ -366,7 +376,7 @@ __device__ __forceinline__ void rmatvec_tile(const uint8_t* __restrict__ P, int6
     }
 }
 
-__global__ void __launch_bounds__(kMvThreads)
+__global__ void __launch_bounds__(kRmvThreads)
 rmatvec_lut_kernel(const uint8_t* __restrict__ P, int64_t pP, int64_t n, int64_t nq, int64_t p,
                    const double* __restrict__ u, const double* __restrict__ mean,
                    int64_t iq_per_split, double* __restrict__ partial)
@@ -453,8 +463,10 @@ Split mv_split(const Packed& L, int64_t target = kSplitTarget)
 
 Split rmv_split(const Packed& L, int64_t target = kSplitTarget)
 {
-    const int64_t colblocks = L.pP / kColsPerBlock;
-    int64_t cap = (L.nq * 4) / 640;
+    const int64_t colblocks = (L.pP + kRmvCols - 1) / kRmvCols;
+    // partial traffic nsplit * pP * 8 B kept near 10% of the packed bytes (the
+    // partials mostly stay in the last-level cache)
+    int64_t cap = (L.nq * 4) / 320;
     if (cap < 1) cap = 1;
     return choose_split(L.nq, colblocks, kQI, target, cap);
 }
@@ -504,9 +516,9 @@ void launch_rmatvec(const Packed& L, const ColStats& st, const double* u, double
                     const NormTail* tail, const hipEvent_t* ev)
 {
     const Split sp = rmv_split(L);
-    dim3 grid((unsigned int)(L.pP / kColsPerBlock), (unsigned int)sp.nsplit);
+    dim3 grid((unsigned int)((L.pP + kRmvCols - 1) / kRmvCols), (unsigned int)sp.nsplit);
     if (ev) GKL_HIP(hipEventRecord(ev[0], s));
-    hipLaunchKernelGGL(rmatvec_lut_kernel, grid, dim3(kMvThreads), 0, s, L.P, L.pP, L.n, L.nq, L.p,
+    hipLaunchKernelGGL(rmatvec_lut_kernel, grid, dim3(kRmvThreads), 0, s, L.P, L.pP, L.n, L.nq, L.p,
                        u, st.mean, sp.per_split, w.partial);
     GKL_LAUNCH_CHECK("rmatvec_lut_kernel");
     if (ev) GKL_HIP(hipEventRecord(ev[1], s));
@@ -530,7 +542,7 @@ ProductPlan product_plan(const Packed& L, int64_t mv_target, int64_t rmv_target)
     pl.mv_rowblocks = (int)((L.nT + kRowsPerBlock - 1) / kRowsPerBlock);
     pl.rmv_per_split = b.per_split;
     pl.rmv_nsplit = b.nsplit;
-    pl.rmv_colblocks = (int)(L.pP / kColsPerBlock);
+    pl.rmv_colblocks = (int)((L.pP + kRmvCols - 1) / kRmvCols);
     return pl;
 }
 
@@ -574,7 +586,7 @@ bmatvec_kernel(const BatchDesc* __restrict__ desc, const int* __restrict__ tile0
     }
 }
 
-__global__ void __launch_bounds__(kMvThreads)
+__global__ void __launch_bounds__(kRmvThreads)
 brmatvec_kernel(const BatchDesc* __restrict__ desc, const int* __restrict__ tile0, int count,
                 const int* __restrict__ state)
 {
@@ -661,7 +673,7 @@ void launch_bmatvec(const BatchDesc* d, const int* tile0, int count, const int* 
 void launch_brmatvec(const BatchDesc* d, const int* tile0, int count, const int* state, int grid,
                      hipStream_t s)
 {
-    hipLaunchKernelGGL(brmatvec_kernel, dim3(grid), dim3(kMvThreads), 0, s, d, tile0, count, state);
+    hipLaunchKernelGGL(brmatvec_kernel, dim3(grid), dim3(kRmvThreads), 0, s, d, tile0, count, state);
     GKL_LAUNCH_CHECK("brmatvec_kernel");
 }
 
