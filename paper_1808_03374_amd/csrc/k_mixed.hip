@@ -207,18 +207,19 @@ __global__ void split_W_kernel(const double* __restrict__ W, int64_t ldw, int b,
     }
 }
 
-// Per column c: K2_c = sum_j mu_j s_j W_jc (FP64, fixed order; one block per column).
-// Column sums over len rows: out[c] = sum_j f_j X(j, c), with f_j = mean_j inv_sd_j
-// when mean != NULL (the product mean_j (inv_sd_j x) is formed in that order)
-// and f_j = 1 otherwise.  grid (kCsSplit, columns): each block sums one chunk of
-// rows; the last block of a column adds the chunk sums in chunk order.
-constexpr int kCsSplit = 64;   // == wavefront size (final sum is one wave)
+// Column sums over len rows: sum_j f_j X(j, c), with f_j = mean_j inv_sd_j when
+// mean != NULL (the product mean_j (inv_sd_j x) is formed in that order) and
+// f_j = 1 otherwise (per column c: K2_c = sum_j mu_j s_j W_jc for A W, T_c =
+// sum_i X_ic for A^T X).  grid (kCsSplit, columns): each block sums one chunk
+// of rows into cpart[c * kCsSplit + chunk]; the reduce kernel that consumes the
+// sums adds the chunk sums (column_sums).  No cross-block handshake: its
+// device-scope fences cost more than the consumer's 64 extra reads.
+constexpr int kCsSplit = 64;   // == wavefront size (the chunk sums are added by one wave)
 
 __global__ void __launch_bounds__(256)
 colsum_kernel(const double* __restrict__ X, int64_t ldx, int64_t len,
               const double* __restrict__ mean, const double* __restrict__ inv_sd,
-              double* __restrict__ cpart, unsigned int* __restrict__ counters,
-              double* __restrict__ out)
+              double* __restrict__ cpart)
 {
     __shared__ double sh[16];
     const int c = blockIdx.y;
@@ -234,11 +235,19 @@ colsum_kernel(const double* __restrict__ X, int64_t ldx, int64_t len,
     }
     a = block_sum(a, sh);
     if (threadIdx.x == 0) cpart[c * kCsSplit + blockIdx.x] = a;
-    if (!last_block_arrived(&counters[c], kCsSplit)) return;
-    if (threadIdx.x < 64) {      // one wave: kCsSplit == 64 chunk sums, fixed butterfly
-        const double t = wave_sum(cpart[c * kCsSplit + threadIdx.x]);
-        if (threadIdx.x == 0) out[c] = t;
+}
+
+// ks[c] for c < nb: the kCsSplit chunk sums of column c added by one wave in a
+// fixed butterfly (every block of the consumer gets the same bits).  Called by
+// every thread of the block.
+__device__ __forceinline__ void column_sums(const double* __restrict__ cpart, int nb, double* ks)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int c = wave; c < nb; c += (int)(blockDim.x >> 6)) {
+        const double t = wave_sum(cpart[c * kCsSplit + lane]);
+        if (lane == 0) ks[c] = t;
     }
+    __syncthreads();
 }
 
 // A^T X operands.  kPack == false: frag[((st*8 + t)*2 + op)*64 + lane][e], ops
@@ -369,10 +378,13 @@ matmat_bf16_kernel(const uint8_t* __restrict__ I, int64_t ldI, int64_t nI,
 // Y[i + c*ldy] = sum_split partial - K2_c for i < n, c < nb (col0 offset); packed:
 // the hi (column c) and lo (column c + 8) partials of each split are added first.
 template <bool kPack>
-__global__ void matmat_reduce_kernel(const double* __restrict__ partial, int nsplit, int64_t nI,
-                                     int64_t n, int nb, const double* __restrict__ K2,
-                                     double* __restrict__ Y, int64_t ldy)
+__global__ void __launch_bounds__(256)
+matmat_reduce_kernel(const double* __restrict__ partial, int nsplit, int64_t nI, int64_t n,
+                     int nb, const double* __restrict__ cpart, double* __restrict__ Y,
+                     int64_t ldy)
 {
+    __shared__ double K2[16];
+    column_sums(cpart, nb, K2);
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n * 16) return;
     const int64_t i = t >> 4;
@@ -481,12 +493,13 @@ rmatmat_bf16_kernel(const uint8_t* __restrict__ S, int64_t ldS, int64_t pS,
 
 // Z[j + c*ldz] = s_j ( SG - mu_j T_c + mu_j SM )
 template <bool kPack>
-__global__ void rmatmat_reduce_kernel(const double* __restrict__ partial, int nsplit, int64_t pS,
-                                      int64_t p, int nb, const double* __restrict__ T,
-                                      const double* __restrict__ mean,
-                                      const double* __restrict__ inv_sd, double* __restrict__ Z,
-                                      int64_t ldz)
+__global__ void __launch_bounds__(256)
+rmatmat_reduce_kernel(const double* __restrict__ partial, int nsplit, int64_t pS, int64_t p,
+                      int nb, const double* __restrict__ cpart, const double* __restrict__ mean,
+                      const double* __restrict__ inv_sd, double* __restrict__ Z, int64_t ldz)
 {
+    __shared__ double T[16];
+    column_sums(cpart, nb, T);
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= p * 16) return;
     const int64_t j = t >> 4;
@@ -566,8 +579,7 @@ void launch_matmat_mixed(const MixedShape& m, const uint8_t* I, const ColStats& 
                                st.mean, st.inv_sd, m.nstW, reinterpret_cast<bf16x8*>(w.frag));
         GKL_LAUNCH_CHECK("split_W_kernel");
         hipLaunchKernelGGL(colsum_kernel, dim3(kCsSplit, nb), dim3(256), 0, s,
-                           W + (int64_t)col0 * ldw, ldw, m.p, st.mean, st.inv_sd, w.cpart,
-                           w.counters, w.k2);
+                           W + (int64_t)col0 * ldw, ldw, m.p, st.mean, st.inv_sd, w.cpart);
         GKL_LAUNCH_CHECK("colsum_kernel");
         dim3 grid((unsigned int)(m.nI / (kMxWaves * kRTw * 16)), (unsigned int)m.splitW);
         if (pack)
@@ -580,10 +592,10 @@ void launch_matmat_mixed(const MixedShape& m, const uint8_t* I, const ColStats& 
         const dim3 gred(ceil_div(m.n * 16, 256));
         if (pack)
             hipLaunchKernelGGL(matmat_reduce_kernel<true>, gred, dim3(256), 0, s, w.partial,
-                               m.splitW, m.nI, m.n, nb, w.k2, Y + (int64_t)col0 * ldy, ldy);
+                               m.splitW, m.nI, m.n, nb, w.cpart, Y + (int64_t)col0 * ldy, ldy);
         else
             hipLaunchKernelGGL(matmat_reduce_kernel<false>, gred, dim3(256), 0, s, w.partial,
-                               m.splitW, m.nI, m.n, nb, w.k2, Y + (int64_t)col0 * ldy, ldy);
+                               m.splitW, m.nI, m.n, nb, w.cpart, Y + (int64_t)col0 * ldy, ldy);
         GKL_LAUNCH_CHECK("matmat_reduce_kernel");
     }
 }
@@ -605,8 +617,7 @@ void launch_rmatmat_mixed(const MixedShape& m, const uint8_t* S, const ColStats&
                                m.nstX, reinterpret_cast<bf16x8*>(w.frag));
         GKL_LAUNCH_CHECK("split_X_kernel");
         hipLaunchKernelGGL(colsum_kernel, dim3(kCsSplit, nb), dim3(256), 0, s,
-                           X + (int64_t)col0 * ldx, ldx, m.n, nullptr, nullptr, w.cpart,
-                           w.counters, w.k1);
+                           X + (int64_t)col0 * ldx, ldx, m.n, nullptr, nullptr, w.cpart);
         GKL_LAUNCH_CHECK("colsum_kernel");
         dim3 grid((unsigned int)(m.pS / (kMxWaves * kRTr * 16)), (unsigned int)m.splitX);
         if (pack)
@@ -619,11 +630,11 @@ void launch_rmatmat_mixed(const MixedShape& m, const uint8_t* S, const ColStats&
         const dim3 gred(ceil_div(m.p * 16, 256));
         if (pack)
             hipLaunchKernelGGL(rmatmat_reduce_kernel<true>, gred, dim3(256), 0, s, w.partial,
-                               m.splitX, m.pS, m.p, nb, w.k1, st.mean, st.inv_sd,
+                               m.splitX, m.pS, m.p, nb, w.cpart, st.mean, st.inv_sd,
                                Z + (int64_t)col0 * ldz, ldz);
         else
             hipLaunchKernelGGL(rmatmat_reduce_kernel<false>, gred, dim3(256), 0, s, w.partial,
-                               m.splitX, m.pS, m.p, nb, w.k1, st.mean, st.inv_sd,
+                               m.splitX, m.pS, m.p, nb, w.cpart, st.mean, st.inv_sd,
                                Z + (int64_t)col0 * ldz, ldz);
         GKL_LAUNCH_CHECK("rmatmat_reduce_kernel");
     }

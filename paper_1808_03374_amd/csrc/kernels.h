@@ -279,10 +279,7 @@ struct MixedShape {
 struct MixedWork {
     void* frag = nullptr;         // split-BF16 vector fragments
     double* partial = nullptr;
-    double* k1 = nullptr;         // 16 per-column constants
-    double* k2 = nullptr;
     double* cpart = nullptr;      // 16 x 64 column-sum partials
-    unsigned int* counters = nullptr;   // 16, zero between launches
 };
 MixedShape mixed_shape(int64_t n, int64_t p);
 size_t mixed_frag_bytes(const MixedShape& m);

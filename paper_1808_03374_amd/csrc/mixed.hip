@@ -82,11 +82,7 @@ void gkl_ctx::setup_mixed()
     build_mixed_layouts(prob.G_user, n, p, prob.ld, M.I, M.S, s);
     M.w.frag = A.alloc(mixed_frag_bytes(M.shape));
     M.w.partial = static_cast<double*>(A.alloc(sizeof(double) * mixed_partial_elems(M.shape)));
-    M.w.k1 = static_cast<double*>(A.alloc(sizeof(double) * 32));
-    M.w.k2 = static_cast<double*>(A.alloc(sizeof(double) * 32));
     M.w.cpart = static_cast<double*>(A.alloc(sizeof(double) * 16 * 64));
-    M.w.counters = static_cast<unsigned int*>(A.alloc(sizeof(unsigned int) * 16));
-    GKL_HIP(hipMemsetAsync(M.w.counters, 0, sizeof(unsigned int) * 16, s));
     const int b = M.b;
     M.U = static_cast<double*>(A.alloc(sizeof(double) * (size_t)n * m));
     M.V = static_cast<double*>(A.alloc(sizeof(double) * (size_t)p * (m + b)));
