@@ -7,22 +7,26 @@
 // two products are where the iteration spends its time.  Genotypes stay 2-bit
 // packed in HBM; the dense standardised matrix is never formed.
 //
-// Both products use lookup tables in LDS, so that one byte of four packed codes
-// costs a few table reads and FP64 adds:
+// Both products use lookup tables in LDS so that one byte of four packed codes
+// costs one table read and one FP64 add:
 //   A v   -- layout T: byte (quad J, individual i) holds the codes of SNPs
-//            4J..4J+3 of individual i; with t_j(c) = (c - mu_j) s_j v_j for
-//            c < 3 and 0 for missing, the quad's contribution to individual i
-//            is L_J[b] = sum_k t_{4J+k}(code_k(b)); it is read as the sum of
-//            two 16-entry pair tables (SNPs 4J, 4J+1 by the byte's low nibble,
-//            4J+2, 4J+3 by its high nibble), which is cheaper than filling a
-//            256-entry table per quad and keeps LDS use small.
+//            4J..4J+3 of individual i; for each quad J the 256-entry table
+//            L_J[b] = sum_k t_{4J+k}(code_k(b)), t_j(c) = (c - mu_j) s_j v_j for
+//            c < 3 and 0 for missing, is built in LDS and every lane adds
+//            L_J[byte] into the accumulator of its individual.
 //   A^T u -- layout P: byte (individual quad I, SNP j) holds the codes of
 //            individuals 4I..4I+3 of SNP j; for each quad I one table holds
 //            sum_k g(c_k) u_{4I+k} per byte value and a second, indexed by the
 //            byte's missing-code bits, the sum of u over the quad's missing
 //            individuals; sum_i o_ij u_i = sum_i u_i - that sum.
-// The A^T u table of a quad is filled from two 16-entry pair tables (one add
-// per entry); there the full table is faster than two reads per byte.
+// Tables are filled from two 16-entry pair tables (one add per entry).  Both
+// store the entry of byte b at position b ^ (b >> 4): the LDS bank of an
+// 8-byte entry is set by the low four bits of its position, which for a plain
+// table are the codes of the first two SNPs (A v) or individuals (A^T u) only,
+// so the most frequent bytes -- those two carry code 0 -- would all fall in one
+// bank and conflict; the XOR brings in the other two codes (one extra
+// operation per four bytes).  The kernels are bounded by VALU issue and LDS
+// reads, so one read and one add per byte beat any decode with more of either.
 // Wavefronts read 512 B or 1 KB contiguous per quad row.  Partial sums of the
 // K-splits go to a scratch buffer and a second kernel adds them in a fixed
 // order (deterministic, no atomics).
@@ -163,6 +167,7 @@ __device__ __forceinline__ void matvec_tile(const uint8_t* __restrict__ T, int64
 {
     __shared__ double tv[kQCH * 4 * 4];          // t value per (SNP, code)
     __shared__ double pairs[kQCH * 2 * 16];      // per quad: codes of SNPs (0,1) and (2,3)
+    __shared__ double lut[kQCH * 256];           // 32 KB: L_J, entry of byte b at b ^ (b >> 4)
     const int64_t row0 = bx * kRowsPerBlock + (int64_t)threadIdx.x * kIPT;
     const bool active = row0 < nT;
     const int64_t Jb = by * quads_per_split;
@@ -194,21 +199,24 @@ __device__ __forceinline__ void matvec_tile(const uint8_t* __restrict__ T, int64
             pairs[e] = tv[sa * 4 + (x & 3)] + tv[(sa + 1) * 4 + (x >> 2)];
         }
         __syncthreads();
+        for (int e = threadIdx.x; e < kQCH * 256; e += kMvThreads) {
+            const int q = e >> 8, x = e & 255;
+            const int b = x ^ (x >> 4);     // position x holds byte b
+            lut[e] = pairs[q * 32 + (b & 15)] + pairs[q * 32 + 16 + (b >> 4)];
+        }
+        __syncthreads();
         // nT is a multiple of the rows of a wave, so `active` is the same for
         // every lane of a wave: padding waves skip the table reads
         if (active) {
 #pragma unroll
             for (int q = 0; q < kQCH; ++q) {
-                const double* Lo = pairs + q * 32;
-                const double* Hi = Lo + 16;
+                const double* L = lut + q * 256;
                 const uint32_t w[4] = {d[q].x, d[q].y, d[q].z, d[q].w};
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
+                    const uint32_t wx = w[t] ^ ((w[t] >> 4) & 0x0F0F0F0Fu);   // table positions
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const uint32_t b = (w[t] >> (8 * k)) & 0xFFu;
-                        acc[4 * t + k] += Lo[b & 15] + Hi[b >> 4];
-                    }
+                    for (int k = 0; k < 4; ++k) acc[4 * t + k] += L[(wx >> (8 * k)) & 0xFFu];
                 }
             }
         }
@@ -286,13 +294,8 @@ matvec_reduce_kernel(const double* __restrict__ partial, int64_t nT, int nsplit,
 // of the quad is missing).  x is 0 for almost every byte, so the second read is
 // nearly always the same entry for all lanes.  sum_i o_ij u_i is then
 // sum_i u_i - sum_i m_ij u_i, with sum_i u_i read from the all-ones entry.
-// The genotype table keeps the entry of byte b at position b ^ (b >> 4) (low
-// nibble XOR high nibble).  The LDS bank of an 8-byte entry is set by the low
-// four bits of its position; stored plainly, that is the codes of individuals
-// 0 and 1 only, so every byte in which both carry code 0 -- the most frequent
-// case, whatever individuals 2 and 3 carry -- falls in bank 0, and different
-// such bytes read in the same cycle conflict.  The XOR spreads them (one extra
-// operation per four bytes; 10,000 x 100,000: 106 -> 96 us per product).
+// The genotype table is stored swizzled like the A v table (position
+// b ^ (b >> 4)).
 constexpr int kMT = 88;   // missing-table entries per quad (x <= 0x55)
 
 // A workgroup of kRmvThreads threads covers kRmvCols SNPs, so one table build
