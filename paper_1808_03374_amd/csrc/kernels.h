@@ -277,9 +277,10 @@ struct MixedShape {
     int splitW = 1, splitX = 1;
 };
 struct MixedWork {
-    void* frag = nullptr;         // split-BF16 vector fragments
+    void* frag = nullptr;         // int8 limb fragments of the vector block
     double* partial = nullptr;
     double* cpart = nullptr;      // 16 x 64 column-sum partials
+    double* cmax = nullptr;       // 16 x 64 column-maximum partials
 };
 MixedShape mixed_shape(int64_t n, int64_t p);
 size_t mixed_frag_bytes(const MixedShape& m);

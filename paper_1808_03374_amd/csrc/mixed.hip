@@ -83,6 +83,7 @@ void gkl_ctx::setup_mixed()
     M.w.frag = A.alloc(mixed_frag_bytes(M.shape));
     M.w.partial = static_cast<double*>(A.alloc(sizeof(double) * mixed_partial_elems(M.shape)));
     M.w.cpart = static_cast<double*>(A.alloc(sizeof(double) * 16 * 64));
+    M.w.cmax = static_cast<double*>(A.alloc(sizeof(double) * 16 * 64));
     const int b = M.b;
     M.U = static_cast<double*>(A.alloc(sizeof(double) * (size_t)n * m));
     M.V = static_cast<double*>(A.alloc(sizeof(double) * (size_t)p * (m + b)));
