@@ -91,20 +91,24 @@ def cpu_baseline(g, gpu_matvecs, seconds):
 
 
 MFMA_BF16_PEAK_TFLOPS = 2500.0
+MFMA_INT8_PEAK_TOPS = 5000.0
 # product launches are bracketed with HIP events one in TIMING_STRIDE (per
 # product): a recorded event stalls the stream for a few microseconds, so
 # timing every launch would slow the timed solves themselves
 TIMING_STRIDE = 8
 
 
-def run_mixed(gk, torch, G, n, p, k, args, sigma_fp64, stream):
-    """The same top-k solve by the blocked split-BF16 path; timed like the FP64 steps."""
+def run_mixed(gk, torch, G, n, p, k, args, sigma_fp64, stream, fmt="bf16"):
+    """The same top-k solve by the blocked path, its products in split BF16 (fmt
+    "bf16", GKL_PREC_MIXED) or exact int8 limbs (fmt "int8", GKL_PREC_MIXED_INT8);
+    timed like the FP64 steps."""
     import numpy as np
     import synth
     b = args.block_width
     v0 = torch.from_numpy(np.ascontiguousarray(
         np.random.default_rng([1, 0x6D6978]).standard_normal((b, p)))).cuda()
-    opts = dict(v0=v0, precision=gk.GKL_PREC_MIXED, block_width=b, timing=TIMING_STRIDE, stream=stream)
+    precision = gk.GKL_PREC_MIXED if fmt == "bf16" else gk.GKL_PREC_MIXED_INT8
+    opts = dict(v0=v0, precision=precision, block_width=b, timing=TIMING_STRIDE, stream=stream)
     sig = torch.empty(k, dtype=torch.float64, device="cuda")
     U = torch.empty((k, n), dtype=torch.float64, device="cuda")
     V = torch.empty((k, p), dtype=torch.float64, device="cuda")
@@ -135,8 +139,16 @@ def run_mixed(gk, torch, G, n, p, k, args, sigma_fp64, stream):
     rmv_n = sum(i.timed_rmatvecs for i in infos)
     last = infos[-1]
     alg_bytes = ((n + 3) // 4) * p + b * (4 * p + 8 * n)
-    exec_flop = 8.0 * n * p * b           # g and m operands, each hi + lo
-    out = {"block_width": b, "tol": tol, "value_s_per_step": step_s,
+    if fmt == "bf16":
+        exec_flop = 8.0 * n * p * b           # g and m operands, each hi + lo
+        peak = MFMA_BF16_PEAK_TFLOPS
+    else:
+        # two operands (codes, missing flags) x limb tiles of 16 columns: 2 tiles
+        # for b <= 8, 3 per 16 columns otherwise; 2 ops per multiply-add
+        tiles = 2 if b <= 8 else 3 * ((b + 15) // 16)
+        exec_flop = 2.0 * 2 * 16 * tiles * n * p
+        peak = MFMA_INT8_PEAK_TOPS
+    out = {"format": fmt, "block_width": b, "tol": tol, "value_s_per_step": step_s,
            "solve_s": float(np.mean([i.solve_ms for i in infos])) / 1e3,
            "create_s": float(np.mean([i.create_ms for i in infos])) / 1e3,
            "converged": int(last.converged), "matvecs": int(last.matvecs),
@@ -150,7 +162,7 @@ def run_mixed(gk, torch, G, n, p, k, args, sigma_fp64, stream):
                      "achieved_GBps": alg_bytes / (avg * 1e-3) / 1e9,
                      "hbm_frac": alg_bytes / (avg * 1e-3) / 1e9 / HBM_PEAK_GBPS,
                      "mfma_executed_TFLOPs": exec_flop / (avg * 1e-3) / 1e12,
-                     "mfma_frac": exec_flop / (avg * 1e-3) / 1e12 / MFMA_BF16_PEAK_TFLOPS}
+                     "mfma_frac": exec_flop / (avg * 1e-3) / 1e12 / peak}
     return out
 
 
@@ -223,7 +235,8 @@ def run_batched(gk, torch, args):
 
 def run_c3(gk, torch, args):
     """50,000 x 500,000 (6.25 GB packed): FP64 GKL (PRO, thick restart m=60) and the
-    blocked split-BF16 solve (block width 8), one solve each after a warmup."""
+    blocked solves (block width 8, split-BF16 and int8-limb products), one solve each
+    after a warmup."""
     import numpy as np
     import synth
     log("[bench] c3: generating 50,000 x 500,000")
@@ -240,7 +253,10 @@ def run_c3(gk, torch, args):
                                  krylov_dim=60, reorth=gk.GKL_REORTH_PARTIAL)),
             ("mixed", 1e-8, dict(v0=torch.from_numpy(np.ascontiguousarray(
                 np.random.default_rng([1, 0x6D6978]).standard_normal((8, p)))).cuda(),
-                precision=gk.GKL_PREC_MIXED, block_width=8, reorth=gk.GKL_REORTH_FULL))):
+                precision=gk.GKL_PREC_MIXED, block_width=8, reorth=gk.GKL_REORTH_FULL)),
+            ("mixed_int8", 1e-8, dict(v0=torch.from_numpy(np.ascontiguousarray(
+                np.random.default_rng([1, 0x6D6978]).standard_normal((8, p)))).cuda(),
+                precision=gk.GKL_PREC_MIXED_INT8, block_width=8, reorth=gk.GKL_REORTH_FULL))):
         reorth = opts.pop("reorth")
         for rep in range(2):
             ctx = gk.Context(G, n, p, k, tol, reorth, timing=TIMING_STRIDE, **opts)
@@ -259,15 +275,16 @@ def run_c3(gk, torch, args):
                       "passes_over_G": int(info.passes_over_G), "restarts": int(info.restarts),
                       "avg_product_ms": [mv, rmv]}
         log(f"[bench] c3 {label}: {dt:.2f} s, {info.matvecs} matvecs")
-    rel = np.abs(res["mixed"] - res["fp64"]) / res["fp64"]
-    out["mixed"]["sigma_max_rel_err_vs_fp64"] = float(rel.max())
-    out["mixed_speedup_vs_fp64"] = out["fp64"]["solve_s"] / out["mixed"]["solve_s"]
+    for key in ("mixed", "mixed_int8"):
+        rel = np.abs(res[key] - res["fp64"]) / res["fp64"]
+        out[key]["sigma_max_rel_err_vs_fp64"] = float(rel.max())
+        out[key + "_speedup_vs_fp64"] = out["fp64"]["solve_s"] / out[key]["solve_s"]
     return out
 
 
 def run_c5(gk, torch, args):
     """100,000 x 1,000,000 (25 GB packed), a pure noise bulk with ten planted spikes at
-    1.5..20 times the bulk edge: the blocked split-BF16 solve (k = 10, b = 8) and the
+    1.5..20 times the bulk edge: the blocked solves (k = 10, b = 8; split-BF16 and int8-limb products) and the
     FP64 solve (PRO, m = 30), each once after nothing else has touched the matrix;
     reports the spike recovery against the planted ratios."""
     import numpy as np
@@ -289,6 +306,8 @@ def run_c5(gk, torch, args):
     res = {}
     for label, tol, opts, reorth in (
             ("mixed", 1e-8, dict(precision=gk.GKL_PREC_MIXED, block_width=8), gk.GKL_REORTH_FULL),
+            ("mixed_int8", 1e-8, dict(precision=gk.GKL_PREC_MIXED_INT8, block_width=8),
+             gk.GKL_REORTH_FULL),
             ("fp64", 1e-10, dict(v0=torch.from_numpy(synth.start_vector(p, 1)).cuda(), krylov_dim=30),
              gk.GKL_REORTH_PARTIAL)):
         log(f"[bench] c5: {label} create")
@@ -315,9 +334,10 @@ def run_c5(gk, torch, args):
                       "sigma_over_edge": (s / edge).tolist(),
                       "sigma_vs_planted_ratio": (s / (ratios * edge) - 1.0).tolist()}
         log(f"[bench] c5 {label}: {dt:.2f} s, {info.matvecs} matvecs, status {st}")
-    rel = np.abs(res["mixed"] - res["fp64"]) / res["fp64"]
-    out["mixed"]["sigma_max_rel_err_vs_fp64"] = float(rel.max())
-    out["mixed_speedup_vs_fp64"] = out["fp64"]["solve_s"] / out["mixed"]["solve_s"]
+    for key in ("mixed", "mixed_int8"):
+        rel = np.abs(res[key] - res["fp64"]) / res["fp64"]
+        out[key]["sigma_max_rel_err_vs_fp64"] = float(rel.max())
+        out[key + "_speedup_vs_fp64"] = out["fp64"]["solve_s"] / out[key]["solve_s"]
     out["outliers_above_1.05_edge"] = int(np.sum(res["fp64"] > 1.05 * edge))
     return out
 
@@ -331,7 +351,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-mixed", action="store_true",
-                    help="skip the blocked split-BF16 solve of the same workload")
+                    help="skip the blocked (split-BF16 and int8-limb) solves of the same workload")
     ap.add_argument("--block-width", type=int, default=8)
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched solve of the 22 chromosome blocks")
@@ -453,6 +473,8 @@ def main():
     }
     if not args.no_mixed:
         line["mixed"] = run_mixed(gk, torch, G, n, p, k, args, sigma.cpu().numpy(), stream)
+        line["mixed_int8"] = run_mixed(gk, torch, G, n, p, k, args, sigma.cpu().numpy(), stream,
+                                       fmt="int8")
     if not args.no_batched:
         line["batched"] = run_batched(gk, torch, args)
     if args.c3:

@@ -65,7 +65,14 @@ typedef enum gkl_status {
 } gkl_status;
 
 enum gkl_reorth { GKL_REORTH_FULL = 0, GKL_REORTH_PARTIAL = 1 };
-enum gkl_precision { GKL_PREC_FP64 = 0, GKL_PREC_MIXED = 1 };
+/* GKL_PREC_FP64: single-vector FP64 GKL.  GKL_PREC_MIXED: blocked GKL whose two
+ * products run on the matrix cores with split-BF16 vector tiles (hi + lo, FP32
+ * accumulation per K chunk, FP64 across chunks); every other quantity FP64.
+ * GKL_PREC_MIXED_INT8: the same blocked GKL with the products on the int8
+ * matrix cores: the vector block is rounded per column to 22-bit integers
+ * (power-of-two column scale) in three 8-bit limbs and accumulated exactly in
+ * int32, so the products' only rounding is that quantisation. */
+enum gkl_precision { GKL_PREC_FP64 = 0, GKL_PREC_MIXED = 1, GKL_PREC_MIXED_INT8 = 2 };
 
 /* Options.  Always initialise with gkl_options_default(). */
 typedef struct gkl_options {
@@ -200,10 +207,12 @@ gkl_status gkl_matvec(gkl_ctx* ctx, const double* v, double* y);
 /* z = A^T u (u: n values, z: p values), FP64. */
 gkl_status gkl_rmatvec(gkl_ctx* ctx, const double* u, double* z);
 /* Y = A W for b columns (W: p x b, Y: n x b, column-major, leading dims p and n),
- * through the split-BF16 MFMA path (W split into bf16 hi + lo, FP32 accumulate per
- * K-chunk, FP64 across chunks, exact FP64 centring and missing-value terms). */
+ * through the matrix-core path of the context's precision (GKL_PREC_MIXED: W
+ * split into bf16 hi + lo, FP32 accumulate per K-chunk, FP64 across chunks;
+ * GKL_PREC_MIXED_INT8: W in exact int8 limbs of a 22-bit per-column fixed point,
+ * int32 accumulation), with FP64 centring and missing-value terms. */
 gkl_status gkl_matmat_mixed(gkl_ctx* ctx, const double* W, int32_t b, double* Y);
-/* Z = A^T X for b columns (X: n x b, Z: p x b), split-BF16 MFMA path. */
+/* Z = A^T X for b columns (X: n x b, Z: p x b), the same matrix-core path. */
 gkl_status gkl_rmatmat_mixed(gkl_ctx* ctx, const double* X, int32_t b, double* Z);
 /* Per-step trace of the last solve, as rows of GKL_TRACE_FIELDS doubles:
  *   step, alpha, beta, reorth_left, reorth_right, restart, max_residual_rel.

@@ -21,6 +21,7 @@ GKL_REORTH_FULL = 0
 GKL_REORTH_PARTIAL = 1
 GKL_PREC_FP64 = 0
 GKL_PREC_MIXED = 1
+GKL_PREC_MIXED_INT8 = 2
 GKL_TRACE_FIELDS = 7
 
 

@@ -36,7 +36,7 @@ struct Problem {
 // ||r|| into *out (no scaling).
 void launch_norm(const double* r, int64_t len, double* out, OrthoWork& w, hipStream_t s);
 
-struct MixedState;   // blocked split-BF16 solver (k_mixed / mixed.hip)
+struct MixedState;   // blocked matrix-core solver (k_mixed / mixed.hip)
 struct BatchState;   // batched persistent solver (batched.hip)
 bool mixed_supported();
 // Message returned by gkl_last_error(NULL) (last failed create on this thread).

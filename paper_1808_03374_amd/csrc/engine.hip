@@ -610,7 +610,8 @@ static gkl_status validate(const uint8_t* G, int64_t n, int64_t p, int32_t k, do
         return set_error(nullptr, GKL_ERR_INVALID, "keep must lie in [k, krylov_dim)");
     if (o->ld_bytes != 0 && o->ld_bytes < (n + 3) / 4)
         return set_error(nullptr, GKL_ERR_INVALID, "ld_bytes < ceil(n/4)");
-    if (o->precision != GKL_PREC_FP64 && o->precision != GKL_PREC_MIXED)
+    if (o->precision != GKL_PREC_FP64 && o->precision != GKL_PREC_MIXED &&
+        o->precision != GKL_PREC_MIXED_INT8)
         return set_error(nullptr, GKL_ERR_INVALID, "unknown precision");
     if (o->block_width < 0 || o->block_width > 32)
         return set_error(nullptr, GKL_ERR_INVALID, "block_width must lie in [0, 32]");
@@ -625,7 +626,8 @@ gkl_status gkl_create_ex(const uint8_t* G, int64_t n, int64_t p, int32_t k, doub
 {
     gkl_status v = validate(G, n, p, k, tol, reorth, o, out);
     if (v != GKL_OK) return v;
-    if (o->precision == GKL_PREC_MIXED && !gkl::mixed_supported())
+    const bool blocked = o->precision != GKL_PREC_FP64;
+    if (blocked && !gkl::mixed_supported())
         return set_error(nullptr, GKL_ERR_UNSUPPORTED, "mixed precision path not built");
     gkl_ctx* ctx = nullptr;
     try {
@@ -638,7 +640,7 @@ gkl_status gkl_create_ex(const uint8_t* G, int64_t n, int64_t p, int32_t k, doub
         ctx->omega = o->pro_omega > 0.0 ? o->pro_omega : 1e-8;
         hipStream_t s = static_cast<hipStream_t>(o->stream);
         const int64_t ld = o->ld_bytes ? o->ld_bytes : (n + 3) / 4;
-        ctx->prob.setup(G, n, p, ld, s, o->precision != GKL_PREC_MIXED);
+        ctx->prob.setup(G, n, p, ld, s, !blocked);
         ctx->root_maxdim = sqrt((double)std::max(n, p));
         ctx->noise_scale = 2.220446049250313e-16 * ctx->root_maxdim;
         ctx->krylov = o->krylov_dim;
@@ -653,7 +655,7 @@ gkl_status gkl_create_ex(const uint8_t* G, int64_t n, int64_t p, int32_t k, doub
             ctx->keep = 0;
         }
         if (ctx->maxm < k) fail(GKL_ERR_INVALID, "basis smaller than k");
-        if (o->precision == GKL_PREC_MIXED) ctx->setup_mixed();
+        if (blocked) ctx->setup_mixed();
         else ctx->allocate_solver();
         GKL_HIP(hipStreamSynchronize(s));
         ctx->create_ms =
@@ -684,7 +686,7 @@ gkl_status gkl_solve(gkl_ctx* ctx, double* sigma, double* U, int64_t ldu, double
         auto t0 = std::chrono::steady_clock::now();
         ctx->info = gkl_info{};
         ctx->trace.clear();
-        gkl_status st = ctx->opt.precision == GKL_PREC_MIXED
+        gkl_status st = ctx->opt.precision != GKL_PREC_FP64
                             ? ctx->solve_mixed(sigma, U, ldu, V, ldv)
                             : ctx->solve_fp64(sigma, U, ldu, V, ldv);
         GKL_HIP(hipStreamSynchronize(ctx->prob.stream));

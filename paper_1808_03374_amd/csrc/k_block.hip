@@ -3,7 +3,7 @@
 // Block Lanczos (named as future work in Section 5 of the paper) keeps the
 // recurrence scalars, the Gram-Schmidt reorthogonalisation and the projected
 // matrix in FP64; only the two products with the genotype matrix use the
-// split-BF16 MFMA path.  This file holds the FP64 pieces:
+// matrix-core path (split BF16 or int8 limbs).  This file holds the FP64 pieces:
 //   * H = Q^T Y for tall Q (len x q) and Y (len x b) on the FP64 matrix cores:
 //     one partial per workgroup, summed in a fixed order by a second kernel;
 //   * Out -= Q H and Out = Q H (also in place, for Y <- Y R^-1), FP64 MFMA;

@@ -1,48 +1,65 @@
-// Blocked products A W and A^T X on the int8 matrix cores (gfx950).
+// Blocked products A W and A^T X on the matrix cores (gfx950).
 //
 // Section 5 of the paper names block Lanczos (many vectors per pass, BLAS3) as
 // the next step; with b vectors per pass the product becomes a dense contraction
-// and runs on the matrix cores.
+// and runs on the matrix cores.  Two operand formats are built; both keep the
+// genotypes exact and differ in how the FP64 vector block is carried.
 //
-// Exact operands, exact accumulation.  The A operand is the raw 2-bit code
-// (0, 1, 2, and 3 for missing) as an int8, and a second operand is the missing
-// flag m (0 or 1); neither needs a table: for one 32-bit word of 16 codes,
-// (w >> 2i) & 0x03030303 puts codes i, 4+i, 8+i, 12+i into the four bytes of
-// operand dword i (two operations per four codes).  The vector block is scaled
-// per column by a power of two, rounded to integers q (|q| <= 2^22) and split
-// into three balanced 8-bit limbs, q = l0 2^16 + l1 2^8 + l2, each an int8 B
-// operand.  v_mfma_i32_16x16x64_i8 accumulates in int32 without rounding
-// (|code x limb| + |flag x limb| <= 512 per contraction index, so a K range of
-// up to 4 10^6 cannot overflow), the limbs are recombined exactly, and the
-// partials of the K splits are exact integers below 2^53 in FP64, so the only
-// rounding is the per-column quantisation (half a unit of 2^-22 times the
-// column's scale, which is below twice its largest entry) and the final
-// scaling.  Because code 3 counts as 3 in sum_j c_ij v_j, the missing operand
-// carries the correction (mu_j - 3) instead of mu_j:
+//   A W   (contract over SNPs, layout I: row = individual)
+//   A^T X (contract over individuals, layout S: row = SNP)
 //
-//   A W   (contract over SNPs, layout I: row = individual):
-//     sum_j A_ij W_jc = sum_j c_ij W'_jc + sum_j m_ij Z'_jc - K2_c
-//     W' = s W, Z' = (mu - 3) s W, K2_c = sum_j mu_j W'_jc
-//     (W' and Z' share one scale per column, so both products accumulate
-//     together)
-//   A^T X (contract over individuals, layout S: row = SNP):
+// Split BF16 (GKL_PREC_MIXED).  Genotype codes are decoded in registers to two
+// exact BF16 operands: g (0, 1, 2; 0 for missing) and the missing indicator m
+// (0 or 1).  Two codes of a 32-bit word form one pair word: a shift and a mask
+// isolate them, one 24-bit multiply-add turns them into a byte selector, and
+// v_perm_b32 reads both BF16 values from an 8-byte table held in two constants.
+// The vector block is split into BF16 hi + lo (hi = bf16(w), lo = bf16(w - hi)),
+// multiplied with v_mfma_f32_16x16x32_bf16, accumulated in FP32 per K-chunk and
+// in FP64 across chunks and splits.
+//     sum_j A_ij W_jc = sum_j g_ij W'_jc + sum_j m_ij X'_jc - K2_c,
+//       W' = s W, X' = mu s W, K2_c = sum_j mu_j W'_jc
+//     sum_i A_ij X_ic = s_j ( sum_i g_ij X_ic - mu_j T_c + mu_j sum_i m_ij X_ic )
+//   MFMA layout: A lane l holds row l%16, B lane l column l%16, both with the K
+//   slice selected by (l/16, element); C lane l element e is row 4*(l/16)+e,
+//   column l%16.  Element e of K step h is code 4h + (e>>1) + 8(e&1) of the
+//   lane's word, and the fragments are written in the same order.
+//
+// Int8 limbs (GKL_PREC_MIXED_INT8).  The A operand is the raw 2-bit code (0, 1,
+// 2, and 3 for missing) as an int8, the second operand the missing flag;
+// (w >> 2i) & 0x03030303 puts codes i, 4+i, 8+i, 12+i of a word into the bytes
+// of operand dword i (no table, two operations per four codes).  The vector
+// block is scaled per column by a power of two, rounded to integers q (|q| <=
+// 2^22) and split into three balanced 8-bit limbs, q = l0 2^16 + l1 2^8 + l2.
+// v_mfma_i32_16x16x64_i8 accumulates in int32 without rounding (|code x limb|
+// + |flag x limb| <= 512 per contraction index, so a K range of up to 4 10^6
+// cannot overflow), the limbs are recombined exactly and the K-split partials
+// are exact integers below 2^53 in FP64: the only rounding is the per-column
+// quantisation (half a unit of 2^-22 times the column's scale, which is below
+// twice its largest entry) and the final scaling.  Code 3 counts as 3 in
+// sum_j c_ij v_j, so the missing operand carries (mu_j - 3) instead of mu_j:
+//     sum_j A_ij W_jc = sum_j c_ij W'_jc + sum_j m_ij Z'_jc - K2_c,
+//       Z' = (mu - 3) s W  (W' and Z' share one scale per column)
 //     sum_i A_ij X_ic = s_j ( sum_i c_ij X_ic + (mu_j - 3) sum_i m_ij X_ic - mu_j T_c )
-//     T_c = sum_i X_ic
-//
-// MFMA v_mfma_i32_16x16x64_i8 (probe-confirmed): A lane l holds row l%16 and
-// B lane l column l%16, byte e of both pairing in the contraction index with
-// byte e of the other operand in lane group l/16; C lane l element e is row
-// 4*(l/16)+e, column l%16.  Byte e of a lane's operand is code
-// 4 (e & 3) + (e >> 2) of its word, and the vector fragments are written in
-// the same order.  The three limbs of a column sit in three column tiles at the
-// same lane, so they recombine without data movement.
+//   MFMA layout (v_mfma_i32_16x16x64_i8, probe-confirmed): byte e of A lane l
+//   pairs with byte e of B in lane group l/16; byte e of a lane's operand is
+//   code 4 (e & 3) + (e >> 2) of its word.  The limbs of a column sit at the
+//   same lane in different column tiles (or, for up to 8 columns, limbs 0 and 1
+//   share a tile 8 lanes apart), so they recombine with no or one lane shift.
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace gkl {
 
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 
 namespace {
+constexpr int kKSteps = 256 / 32;      // split BF16: MFMA K steps per super-tile
+constexpr int kRTw = 8;                // split BF16, A W: row tiles per wave
+constexpr int kRTr = 4;                // split BF16, A^T X: row tiles per wave
+constexpr int kFlush = 4;              // split BF16: super-tiles per FP32 chunk
 constexpr int kSuper = 256;            // K per super-tile (64 bytes of codes per row)
 constexpr int kWords = kSuper / 64;    // MFMA K steps per super-tile (one code word per lane)
 constexpr int kQBits = 22;             // |q| <= 2^kQBits (so |l0| <= 65 fits int8)
@@ -144,7 +161,7 @@ void build_mixed_layouts(const uint8_t* G, int64_t n, int64_t p, int64_t ld, uin
 }
 
 // ---------------------------------------------------------------------------
-// Operands
+// Int8 limbs: operands
 // ---------------------------------------------------------------------------
 // The 16 codes of a word as int8: dword i holds codes i, 4+i, 8+i, 12+i.
 __device__ __forceinline__ i32x4 raw_codes(uint32_t w)
@@ -195,6 +212,86 @@ __device__ __forceinline__ void put_byte(i32x4& v, int e, int x)
 __device__ __forceinline__ i32x4 mfma_i8(i32x4 a, i32x4 b, i32x4 c)
 {
     return __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// Split BF16: decode 16 codes of a word -> 8 pair words of each pattern
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void decode16(uint32_t d, uint32_t C[8], uint32_t M[8])
+{
+    // table bytes {S0:S1} = [lo(c=0), hi(c=0), lo(1), hi(1), lo(2), hi(2), lo(3), hi(3)]
+    constexpr uint32_t kG1 = 0x3F800000u, kG0 = 0x00004000u;   // g: 0, 1.0, 2.0, 0
+    constexpr uint32_t kM1 = 0x00000000u, kM0 = 0x3F800000u;   // m: 0, 0, 0, 1.0
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const uint32_t u = (d >> (2 * k)) & 0x00030003u;        // code k (byte 0), k+8 (byte 2)
+        const uint32_t sel = u * 0x0202u + 0x01000100u;        // [2c, 2c+1, 2c', 2c'+1]
+        C[k] = __builtin_amdgcn_perm(kG0, kG1, sel);
+        M[k] = __builtin_amdgcn_perm(kM0, kM1, sel);
+    }
+}
+
+__device__ __forceinline__ bf16x8 pack4(uint32_t a, uint32_t b, uint32_t c, uint32_t d)
+{
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    u32x4 v = {a, b, c, d};
+    return __builtin_bit_cast(bf16x8, v);
+}
+
+// position (within the lane's 16-code word) of element e of K step h
+__host__ __device__ __forceinline__ int code_pos(int h, int e) { return 4 * h + (e >> 1) + 8 * (e & 1); }
+
+__device__ __forceinline__ __bf16 to_bf16(double v) { return (__bf16)(float)v; }
+
+// ---------------------------------------------------------------------------
+// Vector fragments
+// ---------------------------------------------------------------------------
+// A W operands.  kPack == false: frag[((st*8 + t)*4 + op)*64 + lane][e], ops
+// 0..3 = W'hi, W'lo, X'hi, X'lo for the 16 columns starting at col0.
+// kPack == true (b <= 8): two operands whose 16 columns hold the hi parts of the
+// b columns in 0..7 and their lo parts in 8..15: op 0 = [W'hi | W'lo], op 1 =
+// [X'hi | X'lo]; one MFMA per operand then covers both halves of the split.
+template <bool kPack>
+__global__ void split_W_kernel(const double* __restrict__ W, int64_t ldw, int b, int col0,
+                               int64_t p, const double* __restrict__ mean,
+                               const double* __restrict__ inv_sd, int64_t nst,
+                               bf16x8* __restrict__ frag)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // (st, ks, lane)
+    if (t >= nst * kKSteps * 64) return;
+    const int lane = (int)(t & 63);
+    const int ks = (int)((t >> 6) % kKSteps);
+    const int64_t st = t / (64 * kKSteps);
+    const int g = lane >> 4;
+    const int col = kPack ? (lane & 7) : col0 + (lane & 15);
+    const bool hi_half = !kPack || (lane & 15) < 8;
+    bf16x8 whi, wlo, zhi, zlo;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int64_t j = st * kSuper + 64 * g + 16 * (ks >> 1) + code_pos(ks & 1, e);
+        double w = 0.0, z = 0.0;
+        if (j < p && col < b) {
+            w = inv_sd[j] * W[(int64_t)col * ldw + j];
+            z = mean[j] * w;
+        }
+        const __bf16 h1 = to_bf16(w), h2 = to_bf16(z);
+        const __bf16 l1 = to_bf16(w - (double)(float)h1), l2 = to_bf16(z - (double)(float)h2);
+        whi[e] = hi_half ? h1 : l1;
+        zhi[e] = hi_half ? h2 : l2;
+        wlo[e] = l1;
+        zlo[e] = l2;
+    }
+    if (kPack) {
+        bf16x8* f = frag + (((st * kKSteps + ks) * 2) * 64) + lane;
+        f[0 * 64] = whi;
+        f[1 * 64] = zhi;
+    } else {
+        bf16x8* f = frag + (((st * kKSteps + ks) * 4) * 64) + lane;
+        f[0 * 64] = whi;
+        f[1 * 64] = wlo;
+        f[2 * 64] = zhi;
+        f[3 * 64] = zlo;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -276,6 +373,272 @@ __device__ __forceinline__ void column_scales(const double* __restrict__ cmax, i
     __syncthreads();
 }
 
+// A^T X operands.  kPack == false: frag[((st*8 + t)*2 + op)*64 + lane][e], ops
+// 0..1 = Xhi, Xlo.  kPack == true (b <= 8): one operand [Xhi | Xlo] (hi parts in
+// columns 0..7, lo parts in 8..15), frag[(st*8 + t)*64 + lane].
+template <bool kPack>
+__global__ void split_X_kernel(const double* __restrict__ X, int64_t ldx, int b, int col0,
+                               int64_t n, int64_t nst, bf16x8* __restrict__ frag)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nst * kKSteps * 64) return;
+    const int lane = (int)(t & 63);
+    const int ks = (int)((t >> 6) % kKSteps);
+    const int64_t st = t / (64 * kKSteps);
+    const int g = lane >> 4;
+    const int col = kPack ? (lane & 7) : col0 + (lane & 15);
+    const bool hi_half = !kPack || (lane & 15) < 8;
+    bf16x8 xhi, xlo;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int64_t i = st * kSuper + 64 * g + 16 * (ks >> 1) + code_pos(ks & 1, e);
+        double x = 0.0;
+        if (i < n && col < b) x = X[(int64_t)col * ldx + i];
+        const __bf16 h = to_bf16(x);
+        const __bf16 l = to_bf16(x - (double)(float)h);
+        xhi[e] = hi_half ? h : l;
+        xlo[e] = l;
+    }
+    if (kPack) {
+        frag[(st * kKSteps + ks) * 64 + lane] = xhi;
+    } else {
+        bf16x8* f = frag + (((st * kKSteps + ks) * 2) * 64) + lane;
+        f[0] = xhi;
+        f[64] = xlo;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// A W main kernel: block = 4 waves x 8 row tiles x 16 rows = 512 rows, K split in
+// super-tiles; partial[split][row][16] FP64.
+// ---------------------------------------------------------------------------
+template <bool kPack>
+__global__ void __launch_bounds__(256)
+matmat_bf16_kernel(const uint8_t* __restrict__ I, int64_t ldI, int64_t nI,
+                   const bf16x8* __restrict__ frag, int64_t nst, int64_t st_per_split,
+                   double* __restrict__ partial)
+{
+    constexpr int kOps = kPack ? 2 : 4;
+    __shared__ bf16x8 bs[kKSteps * kOps * 64];      // one super-tile of the operands
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int g = lane >> 4, r = lane & 15;
+    const int64_t row_base = (int64_t)blockIdx.x * (kMxWaves * kRTw * 16) + wave * (kRTw * 16);
+    const int64_t st0 = (int64_t)blockIdx.y * st_per_split;
+    const int64_t st1 = st0 + st_per_split < nst ? st0 + st_per_split : nst;
+    f32x4 acc[kRTw];
+    double accd[kRTw][4];
+#pragma unroll
+    for (int t = 0; t < kRTw; ++t) {
+        acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) accd[t][e] = 0.0;
+    }
+    int chunk = 0;
+    for (int64_t st = st0; st < st1; ++st) {
+        uint4 a[kRTw];
+#pragma unroll
+        for (int t = 0; t < kRTw; ++t)
+            a[t] = *reinterpret_cast<const uint4*>(I + tiled_offset(row_base + 16 * t + r, st * 64 + 16 * g, ldI));
+        const bf16x8* src = frag + st * (kKSteps * kOps * 64);
+        for (int q = threadIdx.x; q < kKSteps * kOps * 64; q += 256) bs[q] = src[q];
+        __syncthreads();
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            bf16x8 bw0[2], bw1[2], bz0[2], bz1[2];   // W'hi, W'lo, X'hi, X'lo (packed: 0 only)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int ks = 2 * w + h;
+                if (kPack) {
+                    bw0[h] = bs[(ks * 2 + 0) * 64 + lane];
+                    bz0[h] = bs[(ks * 2 + 1) * 64 + lane];
+                } else {
+                    bw0[h] = bs[(ks * 4 + 0) * 64 + lane];
+                    bw1[h] = bs[(ks * 4 + 1) * 64 + lane];
+                    bz0[h] = bs[(ks * 4 + 2) * 64 + lane];
+                    bz1[h] = bs[(ks * 4 + 3) * 64 + lane];
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < kRTw; ++t) {
+                const uint32_t d = w == 0 ? a[t].x : w == 1 ? a[t].y : w == 2 ? a[t].z : a[t].w;
+                uint32_t C[8], M[8];
+                decode16(d, C, M);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const bf16x8 ca = pack4(C[4 * h], C[4 * h + 1], C[4 * h + 2], C[4 * h + 3]);
+                    const bf16x8 ma = pack4(M[4 * h], M[4 * h + 1], M[4 * h + 2], M[4 * h + 3]);
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ca, bw0[h], acc[t], 0, 0, 0);
+                    if (!kPack)
+                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ca, bw1[h], acc[t], 0, 0, 0);
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ma, bz0[h], acc[t], 0, 0, 0);
+                    if (!kPack)
+                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ma, bz1[h], acc[t], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+        if (++chunk == kFlush) {
+            chunk = 0;
+#pragma unroll
+            for (int t = 0; t < kRTw; ++t) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) accd[t][e] += (double)acc[t][e];
+                acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+            }
+        }
+    }
+    double* out = partial + (int64_t)blockIdx.y * nI * 16;
+#pragma unroll
+    for (int t = 0; t < kRTw; ++t) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t row = row_base + 16 * t + 4 * g + e;
+            out[row * 16 + r] = accd[t][e] + (double)acc[t][e];
+        }
+    }
+}
+
+// Y[i + c*ldy] = sum_split partial - K2_c for i < n, c < nb (col0 offset); packed:
+// the hi (column c) and lo (column c + 8) partials of each split are added first.
+template <bool kPack>
+__global__ void __launch_bounds__(256)
+matmat_reduce_kernel(const double* __restrict__ partial, int nsplit, int64_t nI, int64_t n,
+                     int nb, const double* __restrict__ cpart, double* __restrict__ Y,
+                     int64_t ldy)
+{
+    __shared__ double K2[16];
+    column_sums(cpart, nb, K2);
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * 16) return;
+    const int64_t i = t >> 4;
+    const int c = (int)(t & 15);
+    if (c >= nb) return;
+    double s = 0.0;
+    for (int sp = 0; sp < nsplit; ++sp) {
+        const double* pr = partial + ((int64_t)sp * nI + i) * 16;
+        s += kPack ? pr[c] + pr[c + 8] : pr[c];
+    }
+    Y[(int64_t)c * ldy + i] = s - K2[c];
+}
+
+// ---------------------------------------------------------------------------
+// A^T X main kernel: block = 4 waves x 4 SNP tiles x 16 = 256 SNPs; K = individuals.
+// partial[split][2][row][16]: sums with the code operand and the missing operand.
+// ---------------------------------------------------------------------------
+template <bool kPack>
+__global__ void __launch_bounds__(256)
+rmatmat_bf16_kernel(const uint8_t* __restrict__ S, int64_t ldS, int64_t pS,
+                    const bf16x8* __restrict__ frag, int64_t nst, int64_t st_per_split,
+                    double* __restrict__ partial)
+{
+    constexpr int kOps = kPack ? 1 : 2;
+    __shared__ bf16x8 bs[kKSteps * kOps * 64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int g = lane >> 4, r = lane & 15;
+    const int64_t row_base = (int64_t)blockIdx.x * (kMxWaves * kRTr * 16) + wave * (kRTr * 16);
+    const int64_t st0 = (int64_t)blockIdx.y * st_per_split;
+    const int64_t st1 = st0 + st_per_split < nst ? st0 + st_per_split : nst;
+    f32x4 accC[kRTr], accM[kRTr];
+    double dC[kRTr][4], dM[kRTr][4];
+#pragma unroll
+    for (int t = 0; t < kRTr; ++t) {
+        accC[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+        accM[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) { dC[t][e] = 0.0; dM[t][e] = 0.0; }
+    }
+    int chunk = 0;
+    for (int64_t st = st0; st < st1; ++st) {
+        uint4 a[kRTr];
+#pragma unroll
+        for (int t = 0; t < kRTr; ++t)
+            a[t] = *reinterpret_cast<const uint4*>(S + tiled_offset(row_base + 16 * t + r, st * 64 + 16 * g, ldS));
+        const bf16x8* src = frag + st * (kKSteps * kOps * 64);
+        for (int q = threadIdx.x; q < kKSteps * kOps * 64; q += 256) bs[q] = src[q];
+        __syncthreads();
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            bf16x8 x0[2], x1[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int ks = 2 * w + h;
+                if (kPack) {
+                    x0[h] = bs[ks * 64 + lane];
+                } else {
+                    x0[h] = bs[(ks * 2 + 0) * 64 + lane];
+                    x1[h] = bs[(ks * 2 + 1) * 64 + lane];
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < kRTr; ++t) {
+                const uint32_t d = w == 0 ? a[t].x : w == 1 ? a[t].y : w == 2 ? a[t].z : a[t].w;
+                uint32_t C[8], M[8];
+                decode16(d, C, M);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const bf16x8 ca = pack4(C[4 * h], C[4 * h + 1], C[4 * h + 2], C[4 * h + 3]);
+                    const bf16x8 ma = pack4(M[4 * h], M[4 * h + 1], M[4 * h + 2], M[4 * h + 3]);
+                    accC[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ca, x0[h], accC[t], 0, 0, 0);
+                    if (!kPack)
+                        accC[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ca, x1[h], accC[t], 0, 0, 0);
+                    accM[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ma, x0[h], accM[t], 0, 0, 0);
+                    if (!kPack)
+                        accM[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ma, x1[h], accM[t], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+        if (++chunk == kFlush) {
+            chunk = 0;
+#pragma unroll
+            for (int t = 0; t < kRTr; ++t) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    dC[t][e] += (double)accC[t][e];
+                    dM[t][e] += (double)accM[t][e];
+                }
+                accC[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+                accM[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+            }
+        }
+    }
+    double* out = partial + (int64_t)blockIdx.y * 2 * pS * 16;
+#pragma unroll
+    for (int t = 0; t < kRTr; ++t) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t row = row_base + 16 * t + 4 * g + e;
+            out[row * 16 + r] = dC[t][e] + (double)accC[t][e];
+            out[(pS + row) * 16 + r] = dM[t][e] + (double)accM[t][e];
+        }
+    }
+}
+
+// Z[j + c*ldz] = s_j ( SG - mu_j T_c + mu_j SM )
+template <bool kPack>
+__global__ void __launch_bounds__(256)
+rmatmat_reduce_kernel(const double* __restrict__ partial, int nsplit, int64_t pS, int64_t p,
+                      int nb, const double* __restrict__ cpart, const double* __restrict__ mean,
+                      const double* __restrict__ inv_sd, double* __restrict__ Z, int64_t ldz)
+{
+    __shared__ double T[16];
+    column_sums(cpart, nb, T);
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= p * 16) return;
+    const int64_t j = t >> 4;
+    const int c = (int)(t & 15);
+    if (c >= nb) return;
+    double sc = 0.0, sm = 0.0;
+    for (int sp = 0; sp < nsplit; ++sp) {
+        const double* pc = partial + ((int64_t)sp * 2 * pS + j) * 16;
+        const double* pm = partial + ((int64_t)sp * 2 * pS + pS + j) * 16;
+        sc += kPack ? pc[c] + pc[c + 8] : pc[c];
+        sm += kPack ? pm[c] + pm[c + 8] : pm[c];
+    }
+    const double mu = mean[j];
+    Z[(int64_t)c * ldz + j] = inv_sd[j] * (sc - mu * T[c] + mu * sm);
+}
+
 // ---------------------------------------------------------------------------
 // Vector fragments
 // ---------------------------------------------------------------------------
@@ -294,7 +657,7 @@ __device__ __forceinline__ int limb_for(int tile, int col, int l0, int l1, int l
 // Byte e holds SNP st*256 + 64 (lane >> 4) + 16 word + code_of_elem(e).
 template <bool kPack>
 __global__ void __launch_bounds__(256)
-split_W_kernel(const double* __restrict__ W, int64_t ldw, int nb, int64_t p,
+split_W_i8_kernel(const double* __restrict__ W, int64_t ldw, int nb, int64_t p,
                const double* __restrict__ mean, const double* __restrict__ inv_sd,
                const double* __restrict__ cmax, int64_t nst, i32x4* __restrict__ frag)
 {
@@ -340,7 +703,7 @@ split_W_kernel(const double* __restrict__ W, int64_t ldw, int nb, int64_t p,
 // X; byte e holds individual st*256 + 64 (lane >> 4) + 16 word + code_of_elem(e).
 template <bool kPack>
 __global__ void __launch_bounds__(256)
-split_X_kernel(const double* __restrict__ X, int64_t ldx, int nb, int64_t n,
+split_X_i8_kernel(const double* __restrict__ X, int64_t ldx, int nb, int64_t n,
                const double* __restrict__ cmax, int64_t nst, i32x4* __restrict__ frag)
 {
     constexpr int T = tiles<kPack>();
@@ -450,7 +813,7 @@ matmat_i8_kernel(const uint8_t* __restrict__ I, int64_t ldI, int64_t nI,
 // Y[i + c*ldy] = 2^(ex_c - 22) sum_split partial - K2_c for i < n, c < nb (col0
 // offset).  The split sums are exact (integers below 2^53).
 __global__ void __launch_bounds__(256)
-matmat_reduce_kernel(const double* __restrict__ partial, int nsplit, int64_t nI, int64_t n,
+matmat_i8_reduce_kernel(const double* __restrict__ partial, int nsplit, int64_t nI, int64_t n,
                      int nb, const double* __restrict__ cpart, const double* __restrict__ cmax,
                      double* __restrict__ Y, int64_t ldy)
 {
@@ -538,7 +901,7 @@ rmatmat_i8_kernel(const uint8_t* __restrict__ S, int64_t ldS, int64_t pS,
 
 // Z[j + c*ldz] = s_j ( 2^(ex_c - 22) (SC + (mu_j - 3) SM) - mu_j T_c )
 __global__ void __launch_bounds__(256)
-rmatmat_reduce_kernel(const double* __restrict__ partial, int nsplit, int64_t pS, int64_t p,
+rmatmat_i8_reduce_kernel(const double* __restrict__ partial, int nsplit, int64_t pS, int64_t p,
                       int nb, const double* __restrict__ cpart, const double* __restrict__ cmax,
                       const double* __restrict__ mean, const double* __restrict__ inv_sd,
                       double* __restrict__ Z, int64_t ldz)
@@ -596,9 +959,13 @@ MixedShape mixed_shape(int64_t n, int64_t p)
 
 size_t mixed_frag_bytes(const MixedShape& m)
 {
-    const size_t a = (size_t)m.nstW * kWords * 2 * tiles<false>() * 64 * sizeof(i32x4);
-    const size_t b = (size_t)m.nstX * kWords * tiles<false>() * 64 * sizeof(i32x4);
-    return a > b ? a : b;
+    // the larger of the two formats: split BF16 (4 operands per K step of 32) and
+    // int8 limbs (6 operands per K step of 64)
+    const size_t a = (size_t)m.nstW * kKSteps * 4 * 64 * sizeof(bf16x8);
+    const size_t b = (size_t)m.nstX * kKSteps * 2 * 64 * sizeof(bf16x8);
+    const size_t c = (size_t)m.nstW * kWords * 2 * tiles<false>() * 64 * sizeof(i32x4);
+    const size_t d = (size_t)m.nstX * kWords * tiles<false>() * 64 * sizeof(i32x4);
+    return std::max(std::max(a, b), std::max(c, d));
 }
 
 size_t mixed_partial_elems(const MixedShape& m)
@@ -608,9 +975,84 @@ size_t mixed_partial_elems(const MixedShape& m)
     return a > b ? a : b;
 }
 
-void launch_matmat_mixed(const MixedShape& m, const uint8_t* I, const ColStats& st,
-                         const double* W, int64_t ldw, int b, double* Y, int64_t ldy,
-                         MixedWork& w, hipStream_t s)
+static void matmat_bf16(const MixedShape& m, const uint8_t* I, const ColStats& st, const double* W,
+                        int64_t ldw, int b, double* Y, int64_t ldy, MixedWork& w, hipStream_t s)
+{
+    const bool pack = b <= 8;
+    for (int col0 = 0; col0 < b; col0 += 16) {
+        const int nb = b - col0 < 16 ? b - col0 : 16;
+        const int64_t nthr = m.nstW * kKSteps * 64;
+        const dim3 gsplit(ceil_div(nthr, 256));
+        if (pack)
+            hipLaunchKernelGGL(split_W_kernel<true>, gsplit, dim3(256), 0, s, W, ldw, b, col0, m.p,
+                               st.mean, st.inv_sd, m.nstW, reinterpret_cast<bf16x8*>(w.frag));
+        else
+            hipLaunchKernelGGL(split_W_kernel<false>, gsplit, dim3(256), 0, s, W, ldw, b, col0, m.p,
+                               st.mean, st.inv_sd, m.nstW, reinterpret_cast<bf16x8*>(w.frag));
+        GKL_LAUNCH_CHECK("split_W_kernel");
+        hipLaunchKernelGGL(colsum_kernel, dim3(kCsSplit, nb), dim3(256), 0, s,
+                           W + (int64_t)col0 * ldw, ldw, m.p, st.mean, st.inv_sd, w.cpart, w.cmax);
+        GKL_LAUNCH_CHECK("colsum_kernel");
+        dim3 grid((unsigned int)(m.nI / (kMxWaves * kRTw * 16)), (unsigned int)m.splitW);
+        if (pack)
+            hipLaunchKernelGGL(matmat_bf16_kernel<true>, grid, dim3(256), 0, s, I, m.ldI, m.nI,
+                               reinterpret_cast<const bf16x8*>(w.frag), m.nstW, m.stW, w.partial);
+        else
+            hipLaunchKernelGGL(matmat_bf16_kernel<false>, grid, dim3(256), 0, s, I, m.ldI, m.nI,
+                               reinterpret_cast<const bf16x8*>(w.frag), m.nstW, m.stW, w.partial);
+        GKL_LAUNCH_CHECK("matmat_bf16_kernel");
+        const dim3 gred(ceil_div(m.n * 16, 256));
+        if (pack)
+            hipLaunchKernelGGL(matmat_reduce_kernel<true>, gred, dim3(256), 0, s, w.partial,
+                               m.splitW, m.nI, m.n, nb, w.cpart, Y + (int64_t)col0 * ldy, ldy);
+        else
+            hipLaunchKernelGGL(matmat_reduce_kernel<false>, gred, dim3(256), 0, s, w.partial,
+                               m.splitW, m.nI, m.n, nb, w.cpart, Y + (int64_t)col0 * ldy, ldy);
+        GKL_LAUNCH_CHECK("matmat_reduce_kernel");
+    }
+}
+
+static void rmatmat_bf16(const MixedShape& m, const uint8_t* S, const ColStats& st, const double* X,
+                         int64_t ldx, int b, double* Z, int64_t ldz, MixedWork& w, hipStream_t s)
+{
+    const bool pack = b <= 8;
+    for (int col0 = 0; col0 < b; col0 += 16) {
+        const int nb = b - col0 < 16 ? b - col0 : 16;
+        const int64_t nthr = m.nstX * kKSteps * 64;
+        const dim3 gsplit(ceil_div(nthr, 256));
+        if (pack)
+            hipLaunchKernelGGL(split_X_kernel<true>, gsplit, dim3(256), 0, s, X, ldx, b, col0, m.n,
+                               m.nstX, reinterpret_cast<bf16x8*>(w.frag));
+        else
+            hipLaunchKernelGGL(split_X_kernel<false>, gsplit, dim3(256), 0, s, X, ldx, b, col0, m.n,
+                               m.nstX, reinterpret_cast<bf16x8*>(w.frag));
+        GKL_LAUNCH_CHECK("split_X_kernel");
+        hipLaunchKernelGGL(colsum_kernel, dim3(kCsSplit, nb), dim3(256), 0, s,
+                           X + (int64_t)col0 * ldx, ldx, m.n, nullptr, nullptr, w.cpart, w.cmax);
+        GKL_LAUNCH_CHECK("colsum_kernel");
+        dim3 grid((unsigned int)(m.pS / (kMxWaves * kRTr * 16)), (unsigned int)m.splitX);
+        if (pack)
+            hipLaunchKernelGGL(rmatmat_bf16_kernel<true>, grid, dim3(256), 0, s, S, m.ldS, m.pS,
+                               reinterpret_cast<const bf16x8*>(w.frag), m.nstX, m.stX, w.partial);
+        else
+            hipLaunchKernelGGL(rmatmat_bf16_kernel<false>, grid, dim3(256), 0, s, S, m.ldS, m.pS,
+                               reinterpret_cast<const bf16x8*>(w.frag), m.nstX, m.stX, w.partial);
+        GKL_LAUNCH_CHECK("rmatmat_bf16_kernel");
+        const dim3 gred(ceil_div(m.p * 16, 256));
+        if (pack)
+            hipLaunchKernelGGL(rmatmat_reduce_kernel<true>, gred, dim3(256), 0, s, w.partial,
+                               m.splitX, m.pS, m.p, nb, w.cpart, st.mean, st.inv_sd,
+                               Z + (int64_t)col0 * ldz, ldz);
+        else
+            hipLaunchKernelGGL(rmatmat_reduce_kernel<false>, gred, dim3(256), 0, s, w.partial,
+                               m.splitX, m.pS, m.p, nb, w.cpart, st.mean, st.inv_sd,
+                               Z + (int64_t)col0 * ldz, ldz);
+        GKL_LAUNCH_CHECK("rmatmat_reduce_kernel");
+    }
+}
+
+static void matmat_i8(const MixedShape& m, const uint8_t* I, const ColStats& st, const double* W,
+                      int64_t ldw, int b, double* Y, int64_t ldy, MixedWork& w, hipStream_t s)
 {
     for (int col0 = 0; col0 < b; col0 += 16) {
         const int nb = b - col0 < 16 ? b - col0 : 16;
@@ -624,29 +1066,28 @@ void launch_matmat_mixed(const MixedShape& m, const uint8_t* I, const ColStats& 
         dim3 grid((unsigned int)(m.nI / rows), (unsigned int)m.splitW);
         i32x4* frag = reinterpret_cast<i32x4*>(w.frag);
         if (nb <= 8) {
-            hipLaunchKernelGGL(split_W_kernel<true>, gsplit, dim3(256), 0, s, Wc, ldw, nb, m.p,
+            hipLaunchKernelGGL(split_W_i8_kernel<true>, gsplit, dim3(256), 0, s, Wc, ldw, nb, m.p,
                                st.mean, st.inv_sd, w.cmax, m.nstW, frag);
-            GKL_LAUNCH_CHECK("split_W_kernel");
+            GKL_LAUNCH_CHECK("split_W_i8_kernel");
             hipLaunchKernelGGL(matmat_i8_kernel<true>, grid, dim3(256), 0, s, I, m.ldI, m.nI, frag,
                                m.nstW, m.stW, w.partial);
         } else {
-            hipLaunchKernelGGL(split_W_kernel<false>, gsplit, dim3(256), 0, s, Wc, ldw, nb, m.p,
+            hipLaunchKernelGGL(split_W_i8_kernel<false>, gsplit, dim3(256), 0, s, Wc, ldw, nb, m.p,
                                st.mean, st.inv_sd, w.cmax, m.nstW, frag);
-            GKL_LAUNCH_CHECK("split_W_kernel");
+            GKL_LAUNCH_CHECK("split_W_i8_kernel");
             hipLaunchKernelGGL(matmat_i8_kernel<false>, grid, dim3(256), 0, s, I, m.ldI, m.nI, frag,
                                m.nstW, m.stW, w.partial);
         }
         GKL_LAUNCH_CHECK("matmat_i8_kernel");
-        hipLaunchKernelGGL(matmat_reduce_kernel, dim3(ceil_div(m.n * 16, 256)), dim3(256), 0, s,
+        hipLaunchKernelGGL(matmat_i8_reduce_kernel, dim3(ceil_div(m.n * 16, 256)), dim3(256), 0, s,
                            w.partial, m.splitW, m.nI, m.n, nb, w.cpart, w.cmax,
                            Y + (int64_t)col0 * ldy, ldy);
-        GKL_LAUNCH_CHECK("matmat_reduce_kernel");
+        GKL_LAUNCH_CHECK("matmat_i8_reduce_kernel");
     }
 }
 
-void launch_rmatmat_mixed(const MixedShape& m, const uint8_t* S, const ColStats& st,
-                          const double* X, int64_t ldx, int b, double* Z, int64_t ldz,
-                          MixedWork& w, hipStream_t s)
+static void rmatmat_i8(const MixedShape& m, const uint8_t* S, const ColStats& st, const double* X,
+                       int64_t ldx, int b, double* Z, int64_t ldz, MixedWork& w, hipStream_t s)
 {
     for (int col0 = 0; col0 < b; col0 += 16) {
         const int nb = b - col0 < 16 ? b - col0 : 16;
@@ -660,24 +1101,40 @@ void launch_rmatmat_mixed(const MixedShape& m, const uint8_t* S, const ColStats&
         dim3 grid((unsigned int)(m.pS / rows), (unsigned int)m.splitX);
         i32x4* frag = reinterpret_cast<i32x4*>(w.frag);
         if (nb <= 8) {
-            hipLaunchKernelGGL(split_X_kernel<true>, gsplit, dim3(256), 0, s, Xc, ldx, nb, m.n,
+            hipLaunchKernelGGL(split_X_i8_kernel<true>, gsplit, dim3(256), 0, s, Xc, ldx, nb, m.n,
                                w.cmax, m.nstX, frag);
-            GKL_LAUNCH_CHECK("split_X_kernel");
+            GKL_LAUNCH_CHECK("split_X_i8_kernel");
             hipLaunchKernelGGL(rmatmat_i8_kernel<true>, grid, dim3(256), 0, s, S, m.ldS, m.pS, frag,
                                m.nstX, m.stX, w.partial);
         } else {
-            hipLaunchKernelGGL(split_X_kernel<false>, gsplit, dim3(256), 0, s, Xc, ldx, nb, m.n,
+            hipLaunchKernelGGL(split_X_i8_kernel<false>, gsplit, dim3(256), 0, s, Xc, ldx, nb, m.n,
                                w.cmax, m.nstX, frag);
-            GKL_LAUNCH_CHECK("split_X_kernel");
+            GKL_LAUNCH_CHECK("split_X_i8_kernel");
             hipLaunchKernelGGL(rmatmat_i8_kernel<false>, grid, dim3(256), 0, s, S, m.ldS, m.pS, frag,
                                m.nstX, m.stX, w.partial);
         }
         GKL_LAUNCH_CHECK("rmatmat_i8_kernel");
-        hipLaunchKernelGGL(rmatmat_reduce_kernel, dim3(ceil_div(m.p * 16, 256)), dim3(256), 0, s,
+        hipLaunchKernelGGL(rmatmat_i8_reduce_kernel, dim3(ceil_div(m.p * 16, 256)), dim3(256), 0, s,
                            w.partial, m.splitX, m.pS, m.p, nb, w.cpart, w.cmax, st.mean, st.inv_sd,
                            Z + (int64_t)col0 * ldz, ldz);
-        GKL_LAUNCH_CHECK("rmatmat_reduce_kernel");
+        GKL_LAUNCH_CHECK("rmatmat_i8_reduce_kernel");
     }
+}
+
+void launch_matmat_mixed(const MixedShape& m, const uint8_t* I, const ColStats& st,
+                         const double* W, int64_t ldw, int b, double* Y, int64_t ldy,
+                         MixedWork& w, hipStream_t s)
+{
+    if (m.int8) matmat_i8(m, I, st, W, ldw, b, Y, ldy, w, s);
+    else matmat_bf16(m, I, st, W, ldw, b, Y, ldy, w, s);
+}
+
+void launch_rmatmat_mixed(const MixedShape& m, const uint8_t* S, const ColStats& st,
+                          const double* X, int64_t ldx, int b, double* Z, int64_t ldz,
+                          MixedWork& w, hipStream_t s)
+{
+    if (m.int8) rmatmat_i8(m, S, st, X, ldx, b, Z, ldz, w, s);
+    else rmatmat_bf16(m, S, st, X, ldx, b, Z, ldz, w, s);
 }
 
 }  // namespace gkl

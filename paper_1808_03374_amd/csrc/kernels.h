@@ -267,7 +267,7 @@ void launch_pro_reset(const ProState& st, int maxm, int force, hipStream_t s);
 void launch_restart_scalars(const double* S, const double* P, int m, const double* beta_last,
                             int keep, double* theta, double* rho, hipStream_t s);
 
-// ---- k_mixed.hip: split-BF16 MFMA block products ----
+// ---- k_mixed.hip: MFMA block products (split BF16 or int8 limbs) ----
 struct MixedShape {
     int64_t n = 0, p = 0;
     int64_t nI = 0, ldI = 0;      // layout I: rows (individuals, padded) and bytes per row
@@ -275,6 +275,7 @@ struct MixedShape {
     int64_t nstW = 0, nstX = 0;   // 256-wide super-tiles along SNPs / individuals
     int64_t stW = 0, stX = 0;     // super-tiles per K split
     int splitW = 1, splitX = 1;
+    bool int8 = false;            // operand format: int8 limbs (true) or split BF16
 };
 struct MixedWork {
     void* frag = nullptr;         // int8 limb fragments of the vector block

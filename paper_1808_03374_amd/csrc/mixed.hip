@@ -6,8 +6,10 @@
 //     U_s R_s     = A V_s - U_{s-1} C_{s-1}^T      (block CGS2 against all U, QR)
 //     V_{s+1} C_s = A^T U_s - V_s R_s^T            (block CGS2 against all V, QR)
 // so that A [V_1..V_s] = [U_1..U_s] B with B block upper bidiagonal (R_s on the
-// diagonal, C_s^T above it).  The two products run on MFMA with split-BF16 vector
-// tiles; everything else (Gram-Schmidt, QR, B, its SVD, restart) is FP64.
+// diagonal, C_s^T above it).  The two products run on the matrix cores, with
+// split-BF16 vector tiles (GKL_PREC_MIXED) or exact int8 limbs of a per-column
+// fixed point (GKL_PREC_MIXED_INT8); everything else (Gram-Schmidt, QR, B, its
+// SVD, restart) is FP64.
 // Ritz residual of triplet i: || C_s P(last block rows, i) ||.
 // After a restart that keeps l Ritz vectors, B starts as diag(sigma_1..l) with the
 // spike block G^T = (C_s P(last, 1:l))^T in columns l..l+b, and the next left
@@ -77,6 +79,7 @@ void gkl_ctx::setup_mixed()
     if (M.keep < k) M.keep = k;
     M.ldb = m + M.b;
     M.shape = mixed_shape(n, p);
+    M.shape.int8 = opt.precision == GKL_PREC_MIXED_INT8;
     M.I = static_cast<uint8_t*>(A.alloc((size_t)M.shape.nI * M.shape.ldI));
     M.S = static_cast<uint8_t*>(A.alloc((size_t)M.shape.pS * M.shape.ldS));
     build_mixed_layouts(prob.G_user, n, p, prob.ld, M.I, M.S, s);
@@ -256,7 +259,7 @@ gkl_status gkl_matmat_mixed(gkl_ctx* ctx, const double* W, int32_t b, double* Y)
 {
     if (!ctx || !W || !Y || b < 1 || b > 32) return GKL_ERR_INVALID;
     if (!ctx->mixed) {
-        ctx->last_error = "context was not created with precision GKL_PREC_MIXED";
+        ctx->last_error = "context was not created with a blocked precision (GKL_PREC_MIXED or _MIXED_INT8)";
         return GKL_ERR_INVALID;
     }
     try {
@@ -275,7 +278,7 @@ gkl_status gkl_rmatmat_mixed(gkl_ctx* ctx, const double* X, int32_t b, double* Z
 {
     if (!ctx || !X || !Z || b < 1 || b > 32) return GKL_ERR_INVALID;
     if (!ctx->mixed) {
-        ctx->last_error = "context was not created with precision GKL_PREC_MIXED";
+        ctx->last_error = "context was not created with a blocked precision (GKL_PREC_MIXED or _MIXED_INT8)";
         return GKL_ERR_INVALID;
     }
     try {

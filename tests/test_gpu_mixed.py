@@ -1,7 +1,15 @@
-"""GPU parity of the blocked mixed-precision path (split-BF16 MFMA products).
+"""GPU parity of the blocked mixed-precision path, with both matrix-core formats
+of its products: split-BF16 vector tiles (GKL_PREC_MIXED) and exact int8 limbs
+(GKL_PREC_MIXED_INT8).
 
 Error model and tolerances
-  * The vector block is split into bf16 hi + lo: |w - hi - lo| <= 2^-16 |w| per
+  * Int8 limbs: each vector column is rounded to integers of 22 bits below a
+    power-of-two scale under twice its largest entry (three times that for the
+    missing-term vector, which shares the scale), accumulation is exact, so per
+    element the product error is at most 3 * 2^-22 max|w| times the row's sum of
+    |codes| -- inside the split-BF16 bound below for vectors whose entries are
+    within a factor of ten of their maximum, as random and Lanczos vectors are.
+  * Split BF16: the vector block is split into bf16 hi + lo: |w - hi - lo| <= 2^-16 |w| per
     element; genotype operands are exact.  FP32 accumulation runs over chunks of
     1,024 K values (error ~ sqrt(4096) * 2^-24 of the chunk magnitude, about 4e-6
     relative to |A| |w|) and FP64 across chunks.  Per output element the error is
@@ -32,6 +40,13 @@ def gk():
     return m
 
 
+PRECISIONS = ["bf16", "int8"]
+
+
+def prec(gk, name):
+    return gk.GKL_PREC_MIXED if name == "bf16" else gk.GKL_PREC_MIXED_INT8
+
+
 def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
@@ -41,13 +56,14 @@ def _dense(g):
     return oracle.dense_matrix(oracle.decode(g.packed, g.n, g.p), st.mean, st.inv_sd)
 
 
+@pytest.mark.parametrize("fmt", PRECISIONS)
 @pytest.mark.parametrize("name,n,p,b,pad", [("c1", 300, 900, 16, 0), ("c3", 523, 1111, 7, -1),
                                             ("c5", 1000, 3000, 32, -1), ("c2", 17, 260, 1, -1)])
-def test_mixed_products(gk, name, n, p, b, pad):
+def test_mixed_products(gk, name, n, p, b, pad, fmt):
     g = synth.config(name, n=n, p=p, pad_mode=pad)
     A = _dense(g)
     bw = 16 if min(n, p) >= 32 else 4
-    ctx = gk.Context(dev(g.packed), n, p, 1, precision=gk.GKL_PREC_MIXED, block_width=bw,
+    ctx = gk.Context(dev(g.packed), n, p, 1, precision=prec(gk, fmt), block_width=bw,
                      krylov_dim=2 * bw)
     rng = np.random.default_rng(n + p + b)
     W = rng.standard_normal((p, b))
@@ -73,10 +89,11 @@ def _oracle(g, k):
 @pytest.mark.parametrize("name,n,p,k,b", [("c1", 1000, 5000, 10, 16), ("c3", 2000, 20000, 20, 16),
                                           ("c2", 2000, 20000, 20, 32), ("c3", 3000, 30000, 20, 8),
                                           ("c1", 1000, 5000, 10, 5)])
-def test_mixed_solve_matches_fp64_oracle(gk, name, n, p, k, b):
+@pytest.mark.parametrize("fmt", PRECISIONS)
+def test_mixed_solve_matches_fp64_oracle(gk, name, n, p, k, b, fmt):
     g = synth.config(name, n=n, p=p)
     op, ref = _oracle(g, k)
-    ctx = gk.Context(dev(g.packed), g.n, g.p, k, tol=1e-9, precision=gk.GKL_PREC_MIXED,
+    ctx = gk.Context(dev(g.packed), g.n, g.p, k, tol=1e-9, precision=prec(gk, fmt),
                      block_width=b)
     sigma, U, V, st, info = ctx.solve()
     assert st == gk.GKL_OK, gk.gkl_last_error(ctx.ctx)
@@ -94,7 +111,8 @@ def test_mixed_solve_matches_fp64_oracle(gk, name, n, p, k, b):
     ctx.close()
 
 
-def test_mixed_products_layouts_beyond_4GiB(gk):
+@pytest.mark.parametrize("fmt", PRECISIONS)
+def test_mixed_products_layouts_beyond_4GiB(gk, fmt):
     # 50,000 x 350,000: both internal layouts of the block products hold more than
     # 2^32 bytes, so byte offsets and the layout builders' work-item counts exceed
     # 32 bits.  Checked on sampled rows and columns against the oracle, including
@@ -105,7 +123,7 @@ def test_mixed_products_layouts_beyond_4GiB(gk):
     block = rng.integers(0, 256, size=(1000, ld), dtype=np.uint8)
     packed = np.tile(block, (p // 1000, 1))
     op = oracle.PackedOperator(packed, n, p)
-    ctx = gk.Context(dev(packed), n, p, 1, precision=gk.GKL_PREC_MIXED, block_width=8,
+    ctx = gk.Context(dev(packed), n, p, 1, precision=prec(gk, fmt), block_width=8,
                      krylov_dim=32)
     W = rng.standard_normal((p, 8)) / np.sqrt(p)
     X = rng.standard_normal((n, 8)) / np.sqrt(n)
@@ -121,14 +139,15 @@ def test_mixed_products_layouts_beyond_4GiB(gk):
         assert np.max(np.abs(Z[cols, c] - zr)) <= 1e-4 * np.max(np.abs(zr))
 
 
-def test_mixed_solve_recovers_planted_spikes(gk):
+@pytest.mark.parametrize("fmt", PRECISIONS)
+def test_mixed_solve_recovers_planted_spikes(gk, fmt):
     # the spiked recipe (noise bulk + ten planted spikes at 1.5..20x the bulk edge)
     # at 4,000 x 40,000: the blocked solve matches the oracle to 1e-6 and every
     # planted spike stands clear of the bulk edge
     g = synth.config("c5", n=4000, p=40000)
     k = 10
     op, ref = _oracle(g, k)
-    ctx = gk.Context(dev(g.packed), g.n, g.p, k, tol=1e-9, precision=gk.GKL_PREC_MIXED,
+    ctx = gk.Context(dev(g.packed), g.n, g.p, k, tol=1e-9, precision=prec(gk, fmt),
                      block_width=8)
     sigma, U, V, st, info = ctx.solve()
     ctx.close()
