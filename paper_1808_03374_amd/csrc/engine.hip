@@ -134,6 +134,8 @@ void gkl_ctx::allocate_solver()
     ow.h = static_cast<double*>(A.alloc(sizeof(double) * (3 * (size_t)(cols + 2) + 8)));
     ow.tn_partial = static_cast<double*>(A.alloc(sizeof(double) * gemm_tn_partial_elems(maxlen, cols + 1)));
     ow.npart = static_cast<double*>(A.alloc(sizeof(double) * (ceil_div(maxlen, 256) + 1)));
+    ow.cgs_partial_elems = cgs_partial_elems(maxlen, cols + 1);
+    ow.cgs_partial = static_cast<double*>(A.alloc(sizeof(double) * ow.cgs_partial_elems));
     hipStream_t s = prob.stream;
     GKL_HIP(hipMemsetAsync(ow.counters, 0, sizeof(unsigned int) * kOrthoCounters, s));
     GKL_HIP(hipMemsetAsync(scal, 0, sizeof(double) * kScalars, s));

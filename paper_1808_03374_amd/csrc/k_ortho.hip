@@ -8,11 +8,15 @@
 // is at least 1/sqrt(2) of the norm before the pass).
 //
 // The bases are column-major (length x columns), so every pass streams
-// contiguous rows.  The projection h = Q^T r runs on the FP64 matrix cores (the
-// tall-skinny Q^T Y kernel with one vector); norms are two-stage reductions with
-// a fixed order (block partials, then the last block to arrive sums them).  All
-// results are deterministic.
+// contiguous rows.  The two-pass CGS2 takes three launches: projection partials;
+// update by the first projection fused with the partials of the second; update
+// by the second with the norm partials.  Each launch sums the previous one's
+// partials itself, in a fixed order, so no reduction launches sit between them.
+// Norms are two-stage reductions with a fixed order.  All results are
+// deterministic.
 #include <math.h>
+
+#include <algorithm>
 
 #include "engine.h"
 
@@ -121,6 +125,251 @@ static void launch_update(const double* Q, int64_t ldq, int64_t len, int ncols, 
     GKL_LAUNCH_CHECK("update_kernel");
 }
 
+// ---------------------------------------------------------------------------
+// Two-pass CGS2 of one vector in three launches
+// ---------------------------------------------------------------------------
+// Each wave owns one tile of 64 consecutive rows (lane = row) and each
+// workgroup kCT / 64 tiles, so every pass touches the same rows from the same
+// lane and r is updated in place without cross-workgroup hazards.  A lane loads
+// its row of up to 64 basis columns at once (one coalesced 512-byte access per
+// column and wave); for ncols <= 64 those values stay in registers, so the
+// update and the next projection share one read of Q.  The column sums over a
+// wave are formed by a transpose-sum (lane l ends with column l), then the
+// waves of a workgroup are added in order: part[b * cstride + c].
+namespace {
+constexpr int kCT = 512;          // threads per workgroup
+constexpr int kCW = kCT / 64;     // waves (tiles) per workgroup
+constexpr int kCChunk = 64;       // columns per chunk (one per lane)
+}  // namespace
+
+struct CgsPlan {
+    int nb;        // workgroups
+    int cstride;   // partial row stride (ncols rounded up to kCChunk)
+};
+
+static CgsPlan cgs_plan(int64_t len, int ncols)
+{
+    CgsPlan c;
+    c.nb = (int)ceil_div(len, kCT);
+    c.cstride = (int)ceil_div(ncols, kCChunk) * kCChunk;
+    return c;
+}
+
+size_t cgs_partial_elems(int64_t len, int maxcols)
+{
+    const CgsPlan c = cgs_plan(len, maxcols);
+    return 2 * (size_t)c.nb * (size_t)c.cstride;
+}
+
+int cgs_norm_partials(int64_t len)
+{
+    return cgs_plan(len, 1).nb;
+}
+
+// Lane exchanges for the transpose-sum.  swap32 / swap16: the two halves
+// (rows of 16) of a pair of registers change places between lanes l and l ^ 32
+// (l ^ 16).  xor8 .. xor1: the value of lane l ^ d within a row of 16 (DPP:
+// rotate by 8; half-row mirror after a quad reversal; quad permutes).
+__device__ __forceinline__ void swap_halves32(double& a, double& b)
+{
+    const long long x = __double_as_longlong(a), y = __double_as_longlong(b);
+    const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)x, (unsigned)y, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(x >> 32), (unsigned)(y >> 32),
+                                                     false, false);
+    a = __longlong_as_double(((long long)hi[0] << 32) | lo[0]);
+    b = __longlong_as_double(((long long)hi[1] << 32) | lo[1]);
+}
+
+__device__ __forceinline__ void swap_halves16(double& a, double& b)
+{
+    const long long x = __double_as_longlong(a), y = __double_as_longlong(b);
+    const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)x, (unsigned)y, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(x >> 32), (unsigned)(y >> 32),
+                                                     false, false);
+    a = __longlong_as_double(((long long)hi[0] << 32) | lo[0]);
+    b = __longlong_as_double(((long long)hi[1] << 32) | lo[1]);
+}
+
+template <int kCtrl>
+__device__ __forceinline__ int dpp_i(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, kCtrl, 0xF, 0xF, false);
+}
+
+template <int kD>
+__device__ __forceinline__ double lane_xor(double v)
+{
+    const long long x = __double_as_longlong(v);
+    int lo = (int)(x & 0xffffffff), hi = (int)(x >> 32);
+    if (kD == 8) { lo = dpp_i<0x128>(lo); hi = dpp_i<0x128>(hi); }            // row_ror:8
+    if (kD == 4) {                                                             // quad reverse,
+        lo = dpp_i<0x141>(dpp_i<0x1B>(lo)); hi = dpp_i<0x141>(dpp_i<0x1B>(hi)); // half mirror
+    }
+    if (kD == 2) { lo = dpp_i<0x4E>(lo); hi = dpp_i<0x4E>(hi); }              // [2,3,0,1]
+    if (kD == 1) { lo = dpp_i<0xB1>(lo); hi = dpp_i<0xB1>(hi); }              // [1,0,3,2]
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Round of distance kD <= 8 on v[0..2 kD): lane keeps column i + kD when its
+// bit kD is set, else column i, adding the partner's copy of the same column.
+template <int kD>
+__device__ __forceinline__ void xor_round(double (&v)[kCChunk], bool hi)
+{
+#pragma unroll
+    for (int i = 0; i < kD; ++i) {
+        const double lo_sum = v[i] + lane_xor<kD>(v[i]);
+        const double hi_sum = v[i + kD] + lane_xor<kD>(v[i + kD]);
+        v[i] = hi ? hi_sum : lo_sum;
+    }
+}
+
+// v[0..64) held by every lane of a wave; returns to lane l the sum over the
+// wave of v[l].  Six exchange rounds of distance d = 32 .. 1: each lane keeps
+// the half of its live values whose column has bit d equal to its own lane
+// bit d and adds the partner's (lane l ^ d) copy of that half.  The rounds of
+// distance 32 and 16 swap register halves between lanes, so every lane adds
+// the pair it ends up with; the others exchange both halves and keep one sum.
+// Additions are commutative pairs in a fixed pattern, so the result is
+// deterministic.
+__device__ __forceinline__ double wave_transpose_sum(double (&v)[kCChunk], int lane)
+{
+#pragma unroll
+    for (int i = 0; i < 32; ++i) {
+        swap_halves32(v[i], v[i + 32]);
+        v[i] = v[i] + v[i + 32];
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        swap_halves16(v[i], v[i + 16]);
+        v[i] = v[i] + v[i + 16];
+    }
+    xor_round<8>(v, (lane & 8) != 0);
+    xor_round<4>(v, (lane & 4) != 0);
+    xor_round<2>(v, (lane & 2) != 0);
+    xor_round<1>(v, (lane & 1) != 0);
+    return v[0];
+}
+
+// Row `rowc` of columns [c0, c0 + 64) into q; columns at or past ncols read
+// column ncols - 1 again (in bounds).  Their values only reach partials past
+// ncols, which are never read, and updates through coefficients that are zero
+// there.  The loads are unconditional so they are all in flight together.
+__device__ __forceinline__ void load_row_chunk(const double* __restrict__ Q, int64_t ldq,
+                                               int64_t rowc, int c0, int ncols,
+                                               double (&q)[kCChunk])
+{
+    const double* qp = Q + (int64_t)c0 * ldq + rowc;
+#pragma unroll
+    for (int k = 0; k < kCChunk; ++k) {
+        q[k] = *qp;
+        if (k + 1 < kCChunk) qp += (c0 + k + 1 < ncols) ? ldq : 0;
+    }
+}
+
+// Adds the wave's column sums sw (lane l: column c0 + l) of every wave in order
+// and stores them at out[c0 + l]; red holds kCW x 64 doubles.
+__device__ __forceinline__ void block_columns(double sw, double* red, double* __restrict__ out,
+                                              int c0)
+{
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    __syncthreads();
+    red[wave * 64 + lane] = sw;
+    __syncthreads();
+    if (t < 64) {
+        double h = red[t];
+#pragma unroll
+        for (int w = 1; w < kCW; ++w) h += red[w * 64 + t];
+        out[c0 + t] = h;
+    }
+}
+
+// kMode 0: partials of Q^T r.
+// kMode 1: h = sum of the pass-1 partials; r -= Q h; partials of Q^T r.
+// kMode 2: h = sum of the pass-2 partials; r -= Q h; npart[b] = sum of the
+//          squares of the workgroup's updated rows; block 0 adds 2 to *passes.
+// With *enable == 0 every workgroup returns at once (the same for all).
+template <int kMode>
+__global__ void __launch_bounds__(kCT)
+cgs_pass_kernel(const double* __restrict__ Q, int64_t ldq, int64_t len, int ncols,
+                double* __restrict__ r, const double* __restrict__ pin,
+                double* __restrict__ pout, int nb, int cstride, const int* __restrict__ enable,
+                int* __restrict__ passes)
+{
+    if (enable && *enable == 0) return;
+    extern __shared__ double hs[];             // cstride coefficients (kMode > 0)
+    __shared__ double red[kCW * 64];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int64_t row = (int64_t)blockIdx.x * kCT + t;
+    const bool live = row < len;
+    const int64_t rowc = live ? row : len - 1;
+
+    if (kMode > 0) {   // coefficients, zero past ncols
+        for (int c0 = 0; c0 < ncols; c0 += kCChunk) {
+            const int c = c0 + lane;
+            double sacc = 0.0;
+            if (c < ncols) {
+#pragma unroll 4
+                for (int b = wave; b < nb; b += kCW) sacc += pin[(int64_t)b * cstride + c];
+            }
+            __syncthreads();
+            red[wave * 64 + lane] = sacc;
+            __syncthreads();
+            if (t < 64) {
+                double h = red[t];
+#pragma unroll
+                for (int w = 1; w < kCW; ++w) h += red[w * 64 + t];
+                hs[c0 + t] = c < ncols ? h : 0.0;
+            }
+        }
+        __syncthreads();
+    }
+
+    double x = live ? r[row] : 0.0;
+    double q[kCChunk];
+    if (ncols <= kCChunk) {
+        load_row_chunk(Q, ldq, rowc, 0, ncols, q);
+        if (kMode > 0) {
+#pragma unroll
+            for (int k = 0; k < kCChunk; ++k) x = fma(-q[k], hs[k], x);
+            if (live) r[row] = x;
+            x = live ? x : 0.0;     // lanes past len read row len - 1: no contribution
+        }
+        if (kMode == 2) {
+            const double ss = block_sum(x * x, red);
+            if (t == 0) pout[blockIdx.x] = ss;
+            if (passes && blockIdx.x == 0 && t == 0) *passes += 2;
+            return;
+        }
+#pragma unroll
+        for (int k = 0; k < kCChunk; ++k) q[k] *= x;
+        block_columns(wave_transpose_sum(q, lane), red, pout + (int64_t)blockIdx.x * cstride, 0);
+        return;
+    }
+    // more than 64 columns: update over all chunks first, then the projection
+    // reads the chunks again
+    if (kMode > 0) {
+        for (int c0 = 0; c0 < ncols; c0 += kCChunk) {
+            load_row_chunk(Q, ldq, rowc, c0, ncols, q);
+#pragma unroll
+            for (int k = 0; k < kCChunk; ++k) x = fma(-q[k], hs[c0 + k], x);
+        }
+        if (live) r[row] = x;
+        x = live ? x : 0.0;
+    }
+    if (kMode == 2) {
+        const double ss = block_sum(x * x, red);
+        if (t == 0) pout[blockIdx.x] = ss;
+        if (passes && blockIdx.x == 0 && t == 0) *passes += 2;
+        return;
+    }
+    for (int c0 = 0; c0 < ncols; c0 += kCChunk) {
+        load_row_chunk(Q, ldq, rowc, c0, ncols, q);
+#pragma unroll
+        for (int k = 0; k < kCChunk; ++k) q[k] *= x;
+        block_columns(wave_transpose_sum(q, lane), red, pout + (int64_t)blockIdx.x * cstride, c0);
+    }
+}
+
 __global__ void adapt_decide_kernel(const double* __restrict__ n0, const double* __restrict__ n1,
                                     int* __restrict__ skip, int* __restrict__ passes,
                                     const int* __restrict__ enable)
@@ -160,11 +409,22 @@ void launch_cgs2(const double* Q, int64_t ldq, int64_t len, int ncols, double* r
         proj(skip);
         launch_update(Q, ldq, len, ncols, r, h1, enable, skip, s);
     } else {
-        proj(nullptr);
-        launch_update(Q, ldq, len, ncols, r, h1, enable, nullptr, s);
-        proj(nullptr);
-        // the second update also leaves the partial sums of ||r||^2 in w.npart
-        launch_update(Q, ldq, len, ncols, r, h1, enable, nullptr, s, w.npart, passes);
+        // the last pass also leaves the partial sums of ||r||^2 in w.npart
+        const CgsPlan c = cgs_plan(len, ncols);
+        if (2 * (size_t)c.nb * (size_t)c.cstride > w.cgs_partial_elems)
+            fail(GKL_ERR_INTERNAL, "CGS2 plan exceeds its partial buffer");
+        double* p1 = w.cgs_partial;
+        double* p2 = w.cgs_partial + (size_t)c.nb * c.cstride;
+        const size_t hb = sizeof(double) * (size_t)c.cstride;
+        hipLaunchKernelGGL(cgs_pass_kernel<0>, dim3(c.nb), dim3(kCT), 0, s, Q, ldq, len, ncols, r,
+                           nullptr, p1, c.nb, c.cstride, enable, nullptr);
+        GKL_LAUNCH_CHECK("cgs_pass_kernel<0>");
+        hipLaunchKernelGGL(cgs_pass_kernel<1>, dim3(c.nb), dim3(kCT), hb, s, Q, ldq, len, ncols, r,
+                           p1, p2, c.nb, c.cstride, enable, nullptr);
+        GKL_LAUNCH_CHECK("cgs_pass_kernel<1>");
+        hipLaunchKernelGGL(cgs_pass_kernel<2>, dim3(c.nb), dim3(kCT), hb, s, Q, ldq, len, ncols, r,
+                           p2, w.npart, c.nb, c.cstride, enable, passes);
+        GKL_LAUNCH_CHECK("cgs_pass_kernel<2>");
     }
 }
 
@@ -187,8 +447,8 @@ void launch_norm(const double* r, int64_t len, double* out, OrthoWork& w, hipStr
     launch_norm_raw(r, len, out, w, s);
 }
 
-// Normalisation right after a non-adaptive CGS2 whose second update left the
-// partial sums of ||r||^2 in npart (one per 256 rows).  Every block adds the
+// Normalisation right after a non-adaptive CGS2 whose last pass left the
+// partial sums of ||r||^2 in npart (one per CGS2 workgroup).  Every block adds the
 // partials in the same order, applies the breakdown test of norm_kernel and
 // scales its rows; block 0 records the results.  When *enable == 0 the CGS2 was
 // skipped and *nrm_out already holds ||r|| (computed before it).  Blocks may see
@@ -233,7 +493,7 @@ void launch_normalize_after_cgs2(double* r, int64_t len, double* nrm_out, double
     unsigned int nb = ceil_div(len, 4 * kOT);
     if (nb > 1024) nb = 1024;
     hipLaunchKernelGGL(normalize_fused_kernel, dim3(nb), dim3(kOT), 0, s, r, len, nrm_out, norm_est,
-                       root_maxdim, flag, first_breakdown, step, w.npart, (int)ceil_div(len, kOT),
+                       root_maxdim, flag, first_breakdown, step, w.npart, cgs_norm_partials(len),
                        enable);
     GKL_LAUNCH_CHECK("normalize_fused_kernel");
 }

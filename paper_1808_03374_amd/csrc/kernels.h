@@ -142,9 +142,13 @@ struct OrthoWork {
     unsigned int* counters = nullptr;
     double* h = nullptr;            // projection coefficients (maxcols + 1)
     double* tn_partial = nullptr;   // Q^T r partials (gemm_tn_partial_elems)
-    double* npart = nullptr;        // ||r||^2 partials of the last CGS2 update, ceil(len/256)
+    double* npart = nullptr;        // ||r||^2 partials of the last CGS2 pass (cgs_norm_partials)
+    double* cgs_partial = nullptr;  // CGS2 projection partials, both passes
+    size_t cgs_partial_elems = 0;
 };
 size_t ortho_partial_elems(int64_t len, int maxcols);
+size_t cgs_partial_elems(int64_t len, int maxcols);
+int cgs_norm_partials(int64_t len);
 
 // r <- r - Q (Q^T r) with Q = [Q(:, 0:ncols)], column-major leading dim ldq.
 // `enable` (device, may be NULL = always) gates the whole call: 0 skips it.

@@ -210,6 +210,28 @@ def test_gkl_thick_restart(gk, reorth):
     ctx.close()
 
 
+@pytest.mark.parametrize("reorth", ["full", "partial"])
+def test_gkl_wide_basis_ragged(gk, reorth):
+    # a 100-vector basis (more than 64 columns per Gram-Schmidt pass) on lengths
+    # that are not multiples of the 64-row tiles: 1,300 x 7,000, k = 20
+    g, Gd = gen("c2", 1300, 7000)
+    k = 20
+    op, ref = _oracle_solve(g, k, 5)
+    v0 = dev(synth.start_vector(g.p, 5))
+    re = gk.GKL_REORTH_FULL if reorth == "full" else gk.GKL_REORTH_PARTIAL
+    ctx = gk.Context(Gd, g.n, g.p, k, tol=1e-11, reorth=re, v0=v0, krylov_dim=100)
+    sigma, U, V, st, info = ctx.solve()
+    assert st == gk.GKL_OK, gk.gkl_last_error(ctx.ctx)
+    sigma = sigma.cpu().numpy()
+    U = U.cpu().numpy()
+    V = V.cpu().numpy()
+    assert np.all(np.abs(sigma - ref.sigma) <= 1e-10 * ref.sigma)
+    assert np.abs(U.T @ U - np.eye(k)).max() < 1e-7
+    assert np.abs(V.T @ V - np.eye(k)).max() < 1e-7
+    assert _residuals(op, sigma, U, V) <= 1e-9 * sigma[0]
+    ctx.close()
+
+
 def test_two_group_closed_form_and_rank_deficiency(gk):
     n, p = 40, 30
     codes = np.zeros((n, p), dtype=np.int64)
