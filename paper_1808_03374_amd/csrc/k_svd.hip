@@ -48,7 +48,6 @@ __device__ __forceinline__ double group_sum(double v)
     return v;
 }
 
-constexpr int kRegs = 8;   // column elements per lane kept in registers (mp <= 128)
 
 // 1/x and 1/sqrt(x) from the hardware estimates, each refined by two Newton
 // steps.
@@ -86,24 +85,31 @@ __device__ __forceinline__ bool jacobi_rotation(double sab, double saa, double s
     return true;
 }
 
-// W (mp x mp, column-major, ld = mp) is replaced by B Q = P S; Vr accumulates Q.
-// mp is even (a zero column pads odd m).  Column norms are computed once per
-// sweep and updated after each rotation (d_p -= t c, d_q += t c), so a pair needs
-// one reduction (its inner product).  Returns after a sweep without rotations.
-__device__ __forceinline__ void jacobi_sweeps(double* W, double* Vr, int mp)
+// Column stride of the working arrays: rows are padded with zeros to a
+// multiple of the 16-lane group when mp <= 64 (every lane then holds exactly
+// svd_elems(mp) elements of a column and loads them unconditionally), else mp.
+__host__ __device__ inline int svd_elems(int mp) { return (mp + kGroup - 1) / kGroup; }
+__host__ __device__ inline int svd_ld(int mp) { return mp <= 4 * kGroup ? kGroup * svd_elems(mp) : mp; }
+
+// W (ld x mp, column-major) is replaced by B Q = P S; Vr accumulates Q.  mp is
+// even (a zero column pads odd m); rows past mp are zero and stay zero.  Column
+// norms (dn, mp doubles) are computed once per sweep and updated after each
+// rotation (d_p -= t c, d_q += t c), so a pair needs one reduction (its inner
+// product).  Returns after a sweep without rotations.  kJ > 0: ld = 16 kJ and
+// every lane holds kJ elements of each column of its pair in registers.
+template <int kJ>
+__device__ __forceinline__ void jacobi_sweeps_t(double* W, double* Vr, int mp, int ld, double* dn)
 {
     __shared__ int rotated;
-    __shared__ double dn[kMaxSvd + 2];
     const int g = threadIdx.x / kGroup;
     const int gl = threadIdx.x % kGroup;
     const int npairs = mp / 2;
     const int ring = mp - 1;
     // rotation threshold sqrt(m) * eps (the usual one-sided Jacobi test)
     const double tol = 2.220446049250313e-16 * sqrt((double)mp);
-    const bool in_regs = mp <= kRegs * kGroup;
     for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
         for (int c = g; c < mp; c += kGroups) {
-            const double* wc = W + (int64_t)c * mp;
+            const double* wc = W + (int64_t)c * ld;
             double a = 0.0;
             for (int i = gl; i < mp; i += kGroup) a = fma(wc[i], wc[i], a);
             a = group_sum(a);
@@ -125,47 +131,38 @@ __device__ __forceinline__ void jacobi_sweeps(double* W, double* Vr, int mp)
                     if (b < 0) b += ring;
                 }
                 if (a > b) { const int tmp = a; a = b; b = tmp; }
-                double* xa = W + (int64_t)a * mp;
-                double* xb = W + (int64_t)b * mp;
-                double* ya = Vr + (int64_t)a * mp;
-                double* yb = Vr + (int64_t)b * mp;
+                double* xa = W + (int64_t)a * ld;
+                double* xb = W + (int64_t)b * ld;
+                double* ya = Vr + (int64_t)a * ld;
+                double* yb = Vr + (int64_t)b * ld;
                 const double saa = dn[a], sbb = dn[b];
-                double t, cs, sn;
-                if (in_regs) {
-                    // both pairs of columns are read once; the rotation is
-                    // applied from registers
-                    double u[kRegs], v[kRegs], pa[kRegs], pb[kRegs];
+                double t, cs, sn, sab = 0.0;
+                if (kJ > 0) {
+                    // both pairs of columns are read once, unconditionally (rows
+                    // are padded); the rotation is applied from registers
+                    constexpr int kE = kJ > 0 ? kJ : 1;
+                    double u[kE], v[kE], pa[kE], pb[kE];
 #pragma unroll
-                    for (int j = 0; j < kRegs; ++j) {
+                    for (int j = 0; j < kE; ++j) {
                         const int i = gl + j * kGroup;
-                        const bool ok = i < mp;
-                        u[j] = ok ? xa[i] : 0.0;
-                        v[j] = ok ? xb[i] : 0.0;
-                        pa[j] = ok ? ya[i] : 0.0;
-                        pb[j] = ok ? yb[i] : 0.0;
+                        u[j] = xa[i];
+                        v[j] = xb[i];
+                        pa[j] = ya[i];
+                        pb[j] = yb[i];
                     }
-                    double sab = 0.0;
 #pragma unroll
-                    for (int j = 0; j < kRegs; ++j) sab = fma(u[j], v[j], sab);
+                    for (int j = 0; j < kE; ++j) sab = fma(u[j], v[j], sab);
                     sab = group_sum(sab);
                     if (!jacobi_rotation(sab, saa, sbb, tol, t, cs, sn)) continue;
 #pragma unroll
-                    for (int j = 0; j < kRegs; ++j) {
+                    for (int j = 0; j < kE; ++j) {
                         const int i = gl + j * kGroup;
-                        if (i < mp) {
-                            xa[i] = cs * u[j] - sn * v[j];
-                            xb[i] = sn * u[j] + cs * v[j];
-                            ya[i] = cs * pa[j] - sn * pb[j];
-                            yb[i] = sn * pa[j] + cs * pb[j];
-                        }
-                    }
-                    if (gl == 0) {
-                        dn[a] = saa - t * sab;
-                        dn[b] = sbb + t * sab;
-                        rotated = 1;
+                        xa[i] = cs * u[j] - sn * v[j];
+                        xb[i] = sn * u[j] + cs * v[j];
+                        ya[i] = cs * pa[j] - sn * pb[j];
+                        yb[i] = sn * pa[j] + cs * pb[j];
                     }
                 } else {
-                    double sab = 0.0;
                     for (int i = gl; i < mp; i += kGroup) sab = fma(xa[i], xb[i], sab);
                     sab = group_sum(sab);
                     if (!jacobi_rotation(sab, saa, sbb, tol, t, cs, sn)) continue;
@@ -177,11 +174,11 @@ __device__ __forceinline__ void jacobi_sweeps(double* W, double* Vr, int mp)
                         ya[i] = cs * p - sn * q;
                         yb[i] = sn * p + cs * q;
                     }
-                    if (gl == 0) {
-                        dn[a] = saa - t * sab;
-                        dn[b] = sbb + t * sab;
-                        rotated = 1;
-                    }
+                }
+                if (gl == 0) {
+                    dn[a] = saa - t * sab;
+                    dn[b] = sbb + t * sab;
+                    rotated = 1;
                 }
             }
             __syncthreads();
@@ -191,13 +188,25 @@ __device__ __forceinline__ void jacobi_sweeps(double* W, double* Vr, int mp)
     }
 }
 
+__device__ __forceinline__ void jacobi_sweeps(double* W, double* Vr, int mp, int ld, double* dn)
+{
+    switch (ld == kGroup * svd_elems(mp) ? svd_elems(mp) : 0) {
+    case 1: jacobi_sweeps_t<1>(W, Vr, mp, ld, dn); break;
+    case 2: jacobi_sweeps_t<2>(W, Vr, mp, ld, dn); break;
+    case 3: jacobi_sweeps_t<3>(W, Vr, mp, ld, dn); break;
+    case 4: jacobi_sweeps_t<4>(W, Vr, mp, ld, dn); break;
+    default: jacobi_sweeps_t<0>(W, Vr, mp, ld, dn); break;
+    }
+}
+
 // After jacobi_sweeps: singular values are the column norms of W; write the
 // m leading (sorted descending) triplets.
-__device__ __forceinline__ void extract_sorted(const double* W, const double* Vr, int m, int mp, double* sig,
-                               int* order, double* P, int ldp_, double* S, double* Q, int ldq_)
+__device__ __forceinline__ void extract_sorted(const double* W, const double* Vr, int m, int mp,
+                                               int ld, double* sig, int* order, double* P,
+                                               int ldp_, double* S, double* Q, int ldq_)
 {
     for (int c = threadIdx.x / kGroup; c < mp; c += kGroups) {
-        const double* wc = W + (int64_t)c * mp;
+        const double* wc = W + (int64_t)c * ld;
         double s = 0.0;
         for (int i = threadIdx.x % kGroup; i < mp; i += kGroup) s = fma(wc[i], wc[i], s);
         s = group_sum(s);
@@ -220,8 +229,8 @@ __device__ __forceinline__ void extract_sorted(const double* W, const double* Vr
         const int i = t % m, o = t / m;     // row i of output column o
         const int c = order[o];
         const double s = sig[c];
-        P[(int64_t)o * ldp_ + i] = s > 0.0 ? W[(int64_t)c * mp + i] / s : (i == o ? 1.0 : 0.0);
-        Q[(int64_t)o * ldq_ + i] = Vr[(int64_t)c * mp + i];
+        P[(int64_t)o * ldp_ + i] = s > 0.0 ? W[(int64_t)c * ld + i] / s : (i == o ? 1.0 : 0.0);
+        Q[(int64_t)o * ldq_ + i] = Vr[(int64_t)c * ld + i];
     }
     for (int o = threadIdx.x; o < m; o += blockDim.x) S[o] = sig[order[o]];
 }
@@ -237,25 +246,29 @@ dense_svd_kernel(const double* __restrict__ B, int m, double* __restrict__ P,
 {
     extern __shared__ double lds[];
     const int mp = m + (m & 1);
+    const int ld = svd_ld(mp);
     double* W = kLds ? lds : gscratch;
-    double* Vr = W + mp * mp;
-    double* sig = Vr + mp * mp;
-    int* order = reinterpret_cast<int*>(sig + mp);
-    for (int t = threadIdx.x; t < mp * mp; t += blockDim.x) {
-        const int i = t % mp, c = t / mp;
+    double* Vr = W + ld * mp;
+    double* sig = Vr + ld * mp;
+    double* dn = sig + mp;
+    int* order = reinterpret_cast<int*>(dn + mp);
+    for (int t = threadIdx.x; t < ld * mp; t += blockDim.x) {
+        const int i = t % ld, c = t / ld;
         W[t] = (i < m && c < m) ? B[(int64_t)c * m + i] : 0.0;
         Vr[t] = (i == c) ? 1.0 : 0.0;
     }
     __syncthreads();
-    jacobi_sweeps(W, Vr, mp);
+    jacobi_sweeps(W, Vr, mp, ld, dn);
     __syncthreads();
-    extract_sorted(W, Vr, m, mp, sig, order, P, m, S, Q, m);
+    extract_sorted(W, Vr, m, mp, ld, sig, order, P, m, S, Q, m);
 }
 
+// W and Vr (ld x mp each), sig and dn (mp each), order (mp ints).
 static size_t svd_lds_bytes(int m)
 {
     const int mp = m + (m & 1);
-    return sizeof(double) * (2 * (size_t)mp * mp + mp) + sizeof(int) * (size_t)mp;
+    return sizeof(double) * (2 * (size_t)svd_ld(mp) * mp + 2 * (size_t)mp) +
+           sizeof(int) * (size_t)mp;
 }
 
 size_t svd_scratch_elems(int m) { return svd_lds_bytes(m) / sizeof(double) + 1; }
@@ -270,8 +283,8 @@ bool svd_fits_lds(int m)
             v = 65536;
         limit = v;
     }
-    // the kernels' static LDS (column norms, flags) needs room beside the arrays
-    return m <= kMaxKrylov && svd_lds_bytes(m) + sizeof(double) * (kMaxSvd + 2) + 256 <= (size_t)limit;
+    // the kernels' static LDS (flags, reduction scratch) needs room beside the arrays
+    return m <= kMaxKrylov && svd_lds_bytes(m) + 256 <= (size_t)limit;
 }
 
 static void check_svd_size(int m, const double* gscratch)
@@ -303,11 +316,12 @@ __device__ __forceinline__ void ritz_body(const double* __restrict__ alpha,
                                           const double* __restrict__ theta,
                                           const double* __restrict__ rho, int nlock, int m, int k,
                                           double tol, const RitzOut& out, double* W, double* Vr,
-                                          double* sig, int* order)
+                                          double* sig, double* dn, int* order)
 {
     const int mp = m + (m & 1);
-    for (int t = threadIdx.x; t < mp * mp; t += blockDim.x) {
-        const int i = t % mp, c = t / mp;
+    const int ld = svd_ld(mp);
+    for (int t = threadIdx.x; t < ld * mp; t += blockDim.x) {
+        const int i = t % ld, c = t / ld;
         double v = 0.0;
         if (i < m && c < m) {
             if (i < nlock) {
@@ -322,10 +336,10 @@ __device__ __forceinline__ void ritz_body(const double* __restrict__ alpha,
         Vr[t] = (i == c) ? 1.0 : 0.0;
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < m * m; t += blockDim.x) out.B[t] = W[(t / m) * mp + (t % m)];
-    jacobi_sweeps(W, Vr, mp);
+    for (int t = threadIdx.x; t < m * m; t += blockDim.x) out.B[t] = W[(t / m) * ld + (t % m)];
+    jacobi_sweeps(W, Vr, mp, ld, dn);
     __syncthreads();
-    extract_sorted(W, Vr, m, mp, sig, order, out.P, m, out.S, out.Q, m);
+    extract_sorted(W, Vr, m, mp, ld, sig, order, out.P, m, out.S, out.Q, m);
     __syncthreads();
     if (threadIdx.x == 0) {
         const double bl = beta[m - 1];
@@ -352,11 +366,13 @@ ritz_kernel(const double* __restrict__ alpha, const double* __restrict__ beta,
 {
     extern __shared__ double lds[];
     const int mp = m + (m & 1);
+    const int ld = svd_ld(mp);
     double* W = kLds ? lds : gscratch;
-    double* Vr = W + mp * mp;
-    double* sig = Vr + mp * mp;
-    int* order = reinterpret_cast<int*>(sig + mp);
-    ritz_body(alpha, beta, theta, rho, nlock, m, k, tol, out, W, Vr, sig, order);
+    double* Vr = W + ld * mp;
+    double* sig = Vr + ld * mp;
+    double* dn = sig + mp;
+    int* order = reinterpret_cast<int*>(dn + mp);
+    ritz_body(alpha, beta, theta, rho, nlock, m, k, tol, out, W, Vr, sig, dn, order);
 }
 
 // One workgroup per problem of a batch.
@@ -369,11 +385,13 @@ ritz_batched_kernel(const BatchRitzArgs* __restrict__ args, int nlock, int m, in
     const BatchRitzArgs& a = args[blockIdx.x];
     if (!a.run) return;
     const int mp = m + (m & 1);
+    const int ld = svd_ld(mp);
     double* W = kLds ? lds : gscratch + (int64_t)blockIdx.x * gstride;
-    double* Vr = W + mp * mp;
-    double* sig = Vr + mp * mp;
-    int* order = reinterpret_cast<int*>(sig + mp);
-    ritz_body(a.alpha, a.beta, a.theta, a.rho, nlock, m, k, tol, a.out, W, Vr, sig, order);
+    double* Vr = W + ld * mp;
+    double* sig = Vr + ld * mp;
+    double* dn = sig + mp;
+    int* order = reinterpret_cast<int*>(dn + mp);
+    ritz_body(a.alpha, a.beta, a.theta, a.rho, nlock, m, k, tol, a.out, W, Vr, sig, dn, order);
 }
 
 void launch_ritz(const double* alpha, const double* beta, const double* theta, const double* rho,
