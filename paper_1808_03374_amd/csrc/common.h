@@ -62,6 +62,30 @@ __device__ __forceinline__ double block_sum(double v, double* scratch)
     return t;
 }
 
+// Sum of x[q * stride] for q = 0 .. count - 1, added in increasing q exactly as
+// a plain loop would (same result bit for bit), with the loads issued eight at
+// a time: indices past count re-read element count - 1 and are not added.
+// With kPair each term is x[q * stride] + x[q * stride + pair_off].
+template <bool kPair = false>
+__device__ __forceinline__ double strided_sum(const double* __restrict__ x, int64_t stride,
+                                              int count, int64_t pair_off = 0)
+{
+    double s = 0.0;
+    for (int b = 0; b < count; b += 8) {
+        double v[8], w[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t q = b + u < count ? b + u : count - 1;
+            v[u] = x[q * stride];
+            if (kPair) w[u] = x[q * stride + pair_off];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (b + u < count) s += kPair ? v[u] + w[u] : v[u];
+    }
+    return s;
+}
+
 // "Last block reduces" handshake for two-stage deterministic reductions: each
 // block writes its partials, then calls this; exactly one block (the last to
 // arrive) gets true and may read every block's partials.  The counter is

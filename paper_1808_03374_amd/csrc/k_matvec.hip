@@ -407,8 +407,7 @@ __global__ void rmatvec_reduce_kernel(const double* __restrict__ partial, int64_
     double ss = 0.0;
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < p;
          j += (int64_t)gridDim.x * blockDim.x) {
-        double s = 0.0;
-        for (int sp = 0; sp < nsplit; ++sp) s += partial[(int64_t)sp * pP + j];
+        const double s = strided_sum(partial + j, pP, nsplit);
         double r = inv_sd[j] * s;
         if (vprev) r -= a * vprev[j];
         z[j] = r;
@@ -668,8 +667,7 @@ brmatvec_reduce_kernel(const BatchDesc* __restrict__ desc, const int* __restrict
     const int64_t jj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (jj >= D.p) return;
     const int j = state[0];
-    double s = 0.0;
-    for (int sp = 0; sp < D.rmv_nsplit; ++sp) s += D.partial[(int64_t)sp * D.pP + jj];
+    const double s = strided_sum(D.partial + jj, D.pP, D.rmv_nsplit);
     double r = D.inv_sd[jj] * s;
     r -= D.alpha[j] * D.V[(int64_t)j * D.p + jj];
     D.V[(int64_t)(j + 1) * D.p + jj] = r;

@@ -513,11 +513,7 @@ matmat_reduce_kernel(const double* __restrict__ partial, int nsplit, int64_t nI,
     const int64_t i = t >> 4;
     const int c = (int)(t & 15);
     if (c >= nb) return;
-    double s = 0.0;
-    for (int sp = 0; sp < nsplit; ++sp) {
-        const double* pr = partial + ((int64_t)sp * nI + i) * 16;
-        s += kPack ? pr[c] + pr[c + 8] : pr[c];
-    }
+    const double s = strided_sum<kPack>(partial + i * 16 + c, nI * 16, nsplit, 8);
     Y[(int64_t)c * ldy + i] = s - K2[c];
 }
 
@@ -628,13 +624,8 @@ rmatmat_reduce_kernel(const double* __restrict__ partial, int nsplit, int64_t pS
     const int64_t j = t >> 4;
     const int c = (int)(t & 15);
     if (c >= nb) return;
-    double sc = 0.0, sm = 0.0;
-    for (int sp = 0; sp < nsplit; ++sp) {
-        const double* pc = partial + ((int64_t)sp * 2 * pS + j) * 16;
-        const double* pm = partial + ((int64_t)sp * 2 * pS + pS + j) * 16;
-        sc += kPack ? pc[c] + pc[c + 8] : pc[c];
-        sm += kPack ? pm[c] + pm[c + 8] : pm[c];
-    }
+    const double sc = strided_sum<kPack>(partial + j * 16 + c, 2 * pS * 16, nsplit, 8);
+    const double sm = strided_sum<kPack>(partial + (pS + j) * 16 + c, 2 * pS * 16, nsplit, 8);
     const double mu = mean[j];
     Z[(int64_t)c * ldz + j] = inv_sd[j] * (sc - mu * T[c] + mu * sm);
 }
@@ -826,8 +817,7 @@ matmat_i8_reduce_kernel(const double* __restrict__ partial, int nsplit, int64_t 
     const int64_t i = t >> 4;
     const int c = (int)(t & 15);
     if (c >= nb) return;
-    double s = 0.0;
-    for (int sp = 0; sp < nsplit; ++sp) s += partial[((int64_t)sp * nI + i) * 16 + c];
+    const double s = strided_sum(partial + i * 16 + c, nI * 16, nsplit);
     Y[(int64_t)c * ldy + i] = ldexp(s, ex[c] - kQBits) - K2[c];
 }
 
@@ -915,11 +905,8 @@ rmatmat_i8_reduce_kernel(const double* __restrict__ partial, int nsplit, int64_t
     const int64_t j = t >> 4;
     const int c = (int)(t & 15);
     if (c >= nb) return;
-    double sc = 0.0, sm = 0.0;
-    for (int sp = 0; sp < nsplit; ++sp) {
-        sc += partial[((int64_t)sp * 2 * pS + j) * 16 + c];
-        sm += partial[((int64_t)sp * 2 * pS + pS + j) * 16 + c];
-    }
+    const double sc = strided_sum(partial + j * 16 + c, 2 * pS * 16, nsplit);
+    const double sm = strided_sum(partial + (pS + j) * 16 + c, 2 * pS * 16, nsplit);
     const double mu = mean[j];
     const double u = ldexp(sc + (mu - 3.0) * sm, ex[c] - kQBits);
     Z[(int64_t)c * ldz + j] = inv_sd[j] * (u - mu * T[c]);
