@@ -86,10 +86,14 @@ __device__ __forceinline__ bool jacobi_rotation(double sab, double saa, double s
 }
 
 // Column stride of the working arrays: rows are padded with zeros to a
-// multiple of the 16-lane group when mp <= 64 (every lane then holds exactly
+// multiple of the 16-lane group when mp <= 96 (every lane then holds exactly
 // svd_elems(mp) elements of a column and loads them unconditionally), else mp.
+constexpr int kMaxPadElems = 6;
 __host__ __device__ inline int svd_elems(int mp) { return (mp + kGroup - 1) / kGroup; }
-__host__ __device__ inline int svd_ld(int mp) { return mp <= 4 * kGroup ? kGroup * svd_elems(mp) : mp; }
+__host__ __device__ inline int svd_ld(int mp)
+{
+    return mp <= kMaxPadElems * kGroup ? kGroup * svd_elems(mp) : mp;
+}
 
 // W (ld x mp, column-major) is replaced by B Q = P S; Vr accumulates Q.  mp is
 // even (a zero column pads odd m); rows past mp are zero and stay zero.  Column
@@ -195,6 +199,8 @@ __device__ __forceinline__ void jacobi_sweeps(double* W, double* Vr, int mp, int
     case 2: jacobi_sweeps_t<2>(W, Vr, mp, ld, dn); break;
     case 3: jacobi_sweeps_t<3>(W, Vr, mp, ld, dn); break;
     case 4: jacobi_sweeps_t<4>(W, Vr, mp, ld, dn); break;
+    case 5: jacobi_sweeps_t<5>(W, Vr, mp, ld, dn); break;
+    case 6: jacobi_sweeps_t<6>(W, Vr, mp, ld, dn); break;
     default: jacobi_sweeps_t<0>(W, Vr, mp, ld, dn); break;
     }
 }
