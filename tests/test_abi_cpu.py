@@ -52,6 +52,8 @@ def test_create_rejects_bad_arguments(args, msg):
     ("ld_bytes", 2, "ld_bytes"),
     ("block_width", 33, "block_width"),
     ("precision", 5, "precision"),
+    ("precision", 3, "precision"),
+    ("precision", -1, "precision"),
     ("keep", 1, "keep"),
 ])
 def test_create_ex_rejects_bad_options(field, value, msg):
@@ -100,6 +102,7 @@ def _batched(count, ns, ps, k=2, tol=1e-8, reorth=0, **fields):
     ((2, [10, 10], [10, 3]), {}, gk.GKL_ERR_INVALID, "k must"),
     ((1, [10], [10]), {"krylov_dim": 2}, gk.GKL_ERR_INVALID, "krylov_dim"),
     ((1, [10], [10]), {"precision": 1}, gk.GKL_ERR_UNSUPPORTED, "FP64"),
+    ((1, [10], [10]), {"precision": 2}, gk.GKL_ERR_UNSUPPORTED, "FP64"),
 ])
 def test_create_batched_rejects_bad_arguments(args, fields, status, msg):
     count, ns, ps = args
