@@ -78,7 +78,7 @@ enum gkl_precision { GKL_PREC_FP64 = 0, GKL_PREC_MIXED = 1, GKL_PREC_MIXED_INT8 
 typedef struct gkl_options {
     uint32_t struct_size;     /* sizeof(gkl_options), set by gkl_options_default */
     int32_t krylov_dim;       /* m, vectors kept before a thick restart; 0 = no restart
-                                 (FP64), or max(96, 3k + b) rounded to b (blocked) */
+                                 (FP64), or max(128, 3k + b) rounded to b (blocked) */
     int32_t keep;             /* l, Ritz vectors kept at a restart; 0 = k + (m - k)/2
                                  (FP64) or k + (m - k)/4 (blocked) */
     int32_t precision;        /* gkl_precision */

@@ -12,6 +12,7 @@ namespace gkl {
 
 constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kMaxKrylov = 96;     // largest projected matrix the in-LDS SVD handles
+constexpr int kMaxBlockedKrylov = 128;  // largest projected matrix whose SVD runs in LDS with logged rotations
 
 // ---------------------------------------------------------------------------
 // Error plumbing: internal code throws gkl::Error, the ABI layer converts it.

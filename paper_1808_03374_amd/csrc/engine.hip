@@ -798,16 +798,23 @@ gkl_status gkl_dense_svd(const double* B, int32_t m, double* P, double* S, doubl
     try {
         hipStream_t s = static_cast<hipStream_t>(stream);
         double* scratch = nullptr;
-        if (!svd_fits_lds(m))
-            GKL_HIP(hipMalloc(&scratch, sizeof(double) * svd_scratch_elems(m)));
+        double* rlog = nullptr;
+        if (!svd_fits_lds(m)) {
+            if (svd_logged_fits_lds(m))
+                GKL_HIP(hipMalloc(&rlog, sizeof(double) * svd_log_elems(m)));
+            else
+                GKL_HIP(hipMalloc(&scratch, sizeof(double) * svd_scratch_elems(m)));
+        }
         try {
-            launch_dense_svd(B, m, P, S, Q, scratch, s);
+            launch_dense_svd(B, m, P, S, Q, scratch, s, rlog);
             GKL_HIP(hipStreamSynchronize(s));
         } catch (...) {
             if (scratch) (void)hipFree(scratch);
+            if (rlog) (void)hipFree(rlog);
             throw;
         }
         if (scratch) GKL_HIP(hipFree(scratch));
+        if (rlog) GKL_HIP(hipFree(rlog));
         return GKL_OK;
     } catch (const Error& e) {
         return set_error(nullptr, e.status, e.msg);

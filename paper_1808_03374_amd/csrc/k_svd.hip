@@ -86,9 +86,9 @@ __device__ __forceinline__ bool jacobi_rotation(double sab, double saa, double s
 }
 
 // Column stride of the working arrays: rows are padded with zeros to a
-// multiple of the 16-lane group when mp <= 96 (every lane then holds exactly
+// multiple of the 16-lane group when mp <= 128 (every lane then holds exactly
 // svd_elems(mp) elements of a column and loads them unconditionally), else mp.
-constexpr int kMaxPadElems = 6;
+constexpr int kMaxPadElems = 8;
 __host__ __device__ inline int svd_elems(int mp) { return (mp + kGroup - 1) / kGroup; }
 __host__ __device__ inline int svd_ld(int mp)
 {
@@ -101,8 +101,14 @@ __host__ __device__ inline int svd_ld(int mp)
 // rotation (d_p -= t c, d_q += t c), so a pair needs one reduction (its inner
 // product).  Returns after a sweep without rotations.  kJ > 0: ld = 16 kJ and
 // every lane holds kJ elements of each column of its pair in registers.
-template <int kJ>
-__device__ __forceinline__ void jacobi_sweeps_t(double* W, double* Vr, int mp, int ld, double* dn)
+// kLog: Vr is not touched; instead every pair of every round writes its
+// rotation (cs, sn), or (1, 0) when it is not rotated, to
+// rlog[2 ((sweep ring + round) npairs + pair)], for replay_rotations.  Returns
+// the number of sweeps that rotated at least one pair (all sweeps before the
+// last when the last had no rotation).
+template <int kJ, bool kLog>
+__device__ __forceinline__ int jacobi_sweeps_t(double* W, double* Vr, int mp, int ld, double* dn,
+                                               double* __restrict__ rlog)
 {
     __shared__ int rotated;
     const int g = threadIdx.x / kGroup;
@@ -111,7 +117,8 @@ __device__ __forceinline__ void jacobi_sweeps_t(double* W, double* Vr, int mp, i
     const int ring = mp - 1;
     // rotation threshold sqrt(m) * eps (the usual one-sided Jacobi test)
     const double tol = 2.220446049250313e-16 * sqrt((double)mp);
-    for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
+    int sweep = 0;
+    for (; sweep < kMaxSweeps; ++sweep) {
         for (int c = g; c < mp; c += kGroups) {
             const double* wc = W + (int64_t)c * ld;
             double a = 0.0;
@@ -137,8 +144,9 @@ __device__ __forceinline__ void jacobi_sweeps_t(double* W, double* Vr, int mp, i
                 if (a > b) { const int tmp = a; a = b; b = tmp; }
                 double* xa = W + (int64_t)a * ld;
                 double* xb = W + (int64_t)b * ld;
-                double* ya = Vr + (int64_t)a * ld;
-                double* yb = Vr + (int64_t)b * ld;
+                double* ya = kLog ? nullptr : Vr + (int64_t)a * ld;
+                double* yb = kLog ? nullptr : Vr + (int64_t)b * ld;
+                double* lg = kLog ? rlog + 2 * (((int64_t)sweep * ring + r) * npairs + k) : nullptr;
                 const double saa = dn[a], sbb = dn[b];
                 double t, cs, sn, sab = 0.0;
                 if (kJ > 0) {
@@ -151,20 +159,29 @@ __device__ __forceinline__ void jacobi_sweeps_t(double* W, double* Vr, int mp, i
                         const int i = gl + j * kGroup;
                         u[j] = xa[i];
                         v[j] = xb[i];
-                        pa[j] = ya[i];
-                        pb[j] = yb[i];
+                        if (!kLog) {
+                            pa[j] = ya[i];
+                            pb[j] = yb[i];
+                        }
                     }
 #pragma unroll
                     for (int j = 0; j < kE; ++j) sab = fma(u[j], v[j], sab);
                     sab = group_sum(sab);
-                    if (!jacobi_rotation(sab, saa, sbb, tol, t, cs, sn)) continue;
+                    const bool rot = jacobi_rotation(sab, saa, sbb, tol, t, cs, sn);
+                    if (kLog && gl == 0) {
+                        lg[0] = rot ? cs : 1.0;
+                        lg[1] = rot ? sn : 0.0;
+                    }
+                    if (!rot) continue;
 #pragma unroll
                     for (int j = 0; j < kE; ++j) {
                         const int i = gl + j * kGroup;
                         xa[i] = cs * u[j] - sn * v[j];
                         xb[i] = sn * u[j] + cs * v[j];
-                        ya[i] = cs * pa[j] - sn * pb[j];
-                        yb[i] = sn * pa[j] + cs * pb[j];
+                        if (!kLog) {
+                            ya[i] = cs * pa[j] - sn * pb[j];
+                            yb[i] = sn * pa[j] + cs * pb[j];
+                        }
                     }
                 } else {
                     for (int i = gl; i < mp; i += kGroup) sab = fma(xa[i], xb[i], sab);
@@ -190,28 +207,106 @@ __device__ __forceinline__ void jacobi_sweeps_t(double* W, double* Vr, int mp, i
         if (!rotated) break;
         __syncthreads();
     }
+    return sweep;
 }
 
 __device__ __forceinline__ void jacobi_sweeps(double* W, double* Vr, int mp, int ld, double* dn)
 {
     switch (ld == kGroup * svd_elems(mp) ? svd_elems(mp) : 0) {
-    case 1: jacobi_sweeps_t<1>(W, Vr, mp, ld, dn); break;
-    case 2: jacobi_sweeps_t<2>(W, Vr, mp, ld, dn); break;
-    case 3: jacobi_sweeps_t<3>(W, Vr, mp, ld, dn); break;
-    case 4: jacobi_sweeps_t<4>(W, Vr, mp, ld, dn); break;
-    case 5: jacobi_sweeps_t<5>(W, Vr, mp, ld, dn); break;
-    case 6: jacobi_sweeps_t<6>(W, Vr, mp, ld, dn); break;
-    default: jacobi_sweeps_t<0>(W, Vr, mp, ld, dn); break;
+    case 1: jacobi_sweeps_t<1, false>(W, Vr, mp, ld, dn, nullptr); break;
+    case 2: jacobi_sweeps_t<2, false>(W, Vr, mp, ld, dn, nullptr); break;
+    case 3: jacobi_sweeps_t<3, false>(W, Vr, mp, ld, dn, nullptr); break;
+    case 4: jacobi_sweeps_t<4, false>(W, Vr, mp, ld, dn, nullptr); break;
+    case 5: jacobi_sweeps_t<5, false>(W, Vr, mp, ld, dn, nullptr); break;
+    case 6: jacobi_sweeps_t<6, false>(W, Vr, mp, ld, dn, nullptr); break;
+    case 7: jacobi_sweeps_t<7, false>(W, Vr, mp, ld, dn, nullptr); break;
+    case 8: jacobi_sweeps_t<8, false>(W, Vr, mp, ld, dn, nullptr); break;
+    default: jacobi_sweeps_t<0, false>(W, Vr, mp, ld, dn, nullptr); break;
     }
 }
 
+// Applies the logged rotations of nsw sweeps to Vr (ld = 16 kJ, starting from
+// the identity) in the order the sweeps made them, so Vr ends bit for bit as
+// if it had been rotated along with W.  One 16-lane group per pair (mp <= 2 x
+// the groups); each group fetches its next rotation while applying the current
+// one.  Identity entries are skipped, as the sweeps skipped those pairs.
+template <int kJ>
+__device__ __forceinline__ void replay_rotations_t(double* Vr, int mp, int ld,
+                                                   const double* __restrict__ rlog, int nsw)
+{
+    const int g = threadIdx.x / kGroup;
+    const int gl = threadIdx.x % kGroup;
+    const int npairs = mp / 2;
+    const int ring = mp - 1;
+    const bool act = g < npairs;
+    const int total = nsw * ring;
+    double ncs = 1.0, nsn = 0.0;
+    if (act && total > 0) {
+        ncs = rlog[2 * g];
+        nsn = rlog[2 * g + 1];
+    }
+    for (int step = 0; step < total; ++step) {
+        const double cs = ncs, sn = nsn;
+        if (act && step + 1 < total) {
+            const double* nx = rlog + 2 * ((int64_t)(step + 1) * npairs + g);
+            ncs = nx[0];
+            nsn = nx[1];
+        }
+        const int r = step % ring;
+        if (act && !(cs == 1.0 && sn == 0.0)) {
+            int a, b;
+            if (g == 0) {
+                a = ring;
+                b = r;
+            } else {
+                a = r + g;
+                if (a >= ring) a -= ring;
+                b = r - g;
+                if (b < 0) b += ring;
+            }
+            if (a > b) { const int tmp = a; a = b; b = tmp; }
+            double* ya = Vr + (int64_t)a * ld;
+            double* yb = Vr + (int64_t)b * ld;
+            double pa[kJ], pb[kJ];
+#pragma unroll
+            for (int j = 0; j < kJ; ++j) {
+                pa[j] = ya[gl + j * kGroup];
+                pb[j] = yb[gl + j * kGroup];
+            }
+#pragma unroll
+            for (int j = 0; j < kJ; ++j) {
+                ya[gl + j * kGroup] = cs * pa[j] - sn * pb[j];
+                yb[gl + j * kGroup] = sn * pa[j] + cs * pb[j];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Jacobi on W alone with the rotations logged, for 96 < mp <= 128 (ld = 16 kJ).
+__device__ __forceinline__ int jacobi_sweeps_logged(double* W, int mp, int ld, double* dn,
+                                                    double* rlog)
+{
+    return svd_elems(mp) == 7 ? jacobi_sweeps_t<7, true>(W, nullptr, mp, ld, dn, rlog)
+                              : jacobi_sweeps_t<8, true>(W, nullptr, mp, ld, dn, rlog);
+}
+
+__device__ __forceinline__ void replay_rotations(double* Vr, int mp, int ld, const double* rlog,
+                                                 int nsw)
+{
+    if (svd_elems(mp) == 7) replay_rotations_t<7>(Vr, mp, ld, rlog, nsw);
+    else replay_rotations_t<8>(Vr, mp, ld, rlog, nsw);
+}
+
 // After jacobi_sweeps: singular values are the column norms of W; write the
-// m leading (sorted descending) triplets.
+// m leading (sorted descending) triplets.  With W == NULL only Q is written
+// (from Vr), using the norms and order of an earlier call; with Vr == NULL only
+// P and S.
 __device__ __forceinline__ void extract_sorted(const double* W, const double* Vr, int m, int mp,
                                                int ld, double* sig, int* order, double* P,
                                                int ldp_, double* S, double* Q, int ldq_)
 {
-    for (int c = threadIdx.x / kGroup; c < mp; c += kGroups) {
+    for (int c = threadIdx.x / kGroup; W && c < mp; c += kGroups) {
         const double* wc = W + (int64_t)c * ld;
         double s = 0.0;
         for (int i = threadIdx.x % kGroup; i < mp; i += kGroup) s = fma(wc[i], wc[i], s);
@@ -221,7 +316,7 @@ __device__ __forceinline__ void extract_sorted(const double* W, const double* Vr
     __syncthreads();
     // rank by value (ties broken by index) -> stable descending order.  A NaN
     // norm ranks as -1 so that the ranks stay a permutation whatever the input.
-    for (int c = threadIdx.x; c < mp; c += blockDim.x) {
+    for (int c = threadIdx.x; W && c < mp; c += blockDim.x) {
         int rank = 0;
         const double sc = isnan(sig[c]) ? -1.0 : sig[c];
         for (int d = 0; d < mp; ++d) {
@@ -235,10 +330,10 @@ __device__ __forceinline__ void extract_sorted(const double* W, const double* Vr
         const int i = t % m, o = t / m;     // row i of output column o
         const int c = order[o];
         const double s = sig[c];
-        P[(int64_t)o * ldp_ + i] = s > 0.0 ? W[(int64_t)c * ld + i] / s : (i == o ? 1.0 : 0.0);
-        Q[(int64_t)o * ldq_ + i] = Vr[(int64_t)c * ld + i];
+        if (W) P[(int64_t)o * ldp_ + i] = s > 0.0 ? W[(int64_t)c * ld + i] / s : (i == o ? 1.0 : 0.0);
+        if (Vr) Q[(int64_t)o * ldq_ + i] = Vr[(int64_t)c * ld + i];
     }
-    for (int o = threadIdx.x; o < m; o += blockDim.x) S[o] = sig[order[o]];
+    for (int o = threadIdx.x; W && o < m; o += blockDim.x) S[o] = sig[order[o]];
 }
 
 }  // namespace
@@ -248,11 +343,34 @@ __device__ __forceinline__ void extract_sorted(const double* W, const double* Vr
 template <bool kLds>
 __global__ void __launch_bounds__(kSvdThreads)
 dense_svd_kernel(const double* __restrict__ B, int m, double* __restrict__ P,
-                 double* __restrict__ S, double* __restrict__ Q, double* gscratch)
+                 double* __restrict__ S, double* __restrict__ Q, double* gscratch, double* rlog)
 {
     extern __shared__ double lds[];
     const int mp = m + (m & 1);
     const int ld = svd_ld(mp);
+    if (kLds && rlog) {
+        // W alone in LDS; Vr is rebuilt in the same space from the rotation log
+        double* W = lds;
+        double* sig = W + ld * mp;
+        double* dn = sig + mp;
+        int* order = reinterpret_cast<int*>(dn + mp);
+        for (int t = threadIdx.x; t < ld * mp; t += blockDim.x) {
+            const int i = t % ld, c = t / ld;
+            W[t] = (i < m && c < m) ? B[(int64_t)c * m + i] : 0.0;
+        }
+        __syncthreads();
+        const int nsw = jacobi_sweeps_logged(W, mp, ld, dn, rlog);
+        __syncthreads();
+        extract_sorted(W, nullptr, m, mp, ld, sig, order, P, m, S, nullptr, m);
+        __syncthreads();
+        for (int t = threadIdx.x; t < ld * mp; t += blockDim.x) W[t] = (t % ld == t / ld) ? 1.0 : 0.0;
+        __threadfence_block();
+        __syncthreads();
+        replay_rotations(W, mp, ld, rlog, nsw);
+        __syncthreads();
+        extract_sorted(nullptr, W, m, mp, ld, sig, order, nullptr, m, nullptr, Q, m);
+        return;
+    }
     double* W = kLds ? lds : gscratch;
     double* Vr = W + ld * mp;
     double* sig = Vr + ld * mp;
@@ -277,9 +395,22 @@ static size_t svd_lds_bytes(int m)
            sizeof(int) * (size_t)mp;
 }
 
+// The logged path: W (ld x mp), sig and dn (mp each), order (mp ints).
+static size_t svd_logged_lds_bytes(int m)
+{
+    const int mp = m + (m & 1);
+    return sizeof(double) * ((size_t)svd_ld(mp) * mp + 2 * (size_t)mp) + sizeof(int) * (size_t)mp;
+}
+
+size_t svd_log_elems(int m)
+{
+    const int mp = m + (m & 1);
+    return 2 * (size_t)kMaxSweeps * (size_t)(mp - 1) * (size_t)(mp / 2);
+}
+
 size_t svd_scratch_elems(int m) { return svd_lds_bytes(m) / sizeof(double) + 1; }
 
-bool svd_fits_lds(int m)
+static int svd_lds_limit()
 {
     static int limit = -1;
     if (limit < 0) {
@@ -289,8 +420,20 @@ bool svd_fits_lds(int m)
             v = 65536;
         limit = v;
     }
-    // the kernels' static LDS (flags, reduction scratch) needs room beside the arrays
-    return m <= kMaxKrylov && svd_lds_bytes(m) + 256 <= (size_t)limit;
+    return limit;
+}
+
+// the kernels' static LDS (flags, reduction scratch) needs room beside the arrays
+bool svd_fits_lds(int m)
+{
+    return m <= kMaxKrylov && svd_lds_bytes(m) + 256 <= (size_t)svd_lds_limit();
+}
+
+bool svd_logged_fits_lds(int m)
+{
+    const int mp = m + (m & 1);
+    return mp <= kMaxPadElems * kGroup && mp <= 2 * kGroups &&
+           svd_logged_lds_bytes(m) + 256 <= (size_t)svd_lds_limit();
 }
 
 static void check_svd_size(int m, const double* gscratch)
@@ -301,17 +444,20 @@ static void check_svd_size(int m, const double* gscratch)
 }
 
 void launch_dense_svd(const double* B, int m, double* P, double* S, double* Q, double* gscratch,
-                      hipStream_t s)
+                      hipStream_t s, double* rlog)
 {
-    check_svd_size(m, gscratch);
-    const bool global = !svd_fits_lds(m);
-    const size_t lds = global ? 0 : svd_lds_bytes(m);
-    if (global)
+    if (m < 1 || m > kMaxSvd) fail(GKL_ERR_INVALID, "projected matrix size out of range");
+    if (svd_fits_lds(m)) {
+        hipLaunchKernelGGL(dense_svd_kernel<true>, dim3(1), dim3(kSvdThreads), svd_lds_bytes(m), s,
+                           B, m, P, S, Q, nullptr, nullptr);
+    } else if (rlog && svd_logged_fits_lds(m)) {
+        hipLaunchKernelGGL(dense_svd_kernel<true>, dim3(1), dim3(kSvdThreads),
+                           svd_logged_lds_bytes(m), s, B, m, P, S, Q, nullptr, rlog);
+    } else {
+        if (!gscratch) fail(GKL_ERR_INTERNAL, "large projected matrix needs a global scratch buffer");
         hipLaunchKernelGGL(dense_svd_kernel<false>, dim3(1), dim3(kSvdThreads), 0, s, B, m, P, S,
-                           Q, gscratch);
-    else
-        hipLaunchKernelGGL(dense_svd_kernel<true>, dim3(1), dim3(kSvdThreads), lds, s, B, m, P, S,
-                           Q, nullptr);
+                           Q, gscratch, nullptr);
+    }
     GKL_LAUNCH_CHECK("dense_svd_kernel");
 }
 

@@ -184,12 +184,17 @@ void launch_sign_fix(double* U, int64_t ldu, int64_t n, double* V, int64_t ldv, 
                      int k, hipStream_t s);
 
 // ---- k_svd.hip: Ritz extraction ----
-// One-sided Jacobi SVD of a dense m x m matrix (m <= kMaxKrylov) in one workgroup:
-// B = P diag(S) Q^T, S descending.
-// For m > kMaxKrylov the working matrices live in `gscratch` (device, at least
-// svd_scratch_elems(m) doubles); otherwise in LDS and gscratch may be NULL.
+// One-sided Jacobi SVD of a dense m x m matrix in one workgroup:
+// B = P diag(S) Q^T, S descending.  Up to kMaxKrylov the matrix and the
+// accumulated rotations live in LDS.  Beyond that, with `rlog` (device, at
+// least svd_log_elems(m) doubles) and svd_logged_fits_lds(m), only the matrix
+// lives in LDS: the rotations are logged and replayed onto Q afterwards (same
+// result bit for bit).  Otherwise the working matrices live in `gscratch`
+// (device, at least svd_scratch_elems(m) doubles).
 void launch_dense_svd(const double* B, int m, double* P, double* S, double* Q, double* gscratch,
-                      hipStream_t s);
+                      hipStream_t s, double* rlog = nullptr);
+size_t svd_log_elems(int m);
+bool svd_logged_fits_lds(int m);
 size_t svd_scratch_elems(int m);
 // True when the m x m SVD working set fits the device's LDS per workgroup.
 bool svd_fits_lds(int m);

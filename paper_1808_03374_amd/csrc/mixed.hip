@@ -45,6 +45,7 @@ struct MixedState {
     double* tmp = nullptr;     // max(n, p) x keep
     double* gpart = nullptr;
     double* svd_scratch = nullptr;
+    double* svd_log = nullptr;         // rotation log of the SVD for 96 < m <= 128
     int* iflags = nullptr;     // [0] nconv [1] bad pivots
     RitzOut ritz{};
 };
@@ -63,13 +64,15 @@ void gkl_ctx::setup_mixed()
     DeviceArena& A = prob.arena;
     hipStream_t s = prob.stream;
     const int64_t n = prob.n, p = prob.p;
-    // Defaults (measured on 10,000 x 100,000 genotypes, k = 20): block width 8,
-    // a basis of 96 columns (the largest projected matrix whose SVD runs in LDS)
-    // and a quarter of the free columns kept at a restart.
+    // Defaults (measured on 10,000 x 100,000 and 50,000 x 500,000 genotypes,
+    // k = 20): block width 8, a basis of 128 columns (the largest projected
+    // matrix whose SVD runs in LDS, with its rotations logged and replayed; 1.4x
+    // faster than 96 columns at the larger size, the same at the smaller) and a
+    // quarter of the free columns kept at a restart.
     M.b = opt.block_width > 0 ? opt.block_width : 8;
     if (M.b > 32) fail(GKL_ERR_INVALID, "block_width must be <= 32");
     const int64_t mn = std::min(n, p);
-    int m = opt.krylov_dim > 0 ? opt.krylov_dim : std::max(kMaxKrylov, 3 * k + M.b);
+    int m = opt.krylov_dim > 0 ? opt.krylov_dim : std::max(kMaxBlockedKrylov, 3 * k + M.b);
     m = ((m + M.b - 1) / M.b) * M.b;
     if (m > mn) m = (int)(mn / M.b) * M.b;
     if (m < 2 * M.b || m <= k) fail(GKL_ERR_INVALID, "problem too small for the blocked solver");
@@ -108,8 +111,12 @@ void gkl_ctx::setup_mixed()
     M.ritz.S = static_cast<double*>(A.alloc(sizeof(double) * m));
     M.ritz.res = static_cast<double*>(A.alloc(sizeof(double) * m));
     M.ritz.nconv = M.iflags;
-    M.svd_scratch = svd_fits_lds(m) ? nullptr
-                                    : static_cast<double*>(A.alloc(sizeof(double) * svd_scratch_elems(m)));
+    if (!svd_fits_lds(m)) {
+        if (svd_logged_fits_lds(m))
+            M.svd_log = static_cast<double*>(A.alloc(sizeof(double) * svd_log_elems(m)));
+        else
+            M.svd_scratch = static_cast<double*>(A.alloc(sizeof(double) * svd_scratch_elems(m)));
+    }
     GKL_HIP(hipMemsetAsync(M.iflags, 0, sizeof(int) * 8, s));
     maxm = m;
     keep = M.keep;
@@ -190,7 +197,7 @@ gkl_status gkl_ctx::solve_mixed(double* sigma, double* Uo, int64_t ldu, double* 
         if (mcur >= k && (full || budget || since_check >= check_every)) {
             since_check = 0;
             launch_copy_lead(M.Bm, M.ldb, mcur, M.Bc, s);
-            launch_dense_svd(M.Bc, mcur, M.ritz.P, M.ritz.S, M.ritz.Q, M.svd_scratch, s);
+            launch_dense_svd(M.Bc, mcur, M.ritz.P, M.ritz.S, M.ritz.Q, M.svd_scratch, s, M.svd_log);
             launch_block_residual(M.C, b, M.ritz.P, mcur, M.ritz.S, k, tol, M.ritz.res,
                                   M.ritz.nconv, s);
             svd_m = mcur;
@@ -222,7 +229,7 @@ gkl_status gkl_ctx::solve_mixed(double* sigma, double* Uo, int64_t ldu, double* 
     }
     if (svd_m != mcur) {
         launch_copy_lead(M.Bm, M.ldb, mcur, M.Bc, s);
-        launch_dense_svd(M.Bc, mcur, M.ritz.P, M.ritz.S, M.ritz.Q, M.svd_scratch, s);
+        launch_dense_svd(M.Bc, mcur, M.ritz.P, M.ritz.S, M.ritz.Q, M.svd_scratch, s, M.svd_log);
         launch_block_residual(M.C, b, M.ritz.P, mcur, M.ritz.S, k, tol, M.ritz.res, M.ritz.nconv, s);
     }
     const int kk = std::min(k, mcur);

@@ -86,15 +86,22 @@ def _oracle(g, k):
     return op, oracle.gkl_svd(op, k, tol=1e-12, v0=synth.start_vector(g.p, 3))
 
 
-@pytest.mark.parametrize("name,n,p,k,b", [("c1", 1000, 5000, 10, 16), ("c3", 2000, 20000, 20, 16),
-                                          ("c2", 2000, 20000, 20, 32), ("c3", 3000, 30000, 20, 8),
-                                          ("c1", 1000, 5000, 10, 5)])
+# m: basis size (None: the default); 120 and 128 take the projected SVD whose
+# rotations are logged and replayed (more than 96 columns)
+@pytest.mark.parametrize("name,n,p,k,b,m", [("c1", 1000, 5000, 10, 16, None),
+                                            ("c3", 2000, 20000, 20, 16, None),
+                                            ("c2", 2000, 20000, 20, 32, None),
+                                            ("c3", 3000, 30000, 20, 8, None),
+                                            ("c1", 1000, 5000, 10, 5, None),
+                                            ("c3", 3000, 30000, 20, 8, 128),
+                                            ("c1", 1000, 5000, 10, 5, 120)])
 @pytest.mark.parametrize("fmt", PRECISIONS)
-def test_mixed_solve_matches_fp64_oracle(gk, name, n, p, k, b, fmt):
+def test_mixed_solve_matches_fp64_oracle(gk, name, n, p, k, b, m, fmt):
     g = synth.config(name, n=n, p=p)
     op, ref = _oracle(g, k)
+    extra = {} if m is None else {"krylov_dim": m}
     ctx = gk.Context(dev(g.packed), g.n, g.p, k, tol=1e-9, precision=prec(gk, fmt),
-                     block_width=b)
+                     block_width=b, **extra)
     sigma, U, V, st, info = ctx.solve()
     assert st == gk.GKL_OK, gk.gkl_last_error(ctx.ctx)
     sigma = sigma.cpu().numpy()

@@ -120,7 +120,7 @@ def test_matvec_full_size_sampled(gk):
     ctx.close()
 
 
-@pytest.mark.parametrize("m", [1, 2, 7, 60, 96, 150])
+@pytest.mark.parametrize("m", [1, 2, 7, 60, 96, 97, 112, 128, 129, 150])
 def test_dense_svd(gk, m):
     rng = np.random.default_rng(m)
     B = rng.standard_normal((m, m))
