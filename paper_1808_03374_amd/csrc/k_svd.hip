@@ -340,10 +340,18 @@ __device__ __forceinline__ void extract_sorted(const double* W, const double* Vr
 
 // kLds: the working arrays live in LDS (the compiler then emits LDS
 // instructions); otherwise in gscratch.
+// Leading columns of Q recovered as B^T w_c / sig_c^2 (w_c = sig_c p_c, the
+// rotated column) when the last of them has sig_c >= kRecoverRatio sig_max:
+// their error is then below eps / kRecoverRatio^2 (about 1e-13).
+constexpr double kRecoverRatio = 0.05;
+
+// qcols: leading columns of Q the caller reads (the logged path may then skip
+// the replay; columns from qcols on are left unwritten); qcols >= m: all.
 template <bool kLds>
 __global__ void __launch_bounds__(kSvdThreads)
 dense_svd_kernel(const double* __restrict__ B, int m, double* __restrict__ P,
-                 double* __restrict__ S, double* __restrict__ Q, double* gscratch, double* rlog)
+                 double* __restrict__ S, double* __restrict__ Q, double* gscratch, double* rlog,
+                 int qcols)
 {
     extern __shared__ double lds[];
     const int mp = m + (m & 1);
@@ -362,6 +370,22 @@ dense_svd_kernel(const double* __restrict__ B, int m, double* __restrict__ P,
         const int nsw = jacobi_sweeps_logged(W, mp, ld, dn, rlog);
         __syncthreads();
         extract_sorted(W, nullptr, m, mp, ld, sig, order, P, m, S, nullptr, m);
+        __syncthreads();
+        const double smax = sig[order[0]];
+        if (qcols < m && smax > 0.0 && sig[order[qcols - 1]] >= kRecoverRatio * smax) {
+            for (int t = threadIdx.x; t < m * qcols; t += blockDim.x) {
+                const int i = t % m, o = t / m;      // row i of output column o
+                const int c = order[o];
+                const double* bi = B + (int64_t)i * m;
+                const double* wc = W + (int64_t)c * ld;
+                double acc = 0.0;
+#pragma unroll 8
+                for (int r = 0; r < m; ++r) acc = fma(bi[r], wc[r], acc);
+                const double sc = sig[c];
+                Q[(int64_t)o * m + i] = acc / (sc * sc);
+            }
+            return;
+        }
         __syncthreads();
         for (int t = threadIdx.x; t < ld * mp; t += blockDim.x) W[t] = (t % ld == t / ld) ? 1.0 : 0.0;
         __threadfence_block();
@@ -444,19 +468,20 @@ static void check_svd_size(int m, const double* gscratch)
 }
 
 void launch_dense_svd(const double* B, int m, double* P, double* S, double* Q, double* gscratch,
-                      hipStream_t s, double* rlog)
+                      hipStream_t s, double* rlog, int qcols)
 {
     if (m < 1 || m > kMaxSvd) fail(GKL_ERR_INVALID, "projected matrix size out of range");
+    const int qc = qcols > 0 && qcols < m ? qcols : m;
     if (svd_fits_lds(m)) {
         hipLaunchKernelGGL(dense_svd_kernel<true>, dim3(1), dim3(kSvdThreads), svd_lds_bytes(m), s,
-                           B, m, P, S, Q, nullptr, nullptr);
+                           B, m, P, S, Q, nullptr, nullptr, m);
     } else if (rlog && svd_logged_fits_lds(m)) {
         hipLaunchKernelGGL(dense_svd_kernel<true>, dim3(1), dim3(kSvdThreads),
-                           svd_logged_lds_bytes(m), s, B, m, P, S, Q, nullptr, rlog);
+                           svd_logged_lds_bytes(m), s, B, m, P, S, Q, nullptr, rlog, qc);
     } else {
         if (!gscratch) fail(GKL_ERR_INTERNAL, "large projected matrix needs a global scratch buffer");
         hipLaunchKernelGGL(dense_svd_kernel<false>, dim3(1), dim3(kSvdThreads), 0, s, B, m, P, S,
-                           Q, gscratch, nullptr);
+                           Q, gscratch, nullptr, m);
     }
     GKL_LAUNCH_CHECK("dense_svd_kernel");
 }

@@ -190,9 +190,13 @@ void launch_sign_fix(double* U, int64_t ldu, int64_t n, double* V, int64_t ldv, 
 // least svd_log_elems(m) doubles) and svd_logged_fits_lds(m), only the matrix
 // lives in LDS: the rotations are logged and replayed onto Q afterwards (same
 // result bit for bit).  Otherwise the working matrices live in `gscratch`
-// (device, at least svd_scratch_elems(m) doubles).
+// (device, at least svd_scratch_elems(m) doubles).  qcols (0 = all): leading
+// columns of Q the caller reads; on the logged path, when the last of them has
+// a singular value of at least 5% of the largest, they are formed as
+// B^T P diag(1/S) (error below about 1e-13) instead of by the replay, and the
+// columns from qcols on are left unwritten.
 void launch_dense_svd(const double* B, int m, double* P, double* S, double* Q, double* gscratch,
-                      hipStream_t s, double* rlog = nullptr);
+                      hipStream_t s, double* rlog = nullptr, int qcols = 0);
 size_t svd_log_elems(int m);
 bool svd_logged_fits_lds(int m);
 size_t svd_scratch_elems(int m);

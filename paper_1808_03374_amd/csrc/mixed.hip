@@ -197,7 +197,8 @@ gkl_status gkl_ctx::solve_mixed(double* sigma, double* Uo, int64_t ldu, double* 
         if (mcur >= k && (full || budget || since_check >= check_every)) {
             since_check = 0;
             launch_copy_lead(M.Bm, M.ldb, mcur, M.Bc, s);
-            launch_dense_svd(M.Bc, mcur, M.ritz.P, M.ritz.S, M.ritz.Q, M.svd_scratch, s, M.svd_log);
+            launch_dense_svd(M.Bc, mcur, M.ritz.P, M.ritz.S, M.ritz.Q, M.svd_scratch, s, M.svd_log,
+                             M.keep);
             launch_block_residual(M.C, b, M.ritz.P, mcur, M.ritz.S, k, tol, M.ritz.res,
                                   M.ritz.nconv, s);
             svd_m = mcur;
@@ -229,7 +230,8 @@ gkl_status gkl_ctx::solve_mixed(double* sigma, double* Uo, int64_t ldu, double* 
     }
     if (svd_m != mcur) {
         launch_copy_lead(M.Bm, M.ldb, mcur, M.Bc, s);
-        launch_dense_svd(M.Bc, mcur, M.ritz.P, M.ritz.S, M.ritz.Q, M.svd_scratch, s, M.svd_log);
+        launch_dense_svd(M.Bc, mcur, M.ritz.P, M.ritz.S, M.ritz.Q, M.svd_scratch, s, M.svd_log,
+                             M.keep);
         launch_block_residual(M.C, b, M.ritz.P, mcur, M.ritz.S, k, tol, M.ritz.res, M.ritz.nconv, s);
     }
     const int kk = std::min(k, mcur);
