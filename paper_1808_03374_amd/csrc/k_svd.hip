@@ -8,11 +8,16 @@
 // where P holds the left singular vectors of B_j (the Table 3 caption sums these
 // bounds into ||Delta theta||_1).
 //
-// The SVD is a one-sided (Hestenes) Jacobi method run by a single workgroup
-// with the matrix and the accumulated rotations held in LDS (global scratch for
-// matrices too large for it).  Column pairs of a round-robin tournament are
-// rotated concurrently, 16 lanes per pair, with the pair's columns held in
-// registers while they are rotated; sweeps repeat until no pair needs rotating.
+// The SVD is a one-sided (Hestenes) Jacobi method run by a single workgroup.
+// Up to 96 columns the matrix and the accumulated rotations are held in LDS;
+// up to 128 columns the matrix alone is, the rotations are logged to device
+// memory and replayed onto the identity afterwards (or, when the caller needs
+// only well-separated leading columns, those are formed from the rotated
+// matrix); larger matrices work in global scratch.  Column pairs of a
+// round-robin tournament are rotated concurrently, 16 lanes per pair, with the
+// pair's columns held in registers while they are rotated (rows zero-padded to a
+// multiple of 16, so every lane's loads are unconditional); sweeps repeat until
+// no pair needs rotating.
 #include <math.h>
 
 #include "kernels.h"
