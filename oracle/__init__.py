@@ -15,6 +15,12 @@ Parity status per function (what pins it is listed in the tests):
                                   two-group closed form sigma_1 = sqrt(2np),
                                   Frobenius identity at full rank)
   mp_* densities                  pinned (unit mass, Fig. 1 printed edge, Gaussian KS)
+  sign_fix                        pinned (hand-made columns with ties and negative
+                                  maxima; the left vector flips with the right)
+  subspace_angles                 pinned (known rotations from 1.2 down to 1e-9 rad,
+                                  orthogonal and identical spans)
+  certificate                     pinned (operator with a known SVD: exact triplets,
+                                  sigma shifted by known deltas, a tilted vector)
 """
 from .gkl_oracle import (  # noqa: F401
     build_library, decode, counts, column_stats, dense_matrix, DenseOperator,

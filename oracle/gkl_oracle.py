@@ -15,7 +15,7 @@ Paper passages followed:
     of B_j); the sum of these over the top k is the paper's ||Delta theta||_1.
   * Section 4 (ARPACK paragraph): the eigenvalues of [0 X; X^T 0] are +-sigma,
     used as a pin in the tests.
-  * Section 3, eq. (mplaw-ev) and (mplaw-sv): Marchenko-Pastur densities, read
+  * Section 2, eq. (mplaw-ev) and (mplaw-sv): Marchenko-Pastur densities, read
     with denominator 2 pi sigma^2 min(1, rho) xi (eigenvalues) and
     pi sigma^2 min(1, rho) x (singular values), rho = rows / columns.
 
@@ -378,11 +378,23 @@ def certificate(op, sigma, U, V):
 
 
 def subspace_angles(X: np.ndarray, Y: np.ndarray) -> np.ndarray:
-    """Principal angles (radians) between the column spaces of X and Y."""
+    """Principal angles (radians, ascending) between the column spaces of X and Y
+    (same number of columns).
+
+    The cosines are the singular values of Qx^T Qy and the sines those of the
+    part of Qy outside span(Qx), Qy - Qx (Qx^T Qy) (Bjorck & Golub, Math. Comp.
+    1973).  The i-th smallest angle pairs the i-th largest cosine with the i-th
+    smallest sine; atan2 of the pair is accurate for every angle, where arccos of
+    the cosine alone cannot resolve angles below about 1e-8.
+    """
     qx, _ = np.linalg.qr(X)
     qy, _ = np.linalg.qr(Y)
-    c = np.linalg.svd(qx.T @ qy, compute_uv=False)
-    return np.arccos(np.clip(c, -1.0, 1.0))[::-1]
+    if qx.shape[1] != qy.shape[1]:
+        raise ValueError("subspace_angles needs subspaces of equal dimension")
+    M = qx.T @ qy
+    c = np.linalg.svd(M, compute_uv=False)                    # descending
+    s = np.linalg.svd(qy - qx @ M, compute_uv=False)[::-1]    # ascending
+    return np.arctan2(np.clip(s, 0.0, 1.0), np.clip(c, 0.0, 1.0))
 
 
 # ---------------------------------------------------------------------------

@@ -288,30 +288,35 @@ def spare_directions(p: int, count: int, seed: int) -> np.ndarray:
 
 def algorithm1_codes(rows: int, cols: int, r: int, nsignal: int, rkins: float,
                      seed: int) -> np.ndarray:
-    """The paper's random genotype model (Section 3, Algorithm 1) at a small size.
+    """The paper's crude random genotype model (Section 2, "A simple model for
+    genomics data"), built from its three-step description at a small size.
 
-    Starts from all zeros; r random rectangular sub-blocks (each spanning a random
-    contiguous row range and column range) are set to one random value in {0,1,2};
-    nsignal random entries are then set to random values in {0,1,2}; finally
-    round(rkins * rows) random rows are overwritten by copies of random rows.
+    Admixture: r rectangles, each spanning a random contiguous range of rows and
+    of columns (rectangles may overlap; later ones cover earlier ones), hold one
+    random value in {0, 1, 2} each.  Signal: nsignal uniformly random positions
+    (drawn with replacement) get random values in {0, 1, 2}; where a position is
+    drawn more than once its last draw holds.  Kinship: round(rkins * rows) rows
+    are replaced by copies of randomly chosen rows.  Reading: the copies are
+    taken from the matrix as it stands after the signal step, all at once.
     Rows are individuals here, so the copies model related individuals.
     """
     rng = np.random.default_rng([seed, 0xA161])
     M = np.zeros((rows, cols), dtype=np.int8)
-
-    def span(N):
-        a, b = rng.integers(0, N, size=2)
-        return slice(min(a, b), max(a, b) + 1)
-
-    for _ in range(r):
-        val = rng.integers(0, 3)
-        M[span(rows), span(cols)] = val
-    ri = rng.integers(0, rows, size=nsignal)
-    ci = rng.integers(0, cols, size=nsignal)
-    vals = rng.integers(0, 3, size=nsignal)
-    for a, b, v in zip(ri, ci, vals):     # sequential: later writes win, as in the model
-        M[a, b] = v
-    for _ in range(int(round(rkins * rows))):
-        dst, src = rng.integers(0, rows, size=2)
-        M[dst, :] = M[src, :]
+    # admixture: all rectangle bounds and values in one draw
+    rb = np.sort(rng.integers(0, rows, size=(r, 2)), axis=1)
+    cb = np.sort(rng.integers(0, cols, size=(r, 2)), axis=1)
+    val = rng.integers(0, 3, size=r)
+    for (r0, r1), (c0, c1), v in zip(rb, cb, val):
+        M[r0:r1 + 1, c0:c1 + 1] = v
+    # signal: flat positions; keep each position's last draw
+    pos = rng.integers(0, rows * cols, size=nsignal)
+    sval = rng.integers(0, 3, size=nsignal).astype(np.int8)
+    last = pos.size - 1 - np.unique(pos[::-1], return_index=True)[1]
+    M.reshape(-1)[pos[last]] = sval[last]
+    # kinship: destination and source rows drawn together, copies from one snapshot
+    nk = int(round(rkins * rows))
+    dst = rng.integers(0, rows, size=nk)
+    src = rng.integers(0, rows, size=nk)
+    keep = dst.size - 1 - np.unique(dst[::-1], return_index=True)[1]
+    M[dst[keep]] = M.copy()[src[keep]]
     return M

@@ -1,4 +1,4 @@
-"""Oracle pins from random-matrix theory (Section 3, eq. mplaw-ev / mplaw-sv, Figs. 1-2)
+"""Oracle pins from random-matrix theory (Section 2, eq. mplaw-ev / mplaw-sv, Figs. 1-2)
 and statistical checks of the synthetic workloads the oracle is used on."""
 import json
 import os
