@@ -1,14 +1,22 @@
 #!/usr/bin/env python3
 """Bench: top-k principal components of a packed genotype matrix on one MI355X.
 
-Workload (default): 10,000 individuals x 100,000 SNPs, five Balding-Nichols
-subpopulations (F 0.005..0.02), 2% of individuals in related pairs, MAF ~
-U(0.01, 0.5), 1% missing, 2-bit packed (250 MB); top k = 20 by FP64 GKL with
-partial reorthogonalisation (omega = 1e-8) and thick restart (basis 60).
+Workload (default): 50,000 individuals x 500,000 SNPs, ten Balding-Nichols
+subpopulations (F 0.005..0.02) plus 20% admixed individuals (Dirichlet(0.5)
+weights), MAF ~ U(0.01, 0.5), 1% missing, 2-bit packed (6.25 GB); top k = 20.
 
-A step is one pass of the hot path: gkl_create (device column statistics and
-internal layout) + gkl_solve (the Lanczos iteration to tolerance, Ritz
-extraction, output) + gkl_destroy, with the packed matrix already in HBM.
+The timed step (`value`) is one FP64 GKL solve with partial
+reorthogonalisation (omega = 1e-8) and thick restart (basis 60) to tolerance
+1e-10: gkl_create (column statistics, internal layouts) + gkl_solve (Lanczos
+iteration, Ritz extraction, output) + gkl_destroy, with the packed matrix
+already in HBM.  Beside it (`compare`) the same top-k problem is solved by the
+blocked path whose products run on the BF16 matrix cores with split (hi + lo)
+vector tiles, at block widths 8, 16 and 32, and by the FP64 path at the blocked
+path's tolerance (equal accuracy); every blocked solve reports its error
+against the FP64 solve for each sigma_i and the angle of each left and right
+singular vector.  `cpu_baseline` times the CPU oracle on a bounded sample: the
+residual certificate of the leading FP64 triplets on the full matrix.
+
 Prints one JSON line.  `value` is seconds per step (lower is better).
 """
 from __future__ import annotations
@@ -24,8 +32,19 @@ sys.path.insert(0, ROOT)
 
 METRIC = "top-k PC solve time + matvec HBM GB/s, split-BF16 blocked vs FP64 GKL"
 HBM_PEAK_GBPS = 8000.0
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+MFMA_INT8_PEAK_TOPS = 5000.0
+# product launches are bracketed with HIP events one in TIMING_STRIDE (per
+# product): a recorded event stalls the stream for a few microseconds, so
+# timing every launch would slow the timed solves themselves
+TIMING_STRIDE = 8
+BLOCKED_TOL = 1e-8
+ANGLE_TARGET = 1e-6
 
 WORKLOADS = {
+    "c3": dict(name="c3", k=20, tol=1e-10, reorth="partial", krylov_dim=60,
+               desc="50,000 x 500,000 genotypes, 10 subpopulations + 20% admixed, 1% missing; "
+                    "k=20, FP64 GKL, PRO omega=1e-8, thick restart m=60"),
     "c2": dict(name="c2", k=20, tol=1e-10, reorth="partial", krylov_dim=60,
                desc="10,000 x 100,000 genotypes, 5 subpopulations + related pairs, 1% missing; "
                     "k=20, FP64 GKL, PRO omega=1e-8, thick restart m=60"),
@@ -37,6 +56,16 @@ WORKLOADS = {
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def fp64_bytes(n, p):
+    """Algorithmic bytes of one FP64 product: the packed matrix, the vector in and out."""
+    return ((n + 3) // 4) * p + 16 * p + 16 * n
+
+
+def block_bytes(n, p, b):
+    """Algorithmic bytes of one block product of b vectors."""
+    return ((n + 3) // 4) * p + b * (4 * p + 8 * n)
 
 
 def measured_traffic(workload, kernel):
@@ -58,53 +87,112 @@ def measured_traffic(workload, kernel):
     return None if k is None else int(k["fetch"] + k["write"])
 
 
-def cpu_baseline(g, gpu_matvecs, seconds):
-    """Time the oracle (plain FP64 CPU GKL, full CGS2) on the same matrix for a
-    bounded number of steps and scale its per-product time to the GPU solve's
-    product count."""
+def vector_angles(X, Y):
+    """Angle (radians) between matching unit columns of X and Y, sign ignored:
+    atan2(|x - (x.y) y|, |x.y|) per column (accurate for tiny angles)."""
     import numpy as np
-
-    import oracle
-    import synth
-    cores = len(os.sched_getaffinity(0))
-    threads = int(os.environ.get("OMP_NUM_THREADS", cores))
-    op = oracle.PackedOperator(g.packed, g.n, g.p)
-    v0 = synth.start_vector(g.p, 1)
-    t0 = time.perf_counter()
-    oracle.gkl_svd(op, 1, tol=-1.0, v0=v0, max_steps=1)
-    t1 = time.perf_counter() - t0
-    steps = max(2, min(200, int(seconds / max(t1, 1e-6))))
-    op.matvecs = 0
-    t0 = time.perf_counter()
-    res = oracle.gkl_svd(op, 1, tol=-1.0, v0=v0, max_steps=steps)
-    t = time.perf_counter() - t0
-    per_mvp = t / res.matvecs
-    return {
-        "value": per_mvp * gpu_matvecs,
-        "unit": "s",
-        "cores": min(threads, cores),
-        "kind": "oracle",
-        "sample": (f"oracle plain GKL (full CGS2, no restart) on the full matrix: first {steps} "
-                   f"steps = {res.matvecs} products in {t:.1f} s ({per_mvp * 1e3:.1f} ms per "
-                   f"product incl. its CGS2), scaled to the GPU solve's {gpu_matvecs} products"),
-    }
+    c = np.sum(X * Y, axis=0)
+    r = X - Y * c[None, :]
+    return np.arctan2(np.linalg.norm(r, axis=0), np.abs(c))
 
 
-MFMA_BF16_PEAK_TFLOPS = 2500.0
-MFMA_INT8_PEAK_TOPS = 5000.0
-# product launches are bracketed with HIP events one in TIMING_STRIDE (per
-# product): a recorded event stalls the stream for a few microseconds, so
-# timing every launch would slow the timed solves themselves
-TIMING_STRIDE = 8
-
-
-def run_mixed(gk, torch, G, n, p, k, args, sigma_fp64, stream, fmt="bf16"):
-    """The same top-k solve by the blocked path, its products in split BF16 (fmt
-    "bf16", GKL_PREC_MIXED) or exact int8 limbs (fmt "int8", GKL_PREC_MIXED_INT8);
-    timed like the FP64 steps."""
+def relative_gaps(s):
+    """delta_i = min_{j != i} |s_i - s_j| / s_i over the returned values."""
     import numpy as np
-    import synth
-    b = args.block_width
+    d = np.abs(s[:, None] - s[None, :]) + np.diag(np.full(len(s), np.inf))
+    return d.min(axis=1) / s
+
+
+class Workload:
+    """One packed matrix resident on the device plus its FP64 reference solve."""
+
+    def __init__(self, gk, torch, wl, progress=True):
+        import synth
+        self.wl = wl
+        log(f"[bench] generating {wl['name']}")
+        t0 = time.perf_counter()
+        self.g = synth.config(wl["name"], progress=log if progress else None)
+        log(f"[bench] generated {self.g.nbytes / 1e9:.2f} GB in {time.perf_counter() - t0:.1f} s")
+        self.n, self.p, self.k = self.g.n, self.g.p, wl["k"]
+        self.G = torch.from_numpy(self.g.packed).cuda()
+        torch.cuda.synchronize()
+        self.v0 = torch.from_numpy(synth.start_vector(self.p, 1)).cuda()
+        self.sigma = self.U = self.V = None
+
+
+def fp64_solve(gk, torch, W, tol, steps, warmup, stream, keep=True, label="fp64", probe=None):
+    """`steps` timed FP64 solves (create + solve + destroy) after `warmup` untimed ones."""
+    import numpy as np
+    wl = W.wl
+    reorth = gk.GKL_REORTH_PARTIAL if wl["reorth"] == "partial" else gk.GKL_REORTH_FULL
+    opts = dict(v0=W.v0, krylov_dim=wl["krylov_dim"], timing=TIMING_STRIDE, stream=stream)
+    n, p, k = W.n, W.p, W.k
+    sigma = torch.empty(k, dtype=torch.float64, device="cuda")
+    U = torch.empty((k, n), dtype=torch.float64, device="cuda")
+    V = torch.empty((k, p), dtype=torch.float64, device="cuda")
+    probe_out = {}
+
+    def one():
+        ctx = gk.Context(W.G, n, p, k, tol, reorth, **opts)
+        try:
+            st, info = gk.gkl_solve(ctx.ctx, sigma, U, n, V, p)
+        finally:
+            ctx.close()
+        return st, info
+
+    for w in range(warmup):
+        st, info = one()
+        log(f"[bench] {label} warmup {w}: status {st} solve {info.solve_ms:.1f} ms "
+            f"matvecs {info.matvecs}")
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for s in range(steps):
+        st, info = one()
+        infos.append(info)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    for s, info in enumerate(infos):
+        log(f"[bench] {label} step {s}: solve {info.solve_ms:.1f} ms create {info.create_ms:.1f} ms "
+            f"matvecs {info.matvecs} restarts {info.restarts} conv {info.converged}")
+    if probe is not None:
+        # FP64 products of a few random directions, for the blocked products' error
+        ctx = gk.Context(W.G, n, p, k, tol, reorth, **opts)
+        try:
+            probe_out["Y"] = torch.stack([ctx.matvec(probe[:, c].contiguous())
+                                          for c in range(probe.shape[1])], dim=1)
+        finally:
+            ctx.close()
+        torch.cuda.synchronize()
+    out = {"sec_per_step": elapsed / steps, "infos": infos, "status": int(st),
+           "probe_Y": probe_out.get("Y")}
+    if keep:
+        out["sigma"] = sigma.cpu().numpy().copy()
+        out["U"] = U.cpu().numpy().T.copy()
+        out["V"] = V.cpu().numpy().T.copy()
+    return out
+
+
+def product_stats(infos, nbytes):
+    """Average launch time of each product from the sampled HIP events, and rates."""
+    mv_ms = sum(i.matvec_kernel_ms for i in infos)
+    rmv_ms = sum(i.rmatvec_kernel_ms for i in infos)
+    mv_n = sum(i.timed_matvecs for i in infos)
+    rmv_n = sum(i.timed_rmatvecs for i in infos)
+    mv_avg = mv_ms / max(mv_n, 1)
+    rmv_avg = rmv_ms / max(rmv_n, 1)
+    return {"matvec_kernel (A v)": {"total_ms": mv_ms, "avg_ms": mv_avg, "launches": mv_n,
+                                    "GBps": nbytes / (mv_avg * 1e-3) / 1e9},
+            "rmatvec_kernel (A^T u)": {"total_ms": rmv_ms, "avg_ms": rmv_avg, "launches": rmv_n,
+                                       "GBps": nbytes / (rmv_avg * 1e-3) / 1e9}}
+
+
+def blocked_solve(gk, torch, W, b, fmt, ref, stream, reps=1, probe=None, probe_Y=None):
+    """Top-k by the blocked path (block width b, products in split BF16 or int8
+    limbs) at tolerance BLOCKED_TOL: one warm-up solve, then `reps` timed ones;
+    errors against the FP64 reference solve `ref`."""
+    import numpy as np
+    n, p, k = W.n, W.p, W.k
     v0 = torch.from_numpy(np.ascontiguousarray(
         np.random.default_rng([1, 0x6D6978]).standard_normal((b, p)))).cuda()
     precision = gk.GKL_PREC_MIXED if fmt == "bf16" else gk.GKL_PREC_MIXED_INT8
@@ -112,57 +200,111 @@ def run_mixed(gk, torch, G, n, p, k, args, sigma_fp64, stream, fmt="bf16"):
     sig = torch.empty(k, dtype=torch.float64, device="cuda")
     U = torch.empty((k, n), dtype=torch.float64, device="cuda")
     V = torch.empty((k, p), dtype=torch.float64, device="cuda")
-    tol = 1e-8
-
-    def one():
-        ctx = gk.Context(G, n, p, k, tol, gk.GKL_REORTH_FULL, **opts)
+    eps_op = eps_rel = None
+    infos, times = [], []
+    for rep in range(reps + 1):
+        ctx = gk.Context(W.G, n, p, k, BLOCKED_TOL, gk.GKL_REORTH_FULL, **opts)
         try:
-            return gk.gkl_solve(ctx.ctx, sig, U, n, V, p)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, info = gk.gkl_solve(ctx.ctx, sig, U, n, V, p)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            if rep == 0 and probe is not None and probe_Y is not None:
+                Ym = ctx.matmat_mixed(probe)
+                torch.cuda.synchronize()
+                dY = torch.linalg.norm(Ym - probe_Y, dim=0)
+                eps_rel = float(torch.max(dY / torch.linalg.norm(probe_Y, dim=0)))
+                eps_op = float(torch.max(dY / torch.linalg.norm(probe, dim=0))) / float(ref["sigma"][0])
         finally:
             ctx.close()
-
-    for _ in range(args.warmup):
-        one()
-    torch.cuda.synchronize()
-    infos = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        st, info = one()
-        infos.append(info)
-    torch.cuda.synchronize()
-    step_s = (time.perf_counter() - t0) / args.steps
-    s_mixed = sig.cpu().numpy()
-    rel = np.abs(s_mixed - sigma_fp64) / sigma_fp64
-    mv_ms = sum(i.matvec_kernel_ms for i in infos)
-    rmv_ms = sum(i.rmatvec_kernel_ms for i in infos)
-    mv_n = sum(i.timed_matvecs for i in infos)
-    rmv_n = sum(i.timed_rmatvecs for i in infos)
+        if rep > 0:
+            infos.append(info)
+            times.append(dt)
+    s = sig.cpu().numpy()
+    Uh = U.cpu().numpy().T
+    Vh = V.cpu().numpy().T
+    rel = np.abs(s - ref["sigma"]) / ref["sigma"]
+    ang_u = vector_angles(Uh, ref["U"])
+    ang_v = vector_angles(Vh, ref["V"])
+    gaps = relative_gaps(ref["sigma"])
+    # gap rule: a vector is held to the angle target when the bound
+    # eps * sigma_1 / (delta_i sigma_i) on its error is itself below the target,
+    # with eps the larger of the solve tolerance and the measured product error
+    # ||dY|| / (sigma_1 ||w||) on random unit vectors
+    eps = max(BLOCKED_TOL, eps_op or 0.0)
+    bound = eps * ref["sigma"][0] / (gaps * ref["sigma"])
+    gated = bound <= ANGLE_TARGET
+    gated[-1] = False          # the gap below sigma_k is not known
     last = infos[-1]
-    alg_bytes = ((n + 3) // 4) * p + b * (4 * p + 8 * n)
+    nbytes = block_bytes(n, p, b)
+    out = {"format": fmt, "block_width": b, "tol": BLOCKED_TOL, "status": int(st),
+           "solve_s": float(np.mean(times)), "create_s": float(np.mean([i.create_ms for i in infos])) / 1e3,
+           "converged": int(last.converged), "matvecs": int(last.matvecs),
+           "passes_over_G": int(last.passes_over_G), "block_steps": int(last.steps),
+           "restarts": int(last.restarts), "max_residual_rel": last.max_residual_rel,
+           "sigma_max_rel_err_vs_fp64": float(rel.max()),
+           "sigma_rel_err_vs_fp64": [float(x) for x in rel],
+           "angle_u_vs_fp64": [float(x) for x in ang_u],
+           "angle_v_vs_fp64": [float(x) for x in ang_v],
+           "product_err_rel_to_y": eps_rel,
+           "product_err_rel_to_sigma1": eps_op,
+           "gap_rule_gated": [int(x) for x in gated],
+           "gated_max_angle": float(max(ang_u[gated].max(), ang_v[gated].max())) if gated.any() else None}
     if fmt == "bf16":
-        exec_flop = 8.0 * n * p * b           # g and m operands, each hi + lo
+        # 16 x 16 x 32 MFMAs per 16 rows x 32 K: 2 for b <= 8 (hi and lo share a
+        # tile), else 4 per 16 columns; 2 x 16 x 16 x 32 flop each
+        exec_flop = 2.0 * 16 * n * p * (2 if b <= 8 else 4 * ((b + 15) // 16))
         peak = MFMA_BF16_PEAK_TFLOPS
     else:
-        # two operands (codes, missing flags) x limb tiles of 16 columns: 2 tiles
-        # for b <= 8, 3 per 16 columns otherwise; 2 ops per multiply-add
         tiles = 2 if b <= 8 else 3 * ((b + 15) // 16)
         exec_flop = 2.0 * 2 * 16 * tiles * n * p
         peak = MFMA_INT8_PEAK_TOPS
-    out = {"format": fmt, "block_width": b, "tol": tol, "value_s_per_step": step_s,
-           "solve_s": float(np.mean([i.solve_ms for i in infos])) / 1e3,
-           "create_s": float(np.mean([i.create_ms for i in infos])) / 1e3,
-           "converged": int(last.converged), "matvecs": int(last.matvecs),
-           "block_steps": int(last.steps), "restarts": int(last.restarts),
-           "sigma_max_rel_err_vs_fp64": float(rel.max()),
-           "sigma_rel_err_vs_fp64": [float(x) for x in rel]}
-    for name, ms, cnt in (("matmat_mixed (A W)", mv_ms, mv_n), ("rmatmat_mixed (A^T X)", rmv_ms, rmv_n)):
-        avg = ms / max(cnt, 1)
-        out[name] = {"avg_launch_ms": avg, "launches": int(cnt),
-                     "algorithmic_bytes_per_launch": int(alg_bytes),
-                     "achieved_GBps": alg_bytes / (avg * 1e-3) / 1e9,
-                     "hbm_frac": alg_bytes / (avg * 1e-3) / 1e9 / HBM_PEAK_GBPS,
-                     "mfma_executed_TFLOPs": exec_flop / (avg * 1e-3) / 1e12,
-                     "mfma_frac": exec_flop / (avg * 1e-3) / 1e12 / peak}
+    for name, total, core, cnt in (
+            ("A W", sum(i.matvec_kernel_ms for i in infos), sum(i.matvec_core_ms for i in infos),
+             sum(i.timed_matvecs for i in infos)),
+            ("A^T X", sum(i.rmatvec_kernel_ms for i in infos), sum(i.rmatvec_core_ms for i in infos),
+             sum(i.timed_rmatvecs for i in infos))):
+        avg = total / max(cnt, 1)
+        avg_core = core / max(cnt, 1)
+        d = {"chain_avg_ms": avg, "core_kernel_avg_ms": avg_core, "launches": int(cnt),
+             "algorithmic_bytes": int(nbytes),
+             "chain_GBps": nbytes / (avg * 1e-3) / 1e9 if avg > 0 else None}
+        if avg_core > 0:
+            d["core_GBps"] = nbytes / (avg_core * 1e-3) / 1e9
+            d["core_hbm_frac"] = d["core_GBps"] / HBM_PEAK_GBPS
+            d["core_mfma_executed_TFLOPs"] = exec_flop / (avg_core * 1e-3) / 1e12
+            d["core_mfma_frac"] = d["core_mfma_executed_TFLOPs"] / peak
+        out[name] = d
+    log(f"[bench] blocked {fmt} b={b}: {out['solve_s']:.3f} s, {last.steps} block steps, "
+        f"max sigma err {rel.max():.2e}, gated max angle {out['gated_max_angle']}")
+    return out
+
+
+def run_compare(gk, torch, W, ref, args, stream):
+    """FP64 at the blocked tolerance (equal accuracy) and the blocked solves."""
+    import numpy as np
+    out = {"fp64_tol": W.wl["tol"], "blocked_tol": BLOCKED_TOL}
+    r = fp64_solve(gk, torch, W, BLOCKED_TOL, max(1, min(args.steps, 3)), 1, stream, keep=True,
+                   label="fp64@1e-8")
+    rel = np.abs(r["sigma"] - ref["sigma"]) / ref["sigma"]
+    out["fp64_at_blocked_tol"] = {"solve_s": r["sec_per_step"], "matvecs": int(r["infos"][-1].matvecs),
+                                  "restarts": int(r["infos"][-1].restarts),
+                                  "sigma_max_rel_err_vs_fp64": float(rel.max())}
+    rng = np.random.default_rng([7, 0x70726F])
+    probe = torch.from_numpy(rng.standard_normal((W.p, 4)) / np.sqrt(W.p)).cuda()
+    probe_Y = ref.get("probe_Y")
+    for fmt in args.formats:
+        for b in args.widths:
+            key = f"{fmt}_b{b}"
+            res = blocked_solve(gk, torch, W, b, fmt, ref, stream, reps=args.blocked_reps,
+                                probe=probe if b >= 4 else None,
+                                probe_Y=probe_Y if b >= 4 else None)
+            res["speedup_vs_fp64"] = ref["sec_per_step"] / (res["solve_s"] + res["create_s"])
+            res["speedup_vs_fp64_at_equal_tol"] = (out["fp64_at_blocked_tol"]["solve_s"]
+                                                   / (res["solve_s"] + res["create_s"]))
+            out[key] = res
+            torch.cuda.empty_cache()
     return out
 
 
@@ -194,23 +336,27 @@ def run_batched(gk, torch, args):
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t0)
         plan = ctx.plan()
+        sig_b = [s.cpu().numpy() for s in sig]
     finally:
         ctx.close()
     batch_s = float(np.mean(times))
     log(f"[bench] batched: {batch_s * 1e3:.1f} ms per solve, status {st}")
-    bytes_pass = sum(((g.n + 3) // 4) * g.p + 16 * g.p + 16 * g.n for g in gs)
+    bytes_pass = sum(fp64_bytes(g.n, g.p) for g in gs)
     t0 = time.perf_counter()
     seq_mv = 0
+    sig_seq = []
     for q, g in enumerate(gs):
         c1 = gk.Context(Gs[q], g.n, g.p, k, tol=tol, reorth=gk.GKL_REORTH_FULL,
                         v0=v0[sum(ps[:q]):sum(ps[:q + 1])], krylov_dim=m)
         try:
-            _, _, _, _, info = c1.solve()
+            s1, _, _, _, info = c1.solve()
             seq_mv += info.matvecs
+            sig_seq.append(s1.cpu().numpy())
         finally:
             c1.close()
     torch.cuda.synchronize()
     seq_s = time.perf_counter() - t0
+    agree = max(float(np.max(np.abs(a - b) / b)) for a, b in zip(sig_b, sig_seq))
     out = {"workload": "22 chromosome blocks of 20,000 individuals x 8,000..80,000 SNPs "
                        "(701,314 in all), 4 subpopulations, 1% missing; k=10 each, FP64 GKL, "
                        "full CGS2, thick restart m=40",
@@ -223,123 +369,63 @@ def run_batched(gk, torch, args):
            "matvecs_total": int(sum(i.matvecs for i in infos)),
            "plan": plan,
            "sequential_single_solves_s": seq_s, "sequential_matvecs_total": int(seq_mv),
-           "speedup_vs_sequential": seq_s / batch_s}
+           "speedup_vs_sequential": seq_s / batch_s,
+           "sigma_max_rel_diff_batched_vs_sequential": agree}
     for name, ms in (("batched_matvec (A v, all 22)", plan["mv_ms"]),
                      ("batched_rmatvec (A^T u, all 22)", plan["rmv_ms"])):
         if ms > 0:
             out[name] = {"avg_launch_ms": ms, "algorithmic_bytes_per_launch": int(bytes_pass),
                          "achieved_GBps": bytes_pass / (ms * 1e-3) / 1e9,
                          "hbm_frac": bytes_pass / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS}
+    del Gs
+    torch.cuda.empty_cache()
     return out
 
 
-def run_c3(gk, torch, args):
-    """50,000 x 500,000 (6.25 GB packed): FP64 GKL (PRO, thick restart m=60) and the
-    blocked solves (block width 8, split-BF16 and int8-limb products), one solve each
-    after a warmup."""
+def run_extra(gk, torch, name, args, stream):
+    """A second workload (FP64 and blocked b = 8 and 16) reported beside the headline."""
+    W = Workload(gk, torch, WORKLOADS[name], progress=False)
+    ref = fp64_solve(gk, torch, W, W.wl["tol"], 3, 1, stream, label=f"{name} fp64")
+    prod = product_stats(ref["infos"], fp64_bytes(W.n, W.p))
+    out = {"workload": W.wl["desc"], "fp64_s_per_step": ref["sec_per_step"],
+           "fp64_matvecs": int(ref["infos"][-1].matvecs), "products": prod}
+    for b in (8, 16):
+        r = blocked_solve(gk, torch, W, b, "bf16", ref, stream, reps=1)
+        r["speedup_vs_fp64"] = ref["sec_per_step"] / (r["solve_s"] + r["create_s"])
+        out[f"bf16_b{b}"] = {key: r[key] for key in (
+            "solve_s", "create_s", "block_steps", "restarts", "sigma_max_rel_err_vs_fp64",
+            "gated_max_angle", "speedup_vs_fp64", "A W", "A^T X")}
+    del W
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(W, ref, gpu_matvecs, ntrip):
+    """The CPU oracle on the full matrix, bounded: the residual certificate of the
+    leading `ntrip` GPU triplets (one A v and one A^T u per triplet).  The
+    measured per-product time is scaled to the GPU solve's product count."""
     import numpy as np
-    import synth
-    log("[bench] c3: generating 50,000 x 500,000")
-    g = synth.config("c3")
-    n, p, k = g.n, g.p, 20
-    G = torch.from_numpy(g.packed).cuda()
-    sig = torch.empty(k, dtype=torch.float64, device="cuda")
-    U = torch.empty((k, n), dtype=torch.float64, device="cuda")
-    V = torch.empty((k, p), dtype=torch.float64, device="cuda")
-    out = {"workload": "50,000 x 500,000 genotypes, 10 subpopulations + 20% admixed, 1% missing; k=20"}
-    res = {}
-    for label, tol, opts in (
-            ("fp64", 1e-10, dict(v0=torch.from_numpy(synth.start_vector(p, 1)).cuda(),
-                                 krylov_dim=60, reorth=gk.GKL_REORTH_PARTIAL)),
-            ("mixed", 1e-8, dict(v0=torch.from_numpy(np.ascontiguousarray(
-                np.random.default_rng([1, 0x6D6978]).standard_normal((8, p)))).cuda(),
-                precision=gk.GKL_PREC_MIXED, block_width=8, reorth=gk.GKL_REORTH_FULL)),
-            ("mixed_int8", 1e-8, dict(v0=torch.from_numpy(np.ascontiguousarray(
-                np.random.default_rng([1, 0x6D6978]).standard_normal((8, p)))).cuda(),
-                precision=gk.GKL_PREC_MIXED_INT8, block_width=8, reorth=gk.GKL_REORTH_FULL))):
-        reorth = opts.pop("reorth")
-        for rep in range(2):
-            ctx = gk.Context(G, n, p, k, tol, reorth, timing=TIMING_STRIDE, **opts)
-            try:
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                st, info = gk.gkl_solve(ctx.ctx, sig, U, n, V, p)
-                torch.cuda.synchronize()
-                dt = time.perf_counter() - t0
-            finally:
-                ctx.close()
-        res[label] = sig.cpu().numpy().copy()
-        mv = info.matvec_kernel_ms / max(info.timed_matvecs, 1)
-        rmv = info.rmatvec_kernel_ms / max(info.timed_rmatvecs, 1)
-        out[label] = {"solve_s": dt, "status": int(st), "matvecs": int(info.matvecs),
-                      "passes_over_G": int(info.passes_over_G), "restarts": int(info.restarts),
-                      "avg_product_ms": [mv, rmv]}
-        log(f"[bench] c3 {label}: {dt:.2f} s, {info.matvecs} matvecs")
-    for key in ("mixed", "mixed_int8"):
-        rel = np.abs(res[key] - res["fp64"]) / res["fp64"]
-        out[key]["sigma_max_rel_err_vs_fp64"] = float(rel.max())
-        out[key + "_speedup_vs_fp64"] = out["fp64"]["solve_s"] / out[key]["solve_s"]
-    return out
 
-
-def run_c5(gk, torch, args):
-    """100,000 x 1,000,000 (25 GB packed), a pure noise bulk with ten planted spikes at
-    1.5..20 times the bulk edge: the blocked solves (k = 10, b = 8; split-BF16 and int8-limb products) and the
-    FP64 solve (PRO, m = 30), each once after nothing else has touched the matrix;
-    reports the spike recovery against the planted ratios."""
-    import numpy as np
-    import synth
-    log("[bench] c5: generating 100,000 x 1,000,000")
-    g = synth.config("c5", progress=log)
-    n, p, k = g.n, g.p, 10
-    log("[bench] c5: copying 25 GB to the device")
-    G = torch.from_numpy(g.packed).cuda()
-    torch.cuda.synchronize()
-    edge = g.meta["edge"]
-    ratios = np.sort(np.array(g.meta["spike_ratios"]))[::-1]
-    sig = torch.empty(k, dtype=torch.float64, device="cuda")
-    U = torch.empty((k, n), dtype=torch.float64, device="cuda")
-    V = torch.empty((k, p), dtype=torch.float64, device="cuda")
-    out = {"workload": "100,000 x 1,000,000 genotypes, MAF ~ Beta(0.5,0.5) folded, 3% missing, "
-                       "10 planted spikes at 1.5..20x the bulk edge; k=10",
-           "packed_bytes": int(g.nbytes), "bulk_edge": edge, "planted_ratios": ratios.tolist()}
-    res = {}
-    for label, tol, opts, reorth in (
-            ("mixed", 1e-8, dict(precision=gk.GKL_PREC_MIXED, block_width=8), gk.GKL_REORTH_FULL),
-            ("mixed_int8", 1e-8, dict(precision=gk.GKL_PREC_MIXED_INT8, block_width=8),
-             gk.GKL_REORTH_FULL),
-            ("fp64", 1e-10, dict(v0=torch.from_numpy(synth.start_vector(p, 1)).cuda(), krylov_dim=30),
-             gk.GKL_REORTH_PARTIAL)):
-        log(f"[bench] c5: {label} create")
-        t0 = time.perf_counter()
-        ctx = gk.Context(G, n, p, k, tol, reorth, timing=TIMING_STRIDE, **opts)
-        torch.cuda.synchronize()
-        create_s = time.perf_counter() - t0
-        try:
-            log(f"[bench] c5: {label} solve")
-            t0 = time.perf_counter()
-            st, info = gk.gkl_solve(ctx.ctx, sig, U, n, V, p)
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
-        finally:
-            ctx.close()
-        torch.cuda.empty_cache()
-        s = sig.cpu().numpy().copy()
-        res[label] = s
-        mv = info.matvec_kernel_ms / max(info.timed_matvecs, 1)
-        rmv = info.rmatvec_kernel_ms / max(info.timed_rmatvecs, 1)
-        out[label] = {"solve_s": dt, "create_s": create_s, "status": int(st),
-                      "matvecs": int(info.matvecs), "passes_over_G": int(info.passes_over_G),
-                      "restarts": int(info.restarts), "avg_product_ms": [mv, rmv],
-                      "sigma_over_edge": (s / edge).tolist(),
-                      "sigma_vs_planted_ratio": (s / (ratios * edge) - 1.0).tolist()}
-        log(f"[bench] c5 {label}: {dt:.2f} s, {info.matvecs} matvecs, status {st}")
-    for key in ("mixed", "mixed_int8"):
-        rel = np.abs(res[key] - res["fp64"]) / res["fp64"]
-        out[key]["sigma_max_rel_err_vs_fp64"] = float(rel.max())
-        out[key + "_speedup_vs_fp64"] = out["fp64"]["solve_s"] / out[key]["solve_s"]
-    out["outliers_above_1.05_edge"] = int(np.sum(res["fp64"] > 1.05 * edge))
-    return out
+    import oracle
+    cores = len(os.sched_getaffinity(0))
+    threads = min(int(os.environ.get("OMP_NUM_THREADS", cores)), cores)
+    op = oracle.PackedOperator(W.g.packed, W.n, W.p)
+    t0 = time.perf_counter()
+    r1, r2, rq = oracle.certificate(op, ref["sigma"][:ntrip], ref["U"][:, :ntrip], ref["V"][:, :ntrip])
+    t = time.perf_counter() - t0
+    per = t / (2 * ntrip)
+    s1 = ref["sigma"][0]
+    res = np.maximum(r1, r2)
+    cert = {"triplets": ntrip, "tol": W.wl["tol"],
+            "residual_rel": [float(x) for x in res / s1],
+            "max_residual_rel": float(res.max() / s1),
+            "within_tol": bool(np.all(res <= W.wl["tol"] * s1)),
+            "rayleigh_minus_sigma_rel": [float(x) for x in (rq - ref["sigma"][:ntrip]) / s1]}
+    base = {"value": per * gpu_matvecs, "unit": "s", "cores": threads, "kind": "oracle",
+            "sample": (f"oracle residual certificate of the leading {ntrip} FP64 triplets on the full "
+                       f"{W.n:,} x {W.p:,} matrix: {2 * ntrip} products (A v, A^T u) in {t:.1f} s "
+                       f"= {per:.2f} s per product, scaled to the GPU solve's {gpu_matvecs} products")}
+    return base, cert
 
 
 def main():
@@ -347,88 +433,53 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--no-mixed", action="store_true",
-                    help="skip the blocked (split-BF16 and int8-limb) solves of the same workload")
-    ap.add_argument("--block-width", type=int, default=8)
+    ap.add_argument("--certificate-triplets", type=int, default=5,
+                    help="leading triplets checked by the CPU oracle (2 products each)")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the blocked solves and the FP64 solve at the blocked tolerance")
+    ap.add_argument("--widths", default="8,16,32", help="block widths of the blocked solves")
+    ap.add_argument("--formats", default="bf16",
+                    help="blocked product formats: bf16 (split BF16), int8 (int8 limbs)")
+    ap.add_argument("--blocked-reps", type=int, default=1)
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the 10,000 x 100,000 workload reported beside the headline")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched solve of the 22 chromosome blocks")
     ap.add_argument("--batched-steps", type=int, default=2)
-    ap.add_argument("--c3", action="store_true",
-                    help="also compare FP64 and mixed at 50,000 x 500,000 (adds about a minute)")
-    ap.add_argument("--c5", action="store_true",
-                    help="also solve 100,000 x 1,000,000 (25 GB) by both paths (adds a few minutes)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="after the timed steps, copy BYTES bytes device-to-device 3 times "
                          "(reference dispatch for the HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the library has no multi-GPU path "
-              "(--gpus must be 1)", file=sys.stderr)
+        print("bench.py runs on one GPU only; the library has no multi-GPU path, so --gpus "
+              "must be 1", file=sys.stderr)
         sys.exit(2)
+    args.widths = [int(x) for x in args.widths.split(",") if x]
+    args.formats = [x for x in args.formats.split(",") if x]
 
     import numpy as np
     import torch
 
-    import synth
     import paper_1808_03374_amd as gk
 
-    wl = WORKLOADS[args.workload]
-    log(f"[bench] generating workload {wl['name']}")
-    g = synth.config(wl["name"])
-    n, p, k = g.n, g.p, wl["k"]
-    G = torch.from_numpy(g.packed).cuda()
-    v0 = torch.from_numpy(synth.start_vector(p, 1)).cuda()
     stream = torch.cuda.current_stream().cuda_stream
-    reorth = gk.GKL_REORTH_PARTIAL if wl["reorth"] == "partial" else gk.GKL_REORTH_FULL
-    opts = dict(v0=v0, krylov_dim=wl["krylov_dim"], timing=TIMING_STRIDE, stream=stream)
-    sigma = torch.empty(k, dtype=torch.float64, device="cuda")
-    U = torch.empty((k, n), dtype=torch.float64, device="cuda")
-    V = torch.empty((k, p), dtype=torch.float64, device="cuda")
-
-    def one_step():
-        ctx = gk.Context(G, n, p, k, wl["tol"], reorth, **opts)
-        try:
-            st, info = gk.gkl_solve(ctx.ctx, sigma, U, n, V, p)
-        finally:
-            ctx.close()
-        return st, info
-
-    for w in range(args.warmup):
-        st, info = one_step()
-        log(f"[bench] warmup {w}: status {st} solve {info.solve_ms:.1f} ms matvecs {info.matvecs}")
-    torch.cuda.synchronize()
-    infos = []
-    t0 = time.perf_counter()
-    for s in range(args.steps):
-        st, info = one_step()
-        infos.append(info)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    for s, info in enumerate(infos):
-        log(f"[bench] step {s}: solve {info.solve_ms:.1f} ms create {info.create_ms:.1f} ms "
-            f"matvecs {info.matvecs} restarts {info.restarts} conv {info.converged}")
-    sec_per_step = elapsed / args.steps
-
-    # dominant product kernel: average duration from the HIP events taken on the
-    # library's stream during the timed steps
-    mv_ms = sum(i.matvec_kernel_ms for i in infos)
-    rmv_ms = sum(i.rmatvec_kernel_ms for i in infos)
-    mv_n = sum(i.timed_matvecs for i in infos)
-    rmv_n = sum(i.timed_rmatvecs for i in infos)
-    bytes_per_product = ((n + 3) // 4) * p + 16 * p + 16 * n
-    mv_avg = mv_ms / max(mv_n, 1)
-    rmv_avg = rmv_ms / max(rmv_n, 1)
-    kernels = {"matvec_kernel (A v)": (mv_ms, mv_avg), "rmatvec_kernel (A^T u)": (rmv_ms, rmv_avg)}
-    dom = max(kernels, key=lambda key: kernels[key][0])
-    dom_avg = kernels[dom][1]
-    achieved = bytes_per_product / (dom_avg * 1e-3) / 1e9
-    other = [key for key in kernels if key != dom][0]
-    other_avg = kernels[other][1]
-    solve_s = float(np.mean([i.solve_ms for i in infos])) / 1e3
-    create_s = float(np.mean([i.create_ms for i in infos])) / 1e3
+    wl = WORKLOADS[args.workload]
+    W = Workload(gk, torch, wl)
+    n, p, k = W.n, W.p, W.k
+    rng = np.random.default_rng([7, 0x70726F])
+    probe = torch.from_numpy(rng.standard_normal((p, 4)) / np.sqrt(p)).cuda()
+    ref = fp64_solve(gk, torch, W, wl["tol"], args.steps, args.warmup, stream,
+                     probe=None if args.no_compare else probe)
+    infos = ref["infos"]
+    sec_per_step = ref["sec_per_step"]
+    nbytes = fp64_bytes(n, p)
+    prod = product_stats(infos, nbytes)
+    dom = max(prod, key=lambda key: prod[key]["total_ms"])
+    other = [key for key in prod if key != dom][0]
+    dom_avg = prod[dom]["avg_ms"]
+    achieved = nbytes / (dom_avg * 1e-3) / 1e9
     last = infos[-1]
     line = {
         "metric": METRIC,
@@ -445,16 +496,16 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl["desc"], "n": n, "p": p, "k": k, "tol": wl["tol"],
                    "reorth": wl["reorth"], "krylov_dim": wl["krylov_dim"],
-                   "packed_bytes": int(g.nbytes)},
-        "solve_s": solve_s,
-        "create_s": create_s,
+                   "packed_bytes": int(W.g.nbytes)},
+        "solve_s": float(np.mean([i.solve_ms for i in infos])) / 1e3,
+        "create_s": float(np.mean([i.create_ms for i in infos])) / 1e3,
         "matvecs": int(last.matvecs),
         "restarts": int(last.restarts),
         "reorth_passes": int(last.reorths),
         "converged": int(last.converged),
         "max_residual_rel": last.max_residual_rel,
-        "matvec_GBps": bytes_per_product / (mv_avg * 1e-3) / 1e9,
-        "rmatvec_GBps": bytes_per_product / (rmv_avg * 1e-3) / 1e9,
+        "matvec_GBps": prod["matvec_kernel (A v)"]["GBps"],
+        "rmatvec_GBps": prod["rmatvec_kernel (A^T u)"]["GBps"],
         "roofline": {
             "kernel": dom,
             "bound": "hbm",
@@ -464,34 +515,55 @@ def main():
             "frac": achieved / HBM_PEAK_GBPS,
             "traffic": measured_traffic(wl["name"], dom),
             "avg_launch_ms": dom_avg,
-            "launches": int(mv_n if dom.startswith("matvec") else rmv_n),
+            "launches": int(prod[dom]["launches"]),
             "timed_one_launch_in": TIMING_STRIDE,
-            "algorithmic_bytes_per_launch": int(bytes_per_product),
-            "other_kernel": {"kernel": other, "avg_launch_ms": other_avg,
-                             "achieved_GBps": bytes_per_product / (other_avg * 1e-3) / 1e9},
+            "algorithmic_bytes_per_launch": int(nbytes),
+            "other_kernel": {"kernel": other, "avg_launch_ms": prod[other]["avg_ms"],
+                             "achieved_GBps": prod[other]["GBps"],
+                             "traffic": measured_traffic(wl["name"], other)},
         },
     }
-    if not args.no_mixed:
-        line["mixed"] = run_mixed(gk, torch, G, n, p, k, args, sigma.cpu().numpy(), stream)
-        line["mixed_int8"] = run_mixed(gk, torch, G, n, p, k, args, sigma.cpu().numpy(), stream,
-                                       fmt="int8")
-    if not args.no_batched:
-        line["batched"] = run_batched(gk, torch, args)
-    if args.c3:
-        line["c3"] = run_c3(gk, torch, args)
-    if args.c5:
-        line["c5"] = run_c5(gk, torch, args)
     if args.copy_calibration > 0:
         src = torch.empty(args.copy_calibration, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
+        del src, dst
         line["copy_calibration_bytes"] = args.copy_calibration
+    if not args.no_compare:
+        line["compare"] = run_compare(gk, torch, W, ref, args, stream)
     if not args.no_cpu_baseline:
-        log("[bench] timing the CPU oracle on a bounded sample")
-        line["cpu_baseline"] = cpu_baseline(g, int(last.matvecs), args.cpu_seconds)
+        log("[bench] timing the CPU oracle (residual certificate on the full matrix)")
+        line["cpu_baseline"], line["certificate"] = cpu_baseline(
+            W, ref, int(last.matvecs), min(args.certificate_triplets, k))
+        log(f"[bench] certificate: max residual {line['certificate']['max_residual_rel']:.2e} sigma_1")
+    W.G = None
+    torch.cuda.empty_cache()
+    if not args.no_extra and args.workload != "c2":
+        line["c2"] = run_extra(gk, torch, "c2", args, stream)
+    if not args.no_batched:
+        line["batched"] = run_batched(gk, torch, args)
+    torch.cuda.synchronize()
     print(json.dumps(line), flush=True)
+    reap_children()
+
+
+def reap_children():
+    """End any child process this run left behind (named on stderr), so the
+    bench exits with nothing of its own still running."""
+    try:
+        import psutil
+    except ImportError:
+        return
+    kids = psutil.Process().children(recursive=True)
+    for c in kids:
+        try:
+            log(f"[bench] ending leftover child process {c.pid}: {' '.join(c.cmdline())[:200]}")
+            c.terminate()
+        except psutil.Error:
+            pass
+    psutil.wait_procs(kids, timeout=5)
 
 
 if __name__ == "__main__":

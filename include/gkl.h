@@ -123,6 +123,11 @@ typedef struct gkl_info {
     double rmatvec_kernel_ms; /* with options.timing: summed A^T u kernel time */
     int64_t timed_matvecs;    /* launches behind matvec_kernel_ms */
     int64_t timed_rmatvecs;   /* launches behind rmatvec_kernel_ms */
+    double matvec_core_ms;    /* with options.timing: the same launches, main kernel
+                                 only (a blocked product is several kernels: vector
+                                 split, column sums, the matrix-core kernel, reduce);
+                                 equal to matvec_kernel_ms on the FP64 path */
+    double rmatvec_core_ms;   /* likewise for the A^T u / A^T X products */
 } gkl_info;
 
 void gkl_options_default(gkl_options* opt);
@@ -221,9 +226,17 @@ gkl_status gkl_rmatmat_mixed(gkl_ctx* ctx, const double* X, int32_t b, double* Z
 gkl_status gkl_get_trace(gkl_ctx* ctx, double* buf, int64_t cap, int64_t* written);
 
 /*
- * gkl_dense_svd -- the small dense SVD used for Ritz extraction, exposed for
- * testing: B (m x m, column-major, device) = P diag(S) Q^T with S descending.
- * m <= 96.  P, Q: m x m column-major device; S: m device.  stream may be NULL.
+ * gkl_dense_svd -- the small dense SVD used for Ritz extraction (Section 3,
+ * "Convergence criteria": the top Ritz values and the residual bound come from
+ * the SVD of the projected matrix B), exposed for testing:
+ * B (m x m, column-major, device) = P diag(S) Q^T with S descending.
+ * 1 <= m <= 1024.  m <= 96: one workgroup with everything in LDS;
+ * 96 < m <= 128: the matrix in LDS and the rotations logged to a device buffer
+ * (5.2 MB at m = 128) and replayed; m > 128: working matrices in device memory.
+ * The buffer of the last two cases is allocated and freed inside the call.
+ * P, Q: m x m column-major device; S: m device.  stream may be NULL.
+ * Errors: GKL_ERR_INVALID (NULL pointer, m out of range), GKL_ERR_NOMEM /
+ * GKL_ERR_DEVICE.
  */
 gkl_status gkl_dense_svd(const double* B, int32_t m, double* P, double* S, double* Q,
                          void* stream);

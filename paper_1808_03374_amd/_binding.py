@@ -66,6 +66,8 @@ class gkl_info(ctypes.Structure):
         ("rmatvec_kernel_ms", ctypes.c_double),
         ("timed_matvecs", ctypes.c_int64),
         ("timed_rmatvecs", ctypes.c_int64),
+        ("matvec_core_ms", ctypes.c_double),
+        ("rmatvec_core_ms", ctypes.c_double),
     ]
 
     def as_dict(self):

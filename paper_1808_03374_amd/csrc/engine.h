@@ -94,14 +94,14 @@ struct gkl_ctx {
 
     // optional kernel timing (options.timing)
     std::vector<hipEvent_t> ev_pool;
-    std::vector<std::pair<int, int>> ev_mv, ev_rmv;   // (start, stop) indices
+    std::vector<std::pair<int, int>> ev_mv, ev_rmv;   // (product slot, main-kernel slot)
     int ev_next = 0;
     int64_t ev_calls[2] = {0, 0};   // timing_slot calls (A v, A^T u) since the last collection
     int timing_slot(bool right);
     const hipEvent_t* timing_events(int slot);
-    void timing_note(int slot, bool right);
+    void timing_note(int slot, bool right, bool core = false);
     int timing_begin(bool right);
-    void timing_end(int start, bool right);
+    void timing_end(int start, bool right, bool core = false);
     void timing_collect();
 
     gkl::MixedState* mixed = nullptr;

@@ -186,15 +186,17 @@ int gkl_ctx::timing_slot(bool right)
 {
     if (opt.timing <= 0) return -1;
     if (ev_calls[right ? 1 : 0]++ % opt.timing != 0) return -1;
-    if (ev_next + 2 > (int)ev_pool.size()) {
+    if (ev_next + 4 > (int)ev_pool.size()) {
         for (int t = 0; t < 64; ++t) {
             hipEvent_t e;
             GKL_HIP(hipEventCreate(&e));
             ev_pool.push_back(e);
         }
     }
+    // four events per slot: the product (start, end) and, for products made of
+    // several launches, the main kernel alone (start, end)
     const int i = ev_next;
-    ev_next += 2;
+    ev_next += 4;
     return i;
 }
 
@@ -203,9 +205,9 @@ const hipEvent_t* gkl_ctx::timing_events(int slot)
     return slot < 0 ? nullptr : &ev_pool[slot];
 }
 
-void gkl_ctx::timing_note(int slot, bool right)
+void gkl_ctx::timing_note(int slot, bool right, bool core)
 {
-    if (slot >= 0) (right ? ev_rmv : ev_mv).push_back({slot, slot + 1});
+    if (slot >= 0) (right ? ev_rmv : ev_mv).push_back({slot, core ? slot + 2 : slot});
 }
 
 int gkl_ctx::timing_begin(bool right)
@@ -215,30 +217,33 @@ int gkl_ctx::timing_begin(bool right)
     return i;
 }
 
-void gkl_ctx::timing_end(int start, bool right)
+void gkl_ctx::timing_end(int start, bool right, bool core)
 {
     if (start < 0) return;
     GKL_HIP(hipEventRecord(ev_pool[start + 1], prob.stream));
-    timing_note(start, right);
+    timing_note(start, right, core);
 }
 
 void gkl_ctx::timing_collect()
 {
     if (!opt.timing) return;
     GKL_HIP(hipStreamSynchronize(prob.stream));
-    double a = 0.0, b = 0.0;
-    for (auto& pr : ev_mv) {
-        float ms = 0.f;
-        GKL_HIP(hipEventElapsedTime(&ms, ev_pool[pr.first], ev_pool[pr.second]));
-        a += ms;
+    // pr = (slot, core slot): the product spans events slot, slot + 1; its main
+    // kernel spans core, core + 1 (the same pair when the product is one kernel)
+    double t[2] = {0.0, 0.0}, c[2] = {0.0, 0.0};
+    for (int side = 0; side < 2; ++side) {
+        for (auto& pr : side ? ev_rmv : ev_mv) {
+            float ms = 0.f, mc = 0.f;
+            GKL_HIP(hipEventElapsedTime(&ms, ev_pool[pr.first], ev_pool[pr.first + 1]));
+            GKL_HIP(hipEventElapsedTime(&mc, ev_pool[pr.second], ev_pool[pr.second + 1]));
+            t[side] += ms;
+            c[side] += mc;
+        }
     }
-    for (auto& pr : ev_rmv) {
-        float ms = 0.f;
-        GKL_HIP(hipEventElapsedTime(&ms, ev_pool[pr.first], ev_pool[pr.second]));
-        b += ms;
-    }
-    info.matvec_kernel_ms = a;
-    info.rmatvec_kernel_ms = b;
+    info.matvec_kernel_ms = t[0];
+    info.rmatvec_kernel_ms = t[1];
+    info.matvec_core_ms = c[0];
+    info.rmatvec_core_ms = c[1];
     info.timed_matvecs = (int64_t)ev_mv.size();
     info.timed_rmatvecs = (int64_t)ev_rmv.size();
     ev_mv.clear();
@@ -797,23 +802,23 @@ gkl_status gkl_dense_svd(const double* B, int32_t m, double* P, double* S, doubl
         return set_error(nullptr, GKL_ERR_INVALID, "bad argument to gkl_dense_svd");
     try {
         hipStream_t s = static_cast<hipStream_t>(stream);
-        double* scratch = nullptr;
+        double* gscr = nullptr;
         double* rlog = nullptr;
         if (!svd_fits_lds(m)) {
             if (svd_logged_fits_lds(m))
                 GKL_HIP(hipMalloc(&rlog, sizeof(double) * svd_log_elems(m)));
             else
-                GKL_HIP(hipMalloc(&scratch, sizeof(double) * svd_scratch_elems(m)));
+                GKL_HIP(hipMalloc(&gscr, sizeof(double) * svd_scratch_elems(m)));
         }
         try {
-            launch_dense_svd(B, m, P, S, Q, scratch, s, rlog);
+            launch_dense_svd(B, m, P, S, Q, gscr, s, rlog);
             GKL_HIP(hipStreamSynchronize(s));
         } catch (...) {
-            if (scratch) (void)hipFree(scratch);
+            if (gscr) (void)hipFree(gscr);
             if (rlog) (void)hipFree(rlog);
             throw;
         }
-        if (scratch) GKL_HIP(hipFree(scratch));
+        if (gscr) GKL_HIP(hipFree(gscr));
         if (rlog) GKL_HIP(hipFree(rlog));
         return GKL_OK;
     } catch (const Error& e) {

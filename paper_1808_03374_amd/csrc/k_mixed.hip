@@ -963,7 +963,7 @@ size_t mixed_partial_elems(const MixedShape& m)
 }
 
 static void matmat_bf16(const MixedShape& m, const uint8_t* I, const ColStats& st, const double* W,
-                        int64_t ldw, int b, double* Y, int64_t ldy, MixedWork& w, hipStream_t s)
+                        int64_t ldw, int b, double* Y, int64_t ldy, MixedWork& w, hipStream_t s, const hipEvent_t* ev)
 {
     const bool pack = b <= 8;
     for (int col0 = 0; col0 < b; col0 += 16) {
@@ -981,6 +981,7 @@ static void matmat_bf16(const MixedShape& m, const uint8_t* I, const ColStats& s
                            W + (int64_t)col0 * ldw, ldw, m.p, st.mean, st.inv_sd, w.cpart, w.cmax);
         GKL_LAUNCH_CHECK("colsum_kernel");
         dim3 grid((unsigned int)(m.nI / (kMxWaves * kRTw * 16)), (unsigned int)m.splitW);
+        if (ev && col0 == 0) GKL_HIP(hipEventRecord(ev[0], s));
         if (pack)
             hipLaunchKernelGGL(matmat_bf16_kernel<true>, grid, dim3(256), 0, s, I, m.ldI, m.nI,
                                reinterpret_cast<const bf16x8*>(w.frag), m.nstW, m.stW, w.partial);
@@ -988,6 +989,7 @@ static void matmat_bf16(const MixedShape& m, const uint8_t* I, const ColStats& s
             hipLaunchKernelGGL(matmat_bf16_kernel<false>, grid, dim3(256), 0, s, I, m.ldI, m.nI,
                                reinterpret_cast<const bf16x8*>(w.frag), m.nstW, m.stW, w.partial);
         GKL_LAUNCH_CHECK("matmat_bf16_kernel");
+        if (ev && col0 + 16 >= b) GKL_HIP(hipEventRecord(ev[1], s));
         const dim3 gred(ceil_div(m.n * 16, 256));
         if (pack)
             hipLaunchKernelGGL(matmat_reduce_kernel<true>, gred, dim3(256), 0, s, w.partial,
@@ -1000,7 +1002,7 @@ static void matmat_bf16(const MixedShape& m, const uint8_t* I, const ColStats& s
 }
 
 static void rmatmat_bf16(const MixedShape& m, const uint8_t* S, const ColStats& st, const double* X,
-                         int64_t ldx, int b, double* Z, int64_t ldz, MixedWork& w, hipStream_t s)
+                         int64_t ldx, int b, double* Z, int64_t ldz, MixedWork& w, hipStream_t s, const hipEvent_t* ev)
 {
     const bool pack = b <= 8;
     for (int col0 = 0; col0 < b; col0 += 16) {
@@ -1018,6 +1020,7 @@ static void rmatmat_bf16(const MixedShape& m, const uint8_t* S, const ColStats& 
                            X + (int64_t)col0 * ldx, ldx, m.n, nullptr, nullptr, w.cpart, w.cmax);
         GKL_LAUNCH_CHECK("colsum_kernel");
         dim3 grid((unsigned int)(m.pS / (kMxWaves * kRTr * 16)), (unsigned int)m.splitX);
+        if (ev && col0 == 0) GKL_HIP(hipEventRecord(ev[0], s));
         if (pack)
             hipLaunchKernelGGL(rmatmat_bf16_kernel<true>, grid, dim3(256), 0, s, S, m.ldS, m.pS,
                                reinterpret_cast<const bf16x8*>(w.frag), m.nstX, m.stX, w.partial);
@@ -1025,6 +1028,7 @@ static void rmatmat_bf16(const MixedShape& m, const uint8_t* S, const ColStats& 
             hipLaunchKernelGGL(rmatmat_bf16_kernel<false>, grid, dim3(256), 0, s, S, m.ldS, m.pS,
                                reinterpret_cast<const bf16x8*>(w.frag), m.nstX, m.stX, w.partial);
         GKL_LAUNCH_CHECK("rmatmat_bf16_kernel");
+        if (ev && col0 + 16 >= b) GKL_HIP(hipEventRecord(ev[1], s));
         const dim3 gred(ceil_div(m.p * 16, 256));
         if (pack)
             hipLaunchKernelGGL(rmatmat_reduce_kernel<true>, gred, dim3(256), 0, s, w.partial,
@@ -1039,7 +1043,7 @@ static void rmatmat_bf16(const MixedShape& m, const uint8_t* S, const ColStats& 
 }
 
 static void matmat_i8(const MixedShape& m, const uint8_t* I, const ColStats& st, const double* W,
-                      int64_t ldw, int b, double* Y, int64_t ldy, MixedWork& w, hipStream_t s)
+                      int64_t ldw, int b, double* Y, int64_t ldy, MixedWork& w, hipStream_t s, const hipEvent_t* ev)
 {
     for (int col0 = 0; col0 < b; col0 += 16) {
         const int nb = b - col0 < 16 ? b - col0 : 16;
@@ -1056,16 +1060,19 @@ static void matmat_i8(const MixedShape& m, const uint8_t* I, const ColStats& st,
             hipLaunchKernelGGL(split_W_i8_kernel<true>, gsplit, dim3(256), 0, s, Wc, ldw, nb, m.p,
                                st.mean, st.inv_sd, w.cmax, m.nstW, frag);
             GKL_LAUNCH_CHECK("split_W_i8_kernel");
+            if (ev && col0 == 0) GKL_HIP(hipEventRecord(ev[0], s));
             hipLaunchKernelGGL(matmat_i8_kernel<true>, grid, dim3(256), 0, s, I, m.ldI, m.nI, frag,
                                m.nstW, m.stW, w.partial);
         } else {
             hipLaunchKernelGGL(split_W_i8_kernel<false>, gsplit, dim3(256), 0, s, Wc, ldw, nb, m.p,
                                st.mean, st.inv_sd, w.cmax, m.nstW, frag);
             GKL_LAUNCH_CHECK("split_W_i8_kernel");
+            if (ev && col0 == 0) GKL_HIP(hipEventRecord(ev[0], s));
             hipLaunchKernelGGL(matmat_i8_kernel<false>, grid, dim3(256), 0, s, I, m.ldI, m.nI, frag,
                                m.nstW, m.stW, w.partial);
         }
         GKL_LAUNCH_CHECK("matmat_i8_kernel");
+        if (ev && col0 + 16 >= b) GKL_HIP(hipEventRecord(ev[1], s));
         hipLaunchKernelGGL(matmat_i8_reduce_kernel, dim3(ceil_div(m.n * 16, 256)), dim3(256), 0, s,
                            w.partial, m.splitW, m.nI, m.n, nb, w.cpart, w.cmax,
                            Y + (int64_t)col0 * ldy, ldy);
@@ -1074,7 +1081,7 @@ static void matmat_i8(const MixedShape& m, const uint8_t* I, const ColStats& st,
 }
 
 static void rmatmat_i8(const MixedShape& m, const uint8_t* S, const ColStats& st, const double* X,
-                       int64_t ldx, int b, double* Z, int64_t ldz, MixedWork& w, hipStream_t s)
+                       int64_t ldx, int b, double* Z, int64_t ldz, MixedWork& w, hipStream_t s, const hipEvent_t* ev)
 {
     for (int col0 = 0; col0 < b; col0 += 16) {
         const int nb = b - col0 < 16 ? b - col0 : 16;
@@ -1091,16 +1098,19 @@ static void rmatmat_i8(const MixedShape& m, const uint8_t* S, const ColStats& st
             hipLaunchKernelGGL(split_X_i8_kernel<true>, gsplit, dim3(256), 0, s, Xc, ldx, nb, m.n,
                                w.cmax, m.nstX, frag);
             GKL_LAUNCH_CHECK("split_X_i8_kernel");
+            if (ev && col0 == 0) GKL_HIP(hipEventRecord(ev[0], s));
             hipLaunchKernelGGL(rmatmat_i8_kernel<true>, grid, dim3(256), 0, s, S, m.ldS, m.pS, frag,
                                m.nstX, m.stX, w.partial);
         } else {
             hipLaunchKernelGGL(split_X_i8_kernel<false>, gsplit, dim3(256), 0, s, Xc, ldx, nb, m.n,
                                w.cmax, m.nstX, frag);
             GKL_LAUNCH_CHECK("split_X_i8_kernel");
+            if (ev && col0 == 0) GKL_HIP(hipEventRecord(ev[0], s));
             hipLaunchKernelGGL(rmatmat_i8_kernel<false>, grid, dim3(256), 0, s, S, m.ldS, m.pS, frag,
                                m.nstX, m.stX, w.partial);
         }
         GKL_LAUNCH_CHECK("rmatmat_i8_kernel");
+        if (ev && col0 + 16 >= b) GKL_HIP(hipEventRecord(ev[1], s));
         hipLaunchKernelGGL(rmatmat_i8_reduce_kernel, dim3(ceil_div(m.p * 16, 256)), dim3(256), 0, s,
                            w.partial, m.splitX, m.pS, m.p, nb, w.cpart, w.cmax, st.mean, st.inv_sd,
                            Z + (int64_t)col0 * ldz, ldz);
@@ -1110,18 +1120,18 @@ static void rmatmat_i8(const MixedShape& m, const uint8_t* S, const ColStats& st
 
 void launch_matmat_mixed(const MixedShape& m, const uint8_t* I, const ColStats& st,
                          const double* W, int64_t ldw, int b, double* Y, int64_t ldy,
-                         MixedWork& w, hipStream_t s)
+                         MixedWork& w, hipStream_t s, const hipEvent_t* core_ev)
 {
-    if (m.int8) matmat_i8(m, I, st, W, ldw, b, Y, ldy, w, s);
-    else matmat_bf16(m, I, st, W, ldw, b, Y, ldy, w, s);
+    if (m.int8) matmat_i8(m, I, st, W, ldw, b, Y, ldy, w, s, core_ev);
+    else matmat_bf16(m, I, st, W, ldw, b, Y, ldy, w, s, core_ev);
 }
 
 void launch_rmatmat_mixed(const MixedShape& m, const uint8_t* S, const ColStats& st,
                           const double* X, int64_t ldx, int b, double* Z, int64_t ldz,
-                          MixedWork& w, hipStream_t s)
+                          MixedWork& w, hipStream_t s, const hipEvent_t* core_ev)
 {
-    if (m.int8) rmatmat_i8(m, S, st, X, ldx, b, Z, ldz, w, s);
-    else rmatmat_bf16(m, S, st, X, ldx, b, Z, ldz, w, s);
+    if (m.int8) rmatmat_i8(m, S, st, X, ldx, b, Z, ldz, w, s, core_ev);
+    else rmatmat_bf16(m, S, st, X, ldx, b, Z, ldz, w, s, core_ev);
 }
 
 }  // namespace gkl

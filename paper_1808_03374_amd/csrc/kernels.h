@@ -302,12 +302,13 @@ size_t mixed_partial_elems(const MixedShape& m);
 void build_mixed_layouts(const uint8_t* G, int64_t n, int64_t p, int64_t ld, uint8_t* I,
                          uint8_t* S, hipStream_t s);
 // Y (n x b, ldy) = A W (W: p x b, ldw); Z (p x b, ldz) = A^T X (X: n x b, ldx); b <= 32.
+// core_ev (optional): two events recorded around the matrix-core kernels
 void launch_matmat_mixed(const MixedShape& m, const uint8_t* I, const ColStats& st,
                          const double* W, int64_t ldw, int b, double* Y, int64_t ldy,
-                         MixedWork& w, hipStream_t s);
+                         MixedWork& w, hipStream_t s, const hipEvent_t* core_ev = nullptr);
 void launch_rmatmat_mixed(const MixedShape& m, const uint8_t* S, const ColStats& st,
                           const double* X, int64_t ldx, int b, double* Z, int64_t ldz,
-                          MixedWork& w, hipStream_t s);
+                          MixedWork& w, hipStream_t s, const hipEvent_t* core_ev = nullptr);
 
 // ---- k_block.hip: FP64 block operations ----
 size_t gemm_tn_partial_elems(int64_t len, int q);

@@ -161,8 +161,9 @@ gkl_status gkl_ctx::solve_mixed(double* sigma, double* Uo, int64_t ldu, double* 
         double* Vn = M.V + (int64_t)(o + b) * p;
         // left block: A V_o minus the coupling to the previous left block
         const int ev = timing_begin(false);
-        launch_matmat_mixed(M.shape, M.I, prob.st, Vb, p, b, Ub, n, M.w, s);
-        timing_end(ev, false);
+        launch_matmat_mixed(M.shape, M.I, prob.st, Vb, p, b, Ub, n, M.w, s,
+                            ev >= 0 ? &ev_pool[ev + 2] : nullptr);
+        timing_end(ev, false, true);
         info.matvecs += b;
         info.passes_over_G += (b + 15) / 16;
         if (o > 0) {
@@ -178,8 +179,9 @@ gkl_status gkl_ctx::solve_mixed(double* sigma, double* Uo, int64_t ldu, double* 
         launch_put_block(M.Bm, M.ldb, o, o, M.R, b, b, b, 0, s);
         // right block: A^T U_o - V_o R^T
         const int ev2 = timing_begin(true);
-        launch_rmatmat_mixed(M.shape, M.S, prob.st, Ub, n, b, Vn, p, M.w, s);
-        timing_end(ev2, true);
+        launch_rmatmat_mixed(M.shape, M.S, prob.st, Ub, n, b, Vn, p, M.w, s,
+                             ev2 >= 0 ? &ev_pool[ev2 + 2] : nullptr);
+        timing_end(ev2, true, true);
         info.matvecs += b;
         info.passes_over_G += (b + 15) / 16;
         launch_put_block(M.RT, b, 0, 0, M.R, b, b, b, 1, s);
