@@ -241,6 +241,21 @@ gkl_status gkl_get_trace(gkl_ctx* ctx, double* buf, int64_t cap, int64_t* writte
 gkl_status gkl_dense_svd(const double* B, int32_t m, double* P, double* S, double* Q,
                          void* stream);
 
+/*
+ * gkl_dense_svd_noalloc -- gkl_dense_svd for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments and the same result bit for bit, for
+ * 1 <= m <= GKL_DENSE_SVD_NOALLOC_MAX_M; larger m returns GKL_ERR_INVALID.
+ * It calls no allocating routine: the rotation log / working matrices live in
+ * a fixed 5 MiB device array inside the library, one copy per GPU, held until
+ * the process ends.  All calls on one GPU share that array, so calls that
+ * overlap in time on one GPU (several streams or host threads) race; serialise
+ * them.  The call is synchronous on `stream`.
+ */
+#define GKL_DENSE_SVD_NOALLOC_MAX_M 256
+gkl_status gkl_dense_svd_noalloc(const double* B, int32_t m, double* P, double* S, double* Q,
+                                 void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -124,6 +124,7 @@ _SIGS = {
     "gkl_rmatmat_mixed": (_st, [_vp, _vp, _i32, _vp]),
     "gkl_get_trace": (_st, [_vp, _vp, _i64, ctypes.POINTER(_i64)]),
     "gkl_dense_svd": (_st, [_vp, _i32, _vp, _vp, _vp, _vp]),
+    "gkl_dense_svd_noalloc": (_st, [_vp, _i32, _vp, _vp, _vp, _vp]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(lib, _name)
@@ -264,6 +265,10 @@ def gkl_get_trace(ctx, max_rows=100000):
 
 def gkl_dense_svd(B, m, P, S, Q, stream=None):
     _check(lib.gkl_dense_svd(_ptr(B), m, _ptr(P), _ptr(S), _ptr(Q), stream))
+
+
+def gkl_dense_svd_noalloc(B, m, P, S, Q, stream=None):
+    _check(lib.gkl_dense_svd_noalloc(_ptr(B), m, _ptr(P), _ptr(S), _ptr(Q), stream))
 
 
 # ---------------------------------------------------------------------------

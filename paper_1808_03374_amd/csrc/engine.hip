@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -820,6 +821,82 @@ gkl_status gkl_dense_svd(const double* B, int32_t m, double* P, double* S, doubl
         }
         if (gscr) GKL_HIP(hipFree(gscr));
         if (rlog) GKL_HIP(hipFree(rlog));
+        return GKL_OK;
+    } catch (const Error& e) {
+        return set_error(nullptr, e.status, e.msg);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// gkl_dense_svd_noalloc: the same SVD with its working memory in a file-scope
+// device array instead of a hipMalloc'ed buffer.
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+// Largest m taken by gkl_dense_svd_noalloc and the scratch it may need: the
+// rotation log of the in-LDS path for 96 < m <= 128 (svd_log_elems(128) =
+// 650,240 doubles) or the working matrices of the global path for
+// 128 < m <= 256 (about 135,000 doubles); 5 MiB covers both.
+constexpr int kNoAllocMaxM = GKL_DENSE_SVD_NOALLOC_MAX_M;
+constexpr size_t kNoAllocScratchElems = 655360;
+constexpr int kNoAllocMaxDevices = 64;
+}  // namespace
+
+// Device copy per GPU, kept until the process ends.  In host code `scratch`
+// names a host-side stand-in, never the device memory: host code uses the
+// address hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) double scratch[kNoAllocScratchElems];
+
+static std::mutex g_noalloc_mu;
+static double* g_noalloc_ptr[kNoAllocMaxDevices] = {};
+
+// The current device's address of `scratch`, looked up once per device.
+static double* noalloc_scratch()
+{
+    int dev = -1;
+    GKL_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNoAllocMaxDevices)
+        fail(GKL_ERR_DEVICE, "device index out of range for the scratch table");
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || ptr == nullptr)
+            fail(GKL_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_noalloc_ptr[dev] = static_cast<double*>(ptr);
+    }
+    return g_noalloc_ptr[dev];
+}
+
+extern "C" {
+
+gkl_status gkl_dense_svd_noalloc(const double* B, int32_t m, double* P, double* S, double* Q,
+                                 void* stream)
+{
+    if (!B || !P || !S || !Q)
+        return set_error(nullptr, GKL_ERR_INVALID, "gkl_dense_svd_noalloc: NULL pointer argument");
+    if (m < 1 || m > kNoAllocMaxM)
+        return set_error(nullptr, GKL_ERR_INVALID,
+                         "gkl_dense_svd_noalloc: m must lie in [1, " + std::to_string(kNoAllocMaxM) +
+                             "] (its scratch is a fixed 5 MiB device array)");
+    try {
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        double* gscr = nullptr;
+        double* rlog = nullptr;
+        if (!svd_fits_lds(m)) {
+            const bool logged = svd_logged_fits_lds(m);
+            const size_t need = logged ? svd_log_elems(m) : svd_scratch_elems(m);
+            if (need > kNoAllocScratchElems)
+                fail(GKL_ERR_INVALID, "gkl_dense_svd_noalloc: m needs more than the fixed scratch");
+            double* ptr = noalloc_scratch();
+            (logged ? rlog : gscr) = ptr;
+        }
+        // every scratch element the kernel reads it has written earlier in the
+        // same launch (the log is replayed only up to the sweeps just run, the
+        // working matrices are filled from B first), so nothing is cleared
+        launch_dense_svd(B, m, P, S, Q, gscr, s, rlog);
+        GKL_HIP(hipStreamSynchronize(s));
         return GKL_OK;
     } catch (const Error& e) {
         return set_error(nullptr, e.status, e.msg);
