@@ -703,32 +703,4 @@ void launch_brmatvec_reduce(const BatchDesc* d, const int* state, int count, int
     GKL_LAUNCH_CHECK("brmatvec_reduce_kernel");
 }
 
-// Unpack from layout T to n x p column-major int8 (-1 = missing).
-__global__ void unpack_T_kernel(const uint8_t* __restrict__ T, int64_t nT, int64_t n, int64_t p,
-                                int64_t Pq, int8_t* __restrict__ out)
-{
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n * Pq;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t J = t / n;
-        const int64_t i = t - J * n;
-        const uint32_t b = T[J * nT + i];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int64_t j = 4 * J + k;
-            if (j < p) {
-                const int c = (b >> (2 * k)) & 3;
-                out[j * n + i] = (int8_t)(c == 3 ? -1 : c);
-            }
-        }
-    }
-}
-
-void launch_unpack_layout(const Packed& L, int8_t* out, hipStream_t s)
-{
-    const int64_t total = L.n * L.Pq;
-    hipLaunchKernelGGL(unpack_T_kernel, dim3(stride_grid(total, 256)), dim3(256), 0, s, L.T, L.nT, L.n,
-                       L.p, L.Pq, out);
-    GKL_LAUNCH_CHECK("unpack_T_kernel");
-}
-
 }  // namespace gkl

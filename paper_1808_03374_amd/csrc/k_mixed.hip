@@ -57,9 +57,6 @@ typedef int i32x4 __attribute__((ext_vector_type(4)));
 
 namespace {
 constexpr int kKSteps = 256 / 32;      // split BF16: MFMA K steps per super-tile
-constexpr int kRTw = 8;                // split BF16, A W: row tiles per wave
-constexpr int kRTr = 4;                // split BF16, A^T X: row tiles per wave
-constexpr int kFlush = 4;              // split BF16: super-tiles per FP32 chunk
 constexpr int kSuper = 256;            // K per super-tile (64 bytes of codes per row)
 constexpr int kWords = kSuper / 64;    // MFMA K steps per super-tile (one code word per lane)
 constexpr int kQBits = 22;             // |q| <= 2^kQBits (so |l0| <= 65 fits int8)
@@ -215,21 +212,51 @@ __device__ __forceinline__ i32x4 mfma_i8(i32x4 a, i32x4 b, i32x4 c)
 }
 
 // ---------------------------------------------------------------------------
-// Split BF16: decode 16 codes of a word -> 8 pair words of each pattern
+// Split BF16: genotype operands decoded in registers
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void decode16(uint32_t d, uint32_t C[8], uint32_t M[8])
+// A lane's 32-bit word d holds 16 codes (code q at bits 2q, 2q + 1).  Pair word
+// k (k = 0..7) of an operand holds code k in its low bf16 and code k + 8 in its
+// high bf16; pair words 4h..4h+3 are the lane's 8 elements of MFMA K step h, so
+// element e of K step h is code 4h + (e >> 1) + 8 (e & 1) (code_pos).
+//
+// g operand: a code's two bits become the two low bits of the bf16 exponent --
+// one shift and one mask per pair word -- so codes 0, 1, 2, 3 read as 0, 1, 2
+// and 4 times 2^-126, all exact.  The missing code thus counts 4 in the g sum;
+// the missing operand removes it.  The vector operand carries the factor 2^126.
+constexpr uint32_t kExpLow = 0x01800180u;
+
+// The four pair words of K step h: G[i] = pair word 4h + i.
+__device__ __forceinline__ void g_pairs_half(uint32_t d, int h, uint32_t G[4])
 {
-    // table bytes {S0:S1} = [lo(c=0), hi(c=0), lo(1), hi(1), lo(2), hi(2), lo(3), hi(3)]
-    constexpr uint32_t kG1 = 0x3F800000u, kG0 = 0x00004000u;   // g: 0, 1.0, 2.0, 0
-    constexpr uint32_t kM1 = 0x00000000u, kM0 = 0x3F800000u;   // m: 0, 0, 0, 1.0
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const uint32_t u = (d >> (2 * k)) & 0x00030003u;        // code k (byte 0), k+8 (byte 2)
-        const uint32_t sel = u * 0x0202u + 0x01000100u;        // [2c, 2c+1, 2c', 2c'+1]
-        C[k] = __builtin_amdgcn_perm(kG0, kG1, sel);
-        M[k] = __builtin_amdgcn_perm(kM0, kM1, sel);
+    for (int i = 0; i < 4; ++i) {
+        const int k = 4 * h + i;
+        G[i] = (k < 4 ? d << (7 - 2 * k) : d >> (2 * k - 7)) & kExpLow;
     }
 }
+
+// Missing flags at the scale of the g operand (2^-126), used by A^T X: a code is
+// missing when both its bits are set, i.e. bits 7 and 8 (23 and 24) of its g
+// pair word: M = G & (G >> 1).
+//
+// Missing flags with no shift per pair word, used by A W: f = d & (d >> 1) holds
+// the flag of code q at bit 2q.  Those of codes 4..7 and 12..15 already sit at
+// bits 8 + 2i and 24 + 2i (i = k - 4), inside the bf16 exponents; those of codes
+// 0..3 and 8..11 get there by one shift of f by 8.  A lone exponent bit 1 + 2i
+// is the bf16 2^(2^(1 + 2i) - 127): 2^-125, 2^-119, 2^-95, 2^1 for i = 0..3
+// (m_scale_exp of the element); the vector operand carries the inverse factor
+// element by element.
+__device__ __forceinline__ void m_pairs_scaled_half(uint32_t d, int h, uint32_t M[4])
+{
+    const uint32_t f = d & (d >> 1);
+    const uint32_t fh = h == 0 ? f << 8 : f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) M[i] = fh & (0x01000100u << (2 * i));
+}
+
+// Exponent of the value a set missing flag takes in element e of a K step
+// (m_pairs_scaled): element e belongs to pair word 4h + (e >> 1).
+__host__ __device__ __forceinline__ int m_scale_exp(int e) { return (1 << (1 + 2 * (e >> 1))) - 127; }
 
 __device__ __forceinline__ bf16x8 pack4(uint32_t a, uint32_t b, uint32_t c, uint32_t d)
 {
@@ -238,60 +265,39 @@ __device__ __forceinline__ bf16x8 pack4(uint32_t a, uint32_t b, uint32_t c, uint
     return __builtin_bit_cast(bf16x8, v);
 }
 
+__device__ __forceinline__ f32x4 mfma_bf16(bf16x8 a, bf16x8 b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
 // position (within the lane's 16-code word) of element e of K step h
 __host__ __device__ __forceinline__ int code_pos(int h, int e) { return 4 * h + (e >> 1) + 8 * (e & 1); }
 
 __device__ __forceinline__ __bf16 to_bf16(double v) { return (__bf16)(float)v; }
 
-// ---------------------------------------------------------------------------
-// Vector fragments
-// ---------------------------------------------------------------------------
-// A W operands.  kPack == false: frag[((st*8 + t)*4 + op)*64 + lane][e], ops
-// 0..3 = W'hi, W'lo, X'hi, X'lo for the 16 columns starting at col0.
-// kPack == true (b <= 8): two operands whose 16 columns hold the hi parts of the
-// b columns in 0..7 and their lo parts in 8..15: op 0 = [W'hi | W'lo], op 1 =
-// [X'hi | X'lo]; one MFMA per operand then covers both halves of the split.
-template <bool kPack>
-__global__ void split_W_kernel(const double* __restrict__ W, int64_t ldw, int b, int col0,
-                               int64_t p, const double* __restrict__ mean,
-                               const double* __restrict__ inv_sd, int64_t nst,
-                               bf16x8* __restrict__ frag)
+// Products are formed at 2^-(kProdShift + ex_c): the g vector operand holds
+// v 2^(126 - kProdShift - ex_c), the missing one v 2^(-m_scale_exp(e) -
+// kProdShift - ex_c), with 2^ex_c >= the column's largest |v|.  Every operand then
+// lies below 2^110 (bf16 and FP32 reach 2^128) and every product is a normal FP32.
+constexpr int kProdShift = 16;
+
+// Workgroup -> (K split, row block).  Workgroups are dealt to the 8 XCDs of the
+// chip round robin (workgroup g runs on XCD g % 8), each XCD with its own L2.
+// With xcd set (nsplit a multiple of 8) every row block of one K split runs on
+// the same XCD, so the split's vector fragments come from that XCD's L2 after
+// the first touch instead of from the memory-side cache.
+__device__ __forceinline__ void block_coords(int g, int nsplit, int nrb, int xcd, int& split,
+                                             int& rb)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // (st, ks, lane)
-    if (t >= nst * kKSteps * 64) return;
-    const int lane = (int)(t & 63);
-    const int ks = (int)((t >> 6) % kKSteps);
-    const int64_t st = t / (64 * kKSteps);
-    const int g = lane >> 4;
-    const int col = kPack ? (lane & 7) : col0 + (lane & 15);
-    const bool hi_half = !kPack || (lane & 15) < 8;
-    bf16x8 whi, wlo, zhi, zlo;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const int64_t j = st * kSuper + 64 * g + 16 * (ks >> 1) + code_pos(ks & 1, e);
-        double w = 0.0, z = 0.0;
-        if (j < p && col < b) {
-            w = inv_sd[j] * W[(int64_t)col * ldw + j];
-            z = mean[j] * w;
-        }
-        const __bf16 h1 = to_bf16(w), h2 = to_bf16(z);
-        const __bf16 l1 = to_bf16(w - (double)(float)h1), l2 = to_bf16(z - (double)(float)h2);
-        whi[e] = hi_half ? h1 : l1;
-        zhi[e] = hi_half ? h2 : l2;
-        wlo[e] = l1;
-        zlo[e] = l2;
-    }
-    if (kPack) {
-        bf16x8* f = frag + (((st * kKSteps + ks) * 2) * 64) + lane;
-        f[0 * 64] = whi;
-        f[1 * 64] = zhi;
+    if (xcd) {
+        const int x = g & 7, q = g >> 3;
+        split = x + 8 * (q / nrb);
+        rb = q % nrb;
     } else {
-        bf16x8* f = frag + (((st * kKSteps + ks) * 4) * 64) + lane;
-        f[0 * 64] = whi;
-        f[1 * 64] = wlo;
-        f[2 * 64] = zhi;
-        f[3 * 64] = zlo;
+        split = g / nrb;
+        rb = g % nrb;
     }
+    (void)nsplit;
 }
 
 // ---------------------------------------------------------------------------
@@ -300,8 +306,10 @@ __global__ void split_W_kernel(const double* __restrict__ W, int64_t ldw, int b,
 // Column sums over len rows: sum_j f_j X(j, c), with f_j = mean_j inv_sd_j when
 // mean != NULL (the product mean_j (inv_sd_j x) is formed in that order) and
 // f_j = 1 otherwise (per column c: K2_c = sum_j mu_j s_j W_jc for A W, T_c =
-// sum_i X_ic for A^T X); with them the largest magnitude to be quantised:
-// (3 - mu_j) |s_j W_jc| (= |Z'_jc| >= |W'_jc|) for A W, |X_ic| for A^T X.
+// sum_i X_ic for A^T X); with them the largest magnitude to be scaled:
+// |mref - mu_j| |s_j W_jc| for A W (the missing-operand values, which bound
+// |s_j W_jc| since mref - mu_j >= 1; mref = 3 for int8 limbs, 4 for split BF16),
+// |X_ic| for A^T X.
 // grid (kCsSplit, columns): each block writes its chunk's sum and maximum to
 // cpart / cmax[c * kCsSplit + chunk]; consumers add / take the maximum of the
 // chunk values themselves (no cross-block handshake: its device-scope fences
@@ -310,7 +318,7 @@ constexpr int kCsSplit = 64;   // == wavefront size (the chunk values are combin
 
 __global__ void __launch_bounds__(256)
 colsum_kernel(const double* __restrict__ X, int64_t ldx, int64_t len,
-              const double* __restrict__ mean, const double* __restrict__ inv_sd,
+              const double* __restrict__ mean, const double* __restrict__ inv_sd, double mref,
               double* __restrict__ cpart, double* __restrict__ cmax)
 {
     __shared__ double sh[16];
@@ -324,7 +332,7 @@ colsum_kernel(const double* __restrict__ X, int64_t ldx, int64_t len,
         for (int64_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
             const double w = inv_sd[j] * xc[j];
             a += mean[j] * w;
-            mx = fmax(mx, fabs((mean[j] - 3.0) * w));
+            mx = fmax(mx, fabs((mean[j] - mref) * w));
         }
     } else {
         for (int64_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
@@ -373,261 +381,409 @@ __device__ __forceinline__ void column_scales(const double* __restrict__ cmax, i
     __syncthreads();
 }
 
-// A^T X operands.  kPack == false: frag[((st*8 + t)*2 + op)*64 + lane][e], ops
-// 0..1 = Xhi, Xlo.  kPack == true (b <= 8): one operand [Xhi | Xlo] (hi parts in
-// columns 0..7, lo parts in 8..15), frag[(st*8 + t)*64 + lane].
-template <bool kPack>
-__global__ void split_X_kernel(const double* __restrict__ X, int64_t ldx, int b, int col0,
-                               int64_t n, int64_t nst, bf16x8* __restrict__ frag)
+// ---------------------------------------------------------------------------
+// Split BF16: vector fragments
+// ---------------------------------------------------------------------------
+// frag[((st * kKSteps + ks) * ops + op) * 64 + lane] holds the 8 elements of MFMA
+// K step ks of super-tile st for operand op; element e is contraction index
+// st * 256 + 64 (lane >> 4) + 16 (ks >> 1) + code_pos(ks & 1, e).
+//   kPack (b <= 8): the 16 columns of an operand hold the hi parts of the b
+//   columns in 0..7 and their lo parts in 8..15 (one MFMA covers both halves).
+//   Otherwise column tile t (16 columns, t < kT) has its own operands.
+// A W operands: kPack: op 0 = g part, op 1 = missing part; otherwise op 4t + q,
+// q = g hi, g lo, missing hi, missing lo.  g part v = s_j W_jc, missing part
+// z = (mu_j - 4) s_j W_jc (the g operand counts the missing code as 4).
+template <bool kPack, int kT>
+__global__ void __launch_bounds__(256)
+split_W_bf16_kernel(const double* __restrict__ W, int64_t ldw, int nb, int64_t p,
+                    const double* __restrict__ mean, const double* __restrict__ inv_sd,
+                    const double* __restrict__ cmax, int64_t nst, bf16x8* __restrict__ frag)
 {
+    constexpr int kOps = kPack ? 2 : 4 * kT;
+    constexpr int kTiles = kPack ? 1 : kT;
+    __shared__ int ex[32];
+    column_scales(cmax, nb, ex);
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // (st, ks, lane)
+    if (t >= nst * kKSteps * 64) return;
+    const int lane = (int)(t & 63);
+    const int ks = (int)((t >> 6) % kKSteps);
+    const int64_t st = t / (64 * kKSteps);
+    const int g = lane >> 4, cl = lane & 15;
+    bf16x8 out[kOps];
+#pragma unroll
+    for (int tile = 0; tile < kTiles; ++tile) {
+        const int col = kPack ? (cl & 7) : 16 * tile + cl;
+        const bool lo_half = kPack && cl >= 8;
+        const int e_c = col < nb ? ex[col] : 0;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int64_t j = st * kSuper + 64 * g + 16 * (ks >> 1) + code_pos(ks & 1, e);
+            double v = 0.0, z = 0.0;
+            if (j < p && col < nb) {
+                v = inv_sd[j] * W[(int64_t)col * ldw + j];
+                z = (mean[j] - 4.0) * v;
+            }
+            const double vg = ldexp(v, 126 - kProdShift - e_c);
+            const double zm = ldexp(z, -m_scale_exp(e) - kProdShift - e_c);
+            const __bf16 gh = to_bf16(vg), mh = to_bf16(zm);
+            const __bf16 gl = to_bf16(vg - (double)(float)gh), ml = to_bf16(zm - (double)(float)mh);
+            if (kPack) {
+                out[0][e] = lo_half ? gl : gh;
+                out[1][e] = lo_half ? ml : mh;
+            } else {
+                out[4 * tile + 0][e] = gh;
+                out[4 * tile + 1][e] = gl;
+                out[4 * tile + 2][e] = mh;
+                out[4 * tile + 3][e] = ml;
+            }
+        }
+    }
+    bf16x8* f = frag + ((st * kKSteps + ks) * kOps) * 64 + lane;
+#pragma unroll
+    for (int op = 0; op < kOps; ++op) f[op * 64] = out[op];
+}
+
+// A^T X operands (the g and missing operands share them: both carry 2^-126):
+// kPack: op 0; otherwise op 2t + q, q = hi, lo.  Element value x 2^(126 -
+// kProdShift - ex_c).
+template <bool kPack, int kT>
+__global__ void __launch_bounds__(256)
+split_X_bf16_kernel(const double* __restrict__ X, int64_t ldx, int nb, int64_t n,
+                    const double* __restrict__ cmax, int64_t nst, bf16x8* __restrict__ frag)
+{
+    constexpr int kOps = kPack ? 1 : 2 * kT;
+    constexpr int kTiles = kPack ? 1 : kT;
+    __shared__ int ex[32];
+    column_scales(cmax, nb, ex);
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nst * kKSteps * 64) return;
     const int lane = (int)(t & 63);
     const int ks = (int)((t >> 6) % kKSteps);
     const int64_t st = t / (64 * kKSteps);
-    const int g = lane >> 4;
-    const int col = kPack ? (lane & 7) : col0 + (lane & 15);
-    const bool hi_half = !kPack || (lane & 15) < 8;
-    bf16x8 xhi, xlo;
+    const int g = lane >> 4, cl = lane & 15;
+    bf16x8 out[kOps];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const int64_t i = st * kSuper + 64 * g + 16 * (ks >> 1) + code_pos(ks & 1, e);
-        double x = 0.0;
-        if (i < n && col < b) x = X[(int64_t)col * ldx + i];
-        const __bf16 h = to_bf16(x);
-        const __bf16 l = to_bf16(x - (double)(float)h);
-        xhi[e] = hi_half ? h : l;
-        xlo[e] = l;
+    for (int tile = 0; tile < kTiles; ++tile) {
+        const int col = kPack ? (cl & 7) : 16 * tile + cl;
+        const bool lo_half = kPack && cl >= 8;
+        const int e_c = col < nb ? ex[col] : 0;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int64_t i = st * kSuper + 64 * g + 16 * (ks >> 1) + code_pos(ks & 1, e);
+            const double x = (i < n && col < nb) ? X[(int64_t)col * ldx + i] : 0.0;
+            const double xs = ldexp(x, 126 - kProdShift - e_c);
+            const __bf16 h = to_bf16(xs);
+            const __bf16 l = to_bf16(xs - (double)(float)h);
+            if (kPack) {
+                out[0][e] = lo_half ? l : h;
+            } else {
+                out[2 * tile + 0][e] = h;
+                out[2 * tile + 1][e] = l;
+            }
+        }
     }
-    if (kPack) {
-        frag[(st * kKSteps + ks) * 64 + lane] = xhi;
-    } else {
-        bf16x8* f = frag + (((st * kKSteps + ks) * 2) * 64) + lane;
-        f[0] = xhi;
-        f[64] = xlo;
-    }
+    bf16x8* f = frag + ((st * kKSteps + ks) * kOps) * 64 + lane;
+#pragma unroll
+    for (int op = 0; op < kOps; ++op) f[op * 64] = out[op];
 }
 
 // ---------------------------------------------------------------------------
-// A W main kernel: block = 4 waves x 8 row tiles x 16 rows = 512 rows, K split in
-// super-tiles; partial[split][row][16] FP64.
+// Split BF16: A W.  Workgroup = 4 waves x kRTW row tiles x 16 individuals; one
+// K split of the SNPs.  Each lane loads 16 bytes (64 codes) of its row per
+// super-tile and decodes one 16-code word per two MFMA K steps; the vector
+// fragments of a super-tile are staged in LDS and shared by the row tiles.
+// FP32 accumulation per 1,024 K values, FP64 across those chunks.
+// partial[split][row][kCS] (kCS = 8 packed, 16 kT otherwise; packed rows hold
+// hi + lo already added).
 // ---------------------------------------------------------------------------
-template <bool kPack>
+constexpr int kRTW = 4;       // A W: row tiles per wave
+constexpr int kRTX = 2;       // A^T X: row tiles per wave
+constexpr int kFlush = 4;     // super-tiles per FP32 chunk
+
+template <bool kPack, int kT>
 __global__ void __launch_bounds__(256)
 matmat_bf16_kernel(const uint8_t* __restrict__ I, int64_t ldI, int64_t nI,
                    const bf16x8* __restrict__ frag, int64_t nst, int64_t st_per_split,
-                   double* __restrict__ partial)
+                   int nsplit, int nrb, int xcd, double* __restrict__ partial)
 {
-    constexpr int kOps = kPack ? 2 : 4;
-    __shared__ bf16x8 bs[kKSteps * kOps * 64];      // one super-tile of the operands
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int g = lane >> 4, r = lane & 15;
-    const int64_t row_base = (int64_t)blockIdx.x * (kMxWaves * kRTw * 16) + wave * (kRTw * 16);
-    const int64_t st0 = (int64_t)blockIdx.y * st_per_split;
-    const int64_t st1 = st0 + st_per_split < nst ? st0 + st_per_split : nst;
-    f32x4 acc[kRTw];
-    double accd[kRTw][4];
-#pragma unroll
-    for (int t = 0; t < kRTw; ++t) {
-        acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int e = 0; e < 4; ++e) accd[t][e] = 0.0;
-    }
-    int chunk = 0;
-    for (int64_t st = st0; st < st1; ++st) {
-        uint4 a[kRTw];
-#pragma unroll
-        for (int t = 0; t < kRTw; ++t)
-            a[t] = *reinterpret_cast<const uint4*>(I + tiled_offset(row_base + 16 * t + r, st * 64 + 16 * g, ldI));
-        const bf16x8* src = frag + st * (kKSteps * kOps * 64);
-        for (int q = threadIdx.x; q < kKSteps * kOps * 64; q += 256) bs[q] = src[q];
-        __syncthreads();
-#pragma unroll
-        for (int w = 0; w < 4; ++w) {
-            bf16x8 bw0[2], bw1[2], bz0[2], bz1[2];   // W'hi, W'lo, X'hi, X'lo (packed: 0 only)
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int ks = 2 * w + h;
-                if (kPack) {
-                    bw0[h] = bs[(ks * 2 + 0) * 64 + lane];
-                    bz0[h] = bs[(ks * 2 + 1) * 64 + lane];
-                } else {
-                    bw0[h] = bs[(ks * 4 + 0) * 64 + lane];
-                    bw1[h] = bs[(ks * 4 + 1) * 64 + lane];
-                    bz0[h] = bs[(ks * 4 + 2) * 64 + lane];
-                    bz1[h] = bs[(ks * 4 + 3) * 64 + lane];
-                }
-            }
-#pragma unroll
-            for (int t = 0; t < kRTw; ++t) {
-                const uint32_t d = w == 0 ? a[t].x : w == 1 ? a[t].y : w == 2 ? a[t].z : a[t].w;
-                uint32_t C[8], M[8];
-                decode16(d, C, M);
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const bf16x8 ca = pack4(C[4 * h], C[4 * h + 1], C[4 * h + 2], C[4 * h + 3]);
-                    const bf16x8 ma = pack4(M[4 * h], M[4 * h + 1], M[4 * h + 2], M[4 * h + 3]);
-                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ca, bw0[h], acc[t], 0, 0, 0);
-                    if (!kPack)
-                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ca, bw1[h], acc[t], 0, 0, 0);
-                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ma, bz0[h], acc[t], 0, 0, 0);
-                    if (!kPack)
-                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ma, bz1[h], acc[t], 0, 0, 0);
-                }
-            }
-        }
-        __syncthreads();
-        if (++chunk == kFlush) {
-            chunk = 0;
-#pragma unroll
-            for (int t = 0; t < kRTw; ++t) {
-#pragma unroll
-                for (int e = 0; e < 4; ++e) accd[t][e] += (double)acc[t][e];
-                acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-            }
-        }
-    }
-    double* out = partial + (int64_t)blockIdx.y * nI * 16;
-#pragma unroll
-    for (int t = 0; t < kRTw; ++t) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int64_t row = row_base + 16 * t + 4 * g + e;
-            out[row * 16 + r] = accd[t][e] + (double)acc[t][e];
-        }
-    }
-}
-
-// Y[i + c*ldy] = sum_split partial - K2_c for i < n, c < nb (col0 offset); packed:
-// the hi (column c) and lo (column c + 8) partials of each split are added first.
-template <bool kPack>
-__global__ void __launch_bounds__(256)
-matmat_reduce_kernel(const double* __restrict__ partial, int nsplit, int64_t nI, int64_t n,
-                     int nb, const double* __restrict__ cpart, double* __restrict__ Y,
-                     int64_t ldy)
-{
-    __shared__ double K2[16];
-    column_sums(cpart, nb, K2);
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n * 16) return;
-    const int64_t i = t >> 4;
-    const int c = (int)(t & 15);
-    if (c >= nb) return;
-    const double s = strided_sum<kPack>(partial + i * 16 + c, nI * 16, nsplit, 8);
-    Y[(int64_t)c * ldy + i] = s - K2[c];
-}
-
-// ---------------------------------------------------------------------------
-// A^T X main kernel: block = 4 waves x 4 SNP tiles x 16 = 256 SNPs; K = individuals.
-// partial[split][2][row][16]: sums with the code operand and the missing operand.
-// ---------------------------------------------------------------------------
-template <bool kPack>
-__global__ void __launch_bounds__(256)
-rmatmat_bf16_kernel(const uint8_t* __restrict__ S, int64_t ldS, int64_t pS,
-                    const bf16x8* __restrict__ frag, int64_t nst, int64_t st_per_split,
-                    double* __restrict__ partial)
-{
-    constexpr int kOps = kPack ? 1 : 2;
+    constexpr int kOps = kPack ? 2 : 4 * kT;
+    constexpr int kTiles = kPack ? 1 : kT;
+    constexpr int kCS = kPack ? 8 : 16 * kT;
     __shared__ bf16x8 bs[kKSteps * kOps * 64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = lane >> 4, r = lane & 15;
-    const int64_t row_base = (int64_t)blockIdx.x * (kMxWaves * kRTr * 16) + wave * (kRTr * 16);
-    const int64_t st0 = (int64_t)blockIdx.y * st_per_split;
+    int split, rb;
+    block_coords(blockIdx.x, nsplit, nrb, xcd, split, rb);
+    const int64_t row_base = (int64_t)rb * (kMxWaves * kRTW * 16) + wave * (kRTW * 16);
+    const int64_t st0 = (int64_t)split * st_per_split;
     const int64_t st1 = st0 + st_per_split < nst ? st0 + st_per_split : nst;
-    f32x4 accC[kRTr], accM[kRTr];
-    double dC[kRTr][4], dM[kRTr][4];
+    f32x4 acc[kRTW][kTiles];
+    double accd[kRTW][kTiles][4];
 #pragma unroll
-    for (int t = 0; t < kRTr; ++t) {
-        accC[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-        accM[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < kRTW; ++t)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) { dC[t][e] = 0.0; dM[t][e] = 0.0; }
+        for (int c = 0; c < kTiles; ++c) {
+            acc[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) accd[t][c][e] = 0.0;
+        }
+    uint4 a[kRTW];
+    if (st0 < st1) {
+#pragma unroll
+        for (int t = 0; t < kRTW; ++t)
+            a[t] = *reinterpret_cast<const uint4*>(
+                I + tiled_offset(row_base + 16 * t + r, st0 * 64 + 16 * g, ldI));
     }
     int chunk = 0;
     for (int64_t st = st0; st < st1; ++st) {
-        uint4 a[kRTr];
-#pragma unroll
-        for (int t = 0; t < kRTr; ++t)
-            a[t] = *reinterpret_cast<const uint4*>(S + tiled_offset(row_base + 16 * t + r, st * 64 + 16 * g, ldS));
         const bf16x8* src = frag + st * (kKSteps * kOps * 64);
         for (int q = threadIdx.x; q < kKSteps * kOps * 64; q += 256) bs[q] = src[q];
+        // the next super-tile's codes are in flight while this one is used
+        uint4 an[kRTW];
+        const int64_t stn = st + 1 < st1 ? st + 1 : st;
+#pragma unroll
+        for (int t = 0; t < kRTW; ++t)
+            an[t] = *reinterpret_cast<const uint4*>(
+                I + tiled_offset(row_base + 16 * t + r, stn * 64 + 16 * g, ldI));
         __syncthreads();
 #pragma unroll
-        for (int w = 0; w < 4; ++w) {
-            bf16x8 x0[2], x1[2];
+        for (int ks = 0; ks < kKSteps; ++ks) {
+            const int w = ks >> 1, h = ks & 1;
+            bf16x8 bo[kOps];
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int ks = 2 * w + h;
-                if (kPack) {
-                    x0[h] = bs[ks * 64 + lane];
-                } else {
-                    x0[h] = bs[(ks * 2 + 0) * 64 + lane];
-                    x1[h] = bs[(ks * 2 + 1) * 64 + lane];
-                }
-            }
+            for (int op = 0; op < kOps; ++op) bo[op] = bs[(ks * kOps + op) * 64 + lane];
 #pragma unroll
-            for (int t = 0; t < kRTr; ++t) {
+            for (int t = 0; t < kRTW; ++t) {
                 const uint32_t d = w == 0 ? a[t].x : w == 1 ? a[t].y : w == 2 ? a[t].z : a[t].w;
-                uint32_t C[8], M[8];
-                decode16(d, C, M);
+                uint32_t G[4], M[4];
+                g_pairs_half(d, h, G);
+                m_pairs_scaled_half(d, h, M);
+                const bf16x8 ca = pack4(G[0], G[1], G[2], G[3]);
+                const bf16x8 ma = pack4(M[0], M[1], M[2], M[3]);
+                if (kPack) {
+                    acc[t][0] = mfma_bf16(ca, bo[0], acc[t][0]);
+                    acc[t][0] = mfma_bf16(ma, bo[1], acc[t][0]);
+                } else {
 #pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const bf16x8 ca = pack4(C[4 * h], C[4 * h + 1], C[4 * h + 2], C[4 * h + 3]);
-                    const bf16x8 ma = pack4(M[4 * h], M[4 * h + 1], M[4 * h + 2], M[4 * h + 3]);
-                    accC[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ca, x0[h], accC[t], 0, 0, 0);
-                    if (!kPack)
-                        accC[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ca, x1[h], accC[t], 0, 0, 0);
-                    accM[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ma, x0[h], accM[t], 0, 0, 0);
-                    if (!kPack)
-                        accM[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ma, x1[h], accM[t], 0, 0, 0);
+                    for (int c = 0; c < kT; ++c) {
+                        acc[t][c] = mfma_bf16(ca, bo[4 * c + 0], acc[t][c]);
+                        acc[t][c] = mfma_bf16(ca, bo[4 * c + 1], acc[t][c]);
+                        acc[t][c] = mfma_bf16(ma, bo[4 * c + 2], acc[t][c]);
+                        acc[t][c] = mfma_bf16(ma, bo[4 * c + 3], acc[t][c]);
+                    }
                 }
             }
         }
         __syncthreads();
+#pragma unroll
+        for (int t = 0; t < kRTW; ++t) a[t] = an[t];
         if (++chunk == kFlush) {
             chunk = 0;
 #pragma unroll
-            for (int t = 0; t < kRTr; ++t) {
+            for (int t = 0; t < kRTW; ++t)
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    dC[t][e] += (double)accC[t][e];
-                    dM[t][e] += (double)accM[t][e];
+                for (int c = 0; c < kTiles; ++c) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) accd[t][c][e] += (double)acc[t][c][e];
+                    acc[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
                 }
-                accC[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-                accM[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+    }
+    double* out = partial + (int64_t)split * nI * kCS;
+#pragma unroll
+    for (int t = 0; t < kRTW; ++t)
+#pragma unroll
+        for (int c = 0; c < kTiles; ++c)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t row = row_base + 16 * t + 4 * g + e;
+                double v = accd[t][c][e] + (double)acc[t][c][e];
+                if (kPack) {
+                    // lane r < 8 holds the hi column r, lane r + 8 its lo column
+                    v += __shfl_down(v, 8, 16);
+                    if (r < 8) out[row * kCS + r] = v;
+                } else {
+                    out[row * kCS + 16 * c + r] = v;
+                }
             }
-        }
-    }
-    double* out = partial + (int64_t)blockIdx.y * 2 * pS * 16;
-#pragma unroll
-    for (int t = 0; t < kRTr; ++t) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int64_t row = row_base + 16 * t + 4 * g + e;
-            out[row * 16 + r] = dC[t][e] + (double)accC[t][e];
-            out[(pS + row) * 16 + r] = dM[t][e] + (double)accM[t][e];
-        }
-    }
 }
 
-// Z[j + c*ldz] = s_j ( SG - mu_j T_c + mu_j SM )
-template <bool kPack>
+// Y[i + c ldy] = 2^(kProdShift + ex_c) sum_split partial - K2_c for i < n, c < nb.
 __global__ void __launch_bounds__(256)
-rmatmat_reduce_kernel(const double* __restrict__ partial, int nsplit, int64_t pS, int64_t p,
-                      int nb, const double* __restrict__ cpart, const double* __restrict__ mean,
-                      const double* __restrict__ inv_sd, double* __restrict__ Z, int64_t ldz)
+matmat_bf16_reduce_kernel(const double* __restrict__ partial, int nsplit, int64_t nI, int64_t n,
+                          int nb, int kcs, const double* __restrict__ cpart,
+                          const double* __restrict__ cmax, double* __restrict__ Y, int64_t ldy)
 {
-    __shared__ double T[16];
-    column_sums(cpart, nb, T);
+    __shared__ double K2[32];
+    __shared__ int ex[32];
+    column_sums(cpart, nb, K2);
+    column_scales(cmax, nb, ex);
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= p * 16) return;
-    const int64_t j = t >> 4;
-    const int c = (int)(t & 15);
+    if (t >= n * kcs) return;
+    const int64_t i = t / kcs;
+    const int c = (int)(t - i * kcs);
     if (c >= nb) return;
-    const double sc = strided_sum<kPack>(partial + j * 16 + c, 2 * pS * 16, nsplit, 8);
-    const double sm = strided_sum<kPack>(partial + (pS + j) * 16 + c, 2 * pS * 16, nsplit, 8);
+    const double s = strided_sum(partial + i * kcs + c, nI * kcs, nsplit);
+    Y[(int64_t)c * ldy + i] = ldexp(s, kProdShift + ex[c]) - K2[c];
+}
+
+// ---------------------------------------------------------------------------
+// Split BF16: A^T X.  Workgroup = 4 waves x kRTX SNP tiles x 16 SNPs; K =
+// individuals.  The g and missing operands share the vector fragments, so each
+// row tile keeps two accumulators (g sum SC, missing sum SM).
+// With one K split (kFused) the kernel writes Z itself:
+//   Z[j + c ldz] = s_j (2^(kProdShift + ex_c) (SC + (mu_j - 4) SM) - mu_j T_c);
+// otherwise partial[split][2][row][kCS] for the reduce kernel.
+// ---------------------------------------------------------------------------
+template <bool kPack, int kT, bool kFused>
+__global__ void __launch_bounds__(256)
+rmatmat_bf16_kernel(const uint8_t* __restrict__ S, int64_t ldS, int64_t pS,
+                    const bf16x8* __restrict__ frag, int64_t nst, int64_t st_per_split,
+                    int nsplit, int nrb, int xcd, double* __restrict__ partial, int64_t p, int nb,
+                    const double* __restrict__ cpart, const double* __restrict__ cmax,
+                    const double* __restrict__ mean, const double* __restrict__ inv_sd,
+                    double* __restrict__ Z, int64_t ldz)
+{
+    constexpr int kOps = kPack ? 1 : 2 * kT;
+    constexpr int kTiles = kPack ? 1 : kT;
+    constexpr int kCS = kPack ? 8 : 16 * kT;
+    __shared__ bf16x8 bs[kKSteps * kOps * 64];
+    __shared__ double Tc[32];
+    __shared__ int ex[32];
+    if (kFused) {
+        column_sums(cpart, nb, Tc);
+        column_scales(cmax, nb, ex);
+    }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int g = lane >> 4, r = lane & 15;
+    int split, rb;
+    block_coords(blockIdx.x, nsplit, nrb, xcd, split, rb);
+    const int64_t row_base = (int64_t)rb * (kMxWaves * kRTX * 16) + wave * (kRTX * 16);
+    const int64_t st0 = (int64_t)split * st_per_split;
+    const int64_t st1 = st0 + st_per_split < nst ? st0 + st_per_split : nst;
+    f32x4 aC[kRTX][kTiles], aM[kRTX][kTiles];
+    double dC[kRTX][kTiles][4], dM[kRTX][kTiles][4];
+#pragma unroll
+    for (int t = 0; t < kRTX; ++t)
+#pragma unroll
+        for (int c = 0; c < kTiles; ++c) {
+            aC[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+            aM[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) dC[t][c][e] = dM[t][c][e] = 0.0;
+        }
+    uint4 a[kRTX];
+    if (st0 < st1) {
+#pragma unroll
+        for (int t = 0; t < kRTX; ++t)
+            a[t] = *reinterpret_cast<const uint4*>(
+                S + tiled_offset(row_base + 16 * t + r, st0 * 64 + 16 * g, ldS));
+    }
+    int chunk = 0;
+    for (int64_t st = st0; st < st1; ++st) {
+        const bf16x8* src = frag + st * (kKSteps * kOps * 64);
+        for (int q = threadIdx.x; q < kKSteps * kOps * 64; q += 256) bs[q] = src[q];
+        uint4 an[kRTX];
+        const int64_t stn = st + 1 < st1 ? st + 1 : st;
+#pragma unroll
+        for (int t = 0; t < kRTX; ++t)
+            an[t] = *reinterpret_cast<const uint4*>(
+                S + tiled_offset(row_base + 16 * t + r, stn * 64 + 16 * g, ldS));
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < kKSteps; ++ks) {
+            const int w = ks >> 1, h = ks & 1;
+            bf16x8 bo[kOps];
+#pragma unroll
+            for (int op = 0; op < kOps; ++op) bo[op] = bs[(ks * kOps + op) * 64 + lane];
+#pragma unroll
+            for (int t = 0; t < kRTX; ++t) {
+                const uint32_t d = w == 0 ? a[t].x : w == 1 ? a[t].y : w == 2 ? a[t].z : a[t].w;
+                uint32_t G[4], M[4];
+                g_pairs_half(d, h, G);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) M[k] = G[k] & (G[k] >> 1);
+                const bf16x8 ca = pack4(G[0], G[1], G[2], G[3]);
+                const bf16x8 ma = pack4(M[0], M[1], M[2], M[3]);
+#pragma unroll
+                for (int c = 0; c < kTiles; ++c) {
+#pragma unroll
+                    for (int q = 0; q < (kPack ? 1 : 2); ++q) {
+                        const bf16x8 b = bo[kPack ? 0 : 2 * c + q];
+                        aC[t][c] = mfma_bf16(ca, b, aC[t][c]);
+                        aM[t][c] = mfma_bf16(ma, b, aM[t][c]);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < kRTX; ++t) a[t] = an[t];
+        if (++chunk == kFlush) {
+            chunk = 0;
+#pragma unroll
+            for (int t = 0; t < kRTX; ++t)
+#pragma unroll
+                for (int c = 0; c < kTiles; ++c) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        dC[t][c][e] += (double)aC[t][c][e];
+                        dM[t][c][e] += (double)aM[t][c][e];
+                    }
+                    aC[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+                    aM[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+                }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < kRTX; ++t)
+#pragma unroll
+        for (int c = 0; c < kTiles; ++c)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t row = row_base + 16 * t + 4 * g + e;
+                double vc = dC[t][c][e] + (double)aC[t][c][e];
+                double vm = dM[t][c][e] + (double)aM[t][c][e];
+                if (kPack) {
+                    vc += __shfl_down(vc, 8, 16);
+                    vm += __shfl_down(vm, 8, 16);
+                }
+                const int col = kPack ? r : 16 * c + r;
+                if (kPack && r >= 8) continue;
+                if (kFused) {
+                    if (row < p && col < nb) {
+                        const double mu = mean[row];
+                        const double u = ldexp(vc + (mu - 4.0) * vm, kProdShift + ex[col]);
+                        Z[(int64_t)col * ldz + row] = inv_sd[row] * (u - mu * Tc[col]);
+                    }
+                } else {
+                    double* out = partial + (int64_t)split * 2 * pS * kCS;
+                    out[row * kCS + col] = vc;
+                    out[(pS + row) * kCS + col] = vm;
+                }
+            }
+}
+
+// Z[j + c ldz] = s_j (2^(kProdShift + ex_c) (SC + (mu_j - 4) SM) - mu_j T_c)
+__global__ void __launch_bounds__(256)
+rmatmat_bf16_reduce_kernel(const double* __restrict__ partial, int nsplit, int64_t pS, int64_t p,
+                           int nb, int kcs, const double* __restrict__ cpart,
+                           const double* __restrict__ cmax, const double* __restrict__ mean,
+                           const double* __restrict__ inv_sd, double* __restrict__ Z, int64_t ldz)
+{
+    __shared__ double T[32];
+    __shared__ int ex[32];
+    column_sums(cpart, nb, T);
+    column_scales(cmax, nb, ex);
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= p * kcs) return;
+    const int64_t j = t / kcs;
+    const int c = (int)(t - j * kcs);
+    if (c >= nb) return;
+    const double sc = strided_sum(partial + j * kcs + c, 2 * pS * kcs, nsplit);
+    const double sm = strided_sum(partial + (pS + j) * kcs + c, 2 * pS * kcs, nsplit);
     const double mu = mean[j];
-    Z[(int64_t)c * ldz + j] = inv_sd[j] * (sc - mu * T[c] + mu * sm);
+    Z[(int64_t)c * ldz + j] = inv_sd[j] * (ldexp(sc + (mu - 4.0) * sm, kProdShift + ex[c]) - mu * T[c]);
 }
 
 // ---------------------------------------------------------------------------
@@ -915,6 +1071,26 @@ rmatmat_i8_reduce_kernel(const double* __restrict__ partial, int nsplit, int64_t
 // ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
+// K splits of a split-BF16 product over `rows` padded rows in workgroups of
+// `wg_rows` rows and nst super-tiles of K: enough workgroups to cover the chip
+// several times, at most max_split splits (bounds the partial-sum traffic), a
+// multiple of 8 from 8 on so that each split's row blocks share one XCD.
+static BfSplit bf16_split(int64_t rows, int wg_rows, int64_t nst, int64_t max_split)
+{
+    constexpr int64_t kTargetWorkgroups = 2048;
+    BfSplit g;
+    g.nrb = (int)(rows / wg_rows);
+    int64_t want = (kTargetWorkgroups + g.nrb - 1) / g.nrb;
+    if (want > max_split) want = max_split;
+    if (want > nst) want = nst;
+    if (want < 1) want = 1;
+    if (want >= 8) want = want / 8 * 8;
+    g.st_per = (nst + want - 1) / want;
+    g.nsplit = (int)((nst + g.st_per - 1) / g.st_per);
+    g.xcd = g.nsplit >= 8 && g.nsplit % 8 == 0 ? 1 : 0;
+    return g;
+}
+
 MixedShape mixed_shape(int64_t n, int64_t p)
 {
     MixedShape m;
@@ -941,15 +1117,22 @@ MixedShape mixed_shape(int64_t n, int64_t p)
     if (sX < 1) sX = 1;
     m.stX = (m.nstX + sX - 1) / sX;
     m.splitX = (int)((m.nstX + m.stX - 1) / m.stX);
+    // split BF16, per column class (b <= 8: 8 partial columns, <= 16: 16, <= 32: 32)
+    const int64_t mbytes = m.nI * m.ldI;
+    for (int c = 0; c < 3; ++c) {
+        const int64_t kcs = c == 0 ? 8 : 16 * c;
+        m.bfW[c] = bf16_split(m.nI, kMxWaves * kRTW * 16, m.nstW, mbytes / (4 * 2 * 8 * m.nI * kcs));
+        m.bfX[c] = bf16_split(m.pS, kMxWaves * kRTX * 16, m.nstX, mbytes / (4 * 2 * 8 * 2 * m.pS * kcs));
+    }
     return m;
 }
 
 size_t mixed_frag_bytes(const MixedShape& m)
 {
-    // the larger of the two formats: split BF16 (4 operands per K step of 32) and
-    // int8 limbs (6 operands per K step of 64)
-    const size_t a = (size_t)m.nstW * kKSteps * 4 * 64 * sizeof(bf16x8);
-    const size_t b = (size_t)m.nstX * kKSteps * 2 * 64 * sizeof(bf16x8);
+    // the larger of the two formats: split BF16 (up to 8 operands per K step of 32
+    // for A W, 4 for A^T X) and int8 limbs (6 operands per K step of 64)
+    const size_t a = (size_t)m.nstW * kKSteps * 8 * 64 * sizeof(bf16x8);
+    const size_t b = (size_t)m.nstX * kKSteps * 4 * 64 * sizeof(bf16x8);
     const size_t c = (size_t)m.nstW * kWords * 2 * tiles<false>() * 64 * sizeof(i32x4);
     const size_t d = (size_t)m.nstX * kWords * tiles<false>() * 64 * sizeof(i32x4);
     return std::max(std::max(a, b), std::max(c, d));
@@ -957,89 +1140,90 @@ size_t mixed_frag_bytes(const MixedShape& m)
 
 size_t mixed_partial_elems(const MixedShape& m)
 {
-    const size_t a = (size_t)m.splitW * (size_t)m.nI * 16;
-    const size_t b = (size_t)m.splitX * 2 * (size_t)m.pS * 16;
-    return a > b ? a : b;
+    size_t e = std::max((size_t)m.splitW * (size_t)m.nI * 16, (size_t)m.splitX * 2 * (size_t)m.pS * 16);
+    for (int c = 0; c < 3; ++c) {
+        const size_t kcs = c == 0 ? 8 : 16 * c;
+        e = std::max(e, (size_t)m.bfW[c].nsplit * (size_t)m.nI * kcs);
+        if (m.bfX[c].nsplit > 1) e = std::max(e, (size_t)m.bfX[c].nsplit * 2 * (size_t)m.pS * kcs);
+    }
+    return e;
+}
+
+template <bool kPack, int kT>
+static void matmat_bf16_run(const MixedShape& m, const uint8_t* I, const ColStats& st,
+                            const double* W, int64_t ldw, int b, double* Y, int64_t ldy,
+                            MixedWork& w, hipStream_t s, const hipEvent_t* ev)
+{
+    constexpr int kcs = kPack ? 8 : 16 * kT;
+    const BfSplit& gm = m.bfW[kPack ? 0 : kT];
+    bf16x8* frag = reinterpret_cast<bf16x8*>(w.frag);
+    hipLaunchKernelGGL(colsum_kernel, dim3(kCsSplit, b), dim3(256), 0, s, W, ldw, m.p, st.mean,
+                       st.inv_sd, 4.0, w.cpart, w.cmax);
+    GKL_LAUNCH_CHECK("colsum_kernel");
+    hipLaunchKernelGGL((split_W_bf16_kernel<kPack, kT>), dim3(ceil_div(m.nstW * kKSteps * 64, 256)),
+                       dim3(256), 0, s, W, ldw, b, m.p, st.mean, st.inv_sd, w.cmax, m.nstW, frag);
+    GKL_LAUNCH_CHECK("split_W_bf16_kernel");
+    if (ev) GKL_HIP(hipEventRecord(ev[0], s));
+    hipLaunchKernelGGL((matmat_bf16_kernel<kPack, kT>), dim3((unsigned int)(gm.nsplit * gm.nrb)),
+                       dim3(256), 0, s, I, m.ldI, m.nI, frag, m.nstW, gm.st_per, gm.nsplit, gm.nrb,
+                       gm.xcd, w.partial);
+    GKL_LAUNCH_CHECK("matmat_bf16_kernel");
+    if (ev) GKL_HIP(hipEventRecord(ev[1], s));
+    hipLaunchKernelGGL(matmat_bf16_reduce_kernel, dim3(ceil_div(m.n * kcs, 256)), dim3(256), 0, s,
+                       w.partial, gm.nsplit, m.nI, m.n, b, kcs, w.cpart, w.cmax, Y, ldy);
+    GKL_LAUNCH_CHECK("matmat_bf16_reduce_kernel");
 }
 
 static void matmat_bf16(const MixedShape& m, const uint8_t* I, const ColStats& st, const double* W,
-                        int64_t ldw, int b, double* Y, int64_t ldy, MixedWork& w, hipStream_t s, const hipEvent_t* ev)
+                        int64_t ldw, int b, double* Y, int64_t ldy, MixedWork& w, hipStream_t s,
+                        const hipEvent_t* ev)
 {
-    const bool pack = b <= 8;
-    for (int col0 = 0; col0 < b; col0 += 16) {
-        const int nb = b - col0 < 16 ? b - col0 : 16;
-        const int64_t nthr = m.nstW * kKSteps * 64;
-        const dim3 gsplit(ceil_div(nthr, 256));
-        if (pack)
-            hipLaunchKernelGGL(split_W_kernel<true>, gsplit, dim3(256), 0, s, W, ldw, b, col0, m.p,
-                               st.mean, st.inv_sd, m.nstW, reinterpret_cast<bf16x8*>(w.frag));
-        else
-            hipLaunchKernelGGL(split_W_kernel<false>, gsplit, dim3(256), 0, s, W, ldw, b, col0, m.p,
-                               st.mean, st.inv_sd, m.nstW, reinterpret_cast<bf16x8*>(w.frag));
-        GKL_LAUNCH_CHECK("split_W_kernel");
-        hipLaunchKernelGGL(colsum_kernel, dim3(kCsSplit, nb), dim3(256), 0, s,
-                           W + (int64_t)col0 * ldw, ldw, m.p, st.mean, st.inv_sd, w.cpart, w.cmax);
-        GKL_LAUNCH_CHECK("colsum_kernel");
-        dim3 grid((unsigned int)(m.nI / (kMxWaves * kRTw * 16)), (unsigned int)m.splitW);
-        if (ev && col0 == 0) GKL_HIP(hipEventRecord(ev[0], s));
-        if (pack)
-            hipLaunchKernelGGL(matmat_bf16_kernel<true>, grid, dim3(256), 0, s, I, m.ldI, m.nI,
-                               reinterpret_cast<const bf16x8*>(w.frag), m.nstW, m.stW, w.partial);
-        else
-            hipLaunchKernelGGL(matmat_bf16_kernel<false>, grid, dim3(256), 0, s, I, m.ldI, m.nI,
-                               reinterpret_cast<const bf16x8*>(w.frag), m.nstW, m.stW, w.partial);
-        GKL_LAUNCH_CHECK("matmat_bf16_kernel");
-        if (ev && col0 + 16 >= b) GKL_HIP(hipEventRecord(ev[1], s));
-        const dim3 gred(ceil_div(m.n * 16, 256));
-        if (pack)
-            hipLaunchKernelGGL(matmat_reduce_kernel<true>, gred, dim3(256), 0, s, w.partial,
-                               m.splitW, m.nI, m.n, nb, w.cpart, Y + (int64_t)col0 * ldy, ldy);
-        else
-            hipLaunchKernelGGL(matmat_reduce_kernel<false>, gred, dim3(256), 0, s, w.partial,
-                               m.splitW, m.nI, m.n, nb, w.cpart, Y + (int64_t)col0 * ldy, ldy);
-        GKL_LAUNCH_CHECK("matmat_reduce_kernel");
+    if (b <= 8) matmat_bf16_run<true, 1>(m, I, st, W, ldw, b, Y, ldy, w, s, ev);
+    else if (b <= 16) matmat_bf16_run<false, 1>(m, I, st, W, ldw, b, Y, ldy, w, s, ev);
+    else matmat_bf16_run<false, 2>(m, I, st, W, ldw, b, Y, ldy, w, s, ev);
+}
+
+template <bool kPack, int kT>
+static void rmatmat_bf16_run(const MixedShape& m, const uint8_t* S, const ColStats& st,
+                             const double* X, int64_t ldx, int b, double* Z, int64_t ldz,
+                             MixedWork& w, hipStream_t s, const hipEvent_t* ev)
+{
+    constexpr int kcs = kPack ? 8 : 16 * kT;
+    const BfSplit& gm = m.bfX[kPack ? 0 : kT];
+    bf16x8* frag = reinterpret_cast<bf16x8*>(w.frag);
+    hipLaunchKernelGGL(colsum_kernel, dim3(kCsSplit, b), dim3(256), 0, s, X, ldx, m.n, nullptr,
+                       nullptr, 0.0, w.cpart, w.cmax);
+    GKL_LAUNCH_CHECK("colsum_kernel");
+    hipLaunchKernelGGL((split_X_bf16_kernel<kPack, kT>), dim3(ceil_div(m.nstX * kKSteps * 64, 256)),
+                       dim3(256), 0, s, X, ldx, b, m.n, w.cmax, m.nstX, frag);
+    GKL_LAUNCH_CHECK("split_X_bf16_kernel");
+    if (ev) GKL_HIP(hipEventRecord(ev[0], s));
+    const dim3 grid((unsigned int)(gm.nsplit * gm.nrb));
+    if (gm.nsplit == 1)
+        hipLaunchKernelGGL((rmatmat_bf16_kernel<kPack, kT, true>), grid, dim3(256), 0, s, S, m.ldS,
+                           m.pS, frag, m.nstX, gm.st_per, gm.nsplit, gm.nrb, gm.xcd, w.partial, m.p,
+                           b, w.cpart, w.cmax, st.mean, st.inv_sd, Z, ldz);
+    else
+        hipLaunchKernelGGL((rmatmat_bf16_kernel<kPack, kT, false>), grid, dim3(256), 0, s, S, m.ldS,
+                           m.pS, frag, m.nstX, gm.st_per, gm.nsplit, gm.nrb, gm.xcd, w.partial, m.p,
+                           b, w.cpart, w.cmax, st.mean, st.inv_sd, Z, ldz);
+    GKL_LAUNCH_CHECK("rmatmat_bf16_kernel");
+    if (ev) GKL_HIP(hipEventRecord(ev[1], s));
+    if (gm.nsplit > 1) {
+        hipLaunchKernelGGL(rmatmat_bf16_reduce_kernel, dim3(ceil_div(m.p * kcs, 256)), dim3(256), 0, s,
+                           w.partial, gm.nsplit, m.pS, m.p, b, kcs, w.cpart, w.cmax, st.mean,
+                           st.inv_sd, Z, ldz);
+        GKL_LAUNCH_CHECK("rmatmat_bf16_reduce_kernel");
     }
 }
 
 static void rmatmat_bf16(const MixedShape& m, const uint8_t* S, const ColStats& st, const double* X,
-                         int64_t ldx, int b, double* Z, int64_t ldz, MixedWork& w, hipStream_t s, const hipEvent_t* ev)
+                         int64_t ldx, int b, double* Z, int64_t ldz, MixedWork& w, hipStream_t s,
+                         const hipEvent_t* ev)
 {
-    const bool pack = b <= 8;
-    for (int col0 = 0; col0 < b; col0 += 16) {
-        const int nb = b - col0 < 16 ? b - col0 : 16;
-        const int64_t nthr = m.nstX * kKSteps * 64;
-        const dim3 gsplit(ceil_div(nthr, 256));
-        if (pack)
-            hipLaunchKernelGGL(split_X_kernel<true>, gsplit, dim3(256), 0, s, X, ldx, b, col0, m.n,
-                               m.nstX, reinterpret_cast<bf16x8*>(w.frag));
-        else
-            hipLaunchKernelGGL(split_X_kernel<false>, gsplit, dim3(256), 0, s, X, ldx, b, col0, m.n,
-                               m.nstX, reinterpret_cast<bf16x8*>(w.frag));
-        GKL_LAUNCH_CHECK("split_X_kernel");
-        hipLaunchKernelGGL(colsum_kernel, dim3(kCsSplit, nb), dim3(256), 0, s,
-                           X + (int64_t)col0 * ldx, ldx, m.n, nullptr, nullptr, w.cpart, w.cmax);
-        GKL_LAUNCH_CHECK("colsum_kernel");
-        dim3 grid((unsigned int)(m.pS / (kMxWaves * kRTr * 16)), (unsigned int)m.splitX);
-        if (ev && col0 == 0) GKL_HIP(hipEventRecord(ev[0], s));
-        if (pack)
-            hipLaunchKernelGGL(rmatmat_bf16_kernel<true>, grid, dim3(256), 0, s, S, m.ldS, m.pS,
-                               reinterpret_cast<const bf16x8*>(w.frag), m.nstX, m.stX, w.partial);
-        else
-            hipLaunchKernelGGL(rmatmat_bf16_kernel<false>, grid, dim3(256), 0, s, S, m.ldS, m.pS,
-                               reinterpret_cast<const bf16x8*>(w.frag), m.nstX, m.stX, w.partial);
-        GKL_LAUNCH_CHECK("rmatmat_bf16_kernel");
-        if (ev && col0 + 16 >= b) GKL_HIP(hipEventRecord(ev[1], s));
-        const dim3 gred(ceil_div(m.p * 16, 256));
-        if (pack)
-            hipLaunchKernelGGL(rmatmat_reduce_kernel<true>, gred, dim3(256), 0, s, w.partial,
-                               m.splitX, m.pS, m.p, nb, w.cpart, st.mean, st.inv_sd,
-                               Z + (int64_t)col0 * ldz, ldz);
-        else
-            hipLaunchKernelGGL(rmatmat_reduce_kernel<false>, gred, dim3(256), 0, s, w.partial,
-                               m.splitX, m.pS, m.p, nb, w.cpart, st.mean, st.inv_sd,
-                               Z + (int64_t)col0 * ldz, ldz);
-        GKL_LAUNCH_CHECK("rmatmat_reduce_kernel");
-    }
+    if (b <= 8) rmatmat_bf16_run<true, 1>(m, S, st, X, ldx, b, Z, ldz, w, s, ev);
+    else if (b <= 16) rmatmat_bf16_run<false, 1>(m, S, st, X, ldx, b, Z, ldz, w, s, ev);
+    else rmatmat_bf16_run<false, 2>(m, S, st, X, ldx, b, Z, ldz, w, s, ev);
 }
 
 static void matmat_i8(const MixedShape& m, const uint8_t* I, const ColStats& st, const double* W,
@@ -1049,7 +1233,7 @@ static void matmat_i8(const MixedShape& m, const uint8_t* I, const ColStats& st,
         const int nb = b - col0 < 16 ? b - col0 : 16;
         const double* Wc = W + (int64_t)col0 * ldw;
         hipLaunchKernelGGL(colsum_kernel, dim3(kCsSplit, nb), dim3(256), 0, s, Wc, ldw, m.p,
-                           st.mean, st.inv_sd, w.cpart, w.cmax);
+                           st.mean, st.inv_sd, 3.0, w.cpart, w.cmax);
         GKL_LAUNCH_CHECK("colsum_kernel");
         const int64_t nthr = m.nstW * kWords * 64;
         const dim3 gsplit(ceil_div(nthr, 256));
@@ -1087,7 +1271,7 @@ static void rmatmat_i8(const MixedShape& m, const uint8_t* S, const ColStats& st
         const int nb = b - col0 < 16 ? b - col0 : 16;
         const double* Xc = X + (int64_t)col0 * ldx;
         hipLaunchKernelGGL(colsum_kernel, dim3(kCsSplit, nb), dim3(256), 0, s, Xc, ldx, m.n, nullptr,
-                           nullptr, w.cpart, w.cmax);
+                           nullptr, 0.0, w.cpart, w.cmax);
         GKL_LAUNCH_CHECK("colsum_kernel");
         const int64_t nthr = m.nstX * kWords * 64;
         const dim3 gsplit(ceil_div(nthr, 256));

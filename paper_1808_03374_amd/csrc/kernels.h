@@ -51,8 +51,6 @@ size_t layout_T_bytes(const Packed& L);
 size_t layout_P_bytes(const Packed& L);
 void build_layouts(const uint8_t* G, int64_t ld, const Packed& L, hipStream_t s);
 
-// Unpack from the internal layout to n x p column-major int8, -1 = missing.
-void launch_unpack_layout(const Packed& L, int8_t* out, hipStream_t s);
 
 // ---- k_matvec.hip: FP64 products with the implicit standardised matrix ----
 // y = A v - (beta ? *beta : 0) * uprev      (y, uprev: n; v: p)
@@ -134,6 +132,19 @@ void launch_batch_proj(const BatchDesc* d, const int* state, int count, int side
 void launch_bstep(int* state, hipStream_t s);
 // v_0 of every problem scaled to unit norm (start of a solve).
 void launch_bstart(const BatchDesc* d, int count, int64_t max_p, int hstride, hipStream_t s);
+// Leave-one-block-out batches: problem q's right vectors are zero on its own
+// SNP block [lohi[2q], lohi[2q+1]) (device array); all problems share one matrix.
+// out(:, q) = v_j (side 0, len p) or u_j (side 1, len n); zero when inactive.
+void launch_loco_gather(const BatchDesc* d, const int* state, int count, int side, double* out,
+                        int64_t len, hipStream_t s);
+// u_j = Y(:, q) - beta_{j-1} u_{j-1} (or - U(:, 0:nlock) rho after a restart).
+void launch_loco_left(const BatchDesc* d, const int* state, int count, const double* Y, int64_t n,
+                      hipStream_t s);
+// v_{j+1} = Z(:, q) without the rows of block q, - alpha_j v_j.
+void launch_loco_right(const BatchDesc* d, const int* state, int count, const double* Z, int64_t p,
+                       const int64_t* lohi, hipStream_t s);
+// v_0 of every problem zeroed on its own block.
+void launch_loco_mask(const BatchDesc* d, int count, const int64_t* lohi, hipStream_t s);
 
 // ---- k_ortho.hip: Gram-Schmidt, norms, small dense ops on the Krylov bases ----
 struct OrthoWork {
@@ -170,6 +181,11 @@ void launch_normalize_after_cgs2(double* r, int64_t len, double* nrm_out, double
 void launch_normalize(double* r, int64_t len, double* out, double* nrm_out, double* norm_est,
                       double root_maxdim, int* flag, OrthoWork& w, hipStream_t s,
                       int* first_breakdown = nullptr, int step = 0);
+// One-sided reorthogonalisation: *flag = 1 when the largest |Q(:, 0:ncols)^T q|
+// exceeds omega * *qnorm (device scalar, ||q||); the flag is only ever set, never
+// cleared.
+void launch_overlap_check(const double* Q, int64_t len, int ncols, const double* q, double omega,
+                          const double* qnorm, int* flag, OrthoWork& w, hipStream_t s);
 // y -= Q(:, 0:ncols) * c  (c device, ncols)
 void launch_gemv_n_sub(const double* Q, int64_t ldq, int64_t len, int ncols, const double* c,
                        double* y, hipStream_t s);
@@ -281,6 +297,14 @@ void launch_restart_scalars(const double* S, const double* P, int m, const doubl
                             int keep, double* theta, double* rho, hipStream_t s);
 
 // ---- k_mixed.hip: MFMA block products (split BF16 or int8 limbs) ----
+// K-split geometry of a split-BF16 product: nsplit splits of st_per super-tiles,
+// nrb row blocks, xcd = 1 when the workgroups of one split share an XCD.
+struct BfSplit {
+    int nsplit = 1;
+    int64_t st_per = 1;
+    int nrb = 1;
+    int xcd = 0;
+};
 struct MixedShape {
     int64_t n = 0, p = 0;
     int64_t nI = 0, ldI = 0;      // layout I: rows (individuals, padded) and bytes per row
@@ -289,12 +313,13 @@ struct MixedShape {
     int64_t stW = 0, stX = 0;     // super-tiles per K split
     int splitW = 1, splitX = 1;
     bool int8 = false;            // operand format: int8 limbs (true) or split BF16
+    BfSplit bfW[3], bfX[3];       // split BF16 by column class: b <= 8, <= 16, <= 32
 };
 struct MixedWork {
     void* frag = nullptr;         // int8 limb fragments of the vector block
     double* partial = nullptr;
-    double* cpart = nullptr;      // 16 x 64 column-sum partials
-    double* cmax = nullptr;       // 16 x 64 column-maximum partials
+    double* cpart = nullptr;      // 32 x 64 column-sum partials
+    double* cmax = nullptr;       // 32 x 64 column-maximum partials
 };
 MixedShape mixed_shape(int64_t n, int64_t p);
 size_t mixed_frag_bytes(const MixedShape& m);

@@ -88,8 +88,8 @@ void gkl_ctx::setup_mixed()
     build_mixed_layouts(prob.G_user, n, p, prob.ld, M.I, M.S, s);
     M.w.frag = A.alloc(mixed_frag_bytes(M.shape));
     M.w.partial = static_cast<double*>(A.alloc(sizeof(double) * mixed_partial_elems(M.shape)));
-    M.w.cpart = static_cast<double*>(A.alloc(sizeof(double) * 16 * 64));
-    M.w.cmax = static_cast<double*>(A.alloc(sizeof(double) * 16 * 64));
+    M.w.cpart = static_cast<double*>(A.alloc(sizeof(double) * 32 * 64));
+    M.w.cmax = static_cast<double*>(A.alloc(sizeof(double) * 32 * 64));
     const int b = M.b;
     M.U = static_cast<double*>(A.alloc(sizeof(double) * (size_t)n * m));
     M.V = static_cast<double*>(A.alloc(sizeof(double) * (size_t)p * (m + b)));
@@ -165,7 +165,7 @@ gkl_status gkl_ctx::solve_mixed(double* sigma, double* Uo, int64_t ldu, double* 
                             ev >= 0 ? &ev_pool[ev + 2] : nullptr);
         timing_end(ev, false, true);
         info.matvecs += b;
-        info.passes_over_G += (b + 15) / 16;
+        info.passes_over_G += M.shape.int8 ? (b + 15) / 16 : 1;
         if (o > 0) {
             if (o == nlock_m)
                 launch_gemm_nn_sub(M.U, n, Ub, n, n, nlock_m, b, M.Bm + (int64_t)o * M.ldb, M.ldb, s);
@@ -183,7 +183,7 @@ gkl_status gkl_ctx::solve_mixed(double* sigma, double* Uo, int64_t ldu, double* 
                              ev2 >= 0 ? &ev_pool[ev2 + 2] : nullptr);
         timing_end(ev2, true, true);
         info.matvecs += b;
-        info.passes_over_G += (b + 15) / 16;
+        info.passes_over_G += M.shape.int8 ? (b + 15) / 16 : 1;
         launch_put_block(M.RT, b, 0, 0, M.R, b, b, b, 1, s);
         launch_gemm_nn_sub(Vb, p, Vn, p, p, b, b, M.RT, b, s);
         block_cgs2(M, M.V, p, o + b, Vn, s);

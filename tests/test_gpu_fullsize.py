@@ -17,10 +17,13 @@ Tolerances
     certified FP64 solve, and certificate residuals within 1e-6 sigma_1.
   * Vectors (gap rule): each blocked-path vector whose relative gap delta_i
     satisfies eps * sigma_1 / (delta_i sigma_i) <= 1e-6 must lie within 1e-6
-    rad of the FP64 vector; eps is the larger of the solve tolerance and the
-    measured error of a block product (||dY|| / (sigma_1 ||w||) on random unit
-    vectors).  Every other vector with a gap must satisfy the same bound with a
-    factor of 10 (a Davis-Kahan-type bound sin(theta) <= ||E|| / gap).
+    rad of the FP64 vector.  eps bounds the triplet's residual against the
+    exact operator: the solve tolerance plus the measured error of the block
+    products, the larger of ||dY|| / (sigma_1 ||w||) for A W and
+    ||dZ|| / (sigma_1 ||x||) for A^T X on random unit vectors (Wedin's bound
+    sin(theta) <= max(||A v - s u||, ||A^T u - s v||) / gap takes both sides).
+    Every other vector with a gap must satisfy the same bound with a factor
+    of 10.
 """
 import numpy as np
 import pytest
@@ -107,14 +110,18 @@ def test_blocked_full_10k_x_100k_against_certified_fp64(gk, c2, b):
     ctx = gk.Context(Gd, g.n, g.p, k, tol=tol, precision=gk.GKL_PREC_MIXED, block_width=b, v0=v0)
     sigma, U, V, st, info = ctx.solve()
     assert st == gk.GKL_OK, gk.gkl_last_error(ctx.ctx)
-    # operator error of one block product on random unit vectors, relative to sigma_1
+    # error of both block products on random unit vectors, relative to sigma_1
     rng = np.random.default_rng(17)
     W = rng.standard_normal((g.p, 4))
     W /= np.linalg.norm(W, axis=0)
+    X = rng.standard_normal((g.n, 4))
+    X /= np.linalg.norm(X, axis=0)
     Ym = ctx.matmat_mixed(dev(W)).cpu().numpy()
+    Zm = ctx.rmatmat_mixed(dev(X)).cpu().numpy()
     ctx.close()
     Y0 = np.stack([op.matvec(W[:, c]) for c in range(4)], axis=1)
-    eps_op = np.linalg.norm(Ym - Y0, axis=0).max() / s64[0]
+    Z0 = np.stack([op.rmatvec(X[:, c]) for c in range(4)], axis=1)
+    eps_op = max(np.linalg.norm(Ym - Y0, axis=0).max(), np.linalg.norm(Zm - Z0, axis=0).max()) / s64[0]
     sigma = sigma.cpu().numpy()
     U = U.cpu().numpy()
     V = V.cpu().numpy()
@@ -122,7 +129,7 @@ def test_blocked_full_10k_x_100k_against_certified_fp64(gk, c2, b):
     assert rel.max() <= 1e-6, rel
     res, _ = certify(op, sigma, U, V)
     assert res.max() <= 1e-6 * s64[0], res / s64[0]
-    eps = max(tol, eps_op)
+    eps = tol + eps_op
     gaps = rel_gaps(s64)
     bound = eps * s64[0] / (gaps * s64)
     au, av = vec_angles(U, U64), vec_angles(V, V64)
