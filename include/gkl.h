@@ -58,13 +58,24 @@ typedef enum gkl_status {
     GKL_ERR_INVALID = 1,      /* bad argument; nothing was changed */
     GKL_ERR_NOMEM = 2,        /* device allocation failed */
     GKL_ERR_DEVICE = 3,       /* a HIP call or kernel launch failed */
-    GKL_NOT_CONVERGED = 4,    /* max_matvecs reached; best Ritz triplets written */
+    GKL_NOT_CONVERGED = 4,    /* max_matvecs reached or the basis (max_steps) filled
+                                 without restart; best Ritz triplets written */
     GKL_ERR_BREAKDOWN = 5,    /* no new direction could be found */
     GKL_ERR_INTERNAL = 6,
     GKL_ERR_UNSUPPORTED = 7   /* option combination not built */
 } gkl_status;
 
-enum gkl_reorth { GKL_REORTH_FULL = 0, GKL_REORTH_PARTIAL = 1 };
+/* GKL_REORTH_FULL: CGS2 of every new vector against its whole basis.
+ * GKL_REORTH_PARTIAL: CGS2 only when the estimated loss of orthogonality (PRO
+ * recurrences) exceeds options.pro_omega.
+ * GKL_REORTH_ONESIDED: CGS2 on the shorter side only (U when n <= p, else V);
+ * each new long-side vector is only checked against its basis (one projection
+ * instead of CGS2's three passes) until an overlap exceeds min(pro_omega, tol)
+ * times its norm, from which step on both sides are reorthogonalised; the
+ * returned long-side vectors are recomputed from the short side
+ * (v_i = A^T u_i / ||A^T u_i|| when n <= p).
+ * Section 3, "Choice of reorthogonalization strategy"; FP64 path only. */
+enum gkl_reorth { GKL_REORTH_FULL = 0, GKL_REORTH_PARTIAL = 1, GKL_REORTH_ONESIDED = 2 };
 /* GKL_PREC_FP64: single-vector FP64 GKL.  GKL_PREC_MIXED: blocked GKL whose two
  * products run on the matrix cores with split-BF16 vector tiles (hi + lo, FP32
  * accumulation per K chunk, FP64 across chunks); every other quantity FP64.
@@ -87,7 +98,9 @@ typedef struct gkl_options {
                                  shrank the vector below 1/sqrt(2) of its norm */
     int32_t check_every;      /* steps between convergence tests; 0 = auto (when the
                                  basis is full if restarting, else every 5 steps) */
-    int32_t max_steps;        /* cap on the basis size without restart; 0 = min(n, p) */
+    int32_t max_steps;        /* cap on the basis size without restart; 0 = min(512,
+                                 min(n, p)).  A solve without restart that fills the
+                                 basis before converging returns GKL_NOT_CONVERGED. */
     double pro_omega;         /* PRO threshold on the orthogonality estimate; 0 = 1e-8 */
     int64_t max_matvecs;      /* stop with GKL_NOT_CONVERGED after this many; 0 = unlimited */
     uint64_t seed;            /* start vector seed when v0 is NULL */
@@ -139,7 +152,11 @@ const char* gkl_last_error(const gkl_ctx* ctx);
 /*
  * gkl_create / gkl_create_ex
  *   Validate the arguments, compute the column statistics (counts, mu, s) on the
- *   device and allocate the solver workspace for a top-k solve.
+ *   device and allocate the solver workspace for a top-k solve (the paper's
+ *   preprocessing, whose content it leaves open: Section 4, Table 2 gives its
+ *   time only; the standardisation above is this library's reading).  An FP64
+ *   context builds the two lookup-table layouts of its products, a blocked one
+ *   (GKL_PREC_MIXED*) the two layouts of its matrix-core products.
  *   G      device, p*ld bytes, SNP-major 2-bit codes (see above), borrowed.
  *   n, p   individuals and SNPs, both >= 1.
  *   k      singular triplets wanted, 1 <= k <= min(n, p).
@@ -158,7 +175,9 @@ gkl_status gkl_create_ex(const uint8_t* G, int64_t n, int64_t p, int32_t k, doub
 
 /*
  * gkl_solve
- *   Run the Lanczos iteration and write the top-k triplets.
+ *   Run the Lanczos iteration and write the top-k triplets (Section 3: GKL
+ *   bidiagonalisation, thick restart, CGS2 or partial reorthogonalisation, the
+ *   convergence test beta_j |P_{j,i}| <= tol sigma~_1; blocked: Section 5).
  *   sigma  device, k values, descending.
  *   U      device, n x k column-major with leading dimension ldu >= n (scores).
  *   V      device, p x k column-major with leading dimension ldv >= p (loadings).
@@ -175,7 +194,8 @@ gkl_status gkl_solve(gkl_ctx* ctx, double* sigma, double* U, int64_t ldu, double
 void gkl_destroy(gkl_ctx* ctx);
 
 /*
- * Batched solves of many uneven matrices (per-chromosome PCAs).
+ * Batched solves of many uneven matrices (per-chromosome PCAs), each problem
+ * by the FP64 GKL iteration of Section 3.
  *   count     number of problems (1..1024).
  *   G, n, p   host arrays of count device pointers / sizes; each problem as above.
  *   The context solves all problems together: every Lanczos half-step of all
@@ -197,30 +217,65 @@ gkl_status gkl_solve_batched(gkl_ctx* ctx, double* const* sigma, double* const* 
 gkl_status gkl_batched_plan(const gkl_ctx* ctx, int64_t* mv_target, int64_t* rmv_target,
                             int32_t* grid_mv, int32_t* grid_rmv, double* mv_ms, double* rmv_ms);
 
+/*
+ * gkl_create_loco -- leave-one-block-out PCAs (one per chromosome, say): for
+ * every contiguous SNP block q = [block_start[q], block_start[q+1]) of the
+ * n x p matrix G, the top-k triplets of G without that block, all solved
+ * together.  Problem q runs the GKL iteration of Section 3 (full CGS2, thick
+ * restart when krylov_dim > 0) with its right vectors in the whole p-space and
+ * zero on its own block; the products of all problems are then one block
+ * product with the whole matrix per half-step (nblocks columns, on the matrix
+ * cores: options.precision must be GKL_PREC_MIXED or GKL_PREC_MIXED_INT8),
+ * so the matrix is streamed once per step for all problems instead of
+ * nblocks - 1 times.  Column statistics are those of the whole matrix.
+ *   G           device, SNP-major 2-bit codes as for gkl_create, borrowed.
+ *   nblocks     2..32;  block_start  host array of nblocks + 1 increasing
+ *               offsets, block_start[0] = 0 and block_start[nblocks] = p.
+ *   k           1 <= k <= min(n, p - largest block).
+ * Solve with gkl_solve_batched (count = nblocks): V of problem q is p x k with
+ * zeros on block q's rows; options.v0 holds nblocks p-vectors back to back.
+ * Errors: GKL_ERR_INVALID (arguments), GKL_ERR_UNSUPPORTED (FP64 precision),
+ * GKL_ERR_NOMEM, GKL_ERR_DEVICE.
+ */
+gkl_status gkl_create_loco(const uint8_t* G, int64_t n, int64_t p, int32_t nblocks,
+                           const int64_t* block_start, int32_t k, double tol,
+                           const gkl_options* opt, gkl_ctx** out);
+
 /* ---------------- kernel-level entry points on an existing context ----------
  * Used by the parity tests and the bench; same conventions as above.  All
- * pointers are device pointers; every call is synchronous. */
+ * pointers are device pointers; every call is synchronous.  A batched context
+ * is rejected with GKL_ERR_INVALID by all of them. */
 
-/* Column statistics: count (int64, p), nobs (int64, p), mean (p), inv_sd (p).
- * Any pointer may be NULL to skip it. */
+/* Column statistics of the context's matrix (the preprocessing read above):
+ * count (int64, p: n1 + 2 n2), nobs (int64, p: n - n3), mean (p), inv_sd (p).
+ * Any context kind; any pointer may be NULL to skip it. */
 gkl_status gkl_column_stats(gkl_ctx* ctx, int64_t* count, int64_t* nobs, double* mean,
                             double* inv_sd);
-/* Unpack G to an n x p column-major int8 matrix; missing becomes -1. */
+/* Decode the caller's G (the storage format above; the paper's entries 0, 1, 2
+ * or missing, Section 1) to an n x p column-major int8 matrix, missing = -1.
+ * Any context kind (it reads G, which the context borrows). */
 gkl_status gkl_unpack(gkl_ctx* ctx, int8_t* out);
-/* y = A v (v: p values, y: n values), FP64. */
+/* y = A v (v: p values, y: n values) in FP64: the product every Lanczos step
+ * applies (Section 3).  Needs a GKL_PREC_FP64 context (its lookup-table
+ * layouts); a blocked context gives GKL_ERR_INVALID. */
 gkl_status gkl_matvec(gkl_ctx* ctx, const double* v, double* y);
-/* z = A^T u (u: n values, z: p values), FP64. */
+/* z = A^T u (u: n values, z: p values) in FP64; GKL_PREC_FP64 context only. */
 gkl_status gkl_rmatvec(gkl_ctx* ctx, const double* u, double* z);
-/* Y = A W for b columns (W: p x b, Y: n x b, column-major, leading dims p and n),
- * through the matrix-core path of the context's precision (GKL_PREC_MIXED: W
- * split into bf16 hi + lo, FP32 accumulate per K-chunk, FP64 across chunks;
- * GKL_PREC_MIXED_INT8: W in exact int8 limbs of a 22-bit per-column fixed point,
- * int32 accumulation), with FP64 centring and missing-value terms. */
+/* Y = A W for b columns, 1 <= b <= 32 (W: p x b, Y: n x b, column-major,
+ * leading dims p and n): the block product of the blocked variant (block
+ * Lanczos, Section 5), through the matrix-core path of the context's precision
+ * (GKL_PREC_MIXED: W split into bf16 hi + lo, FP32 accumulate per K-chunk, FP64
+ * across chunks; GKL_PREC_MIXED_INT8: W in exact int8 limbs of a 22-bit
+ * per-column fixed point, int32 accumulation), with FP64 centring and
+ * missing-value terms.  Needs a blocked context; an FP64 one gives
+ * GKL_ERR_INVALID. */
 gkl_status gkl_matmat_mixed(gkl_ctx* ctx, const double* W, int32_t b, double* Y);
-/* Z = A^T X for b columns (X: n x b, Z: p x b), the same matrix-core path. */
+/* Z = A^T X for b columns (X: n x b, Z: p x b), the same matrix-core path and
+ * the same requirements. */
 gkl_status gkl_rmatmat_mixed(gkl_ctx* ctx, const double* X, int32_t b, double* Z);
-/* Per-step trace of the last solve, as rows of GKL_TRACE_FIELDS doubles:
- *   step, alpha, beta, reorth_left, reorth_right, restart, max_residual_rel.
+/* Per-step trace of the last solve (options.trace = 1), as rows of
+ * GKL_TRACE_FIELDS doubles: step, alpha, beta (the bidiagonal's entries of
+ * Section 3), reorth_left, reorth_right, restart, max_residual_rel.
  * buf is HOST memory of cap doubles; *written receives the number of rows. */
 #define GKL_TRACE_FIELDS 7
 gkl_status gkl_get_trace(gkl_ctx* ctx, double* buf, int64_t cap, int64_t* written);

@@ -19,6 +19,7 @@ GKL_ERR_INTERNAL = 6
 GKL_ERR_UNSUPPORTED = 7
 GKL_REORTH_FULL = 0
 GKL_REORTH_PARTIAL = 1
+GKL_REORTH_ONESIDED = 2
 GKL_PREC_FP64 = 0
 GKL_PREC_MIXED = 1
 GKL_PREC_MIXED_INT8 = 2
@@ -115,6 +116,8 @@ _SIGS = {
     "gkl_create_batched": (_st, [_i32, _vp, _vp, _vp, _i32, _dbl, _i32,
                                  ctypes.POINTER(gkl_options), _ctx_pp]),
     "gkl_solve_batched": (_st, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "gkl_create_loco": (_st, [_vp, _i64, _i64, _i32, _vp, _i32, _dbl, ctypes.POINTER(gkl_options),
+                              _ctx_pp]),
     "gkl_batched_plan": (_st, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "gkl_column_stats": (_st, [_vp, _vp, _vp, _vp, _vp]),
     "gkl_unpack": (_st, [_vp, _vp]),
@@ -204,6 +207,14 @@ def gkl_create_batched(Gs, ns, ps, k, tol, reorth, opt):
     ctx = ctypes.c_void_p()
     _check(lib.gkl_create_batched(count, GA, NA, PA, k, tol, reorth, ctypes.byref(opt),
                                   ctypes.byref(ctx)))
+    return ctx.value
+
+
+def gkl_create_loco(G, n, p, block_start, k, tol, opt):
+    nb = len(block_start) - 1
+    BS = (ctypes.c_int64 * (nb + 1))(*[int(x) for x in block_start])
+    ctx = ctypes.c_void_p()
+    _check(lib.gkl_create_loco(_ptr(G), n, p, nb, BS, k, tol, ctypes.byref(opt), ctypes.byref(ctx)))
     return ctx.value
 
 
@@ -421,3 +432,33 @@ def solve(G, n, p, k, tol=1e-10, reorth=GKL_REORTH_FULL, **options):
         return ctx.solve()
     finally:
         ctx.close()
+
+
+class LocoContext(BatchedContext):
+    """Leave-one-block-out PCAs over one torch.uint8 CUDA tensor G (p, ld) with
+    SNP blocks [block_start[q], block_start[q+1]); solve() returns per-problem
+    lists like BatchedContext (V of problem q is p x k, zero on block q)."""
+
+    def __init__(self, G, n, p, block_start, k, tol=1e-8, **options):
+        import torch
+        self._torch = torch
+        self.Gs = [G]
+        nb = len(block_start) - 1
+        self.ns = [int(n)] * nb
+        self.ps = [int(p)] * nb
+        self.k = int(k)
+        opt = gkl_options_default()
+        self._v0 = None
+        for key, val in options.items():
+            if key == "v0":
+                if val is not None:
+                    self._v0 = val
+                    opt.v0 = val.data_ptr()
+            elif key == "stream":
+                opt.stream = val
+            else:
+                setattr(opt, key, val)
+        if not opt.ld_bytes:
+            opt.ld_bytes = G.shape[1] if G.dim() == 2 else 0
+        self.opt = opt
+        self.ctx = gkl_create_loco(G, int(n), int(p), list(block_start), self.k, tol, opt)

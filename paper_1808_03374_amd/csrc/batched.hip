@@ -84,6 +84,20 @@ struct BatchState {
     bool use_graph = true;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // Leave-one-block-out batch: every problem is the shared matrix without its
+    // own SNP block, and the products of all problems are block products with
+    // the whole matrix on the matrix cores (split BF16 or int8 limbs).
+    bool loco = false;
+    Problem shared;                    // the whole matrix: statistics only
+    MixedShape mshape;
+    uint8_t* mI = nullptr;
+    uint8_t* mS = nullptr;
+    MixedWork mw;
+    double* Wg = nullptr;              // p x count: v_j of every problem
+    double* Yg = nullptr;              // n x count: A v_j
+    double* Xg = nullptr;              // n x count: u_j
+    double* Zg = nullptr;              // p x count: A^T u_j
+    int64_t* d_lohi = nullptr;         // own block of each problem
     ~BatchState()
     {
         if (exec) (void)hipGraphExecDestroy(exec);
@@ -162,6 +176,18 @@ struct BatchState {
     // One Lanczos step of every active problem (the captured sequence).
     void record_step()
     {
+        if (loco) {
+            launch_loco_gather(d_desc, d_state, count, 0, Wg, max_p, stream);
+            launch_matmat_mixed(mshape, mI, shared.st, Wg, max_p, count, Yg, max_n, mw, stream);
+            launch_loco_left(d_desc, d_state, count, Yg, max_n, stream);
+            launch_bortho(d_desc, d_state, count, 0, max_n, hstride, stream);
+            launch_loco_gather(d_desc, d_state, count, 1, Xg, max_n, stream);
+            launch_rmatmat_mixed(mshape, mS, shared.st, Xg, max_n, count, Zg, max_p, mw, stream);
+            launch_loco_right(d_desc, d_state, count, Zg, max_p, d_lohi, stream);
+            launch_bortho(d_desc, d_state, count, 1, max_p, hstride, stream);
+            launch_bstep(d_state, stream);
+            return;
+        }
         launch_bmatvec(d_desc, d_tile_mv, count, d_state, grid_mv, stream);
         launch_bmatvec_reduce(d_desc, d_state, count, max_n, stream);
         launch_bortho(d_desc, d_state, count, 0, max_n, hstride, stream);
@@ -253,6 +279,83 @@ struct BatchState {
 void destroy_batch(BatchState* b) { delete b; }
 
 namespace {
+// Krylov bases, scalars and Ritz workspace of one problem (n x p, basis m).
+void alloc_problem(BatchState& B, BatchProblem& P, int64_t n, int64_t p, hipStream_t s)
+{
+    const int m = B.maxm;
+    DeviceArena& A = P.prob.arena;
+    P.U = static_cast<double*>(A.alloc(sizeof(double) * (size_t)n * m));
+    P.V = static_cast<double*>(A.alloc(sizeof(double) * (size_t)p * (m + 1)));
+    double* sc = static_cast<double*>(A.alloc(sizeof(double) * 4 * (size_t)(m + 2)));
+    P.alpha = sc;
+    P.beta = sc + (m + 2);
+    P.theta = sc + 2 * (m + 2);
+    P.rho = sc + 3 * (m + 2);
+    const size_t ch = bortho_chunks(std::max(n, p));
+    P.tnpart = static_cast<double*>(A.alloc(sizeof(double) * batch_tn_partial_elems(B.hstride)));
+    P.h = static_cast<double*>(A.alloc(sizeof(double) * B.hstride));
+    P.npart = static_cast<double*>(A.alloc(sizeof(double) * ch));
+    P.anorm = static_cast<double*>(A.alloc(sizeof(double)));
+    if (B.krylov > 0)
+        P.tmp = static_cast<double*>(A.alloc(sizeof(double) * (size_t)std::max(n, p) * B.keep));
+    const size_t mm = (size_t)m * m;
+    P.ritz.B = static_cast<double*>(A.alloc(sizeof(double) * mm));
+    P.ritz.P = static_cast<double*>(A.alloc(sizeof(double) * mm));
+    P.ritz.Q = static_cast<double*>(A.alloc(sizeof(double) * mm));
+    P.ritz.S = static_cast<double*>(A.alloc(sizeof(double) * m));
+    P.ritz.res = static_cast<double*>(A.alloc(sizeof(double) * m));
+    GKL_HIP(hipMemsetAsync(sc, 0, sizeof(double) * 4 * (size_t)(m + 2), s));
+}
+
+// Shared device state of a batch (descriptors, step state, flags, Ritz args).
+void alloc_batch_state(BatchState& B, hipStream_t s)
+{
+    const int count = B.count, m = B.maxm;
+    DeviceArena& A = B.arena;
+    B.d_desc = static_cast<BatchDesc*>(A.alloc(sizeof(BatchDesc) * count));
+    B.d_tile_mv = static_cast<int*>(A.alloc(sizeof(int) * (count + 1)));
+    B.d_tile_rmv = static_cast<int*>(A.alloc(sizeof(int) * (count + 1)));
+    B.d_state = static_cast<int*>(A.alloc(sizeof(int) * 2));
+    B.d_active = static_cast<int*>(A.alloc(sizeof(int) * count));
+    B.d_breakdown = static_cast<int*>(A.alloc(sizeof(int) * count));
+    B.d_nconv = static_cast<int*>(A.alloc(sizeof(int) * count));
+    B.d_rargs = static_cast<BatchRitzArgs*>(A.alloc(sizeof(BatchRitzArgs) * count));
+    if (!svd_fits_lds(m))
+        B.svd_scratch = static_cast<double*>(A.alloc(sizeof(double) * svd_scratch_elems(m) * count));
+    for (int q = 0; q < count; ++q) B.probs[q]->ritz.nconv = B.d_nconv + q;
+    GKL_HIP(hipMemsetAsync(B.d_breakdown, 0, sizeof(int) * count, s));
+}
+
+// Basis capacity and restart keep count shared by the batch.
+void batch_basis(BatchState& B, const gkl_options* o, int k, int64_t mx)
+{
+    if (o->krylov_dim > 0) {
+        B.krylov = o->krylov_dim;
+        B.maxm = (int)std::min<int64_t>(o->krylov_dim, mx);
+        B.keep = o->keep > 0 ? o->keep : k + (B.krylov - k) / 2;
+        B.keep = std::min(B.keep, B.maxm - 1);
+        if (B.maxm <= k) B.krylov = 0;
+    } else {
+        B.maxm = (int)std::min<int64_t>(o->max_steps > 0 ? o->max_steps : 512, mx);
+    }
+    B.hstride = B.maxm + 2;
+}
+
+// The batch's stream: the caller's, or a new non-blocking one (graph capture
+// needs a stream other than the null stream, which it does not order after).
+void batch_stream(BatchState& B, const gkl_options* o)
+{
+    if (o->stream) {
+        B.stream = static_cast<hipStream_t>(o->stream);
+    } else {
+        GKL_HIP(hipDeviceSynchronize());
+        GKL_HIP(hipStreamCreateWithFlags(&B.stream, hipStreamNonBlocking));
+        B.own_stream = true;
+    }
+}
+}  // namespace
+
+namespace {
 gkl_status batch_error(gkl_ctx* ctx, gkl_status s, const std::string& msg)
 {
     if (ctx) ctx->last_error = msg;
@@ -291,9 +394,10 @@ gkl_status gkl_create_batched(int32_t count, const uint8_t* const* G, const int6
         return batch_error(nullptr, GKL_ERR_INVALID, "options.struct_size mismatch (ABI version)");
     if (!(tol > 0.0) || !std::isfinite(tol))
         return batch_error(nullptr, GKL_ERR_INVALID, "tol must be > 0");
-    if (reorth != GKL_REORTH_FULL && reorth != GKL_REORTH_PARTIAL)
-        return batch_error(nullptr, GKL_ERR_INVALID, "reorth must be GKL_REORTH_FULL or _PARTIAL");
-    if (reorth == GKL_REORTH_PARTIAL)
+    if (reorth != GKL_REORTH_FULL && reorth != GKL_REORTH_PARTIAL && reorth != GKL_REORTH_ONESIDED)
+        return batch_error(nullptr, GKL_ERR_INVALID,
+                           "reorth must be GKL_REORTH_FULL, _PARTIAL or _ONESIDED");
+    if (reorth != GKL_REORTH_FULL)
         return batch_error(nullptr, GKL_ERR_UNSUPPORTED,
                            "batched solves use full reorthogonalisation (GKL_REORTH_FULL)");
     if (o->precision != GKL_PREC_FP64)
@@ -330,30 +434,11 @@ gkl_status gkl_create_batched(int32_t count, const uint8_t* const* G, const int6
         BatchState& B = *ctx->batch;
         B.count = count;
         B.use_graph = o->graph != 0;
-        if (o->stream) {
-            B.stream = static_cast<hipStream_t>(o->stream);
-        } else {
-            // graph capture needs a stream other than the null stream; it does not
-            // order itself after the null stream, so wait for the device first
-            GKL_HIP(hipDeviceSynchronize());
-            GKL_HIP(hipStreamCreateWithFlags(&B.stream, hipStreamNonBlocking));
-            B.own_stream = true;
-        }
+        batch_stream(B, o);
         hipStream_t s = B.stream;
         // The basis capacity is shared (problems step together); a problem whose own
         // min(n, p) is smaller leaves the batch when its Krylov space is complete.
-        if (o->krylov_dim > 0) {
-            B.krylov = o->krylov_dim;
-            B.maxm = (int)std::min<int64_t>(o->krylov_dim, mx);
-            B.keep = o->keep > 0 ? o->keep : k + (B.krylov - k) / 2;
-            B.keep = std::min(B.keep, B.maxm - 1);
-            if (B.maxm <= k) B.krylov = 0;
-        } else {
-            B.maxm = (int)std::min<int64_t>(o->max_steps > 0 ? o->max_steps : 512, mx);
-        }
-        const int m = B.maxm;
-        B.hstride = m + 2;
-        int64_t max_partial = 0;
+        batch_basis(B, o, k, mx);
         for (int q = 0; q < count; ++q) {
             B.probs.emplace_back(new BatchProblem());
             BatchProblem& P = *B.probs.back();
@@ -366,45 +451,10 @@ gkl_status gkl_create_batched(int32_t count, const uint8_t* const* G, const int6
             for (int64_t t : kTargets)
                 pe = std::max(pe, product_plan_partial_elems(P.prob.packed,
                                                              product_plan(P.prob.packed, t, t)));
-            DeviceArena& A = P.prob.arena;
-            P.partial = static_cast<double*>(A.alloc(sizeof(double) * pe));
-            max_partial = std::max<int64_t>(max_partial, (int64_t)pe);
-            P.U = static_cast<double*>(A.alloc(sizeof(double) * (size_t)n[q] * m));
-            P.V = static_cast<double*>(A.alloc(sizeof(double) * (size_t)p[q] * (m + 1)));
-            double* sc = static_cast<double*>(A.alloc(sizeof(double) * 4 * (size_t)(m + 2)));
-            P.alpha = sc;
-            P.beta = sc + (m + 2);
-            P.theta = sc + 2 * (m + 2);
-            P.rho = sc + 3 * (m + 2);
-            const size_t ch = bortho_chunks(std::max(n[q], p[q]));
-            P.tnpart = static_cast<double*>(A.alloc(sizeof(double) * batch_tn_partial_elems(B.hstride)));
-            P.h = static_cast<double*>(A.alloc(sizeof(double) * B.hstride));
-            P.npart = static_cast<double*>(A.alloc(sizeof(double) * ch));
-            P.anorm = static_cast<double*>(A.alloc(sizeof(double)));
-            if (B.krylov > 0)
-                P.tmp = static_cast<double*>(
-                    A.alloc(sizeof(double) * (size_t)std::max(n[q], p[q]) * B.keep));
-            const size_t mm = (size_t)m * m;
-            P.ritz.B = static_cast<double*>(A.alloc(sizeof(double) * mm));
-            P.ritz.P = static_cast<double*>(A.alloc(sizeof(double) * mm));
-            P.ritz.Q = static_cast<double*>(A.alloc(sizeof(double) * mm));
-            P.ritz.S = static_cast<double*>(A.alloc(sizeof(double) * m));
-            P.ritz.res = static_cast<double*>(A.alloc(sizeof(double) * m));
-            GKL_HIP(hipMemsetAsync(sc, 0, sizeof(double) * 4 * (size_t)(m + 2), s));
+            P.partial = static_cast<double*>(P.prob.arena.alloc(sizeof(double) * pe));
+            alloc_problem(B, P, n[q], p[q], s);
         }
-        DeviceArena& A = B.arena;
-        B.d_desc = static_cast<BatchDesc*>(A.alloc(sizeof(BatchDesc) * count));
-        B.d_tile_mv = static_cast<int*>(A.alloc(sizeof(int) * (count + 1)));
-        B.d_tile_rmv = static_cast<int*>(A.alloc(sizeof(int) * (count + 1)));
-        B.d_state = static_cast<int*>(A.alloc(sizeof(int) * 2));
-        B.d_active = static_cast<int*>(A.alloc(sizeof(int) * count));
-        B.d_breakdown = static_cast<int*>(A.alloc(sizeof(int) * count));
-        B.d_nconv = static_cast<int*>(A.alloc(sizeof(int) * count));
-        B.d_rargs = static_cast<BatchRitzArgs*>(A.alloc(sizeof(BatchRitzArgs) * count));
-        if (!svd_fits_lds(m))
-            B.svd_scratch = static_cast<double*>(A.alloc(sizeof(double) * svd_scratch_elems(m) * count));
-        for (int q = 0; q < count; ++q) B.probs[q]->ritz.nconv = B.d_nconv + q;
-        GKL_HIP(hipMemsetAsync(B.d_breakdown, 0, sizeof(int) * count, s));
+        alloc_batch_state(B, s);
         B.set_geometry(kDefaultTarget, kDefaultTarget);
         if (o->autotune) B.autotune(o->seed);
         GKL_HIP(hipStreamSynchronize(s));
@@ -421,6 +471,123 @@ gkl_status gkl_create_batched(int32_t count, const uint8_t* const* G, const int6
     } catch (...) {
         delete ctx;
         return batch_error(nullptr, GKL_ERR_INTERNAL, "unexpected exception in gkl_create_batched");
+    }
+}
+
+gkl_status gkl_create_loco(const uint8_t* G, int64_t n, int64_t p, int32_t nblocks,
+                           const int64_t* block_start, int32_t k, double tol,
+                           const gkl_options* o, gkl_ctx** out)
+{
+    if (!out) return batch_error(nullptr, GKL_ERR_INVALID, "out is NULL");
+    if (!G || !block_start || !o) return batch_error(nullptr, GKL_ERR_INVALID, "NULL argument");
+    if (o->struct_size != sizeof(gkl_options))
+        return batch_error(nullptr, GKL_ERR_INVALID, "options.struct_size mismatch (ABI version)");
+    if (nblocks < 2 || nblocks > 32)
+        return batch_error(nullptr, GKL_ERR_INVALID, "nblocks must lie in [2, 32]");
+    if (n < 1 || p < 1) return batch_error(nullptr, GKL_ERR_INVALID, "n and p must be >= 1");
+    if (block_start[0] != 0 || block_start[nblocks] != p)
+        return batch_error(nullptr, GKL_ERR_INVALID, "block_start must run from 0 to p");
+    int64_t max_block = 0;
+    for (int q = 0; q < nblocks; ++q) {
+        if (block_start[q + 1] <= block_start[q])
+            return batch_error(nullptr, GKL_ERR_INVALID, "blocks must be non-empty and increasing");
+        max_block = std::max(max_block, block_start[q + 1] - block_start[q]);
+    }
+    if (!(tol > 0.0) || !std::isfinite(tol))
+        return batch_error(nullptr, GKL_ERR_INVALID, "tol must be > 0");
+    const int64_t mn = std::min(n, p - max_block);
+    if (k < 1 || (int64_t)k > mn)
+        return batch_error(nullptr, GKL_ERR_INVALID,
+                           "k must lie in [1, min(n, p - largest block)]");
+    if (o->precision != GKL_PREC_MIXED && o->precision != GKL_PREC_MIXED_INT8)
+        return batch_error(nullptr, GKL_ERR_UNSUPPORTED,
+                           "leave-one-block-out solves use the matrix-core block products "
+                           "(GKL_PREC_MIXED or GKL_PREC_MIXED_INT8)");
+    if (o->ld_bytes != 0 && o->ld_bytes < (n + 3) / 4)
+        return batch_error(nullptr, GKL_ERR_INVALID, "ld_bytes < ceil(n/4)");
+    if (o->krylov_dim < 0 || (o->krylov_dim > 0 && o->krylov_dim <= k))
+        return batch_error(nullptr, GKL_ERR_INVALID, "krylov_dim must be 0 or > k");
+    if (o->krylov_dim > kMaxSvd || o->max_steps < 0 || o->max_steps > kMaxSvd)
+        return batch_error(nullptr, GKL_ERR_INVALID, "krylov_dim / max_steps too large");
+    if (o->keep < 0 || (o->krylov_dim > 0 && o->keep > 0 && (o->keep < k || o->keep >= o->krylov_dim)))
+        return batch_error(nullptr, GKL_ERR_INVALID, "keep must lie in [k, krylov_dim)");
+    if (o->check_every < 0 || o->max_matvecs < 0)
+        return batch_error(nullptr, GKL_ERR_INVALID, "bad check_every / max_matvecs");
+    gkl_ctx* ctx = nullptr;
+    try {
+        auto t0 = std::chrono::steady_clock::now();
+        ctx = new gkl_ctx();
+        ctx->batched = true;
+        ctx->opt = *o;
+        ctx->k = k;
+        ctx->tol = tol;
+        ctx->reorth = GKL_REORTH_FULL;
+        ctx->batch = new BatchState();
+        BatchState& B = *ctx->batch;
+        B.count = nblocks;
+        B.loco = true;
+        B.use_graph = o->graph != 0;
+        batch_stream(B, o);
+        hipStream_t s = B.stream;
+        batch_basis(B, o, k, mn);
+        const int64_t ld = o->ld_bytes ? o->ld_bytes : (n + 3) / 4;
+        B.shared.setup(G, n, p, ld, s, false);
+        B.max_n = n;
+        B.max_p = p;
+        DeviceArena& A = B.arena;
+        B.mshape = mixed_shape(n, p);
+        B.mshape.int8 = o->precision == GKL_PREC_MIXED_INT8;
+        B.mI = static_cast<uint8_t*>(A.alloc((size_t)B.mshape.nI * B.mshape.ldI));
+        B.mS = static_cast<uint8_t*>(A.alloc((size_t)B.mshape.pS * B.mshape.ldS));
+        build_mixed_layouts(G, n, p, ld, B.mI, B.mS, s);
+        B.mw.frag = A.alloc(mixed_frag_bytes(B.mshape));
+        B.mw.partial = static_cast<double*>(A.alloc(sizeof(double) * mixed_partial_elems(B.mshape)));
+        B.mw.cpart = static_cast<double*>(A.alloc(sizeof(double) * 32 * 64));
+        B.mw.cmax = static_cast<double*>(A.alloc(sizeof(double) * 32 * 64));
+        B.Wg = static_cast<double*>(A.alloc(sizeof(double) * (size_t)p * nblocks));
+        B.Zg = static_cast<double*>(A.alloc(sizeof(double) * (size_t)p * nblocks));
+        B.Yg = static_cast<double*>(A.alloc(sizeof(double) * (size_t)n * nblocks));
+        B.Xg = static_cast<double*>(A.alloc(sizeof(double) * (size_t)n * nblocks));
+        std::vector<int64_t> lohi(2 * (size_t)nblocks);
+        for (int q = 0; q < nblocks; ++q) {
+            lohi[2 * q] = block_start[q];
+            lohi[2 * q + 1] = block_start[q + 1];
+        }
+        B.d_lohi = static_cast<int64_t*>(A.alloc(sizeof(int64_t) * lohi.size()));
+        GKL_HIP(hipMemcpyAsync(B.d_lohi, lohi.data(), sizeof(int64_t) * lohi.size(),
+                               hipMemcpyHostToDevice, s));
+        for (int q = 0; q < nblocks; ++q) {
+            B.probs.emplace_back(new BatchProblem());
+            BatchProblem& P = *B.probs.back();
+            // the problem's sizes and statistics are the shared matrix's; its
+            // right vectors carry zeros on its own block
+            P.prob.n = n;
+            P.prob.p = p;
+            P.prob.ld = ld;
+            P.prob.G_user = G;
+            P.prob.stream = s;
+            P.prob.st = B.shared.st;
+            layout_shape(n, p, P.prob.packed);
+            P.cap = std::min(n, p - (lohi[2 * q + 1] - lohi[2 * q]));
+            P.partial = nullptr;
+            alloc_problem(B, P, n, p, s);
+        }
+        alloc_batch_state(B, s);
+        B.set_geometry(kDefaultTarget, kDefaultTarget);
+        GKL_HIP(hipStreamSynchronize(s));
+        ctx->create_ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        *out = ctx;
+        return GKL_OK;
+    } catch (const Error& e) {
+        delete ctx;
+        return batch_error(nullptr, e.status, e.msg);
+    } catch (const std::bad_alloc&) {
+        delete ctx;
+        return batch_error(nullptr, GKL_ERR_NOMEM, "host allocation failed");
+    } catch (...) {
+        delete ctx;
+        return batch_error(nullptr, GKL_ERR_INTERNAL, "unexpected exception in gkl_create_loco");
     }
 }
 
@@ -465,6 +632,7 @@ gkl_status gkl_solve_batched(gkl_ctx* ctx, double* const* sigma, double* const* 
         GKL_HIP(hipMemsetAsync(B.d_breakdown, 0, sizeof(int) * count, s));
         std::vector<int> act(count, 1);
         B.set_active(act);
+        if (B.loco) launch_loco_mask(B.d_desc, count, B.d_lohi, s);
         launch_bstart(B.d_desc, count, B.max_p, B.hstride, s);
         B.set_state(0, 0);
         const int check_every = o.check_every > 0 ? o.check_every : (B.krylov > 0 ? 0 : 5);

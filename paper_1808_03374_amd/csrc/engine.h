@@ -52,6 +52,8 @@ struct gkl_ctx {
     int k = 0;
     double tol = 0.0;
     int reorth = 0;
+    int short_side = 0;      // 0: U (n <= p), 1: V -- the side one-sided reorth keeps
+    bool two_sided = false;  // one-sided reorth switched to both sides
     double omega = 1e-8;
     double root_maxdim = 1.0;
     double noise_scale = 0.0;
@@ -120,6 +122,10 @@ struct gkl_ctx {
     gkl::ProArgs pro_args(int j) const;
     gkl::NormTail pro_tail(double* nrm_out, int side, int j) const;
     void handle_breakdown(bool left, int j);
+    bool long_side_free(int side) const;
+    const int* long_side_check(const double* Q, int64_t len, int ncols, const double* r,
+                               double* nrm);
+    double onesided_tol() const;
     int check_convergence(int m);
     void restart(int m);
     void finalize(int m, double* sigma, double* Uo, int64_t ldu, double* Vo, int64_t ldv);

@@ -289,6 +289,8 @@ void gkl_ctx::left_step(int j)
                 launch_pro_left(pro_args(j), s);
             }
             gate = pro.flag_left;
+        } else if (long_side_free(0)) {
+            gate = long_side_check(U, n, j, uj, alpha + j);
         }
         launch_cgs2(U, n, n, j, uj, gate, opt.adaptive_cgs2, flags + 6, ow, s);
     }
@@ -316,6 +318,7 @@ void gkl_ctx::right_step(int j)
     info.matvecs += 1;
     info.passes_over_G += 1;
     const int* gate = pro_on ? pro.flag_right : nullptr;
+    if (long_side_free(1)) gate = long_side_check(V, p, j + 1, vn, beta + j);
     launch_cgs2(V, p, p, j + 1, vn, gate, opt.adaptive_cgs2, flags + 6, ow, s);
     if (!opt.adaptive_cgs2)
         launch_normalize_after_cgs2(vn, p, beta + j, norm_est, root_maxdim, flags + 1, gate, ow, s,
@@ -354,11 +357,42 @@ NormTail gkl_ctx::pro_tail(double* nrm_out, int side, int j) const
 // (-1 if none) in one copy.
 void gkl_ctx::sync_state(int* nconv, int* breakdown)
 {
-    int h[2] = {0, -1};
-    GKL_HIP(hipMemcpyAsync(h, flags + 8, 2 * sizeof(int), hipMemcpyDeviceToHost, prob.stream));
+    int h[3] = {0, -1, 0};
+    GKL_HIP(hipMemcpyAsync(h, flags + 8, 3 * sizeof(int), hipMemcpyDeviceToHost, prob.stream));
     GKL_HIP(hipStreamSynchronize(prob.stream));
     *nconv = h[0];
     *breakdown = h[1];
+    if (reorth == GKL_REORTH_ONESIDED && h[2] && !two_sided) two_sided = true;
+}
+
+// One-sided reorthogonalisation (Section 3, "Choice of reorthogonalization
+// strategy"): the longer side's Gram-Schmidt is skipped while its basis stays
+// orthogonal.  True until the device's overlap flag has been read back set.
+bool gkl_ctx::long_side_free(int side) const
+{
+    return reorth == GKL_REORTH_ONESIDED && !two_sided && side != short_side;
+}
+
+// The longer side's new (unnormalised) vector r against Q(:, 0:ncols): ||r|| into
+// *nrm (what the normalisation uses when Gram-Schmidt is skipped) and the sticky
+// flag set when the largest overlap exceeds onesided_tol() ||r||.  Returns the
+// flag, which then gates this and every later Gram-Schmidt of that side on the
+// device -- no read-back in the step.
+const int* gkl_ctx::long_side_check(const double* Q, int64_t len, int ncols, const double* r,
+                                    double* nrm)
+{
+    launch_norm(r, len, nrm, ow, prob.stream);
+    launch_overlap_check(Q, len, ncols, r, onesided_tol(), nrm, flags + 10, ow, prob.stream);
+    return flags + 10;
+}
+
+// A loss of orthogonality eta in the unreorthogonalised basis moves the Ritz
+// values (and the norms of the Ritz vectors formed from that basis) by about
+// eta relative, to first order: the threshold is the smaller of omega and the
+// convergence tolerance.
+double gkl_ctx::onesided_tol() const
+{
+    return std::min(omega, tol);
 }
 
 // ||r|| into *out without scaling (PRO needs alpha_j / beta_j before deciding).
@@ -438,6 +472,27 @@ void gkl_ctx::finalize(int m, double* sigma, double* Uo, int64_t ldu, double* Vo
     GKL_HIP(hipMemcpyAsync(sigma, ritz.S, sizeof(double) * kk, hipMemcpyDeviceToDevice, s));
     launch_gemm_tall(U, n, n, m, ritz.P, m, kk, Uo, ldu, s);
     launch_gemm_tall(V, p, p, m, ritz.Q, m, kk, Vo, ldv, s);
+    if (reorth == GKL_REORTH_ONESIDED) {
+        // the long side's basis was not kept orthogonal: its Ritz vectors are
+        // formed from the short side's, v_i = A^T u_i / ||A^T u_i|| (or
+        // u_i = A v_i / ||A v_i||); one product per vector
+        double* scratch_nrm = ow.h;
+        for (int i = 0; i < kk; ++i) {
+            double* uo = Uo + (int64_t)i * ldu;
+            double* vo = Vo + (int64_t)i * ldv;
+            if (short_side == 0) {
+                launch_rmatvec(prob.packed, prob.st, uo, vo, nullptr, nullptr, prob.mvw, s, nullptr,
+                               nullptr);
+                launch_normalize(vo, p, vo, scratch_nrm, norm_est, root_maxdim, flags + 7, ow, s);
+            } else {
+                launch_matvec(prob.packed, prob.st, vo, uo, nullptr, nullptr, prob.mvw, s, nullptr,
+                              nullptr);
+                launch_normalize(uo, n, uo, scratch_nrm, norm_est, root_maxdim, flags + 7, ow, s);
+            }
+            info.matvecs += 1;
+            info.passes_over_G += 1;
+        }
+    }
     launch_sign_fix(Uo, ldu, n, Vo, ldv, p, kk, s);
     std::vector<double> res(kk), sig(1);
     GKL_HIP(hipMemcpyAsync(res.data(), ritz.res, sizeof(double) * kk, hipMemcpyDeviceToHost, s));
@@ -461,6 +516,8 @@ gkl_status gkl_ctx::solve_fp64(double* sigma, double* Uo, int64_t ldu, double* V
     else launch_gaussian(V, p, opt.seed, 0, s);
     GKL_HIP(hipMemsetAsync(scal, 0, sizeof(double) * kScalars, s));
     GKL_HIP(hipMemsetAsync(flags + 9, 0xFF, sizeof(int), s));   // first breakdown = -1
+    GKL_HIP(hipMemsetAsync(flags + 10, 0, sizeof(int), s));     // long side lost orthogonality
+    two_sided = false;
     launch_normalize(V, p, V, tmp, norm_est, root_maxdim, flags + 1, ow, s);
     GKL_HIP(hipMemsetAsync(norm_est, 0, sizeof(double), s));
     if (reorth == GKL_REORTH_PARTIAL) launch_pro_reset(pro, maxm, 0, s);
@@ -609,8 +666,9 @@ static gkl_status validate(const uint8_t* G, int64_t n, int64_t p, int32_t k, do
     if (k < 1 || (int64_t)k > std::min(n, p))
         return set_error(nullptr, GKL_ERR_INVALID, "k must lie in [1, min(n, p)]");
     if (!(tol > 0.0) || !isfinite(tol)) return set_error(nullptr, GKL_ERR_INVALID, "tol must be > 0");
-    if (reorth != GKL_REORTH_FULL && reorth != GKL_REORTH_PARTIAL)
-        return set_error(nullptr, GKL_ERR_INVALID, "reorth must be GKL_REORTH_FULL or _PARTIAL");
+    if (reorth != GKL_REORTH_FULL && reorth != GKL_REORTH_PARTIAL && reorth != GKL_REORTH_ONESIDED)
+        return set_error(nullptr, GKL_ERR_INVALID,
+                         "reorth must be GKL_REORTH_FULL, _PARTIAL or _ONESIDED");
     if (o->krylov_dim < 0 || (o->krylov_dim > 0 && o->krylov_dim <= k))
         return set_error(nullptr, GKL_ERR_INVALID, "krylov_dim must be 0 or > k");
     if (o->krylov_dim > kMaxSvd) return set_error(nullptr, GKL_ERR_INVALID, "krylov_dim too large");
@@ -626,6 +684,9 @@ static gkl_status validate(const uint8_t* G, int64_t n, int64_t p, int32_t k, do
     if (o->max_steps < 0 || o->max_steps > kMaxSvd || o->check_every < 0 || o->max_matvecs < 0)
         return set_error(nullptr, GKL_ERR_INVALID, "bad max_steps / check_every / max_matvecs");
     if (o->pro_omega < 0.0) return set_error(nullptr, GKL_ERR_INVALID, "pro_omega must be >= 0");
+    if (reorth == GKL_REORTH_ONESIDED && o->precision != GKL_PREC_FP64)
+        return set_error(nullptr, GKL_ERR_UNSUPPORTED,
+                         "one-sided reorthogonalisation is built for the FP64 path only");
     return GKL_OK;
 }
 
@@ -645,6 +706,7 @@ gkl_status gkl_create_ex(const uint8_t* G, int64_t n, int64_t p, int32_t k, doub
         ctx->k = k;
         ctx->tol = tol;
         ctx->reorth = reorth;
+        ctx->short_side = n <= p ? 0 : 1;
         ctx->omega = o->pro_omega > 0.0 ? o->pro_omega : 1e-8;
         hipStream_t s = static_cast<hipStream_t>(o->stream);
         const int64_t ld = o->ld_bytes ? o->ld_bytes : (n + 3) / 4;
@@ -742,10 +804,9 @@ gkl_status gkl_column_stats(gkl_ctx* ctx, int64_t* count, int64_t* nobs, double*
 gkl_status gkl_unpack(gkl_ctx* ctx, int8_t* out)
 {
     if (!ctx || ctx->batched || !out) return set_error(ctx, GKL_ERR_INVALID, "bad argument");
-    if (!ctx->prob.packed.T) return set_error(ctx, GKL_ERR_INVALID, "unpack needs an FP64 context");
     try {
         hipStream_t s = ctx->prob.stream;
-        launch_unpack_layout(ctx->prob.packed, out, s);
+        launch_unpack(ctx->prob.G_user, ctx->prob.n, ctx->prob.p, ctx->prob.ld, out, s);
         GKL_HIP(hipStreamSynchronize(s));
         return GKL_OK;
     } catch (const Error& e) {

@@ -203,4 +203,108 @@ void launch_bstart(const BatchDesc* d, int count, int64_t max_p, int, hipStream_
     GKL_LAUNCH_CHECK("bstart_scale_kernel");
 }
 
+
+// ---------------------------------------------------------------------------
+// Leave-one-block-out (LOCO) batches
+// ---------------------------------------------------------------------------
+// Problem q is the whole matrix without its SNP block [lohi[2q], lohi[2q+1]):
+// its right vectors live in the full p-space with that block's rows zero, so
+// A_{-q} v = A v and A_{-q}^T u is A^T u with the block's rows dropped.  The
+// products of all problems are then one block product with the whole matrix.
+
+// out[:, q] = v_j (side 0, len = p) or u_j (side 1, len = n) of problem q; zero
+// for problems no longer active.
+__global__ void __launch_bounds__(256)
+loco_gather_kernel(const BatchDesc* __restrict__ desc, const int* __restrict__ state, int side,
+                   double* __restrict__ out, int64_t len)
+{
+    const int q = blockIdx.y;
+    const BatchDesc& D = desc[q];
+    const int j = state[0];
+    const bool act = *D.active != 0;
+    const double* src = side == 0 ? D.V + (int64_t)j * D.p : D.U + (int64_t)j * D.n;
+    double* dst = out + (int64_t)q * len;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = act ? src[i] : 0.0;
+}
+
+void launch_loco_gather(const BatchDesc* d, const int* state, int count, int side, double* out,
+                        int64_t len, hipStream_t s)
+{
+    unsigned int nb = ceil_div(len, 256);
+    if (nb > 1024) nb = 1024;
+    hipLaunchKernelGGL(loco_gather_kernel, dim3(nb, count), dim3(256), 0, s, d, state, side, out, len);
+    GKL_LAUNCH_CHECK("loco_gather_kernel");
+}
+
+// u_j = Y(:, q) - beta_{j-1} u_{j-1}, or - U(:, 0:nlock) rho right after a restart.
+__global__ void __launch_bounds__(256)
+loco_left_kernel(const BatchDesc* __restrict__ desc, const int* __restrict__ state,
+                 const double* __restrict__ Y, int64_t n)
+{
+    const BatchDesc& D = desc[blockIdx.y];
+    if (!*D.active) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int j = state[0], nlock = state[1];
+    double s = Y[(int64_t)blockIdx.y * n + i];
+    if (j > 0 && j == nlock) {
+        for (int c = 0; c < nlock; ++c) s -= D.rho[c] * D.U[(int64_t)c * n + i];
+    } else if (j > 0) {
+        s -= D.beta[j - 1] * D.U[(int64_t)(j - 1) * n + i];
+    }
+    D.U[(int64_t)j * n + i] = s;
+}
+
+void launch_loco_left(const BatchDesc* d, const int* state, int count, const double* Y, int64_t n,
+                      hipStream_t s)
+{
+    hipLaunchKernelGGL(loco_left_kernel, dim3(ceil_div(n, 256), count), dim3(256), 0, s, d, state, Y,
+                       n);
+    GKL_LAUNCH_CHECK("loco_left_kernel");
+}
+
+// v_{j+1} = Z(:, q) with the rows of block q zeroed, - alpha_j v_j.
+__global__ void __launch_bounds__(256)
+loco_right_kernel(const BatchDesc* __restrict__ desc, const int* __restrict__ state,
+                  const double* __restrict__ Z, int64_t p, const int64_t* __restrict__ lohi)
+{
+    const int q = blockIdx.y;
+    const BatchDesc& D = desc[q];
+    if (!*D.active) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= p) return;
+    const int j = state[0];
+    const bool own = i >= lohi[2 * q] && i < lohi[2 * q + 1];
+    const double z = own ? 0.0 : Z[(int64_t)q * p + i];
+    D.V[(int64_t)(j + 1) * p + i] = z - D.alpha[j] * D.V[(int64_t)j * p + i];
+}
+
+void launch_loco_right(const BatchDesc* d, const int* state, int count, const double* Z, int64_t p,
+                       const int64_t* lohi, hipStream_t s)
+{
+    hipLaunchKernelGGL(loco_right_kernel, dim3(ceil_div(p, 256), count), dim3(256), 0, s, d, state, Z,
+                       p, lohi);
+    GKL_LAUNCH_CHECK("loco_right_kernel");
+}
+
+// Start vectors: zero the rows of each problem's own block.
+__global__ void __launch_bounds__(256)
+loco_mask_kernel(const BatchDesc* __restrict__ desc, const int64_t* __restrict__ lohi)
+{
+    const int q = blockIdx.y;
+    const BatchDesc& D = desc[q];
+    const int64_t lo = lohi[2 * q], hi = lohi[2 * q + 1];
+    for (int64_t i = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hi;
+         i += (int64_t)gridDim.x * blockDim.x)
+        D.V[i] = 0.0;
+}
+
+void launch_loco_mask(const BatchDesc* d, int count, const int64_t* lohi, hipStream_t s)
+{
+    hipLaunchKernelGGL(loco_mask_kernel, dim3(256, count), dim3(256), 0, s, d, lohi);
+    GKL_LAUNCH_CHECK("loco_mask_kernel");
+}
+
 }  // namespace gkl

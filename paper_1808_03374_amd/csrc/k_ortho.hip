@@ -513,6 +513,36 @@ void launch_normalize(double* r, int64_t len, double* out, double* nrm_out, doub
 }
 
 // ---------------------------------------------------------------------------
+// Overlap check of one-sided reorthogonalisation
+// ---------------------------------------------------------------------------
+// flag = 1 when max_i |h_i| > omega ||q||, h = Q(:, 0:ncols)^T q.
+__global__ void __launch_bounds__(256)
+overlap_flag_kernel(const double* __restrict__ h, int ncols, double omega,
+                    const double* __restrict__ qnorm, int* __restrict__ flag)
+{
+    __shared__ double sh[4];
+    double m = 0.0;
+    for (int i = threadIdx.x; i < ncols; i += blockDim.x) m = fmax(m, fabs(h[i]));
+    for (int off = 32; off >= 1; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double mx = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+        if (mx > omega * *qnorm) *flag = 1;
+    }
+}
+
+void launch_overlap_check(const double* Q, int64_t len, int ncols, const double* q, double omega,
+                          const double* qnorm, int* flag, OrthoWork& w, hipStream_t s)
+{
+    if (ncols <= 0) return;
+    launch_gemm_tn(Q, len, q, len, len, ncols, 1, w.h, ncols, w.tn_partial, s);
+    hipLaunchKernelGGL(overlap_flag_kernel, dim3(1), dim3(256), 0, s, w.h, ncols, omega, qnorm,
+                       flag);
+    GKL_LAUNCH_CHECK("overlap_flag_kernel");
+}
+
+// ---------------------------------------------------------------------------
 // y -= Q c
 // ---------------------------------------------------------------------------
 __global__ void gemv_n_sub_kernel(const double* __restrict__ Q, int64_t ldq, int64_t len, int ncols,

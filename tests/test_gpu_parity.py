@@ -81,6 +81,27 @@ def test_unpack_bit_exact(gk, name, n, p, ld, pad):
     ctx.close()
 
 
+def test_hooks_on_a_blocked_context(gk):
+    # unpack decodes the caller's matrix whatever the context kind; the FP64
+    # product hooks need an FP64 context and say so
+    g, Gd = gen("c2", 300, 2000, pad_mode=-1)
+    ctx = gk.Context(Gd, g.n, g.p, 4, precision=gk.GKL_PREC_MIXED, block_width=8)
+    got = ctx.unpack().cpu().numpy()
+    assert np.array_equal(got, oracle.decode(g.packed, g.n, g.p))
+    st = oracle.column_stats(g.n, *oracle.counts(g.packed, g.n, g.p))
+    mean = ctx.column_stats()[2].cpu().numpy()
+    assert np.array_equal(mean.view(np.uint64), st.mean.view(np.uint64))
+    with pytest.raises(gk.GKLError) as e:
+        ctx.matvec(dev(np.ones(g.p)))
+    assert e.value.status == gk.GKL_ERR_INVALID and "FP64" in str(e.value)
+    ctx.close()
+    f64 = gk.Context(Gd, g.n, g.p, 4)
+    with pytest.raises(gk.GKLError) as e:
+        f64.matmat_mixed(dev(np.ones((g.p, 2))))
+    assert e.value.status == gk.GKL_ERR_INVALID
+    f64.close()
+
+
 @pytest.mark.parametrize("name,n,p,ld,pad", SHAPES)
 def test_matvec_parity(gk, name, n, p, ld, pad):
     g, Gd = gen(name, n, p, ld=ld, pad_mode=pad)
@@ -283,3 +304,41 @@ def test_product_timing_sampling(gk, stride):
     assert i1.timed_rmatvecs == -(-n_rmv // stride)
     assert i0.timed_matvecs == 0 and i0.matvec_kernel_ms == 0.0
     assert i1.matvec_kernel_ms > 0.0 and i1.rmatvec_kernel_ms > 0.0
+
+
+@pytest.mark.parametrize("name,n,p,k,m", [("c1", 1000, 5000, 10, 0), ("c2", 2000, 20000, 20, 60),
+                                          ("c3", 3000, 1500, 10, 40)])
+def test_one_sided_reorthogonalisation(gk, name, n, p, k, m):
+    # Section 3, "Choice of reorthogonalization strategy": Gram-Schmidt on the
+    # shorter side only (U for n <= p, V for the tall 3,000 x 1,500 case), the
+    # longer side's vectors recomputed from it at the end; sigma must match the
+    # oracle as with full reorthogonalisation
+    g, Gd = gen(name, n, p)
+    op, ref = _oracle_solve(g, k, 2)
+    v0 = dev(synth.start_vector(g.p, 2))
+    runs = {}
+    for mode in (gk.GKL_REORTH_FULL, gk.GKL_REORTH_ONESIDED):
+        ctx = gk.Context(Gd, g.n, g.p, k, tol=1e-11, reorth=mode, v0=v0, krylov_dim=m)
+        runs[mode] = ctx.solve()
+        ctx.close()
+    sigma, U, V, st, info = runs[gk.GKL_REORTH_ONESIDED]
+    assert st == gk.GKL_OK
+    full = runs[gk.GKL_REORTH_FULL][4]
+    assert info.reorths < full.reorths, (info.reorths, full.reorths)
+    sigma = sigma.cpu().numpy()
+    U = U.cpu().numpy()
+    V = V.cpu().numpy()
+    assert np.all(np.abs(sigma - ref.sigma) <= 1e-10 * ref.sigma)
+    assert np.abs(U.T @ U - np.eye(k)).max() < 1e-9
+    assert np.abs(V.T @ V - np.eye(k)).max() < 1e-9
+    assert _residuals(op, sigma, U, V) <= 1e-9 * sigma[0]
+    # same sign rule as the oracle on the leading (gapped) vector
+    assert np.dot(V[:, 0], ref.V[:, 0]) > 0
+
+
+def test_one_sided_is_fp64_only(gk):
+    g, Gd = gen("c1", 200, 900)
+    with pytest.raises(gk.GKLError) as e:
+        gk.Context(Gd, g.n, g.p, 3, reorth=gk.GKL_REORTH_ONESIDED, precision=gk.GKL_PREC_MIXED,
+                   block_width=4)
+    assert e.value.status == gk.GKL_ERR_UNSUPPORTED
