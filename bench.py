@@ -68,23 +68,43 @@ def block_bytes(n, p, b):
     return ((n + 3) // 4) * p + b * (4 * p + 8 * n)
 
 
-def measured_traffic(workload, kernel):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or None
-    when the kernel source changed since the counters were taken."""
+# FP64 product format of the FP64 solves: (gkl_fp64_products value, name)
+FP64_PRODUCTS = [0, "auto"]
+FORMAT_NAMES = {1: "lut", 2: "limbs", 3: "lut+limbs"}
+
+
+def source_digest(path, region=None):
+    """sha256 of a source file, or of the text between two marker strings of it."""
     import hashlib
+    text = open(path, "rb").read()
+    if region:
+        a = text.index(region[0].encode())
+        b = text.index(region[1].encode(), a)
+        text = text[a:b]
+    return hashlib.sha256(text).hexdigest()
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summaries of the workload (profiles/<workload>_*hbm_traffic*.md, one JSON
+    record per summary), or None when none covers it or the kernel's source
+    changed since the counters were taken."""
+    import glob
     import re
-    path = os.path.join(ROOT, "profiles", f"{workload}_fp64_hbm_traffic.md")
-    if not os.path.exists(path):
-        return None
-    m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
-    if not m:
-        return None
-    rec = json.loads(m.group(1))
-    src = os.path.join(ROOT, rec["kernel_source"])
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
-        return None
-    k = rec["per_launch_bytes"].get(kernel)
-    return None if k is None else int(k["fetch"] + k["write"])
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", f"{workload}_*hbm_traffic*.md"))):
+        for block in re.findall(r"```json\n(.*?)\n```", open(path).read(), re.S):
+            rec = json.loads(block)
+            k = rec.get("per_launch_bytes", {}).get(kernel)
+            if k is None:
+                continue
+            try:
+                digest = source_digest(os.path.join(ROOT, rec["kernel_source"]), rec.get("region"))
+            except (OSError, ValueError):
+                return None
+            if digest != rec["source_sha256"]:
+                return None
+            return int(k["fetch"] + k["write"])
+    return None
 
 
 def vector_angles(X, Y):
@@ -125,7 +145,8 @@ def fp64_solve(gk, torch, W, tol, steps, warmup, stream, keep=True, label="fp64"
     import numpy as np
     wl = W.wl
     reorth = gk.GKL_REORTH_PARTIAL if wl["reorth"] == "partial" else gk.GKL_REORTH_FULL
-    opts = dict(v0=W.v0, krylov_dim=wl["krylov_dim"], timing=TIMING_STRIDE, stream=stream)
+    opts = dict(v0=W.v0, krylov_dim=wl["krylov_dim"], timing=TIMING_STRIDE, stream=stream,
+                fp64_products=FP64_PRODUCTS[0])
     n, p, k = W.n, W.p, W.k
     sigma = torch.empty(k, dtype=torch.float64, device="cuda")
     U = torch.empty((k, n), dtype=torch.float64, device="cuda")
@@ -157,15 +178,18 @@ def fp64_solve(gk, torch, W, tol, steps, warmup, stream, keep=True, label="fp64"
             f"matvecs {info.matvecs} restarts {info.restarts} conv {info.converged}")
     if probe is not None:
         # FP64 products of a few random directions, for the blocked products' error
+        pw, px = probe
         ctx = gk.Context(W.G, n, p, k, tol, reorth, **opts)
         try:
-            probe_out["Y"] = torch.stack([ctx.matvec(probe[:, c].contiguous())
-                                          for c in range(probe.shape[1])], dim=1)
+            probe_out["Y"] = torch.stack([ctx.matvec(pw[:, c].contiguous())
+                                          for c in range(pw.shape[1])], dim=1)
+            probe_out["Z"] = torch.stack([ctx.rmatvec(px[:, c].contiguous())
+                                          for c in range(px.shape[1])], dim=1)
         finally:
             ctx.close()
         torch.cuda.synchronize()
     out = {"sec_per_step": elapsed / steps, "infos": infos, "status": int(st),
-           "probe_Y": probe_out.get("Y")}
+           "probe_Y": probe_out.get("Y"), "probe_Z": probe_out.get("Z")}
     if keep:
         out["sigma"] = sigma.cpu().numpy().copy()
         out["U"] = U.cpu().numpy().T.copy()
@@ -173,7 +197,12 @@ def fp64_solve(gk, torch, W, tol, steps, warmup, stream, keep=True, label="fp64"
     return out
 
 
-def product_stats(infos, nbytes):
+KERNEL_NAMES = {"lut": ("matvec_lut_kernel (A v)", "rmatvec_lut_kernel (A^T u)"),
+                "limbs": ("limb_product_kernel<A v>", "limb_product_kernel<A^T u>"),
+                "lut+limbs": ("matvec_lut_kernel (A v)", "limb_product_kernel<A^T u>")}
+
+
+def product_stats(infos, nbytes, products="lut"):
     """Average launch time of each product from the sampled HIP events, and rates."""
     mv_ms = sum(i.matvec_kernel_ms for i in infos)
     rmv_ms = sum(i.rmatvec_kernel_ms for i in infos)
@@ -181,10 +210,11 @@ def product_stats(infos, nbytes):
     rmv_n = sum(i.timed_rmatvecs for i in infos)
     mv_avg = mv_ms / max(mv_n, 1)
     rmv_avg = rmv_ms / max(rmv_n, 1)
-    return {"matvec_kernel (A v)": {"total_ms": mv_ms, "avg_ms": mv_avg, "launches": mv_n,
-                                    "GBps": nbytes / (mv_avg * 1e-3) / 1e9},
-            "rmatvec_kernel (A^T u)": {"total_ms": rmv_ms, "avg_ms": rmv_avg, "launches": rmv_n,
-                                       "GBps": nbytes / (rmv_avg * 1e-3) / 1e9}}
+    a, b = KERNEL_NAMES.get(products, ("A v", "A^T u"))
+    return {a: {"total_ms": mv_ms, "avg_ms": mv_avg, "launches": mv_n,
+                "GBps": nbytes / (mv_avg * 1e-3) / 1e9},
+            b: {"total_ms": rmv_ms, "avg_ms": rmv_avg, "launches": rmv_n,
+                "GBps": nbytes / (rmv_avg * 1e-3) / 1e9}}
 
 
 def blocked_solve(gk, torch, W, b, fmt, ref, stream, reps=1, probe=None, probe_Y=None):
@@ -211,11 +241,17 @@ def blocked_solve(gk, torch, W, b, fmt, ref, stream, reps=1, probe=None, probe_Y
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             if rep == 0 and probe is not None and probe_Y is not None:
-                Ym = ctx.matmat_mixed(probe)
+                pw, px = probe
+                probe_Z = ref["probe_Z"]
+                Ym = ctx.matmat_mixed(pw)
+                Zm = ctx.rmatmat_mixed(px)
                 torch.cuda.synchronize()
                 dY = torch.linalg.norm(Ym - probe_Y, dim=0)
-                eps_rel = float(torch.max(dY / torch.linalg.norm(probe_Y, dim=0)))
-                eps_op = float(torch.max(dY / torch.linalg.norm(probe, dim=0))) / float(ref["sigma"][0])
+                dZ = torch.linalg.norm(Zm - probe_Z, dim=0)
+                eps_rel = float(max(torch.max(dY / torch.linalg.norm(probe_Y, dim=0)),
+                                    torch.max(dZ / torch.linalg.norm(probe_Z, dim=0))))
+                eps_op = float(max(torch.max(dY / torch.linalg.norm(pw, dim=0)),
+                                   torch.max(dZ / torch.linalg.norm(px, dim=0)))) / float(ref["sigma"][0])
         finally:
             ctx.close()
         if rep > 0:
@@ -230,9 +266,9 @@ def blocked_solve(gk, torch, W, b, fmt, ref, stream, reps=1, probe=None, probe_Y
     gaps = relative_gaps(ref["sigma"])
     # gap rule: a vector is held to the angle target when the bound
     # eps * sigma_1 / (delta_i sigma_i) on its error is itself below the target,
-    # with eps the larger of the solve tolerance and the measured product error
+    # with eps the solve tolerance plus the measured product error
     # ||dY|| / (sigma_1 ||w||) on random unit vectors
-    eps = max(BLOCKED_TOL, eps_op or 0.0)
+    eps = BLOCKED_TOL + (eps_op or 0.0)
     bound = eps * ref["sigma"][0] / (gaps * ref["sigma"])
     gated = bound <= ANGLE_TARGET
     gated[-1] = False          # the gap below sigma_k is not known
@@ -247,7 +283,7 @@ def blocked_solve(gk, torch, W, b, fmt, ref, stream, reps=1, probe=None, probe_Y
            "sigma_rel_err_vs_fp64": [float(x) for x in rel],
            "angle_u_vs_fp64": [float(x) for x in ang_u],
            "angle_v_vs_fp64": [float(x) for x in ang_v],
-           "product_err_rel_to_y": eps_rel,
+           "product_err_rel": eps_rel,
            "product_err_rel_to_sigma1": eps_op,
            "gap_rule_gated": [int(x) for x in gated],
            "gated_max_angle": float(max(ang_u[gated].max(), ang_v[gated].max())) if gated.any() else None}
@@ -292,7 +328,8 @@ def run_compare(gk, torch, W, ref, args, stream):
                                   "restarts": int(r["infos"][-1].restarts),
                                   "sigma_max_rel_err_vs_fp64": float(rel.max())}
     rng = np.random.default_rng([7, 0x70726F])
-    probe = torch.from_numpy(rng.standard_normal((W.p, 4)) / np.sqrt(W.p)).cuda()
+    probe = (torch.from_numpy(rng.standard_normal((W.p, 4)) / np.sqrt(W.p)).cuda(),
+             torch.from_numpy(rng.standard_normal((W.n, 4)) / np.sqrt(W.n)).cuda())
     probe_Y = ref.get("probe_Y")
     for fmt in args.formats:
         for b in args.widths:
@@ -308,15 +345,60 @@ def run_compare(gk, torch, W, ref, args, stream):
     return out
 
 
-def run_batched(gk, torch, args):
+def chromosome_blocks():
+    import synth
+    log("[bench] generating the 22 chromosome blocks")
+    return [synth.config("c4", chrom=c) for c in range(1, 23)]
+
+
+def run_loco(gk, torch, gs, args):
+    """Leave-one-chromosome-out PCAs of the 22-block genome: 22 problems (the
+    genome without one chromosome each), solved together with block products of
+    width 22 on the matrix cores (split BF16), one pass over the genome per
+    half-step for all 22."""
+    import numpy as np
+    import synth
+    packed = np.concatenate([g.packed for g in gs], axis=0)
+    starts = np.cumsum([0] + [g.p for g in gs])
+    n, p = gs[0].n, int(starts[-1])
+    G = torch.from_numpy(packed).cuda()
+    del packed
+    k, tol, m = 10, 1e-8, 40
+    v0 = torch.from_numpy(np.concatenate([synth.start_vector(p, 200 + q) for q in range(22)])).cuda()
+    t0 = time.perf_counter()
+    ctx = gk.LocoContext(G, n, p, starts, k, tol=tol, v0=v0, krylov_dim=m,
+                         precision=gk.GKL_PREC_MIXED, graph=1)
+    create_s = time.perf_counter() - t0
+    try:
+        ctx.solve()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sig, Us, Vs, st, infos = ctx.solve()
+        torch.cuda.synchronize()
+        solve_s = time.perf_counter() - t0
+    finally:
+        ctx.close()
+    del G, v0
+    torch.cuda.empty_cache()
+    log(f"[bench] loco: {solve_s:.3f} s, status {st}")
+    return {"workload": "leave-one-chromosome-out: 22 problems, each the 20,000 x 701,314 genome "
+                        "without one chromosome; k=10, tol 1e-8, basis 40, products as 22-column "
+                        "split-BF16 block products of the whole genome",
+            "problems": 22, "k": k, "tol": tol, "krylov_dim": m, "status": int(st),
+            "solve_s": solve_s, "create_s": create_s,
+            "converged": int(sum(i.converged for i in infos)),
+            "steps": int(max(i.steps for i in infos)), "restarts": int(max(i.restarts for i in infos)),
+            "passes_over_genome": int(2 * max(i.steps for i in infos)),
+            "sigma_1": [float(x.cpu()[0]) for x in sig]}
+
+
+def run_batched(gk, torch, gs, args):
     """22 chromosome blocks (20,000 individuals, 8,000..80,000 SNPs, 700,000 in all)
     solved together by the batched path (persistent products, one HIP graph per
     Lanczos step, autotuned product geometry), beside the same 22 problems
     solved one after another through the single-problem entry points."""
     import numpy as np
     import synth
-    log("[bench] batched: generating 22 chromosome blocks")
-    gs = [synth.config("c4", chrom=c) for c in range(1, 23)]
     Gs = [torch.from_numpy(g.packed).cuda() for g in gs]
     ns = [g.n for g in gs]
     ps = [g.p for g in gs]
@@ -382,12 +464,67 @@ def run_batched(gk, torch, args):
     return out
 
 
+def run_paper_model(gk, torch, args, stream):
+    """The paper's own experiment matrix: its Section 2 random model at the Fig. 1
+    size (41,505 individuals x 81,700 SNPs, r = 10, nsignal = n p, rkins = 0.017;
+    848 MB packed), top 25 by FP64 GKL as in its Table 3 -- partial
+    reorthogonalisation without restart, and full reorthogonalisation with thick
+    restart -- reporting products, time, the summed residual estimates (the
+    paper's ||Delta theta||_1), the error of sigma_10 against a solve to 1e-13,
+    and the outliers above 1.1 sigma_+."""
+    import numpy as np
+    import synth
+    log("[bench] paper model: generating 41,505 x 81,700")
+    g = synth.algorithm1()
+    n, p, k = g.n, g.p, 25
+    G = torch.from_numpy(g.packed).cuda()
+    v0 = torch.from_numpy(synth.start_vector(p, 3)).cuda()
+    sig = torch.empty(k, dtype=torch.float64, device="cuda")
+    U = torch.empty((k, n), dtype=torch.float64, device="cuda")
+    V = torch.empty((k, p), dtype=torch.float64, device="cuda")
+    runs = {}
+    for label, reorth, tol, m in (("tight", gk.GKL_REORTH_FULL, 1e-13, 0),
+                                  ("partial_no_restart", gk.GKL_REORTH_PARTIAL, 1e-10, 0),
+                                  ("full_thick_restart", gk.GKL_REORTH_FULL, 1e-10, 60)):
+        for rep in range(2):
+            ctx = gk.Context(G, n, p, k, tol, reorth, v0=v0, krylov_dim=m, stream=stream)
+            try:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st, info = gk.gkl_solve(ctx.ctx, sig, U, n, V, p)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+            finally:
+                ctx.close()
+        runs[label] = (sig.cpu().numpy().copy(), info, dt, int(st))
+    s_t = runs["tight"][0]
+    edge = np.sqrt(n) + np.sqrt(p)
+    out = {"workload": "Section 2 model at the Fig. 1 size: 41,505 x 81,700, r=10, nsignal=n*p, "
+                       "rkins=0.017, rows read as individuals; top 25, FP64",
+           "packed_bytes": int(g.nbytes), "copied_rows": g.meta["copied_rows"],
+           "bulk_edge_unit_variance": float(edge),
+           "outliers_above_1.1_edge": int(np.sum(s_t > 1.1 * edge)),
+           "outliers_above_529.7": int(np.sum(s_t > 529.7)),
+           "sigma_tight": [float(x) for x in s_t]}
+    for label in ("partial_no_restart", "full_thick_restart"):
+        s_l, info, dt, st = runs[label]
+        out[label] = {"status": st, "solve_s": dt, "mvps": int(info.matvecs),
+                      "restarts": int(info.restarts),
+                      "sum_residual_est": info.sum_residual_est,
+                      "rel_err_sigma10_vs_tight": float(abs(s_l[9] - s_t[9]) / s_t[9])}
+    del G
+    torch.cuda.empty_cache()
+    log(f"[bench] paper model: {out['outliers_above_1.1_edge']} outliers above 1.1 edge")
+    return out
+
+
 def run_extra(gk, torch, name, args, stream):
     """A second workload (FP64 and blocked b = 8 and 16) reported beside the headline."""
     W = Workload(gk, torch, WORKLOADS[name], progress=False)
     ref = fp64_solve(gk, torch, W, W.wl["tol"], 3, 1, stream, label=f"{name} fp64")
-    prod = product_stats(ref["infos"], fp64_bytes(W.n, W.p))
-    out = {"workload": W.wl["desc"], "fp64_s_per_step": ref["sec_per_step"],
+    fmt = FORMAT_NAMES.get(int(ref["infos"][-1].fp64_products), "?")
+    prod = product_stats(ref["infos"], fp64_bytes(W.n, W.p), fmt)
+    out = {"workload": W.wl["desc"], "fp64_s_per_step": ref["sec_per_step"], "fp64_products": fmt,
            "fp64_matvecs": int(ref["infos"][-1].matvecs), "products": prod}
     for b in (8, 16):
         r = blocked_solve(gk, torch, W, b, "bf16", ref, stream, reps=1)
@@ -435,6 +572,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fp64-products", default="auto", choices=["auto", "lut", "limbs", "lut+limbs"],
+                    help="product format of the FP64 solves (lookup tables or int8 limbs)")
     ap.add_argument("--certificate-triplets", type=int, default=5,
                     help="leading triplets checked by the CPU oracle (2 products each)")
     ap.add_argument("--no-compare", action="store_true",
@@ -448,6 +587,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched solve of the 22 chromosome blocks")
     ap.add_argument("--batched-steps", type=int, default=2)
+    ap.add_argument("--no-loco", action="store_true",
+                    help="skip the leave-one-chromosome-out solve of the 22-block genome")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="after the timed steps, copy BYTES bytes device-to-device 3 times "
                          "(reference dispatch for the HBM traffic counters)")
@@ -456,6 +597,8 @@ def main():
         print("bench.py runs on one GPU only; the library has no multi-GPU path, so --gpus "
               "must be 1", file=sys.stderr)
         sys.exit(2)
+    FP64_PRODUCTS[:] = [{"auto": 0, "lut": 1, "limbs": 2, "lut+limbs": 3}[args.fp64_products],
+                        args.fp64_products]
     args.widths = [int(x) for x in args.widths.split(",") if x]
     args.formats = [x for x in args.formats.split(",") if x]
 
@@ -469,18 +612,20 @@ def main():
     W = Workload(gk, torch, wl)
     n, p, k = W.n, W.p, W.k
     rng = np.random.default_rng([7, 0x70726F])
-    probe = torch.from_numpy(rng.standard_normal((p, 4)) / np.sqrt(p)).cuda()
+    probe = (torch.from_numpy(rng.standard_normal((p, 4)) / np.sqrt(p)).cuda(),
+             torch.from_numpy(rng.standard_normal((n, 4)) / np.sqrt(n)).cuda())
     ref = fp64_solve(gk, torch, W, wl["tol"], args.steps, args.warmup, stream,
                      probe=None if args.no_compare else probe)
     infos = ref["infos"]
     sec_per_step = ref["sec_per_step"]
     nbytes = fp64_bytes(n, p)
-    prod = product_stats(infos, nbytes)
+    last = infos[-1]
+    products = FORMAT_NAMES.get(int(last.fp64_products), "?")
+    prod = product_stats(infos, nbytes, products)
     dom = max(prod, key=lambda key: prod[key]["total_ms"])
     other = [key for key in prod if key != dom][0]
     dom_avg = prod[dom]["avg_ms"]
     achieved = nbytes / (dom_avg * 1e-3) / 1e9
-    last = infos[-1]
     line = {
         "metric": METRIC,
         "value": sec_per_step,
@@ -495,7 +640,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": wl["desc"], "n": n, "p": p, "k": k, "tol": wl["tol"],
-                   "reorth": wl["reorth"], "krylov_dim": wl["krylov_dim"],
+                   "reorth": wl["reorth"], "krylov_dim": wl["krylov_dim"], "fp64_products": products,
                    "packed_bytes": int(W.g.nbytes)},
         "solve_s": float(np.mean([i.solve_ms for i in infos])) / 1e3,
         "create_s": float(np.mean([i.create_ms for i in infos])) / 1e3,
@@ -504,8 +649,8 @@ def main():
         "reorth_passes": int(last.reorths),
         "converged": int(last.converged),
         "max_residual_rel": last.max_residual_rel,
-        "matvec_GBps": prod["matvec_kernel (A v)"]["GBps"],
-        "rmatvec_GBps": prod["rmatvec_kernel (A^T u)"]["GBps"],
+        "matvec_GBps": prod[KERNEL_NAMES[products][0]]["GBps"],
+        "rmatvec_GBps": prod[KERNEL_NAMES[products][1]]["GBps"],
         "roofline": {
             "kernel": dom,
             "bound": "hbm",
@@ -542,8 +687,15 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_extra and args.workload != "c2":
         line["c2"] = run_extra(gk, torch, "c2", args, stream)
-    if not args.no_batched:
-        line["batched"] = run_batched(gk, torch, args)
+    if not args.no_extra:
+        line["paper_model"] = run_paper_model(gk, torch, args, stream)
+    if not (args.no_batched and args.no_loco):
+        gs = chromosome_blocks()
+        if not args.no_batched:
+            line["batched"] = run_batched(gk, torch, gs, args)
+        if not args.no_loco:
+            line["loco"] = run_loco(gk, torch, gs, args)
+        del gs
     torch.cuda.synchronize()
     print(json.dumps(line), flush=True)
     reap_children()

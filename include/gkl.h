@@ -84,6 +84,22 @@ enum gkl_reorth { GKL_REORTH_FULL = 0, GKL_REORTH_PARTIAL = 1, GKL_REORTH_ONESID
  * (power-of-two column scale) in three 8-bit limbs and accumulated exactly in
  * int32, so the products' only rounding is that quantisation. */
 enum gkl_precision { GKL_PREC_FP64 = 0, GKL_PREC_MIXED = 1, GKL_PREC_MIXED_INT8 = 2 };
+/* How a GKL_PREC_FP64 context forms its products A v and A^T u (Section 3: one
+ * of each per Lanczos step).  Both are FP64-accurate and pass the same parity
+ * tests.  GKL_FP64_LUT: 256-entry FP64 tables per four genotypes in LDS, one
+ * table read and one FP64 add per byte.  GKL_FP64_LIMBS: the int8 matrix cores
+ * with the vector scaled by a power of two at least its largest magnitude,
+ * rounded to a 52-bit integer and split into seven 8-bit limbs; the limb sums
+ * are exact and recombined in FP64, so the product carries the vector's
+ * quantisation (at most 2^-53 of that scale per entry) and FP64 roundings only.
+ * GKL_FP64_LUT_LIMBS: tables for A v, limbs for A^T u -- the faster form of
+ * each as measured (50,000 x 500,000: A v 1.29 ms from the tables against 1.39
+ * ms in limbs, A^T u 2.09 ms against 1.19 ms).  GKL_FP64_AUTO: LUT_LIMBS when
+ * n p >= 4e9 (1 GB packed), else LUT (at 10,000 x 100,000 the two A^T u forms
+ * are within 5% and the limbs add two small kernels per product). */
+enum gkl_fp64_products {
+    GKL_FP64_AUTO = 0, GKL_FP64_LUT = 1, GKL_FP64_LIMBS = 2, GKL_FP64_LUT_LIMBS = 3
+};
 
 /* Options.  Always initialise with gkl_options_default(). */
 typedef struct gkl_options {
@@ -117,6 +133,8 @@ typedef struct gkl_options {
                                  create and keep the fastest; 0 = fixed geometry */
     int32_t graph;            /* batched: 1 (default) = each Lanczos step is one HIP
                                  graph launch; 0 = the same kernels launched one by one */
+    int32_t fp64_products;    /* gkl_fp64_products (GKL_PREC_FP64 single-problem
+                                 contexts; the batched path uses the tables) */
 } gkl_options;
 
 /* Run statistics (host struct). */
@@ -141,6 +159,10 @@ typedef struct gkl_info {
                                  split, column sums, the matrix-core kernel, reduce);
                                  equal to matvec_kernel_ms on the FP64 path */
     double rmatvec_core_ms;   /* likewise for the A^T u / A^T X products */
+    int32_t fp64_products;    /* format the FP64 products ran in: GKL_FP64_LUT,
+                                 _LIMBS or _LUT_LIMBS (0 on the blocked and batched
+                                 paths) */
+    int32_t reserved;
 } gkl_info;
 
 void gkl_options_default(gkl_options* opt);
@@ -155,7 +177,8 @@ const char* gkl_last_error(const gkl_ctx* ctx);
  *   device and allocate the solver workspace for a top-k solve (the paper's
  *   preprocessing, whose content it leaves open: Section 4, Table 2 gives its
  *   time only; the standardisation above is this library's reading).  An FP64
- *   context builds the two lookup-table layouts of its products, a blocked one
+ *   context builds one internal copy of G per product in the format that
+ *   options.fp64_products selects (about n p / 4 bytes each), a blocked one
  *   (GKL_PREC_MIXED*) the two layouts of its matrix-core products.
  *   G      device, p*ld bytes, SNP-major 2-bit codes (see above), borrowed.
  *   n, p   individuals and SNPs, both >= 1.
@@ -256,8 +279,9 @@ gkl_status gkl_column_stats(gkl_ctx* ctx, int64_t* count, int64_t* nobs, double*
  * Any context kind (it reads G, which the context borrows). */
 gkl_status gkl_unpack(gkl_ctx* ctx, int8_t* out);
 /* y = A v (v: p values, y: n values) in FP64: the product every Lanczos step
- * applies (Section 3).  Needs a GKL_PREC_FP64 context (its lookup-table
- * layouts); a blocked context gives GKL_ERR_INVALID. */
+ * applies (Section 3), in the context's options.fp64_products format.  Needs a
+ * GKL_PREC_FP64 context (its product layouts); a blocked context gives
+ * GKL_ERR_INVALID. */
 gkl_status gkl_matvec(gkl_ctx* ctx, const double* v, double* y);
 /* z = A^T u (u: n values, z: p values) in FP64; GKL_PREC_FP64 context only. */
 gkl_status gkl_rmatvec(gkl_ctx* ctx, const double* u, double* z);

@@ -23,6 +23,10 @@ GKL_REORTH_ONESIDED = 2
 GKL_PREC_FP64 = 0
 GKL_PREC_MIXED = 1
 GKL_PREC_MIXED_INT8 = 2
+GKL_FP64_AUTO = 0
+GKL_FP64_LUT = 1
+GKL_FP64_LIMBS = 2
+GKL_FP64_LUT_LIMBS = 3
 GKL_TRACE_FIELDS = 7
 
 
@@ -47,6 +51,7 @@ class gkl_options(ctypes.Structure):
         ("timing", ctypes.c_int32),
         ("autotune", ctypes.c_int32),
         ("graph", ctypes.c_int32),
+        ("fp64_products", ctypes.c_int32),
     ]
 
 
@@ -69,6 +74,8 @@ class gkl_info(ctypes.Structure):
         ("timed_rmatvecs", ctypes.c_int64),
         ("matvec_core_ms", ctypes.c_double),
         ("rmatvec_core_ms", ctypes.c_double),
+        ("fp64_products", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
     def as_dict(self):

@@ -443,7 +443,7 @@ gkl_status gkl_create_batched(int32_t count, const uint8_t* const* G, const int6
             B.probs.emplace_back(new BatchProblem());
             BatchProblem& P = *B.probs.back();
             const int64_t ld = o->ld_bytes ? o->ld_bytes : (n[q] + 3) / 4;
-            P.prob.setup(G[q], n[q], p[q], ld, s, true);
+            P.prob.setup(G[q], n[q], p[q], ld, s, 1);
             P.cap = std::min(n[q], p[q]);
             B.max_n = std::max(B.max_n, n[q]);
             B.max_p = std::max(B.max_p, p[q]);
@@ -531,7 +531,7 @@ gkl_status gkl_create_loco(const uint8_t* G, int64_t n, int64_t p, int32_t nbloc
         hipStream_t s = B.stream;
         batch_basis(B, o, k, mn);
         const int64_t ld = o->ld_bytes ? o->ld_bytes : (n + 3) / 4;
-        B.shared.setup(G, n, p, ld, s, false);
+        B.shared.setup(G, n, p, ld, s, 0);
         B.max_n = n;
         B.max_p = p;
         DeviceArena& A = B.arena;

@@ -30,7 +30,9 @@ struct Problem {
     ColStats st{};
     MatvecWork mvw;
     // lut_layouts: build the two lookup-table layouts of the FP64 products
-    void setup(const uint8_t* G, int64_t n, int64_t p, int64_t ld, hipStream_t s, bool lut_layouts);
+    // products: 0 = none (the blocked path builds its own layouts), 1 = lookup
+    // tables (layouts T and P), 2 = seven int8 limbs (layouts I and S)
+    void setup(const uint8_t* G, int64_t n, int64_t p, int64_t ld, hipStream_t s, int products);
 };
 
 // ||r|| into *out (no scaling).

@@ -61,7 +61,7 @@ DeviceArena::~DeviceArena()
 // Problem setup
 // ---------------------------------------------------------------------------
 void Problem::setup(const uint8_t* G, int64_t n_, int64_t p_, int64_t ld_, hipStream_t s,
-                    bool lut_layouts)
+                    int products)
 {
     n = n_;
     p = p_;
@@ -69,10 +69,30 @@ void Problem::setup(const uint8_t* G, int64_t n_, int64_t p_, int64_t ld_, hipSt
     G_user = G;
     stream = s;
     layout_shape(n, p, packed);
-    if (lut_layouts) {
-        packed.T = static_cast<uint8_t*>(arena.alloc(layout_T_bytes(packed)));
-        packed.P = static_cast<uint8_t*>(arena.alloc(layout_P_bytes(packed)));
+    if (products != 0) {
+        // 1: tables for both products, 2: limbs for both, 3: tables for A v and
+        // limbs for A^T u
+        packed.limb_mv = products == 2;
+        packed.limb_rmv = products >= 2;
+        if (!packed.limb_mv) packed.T = static_cast<uint8_t*>(arena.alloc(layout_T_bytes(packed)));
+        if (!packed.limb_rmv) packed.P = static_cast<uint8_t*>(arena.alloc(layout_P_bytes(packed)));
         build_layouts(G, ld, packed, s);
+        if (packed.limb_mv || packed.limb_rmv) {
+            packed.ms = mixed_shape(n, p);
+            const MixedShape& m = packed.ms;
+            uint8_t* I = packed.limb_mv
+                             ? static_cast<uint8_t*>(arena.alloc((size_t)m.nI * (size_t)m.ldI))
+                             : nullptr;
+            uint8_t* S = packed.limb_rmv
+                             ? static_cast<uint8_t*>(arena.alloc((size_t)m.pS * (size_t)m.ldS))
+                             : nullptr;
+            build_mixed_layouts(G, n, p, ld, I, S, s);
+            packed.I = I;
+            packed.S = S;
+            mvw.lfrag = arena.alloc(limb_frag_bytes(m));
+            mvw.lcpart = static_cast<double*>(arena.alloc(sizeof(double) * 64));
+            mvw.lcmax = static_cast<double*>(arena.alloc(sizeof(double) * 64));
+        }
     }
     st.count = static_cast<int64_t*>(arena.alloc(sizeof(int64_t) * p));
     st.nobs = static_cast<int64_t*>(arena.alloc(sizeof(int64_t) * p));
@@ -80,7 +100,7 @@ void Problem::setup(const uint8_t* G, int64_t n_, int64_t p_, int64_t ld_, hipSt
     st.mean = static_cast<double*>(arena.alloc(sizeof(double) * p));
     st.inv_sd = static_cast<double*>(arena.alloc(sizeof(double) * p));
     launch_colstats(G, n, p, ld, st, s);
-    if (!lut_layouts) return;
+    if (products == 0) return;
     mvw.partial_elems = matvec_partial_elems(packed);
     mvw.partial = static_cast<double*>(arena.alloc(sizeof(double) * mvw.partial_elems));
     mvw.ncounters = matvec_counters(packed);
@@ -654,6 +674,19 @@ gkl_status gkl_create(const uint8_t* G, int64_t n, int64_t p, int32_t k, double 
     return gkl_create_ex(G, n, p, k, tol, reorth, &o, out);
 }
 
+// Product format of an FP64 context: 1 = lookup tables, 2 = int8 limbs.
+static int fp64_products_for(int64_t n, int64_t p, int32_t choice)
+{
+    if (choice == GKL_FP64_LUT) return 1;
+    if (choice == GKL_FP64_LIMBS) return 2;
+    // GKL_FP64_AUTO: from 1 GB of packed genotypes on, A v from the tables and
+    // A^T u on the int8 matrix cores, the faster form of each (50,000 x 500,000:
+    // A v 1.29 ms against 1.39 ms in limbs, A^T u 2.09 ms against 1.19 ms);
+    // below that the tables for both (10,000 x 100,000: A^T u 96 us against 92
+    // us in limbs plus the two small kernels that quantise the vector)
+    return (double)n * (double)p >= 4e9 ? 3 : 1;
+}
+
 static gkl_status validate(const uint8_t* G, int64_t n, int64_t p, int32_t k, double tol,
                            int32_t reorth, const gkl_options* o, gkl_ctx** out)
 {
@@ -684,6 +717,8 @@ static gkl_status validate(const uint8_t* G, int64_t n, int64_t p, int32_t k, do
     if (o->max_steps < 0 || o->max_steps > kMaxSvd || o->check_every < 0 || o->max_matvecs < 0)
         return set_error(nullptr, GKL_ERR_INVALID, "bad max_steps / check_every / max_matvecs");
     if (o->pro_omega < 0.0) return set_error(nullptr, GKL_ERR_INVALID, "pro_omega must be >= 0");
+    if (o->fp64_products < GKL_FP64_AUTO || o->fp64_products > GKL_FP64_LUT_LIMBS)
+        return set_error(nullptr, GKL_ERR_INVALID, "unknown fp64_products");
     if (reorth == GKL_REORTH_ONESIDED && o->precision != GKL_PREC_FP64)
         return set_error(nullptr, GKL_ERR_UNSUPPORTED,
                          "one-sided reorthogonalisation is built for the FP64 path only");
@@ -710,7 +745,7 @@ gkl_status gkl_create_ex(const uint8_t* G, int64_t n, int64_t p, int32_t k, doub
         ctx->omega = o->pro_omega > 0.0 ? o->pro_omega : 1e-8;
         hipStream_t s = static_cast<hipStream_t>(o->stream);
         const int64_t ld = o->ld_bytes ? o->ld_bytes : (n + 3) / 4;
-        ctx->prob.setup(G, n, p, ld, s, !blocked);
+        ctx->prob.setup(G, n, p, ld, s, blocked ? 0 : fp64_products_for(n, p, o->fp64_products));
         ctx->root_maxdim = sqrt((double)std::max(n, p));
         ctx->noise_scale = 2.220446049250313e-16 * ctx->root_maxdim;
         ctx->krylov = o->krylov_dim;
@@ -763,6 +798,10 @@ gkl_status gkl_solve(gkl_ctx* ctx, double* sigma, double* U, int64_t ldu, double
         ctx->info.solve_ms =
             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         ctx->info.create_ms = ctx->create_ms;
+        if (ctx->opt.precision == GKL_PREC_FP64)
+            ctx->info.fp64_products = ctx->prob.packed.limb_mv    ? GKL_FP64_LIMBS
+                                      : ctx->prob.packed.limb_rmv ? GKL_FP64_LUT_LIMBS
+                                                                  : GKL_FP64_LUT;
         ctx->timing_collect();
         if (info) *info = ctx->info;
         if (st == GKL_NOT_CONVERGED) ctx->last_error = "tolerance not met within the matvec budget";
@@ -817,7 +856,8 @@ gkl_status gkl_unpack(gkl_ctx* ctx, int8_t* out)
 gkl_status gkl_matvec(gkl_ctx* ctx, const double* v, double* y)
 {
     if (!ctx || ctx->batched || !v || !y) return set_error(ctx, GKL_ERR_INVALID, "bad argument");
-    if (!ctx->prob.packed.T) return set_error(ctx, GKL_ERR_INVALID, "FP64 products need an FP64 context");
+    if (ctx->opt.precision != GKL_PREC_FP64 || ctx->batched)
+        return set_error(ctx, GKL_ERR_INVALID, "FP64 products need an FP64 context");
     try {
         hipStream_t s = ctx->prob.stream;
         const int ev = ctx->timing_slot(false);
@@ -834,7 +874,8 @@ gkl_status gkl_matvec(gkl_ctx* ctx, const double* v, double* y)
 gkl_status gkl_rmatvec(gkl_ctx* ctx, const double* u, double* z)
 {
     if (!ctx || ctx->batched || !u || !z) return set_error(ctx, GKL_ERR_INVALID, "bad argument");
-    if (!ctx->prob.packed.T) return set_error(ctx, GKL_ERR_INVALID, "FP64 products need an FP64 context");
+    if (ctx->opt.precision != GKL_PREC_FP64 || ctx->batched)
+        return set_error(ctx, GKL_ERR_INVALID, "FP64 products need an FP64 context");
     try {
         hipStream_t s = ctx->prob.stream;
         const int ev = ctx->timing_slot(true);

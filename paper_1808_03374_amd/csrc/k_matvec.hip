@@ -136,10 +136,13 @@ void build_layouts(const uint8_t* G, int64_t ld, const Packed& L, hipStream_t s)
     const int64_t n = L.n, p = L.p;
     uint8_t* T = const_cast<uint8_t*>(L.T);
     uint8_t* P = const_cast<uint8_t*>(L.P);
-    const int64_t tT = (L.nT / 4) * L.Pq;
-    hipLaunchKernelGGL(build_T_kernel, dim3(stride_grid(tT, 256)), dim3(256), 0, s, G, n, p, ld, T,
-                       L.nT, L.Pq);
-    GKL_LAUNCH_CHECK("build_T_kernel");
+    if (T) {
+        const int64_t tT = (L.nT / 4) * L.Pq;
+        hipLaunchKernelGGL(build_T_kernel, dim3(stride_grid(tT, 256)), dim3(256), 0, s, G, n, p, ld,
+                           T, L.nT, L.Pq);
+        GKL_LAUNCH_CHECK("build_T_kernel");
+    }
+    if (!P) return;
     int64_t done = 0;
     const int64_t ytiles = (L.nqP + 63) / 64;
     while (done < ytiles) {   // grid.y <= 65535
@@ -485,8 +488,10 @@ Split rmv_split(const Packed& L, int64_t target = kSplitTarget)
 
 size_t matvec_partial_elems(const Packed& L)
 {
-    const size_t a = (size_t)mv_split(L).nsplit * (size_t)L.nT;
-    const size_t b = (size_t)rmv_split(L).nsplit * (size_t)L.pP;
+    const size_t a = L.limb_mv ? (size_t)L.ms.limbW.nsplit * (size_t)L.ms.nI
+                               : (size_t)mv_split(L).nsplit * (size_t)L.nT;
+    const size_t b = L.limb_rmv ? (size_t)L.ms.limbX.nsplit * (size_t)L.ms.pS
+                                : (size_t)rmv_split(L).nsplit * (size_t)L.pP;
     return a > b ? a : b;
 }
 
@@ -508,6 +513,15 @@ void launch_matvec(const Packed& L, const ColStats& st, const double* v, double*
                    const double* beta, const double* uprev, MatvecWork& w, hipStream_t s,
                    const NormTail* tail, const hipEvent_t* ev)
 {
+    if (L.limb_mv) {
+        const int nsplit = launch_matvec_limb(L.ms, L.I, st, v, w, s, ev);
+        hipLaunchKernelGGL(matvec_reduce_kernel, dim3(ceil_div(L.n, kRedRows)),
+                           dim3(kRedRows * kRedGroups), 0, s, w.partial, L.ms.nI, nsplit, L.n, y,
+                           beta, uprev, tail ? w.npart : nullptr);
+        GKL_LAUNCH_CHECK("matvec_reduce_kernel");
+        if (tail) launch_norm_pro(tail, w, (int)ceil_div(L.n, kRedRows), s);
+        return;
+    }
     const Split sp = mv_split(L);
     dim3 grid((unsigned int)((L.nT + kRowsPerBlock - 1) / kRowsPerBlock), (unsigned int)sp.nsplit);
     if (ev) GKL_HIP(hipEventRecord(ev[0], s));
@@ -526,6 +540,16 @@ void launch_rmatvec(const Packed& L, const ColStats& st, const double* u, double
                     const double* alpha, const double* vprev, MatvecWork& w, hipStream_t s,
                     const NormTail* tail, const hipEvent_t* ev)
 {
+    unsigned int nb = ceil_div(L.p, 256);
+    if (nb > kRmvReduceBlocks) nb = kRmvReduceBlocks;
+    if (L.limb_rmv) {
+        const int nsplit = launch_rmatvec_limb(L.ms, L.S, st, u, w, s, ev);
+        hipLaunchKernelGGL(rmatvec_reduce_kernel, dim3(nb), dim3(256), 0, s, w.partial, L.ms.pS,
+                           nsplit, L.p, st.inv_sd, z, alpha, vprev, tail ? w.npart : nullptr);
+        GKL_LAUNCH_CHECK("rmatvec_reduce_kernel");
+        if (tail) launch_norm_pro(tail, w, (int)nb, s);
+        return;
+    }
     const Split sp = rmv_split(L);
     dim3 grid((unsigned int)((L.pP + kRmvCols - 1) / kRmvCols), (unsigned int)sp.nsplit);
     if (ev) GKL_HIP(hipEventRecord(ev[0], s));
@@ -533,8 +557,6 @@ void launch_rmatvec(const Packed& L, const ColStats& st, const double* u, double
                        u, st.mean, sp.per_split, w.partial);
     GKL_LAUNCH_CHECK("rmatvec_lut_kernel");
     if (ev) GKL_HIP(hipEventRecord(ev[1], s));
-    unsigned int nb = ceil_div(L.p, 256);
-    if (nb > kRmvReduceBlocks) nb = kRmvReduceBlocks;
     hipLaunchKernelGGL(rmatvec_reduce_kernel, dim3(nb), dim3(256), 0, s, w.partial, L.pP,
                        sp.nsplit, L.p, st.inv_sd, z, alpha, vprev, tail ? w.npart : nullptr);
     GKL_LAUNCH_CHECK("rmatvec_reduce_kernel");

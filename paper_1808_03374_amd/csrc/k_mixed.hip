@@ -147,14 +147,18 @@ void build_mixed_layouts(const uint8_t* G, int64_t n, int64_t p, int64_t ld, uin
 {
     const int64_t nI = mixed_rows_I(n), ldI = mixed_ld_I(p);
     const int64_t pS = mixed_rows_S(p), ldS = mixed_ld_S(n);
-    const int64_t tI = (nI / 4) * ldI;
-    hipLaunchKernelGGL(build_I_kernel, dim3(stride_grid(tI, 256)), dim3(256), 0, s, G, n, p, ld, I,
-                       nI, ldI);
-    GKL_LAUNCH_CHECK("build_I_kernel");
-    const int64_t tS = pS * ldS;
-    hipLaunchKernelGGL(build_S_kernel, dim3(stride_grid(tS, 256)), dim3(256), 0, s, G, n, p, ld, S,
-                       pS, ldS);
-    GKL_LAUNCH_CHECK("build_S_kernel");
+    if (I) {
+        const int64_t tI = (nI / 4) * ldI;
+        hipLaunchKernelGGL(build_I_kernel, dim3(stride_grid(tI, 256)), dim3(256), 0, s, G, n, p, ld,
+                           I, nI, ldI);
+        GKL_LAUNCH_CHECK("build_I_kernel");
+    }
+    if (S) {
+        const int64_t tS = pS * ldS;
+        hipLaunchKernelGGL(build_S_kernel, dim3(stride_grid(tS, 256)), dim3(256), 0, s, G, n, p, ld,
+                           S, pS, ldS);
+        GKL_LAUNCH_CHECK("build_S_kernel");
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1069,6 +1073,235 @@ rmatmat_i8_reduce_kernel(const double* __restrict__ partial, int nsplit, int64_t
 }
 
 // ---------------------------------------------------------------------------
+// FP64 single-vector products in seven int8 limbs
+// ---------------------------------------------------------------------------
+// The FP64 path's A v and A^T u on the int8 matrix cores, as the limb products
+// above but with one vector carried to FP64 accuracy.  The vector is scaled by
+// a power of two 2^ex at least its largest magnitude (for A v the largest of
+// the missing-term vector z = (mu - 3) s v, which bounds |s v| and shares the
+// scale), rounded to an integer q with |q| <= 2^52 -- the rounding is at most
+// half a unit of 2^(ex - 52), the last place of a double at the scale -- and q
+// is split into seven balanced 8-bit limbs, q = sum_l l_l 2^(8 (6 - l)).
+// Column l < 7 of the B operand holds limb l; columns 7..15 are zero.
+// v_mfma_i32_16x16x64_i8 adds every limb sum exactly (|code x limb| + |flag x
+// limb| <= 512 per contraction index; a K split of at most 2^20 indices keeps
+// every limb sum below 2^29), the recombination
+//   S = (l0 2^24 + l1 2^16 + l2 2^8 + l3) 2^24 + (l4 2^16 + l5 2^8 + l6)
+// is exact up to its last addition (both brackets are integers below 2^53), so
+// each split's partial carries one FP64 rounding besides the quantisation of
+// the vector: the accuracy of a plain FP64 sum.
+//   (A v)_i   = 2^(ex - 52) (sum_j c_ij q(s v)_j + sum_j m_ij q(z)_j) - sum_j mu_j s_j v_j
+//   (A^T u)_j = s_j ( 2^(ex - 52) (SC_j + (mu_j - 3) SM_j) - mu_j sum_i u_i ),
+//               SC_j = sum_i c_ij q(u)_i, SM_j = sum_i m_ij q(u)_i
+// The mean terms are added by split 0; the FP64 reduce kernels add the splits,
+// scale by s_j (A^T u) and apply the Lanczos recurrence term.
+constexpr int kLimbs = 7;
+constexpr int kQ64 = 52;
+constexpr int64_t kLimbMaxSt = ((int64_t)1 << 20) / kSuper;   // super-tiles per K split
+constexpr int kRTv = 8;    // A v: row tiles per wave (512 rows per workgroup)
+constexpr int kRTu = 4;    // A^T u: row tiles per wave (256 rows per workgroup)
+
+// Limb l (0 = most significant) of q.
+__device__ __forceinline__ int limb_of(int64_t q, int l)
+{
+    int out = 0;
+#pragma unroll
+    for (int k = kLimbs - 1; k >= 1; --k) {
+        const int d = (int)(((q + 128) & 255) - 128);
+        q = (q - d) >> 8;
+        if (k == l) out = d;
+    }
+    return l == 0 ? (int)q : out;
+}
+
+__device__ __forceinline__ int64_t quantise52(double x, int ex)
+{
+    return (int64_t)rint(ldexp(x, kQ64 - ex));
+}
+
+// B operands of A v: frag[((st * kWords + word) * 2 + op) * 64 + lane], op 0 =
+// limbs of s v, op 1 = limbs of z; byte e of lane (g, col) holds SNP st*256 +
+// 64 g + 16 word + code_of_elem(e), limb col (zero for col >= 7).
+__global__ void __launch_bounds__(256)
+limb_v_kernel(const double* __restrict__ v, int64_t p, const double* __restrict__ mean,
+              const double* __restrict__ inv_sd, const double* __restrict__ cmax, int64_t nst,
+              i32x4* __restrict__ frag)
+{
+    __shared__ int ex[1];
+    column_scales(cmax, 1, ex);
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // (st, word, lane)
+    if (t >= nst * kWords * 64) return;
+    const int lane = (int)(t & 63);
+    const int word = (int)((t >> 6) % kWords);
+    const int64_t st = t / (64 * kWords);
+    const int g = lane >> 4, col = lane & 15;
+    const int e0 = ex[0];
+    i32x4 fw = {0, 0, 0, 0}, fz = {0, 0, 0, 0};
+    if (col < kLimbs) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int64_t j = st * kSuper + 64 * g + 16 * word + code_of_elem(e);
+            double w = 0.0, z = 0.0;
+            if (j < p) {
+                w = inv_sd[j] * v[j];
+                z = (mean[j] - 3.0) * w;
+            }
+            put_byte(fw, e, limb_of(quantise52(w, e0), col));
+            put_byte(fz, e, limb_of(quantise52(z, e0), col));
+        }
+    }
+    i32x4* f = frag + ((st * kWords + word) * 2) * 64 + lane;
+    f[0] = fw;
+    f[64] = fz;
+}
+
+// B operand of A^T u: frag[(st * kWords + word) * 64 + lane]; byte e of lane
+// (g, col) holds individual st*256 + 64 g + 16 word + code_of_elem(e), limb col.
+__global__ void __launch_bounds__(256)
+limb_u_kernel(const double* __restrict__ u, int64_t n, const double* __restrict__ cmax,
+              int64_t nst, i32x4* __restrict__ frag)
+{
+    __shared__ int ex[1];
+    column_scales(cmax, 1, ex);
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nst * kWords * 64) return;
+    const int lane = (int)(t & 63);
+    const int word = (int)((t >> 6) % kWords);
+    const int64_t st = t / (64 * kWords);
+    const int g = lane >> 4, col = lane & 15;
+    const int e0 = ex[0];
+    i32x4 fx = {0, 0, 0, 0};
+    if (col < kLimbs) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int64_t i = st * kSuper + 64 * g + 16 * word + code_of_elem(e);
+            const double x = i < n ? u[i] : 0.0;
+            put_byte(fx, e, limb_of(quantise52(x, e0), col));
+        }
+    }
+    frag[(st * kWords + word) * 64 + lane] = fx;
+}
+
+// Element e of accumulator a recombined from the seven limb columns of the
+// lane's 16-lane group (every lane calls it; the value is that of its group).
+__device__ __forceinline__ double limb_sum(const i32x4& a, int e, int lane)
+{
+    int32_t l[kLimbs];
+#pragma unroll
+    for (int k = 0; k < kLimbs; ++k) l[k] = __shfl(a[e], (lane & 48) + k, 64);
+    const int64_t hi = ((int64_t)l[0] << 24) + ((int64_t)l[1] << 16) + ((int64_t)l[2] << 8) + l[3];
+    const int64_t lo = ((int64_t)l[4] << 16) + ((int64_t)l[5] << 8) + l[6];
+    return (double)hi * 16777216.0 + (double)lo;
+}
+
+// Main kernel.  kAv: A v over layout I (rows = individuals, K = SNPs), one
+// accumulator per row tile fed by the code operand with the limbs of s v and
+// the missing operand with the limbs of z.  Otherwise A^T u over layout S
+// (rows = SNPs, K = individuals), a code and a missing accumulator sharing the
+// limbs of u.  Workgroup = 4 waves x kRT row tiles of 16 rows; the K range of
+// one split is walked in super-tiles of 256, the next super-tile's codes and
+// fragments loaded while the current one is multiplied (fragments double
+// buffered in LDS, one barrier per super-tile).  partial[split * rows_pad +
+// row] = the split's share of the product (before s_j for A^T u).
+template <bool kAv>
+__global__ void __launch_bounds__(256)
+limb_product_kernel(const uint8_t* __restrict__ L, int64_t ldL, int64_t rows_pad, int64_t rows,
+                    const i32x4* __restrict__ frag, int64_t nst, int64_t st_per, int nsplit,
+                    int nrb, int xcd, const double* __restrict__ cpart,
+                    const double* __restrict__ cmax, const double* __restrict__ mean,
+                    double* __restrict__ partial)
+{
+    constexpr int kRT = kAv ? kRTv : kRTu;
+    constexpr int kOps = kAv ? 2 : 1;
+    constexpr int kAcc = kAv ? 1 : 2;
+    constexpr int kFr = kWords * kOps * 64;     // fragments per super-tile
+    constexpr int kFrT = kFr / 256;             // per thread
+    __shared__ i32x4 bs[2][kFr];
+    __shared__ double ksum[1];
+    __shared__ int ex[1];
+    column_sums(cpart, 1, ksum);
+    column_scales(cmax, 1, ex);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int g = lane >> 4, r = lane & 15;
+    int split, rb;
+    block_coords(blockIdx.x, nsplit, nrb, xcd, split, rb);
+    const int64_t row_base = (int64_t)rb * (kMxWaves * kRT * 16) + wave * (kRT * 16);
+    const int64_t st0 = (int64_t)split * st_per;
+    const int64_t st1 = st0 + st_per < nst ? st0 + st_per : nst;
+    i32x4 acc[kRT][kAcc];
+#pragma unroll
+    for (int t = 0; t < kRT; ++t)
+#pragma unroll
+        for (int q = 0; q < kAcc; ++q) acc[t][q] = i32x4{0, 0, 0, 0};
+    uint4 a[kRT];
+    if (st0 < st1) {
+#pragma unroll
+        for (int t = 0; t < kRT; ++t)
+            a[t] = *reinterpret_cast<const uint4*>(
+                L + tiled_offset(row_base + 16 * t + r, st0 * 64 + 16 * g, ldL));
+#pragma unroll
+        for (int k = 0; k < kFrT; ++k) bs[0][threadIdx.x + 256 * k] = frag[st0 * kFr + threadIdx.x + 256 * k];
+    }
+    __syncthreads();
+    int buf = 0;
+    for (int64_t st = st0; st < st1; ++st) {
+        const int64_t stn = st + 1 < st1 ? st + 1 : st;
+        uint4 an[kRT];
+#pragma unroll
+        for (int t = 0; t < kRT; ++t)
+            an[t] = *reinterpret_cast<const uint4*>(
+                L + tiled_offset(row_base + 16 * t + r, stn * 64 + 16 * g, ldL));
+        i32x4 fr[kFrT];
+#pragma unroll
+        for (int k = 0; k < kFrT; ++k) fr[k] = frag[stn * kFr + threadIdx.x + 256 * k];
+#pragma unroll
+        for (int w = 0; w < kWords; ++w) {
+            const i32x4 b0 = bs[buf][(w * kOps) * 64 + lane];
+            const i32x4 b1 = kAv ? bs[buf][(w * kOps + 1) * 64 + lane] : b0;
+#pragma unroll
+            for (int t = 0; t < kRT; ++t) {
+                const uint32_t d = w == 0 ? a[t].x : w == 1 ? a[t].y : w == 2 ? a[t].z : a[t].w;
+                const i32x4 ac = raw_codes(d), am = missing_flags(d);
+                if (kAv) {
+                    acc[t][0] = mfma_i8(ac, b0, acc[t][0]);
+                    acc[t][0] = mfma_i8(am, b1, acc[t][0]);
+                } else {
+                    acc[t][0] = mfma_i8(ac, b0, acc[t][0]);
+                    acc[t][kAcc - 1] = mfma_i8(am, b0, acc[t][kAcc - 1]);
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kFrT; ++k) bs[buf ^ 1][threadIdx.x + 256 * k] = fr[k];
+        __syncthreads();
+        buf ^= 1;
+#pragma unroll
+        for (int t = 0; t < kRT; ++t) a[t] = an[t];
+    }
+    double* out = partial + (int64_t)split * rows_pad;
+    const int e0 = ex[0];
+#pragma unroll
+    for (int t = 0; t < kRT; ++t) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t row = row_base + 16 * t + 4 * g + e;
+            double val;
+            if (kAv) {
+                val = ldexp(limb_sum(acc[t][0], e, lane), e0 - kQ64);
+                if (split == 0) val -= ksum[0];
+            } else {
+                const double sc = limb_sum(acc[t][0], e, lane);
+                const double sm = limb_sum(acc[t][kAcc - 1], e, lane);
+                const double mu = row < rows ? mean[row] : 0.0;
+                val = ldexp(sc + (mu - 3.0) * sm, e0 - kQ64);
+                if (split == 0) val -= mu * ksum[0];
+            }
+            if (r == 0) out[row] = val;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
 // K splits of a split-BF16 product over `rows` padded rows in workgroups of
@@ -1088,6 +1321,19 @@ static BfSplit bf16_split(int64_t rows, int wg_rows, int64_t nst, int64_t max_sp
     g.st_per = (nst + want - 1) / want;
     g.nsplit = (int)((nst + g.st_per - 1) / g.st_per);
     g.xcd = g.nsplit >= 8 && g.nsplit % 8 == 0 ? 1 : 0;
+    return g;
+}
+
+// The same for the FP64 limb products, with at most kLimbMaxSt super-tiles per split.
+static BfSplit limb_split(int64_t rows, int wg_rows, int64_t nst, int64_t max_split)
+{
+    const int64_t min_split = (nst + kLimbMaxSt - 1) / kLimbMaxSt;
+    BfSplit g = bf16_split(rows, wg_rows, nst, max_split > min_split ? max_split : min_split);
+    if (g.st_per > kLimbMaxSt) {
+        g.st_per = kLimbMaxSt;
+        g.nsplit = (int)((nst + g.st_per - 1) / g.st_per);
+        g.xcd = g.nsplit >= 8 && g.nsplit % 8 == 0 ? 1 : 0;
+    }
     return g;
 }
 
@@ -1119,6 +1365,10 @@ MixedShape mixed_shape(int64_t n, int64_t p)
     m.splitX = (int)((m.nstX + m.stX - 1) / m.stX);
     // split BF16, per column class (b <= 8: 8 partial columns, <= 16: 16, <= 32: 32)
     const int64_t mbytes = m.nI * m.ldI;
+    // FP64 limb products: partial traffic (8 B per row and split) at most 1/16
+    // of the matrix, K splits of at most 2^20 (exact limb sums)
+    m.limbW = limb_split(m.nI, kMxWaves * kRTv * 16, m.nstW, mbytes / (16 * 8 * m.nI));
+    m.limbX = limb_split(m.pS, kMxWaves * kRTu * 16, m.nstX, mbytes / (16 * 8 * m.pS));
     for (int c = 0; c < 3; ++c) {
         const int64_t kcs = c == 0 ? 8 : 16 * c;
         m.bfW[c] = bf16_split(m.nI, kMxWaves * kRTW * 16, m.nstW, mbytes / (4 * 2 * 8 * m.nI * kcs));
@@ -1147,6 +1397,56 @@ size_t mixed_partial_elems(const MixedShape& m)
         if (m.bfX[c].nsplit > 1) e = std::max(e, (size_t)m.bfX[c].nsplit * 2 * (size_t)m.pS * kcs);
     }
     return e;
+}
+
+size_t limb_frag_bytes(const MixedShape& m)
+{
+    return std::max((size_t)m.nstW * kWords * 2, (size_t)m.nstX * kWords) * 64 * sizeof(i32x4);
+}
+
+size_t limb_partial_elems(const MixedShape& m)
+{
+    return std::max((size_t)m.limbW.nsplit * (size_t)m.nI, (size_t)m.limbX.nsplit * (size_t)m.pS);
+}
+
+int launch_matvec_limb(const MixedShape& m, const uint8_t* I, const ColStats& st, const double* v,
+                       MatvecWork& w, hipStream_t s, const hipEvent_t* ev)
+{
+    const BfSplit& gm = m.limbW;
+    i32x4* frag = reinterpret_cast<i32x4*>(w.lfrag);
+    hipLaunchKernelGGL(colsum_kernel, dim3(kCsSplit, 1), dim3(256), 0, s, v, m.p, m.p, st.mean,
+                       st.inv_sd, 3.0, w.lcpart, w.lcmax);
+    GKL_LAUNCH_CHECK("colsum_kernel");
+    hipLaunchKernelGGL(limb_v_kernel, dim3(ceil_div(m.nstW * kWords * 64, 256)), dim3(256), 0, s, v,
+                       m.p, st.mean, st.inv_sd, w.lcmax, m.nstW, frag);
+    GKL_LAUNCH_CHECK("limb_v_kernel");
+    if (ev) GKL_HIP(hipEventRecord(ev[0], s));
+    hipLaunchKernelGGL(limb_product_kernel<true>, dim3((unsigned int)(gm.nsplit * gm.nrb)),
+                       dim3(256), 0, s, I, m.ldI, m.nI, m.n, frag, m.nstW, gm.st_per, gm.nsplit,
+                       gm.nrb, gm.xcd, w.lcpart, w.lcmax, st.mean, w.partial);
+    GKL_LAUNCH_CHECK("limb_product_kernel<A v>");
+    if (ev) GKL_HIP(hipEventRecord(ev[1], s));
+    return gm.nsplit;
+}
+
+int launch_rmatvec_limb(const MixedShape& m, const uint8_t* S, const ColStats& st, const double* u,
+                        MatvecWork& w, hipStream_t s, const hipEvent_t* ev)
+{
+    const BfSplit& gm = m.limbX;
+    i32x4* frag = reinterpret_cast<i32x4*>(w.lfrag);
+    hipLaunchKernelGGL(colsum_kernel, dim3(kCsSplit, 1), dim3(256), 0, s, u, m.n, m.n, nullptr,
+                       nullptr, 0.0, w.lcpart, w.lcmax);
+    GKL_LAUNCH_CHECK("colsum_kernel");
+    hipLaunchKernelGGL(limb_u_kernel, dim3(ceil_div(m.nstX * kWords * 64, 256)), dim3(256), 0, s, u,
+                       m.n, w.lcmax, m.nstX, frag);
+    GKL_LAUNCH_CHECK("limb_u_kernel");
+    if (ev) GKL_HIP(hipEventRecord(ev[0], s));
+    hipLaunchKernelGGL(limb_product_kernel<false>, dim3((unsigned int)(gm.nsplit * gm.nrb)),
+                       dim3(256), 0, s, S, m.ldS, m.pS, m.p, frag, m.nstX, gm.st_per, gm.nsplit,
+                       gm.nrb, gm.xcd, w.lcpart, w.lcmax, st.mean, w.partial);
+    GKL_LAUNCH_CHECK("limb_product_kernel<A^T u>");
+    if (ev) GKL_HIP(hipEventRecord(ev[1], s));
+    return gm.nsplit;
 }
 
 template <bool kPack, int kT>

@@ -14,6 +14,25 @@ struct ColStats {
     double* inv_sd;   // s_j
 };
 
+// K-split geometry of a matrix-core product: nsplit splits of st_per super-tiles,
+// nrb row blocks, xcd = 1 when the workgroups of one split share an XCD.
+struct BfSplit {
+    int nsplit = 1;
+    int64_t st_per = 1;
+    int nrb = 1;
+    int xcd = 0;
+};
+struct MixedShape {
+    int64_t n = 0, p = 0;
+    int64_t nI = 0, ldI = 0;      // layout I: rows (individuals, padded) and bytes per row
+    int64_t pS = 0, ldS = 0;      // layout S: rows (SNPs, padded) and bytes per row
+    int64_t nstW = 0, nstX = 0;   // 256-wide super-tiles along SNPs / individuals
+    int64_t stW = 0, stX = 0;     // super-tiles per K split
+    int splitW = 1, splitX = 1;
+    bool int8 = false;            // operand format: int8 limbs (true) or split BF16
+    BfSplit bfW[3], bfX[3];       // split BF16 by column class: b <= 8, <= 16, <= 32
+    BfSplit limbW, limbX;         // single-vector FP64 products in seven int8 limbs
+};
 // Internal copies of the genotype matrix, built once at create.  Padding codes
 // are 3 (missing), so padded individuals and SNPs contribute exactly zero
 // without masking in the hot loops.
@@ -21,18 +40,28 @@ struct ColStats {
 //      (feeds A v: one byte = four SNPs of one individual)
 //   P: nqP x pP bytes; P[I * pP + j] = codes of individuals 4I..4I+3 of SNP j
 //      (feeds A^T u: one byte = four individuals of one SNP)
+// With limb_mv (limb_rmv) set, A v (A^T u) runs on the int8 matrix cores
+// instead and reads the tiled layout I (S) of the blocked path (geometry ms);
+// T (P) is then not built.
 struct Packed {
     const uint8_t* T = nullptr;
     const uint8_t* P = nullptr;
     int64_t n = 0, p = 0;
     int64_t nT = 0, Pq = 0;       // rows (padded individuals), SNP quads of T
     int64_t pP = 0, nq = 0, nqP = 0;  // padded SNPs, individual quads (real, padded) of P
+    bool limb_mv = false, limb_rmv = false;
+    const uint8_t* I = nullptr;
+    const uint8_t* S = nullptr;
+    MixedShape ms;
 };
 
 // Device scratch used by the two-stage reductions of the matvec kernels.
 struct MatvecWork {
     double* partial = nullptr;        // split partials
     size_t partial_elems = 0;
+    void* lfrag = nullptr;            // limb products: B operand fragments of the vector
+    double* lcpart = nullptr;         // limb products: 64 chunk sums of the vector
+    double* lcmax = nullptr;          // limb products: 64 chunk maxima
     unsigned int* counters = nullptr; // zeroed, one per output block
     size_t ncounters = 0;
     double* npart = nullptr;          // per-block sums of squares for a NormTail
@@ -297,24 +326,6 @@ void launch_restart_scalars(const double* S, const double* P, int m, const doubl
                             int keep, double* theta, double* rho, hipStream_t s);
 
 // ---- k_mixed.hip: MFMA block products (split BF16 or int8 limbs) ----
-// K-split geometry of a split-BF16 product: nsplit splits of st_per super-tiles,
-// nrb row blocks, xcd = 1 when the workgroups of one split share an XCD.
-struct BfSplit {
-    int nsplit = 1;
-    int64_t st_per = 1;
-    int nrb = 1;
-    int xcd = 0;
-};
-struct MixedShape {
-    int64_t n = 0, p = 0;
-    int64_t nI = 0, ldI = 0;      // layout I: rows (individuals, padded) and bytes per row
-    int64_t pS = 0, ldS = 0;      // layout S: rows (SNPs, padded) and bytes per row
-    int64_t nstW = 0, nstX = 0;   // 256-wide super-tiles along SNPs / individuals
-    int64_t stW = 0, stX = 0;     // super-tiles per K split
-    int splitW = 1, splitX = 1;
-    bool int8 = false;            // operand format: int8 limbs (true) or split BF16
-    BfSplit bfW[3], bfX[3];       // split BF16 by column class: b <= 8, <= 16, <= 32
-};
 struct MixedWork {
     void* frag = nullptr;         // int8 limb fragments of the vector block
     double* partial = nullptr;
@@ -324,8 +335,19 @@ struct MixedWork {
 MixedShape mixed_shape(int64_t n, int64_t p);
 size_t mixed_frag_bytes(const MixedShape& m);
 size_t mixed_partial_elems(const MixedShape& m);
+// Either layout pointer may be NULL (that layout is not built).
 void build_mixed_layouts(const uint8_t* G, int64_t n, int64_t p, int64_t ld, uint8_t* I,
                          uint8_t* S, hipStream_t s);
+// FP64 A v and A^T u in seven int8 limbs (layouts I and S): the colsum,
+// fragment and matrix-core kernels, leaving per-split partials in w.partial
+// (stride ms.nI for A v, ms.pS for A^T u) in the form the FP64 reduce kernels
+// take.  Returns the number of K splits.
+size_t limb_frag_bytes(const MixedShape& m);
+size_t limb_partial_elems(const MixedShape& m);
+int launch_matvec_limb(const MixedShape& m, const uint8_t* I, const ColStats& st, const double* v,
+                       MatvecWork& w, hipStream_t s, const hipEvent_t* ev);
+int launch_rmatvec_limb(const MixedShape& m, const uint8_t* S, const ColStats& st, const double* u,
+                        MatvecWork& w, hipStream_t s, const hipEvent_t* ev);
 // Y (n x b, ldy) = A W (W: p x b, ldw); Z (p x b, ldz) = A^T X (X: n x b, ldx); b <= 32.
 // core_ev (optional): two events recorded around the matrix-core kernels
 void launch_matmat_mixed(const MixedShape& m, const uint8_t* I, const ColStats& st,

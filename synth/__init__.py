@@ -51,6 +51,8 @@ def _load():
             lib.synth_genotypes_range.restype = ctypes.c_int
             lib.synth_pack.argtypes = [i64, i64, i64, vp, i32, vp]
             lib.synth_pack.restype = ctypes.c_int
+            lib.synth_algorithm1.argtypes = [i64, i64, i64, vp, dbl, vp, u64, vp, i64, vp]
+            lib.synth_algorithm1.restype = ctypes.c_int
             _lib = lib
     return _lib
 
@@ -286,37 +288,61 @@ def spare_directions(p: int, count: int, seed: int) -> np.ndarray:
     return np.random.default_rng([seed, 0x62726B]).standard_normal((count, p))
 
 
+def _algorithm1_params(rows, cols, r, nsignal, rkins, seed):
+    """Rectangles, per-entry hit probability and row sources of the model."""
+    rng = np.random.default_rng([seed, 0xA161])
+    rb = np.sort(rng.integers(0, rows, size=(r, 2)), axis=1)
+    cb = np.sort(rng.integers(0, cols, size=(r, 2)), axis=1)
+    val = rng.integers(0, 3, size=r)
+    rect = np.ascontiguousarray(np.column_stack([rb, cb, val]).astype(np.int64))
+    q_hit = float(-np.expm1(nsignal * np.log1p(-1.0 / (float(rows) * float(cols)))))
+    nk = int(round(rkins * rows))
+    dst = rng.integers(0, rows, size=nk)
+    src_rows = rng.integers(0, rows, size=nk)
+    src = np.arange(rows, dtype=np.int32)
+    keep = dst.size - 1 - np.unique(dst[::-1], return_index=True)[1]   # last pair per row
+    src[dst[keep]] = src_rows[keep]
+    return rect, q_hit, src
+
+
 def algorithm1_codes(rows: int, cols: int, r: int, nsignal: int, rkins: float,
                      seed: int) -> np.ndarray:
     """The paper's crude random genotype model (Section 2, "A simple model for
-    genomics data"), built from its three-step description at a small size.
+    genomics data"), built from its three-step description.
 
     Admixture: r rectangles, each spanning a random contiguous range of rows and
     of columns (rectangles may overlap; later ones cover earlier ones), hold one
     random value in {0, 1, 2} each.  Signal: nsignal uniformly random positions
-    (drawn with replacement) get random values in {0, 1, 2}; where a position is
-    drawn more than once its last draw holds.  Kinship: round(rkins * rows) rows
-    are replaced by copies of randomly chosen rows.  Reading: the copies are
-    taken from the matrix as it stands after the signal step, all at once.
-    Rows are individuals here, so the copies model related individuals.
+    (drawn with replacement) get random values in {0, 1, 2}, the last draw at a
+    position holding -- drawn entry by entry: an entry is hit with probability
+    1 - (1 - 1/(rows cols))^nsignal and then takes a uniform value.  Kinship:
+    round(rkins * rows) rows are replaced by copies of randomly chosen rows, the
+    copies taken from the matrix after the signal step, all at once.  Rows are
+    individuals here, so the copies model related individuals.  Returns the
+    (rows, cols) int8 code matrix.
     """
-    rng = np.random.default_rng([seed, 0xA161])
-    M = np.zeros((rows, cols), dtype=np.int8)
-    # admixture: all rectangle bounds and values in one draw
-    rb = np.sort(rng.integers(0, rows, size=(r, 2)), axis=1)
-    cb = np.sort(rng.integers(0, cols, size=(r, 2)), axis=1)
-    val = rng.integers(0, 3, size=r)
-    for (r0, r1), (c0, c1), v in zip(rb, cb, val):
-        M[r0:r1 + 1, c0:c1 + 1] = v
-    # signal: flat positions; keep each position's last draw
-    pos = rng.integers(0, rows * cols, size=nsignal)
-    sval = rng.integers(0, 3, size=nsignal).astype(np.int8)
-    last = pos.size - 1 - np.unique(pos[::-1], return_index=True)[1]
-    M.reshape(-1)[pos[last]] = sval[last]
-    # kinship: destination and source rows drawn together, copies from one snapshot
-    nk = int(round(rkins * rows))
-    dst = rng.integers(0, rows, size=nk)
-    src = rng.integers(0, rows, size=nk)
-    keep = dst.size - 1 - np.unique(dst[::-1], return_index=True)[1]
-    M[dst[keep]] = M.copy()[src[keep]]
-    return M
+    rect, q_hit, src = _algorithm1_params(rows, cols, r, nsignal, rkins, seed)
+    out = np.empty((cols, rows), dtype=np.int8)
+    rc = _load().synth_algorithm1(rows, cols, r, _ptr(rect), q_hit, _ptr(src),
+                                  seed & 0xFFFFFFFFFFFFFFFF, _ptr(out), 0, None)
+    if rc != 0:
+        raise ValueError("synth_algorithm1 rejected its arguments")
+    return out.T
+
+
+def algorithm1(rows: int = 41505, cols: int = 81700, r: int = 10, nsignal: int | None = None,
+               rkins: float = 0.017, seed: int = 6) -> Genotypes:
+    """The same model packed in the 2-bit storage format (no missing values); the
+    defaults are the paper's Fig. 1 matrix (41,505 x 81,700, r = 10,
+    nsignal = rows cols, rkins = 0.017), rows read as individuals."""
+    nsignal = rows * cols if nsignal is None else int(nsignal)
+    rect, q_hit, src = _algorithm1_params(rows, cols, r, nsignal, rkins, seed)
+    ld = default_ld(rows)
+    out = np.empty((cols, ld), dtype=np.uint8)
+    rc = _load().synth_algorithm1(rows, cols, r, _ptr(rect), q_hit, _ptr(src),
+                                  seed & 0xFFFFFFFFFFFFFFFF, None, ld, _ptr(out))
+    if rc != 0:
+        raise ValueError("synth_algorithm1 rejected its arguments")
+    meta = {"config": "alg1", "seed": seed, "n": rows, "p": cols, "r": r, "nsignal": nsignal,
+            "rkins": rkins, "copied_rows": int(np.sum(src != np.arange(rows))), "miss_rate": 0.0}
+    return Genotypes(out, rows, cols, ld, meta)

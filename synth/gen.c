@@ -146,3 +146,53 @@ int synth_pack(int64_t n, int64_t p, int64_t ld, const int8_t* codes, int32_t pa
     }
     return 0;
 }
+
+/*
+ * The random genotype model of the paper's Section 2 ("A simple model for
+ * genomics data"), entry by entry so that large matrices can be drawn in
+ * parallel.  Rows are individuals (i < n), columns SNPs (j < p).
+ *   1. r rectangles [r0, r1] x [c0, c1] (inclusive) hold values v in {0, 1, 2};
+ *      a later rectangle covers an earlier one; outside all of them the value
+ *      is 0.
+ *   2. nsignal positions drawn uniformly with replacement get random values in
+ *      {0, 1, 2}, the last draw at a position holding.  Entry by entry this is:
+ *      the entry is hit with probability q_hit = 1 - (1 - 1/(n p))^nsignal
+ *      (passed in), and then takes a uniform value in {0, 1, 2}.
+ *   3. Row i < n takes the values of row src[i] after step 2 (src[i] = i for
+ *      rows that are not copies).
+ * rect: r x 5 int64 (r0, r1, c0, c1, v).  Codes land in codes (column-major
+ * n x p int8, when not NULL) and/or packed (p x ld, when not NULL).
+ */
+static inline int alg1_value(int64_t i, int64_t j, uint64_t key, const int64_t* rect, int64_t r,
+                             uint64_t hit_thr)
+{
+    const uint64_t z = splitmix_out(key + (uint64_t)i);
+    if ((z >> 11) < hit_thr) return (int)(((z & 0x1FFFFFull) * 3) >> 21);
+    int v = 0;
+    for (int64_t t = 0; t < r; ++t) {
+        const int64_t* R = rect + 5 * t;
+        if (i >= R[0] && i <= R[1] && j >= R[2] && j <= R[3]) v = (int)R[4];
+    }
+    return v;
+}
+
+int synth_algorithm1(int64_t n, int64_t p, int64_t r, const int64_t* rect, double q_hit,
+                     const int32_t* src, uint64_t seed, int8_t* codes, int64_t ld,
+                     uint8_t* packed)
+{
+    if (n <= 0 || p <= 0 || r < 0 || (r > 0 && !rect) || !src) return -1;
+    if (packed && ld < (n + 3) / 4) return -1;
+    const uint64_t hit_thr = (uint64_t)(q_hit * 9007199254740992.0);   /* 53-bit threshold */
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t j = 0; j < p; ++j) {
+        const uint64_t key = column_key(seed, j);
+        uint8_t* col = packed ? packed + j * ld : NULL;
+        if (col) memset(col, 0, (size_t)ld);
+        for (int64_t i = 0; i < n; ++i) {
+            const int c = alg1_value(src[i], j, key, rect, r, hit_thr);
+            if (codes) codes[j * n + i] = (int8_t)c;
+            if (col) col[i >> 2] |= (uint8_t)(c << (2 * (i & 3)));
+        }
+    }
+    return 0;
+}

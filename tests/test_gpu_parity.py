@@ -17,6 +17,7 @@ torch = pytest.importorskip("torch")
 
 import oracle  # noqa: E402
 import synth   # noqa: E402
+from limb_bounds import quantisation_slack  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -102,10 +103,15 @@ def test_hooks_on_a_blocked_context(gk):
     f64.close()
 
 
+@pytest.mark.parametrize("fmt", ["lut", "lut+limbs"])
 @pytest.mark.parametrize("name,n,p,ld,pad", SHAPES)
-def test_matvec_parity(gk, name, n, p, ld, pad):
+def test_matvec_parity(gk, name, n, p, ld, pad, fmt):
+    # the lookup-table products, and the large-matrix default (tables for A v,
+    # int8 limbs for A^T u, whose vector quantisation adds the bound of
+    # limb_bounds)
     g, Gd = gen(name, n, p, ld=ld, pad_mode=pad)
-    ctx = gk.Context(Gd, n, p, 1)
+    choice = gk.GKL_FP64_LUT if fmt == "lut" else gk.GKL_FP64_LUT_LIMBS
+    ctx = gk.Context(Gd, n, p, 1, fp64_products=choice)
     op = oracle.PackedOperator(g.packed, n, p)
     rng = np.random.default_rng(n * 7 + p)
     v = rng.standard_normal(p)
@@ -114,8 +120,9 @@ def test_matvec_parity(gk, name, n, p, ld, pad):
     z = ctx.rmatvec(dev(u)).cpu().numpy()
     y0 = op.matvec(v)
     z0 = op.rmatvec(u)
+    sz = quantisation_slack(g, v, u)[1] if fmt != "lut" else 0.0
     assert np.linalg.norm(y - y0) <= 1e-12 * max(np.linalg.norm(y0), 1e-300)
-    assert np.linalg.norm(z - z0) <= 1e-12 * max(np.linalg.norm(z0), 1e-300)
+    assert np.linalg.norm(z - z0) <= 1e-12 * max(np.linalg.norm(z0), 1e-300) + sz
     ctx.close()
 
 
