@@ -532,8 +532,42 @@ def run_extra(gk, torch, name, args, stream):
         out[f"bf16_b{b}"] = {key: r[key] for key in (
             "solve_s", "create_s", "block_steps", "restarts", "sigma_max_rel_err_vs_fp64",
             "gated_max_angle", "speedup_vs_fp64", "A W", "A^T X")}
+    out["reorthogonalisation"] = reorth_compare(gk, torch, W, ref, stream)
     del W
     torch.cuda.empty_cache()
+    return out
+
+
+def reorth_compare(gk, torch, W, ref, stream):
+    """The workload's FP64 solve with full, one-sided and partial
+    reorthogonalisation (thick restart m = 60, tol as the workload): seconds per
+    solve, Gram-Schmidt passes, products, and the sigma error against `ref`."""
+    import numpy as np
+    n, p, k = W.n, W.p, W.k
+    out = {}
+    sig = torch.empty(k, dtype=torch.float64, device="cuda")
+    U = torch.empty((k, n), dtype=torch.float64, device="cuda")
+    V = torch.empty((k, p), dtype=torch.float64, device="cuda")
+    for label, mode in (("full", gk.GKL_REORTH_FULL), ("one_sided", gk.GKL_REORTH_ONESIDED),
+                        ("partial", gk.GKL_REORTH_PARTIAL)):
+        times = []
+        for rep in range(3):
+            ctx = gk.Context(W.G, n, p, k, W.wl["tol"], mode, v0=W.v0,
+                             krylov_dim=W.wl["krylov_dim"], stream=stream,
+                             fp64_products=FP64_PRODUCTS[0])
+            try:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st, info = gk.gkl_solve(ctx.ctx, sig, U, n, V, p)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+            finally:
+                ctx.close()
+        s = sig.cpu().numpy()
+        out[label] = {"status": int(st), "solve_s": float(np.median(times)),
+                      "reorth_passes": int(info.reorths), "matvecs": int(info.matvecs),
+                      "sigma_max_rel_err": float(np.max(np.abs(s - ref["sigma"]) / ref["sigma"]))}
+    log(f"[bench] reorthogonalisation: {out}")
     return out
 
 
@@ -565,6 +599,70 @@ def cpu_baseline(W, ref, gpu_matvecs, ntrip):
     return base, cert
 
 
+def product_bench(gk, torch, wl, widths, reps):
+    """Per-call time and error of every product kernel chain on one workload:
+    the FP64 products in each format (tables, int8 limbs) and the block products
+    (split BF16 and int8 limbs at the given widths), errors against the FP64
+    table products.  One JSON line; no solve."""
+    import numpy as np
+    W = Workload(gk, torch, wl)
+    n, p = W.n, W.p
+    rng = np.random.default_rng([11, 0x70726F])
+    bmax = max(widths) if widths else 1
+    Wv = torch.from_numpy(rng.standard_normal((p, bmax)) / np.sqrt(p)).cuda()
+    Xv = torch.from_numpy(rng.standard_normal((n, bmax)) / np.sqrt(n)).cuda()
+    nbytes = fp64_bytes(n, p)
+    out = {"workload": wl["desc"], "reps": reps, "fp64": {}, "blocked": {}}
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = fn()
+        torch.cuda.synchronize()
+        return r, (time.perf_counter() - t0) / reps
+
+    ref = None
+    for name, choice in (("lut", gk.GKL_FP64_LUT), ("limbs", gk.GKL_FP64_LIMBS)):
+        ctx = gk.Context(W.G, n, p, 1, fp64_products=choice)
+        try:
+            y, ty = timed(lambda: ctx.matvec(Wv[:, 0].contiguous()))
+            z, tz = timed(lambda: ctx.rmatvec(Xv[:, 0].contiguous()))
+            if ref is None:
+                ref = (y, z)
+            out["fp64"][name] = {
+                "A v ms": ty * 1e3, "A v GBps": nbytes / ty / 1e9,
+                "A^T u ms": tz * 1e3, "A^T u GBps": nbytes / tz / 1e9,
+                "A v rel diff vs lut": float(torch.linalg.norm(y - ref[0]) / torch.linalg.norm(ref[0])),
+                "A^T u rel diff vs lut": float(torch.linalg.norm(z - ref[1]) / torch.linalg.norm(ref[1]))}
+        finally:
+            ctx.close()
+        log(f"[bench] product bench fp64 {name}: {out['fp64'][name]}")
+    if widths:
+        f64 = gk.Context(W.G, n, p, 1, fp64_products=gk.GKL_FP64_LUT)
+        try:
+            Y0 = torch.stack([f64.matvec(Wv[:, c].contiguous()) for c in range(bmax)], 1)
+            Z0 = torch.stack([f64.rmatvec(Xv[:, c].contiguous()) for c in range(bmax)], 1)
+        finally:
+            f64.close()
+        for fmt, prec in (("bf16", gk.GKL_PREC_MIXED), ("int8", gk.GKL_PREC_MIXED_INT8)):
+            ctx = gk.Context(W.G, n, p, 1, precision=prec, block_width=8, krylov_dim=32)
+            try:
+                for b in widths:
+                    y, ty = timed(lambda: ctx.matmat_mixed(Wv[:, :b]))
+                    z, tz = timed(lambda: ctx.rmatmat_mixed(Xv[:, :b]))
+                    out["blocked"][f"{fmt}_b{b}"] = {
+                        "A W ms": ty * 1e3, "A W GBps": block_bytes(n, p, b) / ty / 1e9,
+                        "A^T X ms": tz * 1e3, "A^T X GBps": block_bytes(n, p, b) / tz / 1e9,
+                        "A W rel err": float(torch.linalg.norm(y - Y0[:, :b]) / torch.linalg.norm(Y0[:, :b])),
+                        "A^T X rel err": float(torch.linalg.norm(z - Z0[:, :b]) / torch.linalg.norm(Z0[:, :b]))}
+                    log(f"[bench] product bench {fmt} b={b}: {out['blocked'][f'{fmt}_b{b}']}")
+            finally:
+                ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -589,6 +687,11 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=2)
     ap.add_argument("--no-loco", action="store_true",
                     help="skip the leave-one-chromosome-out solve of the 22-block genome")
+    ap.add_argument("--product-bench", default=None, metavar="WIDTHS",
+                    help="only time the product kernels (FP64 formats, and block products at "
+                         "these comma-separated widths, '' for none) on the workload; prints "
+                         "one JSON line")
+    ap.add_argument("--product-reps", type=int, default=10)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="after the timed steps, copy BYTES bytes device-to-device 3 times "
                          "(reference dispatch for the HBM traffic counters)")
@@ -608,6 +711,19 @@ def main():
     import paper_1808_03374_amd as gk
 
     stream = torch.cuda.current_stream().cuda_stream
+    if args.product_bench is not None:
+        widths = [int(x) for x in args.product_bench.split(",") if x]
+        res = product_bench(gk, torch, WORKLOADS[args.workload], widths, args.product_reps)
+        if args.copy_calibration > 0:
+            src = torch.empty(args.copy_calibration, dtype=torch.uint8, device="cuda")
+            dst = torch.empty_like(src)
+            for _ in range(3):
+                dst.copy_(src)
+            torch.cuda.synchronize()
+            res["copy_calibration_bytes"] = args.copy_calibration
+        print(json.dumps(res), flush=True)
+        reap_children()
+        return
     wl = WORKLOADS[args.workload]
     W = Workload(gk, torch, wl)
     n, p, k = W.n, W.p, W.k

@@ -113,7 +113,9 @@ typedef struct gkl_options {
     int32_t adaptive_cgs2;    /* 1: second Gram-Schmidt pass only when the first pass
                                  shrank the vector below 1/sqrt(2) of its norm */
     int32_t check_every;      /* steps between convergence tests; 0 = auto (when the
-                                 basis is full if restarting, else every 5 steps) */
+                                 basis is full if restarting; else every 5 steps up
+                                 to a 20-vector basis, then each time it has grown
+                                 by a quarter, as the projected SVD costs O(j^3)) */
     int32_t max_steps;        /* cap on the basis size without restart; 0 = min(512,
                                  min(n, p)).  A solve without restart that fills the
                                  basis before converging returns GKL_NOT_CONVERGED. */
@@ -133,8 +135,10 @@ typedef struct gkl_options {
                                  create and keep the fastest; 0 = fixed geometry */
     int32_t graph;            /* batched: 1 (default) = each Lanczos step is one HIP
                                  graph launch; 0 = the same kernels launched one by one */
-    int32_t fp64_products;    /* gkl_fp64_products (GKL_PREC_FP64 single-problem
-                                 contexts; the batched path uses the tables) */
+    int32_t fp64_products;    /* gkl_fp64_products (GKL_PREC_FP64 contexts; the
+                                 batched path forms A v from the tables in every case
+                                 and A^T u in limbs for _LIMBS, _LUT_LIMBS, and for
+                                 _AUTO from 1 GB of packed genotypes in the batch) */
 } gkl_options;
 
 /* Run statistics (host struct). */
@@ -160,7 +164,7 @@ typedef struct gkl_info {
                                  equal to matvec_kernel_ms on the FP64 path */
     double rmatvec_core_ms;   /* likewise for the A^T u / A^T X products */
     int32_t fp64_products;    /* format the FP64 products ran in: GKL_FP64_LUT,
-                                 _LIMBS or _LUT_LIMBS (0 on the blocked and batched
+                                 _LIMBS or _LUT_LIMBS (0 on the blocked and LOCO
                                  paths) */
     int32_t reserved;
 } gkl_info;

@@ -79,6 +79,8 @@ struct BatchState {
     int64_t mv_target = kDefaultTarget, rmv_target = kDefaultTarget;
     int grid_mv = kDefaultGrid, grid_rmv = kDefaultGrid;
     double tuned_mv_ms = 0.0, tuned_rmv_ms = 0.0;
+    bool limb_rmv = false;             // A^T u in int8 limbs (layout S per problem)
+    int64_t max_nstX = 0;              // largest number of limb super-tiles along n
     hipStream_t stream = nullptr;
     bool own_stream = false;
     bool use_graph = true;
@@ -113,9 +115,11 @@ struct BatchState {
         for (int q = 0; q < count; ++q) {
             BatchProblem& P = *probs[q];
             P.plan = product_plan(P.prob.packed, mvt, rmvt);
-            t_mv[q + 1] = t_mv[q] + P.plan.mv_rowblocks * P.plan.mv_nsplit;
-            t_rmv[q + 1] = t_rmv[q] + P.plan.rmv_colblocks * P.plan.rmv_nsplit;
             const Packed& L = P.prob.packed;
+            t_mv[q + 1] = t_mv[q] + P.plan.mv_rowblocks * P.plan.mv_nsplit;
+            const BfSplit lg = limb_rmv ? limb_batch_split(L.ms, rmvt) : BfSplit{};
+            t_rmv[q + 1] = t_rmv[q] + (limb_rmv ? lg.nrb * lg.nsplit
+                                                : P.plan.rmv_colblocks * P.plan.rmv_nsplit);
             BatchDesc& d = desc[q];
             d.T = L.T;
             d.P = L.P;
@@ -146,6 +150,24 @@ struct BatchState {
             d.anorm = P.anorm;
             d.active = d_active + q;
             d.breakdown = d_breakdown + q;
+            d.S = nullptr;
+            d.ldS = d.nstX = d.limb_st_per = 0;
+            d.limb_nrb = 0;
+            d.lfrag = nullptr;
+            d.lcpart = d.lcmax = nullptr;
+            if (limb_rmv) {
+                const MixedShape& m = L.ms;
+                d.S = L.S;
+                d.ldS = m.ldS;
+                d.nstX = m.nstX;
+                d.pP = m.pS;
+                d.rmv_nsplit = lg.nsplit;
+                d.limb_st_per = lg.st_per;
+                d.limb_nrb = lg.nrb;
+                d.lfrag = P.prob.mvw.lfrag;
+                d.lcpart = P.prob.mvw.lcpart;
+                d.lcmax = P.prob.mvw.lcmax;
+            }
         }
         if (t_mv[count] < 0 || t_rmv[count] < 0) fail(GKL_ERR_INVALID, "batch too large");
         GKL_HIP(hipMemcpyAsync(d_desc, desc.data(), sizeof(BatchDesc) * count,
@@ -173,6 +195,15 @@ struct BatchState {
         GKL_HIP(hipStreamSynchronize(stream));   // h lives on this stack frame
     }
 
+    // The partials of A^T u_j of every active problem.
+    void right_product(int grid)
+    {
+        if (limb_rmv)
+            launch_blimb_rmatvec(d_desc, d_tile_rmv, count, d_state, grid, max_nstX, stream);
+        else
+            launch_brmatvec(d_desc, d_tile_rmv, count, d_state, grid, stream);
+    }
+
     // One Lanczos step of every active problem (the captured sequence).
     void record_step()
     {
@@ -191,7 +222,7 @@ struct BatchState {
         launch_bmatvec(d_desc, d_tile_mv, count, d_state, grid_mv, stream);
         launch_bmatvec_reduce(d_desc, d_state, count, max_n, stream);
         launch_bortho(d_desc, d_state, count, 0, max_n, hstride, stream);
-        launch_brmatvec(d_desc, d_tile_rmv, count, d_state, grid_rmv, stream);
+        right_product(grid_rmv);
         launch_brmatvec_reduce(d_desc, d_state, count, max_p, stream);
         launch_bortho(d_desc, d_state, count, 1, max_p, hstride, stream);
         launch_bstep(d_state, stream);
@@ -230,7 +261,7 @@ struct BatchState {
         try {
             for (int r = 0; r <= reps; ++r) {
                 if (r == 1) GKL_HIP(hipEventRecord(e0, stream));
-                if (right) launch_brmatvec(d_desc, d_tile_rmv, count, d_state, grid, stream);
+                if (right) right_product(grid);
                 else launch_bmatvec(d_desc, d_tile_mv, count, d_state, grid, stream);
             }
             GKL_HIP(hipEventRecord(e1, stream));
@@ -439,11 +470,19 @@ gkl_status gkl_create_batched(int32_t count, const uint8_t* const* G, const int6
         // The basis capacity is shared (problems step together); a problem whose own
         // min(n, p) is smaller leaves the batch when its Krylov space is complete.
         batch_basis(B, o, k, mx);
+        double total = 0.0;
+        for (int q = 0; q < count; ++q) total += (double)n[q] * (double)p[q];
+        // A^T u from the tables or in int8 limbs (A v always from the tables), as
+        // options.fp64_products asks; GKL_FP64_AUTO takes the limbs from 1 GB of
+        // packed genotypes in the whole batch on
+        B.limb_rmv = o->fp64_products == GKL_FP64_LIMBS || o->fp64_products == GKL_FP64_LUT_LIMBS ||
+                     (o->fp64_products == GKL_FP64_AUTO && total >= 4e9);
         for (int q = 0; q < count; ++q) {
             B.probs.emplace_back(new BatchProblem());
             BatchProblem& P = *B.probs.back();
             const int64_t ld = o->ld_bytes ? o->ld_bytes : (n[q] + 3) / 4;
-            P.prob.setup(G[q], n[q], p[q], ld, s, 1);
+            P.prob.setup(G[q], n[q], p[q], ld, s, B.limb_rmv ? 3 : 1);
+            if (B.limb_rmv) B.max_nstX = std::max(B.max_nstX, P.prob.packed.ms.nstX);
             P.cap = std::min(n[q], p[q]);
             B.max_n = std::max(B.max_n, n[q]);
             B.max_p = std::max(B.max_p, p[q]);
@@ -451,6 +490,11 @@ gkl_status gkl_create_batched(int32_t count, const uint8_t* const* G, const int6
             for (int64_t t : kTargets)
                 pe = std::max(pe, product_plan_partial_elems(P.prob.packed,
                                                              product_plan(P.prob.packed, t, t)));
+            if (B.limb_rmv) {
+                const MixedShape& m = P.prob.packed.ms;
+                for (int64_t t : kTargets)
+                    pe = std::max(pe, (size_t)limb_batch_split(m, t).nsplit * (size_t)m.pS);
+            }
             P.partial = static_cast<double*>(P.prob.arena.alloc(sizeof(double) * pe));
             alloc_problem(B, P, n[q], p[q], s);
         }
@@ -750,6 +794,7 @@ gkl_status gkl_solve_batched(gkl_ctx* ctx, double* const* sigma, double* const* 
                 I.reorths = 2 * P.matvecs;
                 I.converged = P.converged ? 1 : 0;
                 I.nconv = P.converged ? k : 0;
+                if (!B.loco) I.fp64_products = B.limb_rmv ? GKL_FP64_LUT_LIMBS : GKL_FP64_LUT;
                 const int kk = std::min(k, P.final_m);
                 double sum = 0.0, mx = 0.0;
                 for (int i = 0; i < kk; ++i) {

@@ -550,7 +550,12 @@ gkl_status gkl_ctx::solve_fp64(double* sigma, double* Uo, int64_t ldu, double* V
     int last_check = 0;
     int nconv = 0;
     const int64_t maxbasis = std::min(prob.n, prob.p);
+    // Convergence tests: every check_every steps if given; with thick restart when
+    // the basis is full; without restart every 5 steps until the basis holds 20
+    // vectors, then whenever it has grown by a quarter -- the projected SVD costs
+    // O(j^3), so testing at a fixed interval would make it dominate large bases
     const int check_every = opt.check_every > 0 ? opt.check_every : (krylov > 0 ? 0 : 5);
+    const bool grow_checks = opt.check_every <= 0 && krylov == 0;
     bool converged = false;
     while (true) {
         left_step(j);
@@ -558,7 +563,8 @@ gkl_status gkl_ctx::solve_fp64(double* sigma, double* Uo, int64_t ldu, double* V
         ++j;
         const bool budget = opt.max_matvecs > 0 && info.matvecs >= opt.max_matvecs;
         const bool full = (j == maxm) || (j >= maxbasis);
-        const bool due = j >= k && (full || (check_every > 0 && j - last_check >= check_every));
+        const int every = grow_checks ? std::max(check_every, last_check / 4) : check_every;
+        const bool due = j >= k && (full || (every > 0 && j - last_check >= every));
         if (opt.trace) record(j - 1, false, NAN);
         if (!(due || budget || full)) continue;
         nconv = j >= k ? check_convergence(j) : 0;
@@ -679,6 +685,7 @@ static int fp64_products_for(int64_t n, int64_t p, int32_t choice)
 {
     if (choice == GKL_FP64_LUT) return 1;
     if (choice == GKL_FP64_LIMBS) return 2;
+    if (choice == GKL_FP64_LUT_LIMBS) return 3;
     // GKL_FP64_AUTO: from 1 GB of packed genotypes on, A v from the tables and
     // A^T u on the int8 matrix cores, the faster form of each (50,000 x 500,000:
     // A v 1.29 ms against 1.39 ms in limbs, A^T u 2.09 ms against 1.19 ms);

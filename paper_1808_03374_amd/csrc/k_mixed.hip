@@ -320,17 +320,19 @@ __device__ __forceinline__ void block_coords(int g, int nsplit, int nrb, int xcd
 // cost more than the consumer's 64 extra reads).
 constexpr int kCsSplit = 64;   // == wavefront size (the chunk values are combined by one wave)
 
-__global__ void __launch_bounds__(256)
-colsum_kernel(const double* __restrict__ X, int64_t ldx, int64_t len,
-              const double* __restrict__ mean, const double* __restrict__ inv_sd, double mref,
-              double* __restrict__ cpart, double* __restrict__ cmax)
+// Chunk `chunk` of one column xc (len entries): its sum (of mean_j s_j x_j when
+// mean is given) and its largest magnitude (of (mref - mu_j) s_j x_j).  Called
+// by every thread of the block.
+__device__ __forceinline__ void colsum_chunk(const double* __restrict__ xc, int64_t len,
+                                             const double* __restrict__ mean,
+                                             const double* __restrict__ inv_sd, double mref,
+                                             int chunk, double* __restrict__ sum_out,
+                                             double* __restrict__ max_out)
 {
     __shared__ double sh[16];
-    const int c = blockIdx.y;
-    const int64_t chunk = (len + kCsSplit - 1) / kCsSplit;
-    const int64_t j0 = (int64_t)blockIdx.x * chunk;
-    const int64_t j1 = j0 + chunk < len ? j0 + chunk : len;
-    const double* xc = X + (int64_t)c * ldx;
+    const int64_t per = (len + kCsSplit - 1) / kCsSplit;
+    const int64_t j0 = (int64_t)chunk * per;
+    const int64_t j1 = j0 + per < len ? j0 + per : len;
     double a = 0.0, mx = 0.0;
     if (mean) {
         for (int64_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
@@ -345,7 +347,7 @@ colsum_kernel(const double* __restrict__ X, int64_t ldx, int64_t len,
         }
     }
     a = block_sum(a, sh);
-    if (threadIdx.x == 0) cpart[c * kCsSplit + blockIdx.x] = a;
+    if (threadIdx.x == 0) *sum_out = a;
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
     __syncthreads();
@@ -354,8 +356,18 @@ colsum_kernel(const double* __restrict__ X, int64_t ldx, int64_t len,
     if (threadIdx.x == 0) {
         double m = 0.0;
         for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, sh[w]);
-        cmax[c * kCsSplit + blockIdx.x] = m;
+        *max_out = m;
     }
+}
+
+__global__ void __launch_bounds__(256)
+colsum_kernel(const double* __restrict__ X, int64_t ldx, int64_t len,
+              const double* __restrict__ mean, const double* __restrict__ inv_sd, double mref,
+              double* __restrict__ cpart, double* __restrict__ cmax)
+{
+    const int c = blockIdx.y;
+    colsum_chunk(X + (int64_t)c * ldx, len, mean, inv_sd, mref, blockIdx.x,
+                 cpart + c * kCsSplit + blockIdx.x, cmax + c * kCsSplit + blockIdx.x);
 }
 
 // ks[c] for c < nb: the kCsSplit chunk sums of column c added by one wave in a
@@ -500,6 +512,25 @@ split_X_bf16_kernel(const double* __restrict__ X, int64_t ldx, int nb, int64_t n
 // partial[split][row][kCS] (kCS = 8 packed, 16 kT otherwise; packed rows hold
 // hi + lo already added).
 // ---------------------------------------------------------------------------
+// Fragments are staged in LDS in blocks of kStage K steps (half a super-tile),
+// double buffered: block s + 1 is loaded straight from global memory into LDS
+// (global_load_lds_dwordx4: lane l of a wave writes bytes 16 l .. 16 l + 15 of
+// the wave's 1 KB) while block s is multiplied, and one barrier per block,
+// after every wave's loads have landed, hands the buffers over.
+constexpr int kStage = 4;
+
+template <int kFr>
+__device__ __forceinline__ void stage_to_lds(const bf16x8* __restrict__ src, bf16x8* dst)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < kFr / 256; ++k) {
+        const int base = 256 * k + 64 * wave;     // wave-uniform
+        __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(src + base + lane),
+                                         dst + base, 16, 0, 0);
+    }
+}
+
 constexpr int kRTW = 4;       // A W: row tiles per wave
 constexpr int kRTX = 2;       // A^T X: row tiles per wave
 constexpr int kFlush = 4;     // super-tiles per FP32 chunk
@@ -513,7 +544,8 @@ matmat_bf16_kernel(const uint8_t* __restrict__ I, int64_t ldI, int64_t nI,
     constexpr int kOps = kPack ? 2 : 4 * kT;
     constexpr int kTiles = kPack ? 1 : kT;
     constexpr int kCS = kPack ? 8 : 16 * kT;
-    __shared__ bf16x8 bs[kKSteps * kOps * 64];
+    constexpr int kFr = kStage * kOps * 64;        // fragments per staged block
+    __shared__ bf16x8 bs[2][kFr];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = lane >> 4, r = lane & 15;
     int split, rb;
@@ -531,31 +563,38 @@ matmat_bf16_kernel(const uint8_t* __restrict__ I, int64_t ldI, int64_t nI,
 #pragma unroll
             for (int e = 0; e < 4; ++e) accd[t][c][e] = 0.0;
         }
-    uint4 a[kRTW];
-    if (st0 < st1) {
+    uint4 a[kRTW], an[kRTW];
+    const int64_t nstage = 2 * (st1 - st0);
+    if (nstage > 0) {
+        stage_to_lds<kFr>(frag + st0 * (2 * kFr), bs[0]);
 #pragma unroll
         for (int t = 0; t < kRTW; ++t)
             a[t] = *reinterpret_cast<const uint4*>(
                 I + tiled_offset(row_base + 16 * t + r, st0 * 64 + 16 * g, ldI));
     }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
     int chunk = 0;
-    for (int64_t st = st0; st < st1; ++st) {
-        const bf16x8* src = frag + st * (kKSteps * kOps * 64);
-        for (int q = threadIdx.x; q < kKSteps * kOps * 64; q += 256) bs[q] = src[q];
-        // the next super-tile's codes are in flight while this one is used
-        uint4 an[kRTW];
-        const int64_t stn = st + 1 < st1 ? st + 1 : st;
+    for (int64_t sidx = 0; sidx < nstage; ++sidx) {
+        const int64_t st = st0 + (sidx >> 1);
+        const int half = (int)(sidx & 1);
+        const int buf = (int)(sidx & 1);
+        if (half == 0) {
+            // the next super-tile's codes are in flight while this one is used
+            const int64_t stn = st + 1 < st1 ? st + 1 : st;
 #pragma unroll
-        for (int t = 0; t < kRTW; ++t)
-            an[t] = *reinterpret_cast<const uint4*>(
-                I + tiled_offset(row_base + 16 * t + r, stn * 64 + 16 * g, ldI));
-        __syncthreads();
+            for (int t = 0; t < kRTW; ++t)
+                an[t] = *reinterpret_cast<const uint4*>(
+                    I + tiled_offset(row_base + 16 * t + r, stn * 64 + 16 * g, ldI));
+        }
+        if (sidx + 1 < nstage) stage_to_lds<kFr>(frag + st0 * (2 * kFr) + (sidx + 1) * kFr, bs[buf ^ 1]);
 #pragma unroll
-        for (int ks = 0; ks < kKSteps; ++ks) {
+        for (int kk = 0; kk < kStage; ++kk) {
+            const int ks = half * kStage + kk;
             const int w = ks >> 1, h = ks & 1;
             bf16x8 bo[kOps];
 #pragma unroll
-            for (int op = 0; op < kOps; ++op) bo[op] = bs[(ks * kOps + op) * 64 + lane];
+            for (int op = 0; op < kOps; ++op) bo[op] = bs[buf][(kk * kOps + op) * 64 + lane];
 #pragma unroll
             for (int t = 0; t < kRTW; ++t) {
                 const uint32_t d = w == 0 ? a[t].x : w == 1 ? a[t].y : w == 2 ? a[t].z : a[t].w;
@@ -578,19 +617,22 @@ matmat_bf16_kernel(const uint8_t* __restrict__ I, int64_t ldI, int64_t nI,
                 }
             }
         }
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
+        if (half == 1) {
 #pragma unroll
-        for (int t = 0; t < kRTW; ++t) a[t] = an[t];
-        if (++chunk == kFlush) {
-            chunk = 0;
+            for (int t = 0; t < kRTW; ++t) a[t] = an[t];
+            if (++chunk == kFlush) {
+                chunk = 0;
 #pragma unroll
-            for (int t = 0; t < kRTW; ++t)
+                for (int t = 0; t < kRTW; ++t)
 #pragma unroll
-                for (int c = 0; c < kTiles; ++c) {
+                    for (int c = 0; c < kTiles; ++c) {
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) accd[t][c][e] += (double)acc[t][c][e];
-                    acc[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
-                }
+                        for (int e = 0; e < 4; ++e) accd[t][c][e] += (double)acc[t][c][e];
+                        acc[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+                    }
+            }
         }
     }
     double* out = partial + (int64_t)split * nI * kCS;
@@ -651,7 +693,8 @@ rmatmat_bf16_kernel(const uint8_t* __restrict__ S, int64_t ldS, int64_t pS,
     constexpr int kOps = kPack ? 1 : 2 * kT;
     constexpr int kTiles = kPack ? 1 : kT;
     constexpr int kCS = kPack ? 8 : 16 * kT;
-    __shared__ bf16x8 bs[kKSteps * kOps * 64];
+    constexpr int kFr = kStage * kOps * 64;        // fragments per staged block
+    __shared__ bf16x8 bs[2][kFr];
     __shared__ double Tc[32];
     __shared__ int ex[32];
     if (kFused) {
@@ -676,30 +719,37 @@ rmatmat_bf16_kernel(const uint8_t* __restrict__ S, int64_t ldS, int64_t pS,
 #pragma unroll
             for (int e = 0; e < 4; ++e) dC[t][c][e] = dM[t][c][e] = 0.0;
         }
-    uint4 a[kRTX];
-    if (st0 < st1) {
+    uint4 a[kRTX], an[kRTX];
+    const int64_t nstage = 2 * (st1 - st0);
+    if (nstage > 0) {
+        stage_to_lds<kFr>(frag + st0 * (2 * kFr), bs[0]);
 #pragma unroll
         for (int t = 0; t < kRTX; ++t)
             a[t] = *reinterpret_cast<const uint4*>(
                 S + tiled_offset(row_base + 16 * t + r, st0 * 64 + 16 * g, ldS));
     }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
     int chunk = 0;
-    for (int64_t st = st0; st < st1; ++st) {
-        const bf16x8* src = frag + st * (kKSteps * kOps * 64);
-        for (int q = threadIdx.x; q < kKSteps * kOps * 64; q += 256) bs[q] = src[q];
-        uint4 an[kRTX];
-        const int64_t stn = st + 1 < st1 ? st + 1 : st;
+    for (int64_t sidx = 0; sidx < nstage; ++sidx) {
+        const int64_t st = st0 + (sidx >> 1);
+        const int half = (int)(sidx & 1);
+        const int buf = (int)(sidx & 1);
+        if (half == 0) {
+            const int64_t stn = st + 1 < st1 ? st + 1 : st;
 #pragma unroll
-        for (int t = 0; t < kRTX; ++t)
-            an[t] = *reinterpret_cast<const uint4*>(
-                S + tiled_offset(row_base + 16 * t + r, stn * 64 + 16 * g, ldS));
-        __syncthreads();
+            for (int t = 0; t < kRTX; ++t)
+                an[t] = *reinterpret_cast<const uint4*>(
+                    S + tiled_offset(row_base + 16 * t + r, stn * 64 + 16 * g, ldS));
+        }
+        if (sidx + 1 < nstage) stage_to_lds<kFr>(frag + st0 * (2 * kFr) + (sidx + 1) * kFr, bs[buf ^ 1]);
 #pragma unroll
-        for (int ks = 0; ks < kKSteps; ++ks) {
+        for (int kk = 0; kk < kStage; ++kk) {
+            const int ks = half * kStage + kk;
             const int w = ks >> 1, h = ks & 1;
             bf16x8 bo[kOps];
 #pragma unroll
-            for (int op = 0; op < kOps; ++op) bo[op] = bs[(ks * kOps + op) * 64 + lane];
+            for (int op = 0; op < kOps; ++op) bo[op] = bs[buf][(kk * kOps + op) * 64 + lane];
 #pragma unroll
             for (int t = 0; t < kRTX; ++t) {
                 const uint32_t d = w == 0 ? a[t].x : w == 1 ? a[t].y : w == 2 ? a[t].z : a[t].w;
@@ -720,23 +770,26 @@ rmatmat_bf16_kernel(const uint8_t* __restrict__ S, int64_t ldS, int64_t pS,
                 }
             }
         }
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
+        if (half == 1) {
 #pragma unroll
-        for (int t = 0; t < kRTX; ++t) a[t] = an[t];
-        if (++chunk == kFlush) {
-            chunk = 0;
+            for (int t = 0; t < kRTX; ++t) a[t] = an[t];
+            if (++chunk == kFlush) {
+                chunk = 0;
 #pragma unroll
-            for (int t = 0; t < kRTX; ++t)
+                for (int t = 0; t < kRTX; ++t)
 #pragma unroll
-                for (int c = 0; c < kTiles; ++c) {
+                    for (int c = 0; c < kTiles; ++c) {
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        dC[t][c][e] += (double)aC[t][c][e];
-                        dM[t][c][e] += (double)aM[t][c][e];
+                        for (int e = 0; e < 4; ++e) {
+                            dC[t][c][e] += (double)aC[t][c][e];
+                            dM[t][c][e] += (double)aM[t][c][e];
+                        }
+                        aC[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+                        aM[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
                     }
-                    aC[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
-                    aM[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
-                }
+            }
         }
     }
 #pragma unroll
@@ -1098,88 +1151,72 @@ rmatmat_i8_reduce_kernel(const double* __restrict__ partial, int nsplit, int64_t
 constexpr int kLimbs = 7;
 constexpr int kQ64 = 52;
 constexpr int64_t kLimbMaxSt = ((int64_t)1 << 20) / kSuper;   // super-tiles per K split
-constexpr int kRTv = 8;    // A v: row tiles per wave (512 rows per workgroup)
+constexpr int kRTv = 4;    // A v: row tiles per wave (256 rows per workgroup)
 constexpr int kRTu = 4;    // A^T u: row tiles per wave (256 rows per workgroup)
-
-// Limb l (0 = most significant) of q.
-__device__ __forceinline__ int limb_of(int64_t q, int l)
-{
-    int out = 0;
-#pragma unroll
-    for (int k = kLimbs - 1; k >= 1; --k) {
-        const int d = (int)(((q + 128) & 255) - 128);
-        q = (q - d) >> 8;
-        if (k == l) out = d;
-    }
-    return l == 0 ? (int)q : out;
-}
 
 __device__ __forceinline__ int64_t quantise52(double x, int ex)
 {
     return (int64_t)rint(ldexp(x, kQ64 - ex));
 }
 
-// B operands of A v: frag[((st * kWords + word) * 2 + op) * 64 + lane], op 0 =
-// limbs of s v, op 1 = limbs of z; byte e of lane (g, col) holds SNP st*256 +
-// 64 g + 16 word + code_of_elem(e), limb col (zero for col >= 7).
-__global__ void __launch_bounds__(256)
-limb_v_kernel(const double* __restrict__ v, int64_t p, const double* __restrict__ mean,
-              const double* __restrict__ inv_sd, const double* __restrict__ cmax, int64_t nst,
-              i32x4* __restrict__ frag)
+// Limb fragments of one vector (kOps = 1: x; kOps = 2: w = s v and z = (mu - 3) w).
+// One workgroup per super-tile of 256 contraction indices, one thread per index:
+// the thread quantises its entries once and writes their seven limbs as bytes
+// of the fragment image in LDS, which the workgroup then stores as whole
+// operands.  frag[((st * kWords + word) * kOps + op) * 64 + lane]: byte e of
+// lane (g, col) holds index st*256 + 64 g + 16 word + code_of_elem(e), limb col
+// (zero for col >= 7).
+template <int kOps>
+__device__ __forceinline__ void limb_frag_body(const double* __restrict__ x, int64_t len,
+                                               const double* __restrict__ mean,
+                                               const double* __restrict__ inv_sd,
+                                               const double* __restrict__ cmax,
+                                               i32x4* __restrict__ frag, int64_t st)
 {
+    __shared__ i32x4 img[kWords * kOps * 64];
     __shared__ int ex[1];
     column_scales(cmax, 1, ex);
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // (st, word, lane)
-    if (t >= nst * kWords * 64) return;
-    const int lane = (int)(t & 63);
-    const int word = (int)((t >> 6) % kWords);
-    const int64_t st = t / (64 * kWords);
-    const int g = lane >> 4, col = lane & 15;
-    const int e0 = ex[0];
-    i32x4 fw = {0, 0, 0, 0}, fz = {0, 0, 0, 0};
-    if (col < kLimbs) {
-#pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const int64_t j = st * kSuper + 64 * g + 16 * word + code_of_elem(e);
-            double w = 0.0, z = 0.0;
-            if (j < p) {
-                w = inv_sd[j] * v[j];
-                z = (mean[j] - 3.0) * w;
-            }
-            put_byte(fw, e, limb_of(quantise52(w, e0), col));
-            put_byte(fz, e, limb_of(quantise52(z, e0), col));
-        }
+    for (int q = threadIdx.x; q < kWords * kOps * 64; q += 256) img[q] = i32x4{0, 0, 0, 0};
+    __syncthreads();
+    const int o = threadIdx.x;                       // index within the super-tile
+    const int64_t j = st * kSuper + o;
+    const int g = o >> 6, word = (o >> 4) & 3, c = o & 15;
+    const int e = (c & 3) * 4 + (c >> 2);            // code_of_elem(e) == c
+    double val[kOps];
+    if (kOps == 2) {
+        const double w = j < len ? inv_sd[j] * x[j] : 0.0;
+        val[0] = w;
+        val[kOps - 1] = j < len ? (mean[j] - 3.0) * w : 0.0;
+    } else {
+        val[0] = j < len ? x[j] : 0.0;
     }
-    i32x4* f = frag + ((st * kWords + word) * 2) * 64 + lane;
-    f[0] = fw;
-    f[64] = fz;
+    uint8_t* bytes = reinterpret_cast<uint8_t*>(img);
+#pragma unroll
+    for (int op = 0; op < kOps; ++op) {
+        int64_t q = quantise52(val[op], ex[0]);
+        int lim[kLimbs];
+#pragma unroll
+        for (int k = kLimbs - 1; k >= 1; --k) {
+            lim[k] = (int)(((q + 128) & 255) - 128);
+            q = (q - lim[k]) >> 8;
+        }
+        lim[0] = (int)q;
+#pragma unroll
+        for (int l = 0; l < kLimbs; ++l)
+            bytes[(((word * kOps + op) * 64) + g * 16 + l) * 16 + e] = (uint8_t)(lim[l] & 0xFF);
+    }
+    __syncthreads();
+    i32x4* f = frag + st * (kWords * kOps * 64);
+    for (int q = threadIdx.x; q < kWords * kOps * 64; q += 256) f[q] = img[q];
 }
 
-// B operand of A^T u: frag[(st * kWords + word) * 64 + lane]; byte e of lane
-// (g, col) holds individual st*256 + 64 g + 16 word + code_of_elem(e), limb col.
+template <int kOps>
 __global__ void __launch_bounds__(256)
-limb_u_kernel(const double* __restrict__ u, int64_t n, const double* __restrict__ cmax,
-              int64_t nst, i32x4* __restrict__ frag)
+limb_frag_kernel(const double* __restrict__ x, int64_t len, const double* __restrict__ mean,
+                 const double* __restrict__ inv_sd, const double* __restrict__ cmax,
+                 i32x4* __restrict__ frag)
 {
-    __shared__ int ex[1];
-    column_scales(cmax, 1, ex);
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nst * kWords * 64) return;
-    const int lane = (int)(t & 63);
-    const int word = (int)((t >> 6) % kWords);
-    const int64_t st = t / (64 * kWords);
-    const int g = lane >> 4, col = lane & 15;
-    const int e0 = ex[0];
-    i32x4 fx = {0, 0, 0, 0};
-    if (col < kLimbs) {
-#pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const int64_t i = st * kSuper + 64 * g + 16 * word + code_of_elem(e);
-            const double x = i < n ? u[i] : 0.0;
-            put_byte(fx, e, limb_of(quantise52(x, e0), col));
-        }
-    }
-    frag[(st * kWords + word) * 64 + lane] = fx;
+    limb_frag_body<kOps>(x, len, mean, inv_sd, cmax, frag, blockIdx.x);
 }
 
 // Element e of accumulator a recombined from the seven limb columns of the
@@ -1204,12 +1241,14 @@ __device__ __forceinline__ double limb_sum(const i32x4& a, int e, int lane)
 // buffered in LDS, one barrier per super-tile).  partial[split * rows_pad +
 // row] = the split's share of the product (before s_j for A^T u).
 template <bool kAv>
-__global__ void __launch_bounds__(256)
-limb_product_kernel(const uint8_t* __restrict__ L, int64_t ldL, int64_t rows_pad, int64_t rows,
-                    const i32x4* __restrict__ frag, int64_t nst, int64_t st_per, int nsplit,
-                    int nrb, int xcd, const double* __restrict__ cpart,
-                    const double* __restrict__ cmax, const double* __restrict__ mean,
-                    double* __restrict__ partial)
+__device__ __forceinline__ void limb_product_body(const uint8_t* __restrict__ L, int64_t ldL,
+                                                  int64_t rows_pad, int64_t rows,
+                                                  const i32x4* __restrict__ frag, int64_t nst,
+                                                  int64_t st_per, int split, int rb,
+                                                  const double* __restrict__ cpart,
+                                                  const double* __restrict__ cmax,
+                                                  const double* __restrict__ mean,
+                                                  double* __restrict__ partial)
 {
     constexpr int kRT = kAv ? kRTv : kRTu;
     constexpr int kOps = kAv ? 2 : 1;
@@ -1223,8 +1262,6 @@ limb_product_kernel(const uint8_t* __restrict__ L, int64_t ldL, int64_t rows_pad
     column_scales(cmax, 1, ex);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = lane >> 4, r = lane & 15;
-    int split, rb;
-    block_coords(blockIdx.x, nsplit, nrb, xcd, split, rb);
     const int64_t row_base = (int64_t)rb * (kMxWaves * kRT * 16) + wave * (kRT * 16);
     const int64_t st0 = (int64_t)split * st_per;
     const int64_t st1 = st0 + st_per < nst ? st0 + st_per : nst;
@@ -1299,6 +1336,83 @@ limb_product_kernel(const uint8_t* __restrict__ L, int64_t ldL, int64_t rows_pad
             if (r == 0) out[row] = val;
         }
     }
+}
+
+template <bool kAv>
+__global__ void __launch_bounds__(256)
+limb_product_kernel(const uint8_t* __restrict__ L, int64_t ldL, int64_t rows_pad, int64_t rows,
+                    const i32x4* __restrict__ frag, int64_t nst, int64_t st_per, int nsplit,
+                    int nrb, int xcd, const double* __restrict__ cpart,
+                    const double* __restrict__ cmax, const double* __restrict__ mean,
+                    double* __restrict__ partial)
+{
+    int split, rb;
+    block_coords(blockIdx.x, nsplit, nrb, xcd, split, rb);
+    limb_product_body<kAv>(L, ldL, rows_pad, rows, frag, nst, st_per, split, rb, cpart, cmax, mean,
+                           partial);
+}
+
+// Batched A^T u in limbs (the batched path with the S layout per problem).
+// Problem q = blockIdx.y; u_j at U + j n; inactive problems skip (whole blocks).
+__global__ void __launch_bounds__(256)
+blimb_colsum_kernel(const BatchDesc* __restrict__ desc, const int* __restrict__ state)
+{
+    const BatchDesc& D = desc[blockIdx.y];
+    if (!*D.active) return;
+    const int64_t j = state[0];
+    colsum_chunk(D.U + j * D.n, D.n, nullptr, nullptr, 0.0, blockIdx.x, D.lcpart + blockIdx.x,
+                 D.lcmax + blockIdx.x);
+}
+
+__global__ void __launch_bounds__(256)
+blimb_frag_kernel(const BatchDesc* __restrict__ desc, const int* __restrict__ state)
+{
+    const BatchDesc& D = desc[blockIdx.y];
+    if (!*D.active || (int64_t)blockIdx.x >= D.nstX) return;
+    const int64_t j = state[0];
+    limb_frag_body<1>(D.U + j * D.n, D.n, nullptr, nullptr, D.lcmax,
+                      static_cast<i32x4*>(D.lfrag), blockIdx.x);
+}
+
+// Persistent over the (split, row block) tiles of every active problem:
+// tile0[q] is problem q's first tile; tile l of a problem is split l / nrb, row
+// block l % nrb.  A barrier opens every tile, so the shared scalars and operand
+// buffers of the previous tile are no longer in use.
+__global__ void __launch_bounds__(256)
+blimb_rmatvec_kernel(const BatchDesc* __restrict__ desc, const int* __restrict__ tile0, int count,
+                     const int* __restrict__ state)
+{
+    __shared__ int t0[kMaxBatch + 1];
+    for (int i = threadIdx.x; i <= count; i += blockDim.x) t0[i] = tile0[i];
+    __syncthreads();
+    const int total = t0[count];
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+        int lo = 0, hi = count - 1;          // owner: the last q with t0[q] <= t
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (t0[mid] <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const BatchDesc& D = desc[lo];
+        if (!*D.active) continue;            // the same for the whole workgroup
+        const int l = t - t0[lo];
+        __syncthreads();
+        limb_product_body<false>(D.S, D.ldS, D.pP, D.p, static_cast<const i32x4*>(D.lfrag),
+                                 D.nstX, D.limb_st_per, l / D.limb_nrb, l % D.limb_nrb, D.lcpart,
+                                 D.lcmax, D.mean, D.partial);
+    }
+}
+
+void launch_blimb_rmatvec(const BatchDesc* d, const int* tile0, int count, const int* state,
+                          int grid, int64_t max_nst, hipStream_t s)
+{
+    hipLaunchKernelGGL(blimb_colsum_kernel, dim3(kCsSplit, count), dim3(256), 0, s, d, state);
+    GKL_LAUNCH_CHECK("blimb_colsum_kernel");
+    hipLaunchKernelGGL(blimb_frag_kernel, dim3((unsigned int)max_nst, count), dim3(256), 0, s, d,
+                       state);
+    GKL_LAUNCH_CHECK("blimb_frag_kernel");
+    hipLaunchKernelGGL(blimb_rmatvec_kernel, dim3(grid), dim3(256), 0, s, d, tile0, count, state);
+    GKL_LAUNCH_CHECK("blimb_rmatvec_kernel");
 }
 
 // ---------------------------------------------------------------------------
@@ -1399,6 +1513,21 @@ size_t mixed_partial_elems(const MixedShape& m)
     return e;
 }
 
+BfSplit limb_batch_split(const MixedShape& m, int64_t target)
+{
+    BfSplit g;
+    g.nrb = (int)(m.pS / (kMxWaves * kRTu * 16));
+    int64_t ns = (target + g.nrb - 1) / g.nrb;
+    const int64_t lo = (m.nstX + kLimbMaxSt - 1) / kLimbMaxSt;
+    if (ns > m.nstX) ns = m.nstX;
+    if (ns < lo) ns = lo;
+    if (ns < 1) ns = 1;
+    g.st_per = (m.nstX + ns - 1) / ns;
+    g.nsplit = (int)((m.nstX + g.st_per - 1) / g.st_per);
+    g.xcd = 0;
+    return g;
+}
+
 size_t limb_frag_bytes(const MixedShape& m)
 {
     return std::max((size_t)m.nstW * kWords * 2, (size_t)m.nstX * kWords) * 64 * sizeof(i32x4);
@@ -1417,9 +1546,9 @@ int launch_matvec_limb(const MixedShape& m, const uint8_t* I, const ColStats& st
     hipLaunchKernelGGL(colsum_kernel, dim3(kCsSplit, 1), dim3(256), 0, s, v, m.p, m.p, st.mean,
                        st.inv_sd, 3.0, w.lcpart, w.lcmax);
     GKL_LAUNCH_CHECK("colsum_kernel");
-    hipLaunchKernelGGL(limb_v_kernel, dim3(ceil_div(m.nstW * kWords * 64, 256)), dim3(256), 0, s, v,
-                       m.p, st.mean, st.inv_sd, w.lcmax, m.nstW, frag);
-    GKL_LAUNCH_CHECK("limb_v_kernel");
+    hipLaunchKernelGGL(limb_frag_kernel<2>, dim3((unsigned int)m.nstW), dim3(256), 0, s, v, m.p,
+                       st.mean, st.inv_sd, w.lcmax, frag);
+    GKL_LAUNCH_CHECK("limb_frag_kernel<2>");
     if (ev) GKL_HIP(hipEventRecord(ev[0], s));
     hipLaunchKernelGGL(limb_product_kernel<true>, dim3((unsigned int)(gm.nsplit * gm.nrb)),
                        dim3(256), 0, s, I, m.ldI, m.nI, m.n, frag, m.nstW, gm.st_per, gm.nsplit,
@@ -1437,9 +1566,9 @@ int launch_rmatvec_limb(const MixedShape& m, const uint8_t* S, const ColStats& s
     hipLaunchKernelGGL(colsum_kernel, dim3(kCsSplit, 1), dim3(256), 0, s, u, m.n, m.n, nullptr,
                        nullptr, 0.0, w.lcpart, w.lcmax);
     GKL_LAUNCH_CHECK("colsum_kernel");
-    hipLaunchKernelGGL(limb_u_kernel, dim3(ceil_div(m.nstX * kWords * 64, 256)), dim3(256), 0, s, u,
-                       m.n, w.lcmax, m.nstX, frag);
-    GKL_LAUNCH_CHECK("limb_u_kernel");
+    hipLaunchKernelGGL(limb_frag_kernel<1>, dim3((unsigned int)m.nstX), dim3(256), 0, s, u, m.n,
+                       nullptr, nullptr, w.lcmax, frag);
+    GKL_LAUNCH_CHECK("limb_frag_kernel<1>");
     if (ev) GKL_HIP(hipEventRecord(ev[0], s));
     hipLaunchKernelGGL(limb_product_kernel<false>, dim3((unsigned int)(gm.nsplit * gm.nrb)),
                        dim3(256), 0, s, S, m.ldS, m.pS, m.p, frag, m.nstX, gm.st_per, gm.nsplit,

@@ -125,6 +125,15 @@ struct BatchDesc {
     double* anorm;                   // running max of the alphas and betas
     int32_t* active;                 // 0 once converged or stopped
     int32_t* breakdown;              // 1 + half-step (2j + side) of a breakdown, else 0
+    // A^T u in int8 limbs (when S is set): layout S (pP then holds its padded
+    // rows and rmv_nsplit its K splits, as the reduce kernel reads them), the
+    // limb fragments of u_j and its column sum / maximum chunks
+    const uint8_t* S;
+    int64_t ldS, nstX, limb_st_per;
+    int32_t limb_nrb;
+    void* lfrag;
+    double* lcpart;
+    double* lcmax;
 };
 
 // Product geometry of one problem for the given split targets (blocks per launch).
@@ -141,6 +150,14 @@ void launch_bmatvec(const BatchDesc* d, const int* tile0, int count, const int* 
                     hipStream_t s);
 void launch_brmatvec(const BatchDesc* d, const int* tile0, int count, const int* state, int grid,
                      hipStream_t s);
+// K splits of one problem's A^T u in limbs inside a batch: about `target` tiles
+// (split x row block) per problem, at least one split, at most 2^20 per split.
+BfSplit limb_batch_split(const MixedShape& m, int64_t target);
+// Persistent A^T u_j in int8 limbs for the problems whose descriptor has S set
+// (all of the batch): column sums, limb fragments, then the matrix-core kernel
+// over the (split, row block) tiles of every active problem.
+void launch_blimb_rmatvec(const BatchDesc* d, const int* tile0, int count, const int* state,
+                          int grid, int64_t max_nst, hipStream_t s);
 // u_j = sum of partials - beta_{j-1} u_{j-1} (or - U(:, 0:nlock) rho right after a
 // restart); v_{j+1} = s o (sum of partials) - alpha_j v_j.
 void launch_bmatvec_reduce(const BatchDesc* d, const int* state, int count, int64_t max_n,

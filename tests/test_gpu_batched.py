@@ -77,15 +77,23 @@ def run_batch(gk, Gs, gs, k, v0s, **opts):
     return sig, Us, Vs, st, infos, plan
 
 
+def fmt_option(gk, fmt):
+    # A^T u from the tables, or in int8 limbs (A v is always from the tables)
+    return gk.GKL_FP64_LUT if fmt == "lut" else gk.GKL_FP64_LUT_LIMBS
+
+
+@pytest.mark.parametrize("fmt", ["lut", "limbs"])
 @pytest.mark.parametrize("krylov", [0, 16])
-def test_batched_matches_oracle_per_problem(gk, krylov):
+def test_batched_matches_oracle_per_problem(gk, krylov, fmt):
     # six blocks of the 4-subpopulation genome, 700 individuals, 96..2,000 SNPs
     gs, Gs = chromosome_batch(700, [1, 4, 9, 14, 19, 22], 40)
     k = 5
     v0s = start_vectors(gs)
     refs = oracle_solutions(gs, k, v0s)
-    sig, Us, Vs, st, infos, _ = run_batch(gk, Gs, gs, k, v0s, krylov_dim=krylov)
+    sig, Us, Vs, st, infos, _ = run_batch(gk, Gs, gs, k, v0s, krylov_dim=krylov,
+                                          fp64_products=fmt_option(gk, fmt))
     assert st == gk.GKL_OK
+    assert all(i.fp64_products == fmt_option(gk, fmt) for i in infos)
     for q, (op, ref) in enumerate(refs):
         assert infos[q].converged == 1
         check_against_oracle(sig[q], Us[q], Vs[q], op, ref, k)
@@ -93,16 +101,18 @@ def test_batched_matches_oracle_per_problem(gk, krylov):
         assert max(i.restarts for i in infos) >= 1
 
 
-def test_graph_replay_matches_eager_launches(gk):
+@pytest.mark.parametrize("fmt", ["lut", "limbs"])
+def test_graph_replay_matches_eager_launches(gk, fmt):
     gs, Gs = chromosome_batch(640, [2, 7, 12, 21], 30)
     k = 4
     v0s = start_vectors(gs)
-    a = run_batch(gk, Gs, gs, k, v0s, krylov_dim=14, graph=1)
+    f = fmt_option(gk, fmt)
+    a = run_batch(gk, Gs, gs, k, v0s, krylov_dim=14, graph=1, fp64_products=f)
     # eager work on the same stream between the two solves
     x = torch.randn(1 << 20, dtype=torch.float64, device="cuda")
     float((x * x).sum())
-    b = run_batch(gk, Gs, gs, k, v0s, krylov_dim=14, graph=0)
-    c = run_batch(gk, Gs, gs, k, v0s, krylov_dim=14, graph=1)
+    b = run_batch(gk, Gs, gs, k, v0s, krylov_dim=14, graph=0, fp64_products=f)
+    c = run_batch(gk, Gs, gs, k, v0s, krylov_dim=14, graph=1, fp64_products=f)
     for q in range(len(gs)):
         for r in (b, c):
             assert torch.equal(a[0][q], r[0][q])
@@ -125,12 +135,14 @@ def test_problems_converge_and_leave_independently(gk):
         check_against_oracle(sig[q], Us[q], Vs[q], op, ref, k)
 
 
-def test_autotuned_geometry(gk):
+@pytest.mark.parametrize("fmt", ["lut", "limbs"])
+def test_autotuned_geometry(gk, fmt):
     gs, Gs = chromosome_batch(900, [3, 8, 17], 25)
     k = 4
     v0s = start_vectors(gs)
-    a = run_batch(gk, Gs, gs, k, v0s, krylov_dim=16)
-    b = run_batch(gk, Gs, gs, k, v0s, krylov_dim=16, autotune=1)
+    f = fmt_option(gk, fmt)
+    a = run_batch(gk, Gs, gs, k, v0s, krylov_dim=16, fp64_products=f)
+    b = run_batch(gk, Gs, gs, k, v0s, krylov_dim=16, autotune=1, fp64_products=f)
     plan = b[5]
     assert plan["mv_target"] in (192, 384, 768, 1536)
     assert plan["rmv_target"] in (192, 384, 768, 1536)
@@ -141,7 +153,8 @@ def test_autotuned_geometry(gk):
         assert np.all(np.abs(s0 - s1) <= 1e-10 * s0)
 
 
-def test_problems_of_different_sizes_and_a_single_problem(gk):
+@pytest.mark.parametrize("fmt", ["lut", "limbs"])
+def test_problems_of_different_sizes_and_a_single_problem(gk, fmt):
     # individuals differ between problems too; and a batch of one
     sizes = [(300, 1500, 5), (900, 700, 9), (520, 2600, 13)]
     gs = [synth.config("c4", n=n, p=p, chrom=c) for n, p, c in sizes]
@@ -149,11 +162,13 @@ def test_problems_of_different_sizes_and_a_single_problem(gk):
     k = 4
     v0s = start_vectors(gs)
     refs = oracle_solutions(gs, k, v0s)
-    sig, Us, Vs, st, infos, _ = run_batch(gk, Gs, gs, k, v0s, krylov_dim=16)
+    f = fmt_option(gk, fmt)
+    sig, Us, Vs, st, infos, _ = run_batch(gk, Gs, gs, k, v0s, krylov_dim=16, fp64_products=f)
     assert st == gk.GKL_OK
     for q, (op, ref) in enumerate(refs):
         check_against_oracle(sig[q], Us[q], Vs[q], op, ref, k)
-    sig1, Us1, Vs1, st1, _, _ = run_batch(gk, Gs[1:2], gs[1:2], k, v0s[1:2], krylov_dim=16)
+    sig1, Us1, Vs1, st1, _, _ = run_batch(gk, Gs[1:2], gs[1:2], k, v0s[1:2], krylov_dim=16,
+                                          fp64_products=f)
     assert st1 == gk.GKL_OK
     check_against_oracle(sig1[0], Us1[0], Vs1[0], refs[1][0], refs[1][1], k)
 

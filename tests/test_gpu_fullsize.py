@@ -179,17 +179,20 @@ def test_adaptive_cgs2(gk, case):
     assert np.abs(V.T @ V - np.eye(k)).max() < 1e-12
 
 
-def test_batched_full_size_chromosome_pair(gk):
+@pytest.mark.parametrize("fmt", ["lut", "limbs"])
+def test_batched_full_size_chromosome_pair(gk, fmt):
     # the largest and the smallest chromosome block of the 22-block genome at full
     # size (20,000 x 80,000 and 20,000 x 8,000) solved together by the batched
-    # path; each problem certified by the oracle
+    # path, A^T u from the tables or in int8 limbs; each problem certified by the
+    # oracle
     gs = [synth.config("c4", chrom=1), synth.config("c4", chrom=22)]
     assert (gs[0].p, gs[1].p) == (80000, 8000)
     k, tol = 10, 1e-10
     v0 = dev(np.concatenate([synth.start_vector(g.p, 40 + q) for q, g in enumerate(gs)]))
     Gs = [dev(g.packed) for g in gs]
     ctx = gk.BatchedContext(Gs, [g.n for g in gs], [g.p for g in gs], k, tol=tol, v0=v0,
-                            krylov_dim=40, graph=1)
+                            krylov_dim=40, graph=1,
+                            fp64_products=gk.GKL_FP64_LUT if fmt == "lut" else gk.GKL_FP64_LUT_LIMBS)
     sig, Us, Vs, st, infos = ctx.solve()
     ctx.close()
     assert st == gk.GKL_OK
