@@ -84,11 +84,21 @@ def source_digest(path, region=None):
     return hashlib.sha256(text).hexdigest()
 
 
+def sources_digest(paths):
+    """sha256 over the bytes of whole files, in order."""
+    import hashlib
+    h = hashlib.sha256()
+    for path in paths:
+        h.update(open(os.path.join(ROOT, path), "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic(workload, kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summaries of the workload (profiles/<workload>_*hbm_traffic*.md, one JSON
     record per summary), or None when none covers it or the kernel's source
-    changed since the counters were taken."""
+    changed since the counters were taken (a record names either whole files,
+    `sources`, or one file and a marked region of it)."""
     import glob
     import re
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", f"{workload}_*hbm_traffic*.md"))):
@@ -98,7 +108,10 @@ def measured_traffic(workload, kernel):
             if k is None:
                 continue
             try:
-                digest = source_digest(os.path.join(ROOT, rec["kernel_source"]), rec.get("region"))
+                if "sources" in rec:
+                    digest = sources_digest(rec["sources"])
+                else:
+                    digest = source_digest(os.path.join(ROOT, rec["kernel_source"]), rec.get("region"))
             except (OSError, ValueError):
                 return None
             if digest != rec["source_sha256"]:

@@ -92,11 +92,12 @@ enum gkl_precision { GKL_PREC_FP64 = 0, GKL_PREC_MIXED = 1, GKL_PREC_MIXED_INT8 
  * rounded to a 52-bit integer and split into seven 8-bit limbs; the limb sums
  * are exact and recombined in FP64, so the product carries the vector's
  * quantisation (at most 2^-53 of that scale per entry) and FP64 roundings only.
- * GKL_FP64_LUT_LIMBS: tables for A v, limbs for A^T u -- the faster form of
- * each as measured (50,000 x 500,000: A v 1.29 ms from the tables against 1.39
- * ms in limbs, A^T u 2.09 ms against 1.19 ms).  GKL_FP64_AUTO: LUT_LIMBS when
- * n p >= 4e9 (1 GB packed), else LUT (at 10,000 x 100,000 the two A^T u forms
- * are within 5% and the limbs add two small kernels per product). */
+ * GKL_FP64_LUT_LIMBS: tables for A v, limbs for A^T u.  GKL_FP64_AUTO: LIMBS
+ * when n p >= 1e9 (250 MB packed), else LUT.  Measured at 50,000 x 500,000: A v
+ * 1.13 ms in limbs against 1.29 ms from the tables, A^T u 1.14 ms against 2.09
+ * ms; at 10,000 x 100,000 a 720-product solve takes 94 ms in limbs and 97 ms
+ * from the tables, and below that the tables avoid the two small quantisation
+ * kernels each limb product adds. */
 enum gkl_fp64_products {
     GKL_FP64_AUTO = 0, GKL_FP64_LUT = 1, GKL_FP64_LIMBS = 2, GKL_FP64_LUT_LIMBS = 3
 };

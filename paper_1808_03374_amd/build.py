@@ -23,6 +23,10 @@ SOURCES = ["engine.hip", "k_stats.hip", "k_matvec.hip", "k_ortho.hip", "k_svd.hi
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # packed-FP32 instructions are disabled on purpose (see the design notes)
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # matrix-core operands and accumulators in VGPRs: with the default
+         # heuristic the loop-carried accumulators of every matrix-core loop were
+         # rotated through 24-64 v_accvgpr moves per iteration
+         "-mllvm", "-amdgpu-mfma-vgpr-form",
          "-Wall", "-Wno-unused-function", "-Wno-unused-result"]
 
 

@@ -69,6 +69,12 @@ void Problem::setup(const uint8_t* G, int64_t n_, int64_t p_, int64_t ld_, hipSt
     G_user = G;
     stream = s;
     layout_shape(n, p, packed);
+    st.count = static_cast<int64_t*>(arena.alloc(sizeof(int64_t) * p));
+    st.nobs = static_cast<int64_t*>(arena.alloc(sizeof(int64_t) * p));
+    st.n3 = static_cast<int64_t*>(arena.alloc(sizeof(int64_t) * p));
+    st.mean = static_cast<double*>(arena.alloc(sizeof(double) * p));
+    st.inv_sd = static_cast<double*>(arena.alloc(sizeof(double) * p));
+    bool stats_done = false;
     if (products != 0) {
         // 1: tables for both products, 2: limbs for both, 3: tables for A v and
         // limbs for A^T u
@@ -86,7 +92,9 @@ void Problem::setup(const uint8_t* G, int64_t n_, int64_t p_, int64_t ld_, hipSt
             uint8_t* S = packed.limb_rmv
                              ? static_cast<uint8_t*>(arena.alloc((size_t)m.pS * (size_t)m.ldS))
                              : nullptr;
-            build_mixed_layouts(G, n, p, ld, I, S, s);
+            // the pass that builds S also forms the column statistics
+            build_mixed_layouts(G, n, p, ld, I, S, s, S ? &st : nullptr);
+            stats_done = S != nullptr;
             packed.I = I;
             packed.S = S;
             mvw.lfrag = arena.alloc(limb_frag_bytes(m));
@@ -94,12 +102,7 @@ void Problem::setup(const uint8_t* G, int64_t n_, int64_t p_, int64_t ld_, hipSt
             mvw.lcmax = static_cast<double*>(arena.alloc(sizeof(double) * 64));
         }
     }
-    st.count = static_cast<int64_t*>(arena.alloc(sizeof(int64_t) * p));
-    st.nobs = static_cast<int64_t*>(arena.alloc(sizeof(int64_t) * p));
-    st.n3 = static_cast<int64_t*>(arena.alloc(sizeof(int64_t) * p));
-    st.mean = static_cast<double*>(arena.alloc(sizeof(double) * p));
-    st.inv_sd = static_cast<double*>(arena.alloc(sizeof(double) * p));
-    launch_colstats(G, n, p, ld, st, s);
+    if (!stats_done) launch_colstats(G, n, p, ld, st, s);
     if (products == 0) return;
     mvw.partial_elems = matvec_partial_elems(packed);
     mvw.partial = static_cast<double*>(arena.alloc(sizeof(double) * mvw.partial_elems));
@@ -686,12 +689,12 @@ static int fp64_products_for(int64_t n, int64_t p, int32_t choice)
     if (choice == GKL_FP64_LUT) return 1;
     if (choice == GKL_FP64_LIMBS) return 2;
     if (choice == GKL_FP64_LUT_LIMBS) return 3;
-    // GKL_FP64_AUTO: from 1 GB of packed genotypes on, A v from the tables and
-    // A^T u on the int8 matrix cores, the faster form of each (50,000 x 500,000:
-    // A v 1.29 ms against 1.39 ms in limbs, A^T u 2.09 ms against 1.19 ms);
-    // below that the tables for both (10,000 x 100,000: A^T u 96 us against 92
-    // us in limbs plus the two small kernels that quantise the vector)
-    return (double)n * (double)p >= 4e9 ? 3 : 1;
+    // GKL_FP64_AUTO: from 1e9 genotypes (250 MB packed) on, both products on the
+    // int8 matrix cores (50,000 x 500,000: A v 1.13 ms against 1.29 ms from the
+    // tables, A^T u 1.14 ms against 2.09 ms; 10,000 x 100,000: a solve of 720
+    // products 94 ms against 97 ms); below that the tables, which need no
+    // quantisation kernels per product
+    return (double)n * (double)p >= 1e9 ? 2 : 1;
 }
 
 static gkl_status validate(const uint8_t* G, int64_t n, int64_t p, int32_t k, double tol,

@@ -88,75 +88,152 @@ __host__ __device__ __forceinline__ int64_t tiled_offset(int64_t row, int64_t by
     return ((row >> 4) * (ld >> 6) + (byte >> 6)) * 1024 + (row & 15) * 64 + (byte & 63);
 }
 
-// I: byte J of individual i = codes of SNPs 4J..4J+3 of individual i (tiled, ld
-// = ldI); padding = code 3.
-__global__ void build_I_kernel(const uint8_t* __restrict__ G, int64_t n, int64_t p, int64_t ld,
-                               uint8_t* __restrict__ I, int64_t nI, int64_t ldI)
+// Four bytes q..q+3 of packed column j as one little-endian word; bytes at or
+// past nb (and rows past n in the last real byte) are code 3.  aligned: the
+// column's bytes are 4-byte aligned, so a full word is one load.
+__device__ __forceinline__ uint32_t column_word(const uint8_t* __restrict__ G, int64_t ld,
+                                                int64_t j, int64_t q, int64_t n, int64_t nb,
+                                                bool aligned)
 {
+    const uint8_t* c = G + j * ld;
+    uint32_t w;
+    if (aligned && q + 4 <= nb) {
+        w = *reinterpret_cast<const uint32_t*>(c + q);
+    } else {
+        w = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) w |= (q + e < nb ? (uint32_t)c[q + e] : 0xFFu) << (8 * e);
+    }
+    const int64_t last = nb - 1 - q;          // position of the last real byte in w
+    const int64_t valid = n - 4 * (nb - 1);   // individuals in that byte (1..4)
+    if (valid < 4 && last >= 0 && last < 4) w |= ((0xFFu << (2 * valid)) & 0xFFu) << (8 * last);
+    return w;
+}
+
+// I: byte J of individual i = codes of SNPs 4J..4J+3 of individual i (tiled, ld
+// = ldI); padding = code 3.  A workgroup takes one 64-byte tile column (SNPs
+// 256 st .. 256 st + 255) of 512 individuals (bytes 128 ib .. 128 ib + 127 of
+// those 256 packed columns: whole 128-byte lines) through LDS.  The codes of
+// SNPs 4J..4J+3 (k) of individuals 4b..4b+3 (r) form a 4 x 4 matrix of 2-bit
+// fields, field (k, r) at bit 8k + 2r of the word of the four column bytes;
+// two delta swaps transpose it to bit 8r + 2k, so byte r of the result is
+// byte J of individual 4b + r.  Each thread forms 16 such bytes for 4
+// individuals and stores them as 4 x 16 bytes; 4 neighbouring lanes fill one
+// 64-byte tile row.
+constexpr int kBiCols = 256;    // SNP columns per workgroup (one tile column of I)
+constexpr int kBiBytes = 128;   // packed bytes per column (512 individuals)
+
+__global__ void __launch_bounds__(256) build_I_kernel(const uint8_t* __restrict__ G, int64_t n,
+                                                      int64_t p, int64_t ld,
+                                                      uint8_t* __restrict__ I, int64_t nI,
+                                                      int64_t ldI)
+{
+    // column c at c * kBiBytes + (c / 64) * 16: the reads of the four column
+    // groups fall in different banks
+    __shared__ __align__(16) uint8_t col[kBiCols * kBiBytes + 4 * 16];
     const int64_t nb = (n + 3) / 4;
-    const int64_t nrq = nI / 4;
-    // t = (SNP quad J, individual quad Iq)
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nrq * ldI;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t J = t / nrq;
-        const int64_t Iq = t - J * nrq;
-        uint32_t in[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int64_t j = 4 * J + k;
-            uint32_t b = 0xFF;
-            if (j < p && Iq < nb) {
-                b = G[j * ld + Iq];
-                const int64_t valid = n - 4 * Iq;
-                if (valid < 4) b |= (0xFFu << (2 * valid)) & 0xFFu;
-            }
-            in[k] = b;
+    const int64_t nib = nI / (4 * kBiBytes), nst = ldI / 64;
+    const bool aligned = (ld & 3) == 0 && (reinterpret_cast<uintptr_t>(G) & 3) == 0;
+    const int t = threadIdx.x;
+    for (int64_t blk = blockIdx.x; blk < nib * nst; blk += gridDim.x) {
+        const int64_t ib = blk % nib, st = blk / nib;
+        const int64_t q0 = ib * kBiBytes, j0 = st * kBiCols;
+        __syncthreads();   // the previous block's reads of col are done
+#pragma unroll 8
+        for (int k = 0; k < kBiCols / 8; ++k) {   // dword t & 31 of columns 8k + t / 32
+            const int c = 8 * k + (t >> 5);
+            const int64_t j = j0 + c;
+            const uint32_t w = j < p ? column_word(G, ld, j, q0 + 4 * (t & 31), n, nb, aligned)
+                                     : 0xFFFFFFFFu;
+            *reinterpret_cast<uint32_t*>(col + c * kBiBytes + (c >> 6) * 16 + 4 * (t & 31)) = w;
         }
+        __syncthreads();
+        const int jq = t & 3;   // output bytes 16 jq .. 16 jq + 15 of the tile row
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            uint32_t byte = 0;
+        for (int h = 0; h < 2; ++h) {
+            const int b = (t >> 2) + 64 * h;   // packed byte: individuals 4b .. 4b + 3
+            uint32_t W[16];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) byte |= ((in[k] >> (2 * r)) & 3u) << (2 * k);
-            I[tiled_offset(4 * Iq + r, J, ldI)] = (uint8_t)byte;
+            for (int q = 0; q < 16; ++q) {
+                const uint8_t* cp = col + (64 * jq + 4 * q) * kBiBytes + jq * 16 + b;
+                uint32_t x = (uint32_t)cp[0] | (uint32_t)cp[kBiBytes] << 8 |
+                             (uint32_t)cp[2 * kBiBytes] << 16 | (uint32_t)cp[3 * kBiBytes] << 24;
+                uint32_t d = ((x >> 6) ^ x) & 0x00CC00CCu;
+                x ^= d ^ (d << 6);
+                d = ((x >> 12) ^ x) & 0x0000F0F0u;
+                x ^= d ^ (d << 12);
+                W[q] = x;
+            }
+            const int64_t row0 = 4 * kBiBytes * ib + 4 * b;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                uint32_t o[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    o[e] = ((W[4 * e] >> (8 * r)) & 0xFFu) |
+                           ((W[4 * e + 1] >> (8 * r)) & 0xFFu) << 8 |
+                           ((W[4 * e + 2] >> (8 * r)) & 0xFFu) << 16 |
+                           ((W[4 * e + 3] >> (8 * r)) & 0xFFu) << 24;
+                *reinterpret_cast<uint4*>(I + tiled_offset(row0 + r, 64 * st + 16 * jq, ldI)) =
+                    make_uint4(o[0], o[1], o[2], o[3]);
+            }
         }
     }
 }
 
 // S: byte Iq of SNP j = codes of individuals 4Iq..4Iq+3 (tiled, ld = ldS);
-// padding = code 3.
-__global__ void build_S_kernel(const uint8_t* __restrict__ G, int64_t n, int64_t p, int64_t ld,
-                               uint8_t* __restrict__ S, int64_t pS, int64_t ldS)
+// padding = code 3.  One wave per SNP row, four bytes per lane (they stay in
+// one 64-byte tile row).  With stats, the wave also counts the codes of its
+// column and writes the column statistics, so no separate pass reads G.
+__global__ void __launch_bounds__(256) build_S_kernel(const uint8_t* __restrict__ G, int64_t n,
+                                                      int64_t p, int64_t ld,
+                                                      uint8_t* __restrict__ S, int64_t pS,
+                                                      int64_t ldS, ColStats st, int with_stats)
 {
     const int64_t nb = (n + 3) / 4;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < pS * ldS;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t j = t / ldS;
-        const int64_t Iq = t - j * ldS;
-        uint32_t b = 0xFF;
-        if (j < p && Iq < nb) {
-            b = G[j * ld + Iq];
-            const int64_t valid = n - 4 * Iq;
-            if (valid < 4) b |= (0xFFu << (2 * valid)) & 0xFFu;
+    const bool aligned = (ld & 3) == 0 && (reinterpret_cast<uintptr_t>(G) & 3) == 0;
+    const int lane = threadIdx.x & 63;
+    for (int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); j < pS;
+         j += (int64_t)gridDim.x * 4) {
+        int64_t c1 = 0, c2 = 0, c3 = 0;
+#pragma unroll 4
+        for (int64_t q = 4 * lane; q < ldS; q += 256) {
+            uint32_t w = 0xFFFFFFFFu;
+            if (j < p && q < nb) {
+                w = column_word(G, ld, j, q, n, nb, aligned);
+                if (with_stats) {
+                    const int64_t valid = n - 4 * q;
+                    count_word(w, valid >= 16 ? 16 : (int)valid, c1, c2, c3);
+                }
+            }
+            *reinterpret_cast<uint32_t*>(S + tiled_offset(j, q, ldS)) = w;
         }
-        S[tiled_offset(j, Iq, ldS)] = (uint8_t)b;
+        if (with_stats && j < p) {
+            c1 = wave_sum_i64(c1);
+            c2 = wave_sum_i64(c2);
+            c3 = wave_sum_i64(c3);
+            if (lane == 0) store_colstats(st, j, n, c1, c2, c3);
+        }
     }
 }
 
 void build_mixed_layouts(const uint8_t* G, int64_t n, int64_t p, int64_t ld, uint8_t* I,
-                         uint8_t* S, hipStream_t s)
+                         uint8_t* S, hipStream_t s, const ColStats* st)
 {
     const int64_t nI = mixed_rows_I(n), ldI = mixed_ld_I(p);
     const int64_t pS = mixed_rows_S(p), ldS = mixed_ld_S(n);
+    if (st && !S) fail(GKL_ERR_INTERNAL, "column statistics come with layout S");
     if (I) {
-        const int64_t tI = (nI / 4) * ldI;
-        hipLaunchKernelGGL(build_I_kernel, dim3(stride_grid(tI, 256)), dim3(256), 0, s, G, n, p, ld,
-                           I, nI, ldI);
+        const int64_t blocks = (nI / (4 * kBiBytes)) * (ldI / 64);
+        const unsigned int grid = (unsigned int)std::min<int64_t>(blocks, (int64_t)1 << 20);
+        hipLaunchKernelGGL(build_I_kernel, dim3(grid), dim3(256), 0, s, G, n, p, ld, I, nI, ldI);
         GKL_LAUNCH_CHECK("build_I_kernel");
     }
     if (S) {
-        const int64_t tS = pS * ldS;
-        hipLaunchKernelGGL(build_S_kernel, dim3(stride_grid(tS, 256)), dim3(256), 0, s, G, n, p, ld,
-                           S, pS, ldS);
+        const int64_t rows4 = pS / 4;
+        const unsigned int grid = (unsigned int)std::min<int64_t>(rows4, (int64_t)1 << 20);
+        hipLaunchKernelGGL(build_S_kernel, dim3(grid), dim3(256), 0, s, G, n, p, ld, S, pS, ldS,
+                           st ? *st : ColStats{}, st ? 1 : 0);
         GKL_LAUNCH_CHECK("build_S_kernel");
     }
 }
@@ -172,12 +249,15 @@ __device__ __forceinline__ i32x4 raw_codes(uint32_t w)
     return r;
 }
 
-// Missing flags (code 3) of the same 16 codes, in the same positions.
-__device__ __forceinline__ i32x4 missing_flags(uint32_t w)
+// Missing flags (code 3) of the same 16 codes, in the same positions, from the
+// code bytes: each code byte (0..3) selects a byte of the constant 0x01000000
+// in a byte permute (v_perm_b32), one instruction per four flags.
+__device__ __forceinline__ i32x4 missing_flags(const i32x4& c)
 {
-    const uint32_t m = w & (w >> 1) & 0x55555555u;   // bit 2k: code k is 3
-    const i32x4 r = {(int)(m & 0x01010101u), (int)((m >> 2) & 0x01010101u),
-                     (int)((m >> 4) & 0x01010101u), (int)((m >> 6) & 0x01010101u)};
+    const i32x4 r = {(int)__builtin_amdgcn_perm(0u, 0x01000000u, (uint32_t)c[0]),
+                     (int)__builtin_amdgcn_perm(0u, 0x01000000u, (uint32_t)c[1]),
+                     (int)__builtin_amdgcn_perm(0u, 0x01000000u, (uint32_t)c[2]),
+                     (int)__builtin_amdgcn_perm(0u, 0x01000000u, (uint32_t)c[3])};
     return r;
 }
 
@@ -992,7 +1072,7 @@ matmat_i8_kernel(const uint8_t* __restrict__ I, int64_t ldI, int64_t nI,
 #pragma unroll
             for (int t = 0; t < kRTw; ++t) {
                 const uint32_t d = w == 0 ? a[t].x : w == 1 ? a[t].y : w == 2 ? a[t].z : a[t].w;
-                const i32x4 ac = raw_codes(d), am = missing_flags(d);
+                const i32x4 ac = raw_codes(d), am = missing_flags(ac);
 #pragma unroll
                 for (int l = 0; l < T; ++l) {
                     acc[t][l] = mfma_i8(ac, bw[l], acc[t][l]);
@@ -1077,7 +1157,7 @@ rmatmat_i8_kernel(const uint8_t* __restrict__ S, int64_t ldS, int64_t pS,
 #pragma unroll
             for (int t = 0; t < kRTr; ++t) {
                 const uint32_t d = w == 0 ? a[t].x : w == 1 ? a[t].y : w == 2 ? a[t].z : a[t].w;
-                const i32x4 ac = raw_codes(d), am = missing_flags(d);
+                const i32x4 ac = raw_codes(d), am = missing_flags(ac);
 #pragma unroll
                 for (int l = 0; l < T; ++l) {
                     accC[t][l] = mfma_i8(ac, bx[l], accC[t][l]);
@@ -1298,7 +1378,7 @@ __device__ __forceinline__ void limb_product_body(const uint8_t* __restrict__ L,
 #pragma unroll
             for (int t = 0; t < kRT; ++t) {
                 const uint32_t d = w == 0 ? a[t].x : w == 1 ? a[t].y : w == 2 ? a[t].z : a[t].w;
-                const i32x4 ac = raw_codes(d), am = missing_flags(d);
+                const i32x4 ac = raw_codes(d), am = missing_flags(ac);
                 if (kAv) {
                     acc[t][0] = mfma_i8(ac, b0, acc[t][0]);
                     acc[t][0] = mfma_i8(am, b1, acc[t][0]);
@@ -1422,12 +1502,12 @@ void launch_blimb_rmatvec(const BatchDesc* d, const int* tile0, int count, const
 // `wg_rows` rows and nst super-tiles of K: enough workgroups to cover the chip
 // several times, at most max_split splits (bounds the partial-sum traffic), a
 // multiple of 8 from 8 on so that each split's row blocks share one XCD.
-static BfSplit bf16_split(int64_t rows, int wg_rows, int64_t nst, int64_t max_split)
+static BfSplit bf16_split(int64_t rows, int wg_rows, int64_t nst, int64_t max_split,
+                          int64_t target = 2048)
 {
-    constexpr int64_t kTargetWorkgroups = 2048;
     BfSplit g;
     g.nrb = (int)(rows / wg_rows);
-    int64_t want = (kTargetWorkgroups + g.nrb - 1) / g.nrb;
+    int64_t want = (target + g.nrb - 1) / g.nrb;
     if (want > max_split) want = max_split;
     if (want > nst) want = nst;
     if (want < 1) want = 1;
@@ -1439,10 +1519,12 @@ static BfSplit bf16_split(int64_t rows, int wg_rows, int64_t nst, int64_t max_sp
 }
 
 // The same for the FP64 limb products, with at most kLimbMaxSt super-tiles per split.
-static BfSplit limb_split(int64_t rows, int wg_rows, int64_t nst, int64_t max_split)
+static BfSplit limb_split(int64_t rows, int wg_rows, int64_t nst, int64_t max_split,
+                          int64_t target = 2048)
 {
     const int64_t min_split = (nst + kLimbMaxSt - 1) / kLimbMaxSt;
-    BfSplit g = bf16_split(rows, wg_rows, nst, max_split > min_split ? max_split : min_split);
+    BfSplit g = bf16_split(rows, wg_rows, nst, max_split > min_split ? max_split : min_split,
+                           target);
     if (g.st_per > kLimbMaxSt) {
         g.st_per = kLimbMaxSt;
         g.nsplit = (int)((nst + g.st_per - 1) / g.st_per);
@@ -1481,7 +1563,14 @@ MixedShape mixed_shape(int64_t n, int64_t p)
     const int64_t mbytes = m.nI * m.ldI;
     // FP64 limb products: partial traffic (8 B per row and split) at most 1/16
     // of the matrix, K splits of at most 2^20 (exact limb sums)
-    m.limbW = limb_split(m.nI, kMxWaves * kRTv * 16, m.nstW, mbytes / (16 * 8 * m.nI));
+    // A v: about eight rounds of the 768 workgroups the chip holds at once (three
+    // per CU), so that the last round is a small share, but K splits of at
+    // least 12 super-tiles; measured at 10,000 x 100,000 and 50,000 x 500,000,
+    // where 8 splits (two rounds and a sliver) took 10% longer than 32
+    int64_t limb_capW = m.nstW / 12;
+    if (limb_capW < 1) limb_capW = 1;
+    if (limb_capW > mbytes / (16 * 8 * m.nI)) limb_capW = mbytes / (16 * 8 * m.nI);
+    m.limbW = limb_split(m.nI, kMxWaves * kRTv * 16, m.nstW, limb_capW, 6144);
     m.limbX = limb_split(m.pS, kMxWaves * kRTu * 16, m.nstX, mbytes / (16 * 8 * m.pS));
     for (int c = 0; c < 3; ++c) {
         const int64_t kcs = c == 0 ? 8 : 16 * c;

@@ -9,20 +9,6 @@
 
 namespace gkl {
 
-// Counts of codes 1, 2, 3 in one 32-bit word holding 16 codes; `valid` low codes
-// are real individuals (the rest is padding and ignored).
-__device__ __forceinline__ void count_word(uint32_t w, int valid, int64_t& c1, int64_t& c2,
-                                           int64_t& c3)
-{
-    const uint32_t keep = valid >= 16 ? 0xFFFFFFFFu : ((1u << (2 * valid)) - 1u);
-    w &= keep;
-    const uint32_t lo = w & 0x55555555u;
-    const uint32_t hi = (w >> 1) & 0x55555555u;
-    c1 += __popc(lo & ~hi);
-    c2 += __popc(hi & ~lo);
-    c3 += __popc(lo & hi);
-}
-
 // One wavefront per SNP column; lanes stride over the column's bytes.
 __global__ void __launch_bounds__(256) colstats_kernel(const uint8_t* __restrict__ G, int64_t n,
                                                        int64_t p, int64_t ld, ColStats st)
@@ -32,40 +18,25 @@ __global__ void __launch_bounds__(256) colstats_kernel(const uint8_t* __restrict
     if (j >= p) return;
     const uint8_t* col = G + j * ld;
     const int64_t nbytes = (n + 3) / 4;
+    // columns 4-byte aligned: dword loads; else assembled from byte loads
+    const bool aligned = (ld & 3) == 0 && (reinterpret_cast<uintptr_t>(G) & 3) == 0;
     int64_t c1 = 0, c2 = 0, c3 = 0;
-    // 4 bytes per lane per iteration, assembled from byte loads (columns need
-    // not be 4-byte aligned)
+    // 4 bytes per lane per iteration
     for (int64_t b = (int64_t)lane * 4; b < nbytes; b += 256) {
         uint32_t w = 0;
-        int nb = (int)(nbytes - b < 4 ? nbytes - b : 4);
-        for (int t = 0; t < nb; ++t) w |= (uint32_t)col[b + t] << (8 * t);
+        if (aligned && b + 4 <= nbytes) {
+            w = *reinterpret_cast<const uint32_t*>(col + b);
+        } else {
+            const int nb = (int)(nbytes - b < 4 ? nbytes - b : 4);
+            for (int t = 0; t < nb; ++t) w |= (uint32_t)col[b + t] << (8 * t);
+        }
         int64_t valid = n - b * 4;
         count_word(w, valid >= 16 ? 16 : (int)valid, c1, c2, c3);
     }
     c1 = wave_sum_i64(c1);
     c2 = wave_sum_i64(c2);
     c3 = wave_sum_i64(c3);
-    if (lane == 0) {
-#pragma clang fp contract(off)
-        const int64_t nobs = n - c3;
-        const int64_t cnt = c1 + 2 * c2;
-        double mu = 0.0, s = 0.0;
-        if (nobs > 0) {
-            mu = (double)cnt / (double)nobs;
-            const double f = 0.5 * mu;
-            const double t = 1.0 - f;
-            const double var = mu * t;
-            if (var > 0.0) {
-                const double d = sqrt(var);
-                s = 1.0 / d;
-            }
-        }
-        st.count[j] = cnt;
-        st.nobs[j] = nobs;
-        st.n3[j] = c3;
-        st.mean[j] = mu;
-        st.inv_sd[j] = s;
-    }
+    if (lane == 0) store_colstats(st, j, n, c1, c2, c3);
 }
 
 void launch_colstats(const uint8_t* G, int64_t n, int64_t p, int64_t ld, const ColStats& st,

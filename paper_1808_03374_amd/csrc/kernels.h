@@ -14,6 +14,47 @@ struct ColStats {
     double* inv_sd;   // s_j
 };
 
+// Counts of codes 1, 2, 3 in one 32-bit word holding 16 codes; `valid` low codes
+// are real individuals (the rest is padding and ignored).
+__device__ __forceinline__ void count_word(uint32_t w, int valid, int64_t& c1, int64_t& c2,
+                                           int64_t& c3)
+{
+    const uint32_t keep = valid >= 16 ? 0xFFFFFFFFu : ((1u << (2 * valid)) - 1u);
+    w &= keep;
+    const uint32_t lo = w & 0x55555555u;
+    const uint32_t hi = (w >> 1) & 0x55555555u;
+    c1 += __popc(lo & ~hi);
+    c2 += __popc(hi & ~lo);
+    c3 += __popc(lo & hi);
+}
+
+// Column j's statistics from its exact code counts: mean = (n1 + 2 n2) / nobs
+// and scale 1/sqrt(2 f (1 - f)) with f = mean/2, in one fixed order of correctly
+// rounded operations (every kernel that forms them calls this).
+__device__ __forceinline__ void store_colstats(const ColStats& st, int64_t j, int64_t n,
+                                               int64_t c1, int64_t c2, int64_t c3)
+{
+#pragma clang fp contract(off)
+    const int64_t nobs = n - c3;
+    const int64_t cnt = c1 + 2 * c2;
+    double mu = 0.0, s = 0.0;
+    if (nobs > 0) {
+        mu = (double)cnt / (double)nobs;
+        const double f = 0.5 * mu;
+        const double t = 1.0 - f;
+        const double var = mu * t;
+        if (var > 0.0) {
+            const double d = sqrt(var);
+            s = 1.0 / d;
+        }
+    }
+    st.count[j] = cnt;
+    st.nobs[j] = nobs;
+    st.n3[j] = c3;
+    st.mean[j] = mu;
+    st.inv_sd[j] = s;
+}
+
 // K-split geometry of a matrix-core product: nsplit splits of st_per super-tiles,
 // nrb row blocks, xcd = 1 when the workgroups of one split share an XCD.
 struct BfSplit {
@@ -352,9 +393,10 @@ struct MixedWork {
 MixedShape mixed_shape(int64_t n, int64_t p);
 size_t mixed_frag_bytes(const MixedShape& m);
 size_t mixed_partial_elems(const MixedShape& m);
-// Either layout pointer may be NULL (that layout is not built).
+// Either layout pointer may be NULL (that layout is not built).  With st, the
+// pass that builds S also writes the column statistics (as launch_colstats).
 void build_mixed_layouts(const uint8_t* G, int64_t n, int64_t p, int64_t ld, uint8_t* I,
-                         uint8_t* S, hipStream_t s);
+                         uint8_t* S, hipStream_t s, const ColStats* st = nullptr);
 // FP64 A v and A^T u in seven int8 limbs (layouts I and S): the colsum,
 // fragment and matrix-core kernels, leaving per-split partials in w.partial
 // (stride ms.nI for A v, ms.pS for A^T u) in the form the FP64 reduce kernels

@@ -192,15 +192,19 @@ def test_fp64_products_option_is_validated(gk):
 
 
 @pytest.mark.parametrize("choice,n,p,expect", [
-    ("AUTO", 2000, 9000, "LUT"), ("AUTO", 40000, 110000, "LUT_LIMBS"), ("LUT", 40000, 110000, "LUT"),
+    ("AUTO", 2000, 9000, "LUT"), ("AUTO", 4000, 249999, "LUT"), ("AUTO", 4000, 250000, "LIMBS"),
+    ("AUTO", 40000, 110000, "LIMBS"), ("LUT", 40000, 110000, "LUT"),
     ("LIMBS", 200, 900, "LIMBS"), ("LUT_LIMBS", 200, 900, "LUT_LIMBS")])
 def test_fp64_products_reported(gk, choice, n, p, expect):
     # the format a solve ran in is reported; GKL_FP64_AUTO takes the limbs for
-    # A^T u from n p >= 4e9 on
-    g, Gd = gen("c1", n, p)
-    ctx = gk.Context(Gd, n, p, 2, tol=1e-6, krylov_dim=8,
+    # both products from n p >= 1e9 on (random bytes: the choice depends on the
+    # shape only)
+    gen_ = torch.Generator(device="cuda").manual_seed(n + p)
+    Gd = torch.randint(0, 256, (p, (n + 3) // 4), dtype=torch.uint8, device="cuda", generator=gen_)
+    ctx = gk.Context(Gd, n, p, 2, tol=1e-6, krylov_dim=8, max_matvecs=64,
                      fp64_products=getattr(gk, "GKL_FP64_" + choice))
     _, _, _, st, info = ctx.solve()
     ctx.close()
-    assert st == gk.GKL_OK
+    assert st in (gk.GKL_OK, gk.GKL_NOT_CONVERGED)
+    assert info.matvecs > 0
     assert info.fp64_products == getattr(gk, "GKL_FP64_" + expect)
