@@ -755,6 +755,11 @@ def main():
     other = [key for key in prod if key != dom][0]
     dom_avg = prod[dom]["avg_ms"]
     achieved = nbytes / (dom_avg * 1e-3) / 1e9
+    # the read rate this GPU reaches in practice: a plain streaming read of the
+    # same packed matrix (the product kernels stream it once per product)
+    read_ms = gk.gkl_read_rate(W.G, reps=5, stream=stream)
+    read_gbps = W.G.numel() / (read_ms * 1e-3) / 1e9
+    log(f"[bench] plain streaming read of the packed matrix: {read_ms:.3f} ms, {read_gbps:.0f} GB/s")
     line = {
         "metric": METRIC,
         "value": sec_per_step,
@@ -792,6 +797,8 @@ def main():
             "launches": int(prod[dom]["launches"]),
             "timed_one_launch_in": TIMING_STRIDE,
             "algorithmic_bytes_per_launch": int(nbytes),
+            "read_ceiling_GBps": read_gbps,
+            "frac_of_read_ceiling": achieved / read_gbps,
             "other_kernel": {"kernel": other, "avg_launch_ms": prod[other]["avg_ms"],
                              "achieved_GBps": prod[other]["GBps"],
                              "traffic": measured_traffic(wl["name"], other)},

@@ -340,6 +340,21 @@ gkl_status gkl_dense_svd(const double* B, int32_t m, double* P, double* S, doubl
 gkl_status gkl_dense_svd_noalloc(const double* B, int32_t m, double* P, double* S, double* Q,
                                  void* stream);
 
+/*
+ * gkl_read_rate -- diagnostic, not part of the method: the time of a plain
+ * streaming read of `bytes` bytes of device memory at buf (each workgroup reads
+ * one contiguous megabyte in 16-byte loads; nothing is written), averaged over
+ * `reps` launches on `stream` (NULL = default) after one untimed launch.  It
+ * measures the read rate this GPU achieves in practice, the ceiling against
+ * which the product kernels, which stream the packed matrix once per product,
+ * are judged.  buf must be 16-byte aligned; bytes >= 16 (a tail that is not a
+ * multiple of 16 is not read).  *ms_per_read (host) receives milliseconds.
+ * Errors: GKL_ERR_INVALID (NULL pointer, misaligned buf, bytes < 16,
+ * reps < 1), GKL_ERR_DEVICE.
+ */
+gkl_status gkl_read_rate(const void* buf, int64_t bytes, int32_t reps, void* stream,
+                         double* ms_per_read);
+
 #ifdef __cplusplus
 }
 #endif

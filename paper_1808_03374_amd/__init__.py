@@ -16,6 +16,6 @@ from ._binding import (  # noqa: F401
     gkl_options, gkl_info, lib, library_path, gkl_options_default, gkl_status_string,
     gkl_last_error, gkl_create, gkl_create_ex, gkl_solve, gkl_destroy, gkl_create_batched,
     gkl_solve_batched, gkl_create_loco, gkl_column_stats, gkl_unpack, gkl_matvec, gkl_rmatvec,
-    gkl_matmat_mixed, gkl_rmatmat_mixed, gkl_get_trace, gkl_dense_svd, gkl_dense_svd_noalloc, gkl_batched_plan,
+    gkl_matmat_mixed, gkl_rmatmat_mixed, gkl_get_trace, gkl_dense_svd, gkl_dense_svd_noalloc, gkl_read_rate, gkl_batched_plan,
     Context, BatchedContext, LocoContext, solve, declared_functions,
 )

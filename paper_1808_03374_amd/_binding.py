@@ -135,6 +135,7 @@ _SIGS = {
     "gkl_get_trace": (_st, [_vp, _vp, _i64, ctypes.POINTER(_i64)]),
     "gkl_dense_svd": (_st, [_vp, _i32, _vp, _vp, _vp, _vp]),
     "gkl_dense_svd_noalloc": (_st, [_vp, _i32, _vp, _vp, _vp, _vp]),
+    "gkl_read_rate": (_st, [_vp, _i64, _i32, _vp, ctypes.POINTER(_dbl)]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(lib, _name)
@@ -287,6 +288,14 @@ def gkl_dense_svd(B, m, P, S, Q, stream=None):
 
 def gkl_dense_svd_noalloc(B, m, P, S, Q, stream=None):
     _check(lib.gkl_dense_svd_noalloc(_ptr(B), m, _ptr(P), _ptr(S), _ptr(Q), stream))
+
+
+def gkl_read_rate(buf, reps=5, stream=None):
+    """Milliseconds of one plain streaming read of the device tensor buf."""
+    ms = _dbl(0.0)
+    nbytes = buf.numel() * buf.element_size()
+    _check(lib.gkl_read_rate(_ptr(buf), nbytes, reps, stream, ctypes.byref(ms)))
+    return ms.value
 
 
 # ---------------------------------------------------------------------------

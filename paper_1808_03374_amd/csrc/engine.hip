@@ -983,6 +983,37 @@ static double* noalloc_scratch()
 
 extern "C" {
 
+gkl_status gkl_read_rate(const void* buf, int64_t bytes, int32_t reps, void* stream,
+                         double* ms_per_read)
+{
+    if (!buf || !ms_per_read)
+        return set_error(nullptr, GKL_ERR_INVALID, "gkl_read_rate: NULL pointer argument");
+    if ((reinterpret_cast<uintptr_t>(buf) & 15) != 0 || bytes < 16 || reps < 1)
+        return set_error(nullptr, GKL_ERR_INVALID,
+                         "gkl_read_rate: buf must be 16-byte aligned, bytes >= 16, reps >= 1");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    try {
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        GKL_HIP(hipEventCreate(&e0));
+        GKL_HIP(hipEventCreate(&e1));
+        launch_read_rate(buf, bytes, s);
+        GKL_HIP(hipEventRecord(e0, s));
+        for (int r = 0; r < reps; ++r) launch_read_rate(buf, bytes, s);
+        GKL_HIP(hipEventRecord(e1, s));
+        GKL_HIP(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        GKL_HIP(hipEventElapsedTime(&ms, e0, e1));
+        *ms_per_read = (double)ms / reps;
+        GKL_HIP(hipEventDestroy(e0));
+        GKL_HIP(hipEventDestroy(e1));
+        return GKL_OK;
+    } catch (const Error& e) {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        return set_error(nullptr, e.status, e.msg);
+    }
+}
+
 gkl_status gkl_dense_svd_noalloc(const double* B, int32_t m, double* P, double* S, double* Q,
                                  void* stream)
 {

@@ -78,5 +78,35 @@ void launch_unpack(const uint8_t* G, int64_t n, int64_t p, int64_t ld, int8_t* o
     GKL_LAUNCH_CHECK("unpack_kernel");
 }
 
-}  // namespace gkl
+// Plain streaming read (diagnostic): workgroup b reads 16-byte words
+// [b per, (b + 1) per) with four loads in flight per thread and folds them; the
+// fold is stored only when `sink` is non-NULL, which the host never passes, so
+// the loads stay and nothing is written.
+__global__ void __launch_bounds__(256) read_rate_kernel(const uint4* __restrict__ src, int64_t n16,
+                                                        int64_t per, uint32_t* __restrict__ sink)
+{
+    uint32_t acc = 0;
+    const int64_t b0 = (int64_t)blockIdx.x * per;
+    const int64_t e = b0 + per < n16 ? b0 + per : n16;
+    for (int64_t i = b0 + threadIdx.x; i < e; i += 4 * 256) {
+        uint4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = i + u * 256 < e ? src[i + u * 256] : make_uint4(0, 0, 0, 0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc ^= v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
+    }
+    if (sink) sink[(int64_t)blockIdx.x * blockDim.x + threadIdx.x] = acc;
+}
 
+void launch_read_rate(const void* buf, int64_t bytes, hipStream_t s)
+{
+    constexpr int64_t kPer = 65536;   // 16-byte words per workgroup (1 MB)
+    const int64_t n16 = bytes / 16;
+    const int64_t blocks = (n16 + kPer - 1) / kPer;
+    if (blocks > 0x7fffffff) fail(GKL_ERR_INVALID, "gkl_read_rate: buffer too large");
+    hipLaunchKernelGGL(read_rate_kernel, dim3((unsigned int)blocks), dim3(256), 0, s,
+                       static_cast<const uint4*>(buf), n16, kPer, nullptr);
+    GKL_LAUNCH_CHECK("read_rate_kernel");
+}
+
+}  // namespace gkl

@@ -115,6 +115,8 @@ void launch_colstats(const uint8_t* G, int64_t n, int64_t p, int64_t ld, const C
                      hipStream_t s);
 void launch_unpack(const uint8_t* G, int64_t n, int64_t p, int64_t ld, int8_t* out,
                    hipStream_t s);
+// Plain streaming read of `bytes` bytes (the read-rate diagnostic).
+void launch_read_rate(const void* buf, int64_t bytes, hipStream_t s);
 // Layout shapes, sizes and the builders (from the caller's SNP-major G).
 void layout_shape(int64_t n, int64_t p, Packed& L);
 size_t layout_T_bytes(const Packed& L);
