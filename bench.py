@@ -63,9 +63,12 @@ def fp64_bytes(n, p):
     return ((n + 3) // 4) * p + 16 * p + 16 * n
 
 
-def block_bytes(n, p, b):
-    """Algorithmic bytes of one block product of b vectors."""
-    return ((n + 3) // 4) * p + b * (4 * p + 8 * n)
+def block_bytes(n, p, b, transpose=False):
+    """Algorithmic bytes of one block product of b vectors: the packed matrix,
+    the vector block read once as split BF16 (hi + lo, 4 bytes per entry) and
+    the FP64 result written (A W: W is p x b, Y n x b; A^T X: X n x b, Z p x b)."""
+    rows_in, rows_out = (n, p) if transpose else (p, n)
+    return ((n + 3) // 4) * p + b * (4 * rows_in + 8 * rows_out)
 
 
 # FP64 product format of the FP64 solves: (gkl_fp64_products value, name)
@@ -286,7 +289,6 @@ def blocked_solve(gk, torch, W, b, fmt, ref, stream, reps=1, probe=None, probe_Y
     gated = bound <= ANGLE_TARGET
     gated[-1] = False          # the gap below sigma_k is not known
     last = infos[-1]
-    nbytes = block_bytes(n, p, b)
     out = {"format": fmt, "block_width": b, "tol": BLOCKED_TOL, "status": int(st),
            "solve_s": float(np.mean(times)), "create_s": float(np.mean([i.create_ms for i in infos])) / 1e3,
            "converged": int(last.converged), "matvecs": int(last.matvecs),
@@ -316,6 +318,7 @@ def blocked_solve(gk, torch, W, b, fmt, ref, stream, reps=1, probe=None, probe_Y
              sum(i.timed_rmatvecs for i in infos))):
         avg = total / max(cnt, 1)
         avg_core = core / max(cnt, 1)
+        nbytes = block_bytes(n, p, b, transpose=name == "A^T X")
         d = {"chain_avg_ms": avg, "core_kernel_avg_ms": avg_core, "launches": int(cnt),
              "algorithmic_bytes": int(nbytes),
              "chain_GBps": nbytes / (avg * 1e-3) / 1e9 if avg > 0 else None}
@@ -667,7 +670,7 @@ def product_bench(gk, torch, wl, widths, reps):
                     z, tz = timed(lambda: ctx.rmatmat_mixed(Xv[:, :b]))
                     out["blocked"][f"{fmt}_b{b}"] = {
                         "A W ms": ty * 1e3, "A W GBps": block_bytes(n, p, b) / ty / 1e9,
-                        "A^T X ms": tz * 1e3, "A^T X GBps": block_bytes(n, p, b) / tz / 1e9,
+                        "A^T X ms": tz * 1e3, "A^T X GBps": block_bytes(n, p, b, True) / tz / 1e9,
                         "A W rel err": float(torch.linalg.norm(y - Y0[:, :b]) / torch.linalg.norm(Y0[:, :b])),
                         "A^T X rel err": float(torch.linalg.norm(z - Z0[:, :b]) / torch.linalg.norm(Z0[:, :b]))}
                     log(f"[bench] product bench {fmt} b={b}: {out['blocked'][f'{fmt}_b{b}']}")
