@@ -233,15 +233,18 @@ def product_stats(infos, nbytes, products="lut"):
                 "GBps": nbytes / (rmv_avg * 1e-3) / 1e9}}
 
 
-def blocked_solve(gk, torch, W, b, fmt, ref, stream, reps=1, probe=None, probe_Y=None):
-    """Top-k by the blocked path (block width b, products in split BF16 or int8
-    limbs) at tolerance BLOCKED_TOL: one warm-up solve, then `reps` timed ones;
-    errors against the FP64 reference solve `ref`."""
+def blocked_solve(gk, torch, W, b, fmt, ref, stream, reps=1, probe=None, probe_Y=None, tol=None):
+    """Top-k by the blocked path (block width b, products in split BF16, int8
+    limbs, or FP64-exact limb pairs for fmt "fp64") at tolerance tol (default
+    BLOCKED_TOL): one warm-up solve, then `reps` timed ones; errors against the
+    FP64 reference solve `ref`."""
     import numpy as np
     n, p, k = W.n, W.p, W.k
+    tol = BLOCKED_TOL if tol is None else tol
     v0 = torch.from_numpy(np.ascontiguousarray(
         np.random.default_rng([1, 0x6D6978]).standard_normal((b, p)))).cuda()
-    precision = gk.GKL_PREC_MIXED if fmt == "bf16" else gk.GKL_PREC_MIXED_INT8
+    precision = {"bf16": gk.GKL_PREC_MIXED, "int8": gk.GKL_PREC_MIXED_INT8,
+                 "fp64": gk.GKL_PREC_BLOCK_FP64}[fmt]
     opts = dict(v0=v0, precision=precision, block_width=b, timing=TIMING_STRIDE, stream=stream)
     sig = torch.empty(k, dtype=torch.float64, device="cuda")
     U = torch.empty((k, n), dtype=torch.float64, device="cuda")
@@ -249,7 +252,7 @@ def blocked_solve(gk, torch, W, b, fmt, ref, stream, reps=1, probe=None, probe_Y
     eps_op = eps_rel = None
     infos, times = [], []
     for rep in range(reps + 1):
-        ctx = gk.Context(W.G, n, p, k, BLOCKED_TOL, gk.GKL_REORTH_FULL, **opts)
+        ctx = gk.Context(W.G, n, p, k, tol, gk.GKL_REORTH_FULL, **opts)
         try:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -284,12 +287,12 @@ def blocked_solve(gk, torch, W, b, fmt, ref, stream, reps=1, probe=None, probe_Y
     # eps * sigma_1 / (delta_i sigma_i) on its error is itself below the target,
     # with eps the solve tolerance plus the measured product error
     # ||dY|| / (sigma_1 ||w||) on random unit vectors
-    eps = BLOCKED_TOL + (eps_op or 0.0)
+    eps = tol + (eps_op or 0.0)
     bound = eps * ref["sigma"][0] / (gaps * ref["sigma"])
     gated = bound <= ANGLE_TARGET
     gated[-1] = False          # the gap below sigma_k is not known
     last = infos[-1]
-    out = {"format": fmt, "block_width": b, "tol": BLOCKED_TOL, "status": int(st),
+    out = {"format": fmt, "block_width": b, "tol": tol, "status": int(st),
            "solve_s": float(np.mean(times)), "create_s": float(np.mean([i.create_ms for i in infos])) / 1e3,
            "converged": int(last.converged), "matvecs": int(last.matvecs),
            "passes_over_G": int(last.passes_over_G), "block_steps": int(last.steps),
@@ -307,9 +310,14 @@ def blocked_solve(gk, torch, W, b, fmt, ref, stream, reps=1, probe=None, probe_Y
         # tile), else 4 per 16 columns; 2 x 16 x 16 x 32 flop each
         exec_flop = 2.0 * 16 * n * p * (2 if b <= 8 else 4 * ((b + 15) // 16))
         peak = MFMA_BF16_PEAK_TFLOPS
-    else:
+    elif fmt == "int8":
         tiles = 2 if b <= 8 else 3 * ((b + 15) // 16)
         exec_flop = 2.0 * 2 * 16 * tiles * n * p
+        peak = MFMA_INT8_PEAK_TOPS
+    else:
+        # one 16-column tile (two vectors' seven limbs) per pass: code and flag
+        # MFMAs of 16 x 16 x 64, 2 x 16 ops per genotype and operand
+        exec_flop = 2.0 * 2 * 16 * n * p * ((b + 1) // 2)
         peak = MFMA_INT8_PEAK_TOPS
     for name, total, core, cnt in (
             ("A W", sum(i.matvec_kernel_ms for i in infos), sum(i.matvec_core_ms for i in infos),
@@ -358,6 +366,16 @@ def run_compare(gk, torch, W, ref, args, stream):
                                                    / (res["solve_s"] + res["create_s"]))
             out[key] = res
             torch.cuda.empty_cache()
+    # the blocked path with FP64-exact products (seven int8 limbs, two columns
+    # per pass) at the FP64 tolerance: the same accuracy as the headline solve
+    for b in args.fp64_block_widths:
+        res = blocked_solve(gk, torch, W, b, "fp64", ref, stream, reps=args.blocked_reps,
+                            tol=W.wl["tol"])
+        res["speedup_vs_fp64"] = ref["sec_per_step"] / (res["solve_s"] + res["create_s"])
+        out[f"fp64_block_b{b}"] = res
+        log(f"[bench] fp64 block b={b}: {res['solve_s']:.3f} s + {res['create_s']:.3f} s create, "
+            f"sigma err {res['sigma_max_rel_err_vs_fp64']:.1e}, speedup {res['speedup_vs_fp64']:.2f}")
+        torch.cuda.empty_cache()
     return out
 
 
@@ -693,6 +711,9 @@ def main():
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the blocked solves and the FP64 solve at the blocked tolerance")
     ap.add_argument("--widths", default="8,16,32", help="block widths of the blocked solves")
+    ap.add_argument("--fp64-block-widths", default="2",
+                    help="block widths of the blocked solves with FP64-exact products, at the FP64 "
+                         "tolerance ('' for none)")
     ap.add_argument("--formats", default="bf16",
                     help="blocked product formats: bf16 (split BF16), int8 (int8 limbs)")
     ap.add_argument("--blocked-reps", type=int, default=1)
@@ -720,6 +741,7 @@ def main():
                         args.fp64_products]
     args.widths = [int(x) for x in args.widths.split(",") if x]
     args.formats = [x for x in args.formats.split(",") if x]
+    args.fp64_block_widths = [int(x) for x in args.fp64_block_widths.split(",") if x]
 
     import numpy as np
     import torch

@@ -82,8 +82,15 @@ enum gkl_reorth { GKL_REORTH_FULL = 0, GKL_REORTH_PARTIAL = 1, GKL_REORTH_ONESID
  * GKL_PREC_MIXED_INT8: the same blocked GKL with the products on the int8
  * matrix cores: the vector block is rounded per column to 22-bit integers
  * (power-of-two column scale) in three 8-bit limbs and accumulated exactly in
- * int32, so the products' only rounding is that quantisation. */
-enum gkl_precision { GKL_PREC_FP64 = 0, GKL_PREC_MIXED = 1, GKL_PREC_MIXED_INT8 = 2 };
+ * int32, so the products' only rounding is that quantisation.
+ * GKL_PREC_BLOCK_FP64: the same blocked GKL with FP64-accurate block products:
+ * each column is rounded to a 52-bit integer of a power-of-two scale and split
+ * into seven 8-bit limbs (as GKL_FP64_LIMBS); two columns share one pass over
+ * the matrix (their 14 limb columns fill one 16-column MFMA tile), so a block of
+ * b vectors costs ceil(b/2) passes. */
+enum gkl_precision {
+    GKL_PREC_FP64 = 0, GKL_PREC_MIXED = 1, GKL_PREC_MIXED_INT8 = 2, GKL_PREC_BLOCK_FP64 = 3
+};
 /* How a GKL_PREC_FP64 context forms its products A v and A^T u (Section 3: one
  * of each per Lanczos step).  Both are FP64-accurate and pass the same parity
  * tests.  GKL_FP64_LUT: 256-entry FP64 tables per four genotypes in LDS, one
@@ -295,9 +302,10 @@ gkl_status gkl_rmatvec(gkl_ctx* ctx, const double* u, double* z);
  * Lanczos, Section 5), through the matrix-core path of the context's precision
  * (GKL_PREC_MIXED: W split into bf16 hi + lo, FP32 accumulate per K-chunk, FP64
  * across chunks; GKL_PREC_MIXED_INT8: W in exact int8 limbs of a 22-bit
- * per-column fixed point, int32 accumulation), with FP64 centring and
- * missing-value terms.  Needs a blocked context; an FP64 one gives
- * GKL_ERR_INVALID. */
+ * per-column fixed point, int32 accumulation; GKL_PREC_BLOCK_FP64: seven limbs
+ * of a 52-bit fixed point, FP64-accurate, one pass per pair of columns), with
+ * FP64 centring and missing-value terms.  Needs a blocked context; an FP64 one
+ * gives GKL_ERR_INVALID. */
 gkl_status gkl_matmat_mixed(gkl_ctx* ctx, const double* W, int32_t b, double* Y);
 /* Z = A^T X for b columns (X: n x b, Z: p x b), the same matrix-core path and
  * the same requirements. */

@@ -23,6 +23,7 @@ GKL_REORTH_ONESIDED = 2
 GKL_PREC_FP64 = 0
 GKL_PREC_MIXED = 1
 GKL_PREC_MIXED_INT8 = 2
+GKL_PREC_BLOCK_FP64 = 3
 GKL_FP64_AUTO = 0
 GKL_FP64_LUT = 1
 GKL_FP64_LIMBS = 2

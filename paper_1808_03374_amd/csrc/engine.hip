@@ -720,7 +720,7 @@ static gkl_status validate(const uint8_t* G, int64_t n, int64_t p, int32_t k, do
     if (o->ld_bytes != 0 && o->ld_bytes < (n + 3) / 4)
         return set_error(nullptr, GKL_ERR_INVALID, "ld_bytes < ceil(n/4)");
     if (o->precision != GKL_PREC_FP64 && o->precision != GKL_PREC_MIXED &&
-        o->precision != GKL_PREC_MIXED_INT8)
+        o->precision != GKL_PREC_MIXED_INT8 && o->precision != GKL_PREC_BLOCK_FP64)
         return set_error(nullptr, GKL_ERR_INVALID, "unknown precision");
     if (o->block_width < 0 || o->block_width > 32)
         return set_error(nullptr, GKL_ERR_INVALID, "block_width must lie in [0, 32]");

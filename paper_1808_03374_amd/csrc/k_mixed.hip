@@ -1241,73 +1241,83 @@ __device__ __forceinline__ int64_t quantise52(double x, int ex)
     return (int64_t)rint(ldexp(x, kQ64 - ex));
 }
 
-// Limb fragments of one vector (kOps = 1: x; kOps = 2: w = s v and z = (mu - 3) w).
-// One workgroup per super-tile of 256 contraction indices, one thread per index:
+// Limb fragments of kVec vectors (kVec <= 2; kOps = 1: x; kOps = 2: w = s v and
+// z = (mu - 3) w), vector c at x + c ldx with its own scale 2^ex[c].  One
+// workgroup per super-tile of 256 contraction indices, one thread per index:
 // the thread quantises its entries once and writes their seven limbs as bytes
 // of the fragment image in LDS, which the workgroup then stores as whole
 // operands.  frag[((st * kWords + word) * kOps + op) * 64 + lane]: byte e of
-// lane (g, col) holds index st*256 + 64 g + 16 word + code_of_elem(e), limb col
-// (zero for col >= 7).
-template <int kOps>
-__device__ __forceinline__ void limb_frag_body(const double* __restrict__ x, int64_t len,
-                                               const double* __restrict__ mean,
+// lane (g, col) holds index st*256 + 64 g + 16 word + code_of_elem(e), limb
+// col - 7c of vector c = col / 7 (zero for col >= 7 kVec): the seven limb
+// columns of two vectors fill 14 of the 16 columns of one MFMA tile, so a pair
+// costs the matrix cores what one vector does.
+template <int kOps, int kVec>
+__device__ __forceinline__ void limb_frag_body(const double* __restrict__ x, int64_t ldx,
+                                               int64_t len, const double* __restrict__ mean,
                                                const double* __restrict__ inv_sd,
                                                const double* __restrict__ cmax,
                                                i32x4* __restrict__ frag, int64_t st)
 {
+    static_assert(kVec == 1 || kVec == 2, "one or two vectors per MFMA tile");
     __shared__ i32x4 img[kWords * kOps * 64];
-    __shared__ int ex[1];
-    column_scales(cmax, 1, ex);
+    __shared__ int ex[kVec];
+    column_scales(cmax, kVec, ex);
     for (int q = threadIdx.x; q < kWords * kOps * 64; q += 256) img[q] = i32x4{0, 0, 0, 0};
     __syncthreads();
     const int o = threadIdx.x;                       // index within the super-tile
     const int64_t j = st * kSuper + o;
     const int g = o >> 6, word = (o >> 4) & 3, c = o & 15;
     const int e = (c & 3) * 4 + (c >> 2);            // code_of_elem(e) == c
-    double val[kOps];
-    if (kOps == 2) {
-        const double w = j < len ? inv_sd[j] * x[j] : 0.0;
-        val[0] = w;
-        val[kOps - 1] = j < len ? (mean[j] - 3.0) * w : 0.0;
-    } else {
-        val[0] = j < len ? x[j] : 0.0;
-    }
     uint8_t* bytes = reinterpret_cast<uint8_t*>(img);
 #pragma unroll
-    for (int op = 0; op < kOps; ++op) {
-        int64_t q = quantise52(val[op], ex[0]);
-        int lim[kLimbs];
-#pragma unroll
-        for (int k = kLimbs - 1; k >= 1; --k) {
-            lim[k] = (int)(((q + 128) & 255) - 128);
-            q = (q - lim[k]) >> 8;
+    for (int vc = 0; vc < kVec; ++vc) {
+        const double* xv = x + (int64_t)vc * ldx;
+        double val[kOps];
+        if (kOps == 2) {
+            const double w = j < len ? inv_sd[j] * xv[j] : 0.0;
+            val[0] = w;
+            val[kOps - 1] = j < len ? (mean[j] - 3.0) * w : 0.0;
+        } else {
+            val[0] = j < len ? xv[j] : 0.0;
         }
-        lim[0] = (int)q;
 #pragma unroll
-        for (int l = 0; l < kLimbs; ++l)
-            bytes[(((word * kOps + op) * 64) + g * 16 + l) * 16 + e] = (uint8_t)(lim[l] & 0xFF);
+        for (int op = 0; op < kOps; ++op) {
+            int64_t q = quantise52(val[op], ex[vc]);
+            int lim[kLimbs];
+#pragma unroll
+            for (int k = kLimbs - 1; k >= 1; --k) {
+                lim[k] = (int)(((q + 128) & 255) - 128);
+                q = (q - lim[k]) >> 8;
+            }
+            lim[0] = (int)q;
+#pragma unroll
+            for (int l = 0; l < kLimbs; ++l)
+                bytes[(((word * kOps + op) * 64) + g * 16 + kLimbs * vc + l) * 16 + e] =
+                    (uint8_t)(lim[l] & 0xFF);
+        }
     }
     __syncthreads();
     i32x4* f = frag + st * (kWords * kOps * 64);
     for (int q = threadIdx.x; q < kWords * kOps * 64; q += 256) f[q] = img[q];
 }
 
-template <int kOps>
+template <int kOps, int kVec>
 __global__ void __launch_bounds__(256)
-limb_frag_kernel(const double* __restrict__ x, int64_t len, const double* __restrict__ mean,
-                 const double* __restrict__ inv_sd, const double* __restrict__ cmax,
-                 i32x4* __restrict__ frag)
+limb_frag_kernel(const double* __restrict__ x, int64_t ldx, int64_t len,
+                 const double* __restrict__ mean, const double* __restrict__ inv_sd,
+                 const double* __restrict__ cmax, i32x4* __restrict__ frag)
 {
-    limb_frag_body<kOps>(x, len, mean, inv_sd, cmax, frag, blockIdx.x);
+    limb_frag_body<kOps, kVec>(x, ldx, len, mean, inv_sd, cmax, frag, blockIdx.x);
 }
 
-// Element e of accumulator a recombined from the seven limb columns of the
-// lane's 16-lane group (every lane calls it; the value is that of its group).
-__device__ __forceinline__ double limb_sum(const i32x4& a, int e, int lane)
+// Element e of accumulator a recombined from the seven limb columns base ..
+// base + 6 of the lane's 16-lane group (every lane calls it; the value is that
+// of its group).
+__device__ __forceinline__ double limb_sum(const i32x4& a, int e, int lane, int base = 0)
 {
     int32_t l[kLimbs];
 #pragma unroll
-    for (int k = 0; k < kLimbs; ++k) l[k] = __shfl(a[e], (lane & 48) + k, 64);
+    for (int k = 0; k < kLimbs; ++k) l[k] = __shfl(a[e], (lane & 48) + base + k, 64);
     const int64_t hi = ((int64_t)l[0] << 24) + ((int64_t)l[1] << 16) + ((int64_t)l[2] << 8) + l[3];
     const int64_t lo = ((int64_t)l[4] << 16) + ((int64_t)l[5] << 8) + l[6];
     return (double)hi * 16777216.0 + (double)lo;
@@ -1325,7 +1335,7 @@ __device__ __forceinline__ double limb_sum(const i32x4& a, int e, int lane)
 // kDepth: super-tiles of codes in flight ahead of the one being multiplied
 // (the three code buffers rotate statically over an unrolled loop, so no
 // register copies).
-template <bool kAv, int kDepth = kAv ? kDepthV : kDepthU>
+template <bool kAv, int kDepth = kAv ? kDepthV : kDepthU, int kVec = 1>
 __device__ __forceinline__ void limb_product_body(const uint8_t* __restrict__ L, int64_t ldL,
                                                   int64_t rows_pad, int64_t rows,
                                                   const i32x4* __restrict__ frag, int64_t nst,
@@ -1342,10 +1352,10 @@ __device__ __forceinline__ void limb_product_body(const uint8_t* __restrict__ L,
     constexpr int kFr = kWords * kOps * 64;     // fragments per super-tile
     constexpr int kFrT = kFr / 256;             // per thread
     __shared__ i32x4 bs[2][kFr];
-    __shared__ double ksum[1];
-    __shared__ int ex[1];
-    column_sums(cpart, 1, ksum);
-    column_scales(cmax, 1, ex);
+    __shared__ double ksum[kVec];
+    __shared__ int ex[kVec];
+    column_sums(cpart, kVec, ksum);
+    column_scales(cmax, kVec, ex);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = lane >> 4, r = lane & 15;
     const int64_t row_base = (int64_t)rb * (kMxWaves * kRT * 16) + wave * (kRT * 16);
@@ -1415,30 +1425,33 @@ __device__ __forceinline__ void limb_product_body(const uint8_t* __restrict__ L,
             if (st + 2 < st1) step(st + 2, a2, a1);
         }
     }
-    double* out = partial + (int64_t)split * rows_pad;
-    const int e0 = ex[0];
 #pragma unroll
-    for (int t = 0; t < kRT; ++t) {
+    for (int vc = 0; vc < kVec; ++vc) {
+        double* out = partial + ((int64_t)split * kVec + vc) * rows_pad;
+        const int e0 = ex[vc];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int64_t row = row_base + 16 * t + 4 * g + e;
-            double val;
-            if (kAv) {
-                val = ldexp(limb_sum(acc[t][0], e, lane), e0 - kQ64);
-                if (split == 0) val -= ksum[0];
-            } else {
-                const double sc = limb_sum(acc[t][0], e, lane);
-                const double sm = limb_sum(acc[t][kAcc - 1], e, lane);
-                const double mu = row < rows ? mean[row] : 0.0;
-                val = ldexp(sc + (mu - 3.0) * sm, e0 - kQ64);
-                if (split == 0) val -= mu * ksum[0];
+        for (int t = 0; t < kRT; ++t) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t row = row_base + 16 * t + 4 * g + e;
+                double val;
+                if (kAv) {
+                    val = ldexp(limb_sum(acc[t][0], e, lane, kLimbs * vc), e0 - kQ64);
+                    if (split == 0) val -= ksum[vc];
+                } else {
+                    const double sc = limb_sum(acc[t][0], e, lane, kLimbs * vc);
+                    const double sm = limb_sum(acc[t][kAcc - 1], e, lane, kLimbs * vc);
+                    const double mu = row < rows ? mean[row] : 0.0;
+                    val = ldexp(sc + (mu - 3.0) * sm, e0 - kQ64);
+                    if (split == 0) val -= mu * ksum[vc];
+                }
+                if (r == 0) out[row] = val;
             }
-            if (r == 0) out[row] = val;
         }
     }
 }
 
-template <bool kAv>
+template <bool kAv, int kVec>
 __global__ void __launch_bounds__(256)
 limb_product_kernel(const uint8_t* __restrict__ L, int64_t ldL, int64_t rows_pad, int64_t rows,
                     const i32x4* __restrict__ frag, int64_t nst, int64_t st_per, int nsplit,
@@ -1448,8 +1461,8 @@ limb_product_kernel(const uint8_t* __restrict__ L, int64_t ldL, int64_t rows_pad
 {
     int split, rb;
     block_coords(blockIdx.x, nsplit, nrb, xcd, split, rb);
-    limb_product_body<kAv>(L, ldL, rows_pad, rows, frag, nst, st_per, split, rb, cpart, cmax, mean,
-                           partial);
+    limb_product_body<kAv, kAv ? kDepthV : kDepthU, kVec>(L, ldL, rows_pad, rows, frag, nst, st_per,
+                                                          split, rb, cpart, cmax, mean, partial);
 }
 
 // Batched A^T u in limbs (the batched path with the S layout per problem).
@@ -1470,8 +1483,8 @@ blimb_frag_kernel(const BatchDesc* __restrict__ desc, const int* __restrict__ st
     const BatchDesc& D = desc[blockIdx.y];
     if (!*D.active || (int64_t)blockIdx.x >= D.nstX) return;
     const int64_t j = state[0];
-    limb_frag_body<1>(D.U + j * D.n, D.n, nullptr, nullptr, D.lcmax,
-                      static_cast<i32x4*>(D.lfrag), blockIdx.x);
+    limb_frag_body<1, 1>(D.U + j * D.n, D.n, D.n, nullptr, nullptr, D.lcmax,
+                         static_cast<i32x4*>(D.lfrag), blockIdx.x);
 }
 
 // Persistent over the (split, row block) tiles of every active problem:
@@ -1614,6 +1627,9 @@ size_t mixed_frag_bytes(const MixedShape& m)
 size_t mixed_partial_elems(const MixedShape& m)
 {
     size_t e = std::max((size_t)m.splitW * (size_t)m.nI * 16, (size_t)m.splitX * 2 * (size_t)m.pS * 16);
+    // FP64-exact pairs: two columns per split
+    e = std::max(e, (size_t)m.limbW.nsplit * 2 * (size_t)m.nI);
+    e = std::max(e, (size_t)m.limbX.nsplit * 2 * (size_t)m.pS);
     for (int c = 0; c < 3; ++c) {
         const size_t kcs = c == 0 ? 8 : 16 * c;
         e = std::max(e, (size_t)m.bfW[c].nsplit * (size_t)m.nI * kcs);
@@ -1655,11 +1671,11 @@ int launch_matvec_limb(const MixedShape& m, const uint8_t* I, const ColStats& st
     hipLaunchKernelGGL(colsum_kernel, dim3(kCsSplit, 1), dim3(256), 0, s, v, m.p, m.p, st.mean,
                        st.inv_sd, 3.0, w.lcpart, w.lcmax);
     GKL_LAUNCH_CHECK("colsum_kernel");
-    hipLaunchKernelGGL(limb_frag_kernel<2>, dim3((unsigned int)m.nstW), dim3(256), 0, s, v, m.p,
-                       st.mean, st.inv_sd, w.lcmax, frag);
+    hipLaunchKernelGGL((limb_frag_kernel<2, 1>), dim3((unsigned int)m.nstW), dim3(256), 0, s, v, m.p,
+                       m.p, st.mean, st.inv_sd, w.lcmax, frag);
     GKL_LAUNCH_CHECK("limb_frag_kernel<2>");
     if (ev) GKL_HIP(hipEventRecord(ev[0], s));
-    hipLaunchKernelGGL(limb_product_kernel<true>, dim3((unsigned int)(gm.nsplit * gm.nrb)),
+    hipLaunchKernelGGL((limb_product_kernel<true, 1>), dim3((unsigned int)(gm.nsplit * gm.nrb)),
                        dim3(256), 0, s, I, m.ldI, m.nI, m.n, frag, m.nstW, gm.st_per, gm.nsplit,
                        gm.nrb, gm.xcd, w.lcpart, w.lcmax, st.mean, w.partial);
     GKL_LAUNCH_CHECK("limb_product_kernel<A v>");
@@ -1675,11 +1691,11 @@ int launch_rmatvec_limb(const MixedShape& m, const uint8_t* S, const ColStats& s
     hipLaunchKernelGGL(colsum_kernel, dim3(kCsSplit, 1), dim3(256), 0, s, u, m.n, m.n, nullptr,
                        nullptr, 0.0, w.lcpart, w.lcmax);
     GKL_LAUNCH_CHECK("colsum_kernel");
-    hipLaunchKernelGGL(limb_frag_kernel<1>, dim3((unsigned int)m.nstX), dim3(256), 0, s, u, m.n,
-                       nullptr, nullptr, w.lcmax, frag);
+    hipLaunchKernelGGL((limb_frag_kernel<1, 1>), dim3((unsigned int)m.nstX), dim3(256), 0, s, u, m.n,
+                       m.n, nullptr, nullptr, w.lcmax, frag);
     GKL_LAUNCH_CHECK("limb_frag_kernel<1>");
     if (ev) GKL_HIP(hipEventRecord(ev[0], s));
-    hipLaunchKernelGGL(limb_product_kernel<false>, dim3((unsigned int)(gm.nsplit * gm.nrb)),
+    hipLaunchKernelGGL((limb_product_kernel<false, 1>), dim3((unsigned int)(gm.nsplit * gm.nrb)),
                        dim3(256), 0, s, S, m.ldS, m.pS, m.p, frag, m.nstX, gm.st_per, gm.nsplit,
                        gm.nrb, gm.xcd, w.lcpart, w.lcmax, st.mean, w.partial);
     GKL_LAUNCH_CHECK("limb_product_kernel<A^T u>");
@@ -1840,11 +1856,112 @@ static void rmatmat_i8(const MixedShape& m, const uint8_t* S, const ColStats& st
     }
 }
 
+// FP64-exact block products (GKL_PREC_BLOCK_FP64): the single-vector limb
+// kernels with two vectors per MFMA tile, one pass over the matrix per pair of
+// columns.  Y[:, c] = the sum of the splits' partials in split order, times s_j
+// for A^T X (inv_sd non-NULL).
+__global__ void __launch_bounds__(256)
+limb_pair_reduce_kernel(const double* __restrict__ partial, int nsplit, int nv, int64_t rows_pad,
+                        int64_t rows, const double* __restrict__ inv_sd, double* __restrict__ Y,
+                        int64_t ldy)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < rows * nv;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i / rows);
+        const int64_t row = i - (int64_t)c * rows;
+        double t = 0.0;
+        for (int sp = 0; sp < nsplit; ++sp) t += partial[((int64_t)sp * nv + c) * rows_pad + row];
+        if (inv_sd) t *= inv_sd[row];
+        Y[(int64_t)c * ldy + row] = t;
+    }
+}
+
+static unsigned int pair_reduce_grid(int64_t rows, int nv)
+{
+    const int64_t g = ceil_div(rows * nv, 256);
+    return (unsigned int)(g < 2048 ? g : 2048);
+}
+
+static void matmat_exact(const MixedShape& m, const uint8_t* I, const ColStats& st, const double* W,
+                         int64_t ldw, int b, double* Y, int64_t ldy, MixedWork& w, hipStream_t s,
+                         const hipEvent_t* ev)
+{
+    const BfSplit& gm = m.limbW;
+    i32x4* frag = reinterpret_cast<i32x4*>(w.frag);
+    const dim3 grid((unsigned int)(gm.nsplit * gm.nrb));
+    for (int c0 = 0; c0 < b; c0 += 2) {
+        const int nv = b - c0 < 2 ? b - c0 : 2;
+        const double* Wc = W + (int64_t)c0 * ldw;
+        hipLaunchKernelGGL(colsum_kernel, dim3(kCsSplit, nv), dim3(256), 0, s, Wc, ldw, m.p, st.mean,
+                           st.inv_sd, 3.0, w.cpart, w.cmax);
+        GKL_LAUNCH_CHECK("colsum_kernel");
+        if (nv == 2)
+            hipLaunchKernelGGL((limb_frag_kernel<2, 2>), dim3((unsigned int)m.nstW), dim3(256), 0, s, Wc,
+                               ldw, m.p, st.mean, st.inv_sd, w.cmax, frag);
+        else
+            hipLaunchKernelGGL((limb_frag_kernel<2, 1>), dim3((unsigned int)m.nstW), dim3(256), 0, s, Wc,
+                               ldw, m.p, st.mean, st.inv_sd, w.cmax, frag);
+        GKL_LAUNCH_CHECK("limb_frag_kernel");
+        if (ev && c0 == 0) GKL_HIP(hipEventRecord(ev[0], s));
+        if (nv == 2)
+            hipLaunchKernelGGL((limb_product_kernel<true, 2>), grid, dim3(256), 0, s, I, m.ldI, m.nI,
+                               m.n, frag, m.nstW, gm.st_per, gm.nsplit, gm.nrb, gm.xcd, w.cpart, w.cmax,
+                               st.mean, w.partial);
+        else
+            hipLaunchKernelGGL((limb_product_kernel<true, 1>), grid, dim3(256), 0, s, I, m.ldI, m.nI,
+                               m.n, frag, m.nstW, gm.st_per, gm.nsplit, gm.nrb, gm.xcd, w.cpart, w.cmax,
+                               st.mean, w.partial);
+        GKL_LAUNCH_CHECK("limb_product_kernel<A W>");
+        if (ev && c0 + 2 >= b) GKL_HIP(hipEventRecord(ev[1], s));
+        hipLaunchKernelGGL(limb_pair_reduce_kernel, dim3(pair_reduce_grid(m.n, nv)), dim3(256), 0, s,
+                           w.partial, gm.nsplit, nv, m.nI, m.n, nullptr, Y + (int64_t)c0 * ldy, ldy);
+        GKL_LAUNCH_CHECK("limb_pair_reduce_kernel");
+    }
+}
+
+static void rmatmat_exact(const MixedShape& m, const uint8_t* S, const ColStats& st, const double* X,
+                          int64_t ldx, int b, double* Z, int64_t ldz, MixedWork& w, hipStream_t s,
+                          const hipEvent_t* ev)
+{
+    const BfSplit& gm = m.limbX;
+    i32x4* frag = reinterpret_cast<i32x4*>(w.frag);
+    const dim3 grid((unsigned int)(gm.nsplit * gm.nrb));
+    for (int c0 = 0; c0 < b; c0 += 2) {
+        const int nv = b - c0 < 2 ? b - c0 : 2;
+        const double* Xc = X + (int64_t)c0 * ldx;
+        hipLaunchKernelGGL(colsum_kernel, dim3(kCsSplit, nv), dim3(256), 0, s, Xc, ldx, m.n, nullptr,
+                           nullptr, 0.0, w.cpart, w.cmax);
+        GKL_LAUNCH_CHECK("colsum_kernel");
+        if (nv == 2)
+            hipLaunchKernelGGL((limb_frag_kernel<1, 2>), dim3((unsigned int)m.nstX), dim3(256), 0, s, Xc,
+                               ldx, m.n, nullptr, nullptr, w.cmax, frag);
+        else
+            hipLaunchKernelGGL((limb_frag_kernel<1, 1>), dim3((unsigned int)m.nstX), dim3(256), 0, s, Xc,
+                               ldx, m.n, nullptr, nullptr, w.cmax, frag);
+        GKL_LAUNCH_CHECK("limb_frag_kernel");
+        if (ev && c0 == 0) GKL_HIP(hipEventRecord(ev[0], s));
+        if (nv == 2)
+            hipLaunchKernelGGL((limb_product_kernel<false, 2>), grid, dim3(256), 0, s, S, m.ldS, m.pS,
+                               m.p, frag, m.nstX, gm.st_per, gm.nsplit, gm.nrb, gm.xcd, w.cpart, w.cmax,
+                               st.mean, w.partial);
+        else
+            hipLaunchKernelGGL((limb_product_kernel<false, 1>), grid, dim3(256), 0, s, S, m.ldS, m.pS,
+                               m.p, frag, m.nstX, gm.st_per, gm.nsplit, gm.nrb, gm.xcd, w.cpart, w.cmax,
+                               st.mean, w.partial);
+        GKL_LAUNCH_CHECK("limb_product_kernel<A^T X>");
+        if (ev && c0 + 2 >= b) GKL_HIP(hipEventRecord(ev[1], s));
+        hipLaunchKernelGGL(limb_pair_reduce_kernel, dim3(pair_reduce_grid(m.p, nv)), dim3(256), 0, s,
+                           w.partial, gm.nsplit, nv, m.pS, m.p, st.inv_sd, Z + (int64_t)c0 * ldz, ldz);
+        GKL_LAUNCH_CHECK("limb_pair_reduce_kernel");
+    }
+}
+
 void launch_matmat_mixed(const MixedShape& m, const uint8_t* I, const ColStats& st,
                          const double* W, int64_t ldw, int b, double* Y, int64_t ldy,
                          MixedWork& w, hipStream_t s, const hipEvent_t* core_ev)
 {
-    if (m.int8) matmat_i8(m, I, st, W, ldw, b, Y, ldy, w, s, core_ev);
+    if (m.exact) matmat_exact(m, I, st, W, ldw, b, Y, ldy, w, s, core_ev);
+    else if (m.int8) matmat_i8(m, I, st, W, ldw, b, Y, ldy, w, s, core_ev);
     else matmat_bf16(m, I, st, W, ldw, b, Y, ldy, w, s, core_ev);
 }
 
@@ -1852,7 +1969,8 @@ void launch_rmatmat_mixed(const MixedShape& m, const uint8_t* S, const ColStats&
                           const double* X, int64_t ldx, int b, double* Z, int64_t ldz,
                           MixedWork& w, hipStream_t s, const hipEvent_t* core_ev)
 {
-    if (m.int8) rmatmat_i8(m, S, st, X, ldx, b, Z, ldz, w, s, core_ev);
+    if (m.exact) rmatmat_exact(m, S, st, X, ldx, b, Z, ldz, w, s, core_ev);
+    else if (m.int8) rmatmat_i8(m, S, st, X, ldx, b, Z, ldz, w, s, core_ev);
     else rmatmat_bf16(m, S, st, X, ldx, b, Z, ldz, w, s, core_ev);
 }
 

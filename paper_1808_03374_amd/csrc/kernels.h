@@ -71,6 +71,8 @@ struct MixedShape {
     int64_t stW = 0, stX = 0;     // super-tiles per K split
     int splitW = 1, splitX = 1;
     bool int8 = false;            // operand format: int8 limbs (true) or split BF16
+    bool exact = false;           // FP64-exact block products: seven int8 limbs, two
+                                  // vectors per pass (overrides int8)
     BfSplit bfW[3], bfX[3];       // split BF16 by column class: b <= 8, <= 16, <= 32
     BfSplit limbW, limbX;         // single-vector FP64 products in seven int8 limbs
 };

@@ -7,8 +7,9 @@
 //     V_{s+1} C_s = A^T U_s - V_s R_s^T            (block CGS2 against all V, QR)
 // so that A [V_1..V_s] = [U_1..U_s] B with B block upper bidiagonal (R_s on the
 // diagonal, C_s^T above it).  The two products run on the matrix cores, with
-// split-BF16 vector tiles (GKL_PREC_MIXED) or exact int8 limbs of a per-column
-// fixed point (GKL_PREC_MIXED_INT8); everything else (Gram-Schmidt, QR, B, its
+// split-BF16 vector tiles (GKL_PREC_MIXED), exact int8 limbs of a per-column
+// fixed point (GKL_PREC_MIXED_INT8) or seven int8 limbs of 52-bit integers, FP64
+// to the rounding of a sum (GKL_PREC_BLOCK_FP64); everything else (Gram-Schmidt, QR, B, its
 // SVD, restart) is FP64.
 // Ritz residual of triplet i: || C_s P(last block rows, i) ||.
 // After a restart that keeps l Ritz vectors, B starts as diag(sigma_1..l) with the
@@ -83,6 +84,7 @@ void gkl_ctx::setup_mixed()
     M.ldb = m + M.b;
     M.shape = mixed_shape(n, p);
     M.shape.int8 = opt.precision == GKL_PREC_MIXED_INT8;
+    M.shape.exact = opt.precision == GKL_PREC_BLOCK_FP64;
     M.I = static_cast<uint8_t*>(A.alloc((size_t)M.shape.nI * M.shape.ldI));
     M.S = static_cast<uint8_t*>(A.alloc((size_t)M.shape.pS * M.shape.ldS));
     build_mixed_layouts(prob.G_user, n, p, prob.ld, M.I, M.S, s);
@@ -165,7 +167,7 @@ gkl_status gkl_ctx::solve_mixed(double* sigma, double* Uo, int64_t ldu, double* 
                             ev >= 0 ? &ev_pool[ev + 2] : nullptr);
         timing_end(ev, false, true);
         info.matvecs += b;
-        info.passes_over_G += M.shape.int8 ? (b + 15) / 16 : 1;
+        info.passes_over_G += M.shape.exact ? (b + 1) / 2 : M.shape.int8 ? (b + 15) / 16 : 1;
         if (o > 0) {
             if (o == nlock_m)
                 launch_gemm_nn_sub(M.U, n, Ub, n, n, nlock_m, b, M.Bm + (int64_t)o * M.ldb, M.ldb, s);
@@ -183,7 +185,7 @@ gkl_status gkl_ctx::solve_mixed(double* sigma, double* Uo, int64_t ldu, double* 
                              ev2 >= 0 ? &ev_pool[ev2 + 2] : nullptr);
         timing_end(ev2, true, true);
         info.matvecs += b;
-        info.passes_over_G += M.shape.int8 ? (b + 15) / 16 : 1;
+        info.passes_over_G += M.shape.exact ? (b + 1) / 2 : M.shape.int8 ? (b + 15) / 16 : 1;
         launch_put_block(M.RT, b, 0, 0, M.R, b, b, b, 1, s);
         launch_gemm_nn_sub(Vb, p, Vn, p, p, b, b, M.RT, b, s);
         block_cgs2(M, M.V, p, o + b, Vn, s);
@@ -270,7 +272,7 @@ gkl_status gkl_matmat_mixed(gkl_ctx* ctx, const double* W, int32_t b, double* Y)
 {
     if (!ctx || !W || !Y || b < 1 || b > 32) return GKL_ERR_INVALID;
     if (!ctx->mixed) {
-        ctx->last_error = "context was not created with a blocked precision (GKL_PREC_MIXED or _MIXED_INT8)";
+        ctx->last_error = "context was not created with a blocked precision (GKL_PREC_MIXED, _MIXED_INT8 or _BLOCK_FP64)";
         return GKL_ERR_INVALID;
     }
     try {
@@ -289,7 +291,7 @@ gkl_status gkl_rmatmat_mixed(gkl_ctx* ctx, const double* X, int32_t b, double* Z
 {
     if (!ctx || !X || !Z || b < 1 || b > 32) return GKL_ERR_INVALID;
     if (!ctx->mixed) {
-        ctx->last_error = "context was not created with a blocked precision (GKL_PREC_MIXED or _MIXED_INT8)";
+        ctx->last_error = "context was not created with a blocked precision (GKL_PREC_MIXED, _MIXED_INT8 or _BLOCK_FP64)";
         return GKL_ERR_INVALID;
     }
     try {

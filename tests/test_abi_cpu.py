@@ -52,7 +52,7 @@ def test_create_rejects_bad_arguments(args, msg):
     ("ld_bytes", 2, "ld_bytes"),
     ("block_width", 33, "block_width"),
     ("precision", 5, "precision"),
-    ("precision", 3, "precision"),
+    ("precision", 4, "precision"),
     ("precision", -1, "precision"),
     ("keep", 1, "keep"),
 ])
