@@ -34,10 +34,15 @@ __device__ __forceinline__ v4d mfma64(double a, double b, v4d c)
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// Rows per workgroup (a multiple of 128) and workgroup count for Q^T Y.
-__host__ __device__ inline void tn_plan(int64_t len, int64_t* rows_per_wg, int* nwg)
+// Rows per workgroup (a multiple of 128) and workgroup count for Q^T Y, at most
+// max_wg workgroups per 64-column group (256 = one per CU; 1,024 measured no
+// faster: the loads are column-strided, and the longer partial sums cost more
+// than the extra workgroups saved).
+constexpr int kTnWgMax = 256;
+__host__ __device__ inline void tn_plan(int64_t len, int64_t* rows_per_wg, int* nwg,
+                                        int max_wg = 256)
 {
-    int64_t r = (len + 255) / 256;
+    int64_t r = (len + max_wg - 1) / max_wg;
     r = (r + 127) / 128 * 128;
     *rows_per_wg = r;
     *nwg = (int)((len + r - 1) / r);
@@ -124,7 +129,11 @@ __device__ __forceinline__ void tn_body(const double* __restrict__ Q, int64_t ld
                     red[wave - 2][(qt * 16 + g + 4 * e) * kBmax + bt * 16 + col] += acc[qt][bt][e];
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < kTnPart; e += 256) my[e] = red[0][e] + red[1][e];
+    // only the b live columns of each of the 64 rows are ever read
+    for (int e = threadIdx.x; e < kTnQ * b; e += 256) {
+        const int idx = (e / b) * kBmax + e % b;
+        my[idx] = red[0][idx] + red[1][idx];
+    }
 }
 
 __global__ void __launch_bounds__(256)
@@ -161,10 +170,11 @@ gemm_tn_reduce_kernel(const double* __restrict__ partial, int nwg, int q, int b,
     if (live && r == 0) H[(int64_t)j * ldh + qc] = s;
 }
 
-// Partial buffer for any len: tn_plan never uses more than 256 workgroups.
+// Partial buffer for any len: the single-context plan uses at most kTnWgMax
+// workgroups per column group.
 size_t gemm_tn_partial_elems(int64_t, int q)
 {
-    return (size_t)256 * (size_t)ceil_div(q < 1 ? 1 : q, kTnQ) * kTnPart;
+    return (size_t)kTnWgMax * (size_t)ceil_div(q < 1 ? 1 : q, kTnQ) * kTnPart;
 }
 
 void launch_gemm_tn(const double* Q, int64_t ldq, const double* Y, int64_t ldy, int64_t len, int q,
@@ -181,8 +191,8 @@ void launch_gemm_tn_gated(const double* Q, int64_t ldq, const double* Y, int64_t
     if (b > kBmax) fail(GKL_ERR_INVALID, "block width above 32");
     int64_t rpw;
     int nwg;
-    tn_plan(len, &rpw, &nwg);
-    if (nwg > 256) fail(GKL_ERR_INTERNAL, "gemm_tn plan exceeds its partial buffer");
+    tn_plan(len, &rpw, &nwg, kTnWgMax);
+    if (nwg > kTnWgMax) fail(GKL_ERR_INTERNAL, "gemm_tn plan exceeds its partial buffer");
     dim3 grid((unsigned int)nwg, (unsigned int)ceil_div(q, kTnQ));
     hipLaunchKernelGGL(gemm_tn_kernel, grid, dim3(256), 0, s, Q, ldq, Y, ldy, len, q, b, rpw,
                        partial, enable, skip);

@@ -370,6 +370,147 @@ cgs_pass_kernel(const double* __restrict__ Q, int64_t ldq, int64_t len, int ncol
     }
 }
 
+// The same three passes for a block of kB <= 4 vectors (Y, column-major, ld
+// ldy) against Q, without the norm tail: the blocked GKL's block Gram-Schmidt
+// (the block QR that follows orthonormalises the block itself).  Each
+// workgroup reads its rows of Q once per pass for all kB vectors, so CGS2
+// costs three passes over Q; partials of vector v at pout + (wg kB + v) cstride.
+// Between passes a separate kernel adds the partials once (with a basis of up
+// to 130 columns and ~1,000 workgroups, every workgroup adding them itself
+// read gigabytes from L2); hin holds the kB x cstride coefficients.
+template <int kMode, int kB>
+__global__ void __launch_bounds__(kCT)
+cgs_block_pass_kernel(const double* __restrict__ Q, int64_t ldq, int64_t len, int ncols,
+                      double* __restrict__ Y, int64_t ldy, const double* __restrict__ hin,
+                      double* __restrict__ pout, int cstride)
+{
+    extern __shared__ double hs[];             // kB x cstride coefficients (kMode > 0)
+    __shared__ double red[kCW * 64];
+    const int t = threadIdx.x, lane = t & 63;
+    const int64_t row = (int64_t)blockIdx.x * kCT + t;
+    const bool live = row < len;
+    const int64_t rowc = live ? row : len - 1;
+
+    if (kMode > 0) {
+        for (int e = t; e < kB * cstride; e += kCT) hs[e] = hin[e];
+        __syncthreads();
+    }
+
+    double x[kB];
+#pragma unroll
+    for (int v = 0; v < kB; ++v) x[v] = live ? Y[(int64_t)v * ldy + row] : 0.0;
+    double q[kCChunk];
+    if (kMode > 0) {
+        for (int c0 = 0; c0 < ncols; c0 += kCChunk) {
+            load_row_chunk(Q, ldq, rowc, c0, ncols, q);
+            // one vector at a time, so that only its coefficients are in flight
+#pragma unroll 1
+            for (int v = 0; v < kB; ++v) {
+                double a = v == 0 ? x[0] : v == 1 ? x[kB > 1 ? 1 : 0]
+                         : v == 2 ? x[kB > 2 ? 2 : 0] : x[kB > 3 ? 3 : 0];
+#pragma unroll
+                for (int k = 0; k < kCChunk; ++k) a = fma(-q[k], hs[v * cstride + c0 + k], a);
+#pragma unroll
+                for (int w = 0; w < kB; ++w) x[w] = v == w ? a : x[w];
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < kB; ++v) {
+            if (live) Y[(int64_t)v * ldy + row] = x[v];
+            x[v] = live ? x[v] : 0.0;   // lanes past len read row len - 1: no contribution
+        }
+    }
+    if (kMode == 2) return;
+    for (int c0 = 0; c0 < ncols; c0 += kCChunk) {
+        // with one chunk the rows loaded for the update are still in q; the
+        // products overwrite q, so every further vector reloads the chunk (from
+        // the cache: the workgroup has just read it)
+        bool have = kMode > 0 && ncols <= kCChunk;
+        // one vector at a time (not unrolled: one copy of the chunk in registers)
+#pragma unroll 1
+        for (int v = 0; v < kB; ++v) {
+            // keep the next vector's reload below this point: hoisted, it would
+            // hold a second copy of the chunk in registers
+            __builtin_amdgcn_sched_barrier(0);
+            if (!have) load_row_chunk(Q, ldq, rowc, c0, ncols, q);
+            have = false;
+            const double xv = v == 0 ? x[0] : v == 1 ? x[kB > 1 ? 1 : 0]
+                            : v == 2 ? x[kB > 2 ? 2 : 0] : x[kB > 3 ? 3 : 0];
+#pragma unroll
+            for (int k = 0; k < kCChunk; ++k) q[k] *= xv;
+            block_columns(wave_transpose_sum(q, lane), red,
+                          pout + ((int64_t)blockIdx.x * kB + v) * cstride, c0);
+        }
+    }
+}
+
+// h[v cstride + c] = sum over the nb workgroup partials of column c of vector
+// v (zero for ncols <= c < cstride): one wave per coefficient, lane l adding
+// workgroups l, l + 64, ... in order, then a fixed butterfly.
+__global__ void __launch_bounds__(256)
+cgs_block_sum_kernel(const double* __restrict__ pin, int nb, int kb, int ncols, int cstride,
+                     double* __restrict__ h)
+{
+    const int o = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (o >= kb * cstride) return;              // the whole wave
+    const int v = o / cstride, c = o - v * cstride;
+    double sum = 0.0;
+    if (c < ncols)
+        for (int b = lane; b < nb; b += 64) sum += pin[((int64_t)b * kb + v) * cstride + c];
+    sum = wave_sum(sum);
+    if (lane == 0) h[o] = sum;
+}
+
+template <int kB>
+static void block_cgs2_run(const double* Q, int64_t ldq, int64_t len, int ncols, double* Y,
+                           int64_t ldy, double* partial, size_t partial_elems, hipStream_t s)
+{
+    const CgsPlan c = cgs_plan(len, ncols);
+    const size_t pe = (size_t)c.nb * kB * c.cstride;
+    const size_t he = (size_t)kB * c.cstride;
+    if (2 * pe + 2 * he > partial_elems)
+        fail(GKL_ERR_INTERNAL, "block CGS2 plan exceeds its partial buffer");
+    double* p1 = partial;
+    double* p2 = partial + pe;
+    double* h1 = partial + 2 * pe;
+    double* h2 = h1 + he;
+    const size_t hb = sizeof(double) * he;
+    const dim3 gsum((unsigned int)ceil_div((int64_t)he, 4));
+    hipLaunchKernelGGL((cgs_block_pass_kernel<0, kB>), dim3(c.nb), dim3(kCT), 0, s, Q, ldq, len,
+                       ncols, Y, ldy, nullptr, p1, c.cstride);
+    GKL_LAUNCH_CHECK("cgs_block_pass_kernel<0>");
+    hipLaunchKernelGGL(cgs_block_sum_kernel, gsum, dim3(256), 0, s, p1, c.nb, kB, ncols, c.cstride, h1);
+    GKL_LAUNCH_CHECK("cgs_block_sum_kernel");
+    hipLaunchKernelGGL((cgs_block_pass_kernel<1, kB>), dim3(c.nb), dim3(kCT), hb, s, Q, ldq, len,
+                       ncols, Y, ldy, h1, p2, c.cstride);
+    GKL_LAUNCH_CHECK("cgs_block_pass_kernel<1>");
+    hipLaunchKernelGGL(cgs_block_sum_kernel, gsum, dim3(256), 0, s, p2, c.nb, kB, ncols, c.cstride, h2);
+    GKL_LAUNCH_CHECK("cgs_block_sum_kernel");
+    hipLaunchKernelGGL((cgs_block_pass_kernel<2, kB>), dim3(c.nb), dim3(kCT), hb, s, Q, ldq, len,
+                       ncols, Y, ldy, h2, nullptr, c.cstride);
+    GKL_LAUNCH_CHECK("cgs_block_pass_kernel<2>");
+}
+
+size_t block_cgs2_partial_elems(int64_t len, int maxcols, int b)
+{
+    const CgsPlan c = cgs_plan(len, maxcols);
+    return 2 * (size_t)c.nb * (size_t)b * (size_t)c.cstride + 2 * (size_t)b * (size_t)c.cstride;
+}
+
+void launch_block_cgs2(const double* Q, int64_t ldq, int64_t len, int ncols, double* Y, int64_t ldy,
+                       int b, double* partial, size_t partial_elems, hipStream_t s)
+{
+    if (ncols <= 0) return;
+    switch (b) {
+    case 1: block_cgs2_run<1>(Q, ldq, len, ncols, Y, ldy, partial, partial_elems, s); break;
+    case 2: block_cgs2_run<2>(Q, ldq, len, ncols, Y, ldy, partial, partial_elems, s); break;
+    case 3: block_cgs2_run<3>(Q, ldq, len, ncols, Y, ldy, partial, partial_elems, s); break;
+    case 4: block_cgs2_run<4>(Q, ldq, len, ncols, Y, ldy, partial, partial_elems, s); break;
+    default: fail(GKL_ERR_INTERNAL, "launch_block_cgs2 takes blocks of 1 to 4 vectors");
+    }
+}
+
 __global__ void adapt_decide_kernel(const double* __restrict__ n0, const double* __restrict__ n1,
                                     int* __restrict__ skip, int* __restrict__ passes,
                                     const int* __restrict__ enable)

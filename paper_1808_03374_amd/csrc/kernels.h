@@ -256,6 +256,11 @@ int cgs_norm_partials(int64_t len);
 // `enable` (device, may be NULL = always) gates the whole call: 0 skips it.
 // If adaptive, the second pass runs only when ||r1|| < ||r0|| / sqrt(2);
 // otherwise two passes always.  Counts performed passes into *passes (device).
+// Block CGS2 of Y (len x b, 1 <= b <= 4, ld ldy) against Q (len x ncols): the
+// single-vector kernels' three fused passes for all b vectors at once.
+size_t block_cgs2_partial_elems(int64_t len, int maxcols, int b);
+void launch_block_cgs2(const double* Q, int64_t ldq, int64_t len, int ncols, double* Y, int64_t ldy,
+                       int b, double* partial, size_t partial_elems, hipStream_t s);
 void launch_cgs2(const double* Q, int64_t ldq, int64_t len, int ncols, double* r,
                  const int* enable, int adaptive, int* passes, OrthoWork& w, hipStream_t s);
 // nrm = ||r||; if nrm <= thresh(*) then breakdown: *flag = 1 and nrm stored as 0,

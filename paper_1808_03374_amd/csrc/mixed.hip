@@ -45,6 +45,7 @@ struct MixedState {
     double* qrwork = nullptr;  // 3 b^2
     double* tmp = nullptr;     // max(n, p) x keep
     double* gpart = nullptr;
+    size_t gpart_elems = 0;
     double* svd_scratch = nullptr;
     double* svd_log = nullptr;         // rotation log of the SVD for 96 < m <= 128
     int* iflags = nullptr;     // [0] nconv [1] bad pivots
@@ -105,7 +106,8 @@ void gkl_ctx::setup_mixed()
     M.tmp = static_cast<double*>(A.alloc(sizeof(double) * (size_t)std::max(n, p) * M.keep));
     const size_t gp = std::max(gemm_tn_partial_elems(std::max(n, p), m + b),
                                gemm_tn_partial_elems(std::max(n, p), b));
-    M.gpart = static_cast<double*>(A.alloc(sizeof(double) * gp));
+    M.gpart_elems = std::max(gp, block_cgs2_partial_elems(std::max(n, p), m + b, b));
+    M.gpart = static_cast<double*>(A.alloc(sizeof(double) * M.gpart_elems));
     M.iflags = static_cast<int*>(A.alloc(sizeof(int) * 8));
     M.ritz.B = M.Bc;
     M.ritz.P = static_cast<double*>(A.alloc(sizeof(double) * (size_t)m * m));
@@ -130,6 +132,11 @@ static void block_cgs2(MixedState& M, const double* Q, int64_t len, int q, doubl
 {
     if (q <= 0) return;
     const int b = M.b;
+    if (b <= 4) {
+        // the fused three-pass kernels: one read of Q per pass for the whole block
+        launch_block_cgs2(Q, len, len, q, Y, len, b, M.gpart, M.gpart_elems, s);
+        return;
+    }
     for (int pass = 0; pass < 2; ++pass) {
         launch_gemm_tn(Q, len, Y, len, len, q, b, M.H, M.mmax + b, M.gpart, s);
         launch_gemm_nn_sub(Q, len, Y, len, len, q, b, M.H, M.mmax + b, s);

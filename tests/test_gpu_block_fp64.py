@@ -103,7 +103,7 @@ def test_block_fp64_products_full_size_sampled(gk):
             1e-12 * np.linalg.norm(Z[:, c]) / np.sqrt(p) * 10
 
 
-@pytest.mark.parametrize("b,m", [(2, 0), (3, 0), (4, 0), (2, 48), (3, 48)])
+@pytest.mark.parametrize("b,m", [(1, 0), (2, 0), (3, 0), (4, 0), (2, 48), (3, 48)])
 def test_block_fp64_solve_matches_oracle(gk, b, m):
     g = synth.config("c2", n=2000, p=20000)
     k = 20
