@@ -396,23 +396,31 @@ cgs_block_pass_kernel(const double* __restrict__ Q, int64_t ldq, int64_t len, in
         __syncthreads();
     }
 
+    // Columns are taken kW at a time, kW = 64 / kP with kP >= kB slots: the
+    // products of the kB vectors with one chunk fill one 64-entry array (slot v
+    // at kW v .. kW v + kW - 1), so one wave transpose-sum serves them all and
+    // every chunk is read once per pass.
+    constexpr int kP = kB == 1 ? 1 : kB == 2 ? 2 : 4;
+    constexpr int kW = kCChunk / kP;
     double x[kB];
 #pragma unroll
     for (int v = 0; v < kB; ++v) x[v] = live ? Y[(int64_t)v * ldy + row] : 0.0;
-    double q[kCChunk];
+    double q[kW];
+    auto load_chunk = [&](int c0) {
+        const double* qp = Q + (int64_t)c0 * ldq + rowc;
+#pragma unroll
+        for (int k = 0; k < kW; ++k) {   // columns past ncols read column ncols - 1 again
+            q[k] = *qp;
+            if (k + 1 < kW) qp += (c0 + k + 1 < ncols) ? ldq : 0;
+        }
+    };
     if (kMode > 0) {
-        for (int c0 = 0; c0 < ncols; c0 += kCChunk) {
-            load_row_chunk(Q, ldq, rowc, c0, ncols, q);
-            // one vector at a time, so that only its coefficients are in flight
-#pragma unroll 1
-            for (int v = 0; v < kB; ++v) {
-                double a = v == 0 ? x[0] : v == 1 ? x[kB > 1 ? 1 : 0]
-                         : v == 2 ? x[kB > 2 ? 2 : 0] : x[kB > 3 ? 3 : 0];
+        for (int c0 = 0; c0 < ncols; c0 += kW) {
+            load_chunk(c0);
 #pragma unroll
-                for (int k = 0; k < kCChunk; ++k) a = fma(-q[k], hs[v * cstride + c0 + k], a);
+            for (int v = 0; v < kB; ++v)
 #pragma unroll
-                for (int w = 0; w < kB; ++w) x[w] = v == w ? a : x[w];
-            }
+                for (int k = 0; k < kW; ++k) x[v] = fma(-q[k], hs[v * cstride + c0 + k], x[v]);
         }
 #pragma unroll
         for (int v = 0; v < kB; ++v) {
@@ -421,25 +429,24 @@ cgs_block_pass_kernel(const double* __restrict__ Q, int64_t ldq, int64_t len, in
         }
     }
     if (kMode == 2) return;
-    for (int c0 = 0; c0 < ncols; c0 += kCChunk) {
-        // with one chunk the rows loaded for the update are still in q; the
-        // products overwrite q, so every further vector reloads the chunk (from
-        // the cache: the workgroup has just read it)
-        bool have = kMode > 0 && ncols <= kCChunk;
-        // one vector at a time (not unrolled: one copy of the chunk in registers)
-#pragma unroll 1
-        for (int v = 0; v < kB; ++v) {
-            // keep the next vector's reload below this point: hoisted, it would
-            // hold a second copy of the chunk in registers
-            __builtin_amdgcn_sched_barrier(0);
-            if (!have) load_row_chunk(Q, ldq, rowc, c0, ncols, q);
-            have = false;
-            const double xv = v == 0 ? x[0] : v == 1 ? x[kB > 1 ? 1 : 0]
-                            : v == 2 ? x[kB > 2 ? 2 : 0] : x[kB > 3 ? 3 : 0];
+    for (int c0 = 0; c0 < ncols; c0 += kW) {
+        // with one chunk the rows loaded for the update are still in q
+        if (kMode == 0 || ncols > kW) load_chunk(c0);
+        double tmp[kCChunk];
 #pragma unroll
-            for (int k = 0; k < kCChunk; ++k) q[k] *= xv;
-            block_columns(wave_transpose_sum(q, lane), red,
-                          pout + ((int64_t)blockIdx.x * kB + v) * cstride, c0);
+        for (int v = 0; v < kP; ++v)
+#pragma unroll
+            for (int k = 0; k < kW; ++k) tmp[v * kW + k] = v < kB ? q[k] * x[v < kB ? v : 0] : 0.0;
+        const double sw = wave_transpose_sum(tmp, lane);   // lane l: slot l / kW, column c0 + l % kW
+        __syncthreads();
+        red[(t >> 6) * 64 + lane] = sw;
+        __syncthreads();
+        if (t < 64) {
+            double h = red[t];
+#pragma unroll
+            for (int w = 1; w < kCW; ++w) h += red[w * 64 + t];
+            const int v = t / kW;
+            if (v < kB) pout[((int64_t)blockIdx.x * kB + v) * cstride + c0 + t % kW] = h;
         }
     }
 }
