@@ -553,7 +553,8 @@ def run_paper_model(gk, torch, args, stream):
 
 
 def run_extra(gk, torch, name, args, stream):
-    """A second workload (FP64 and blocked b = 8 and 16) reported beside the headline."""
+    """A second workload (FP64, blocked b = 8 and 16 in split BF16, blocked with
+    FP64-exact pairs) reported beside the headline."""
     W = Workload(gk, torch, WORKLOADS[name], progress=False)
     ref = fp64_solve(gk, torch, W, W.wl["tol"], 3, 1, stream, label=f"{name} fp64")
     fmt = FORMAT_NAMES.get(int(ref["infos"][-1].fp64_products), "?")
@@ -566,6 +567,15 @@ def run_extra(gk, torch, name, args, stream):
         out[f"bf16_b{b}"] = {key: r[key] for key in (
             "solve_s", "create_s", "block_steps", "restarts", "sigma_max_rel_err_vs_fp64",
             "gated_max_angle", "speedup_vs_fp64", "A W", "A^T X")}
+    # the blocked GKL with FP64-exact limb pairs at the FP64 tolerance
+    for b in args.fp64_block_widths:
+        r = blocked_solve(gk, torch, W, b, "fp64", ref, stream, reps=2, tol=W.wl["tol"])
+        r["speedup_vs_fp64"] = ref["sec_per_step"] / (r["solve_s"] + r["create_s"])
+        out[f"fp64_block_b{b}"] = {key: r[key] for key in (
+            "solve_s", "create_s", "block_steps", "restarts", "passes_over_G",
+            "sigma_max_rel_err_vs_fp64", "gated_max_angle", "speedup_vs_fp64")}
+        log(f"[bench] {name} fp64 block b={b}: {r['solve_s'] * 1e3:.1f} ms + "
+            f"{r['create_s'] * 1e3:.1f} ms create (FP64 GKL {ref['sec_per_step'] * 1e3:.1f} ms)")
     out["reorthogonalisation"] = reorth_compare(gk, torch, W, ref, stream)
     del W
     torch.cuda.empty_cache()
