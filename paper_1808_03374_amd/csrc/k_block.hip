@@ -374,9 +374,9 @@ void launch_batch_proj(const BatchDesc* d, const int* state, int count, int side
 // (accumulated; R = I on the first pass when first != 0).  Non-positive pivots
 // are replaced by a tiny positive value and counted in *bad.  Right-looking
 // factorisation and a row-oriented back substitution, one barrier per stage.
-__global__ void __launch_bounds__(256)
-chol_kernel(const double* __restrict__ Gm, int b, double shift_rel, double* __restrict__ R,
-            double* __restrict__ Ri, int first, int* __restrict__ bad)
+__device__ __forceinline__ void chol_body(const double* Gm, int b, double shift_rel,
+                                          double* __restrict__ R, double* __restrict__ Ri,
+                                          int first, int* __restrict__ bad)
 {
     __shared__ double A[kBmax][kBmax + 1];      // becomes the upper factor Rn
     __shared__ double Xr[kBmax][kBmax + 1];     // inverse of Rn
@@ -447,6 +447,125 @@ chol_kernel(const double* __restrict__ Gm, int b, double shift_rel, double* __re
     if (t == 0 && bad && nbad) *bad += nbad;
 }
 
+__global__ void __launch_bounds__(256)
+chol_kernel(const double* __restrict__ Gm, int b, double shift_rel, double* __restrict__ R,
+            double* __restrict__ Ri, int first, int* __restrict__ bad)
+{
+    chol_body(Gm, b, shift_rel, R, Ri, first, bad);
+}
+
+// Blocks of kB <= 4 columns, one row per thread (grid-stride): with apply, the
+// row is first multiplied by the previous pass's inverse factor (upper
+// triangular, column-major in Ri) and written back; with partial, the
+// workgroup's sums of y_i y_j (i <= j, kB (kB + 1) / 2 of them) go to
+// partial[wg * kG + e].  One pass over Y serves both halves of a CholeskyQR
+// step, where the general path reads Y column-strided twice.
+template <int kB>
+__global__ void __launch_bounds__(256)
+gram_rows_kernel(double* __restrict__ Y, int64_t ldy, int64_t len, const double* __restrict__ Ri,
+                 int apply, double* __restrict__ partial)
+{
+    constexpr int kG = kB * (kB + 1) / 2;
+    __shared__ double ri[kB * kB];
+    __shared__ double red[4][kG];
+    if (apply)
+        for (int e = threadIdx.x; e < kB * kB; e += blockDim.x) ri[e] = Ri[e];
+    __syncthreads();
+    double g[kG];
+#pragma unroll
+    for (int e = 0; e < kG; ++e) g[e] = 0.0;
+    for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < len;
+         row += (int64_t)gridDim.x * blockDim.x) {
+        double y[kB];
+#pragma unroll
+        for (int j = 0; j < kB; ++j) y[j] = Y[(int64_t)j * ldy + row];
+        if (apply) {
+            double z[kB];
+#pragma unroll
+            for (int j = 0; j < kB; ++j) {
+                double a = 0.0;
+#pragma unroll
+                for (int i = 0; i <= j; ++i) a = fma(y[i], ri[i + j * kB], a);
+                z[j] = a;
+            }
+#pragma unroll
+            for (int j = 0; j < kB; ++j) {
+                Y[(int64_t)j * ldy + row] = z[j];
+                y[j] = z[j];
+            }
+        }
+        int e = 0;
+#pragma unroll
+        for (int i = 0; i < kB; ++i)
+#pragma unroll
+            for (int j = i; j < kB; ++j) {
+                g[e] = fma(y[i], y[j], g[e]);
+                ++e;
+            }
+    }
+    if (!partial) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int e = 0; e < kG; ++e) {
+        const double v = wave_sum(g[e]);
+        if (lane == 0) red[wave][e] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < kG)
+        partial[(int64_t)blockIdx.x * kG + threadIdx.x] =
+            ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
+}
+
+// The Gram matrix from gram_rows_kernel's nwg partials (one wave per entry,
+// lanes adding workgroups in order, then a fixed butterfly), then the Cholesky
+// step of chol_kernel.
+template <int kB>
+__global__ void __launch_bounds__(256)
+gram_chol_kernel(const double* __restrict__ partial, int nwg, double shift_rel,
+                 double* __restrict__ R, double* __restrict__ Ri, int first, int* __restrict__ bad)
+{
+    constexpr int kG = kB * (kB + 1) / 2;
+    __shared__ double Gs[kB * kB];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int e = wave; e < kG; e += (int)(blockDim.x >> 6)) {
+        double sum = 0.0;
+        for (int w = lane; w < nwg; w += 64) sum += partial[(int64_t)w * kG + e];
+        sum = wave_sum(sum);
+        if (lane == 0) {
+            int i = 0, r = e;          // entry e is (i, j), i <= j, rows of the upper triangle
+            while (r >= kB - i) {
+                r -= kB - i;
+                ++i;
+            }
+            const int j = i + r;
+            Gs[i + j * kB] = sum;
+            Gs[j + i * kB] = sum;
+        }
+    }
+    __syncthreads();
+    chol_body(Gs, kB, shift_rel, R, Ri, first, bad);
+}
+
+template <int kB>
+static void small_block_qr(double* Y, int64_t ldy, int64_t len, double* Rout, double* Ri,
+                           double* partial, int* bad, double shift, hipStream_t s)
+{
+    int64_t g = ceil_div(len, 256);
+    const int nwg = (int)(g < 1024 ? g : 1024);
+    for (int pass = 0; pass < 3; ++pass) {
+        hipLaunchKernelGGL(gram_rows_kernel<kB>, dim3(nwg), dim3(256), 0, s, Y, ldy, len, Ri,
+                           pass > 0 ? 1 : 0, partial);
+        GKL_LAUNCH_CHECK("gram_rows_kernel");
+        hipLaunchKernelGGL(gram_chol_kernel<kB>, dim3(1), dim3(256), 0, s, partial, nwg,
+                           pass == 0 ? shift : 0.0, Rout, Ri, pass == 0 ? 1 : 0,
+                           pass == 2 ? bad : nullptr);
+        GKL_LAUNCH_CHECK("gram_chol_kernel");
+    }
+    hipLaunchKernelGGL(gram_rows_kernel<kB>, dim3(nwg), dim3(256), 0, s, Y, ldy, len, Ri, 1,
+                       nullptr);
+    GKL_LAUNCH_CHECK("gram_rows_kernel");
+}
+
 // Shifted CholeskyQR3: Y (len x b) -> Q R with Q overwriting Y, R (b x b upper,
 // column-major) written to Rout.  work: >= 3 b*b doubles.
 void launch_block_qr(double* Y, int64_t ldy, int64_t len, int b, double* Rout, double* work,
@@ -456,6 +575,13 @@ void launch_block_qr(double* Y, int64_t ldy, int64_t len, int b, double* Rout, d
     double* Ri = work + b * b;
     const double u = 1.1102230246251565e-16;
     const double shift = 11.0 * ((double)len * b + (double)b * (b + 1)) * u;
+    switch (b) {   // up to four columns: the row-parallel passes (7 launches instead of 12)
+    case 1: small_block_qr<1>(Y, ldy, len, Rout, Ri, partial, bad, shift, s); return;
+    case 2: small_block_qr<2>(Y, ldy, len, Rout, Ri, partial, bad, shift, s); return;
+    case 3: small_block_qr<3>(Y, ldy, len, Rout, Ri, partial, bad, shift, s); return;
+    case 4: small_block_qr<4>(Y, ldy, len, Rout, Ri, partial, bad, shift, s); return;
+    default: break;
+    }
     for (int pass = 0; pass < 3; ++pass) {
         launch_gemm_tn(Y, ldy, Y, ldy, len, b, b, Gm, b, partial, s);
         hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(256), 0, s, Gm, b, pass == 0 ? shift : 0.0,
