@@ -374,9 +374,20 @@ void launch_batch_proj(const BatchDesc* d, const int* state, int count, int side
 // (accumulated; R = I on the first pass when first != 0).  Non-positive pivots
 // are replaced by a tiny positive value and counted in *bad.  Right-looking
 // factorisation and a row-oriented back substitution, one barrier per stage.
+//
+// guard (optional, per solve): guard[0] is the running maximum of the squared
+// column norms the first pass has seen (a scale of the largest singular value);
+// the last pass (pass == 2) sets guard[1] to 1 when a diagonal entry of the
+// accumulated R is at most kGuardRel times that scale, else to 0.  Such a column
+// was (numerically) dependent on the basis or on the block's earlier columns:
+// the Cholesky QR scales its rounding residue up to unit length, and that
+// residue is not orthogonal to the basis.  block_finish_kernel repairs it.
+constexpr double kGuardRel = 1e-4;
+
 __device__ __forceinline__ void chol_body(const double* Gm, int b, double shift_rel,
                                           double* __restrict__ R, double* __restrict__ Ri,
-                                          int first, int* __restrict__ bad)
+                                          int first, int* __restrict__ bad,
+                                          double* __restrict__ guard, int pass)
 {
     __shared__ double A[kBmax][kBmax + 1];      // becomes the upper factor Rn
     __shared__ double Xr[kBmax][kBmax + 1];     // inverse of Rn
@@ -396,6 +407,11 @@ __device__ __forceinline__ void chol_body(const double* Gm, int b, double shift_
         for (int i = 0; i < b; ++i) tr += A[i][i];
         trace = tr;
         nbad = 0;
+        if (guard && pass == 0) {
+            double mx = guard[0];
+            for (int i = 0; i < b; ++i) mx = fmax(mx, A[i][i]);
+            guard[0] = mx;
+        }
         const double sh = shift_rel * tr;
         for (int i = 0; i < b; ++i) A[i][i] += sh;
     }
@@ -445,13 +461,20 @@ __device__ __forceinline__ void chol_body(const double* Gm, int b, double shift_
         R[e] = s;
     }
     if (t == 0 && bad && nbad) *bad += nbad;
+    if (t == 0 && guard && pass == 2) {
+        const double floor = kGuardRel * sqrt(guard[0]);
+        int weak = 0;
+        for (int j = 0; j < b; ++j) weak |= A[j][j] * Rold[j][j] <= floor ? 1 : 0;
+        guard[1] = weak ? 1.0 : 0.0;
+    }
 }
 
 __global__ void __launch_bounds__(256)
 chol_kernel(const double* __restrict__ Gm, int b, double shift_rel, double* __restrict__ R,
-            double* __restrict__ Ri, int first, int* __restrict__ bad)
+            double* __restrict__ Ri, int first, int* __restrict__ bad, double* __restrict__ guard,
+            int pass)
 {
-    chol_body(Gm, b, shift_rel, R, Ri, first, bad);
+    chol_body(Gm, b, shift_rel, R, Ri, first, bad, guard, pass);
 }
 
 // Blocks of kB <= 4 columns, one row per thread (grid-stride): with apply, the
@@ -522,7 +545,8 @@ gram_rows_kernel(double* __restrict__ Y, int64_t ldy, int64_t len, const double*
 template <int kB>
 __global__ void __launch_bounds__(256)
 gram_chol_kernel(const double* __restrict__ partial, int nwg, double shift_rel,
-                 double* __restrict__ R, double* __restrict__ Ri, int first, int* __restrict__ bad)
+                 double* __restrict__ R, double* __restrict__ Ri, int first, int* __restrict__ bad,
+                 double* __restrict__ guard, int pass)
 {
     constexpr int kG = kB * (kB + 1) / 2;
     __shared__ double Gs[kB * kB];
@@ -543,12 +567,12 @@ gram_chol_kernel(const double* __restrict__ partial, int nwg, double shift_rel,
         }
     }
     __syncthreads();
-    chol_body(Gs, kB, shift_rel, R, Ri, first, bad);
+    chol_body(Gs, kB, shift_rel, R, Ri, first, bad, guard, pass);
 }
 
 template <int kB>
 static void small_block_qr(double* Y, int64_t ldy, int64_t len, double* Rout, double* Ri,
-                           double* partial, int* bad, double shift, hipStream_t s)
+                           double* partial, int* bad, double shift, double* guard, hipStream_t s)
 {
     int64_t g = ceil_div(len, 256);
     const int nwg = (int)(g < 1024 ? g : 1024);
@@ -558,7 +582,7 @@ static void small_block_qr(double* Y, int64_t ldy, int64_t len, double* Rout, do
         GKL_LAUNCH_CHECK("gram_rows_kernel");
         hipLaunchKernelGGL(gram_chol_kernel<kB>, dim3(1), dim3(256), 0, s, partial, nwg,
                            pass == 0 ? shift : 0.0, Rout, Ri, pass == 0 ? 1 : 0,
-                           pass == 2 ? bad : nullptr);
+                           pass == 2 ? bad : nullptr, guard, pass);
         GKL_LAUNCH_CHECK("gram_chol_kernel");
     }
     hipLaunchKernelGGL(gram_rows_kernel<kB>, dim3(nwg), dim3(256), 0, s, Y, ldy, len, Ri, 1,
@@ -569,23 +593,23 @@ static void small_block_qr(double* Y, int64_t ldy, int64_t len, double* Rout, do
 // Shifted CholeskyQR3: Y (len x b) -> Q R with Q overwriting Y, R (b x b upper,
 // column-major) written to Rout.  work: >= 3 b*b doubles.
 void launch_block_qr(double* Y, int64_t ldy, int64_t len, int b, double* Rout, double* work,
-                     double* partial, int* bad, hipStream_t s)
+                     double* partial, int* bad, hipStream_t s, double* guard)
 {
     double* Gm = work;
     double* Ri = work + b * b;
     const double u = 1.1102230246251565e-16;
     const double shift = 11.0 * ((double)len * b + (double)b * (b + 1)) * u;
     switch (b) {   // up to four columns: the row-parallel passes (7 launches instead of 12)
-    case 1: small_block_qr<1>(Y, ldy, len, Rout, Ri, partial, bad, shift, s); return;
-    case 2: small_block_qr<2>(Y, ldy, len, Rout, Ri, partial, bad, shift, s); return;
-    case 3: small_block_qr<3>(Y, ldy, len, Rout, Ri, partial, bad, shift, s); return;
-    case 4: small_block_qr<4>(Y, ldy, len, Rout, Ri, partial, bad, shift, s); return;
+    case 1: small_block_qr<1>(Y, ldy, len, Rout, Ri, partial, bad, shift, guard, s); return;
+    case 2: small_block_qr<2>(Y, ldy, len, Rout, Ri, partial, bad, shift, guard, s); return;
+    case 3: small_block_qr<3>(Y, ldy, len, Rout, Ri, partial, bad, shift, guard, s); return;
+    case 4: small_block_qr<4>(Y, ldy, len, Rout, Ri, partial, bad, shift, guard, s); return;
     default: break;
     }
     for (int pass = 0; pass < 3; ++pass) {
         launch_gemm_tn(Y, ldy, Y, ldy, len, b, b, Gm, b, partial, s);
         hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(256), 0, s, Gm, b, pass == 0 ? shift : 0.0,
-                           Rout, Ri, pass == 0 ? 1 : 0, pass == 2 ? bad : nullptr);
+                           Rout, Ri, pass == 0 ? 1 : 0, pass == 2 ? bad : nullptr, guard, pass);
         GKL_LAUNCH_CHECK("chol_kernel");
         launch_gemm_nn(Y, ldy, b, Ri, b, Y, ldy, len, b, 0, s);
     }
@@ -611,6 +635,111 @@ void launch_put_block(double* Bm, int ldb, int r0, int c0, const double* X, int 
     hipLaunchKernelGGL(put_block_kernel, dim3(1), dim3(256), 0, s, Bm, ldb, r0, c0, X, rows, cols,
                        ldx, transpose);
     GKL_LAUNCH_CHECK("put_block_kernel");
+}
+
+// After the block QR of Y (len x b, Y = Q R with Q in place): when the QR set
+// guard[1] (a column of R below the guard level), re-orthogonalise Q column by
+// column against the basis Qb (len x q) and the block's earlier columns, with a
+// second and third pass while a pass shrinks the column below 1/sqrt(2) of its
+// length (Kahan's criterion for Gram-Schmidt).  A column still shrinking after
+// three passes lies in the span and becomes zero.  With Q = Q' T (T upper
+// triangular: the block coefficients above the diagonal, the final lengths on
+// it; basis components, which are rounding residue, are dropped), R becomes
+// T R.  Then R (or R^T when transpose != 0) is written into Bm at (r0, c0).
+// One workgroup: the repair is rare (a Krylov space that runs out on a matrix
+// of low rank), the write is every step's.
+constexpr int kRepChunk = 256;
+
+__global__ void __launch_bounds__(1024)
+block_finish_kernel(double* __restrict__ Y, int64_t ldy, int64_t len, int b,
+                    const double* __restrict__ Qb, int64_t ldq, int q, double* __restrict__ R,
+                    const double* __restrict__ guard, double* __restrict__ Bm, int ldb, int r0,
+                    int c0, int transpose)
+{
+    __shared__ double T[kBmax][kBmax + 1];
+    __shared__ double Rs[kBmax][kBmax + 1];
+    __shared__ double coef[kRepChunk];
+    __shared__ double red[16];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6, nw = (int)(blockDim.x >> 6);
+    for (int e = t; e < b * b; e += blockDim.x) Rs[e % b][e / b] = R[e];
+    const bool repair = guard && guard[1] != 0.0;
+    if (repair) {
+        for (int e = t; e < b * b; e += blockDim.x) T[e % b][e / b] = 0.0;
+        __syncthreads();
+        for (int j = 0; j < b; ++j) {
+            double* w = Y + (int64_t)j * ldy;
+            double a = 0.0;
+            for (int64_t i = t; i < len; i += blockDim.x) a = fma(w[i], w[i], a);
+            double before = sqrt(block_sum(a, red));
+            double nu = before;
+            bool accepted = false;
+            for (int pass = 0; pass < 3 && !accepted; ++pass) {
+                const int ncol = q + j;     // basis, then the block's repaired columns
+                for (int cb = 0; cb < ncol; cb += kRepChunk) {
+                    const int cn = ncol - cb < kRepChunk ? ncol - cb : kRepChunk;
+                    for (int c = wave; c < cn; c += nw) {
+                        const int col = cb + c;
+                        const double* x = col < q ? Qb + (int64_t)col * ldq : Y + (int64_t)(col - q) * ldy;
+                        double d = 0.0;
+                        for (int64_t i = lane; i < len; i += 64) d = fma(x[i], w[i], d);
+                        d = wave_sum(d);
+                        if (lane == 0) coef[c] = d;
+                    }
+                    __syncthreads();
+                    for (int64_t i = t; i < len; i += blockDim.x) {
+                        double v = w[i];
+                        for (int c = 0; c < cn; ++c) {
+                            const int col = cb + c;
+                            const double* x = col < q ? Qb + (int64_t)col * ldq
+                                                      : Y + (int64_t)(col - q) * ldy;
+                            v = fma(-coef[c], x[i], v);
+                        }
+                        w[i] = v;
+                    }
+                    if (t < cn && cb + t >= q) T[cb + t - q][j] += coef[t];
+                    __syncthreads();
+                }
+                a = 0.0;
+                for (int64_t i = t; i < len; i += blockDim.x) a = fma(w[i], w[i], a);
+                nu = sqrt(block_sum(a, red));
+                accepted = nu > 0.70710678118654752 * before;
+                before = nu;
+            }
+            const double scale = accepted && nu > 0.0 ? 1.0 / nu : 0.0;
+            for (int64_t i = t; i < len; i += blockDim.x) w[i] *= scale;
+            if (t == 0) T[j][j] = scale != 0.0 ? nu : 0.0;
+            __syncthreads();
+        }
+        // R <- T R (both upper triangular), kept in Rs
+        double v[4];
+        int cnt = 0;
+        for (int e = t; e < b * b && cnt < 4; e += blockDim.x, ++cnt) {
+            const int i = e % b, k = e / b;
+            double s = 0.0;
+            for (int l = i; l <= k; ++l) s += T[i][l] * Rs[l][k];
+            v[cnt] = i <= k ? s : 0.0;
+        }
+        __syncthreads();
+        cnt = 0;
+        for (int e = t; e < b * b && cnt < 4; e += blockDim.x, ++cnt) {
+            Rs[e % b][e / b] = v[cnt];
+            R[e] = v[cnt];
+        }
+    }
+    __syncthreads();
+    for (int e = t; e < b * b; e += blockDim.x) {
+        const int i = e % b, j = e / b;
+        Bm[(int64_t)(c0 + j) * ldb + r0 + i] = transpose ? Rs[j][i] : Rs[i][j];
+    }
+}
+
+void launch_block_finish(double* Y, int64_t ldy, int64_t len, int b, const double* Qb,
+                         int64_t ldq, int q, double* R, const double* guard, double* Bm, int ldb,
+                         int r0, int c0, int transpose, hipStream_t s)
+{
+    hipLaunchKernelGGL(block_finish_kernel, dim3(1), dim3(1024), 0, s, Y, ldy, len, b, Qb, ldq, q,
+                       R, guard, Bm, ldb, r0, c0, transpose);
+    GKL_LAUNCH_CHECK("block_finish_kernel");
 }
 
 // Copy the leading m x m of Bm (ldb) into a compact m x m buffer.

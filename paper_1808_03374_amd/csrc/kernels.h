@@ -440,9 +440,16 @@ void launch_gemm_nn(const double* Q, int64_t ldq, int q, const double* H, int ld
 // Y -= Q H
 void launch_gemm_nn_sub(const double* Q, int64_t ldq, double* Y, int64_t ldy, int64_t len, int q,
                         int b, const double* H, int ldh, hipStream_t s);
-// shifted CholeskyQR3 of Y in place; R (b x b upper) to Rout; work >= 3 b^2
+// shifted CholeskyQR3 of Y in place; R (b x b upper) to Rout; work >= 3 b^2.
+// guard (2 doubles, optional): running column-norm scale and the flag for a
+// column of R below 1e-4 of it, read by launch_block_finish.
 void launch_block_qr(double* Y, int64_t ldy, int64_t len, int b, double* Rout, double* work,
-                     double* partial, int* bad, hipStream_t s);
+                     double* partial, int* bad, hipStream_t s, double* guard = nullptr);
+// Repairs a flagged block (Y, len x b, against the basis Qb, len x q, and
+// within the block; R updated) and writes R (transpose: R^T) into Bm at (r0, c0).
+void launch_block_finish(double* Y, int64_t ldy, int64_t len, int b, const double* Qb,
+                         int64_t ldq, int q, double* R, const double* guard, double* Bm, int ldb,
+                         int r0, int c0, int transpose, hipStream_t s);
 void launch_put_block(double* Bm, int ldb, int r0, int c0, const double* X, int rows, int cols,
                       int ldx, int transpose, hipStream_t s);
 void launch_copy_lead(const double* Bm, int ldb, int m, double* out, hipStream_t s);

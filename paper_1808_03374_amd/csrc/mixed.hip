@@ -49,6 +49,7 @@ struct MixedState {
     double* svd_scratch = nullptr;
     double* svd_log = nullptr;         // rotation log of the SVD for 96 < m <= 128
     int* iflags = nullptr;     // [0] nconv [1] bad pivots
+    double* guard = nullptr;   // [0] column-norm scale [1] block QR flag
     RitzOut ritz{};
 };
 
@@ -109,6 +110,7 @@ void gkl_ctx::setup_mixed()
     M.gpart_elems = std::max(gp, block_cgs2_partial_elems(std::max(n, p), m + b, b));
     M.gpart = static_cast<double*>(A.alloc(sizeof(double) * M.gpart_elems));
     M.iflags = static_cast<int*>(A.alloc(sizeof(int) * 8));
+    M.guard = static_cast<double*>(A.alloc(sizeof(double) * 2));
     M.ritz.B = M.Bc;
     M.ritz.P = static_cast<double*>(A.alloc(sizeof(double) * (size_t)m * m));
     M.ritz.Q = static_cast<double*>(A.alloc(sizeof(double) * (size_t)m * m));
@@ -154,6 +156,7 @@ gkl_status gkl_ctx::solve_mixed(double* sigma, double* Uo, int64_t ldu, double* 
     else launch_gaussian(M.V, p * b, opt.seed, 0, s);
     GKL_HIP(hipMemsetAsync(M.Bm, 0, sizeof(double) * (size_t)M.ldb * M.ldb, s));
     GKL_HIP(hipMemsetAsync(M.iflags, 0, sizeof(int) * 8, s));
+    GKL_HIP(hipMemsetAsync(M.guard, 0, sizeof(double) * 2, s));
     launch_block_qr(M.V, p, p, b, M.R, M.qrwork, M.gpart, M.iflags + 1, s);
     int o = 0;
     int nlock_m = 0;         // columns kept at the last restart (0 = none)
@@ -184,8 +187,10 @@ gkl_status gkl_ctx::solve_mixed(double* sigma, double* Uo, int64_t ldu, double* 
             block_cgs2(M, M.U, n, o, Ub, s);
             info.reorths += 2;
         }
-        launch_block_qr(Ub, n, n, b, M.R, M.qrwork, M.gpart, M.iflags + 1, s);
-        launch_put_block(M.Bm, M.ldb, o, o, M.R, b, b, b, 0, s);
+        // a block that ran out of new directions (low rank) is repaired before
+        // its R enters the projected matrix
+        launch_block_qr(Ub, n, n, b, M.R, M.qrwork, M.gpart, M.iflags + 1, s, M.guard);
+        launch_block_finish(Ub, n, n, b, M.U, n, o, M.R, M.guard, M.Bm, M.ldb, o, o, 0, s);
         // right block: A^T U_o - V_o R^T
         const int ev2 = timing_begin(true);
         launch_rmatmat_mixed(M.shape, M.S, prob.st, Ub, n, b, Vn, p, M.w, s,
@@ -197,8 +202,8 @@ gkl_status gkl_ctx::solve_mixed(double* sigma, double* Uo, int64_t ldu, double* 
         launch_gemm_nn_sub(Vb, p, Vn, p, p, b, b, M.RT, b, s);
         block_cgs2(M, M.V, p, o + b, Vn, s);
         info.reorths += 2;
-        launch_block_qr(Vn, p, p, b, M.C, M.qrwork, M.gpart, M.iflags + 1, s);
-        launch_put_block(M.Bm, M.ldb, o, o + b, M.C, b, b, b, 1, s);
+        launch_block_qr(Vn, p, p, b, M.C, M.qrwork, M.gpart, M.iflags + 1, s, M.guard);
+        launch_block_finish(Vn, p, p, b, M.V, p, o + b, M.C, M.guard, M.Bm, M.ldb, o, o + b, 1, s);
         o += b;
         mcur = o;
         info.steps += 1;

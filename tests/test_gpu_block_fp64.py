@@ -137,3 +137,37 @@ def test_block_fp64_not_for_loco(gk):
     packed = rng.integers(0, 256, size=(900, 100), dtype=np.uint8)
     with pytest.raises(gk.GKLError):
         gk.LocoContext(dev(packed), 400, 900, [0, 500, 900], 3, precision=gk.GKL_PREC_BLOCK_FP64)
+
+
+def _dense_sigma(packed, n, p, k):
+    st = oracle.column_stats(n, *oracle.counts(packed, n, p))
+    A = oracle.dense_matrix(oracle.decode(packed, n, p), st.mean, st.inv_sd)
+    return np.linalg.svd(A, compute_uv=False)[:k]
+
+
+@pytest.mark.parametrize("fmt,tol_sigma", [("BLOCK_FP64", 1e-10), ("MIXED", 1e-6), ("MIXED_INT8", 1e-6)])
+@pytest.mark.parametrize("b", [2, 3])
+def test_small_blocks_on_rank_deficient_matrices(gk, fmt, tol_sigma, b):
+    # blocks of 2 and 3 columns (the row-parallel block QR and the fused block
+    # Gram-Schmidt) on a matrix of rank at most 8: the Krylov space runs out and
+    # the blocks turn dependent, so the shifted Cholesky QR and the breakdown
+    # handling are exercised; the top singular values still come out right
+    rng = np.random.default_rng(40 + b)
+    n, p, r = 400, 1200, 8
+    base = rng.integers(0, 3, size=(n, r))
+    codes = base[:, rng.integers(0, r, size=p)]
+    packed = synth.pack_codes(codes)
+    k = 4
+    ref = _dense_sigma(packed, n, p, k)
+    # the budget bounds the run if the breakdown handling ever fails
+    ctx = gk.Context(dev(packed), n, p, k, tol=1e-11, precision=getattr(gk, "GKL_PREC_" + fmt),
+                     block_width=b, krylov_dim=24, max_matvecs=3000)
+    sigma, U, V, st, info = ctx.solve()
+    ctx.close()
+    assert st == gk.GKL_OK, (st, info.matvecs, info.restarts)
+    sigma = sigma.cpu().numpy()
+    assert np.all(np.abs(sigma - ref) <= tol_sigma * ref[0]), (sigma, ref)
+    V = V.cpu().numpy()
+    U = U.cpu().numpy()
+    assert np.abs(V.T @ V - np.eye(k)).max() < 1e-8
+    assert np.abs(U.T @ U - np.eye(k)).max() < 1e-8
