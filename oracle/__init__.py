@@ -21,10 +21,17 @@ Parity status per function (what pins it is listed in the tests):
                                   orthogonal and identical spans)
   certificate                     pinned (operator with a known SVD: exact triplets,
                                   sigma shifted by known deltas, a tilted vector)
+  thick_restart                   pinned (harmonic values and vectors against the
+                                  Petrov definition solved as a generalized symmetric
+                                  eigenproblem; the restarted relations A V = U H and
+                                  A^T U in span of the new right basis, with a dense A)
+  gkl_svd_thick                   pinned (dense LAPACK SVD after several restarts of
+                                  either kind)
 """
 from .gkl_oracle import (  # noqa: F401
     build_library, decode, counts, column_stats, dense_matrix, DenseOperator,
     PackedOperator, cgs2, gkl_svd, GKLResult, sign_fix, certificate,
+    thick_restart, gkl_svd_thick, RestartPlan,
     frobenius_sq_from_counts, mp_eigen_density, mp_singular_density,
     mp_singular_edges, subspace_angles,
 )

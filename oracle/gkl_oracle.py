@@ -19,6 +19,13 @@ Paper passages followed:
     with denominator 2 pi sigma^2 min(1, rho) xi (eigenvalues) and
     pi sigma^2 min(1, rho) x (singular values), rho = rows / columns.
 
+  * Section 3, "Thick restarting": restarts that keep l Ritz vectors, from
+    ordinary Ritz values (Wu & Simon 2000) or from harmonic Ritz values (Baglama
+    & Reichel, SIAM J. Sci. Comput. 27, 2005).  Here the harmonic Ritz pairs
+    are those of A^T A on span(V_m) with the Petrov condition taken against
+    A^T A V_m; their values are the squared singular values of [B_m, beta_m e_m]
+    and their vectors V_m B_m^-1 p_j (p_j its left singular vectors).
+
 Readings where the paper is silent (listed with the rest in the design notes):
   * preprocessing: column centring by the observed mean and scaling by
     1/sqrt(2 f (1 - f)), f = mean / 2; missing entries mean-imputed (zero);
@@ -359,6 +366,133 @@ def gkl_svd(op, k: int, tol: float = 1e-12, v0: np.ndarray | None = None,
     Uk, Vk = sign_fix(Uk, Vk)
     return GKLResult(S[:k].copy(), Uk, Vk, res[:k].copy(), alphas[:steps].copy(),
                      betas[:steps].copy(), steps, op.matvecs - start_mv, converged, breakdowns)
+
+
+# ---------------------------------------------------------------------------
+# Thick restart (ordinary or harmonic Ritz vectors), full CGS2
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class RestartPlan:
+    Yl: np.ndarray       # m x l: new left basis U_m Yl
+    Z: np.ndarray        # (m+1) x (l+1): new right basis V_{m+1} Z
+    H: np.ndarray        # l x l: U_new^T A V_new[:, :l]
+    c: np.ndarray        # l: U_new^T A V_new[:, l]
+    values: np.ndarray   # l: the Ritz (or harmonic Ritz) singular values kept
+
+
+def thick_restart(B: np.ndarray, beta_m: float, l: int, kind: str) -> RestartPlan:
+    """Small-space part of a thick restart after m steps (Section 3, "Thick
+    restarting"), from A V_m = U_m B and A^T U_m = V_m B^T + beta_m v_{m+1} e_m^T.
+
+    kind "ritz" (Wu & Simon): B = P S Q^T; keep U_m P_l, V_m Q_l and v_{m+1}.
+    kind "harmonic" (Baglama & Reichel): [B, beta_m e_m] = Ph Sh Qh^T; the
+    harmonic Ritz vectors are V_m B^-1 Ph_l (orthonormalised: V_m Qx), the left
+    vectors U_m Ph_l, and the last new right vector is what is left of
+    v_{m+1} - beta_m V_m B^-1 e_m (the direction every harmonic residual lies
+    on) after orthogonalisation against V_m Qx.
+    H and c follow from their definitions through A V_m = U_m B and
+    u^T A v_{m+1} = (A^T u)^T v_{m+1} = beta_m (e_m^T y) for u = U_m y.
+    """
+    m = B.shape[0]
+    em = np.zeros(m)
+    em[m - 1] = 1.0
+    if kind == "ritz":
+        P, S, Qt = np.linalg.svd(B)
+        Yl = P[:, :l]
+        Z = np.zeros((m + 1, l + 1))
+        Z[:m, :l] = Qt.T[:, :l]
+        Z[m, l] = 1.0
+        values = S[:l].copy()
+    elif kind == "harmonic":
+        Bh = np.hstack([B, beta_m * em[:, None]])
+        Ph, Sh, _ = np.linalg.svd(Bh, full_matrices=False)
+        Yl = Ph[:, :l]
+        X = np.linalg.solve(B, Yl)
+        Qx, _ = np.linalg.qr(X)
+        w = np.concatenate([-beta_m * np.linalg.solve(B, em), [1.0]])
+        Q1 = np.vstack([Qx, np.zeros((1, l))])
+        w = cgs2(Q1, w)
+        Z = np.hstack([Q1, (w / np.linalg.norm(w))[:, None]])
+        values = Sh[:l].copy()
+    else:
+        raise ValueError("kind must be 'ritz' or 'harmonic'")
+    H = Yl.T @ B @ Z[:m, :l]
+    c = Yl.T @ B @ Z[:m, l] + Z[m, l] * beta_m * Yl[m - 1, :]
+    return RestartPlan(Yl, Z, H, c, values)
+
+
+def gkl_svd_thick(op, k: int, tol: float, krylov: int, keep: int, restart: str = "ritz",
+                  v0: np.ndarray | None = None, max_restarts: int = 1000) -> GKLResult:
+    """Top-k singular triplets by GKL with full CGS2 and thick restarts.
+
+    The basis grows to m = krylov vectors; then the residual test of gkl_svd
+    runs on the projected matrix B (its first l rows hold the restart head H and
+    the coupling column c after a restart, the rest is bidiagonal), and if it
+    fails, thick_restart keeps l = keep vectors.  The first step after a restart
+    subtracts U_l c from A v_l (the coupling), every other step beta u_{j-1}.
+    alphas and betas list every step, across restarts.
+    """
+    n, p = op.shape
+    m = int(krylov)
+    if not (1 <= k <= keep < m <= min(n, p)):
+        raise ValueError("need 1 <= k <= keep < krylov <= min(n, p)")
+    if v0 is None:
+        v0 = np.random.default_rng(0).standard_normal(p)
+    U = np.zeros((n, m))
+    V = np.zeros((p, m + 1))
+    B = np.zeros((m, m))
+    V[:, 0] = v0 / np.linalg.norm(v0)
+    alphas, betas = [], []
+    start_mv = op.matvecs
+    nlock = 0
+    restarts = 0
+    j = 0
+    converged = False
+    while True:
+        w = op.matvec(V[:, j])
+        if j > 0 and j == nlock:
+            w = w - U[:, :nlock] @ B[:nlock, nlock]
+        elif j > 0:
+            w = w - B[j - 1, j] * U[:, j - 1]
+        w = cgs2(U[:, :j], w)
+        a = float(np.linalg.norm(w))
+        U[:, j] = w / a
+        B[j, j] = a
+        r = op.rmatvec(U[:, j]) - a * V[:, j]
+        r = cgs2(V[:, : j + 1], r)
+        b = float(np.linalg.norm(r))
+        V[:, j + 1] = r / b
+        if j + 1 < m:
+            B[j, j + 1] = b
+        alphas.append(a)
+        betas.append(b)
+        j += 1
+        if j < m:
+            continue
+        P, S, Qt = np.linalg.svd(B)
+        res = b * np.abs(P[m - 1, :])
+        if np.all(res[:k] <= tol * S[0]):
+            converged = True
+            break
+        if restarts >= max_restarts:
+            break
+        plan = thick_restart(B, b, keep, restart)
+        U[:, :keep] = U @ plan.Yl
+        V[:, : keep + 1] = V @ plan.Z
+        B = np.zeros((m, m))
+        B[:keep, :keep] = plan.H
+        B[:keep, keep] = plan.c
+        nlock = keep
+        j = keep
+        restarts += 1
+    Uk = U @ P[:, :k]
+    Vk = V[:, :m] @ Qt.T[:, :k]
+    Uk, Vk = sign_fix(Uk, Vk)
+    out = GKLResult(S[:k].copy(), Uk, Vk, res[:k].copy(), np.array(alphas), np.array(betas),
+                    len(alphas), op.matvecs - start_mv, converged, 0)
+    out.restarts = restarts
+    return out
 
 
 def certificate(op, sigma, U, V):
