@@ -24,7 +24,8 @@ Paper passages followed:
     & Reichel, SIAM J. Sci. Comput. 27, 2005).  Here the harmonic Ritz pairs
     are those of A^T A on span(V_m) with the Petrov condition taken against
     A^T A V_m; their values are the squared singular values of [B_m, beta_m e_m]
-    and their vectors V_m B_m^-1 p_j (p_j its left singular vectors).
+    and their vectors V_m B_m^-1 p_j (p_j its left singular vectors), formed
+    from the right singular vectors and the null vector of [B_m, beta_m e_m].
 
 Readings where the paper is silent (listed with the rest in the design notes):
   * preprocessing: column centring by the observed mean and scaling by
@@ -386,11 +387,16 @@ def thick_restart(B: np.ndarray, beta_m: float, l: int, kind: str) -> RestartPla
     restarting"), from A V_m = U_m B and A^T U_m = V_m B^T + beta_m v_{m+1} e_m^T.
 
     kind "ritz" (Wu & Simon): B = P S Q^T; keep U_m P_l, V_m Q_l and v_{m+1}.
-    kind "harmonic" (Baglama & Reichel): [B, beta_m e_m] = Ph Sh Qh^T; the
-    harmonic Ritz vectors are V_m B^-1 Ph_l (orthonormalised: V_m Qx), the left
-    vectors U_m Ph_l, and the last new right vector is what is left of
-    v_{m+1} - beta_m V_m B^-1 e_m (the direction every harmonic residual lies
-    on) after orthogonalisation against V_m Qx.
+    kind "harmonic" (Baglama & Reichel): with [B, beta_m e_m] = Ph Sh Qh^T, the
+    harmonic Ritz vectors are V_m B^-1 Ph_l and their residuals all lie along
+    V_{m+1} w, w = [-beta_m B^-1 e_m; 1].  Since [B, beta_m e_m] w = 0, w spans
+    the null space of [B, beta_m e_m] (its last right singular vector), and
+    sigma_j [B^-1 ph_j; 0] = qh_j - qh_j(m+1) w, so the kept space is
+    span{qh_1..qh_l, w} and the harmonic vectors are its members with a zero
+    last coordinate.  Both come from the SVD without B^-1, which is nearly
+    singular when the Krylov space holds a near-null vector of A (a wide
+    genotype matrix).  One Householder reflection of [qh_1..qh_l, w] zeroes the
+    last coordinate of its first l columns; the left vectors are U_m Ph_l.
     H and c follow from their definitions through A V_m = U_m B and
     u^T A v_{m+1} = (A^T u)^T v_{m+1} = beta_m (e_m^T y) for u = U_m y.
     """
@@ -406,14 +412,14 @@ def thick_restart(B: np.ndarray, beta_m: float, l: int, kind: str) -> RestartPla
         values = S[:l].copy()
     elif kind == "harmonic":
         Bh = np.hstack([B, beta_m * em[:, None]])
-        Ph, Sh, _ = np.linalg.svd(Bh, full_matrices=False)
+        Ph, Sh, Qht = np.linalg.svd(Bh, full_matrices=True)
         Yl = Ph[:, :l]
-        X = np.linalg.solve(B, Yl)
-        Qx, _ = np.linalg.qr(X)
-        w = np.concatenate([-beta_m * np.linalg.solve(B, em), [1.0]])
-        Q1 = np.vstack([Qx, np.zeros((1, l))])
-        w = cgs2(Q1, w)
-        Z = np.hstack([Q1, (w / np.linalg.norm(w))[:, None]])
+        QS = np.hstack([Qht[:l].T, Qht[m][:, None]])
+        r = QS[m, :]
+        v = r.copy()
+        v[l] += np.copysign(np.linalg.norm(r), r[l])
+        Z = QS - np.outer(QS @ v, (2.0 / (v @ v)) * v)
+        Z[m, :l] = 0.0
         values = Sh[:l].copy()
     else:
         raise ValueError("kind must be 'ritz' or 'harmonic'")
