@@ -109,6 +109,20 @@ enum gkl_fp64_products {
     GKL_FP64_AUTO = 0, GKL_FP64_LUT = 1, GKL_FP64_LIMBS = 2, GKL_FP64_LUT_LIMBS = 3
 };
 
+/* Thick restart (Section 3, "Thick restarting"), used when krylov_dim > 0.
+ * GKL_RESTART_RITZ: keep the l leading ordinary Ritz vectors (Wu & Simon); the
+ * projected matrix restarts as diag(sigma) with one coupling column.
+ * GKL_RESTART_HARMONIC: keep the l leading harmonic Ritz vectors of A^T A on
+ * span(V_m) (Baglama & Reichel, SIAM J. Sci. Comput. 27, 2005): the squared
+ * singular values of [B_m, beta_m e_m], vectors V_m B_m^-1 p_j, and the
+ * direction their residuals share; the projected matrix restarts with a dense
+ * l x l head.  Convergence tests and the returned triplets use ordinary Ritz
+ * values either way.  Built for GKL_PREC_FP64 with GKL_REORTH_FULL (the
+ * partial reorthogonalisation recurrences assume the diagonal head); a restart
+ * whose basis recorded a breakdown (a zero recurrence scalar, B_m singular)
+ * falls back to the ordinary kind. */
+enum gkl_restart { GKL_RESTART_RITZ = 0, GKL_RESTART_HARMONIC = 1 };
+
 /* Options.  Always initialise with gkl_options_default(). */
 typedef struct gkl_options {
     uint32_t struct_size;     /* sizeof(gkl_options), set by gkl_options_default */
@@ -147,6 +161,7 @@ typedef struct gkl_options {
                                  batched path forms A v from the tables in every case
                                  and A^T u in limbs for _LIMBS, _LUT_LIMBS, and for
                                  _AUTO from 1 GB of packed genotypes in the batch) */
+    int32_t restart;          /* gkl_restart; 0 = GKL_RESTART_RITZ */
 } gkl_options;
 
 /* Run statistics (host struct). */

@@ -13,6 +13,7 @@ from ._binding import (  # noqa: F401
     GKL_ERR_BREAKDOWN, GKL_ERR_INTERNAL, GKL_ERR_UNSUPPORTED, GKL_REORTH_FULL,
     GKL_REORTH_PARTIAL, GKL_REORTH_ONESIDED, GKL_PREC_FP64, GKL_PREC_MIXED, GKL_PREC_MIXED_INT8, GKL_PREC_BLOCK_FP64,
     GKL_FP64_AUTO, GKL_FP64_LUT, GKL_FP64_LIMBS, GKL_FP64_LUT_LIMBS, GKL_TRACE_FIELDS, GKLError,
+    GKL_RESTART_RITZ, GKL_RESTART_HARMONIC,
     gkl_options, gkl_info, lib, library_path, gkl_options_default, gkl_status_string,
     gkl_last_error, gkl_create, gkl_create_ex, gkl_solve, gkl_destroy, gkl_create_batched,
     gkl_solve_batched, gkl_create_loco, gkl_column_stats, gkl_unpack, gkl_matvec, gkl_rmatvec,

@@ -29,6 +29,8 @@ GKL_FP64_LUT = 1
 GKL_FP64_LIMBS = 2
 GKL_FP64_LUT_LIMBS = 3
 GKL_TRACE_FIELDS = 7
+GKL_RESTART_RITZ = 0
+GKL_RESTART_HARMONIC = 1
 
 
 class gkl_options(ctypes.Structure):
@@ -53,6 +55,7 @@ class gkl_options(ctypes.Structure):
         ("autotune", ctypes.c_int32),
         ("graph", ctypes.c_int32),
         ("fp64_products", ctypes.c_int32),
+        ("restart", ctypes.c_int32),
     ]
 
 

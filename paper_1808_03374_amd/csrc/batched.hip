@@ -452,6 +452,11 @@ gkl_status gkl_create_batched(int32_t count, const uint8_t* const* G, const int6
         return batch_error(nullptr, GKL_ERR_INVALID, "keep must lie in [k, krylov_dim)");
     if (o->check_every < 0 || o->max_matvecs < 0)
         return batch_error(nullptr, GKL_ERR_INVALID, "bad check_every / max_matvecs");
+    if (o->restart == GKL_RESTART_HARMONIC)
+        return batch_error(nullptr, GKL_ERR_UNSUPPORTED,
+                           "harmonic restarts are built for single problems (gkl_create_ex)");
+    if (o->restart != GKL_RESTART_RITZ)
+        return batch_error(nullptr, GKL_ERR_INVALID, "restart must be GKL_RESTART_RITZ or _HARMONIC");
     gkl_ctx* ctx = nullptr;
     try {
         auto t0 = std::chrono::steady_clock::now();
@@ -557,6 +562,11 @@ gkl_status gkl_create_loco(const uint8_t* G, int64_t n, int64_t p, int32_t nbloc
         return batch_error(nullptr, GKL_ERR_INVALID, "keep must lie in [k, krylov_dim)");
     if (o->check_every < 0 || o->max_matvecs < 0)
         return batch_error(nullptr, GKL_ERR_INVALID, "bad check_every / max_matvecs");
+    if (o->restart == GKL_RESTART_HARMONIC)
+        return batch_error(nullptr, GKL_ERR_UNSUPPORTED,
+                           "harmonic restarts are built for single problems (gkl_create_ex)");
+    if (o->restart != GKL_RESTART_RITZ)
+        return batch_error(nullptr, GKL_ERR_INVALID, "restart must be GKL_RESTART_RITZ or _HARMONIC");
     gkl_ctx* ctx = nullptr;
     try {
         auto t0 = std::chrono::steady_clock::now();

@@ -77,6 +77,18 @@ struct gkl_ctx {
     double* beta = nullptr;
     double* theta = nullptr;
     double* rho = nullptr;
+    // harmonic thick restart: dense head of the projected matrix and the
+    // small-space plan's buffers ((m+1) x (m+1) SVD, Z, LU work)
+    double* head = nullptr;
+    double* hpad = nullptr;
+    double* hP = nullptr;
+    double* hS = nullptr;
+    double* hQ = nullptr;
+    double* hZ = nullptr;
+    double* hwork = nullptr;
+    double* hsvd_scratch = nullptr;
+    bool head_dense = false;     // the first nlock rows hold a dense head
+    bool zero_scalar = false;    // a breakdown recorded a zero scalar since the last restart
     double* norm_est = nullptr;
     int* flags = nullptr;   // [0] left breakdown [1] right breakdown [2..5] PRO
                             // [6] Gram-Schmidt passes [7] scratch flag [8] nconv
@@ -130,6 +142,7 @@ struct gkl_ctx {
     double onesided_tol() const;
     int check_convergence(int m);
     void restart(int m);
+    void restart_harmonic(int m);
     void finalize(int m, double* sigma, double* Uo, int64_t ldu, double* Vo, int64_t ldv);
     gkl_status solve_fp64(double* sigma, double* Uo, int64_t ldu, double* Vo, int64_t ldv);
     void setup_mixed();

@@ -126,8 +126,21 @@ void gkl_ctx::allocate_solver()
     const int cols = maxm;
     U = static_cast<double*>(A.alloc(sizeof(double) * (size_t)n * cols));
     V = static_cast<double*>(A.alloc(sizeof(double) * (size_t)p * (cols + 1)));
-    const int keep_alloc = std::max(keep, 1);
+    const bool harmonic = krylov > 0 && opt.restart == GKL_RESTART_HARMONIC;
+    const int keep_alloc = std::max(keep, 1) + (harmonic ? 1 : 0);
     tmp = static_cast<double*>(A.alloc(sizeof(double) * (size_t)std::max(n, p) * keep_alloc));
+    if (harmonic) {
+        const size_t m1 = (size_t)cols + 1;
+        head = static_cast<double*>(A.alloc(sizeof(double) * (size_t)keep * keep));
+        hpad = static_cast<double*>(A.alloc(sizeof(double) * m1 * m1));
+        hP = static_cast<double*>(A.alloc(sizeof(double) * m1 * m1));
+        hQ = static_cast<double*>(A.alloc(sizeof(double) * m1 * m1));
+        hS = static_cast<double*>(A.alloc(sizeof(double) * m1));
+        hZ = static_cast<double*>(A.alloc(sizeof(double) * m1 * (keep + 1)));
+        hwork = static_cast<double*>(A.alloc(sizeof(double) * (size_t)cols * (keep + 1)));
+        if (!svd_fits_lds(cols + 1))
+            hsvd_scratch = static_cast<double*>(A.alloc(sizeof(double) * svd_scratch_elems(cols + 1)));
+    }
     kScalars = 4 * (size_t)(cols + 1) + 2;
     scal = static_cast<double*>(A.alloc(sizeof(double) * kScalars));
     alpha = scal;
@@ -458,7 +471,8 @@ void gkl_ctx::handle_breakdown(bool left, int j)
 
 int gkl_ctx::check_convergence(int m)
 {
-    launch_ritz(alpha, beta, theta, rho, nlock, m, k, tol, ritz, svd_scratch, prob.stream);
+    launch_ritz(alpha, beta, theta, rho, nlock, m, k, tol, ritz, svd_scratch, prob.stream,
+                head_dense ? head : nullptr);
     ritz_m = m;
     int nconv = 0, bd = -1;
     sync_state(&nconv, &bd);
@@ -471,6 +485,12 @@ void gkl_ctx::restart(int m)
     hipStream_t s = prob.stream;
     const int64_t n = prob.n, p = prob.p;
     if (ritz_m != m) check_convergence(m);
+    if (opt.restart == GKL_RESTART_HARMONIC && !zero_scalar) {
+        restart_harmonic(m);
+        return;
+    }
+    zero_scalar = false;
+    head_dense = false;
     // V(:, 0:l) = V(:, 0:m) Q(:, 0:l); v_l = v_m
     launch_gemm_tall(V, p, p, m, ritz.Q, m, keep, tmp, p, s);
     GKL_HIP(hipMemcpyAsync(V, tmp, sizeof(double) * (size_t)p * keep, hipMemcpyDeviceToDevice, s));
@@ -484,6 +504,28 @@ void gkl_ctx::restart(int m)
     ritz_m = -1;
     info.restarts += 1;
     if (reorth == GKL_REORTH_PARTIAL) launch_pro_reset(pro, maxm, 2, s);
+}
+
+// Thick restart from harmonic Ritz vectors (the small-space plan is built in
+// one workgroup from the SVD of [B_m, beta_m e_m]): V(:, 0:l+1) = V(:, 0:m+1) Z,
+// U(:, 0:l) = U(:, 0:m) Ph(0:m, 0:l); the projected matrix restarts with the
+// dense head and the coupling column rho.
+void gkl_ctx::restart_harmonic(int m)
+{
+    hipStream_t s = prob.stream;
+    const int64_t n = prob.n, p = prob.p;
+    const int l = keep, m1 = m + 1;
+    launch_harmonic_pad(ritz.B, m, beta + (m - 1), hpad, s);
+    launch_dense_svd(hpad, m1, hP, hS, hQ, hsvd_scratch, s);
+    launch_harmonic_plan(ritz.B, m, beta + (m - 1), hP, hQ, l, hwork, hZ, head, rho, s);
+    launch_gemm_tall(V, p, p, m1, hZ, m1, l + 1, tmp, p, s);
+    GKL_HIP(hipMemcpyAsync(V, tmp, sizeof(double) * (size_t)p * (l + 1), hipMemcpyDeviceToDevice, s));
+    launch_gemm_tall(U, n, n, m, hP, m1, l, tmp, n, s);
+    GKL_HIP(hipMemcpyAsync(U, tmp, sizeof(double) * (size_t)n * l, hipMemcpyDeviceToDevice, s));
+    head_dense = true;
+    nlock = l;
+    ritz_m = -1;
+    info.restarts += 1;
 }
 
 void gkl_ctx::finalize(int m, double* sigma, double* Uo, int64_t ldu, double* Vo, int64_t ldv)
@@ -546,6 +588,8 @@ gkl_status gkl_ctx::solve_fp64(double* sigma, double* Uo, int64_t ldu, double* V
     if (reorth == GKL_REORTH_PARTIAL) launch_pro_reset(pro, maxm, 0, s);
     nlock = 0;
     ritz_m = -1;
+    head_dense = false;
+    zero_scalar = false;
     exhausted = false;
     breakdown_draws = 1;
     last_breakdown = -1;
@@ -583,6 +627,7 @@ gkl_status gkl_ctx::solve_fp64(double* sigma, double* Uo, int64_t ldu, double* V
             GKL_HIP(hipMemsetAsync(flags + 9, 0xFF, sizeof(int), s));
             last_breakdown = -1;
             ritz_m = -1;
+            zero_scalar = true;
             if (hb % 2 == 0) {
                 handle_breakdown(true, jb);
                 if (exhausted) { j = jb; break; }
@@ -732,6 +777,12 @@ static gkl_status validate(const uint8_t* G, int64_t n, int64_t p, int32_t k, do
     if (reorth == GKL_REORTH_ONESIDED && o->precision != GKL_PREC_FP64)
         return set_error(nullptr, GKL_ERR_UNSUPPORTED,
                          "one-sided reorthogonalisation is built for the FP64 path only");
+    if (o->restart != GKL_RESTART_RITZ && o->restart != GKL_RESTART_HARMONIC)
+        return set_error(nullptr, GKL_ERR_INVALID, "restart must be GKL_RESTART_RITZ or _HARMONIC");
+    if (o->restart == GKL_RESTART_HARMONIC &&
+        (o->precision != GKL_PREC_FP64 || reorth != GKL_REORTH_FULL))
+        return set_error(nullptr, GKL_ERR_UNSUPPORTED,
+                         "harmonic restarts are built for GKL_PREC_FP64 with GKL_REORTH_FULL");
     return GKL_OK;
 }
 

@@ -493,12 +493,15 @@ void launch_dense_svd(const double* B, int m, double* P, double* S, double* Q, d
 
 // Projected matrix from the recurrence scalars, its SVD and the residual test
 // (one workgroup; W, Vr, sig, order are the working arrays).
+// head (optional): after a harmonic restart the first nlock rows hold a dense
+// nlock x nlock block (column-major, ld nlock) instead of diag(theta).
 __device__ __forceinline__ void ritz_body(const double* __restrict__ alpha,
                                           const double* __restrict__ beta,
                                           const double* __restrict__ theta,
                                           const double* __restrict__ rho, int nlock, int m, int k,
                                           double tol, const RitzOut& out, double* W, double* Vr,
-                                          double* sig, double* dn, int* order)
+                                          double* sig, double* dn, int* order,
+                                          const double* __restrict__ head = nullptr)
 {
     const int mp = m + (m & 1);
     const int ld = svd_ld(mp);
@@ -507,8 +510,9 @@ __device__ __forceinline__ void ritz_body(const double* __restrict__ alpha,
         double v = 0.0;
         if (i < m && c < m) {
             if (i < nlock) {
-                if (c == i) v = theta[i];
-                else if (c == nlock) v = rho[i];
+                if (c == nlock) v = rho[i];
+                else if (head) v = c < nlock ? head[(int64_t)c * nlock + i] : 0.0;
+                else if (c == i) v = theta[i];
             } else {
                 if (c == i) v = alpha[i];
                 else if (c == i + 1) v = beta[i];
@@ -544,7 +548,7 @@ template <bool kLds>
 __global__ void __launch_bounds__(kSvdThreads)
 ritz_kernel(const double* __restrict__ alpha, const double* __restrict__ beta,
             const double* __restrict__ theta, const double* __restrict__ rho, int nlock, int m,
-            int k, double tol, RitzOut out, double* gscratch)
+            int k, double tol, RitzOut out, double* gscratch, const double* __restrict__ head)
 {
     extern __shared__ double lds[];
     const int mp = m + (m & 1);
@@ -554,7 +558,7 @@ ritz_kernel(const double* __restrict__ alpha, const double* __restrict__ beta,
     double* sig = Vr + ld * mp;
     double* dn = sig + mp;
     int* order = reinterpret_cast<int*>(dn + mp);
-    ritz_body(alpha, beta, theta, rho, nlock, m, k, tol, out, W, Vr, sig, dn, order);
+    ritz_body(alpha, beta, theta, rho, nlock, m, k, tol, out, W, Vr, sig, dn, order, head);
 }
 
 // One workgroup per problem of a batch.
@@ -578,17 +582,17 @@ ritz_batched_kernel(const BatchRitzArgs* __restrict__ args, int nlock, int m, in
 
 void launch_ritz(const double* alpha, const double* beta, const double* theta, const double* rho,
                  int nlock, int m, int k, double tol, const RitzOut& out, double* gscratch,
-                 hipStream_t s)
+                 hipStream_t s, const double* head)
 {
     check_svd_size(m, gscratch);
     const bool global = !svd_fits_lds(m);
     const size_t lds = global ? 0 : svd_lds_bytes(m);
     if (global)
         hipLaunchKernelGGL(ritz_kernel<false>, dim3(1), dim3(kSvdThreads), 0, s, alpha, beta, theta,
-                           rho, nlock, m, k, tol, out, gscratch);
+                           rho, nlock, m, k, tol, out, gscratch, head);
     else
         hipLaunchKernelGGL(ritz_kernel<true>, dim3(1), dim3(kSvdThreads), lds, s, alpha, beta,
-                           theta, rho, nlock, m, k, tol, out, nullptr);
+                           theta, rho, nlock, m, k, tol, out, nullptr, head);
     GKL_LAUNCH_CHECK("ritz_kernel");
 }
 
@@ -623,6 +627,128 @@ void launch_restart_scalars(const double* S, const double* P, int m, const doubl
     hipLaunchKernelGGL(restart_scalars_kernel, dim3(1), dim3(256), 0, s, S, P, m, beta_last, keep,
                        theta, rho);
     GKL_LAUNCH_CHECK("restart_scalars_kernel");
+}
+
+// ---------------------------------------------------------------------------
+// Thick restart from harmonic Ritz vectors (Section 3, "Thick restarting";
+// Baglama & Reichel, SIAM J. Sci. Comput. 27, 2005).
+//
+// After m steps, A V_m = U_m B and A^T U_m = V_{m+1} Bh^T with Bh = [B, beta e_m]
+// (m x (m+1)) = Ph diag(sh) Qh^T.  The harmonic Ritz values of A^T A on span(V_m)
+// are sh^2, its vectors V_m B^-1 ph_j, and every harmonic residual lies along
+// V_{m+1} w with w = [-beta B^-1 e_m; 1].  Bh w = 0, so w is the last right
+// singular vector of Bh, and sh_j [B^-1 ph_j; 0] = qh_j - qh_j(m) w / w(m): the
+// kept space is span{qh_0..qh_{l-1}, w} and the harmonic vectors are its members
+// with a zero last coordinate.  Nothing here needs B^-1 (nearly singular once
+// the Krylov space holds a near-null vector of A, as on a wide genotype
+// matrix).  The restart keeps
+//   U_new = U_m Ph(0:m, 0:l),   V_new = V_{m+1} Z,
+// Z = [qh_0..qh_{l-1}, w] times one Householder reflection that zeroes the last
+// coordinate of its first l columns, and the projected head and coupling
+// column from their definitions: head = Ph_l^T B Z(0:m, 0:l),
+// c = Ph_l^T B Z(0:m, l) + Z(m, l) beta Ph(m-1, 0:l).
+// ---------------------------------------------------------------------------
+
+// Bpad ((m+1) x (m+1)) = [B, beta e_m; 0]: the SVD kernel takes square input.
+__global__ void harmonic_pad_kernel(const double* __restrict__ B, int m,
+                                    const double* __restrict__ beta_last, double* __restrict__ Bp)
+{
+    const int m1 = m + 1;
+    const double bl = *beta_last;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < m1 * m1; e += gridDim.x * blockDim.x) {
+        const int r = e % m1, c = e / m1;
+        double v = 0.0;
+        if (r < m && c < m) v = B[(int64_t)c * m + r];
+        else if (r == m - 1 && c == m) v = bl;
+        Bp[e] = v;
+    }
+}
+
+constexpr int kPlanThreads = 1024;
+
+// One workgroup.  B: m x m (ld m); Ph, Qh: (m+1) x (m+1) (ld m+1), sorted by
+// descending singular value (the last column of Qh belongs to the zero one);
+// work: >= m * (l + 1) doubles.  Writes Z ((m+1) x (l+1), ld m+1), head (l x l,
+// ld l) and c (l).
+__global__ void __launch_bounds__(kPlanThreads)
+harmonic_plan_kernel(const double* __restrict__ B, int m, const double* __restrict__ beta_last,
+                     const double* __restrict__ Ph, const double* __restrict__ Qh, int l,
+                     double* __restrict__ work, double* __restrict__ Z, double* __restrict__ head,
+                     double* __restrict__ c)
+{
+    __shared__ double red[16];
+    __shared__ double hv[kMaxSvd + 1];     // Householder vector
+    const int t = threadIdx.x;
+    const int m1 = m + 1;
+    const double bl = *beta_last;
+    // Z = [qh_0 .. qh_{l-1}, qh_m]
+    for (int e = t; e < m1 * (l + 1); e += kPlanThreads) {
+        const int r = e % m1, j = e / m1;
+        Z[e] = Qh[(int64_t)(j < l ? j : m) * m1 + r];
+    }
+    __syncthreads();
+    // reflection v = z + sign(z_l) |z| e_l of the last row z, applied on the right
+    double a = 0.0;
+    for (int j = t; j <= l; j += kPlanThreads) {
+        const double z = Z[(int64_t)j * m1 + m];
+        hv[j] = z;
+        a = fma(z, z, a);
+    }
+    const double nz = sqrt(block_sum(a, red));
+    if (t == 0) hv[l] += copysign(nz, hv[l]);
+    __syncthreads();
+    a = 0.0;
+    for (int j = t; j <= l; j += kPlanThreads) a = fma(hv[j], hv[j], a);
+    const double vv = block_sum(a, red);
+    const double f = vv > 0.0 ? 2.0 / vv : 0.0;
+    for (int r = t; r < m1; r += kPlanThreads) {
+        double d = 0.0;
+        for (int j = 0; j <= l; ++j) d = fma(Z[(int64_t)j * m1 + r], hv[j], d);
+        d *= f;
+        for (int j = 0; j <= l; ++j) {
+            const double z = Z[(int64_t)j * m1 + r] - d * hv[j];
+            Z[(int64_t)j * m1 + r] = (r == m && j < l) ? 0.0 : z;
+        }
+    }
+    __syncthreads();
+    // work = B Z(0:m, :)  (m x (l+1))
+    for (int e = t; e < m * (l + 1); e += kPlanThreads) {
+        const int r = e % m, j = e / m;
+        const double* z = Z + (int64_t)j * m1;
+        double s = 0.0;
+        for (int q = 0; q < m; ++q) s = fma(B[(int64_t)q * m + r], z[q], s);
+        work[(int64_t)j * m + r] = s;
+    }
+    __syncthreads();
+    // head(i, j) = ph_i^T (B Z_j), c_i = ph_i^T (B Z_l) + Z(m, l) beta ph_i(m-1)
+    for (int e = t; e < l * (l + 1); e += kPlanThreads) {
+        const int i = e % l, j = e / l;
+        const double* p = Ph + (int64_t)i * m1;
+        const double* w = work + (int64_t)j * m;
+        double s = 0.0;
+        for (int r = 0; r < m; ++r) s = fma(p[r], w[r], s);
+        if (j < l) head[(int64_t)j * l + i] = s;
+        else c[i] = s + Z[(int64_t)l * m1 + m] * bl * p[m - 1];
+    }
+}
+
+void launch_harmonic_pad(const double* B, int m, const double* beta_last, double* Bp,
+                         hipStream_t s)
+{
+    hipLaunchKernelGGL(harmonic_pad_kernel, dim3(ceil_div((int64_t)(m + 1) * (m + 1), 256)),
+                       dim3(256), 0, s, B, m, beta_last, Bp);
+    GKL_LAUNCH_CHECK("harmonic_pad_kernel");
+}
+
+void launch_harmonic_plan(const double* B, int m, const double* beta_last, const double* Ph,
+                          const double* Qh, int l, double* work, double* Z, double* head, double* c,
+                          hipStream_t s)
+{
+    if (m < 2 || m > kMaxSvd || l < 1 || l >= m)
+        fail(GKL_ERR_INTERNAL, "harmonic restart plan: bad sizes");
+    hipLaunchKernelGGL(harmonic_plan_kernel, dim3(1), dim3(kPlanThreads), 0, s, B, m, beta_last,
+                       Ph, Qh, l, work, Z, head, c);
+    GKL_LAUNCH_CHECK("harmonic_plan_kernel");
 }
 
 }  // namespace gkl

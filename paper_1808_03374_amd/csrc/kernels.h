@@ -329,9 +329,20 @@ struct RitzOut {
     double* res;    // m
     int* nconv;     // 1
 };
+// head (optional): dense nlock x nlock block (ld nlock) in place of diag(theta),
+// after a harmonic restart.
 void launch_ritz(const double* alpha, const double* beta, const double* theta, const double* rho,
                  int nlock, int m, int k, double tol, const RitzOut& out, double* gscratch,
-                 hipStream_t s);
+                 hipStream_t s, const double* head = nullptr);
+// Harmonic thick restart: Bp ((m+1) x (m+1)) = [B, beta_last e_m; 0]; after its
+// SVD (Ph, Qh), the plan: Z ((m+1) x (l+1), ld m+1) for V_new = V_{m+1} Z,
+// head (l x l, ld l) and coupling c (l); U_new = U_m Ph(0:m, 0:l).
+// work >= m * (l + 1) doubles.
+void launch_harmonic_pad(const double* B, int m, const double* beta_last, double* Bp,
+                         hipStream_t s);
+void launch_harmonic_plan(const double* B, int m, const double* beta_last, const double* Ph,
+                          const double* Qh, int l, double* work, double* Z, double* head,
+                          double* c, hipStream_t s);
 // The same for many problems at once (one workgroup each); problems with
 // run == 0 are skipped.  gscratch: count * svd_scratch_elems(m) doubles when
 // the matrix does not fit LDS.
