@@ -584,21 +584,25 @@ def run_extra(gk, torch, name, args, stream):
 
 def reorth_compare(gk, torch, W, ref, stream):
     """The workload's FP64 solve with full, one-sided and partial
-    reorthogonalisation (thick restart m = 60, tol as the workload): seconds per
-    solve, Gram-Schmidt passes, products, and the sigma error against `ref`."""
+    reorthogonalisation, and with full reorthogonalisation and harmonic Ritz
+    restarts (thick restart m = 60, tol as the workload): seconds per solve,
+    restarts, Gram-Schmidt passes, products, and the sigma error against `ref`."""
     import numpy as np
     n, p, k = W.n, W.p, W.k
     out = {}
     sig = torch.empty(k, dtype=torch.float64, device="cuda")
     U = torch.empty((k, n), dtype=torch.float64, device="cuda")
     V = torch.empty((k, p), dtype=torch.float64, device="cuda")
-    for label, mode in (("full", gk.GKL_REORTH_FULL), ("one_sided", gk.GKL_REORTH_ONESIDED),
-                        ("partial", gk.GKL_REORTH_PARTIAL)):
+    for label, mode, restart in (("full", gk.GKL_REORTH_FULL, gk.GKL_RESTART_RITZ),
+                                 ("one_sided", gk.GKL_REORTH_ONESIDED, gk.GKL_RESTART_RITZ),
+                                 ("partial", gk.GKL_REORTH_PARTIAL, gk.GKL_RESTART_RITZ),
+                                 ("full_harmonic_restart", gk.GKL_REORTH_FULL,
+                                  gk.GKL_RESTART_HARMONIC)):
         times = []
         for rep in range(3):
             ctx = gk.Context(W.G, n, p, k, W.wl["tol"], mode, v0=W.v0,
                              krylov_dim=W.wl["krylov_dim"], stream=stream,
-                             fp64_products=FP64_PRODUCTS[0])
+                             fp64_products=FP64_PRODUCTS[0], restart=restart)
             try:
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
@@ -609,6 +613,7 @@ def reorth_compare(gk, torch, W, ref, stream):
                 ctx.close()
         s = sig.cpu().numpy()
         out[label] = {"status": int(st), "solve_s": float(np.median(times)),
+                      "restarts": int(info.restarts),
                       "reorth_passes": int(info.reorths), "matvecs": int(info.matvecs),
                       "sigma_max_rel_err": float(np.max(np.abs(s - ref["sigma"]) / ref["sigma"]))}
     log(f"[bench] reorthogonalisation: {out}")

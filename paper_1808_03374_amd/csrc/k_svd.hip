@@ -343,6 +343,144 @@ __device__ __forceinline__ void extract_sorted(const double* W, const double* Vr
 
 }  // namespace
 
+// Projected matrices too large for LDS: the sweeps of jacobi_sweeps_t<0> --
+// same tournament, pairs, rotations and column-norm updates -- with the
+// disjoint pairs of each round spread over workgroups (one launch per round;
+// one 16-lane group per pair) instead of one workgroup taking them 64 at a
+// time through L2.  The column norms are refreshed by their own launch at the
+// start of each sweep, which also clears the sweep's rotation flag; the host
+// reads the flag after the sweep and stops after a sweep without rotations.
+constexpr int kMwThreads = 64;
+constexpr int kMwPairs = kMwThreads / kGroup;
+
+__global__ void __launch_bounds__(256)
+jacobi_norms_kernel(const double* __restrict__ W, int mp, int ld, double* __restrict__ dn,
+                    int* __restrict__ rotated)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) *rotated = 0;
+    const int c = (int)((blockIdx.x * blockDim.x + threadIdx.x) / kGroup);
+    const int gl = threadIdx.x % kGroup;
+    if (c >= mp) return;                  // whole 16-lane groups leave together
+    const double* wc = W + (int64_t)c * ld;
+    double a = 0.0;
+    for (int i = gl; i < mp; i += kGroup) a = fma(wc[i], wc[i], a);
+    a = group_sum(a);
+    if (gl == 0) dn[c] = a;
+}
+
+__global__ void __launch_bounds__(kMwThreads)
+jacobi_round_kernel(double* __restrict__ W, double* __restrict__ Vr, int mp, int ld,
+                    double* __restrict__ dn, int r, int* __restrict__ rotated)
+{
+    const int npairs = mp / 2;
+    const int ring = mp - 1;
+    const int k = blockIdx.x * kMwPairs + (int)(threadIdx.x / kGroup);
+    const int gl = threadIdx.x % kGroup;
+    if (k >= npairs) return;
+    const double tol = 2.220446049250313e-16 * sqrt((double)mp);
+    int a, b;
+    if (k == 0) {
+        a = ring;
+        b = r;
+    } else {
+        a = r + k;
+        if (a >= ring) a -= ring;
+        b = r - k;
+        if (b < 0) b += ring;
+    }
+    if (a > b) { const int tmp = a; a = b; b = tmp; }
+    double* xa = W + (int64_t)a * ld;
+    double* xb = W + (int64_t)b * ld;
+    double* ya = Vr + (int64_t)a * ld;
+    double* yb = Vr + (int64_t)b * ld;
+    const double saa = dn[a], sbb = dn[b];
+    double t, cs, sn, sab = 0.0;
+    for (int i = gl; i < mp; i += kGroup) sab = fma(xa[i], xb[i], sab);
+    sab = group_sum(sab);
+    if (!jacobi_rotation(sab, saa, sbb, tol, t, cs, sn)) return;
+    for (int i = gl; i < mp; i += kGroup) {
+        const double x = xa[i], y = xb[i];
+        xa[i] = cs * x - sn * y;
+        xb[i] = sn * x + cs * y;
+        const double p = ya[i], q = yb[i];
+        ya[i] = cs * p - sn * q;
+        yb[i] = sn * p + cs * q;
+    }
+    if (gl == 0) {
+        dn[a] = saa - t * sab;
+        dn[b] = sbb + t * sab;
+        *rotated = 1;
+    }
+}
+
+// flag: one int of device memory (the spare element after the working arrays).
+static void jacobi_multi_wg(double* W, double* Vr, int mp, int ld, double* dn, int* flag,
+                            hipStream_t s)
+{
+    const int npairs = mp / 2, ring = mp - 1;
+    const int nb = (npairs + kMwPairs - 1) / kMwPairs;
+    const int nn = (int)ceil_div((int64_t)mp * kGroup, 256);
+    for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
+        hipLaunchKernelGGL(jacobi_norms_kernel, dim3(nn), dim3(256), 0, s, W, mp, ld, dn, flag);
+        GKL_LAUNCH_CHECK("jacobi_norms_kernel");
+        for (int r = 0; r < ring; ++r)
+            hipLaunchKernelGGL(jacobi_round_kernel, dim3(nb), dim3(kMwThreads), 0, s, W, Vr, mp, ld,
+                               dn, r, flag);
+        GKL_LAUNCH_CHECK("jacobi_round_kernel");
+        int h = 0;
+        GKL_HIP(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+        GKL_HIP(hipStreamSynchronize(s));
+        if (!h) break;
+    }
+}
+
+// Working arrays in gscratch: W, Vr (ld x mp each), sig, dn (mp each), order
+// (mp ints), then the flag.
+struct GlobalSvd {
+    double* W;
+    double* Vr;
+    double* sig;
+    double* dn;
+    int* order;
+    int* flag;
+};
+
+static GlobalSvd global_svd_arrays(double* gscratch, int m)
+{
+    const int mp = m + (m & 1);
+    const int ld = svd_ld(mp);
+    GlobalSvd g;
+    g.W = gscratch;
+    g.Vr = g.W + (int64_t)ld * mp;
+    g.sig = g.Vr + (int64_t)ld * mp;
+    g.dn = g.sig + mp;
+    g.order = reinterpret_cast<int*>(g.dn + mp);
+    g.flag = g.order + mp;
+    return g;
+}
+
+// B (m x m) into W, the identity into Vr.
+__global__ void __launch_bounds__(256)
+svd_load_kernel(const double* __restrict__ B, int m, double* __restrict__ W, double* __restrict__ Vr)
+{
+    const int mp = m + (m & 1);
+    const int ld = svd_ld(mp);
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < (int64_t)ld * mp;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(t % ld), c = (int)(t / ld);
+        W[t] = (i < m && c < m) ? B[(int64_t)c * m + i] : 0.0;
+        Vr[t] = (i == c) ? 1.0 : 0.0;
+    }
+}
+
+__global__ void __launch_bounds__(kSvdThreads)
+svd_extract_kernel(int m, GlobalSvd g, double* __restrict__ P, double* __restrict__ S,
+                   double* __restrict__ Q)
+{
+    const int mp = m + (m & 1);
+    extract_sorted(g.W, g.Vr, m, mp, svd_ld(mp), g.sig, g.order, P, m, S, Q, m);
+}
+
 // kLds: the working arrays live in LDS (the compiler then emits LDS
 // instructions); otherwise in gscratch.
 // Leading columns of Q recovered as B^T w_c / sig_c^2 (w_c = sig_c p_c, the
@@ -485,8 +623,16 @@ void launch_dense_svd(const double* B, int m, double* P, double* S, double* Q, d
                            svd_logged_lds_bytes(m), s, B, m, P, S, Q, nullptr, rlog, qc);
     } else {
         if (!gscratch) fail(GKL_ERR_INTERNAL, "large projected matrix needs a global scratch buffer");
-        hipLaunchKernelGGL(dense_svd_kernel<false>, dim3(1), dim3(kSvdThreads), 0, s, B, m, P, S,
-                           Q, gscratch, nullptr, m);
+        const int mp = m + (m & 1);
+        const GlobalSvd g = global_svd_arrays(gscratch, m);
+        hipLaunchKernelGGL(svd_load_kernel, dim3((unsigned)std::min<int64_t>(
+                               ceil_div((int64_t)svd_ld(mp) * mp, 256), 1024)), dim3(256), 0, s,
+                           B, m, g.W, g.Vr);
+        GKL_LAUNCH_CHECK("svd_load_kernel");
+        jacobi_multi_wg(g.W, g.Vr, mp, svd_ld(mp), g.dn, g.flag, s);
+        hipLaunchKernelGGL(svd_extract_kernel, dim3(1), dim3(kSvdThreads), 0, s, m, g, P, S, Q);
+        GKL_LAUNCH_CHECK("svd_extract_kernel");
+        return;
     }
     GKL_LAUNCH_CHECK("dense_svd_kernel");
 }
@@ -495,13 +641,12 @@ void launch_dense_svd(const double* B, int m, double* P, double* S, double* Q, d
 // (one workgroup; W, Vr, sig, order are the working arrays).
 // head (optional): after a harmonic restart the first nlock rows hold a dense
 // nlock x nlock block (column-major, ld nlock) instead of diag(theta).
-__device__ __forceinline__ void ritz_body(const double* __restrict__ alpha,
-                                          const double* __restrict__ beta,
-                                          const double* __restrict__ theta,
-                                          const double* __restrict__ rho, int nlock, int m, int k,
-                                          double tol, const RitzOut& out, double* W, double* Vr,
-                                          double* sig, double* dn, int* order,
-                                          const double* __restrict__ head = nullptr)
+__device__ __forceinline__ void ritz_assemble(const double* __restrict__ alpha,
+                                              const double* __restrict__ beta,
+                                              const double* __restrict__ theta,
+                                              const double* __restrict__ rho, int nlock, int m,
+                                              const RitzOut& out, double* W, double* Vr,
+                                              const double* __restrict__ head)
 {
     const int mp = m + (m & 1);
     const int ld = svd_ld(mp);
@@ -523,9 +668,14 @@ __device__ __forceinline__ void ritz_body(const double* __restrict__ alpha,
     }
     __syncthreads();
     for (int t = threadIdx.x; t < m * m; t += blockDim.x) out.B[t] = W[(t / m) * ld + (t % m)];
-    jacobi_sweeps(W, Vr, mp, ld, dn);
-    __syncthreads();
-    extract_sorted(W, Vr, m, mp, ld, sig, order, out.P, m, out.S, out.Q, m);
+}
+
+__device__ __forceinline__ void ritz_finish(const double* __restrict__ beta, int m, int k,
+                                            double tol, const RitzOut& out, const double* W,
+                                            const double* Vr, double* sig, int* order)
+{
+    const int mp = m + (m & 1);
+    extract_sorted(W, Vr, m, mp, svd_ld(mp), sig, order, out.P, m, out.S, out.Q, m);
     __syncthreads();
     if (threadIdx.x == 0) {
         const double bl = beta[m - 1];
@@ -542,6 +692,21 @@ __device__ __forceinline__ void ritz_body(const double* __restrict__ alpha,
         }
         *out.nconv = nconv;
     }
+}
+
+__device__ __forceinline__ void ritz_body(const double* __restrict__ alpha,
+                                          const double* __restrict__ beta,
+                                          const double* __restrict__ theta,
+                                          const double* __restrict__ rho, int nlock, int m, int k,
+                                          double tol, const RitzOut& out, double* W, double* Vr,
+                                          double* sig, double* dn, int* order,
+                                          const double* __restrict__ head = nullptr)
+{
+    const int mp = m + (m & 1);
+    ritz_assemble(alpha, beta, theta, rho, nlock, m, out, W, Vr, head);
+    jacobi_sweeps(W, Vr, mp, svd_ld(mp), dn);
+    __syncthreads();
+    ritz_finish(beta, m, k, tol, out, W, Vr, sig, order);
 }
 
 template <bool kLds>
@@ -580,19 +745,41 @@ ritz_batched_kernel(const BatchRitzArgs* __restrict__ args, int nlock, int m, in
     ritz_body(a.alpha, a.beta, a.theta, a.rho, nlock, m, k, tol, a.out, W, Vr, sig, dn, order);
 }
 
+__global__ void __launch_bounds__(kSvdThreads)
+ritz_assemble_kernel(const double* __restrict__ alpha, const double* __restrict__ beta,
+                     const double* __restrict__ theta, const double* __restrict__ rho, int nlock,
+                     int m, RitzOut out, GlobalSvd g, const double* __restrict__ head)
+{
+    ritz_assemble(alpha, beta, theta, rho, nlock, m, out, g.W, g.Vr, head);
+}
+
+__global__ void __launch_bounds__(kSvdThreads)
+ritz_finish_kernel(const double* __restrict__ beta, int m, int k, double tol, RitzOut out,
+                   GlobalSvd g)
+{
+    ritz_finish(beta, m, k, tol, out, g.W, g.Vr, g.sig, g.order);
+}
+
 void launch_ritz(const double* alpha, const double* beta, const double* theta, const double* rho,
                  int nlock, int m, int k, double tol, const RitzOut& out, double* gscratch,
                  hipStream_t s, const double* head)
 {
     check_svd_size(m, gscratch);
-    const bool global = !svd_fits_lds(m);
-    const size_t lds = global ? 0 : svd_lds_bytes(m);
-    if (global)
-        hipLaunchKernelGGL(ritz_kernel<false>, dim3(1), dim3(kSvdThreads), 0, s, alpha, beta, theta,
-                           rho, nlock, m, k, tol, out, gscratch, head);
-    else
-        hipLaunchKernelGGL(ritz_kernel<true>, dim3(1), dim3(kSvdThreads), lds, s, alpha, beta,
-                           theta, rho, nlock, m, k, tol, out, nullptr, head);
+    if (!svd_fits_lds(m)) {
+        // working arrays in gscratch; the sweeps spread over workgroups
+        const int mp = m + (m & 1);
+        const GlobalSvd g = global_svd_arrays(gscratch, m);
+        hipLaunchKernelGGL(ritz_assemble_kernel, dim3(1), dim3(kSvdThreads), 0, s, alpha, beta,
+                           theta, rho, nlock, m, out, g, head);
+        GKL_LAUNCH_CHECK("ritz_assemble_kernel");
+        jacobi_multi_wg(g.W, g.Vr, mp, svd_ld(mp), g.dn, g.flag, s);
+        hipLaunchKernelGGL(ritz_finish_kernel, dim3(1), dim3(kSvdThreads), 0, s, beta, m, k, tol,
+                           out, g);
+        GKL_LAUNCH_CHECK("ritz_finish_kernel");
+        return;
+    }
+    hipLaunchKernelGGL(ritz_kernel<true>, dim3(1), dim3(kSvdThreads), svd_lds_bytes(m), s, alpha,
+                       beta, theta, rho, nlock, m, k, tol, out, nullptr, head);
     GKL_LAUNCH_CHECK("ritz_kernel");
 }
 

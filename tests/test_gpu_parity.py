@@ -349,3 +349,27 @@ def test_one_sided_is_fp64_only(gk):
         gk.Context(Gd, g.n, g.p, 3, reorth=gk.GKL_REORTH_ONESIDED, precision=gk.GKL_PREC_MIXED,
                    block_width=4)
     assert e.value.status == gk.GKL_ERR_UNSUPPORTED
+
+
+def test_gkl_without_restart_past_the_lds_basis(gk):
+    # no restart, 2,000 x 20,000, k = 20 to 1e-12: the basis grows past 128
+    # columns, so the convergence tests run the Ritz SVD whose sweeps are spread
+    # over workgroups (the projected matrix no longer fits LDS)
+    g, Gd = gen("c2", 2000, 20000)
+    k = 20
+    op = oracle.PackedOperator(g.packed, g.n, g.p)
+    ref = oracle.gkl_svd(op, k, tol=1e-12, v0=synth.start_vector(g.p, 7),
+                         spare_left=synth.spare_directions(g.n, 8, 7),
+                         spare_right=synth.spare_directions(g.p, 8, 7), check_every=50)
+    ctx = gk.Context(Gd, g.n, g.p, k, tol=1e-12, reorth=gk.GKL_REORTH_FULL,
+                     v0=dev(synth.start_vector(g.p, 7)))
+    sigma, U, V, st, info = ctx.solve()
+    ctx.close()
+    assert st == gk.GKL_OK and info.steps > 128, (st, info.steps)
+    sigma = sigma.cpu().numpy()
+    U = U.cpu().numpy()
+    V = V.cpu().numpy()
+    assert np.all(np.abs(sigma - ref.sigma) <= 1e-10 * ref.sigma)
+    assert np.abs(U.T @ U - np.eye(k)).max() < 1e-10
+    assert np.abs(V.T @ V - np.eye(k)).max() < 1e-10
+    assert _residuals(op, sigma, U, V) <= 1e-9 * sigma[0]
