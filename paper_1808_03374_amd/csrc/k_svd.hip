@@ -344,14 +344,17 @@ __device__ __forceinline__ void extract_sorted(const double* W, const double* Vr
 }  // namespace
 
 // Projected matrices too large for LDS: the sweeps of jacobi_sweeps_t<0> --
-// same tournament, pairs, rotations and column-norm updates -- with the
+// same tournament, pairs, rotation formula and column-norm updates -- with the
 // disjoint pairs of each round spread over workgroups (one launch per round;
-// one 16-lane group per pair) instead of one workgroup taking them 64 at a
-// time through L2.  The column norms are refreshed by their own launch at the
-// start of each sweep, which also clears the sweep's rotation flag; the host
-// reads the flag after the sweep and stops after a sweep without rotations.
-constexpr int kMwThreads = 64;
-constexpr int kMwPairs = kMwThreads / kGroup;
+// one wave per pair, each lane holding up to kMwElems elements of the pair's
+// four columns in registers, all loaded before the inner product so that one
+// memory round trip serves the pair) instead of one workgroup taking them 64
+// at a time through L2.  The column norms are refreshed by their own launch at
+// the start of each sweep, which also clears the sweep's rotation flag; the
+// host reads the flag after the sweep and stops after a sweep without
+// rotations.  The wave-wide sums add in another order than the 16-lane groups
+// of the in-LDS sweeps, so the two paths agree to rounding, not bit for bit.
+constexpr int kMwElems = (kMaxSvd + 1 + kWave - 1) / kWave;   // mp <= kMaxSvd + 1
 
 __global__ void __launch_bounds__(256)
 jacobi_norms_kernel(const double* __restrict__ W, int mp, int ld, double* __restrict__ dn,
@@ -368,15 +371,13 @@ jacobi_norms_kernel(const double* __restrict__ W, int mp, int ld, double* __rest
     if (gl == 0) dn[c] = a;
 }
 
-__global__ void __launch_bounds__(kMwThreads)
+__global__ void __launch_bounds__(kWave)
 jacobi_round_kernel(double* __restrict__ W, double* __restrict__ Vr, int mp, int ld,
                     double* __restrict__ dn, int r, int* __restrict__ rotated)
 {
-    const int npairs = mp / 2;
     const int ring = mp - 1;
-    const int k = blockIdx.x * kMwPairs + (int)(threadIdx.x / kGroup);
-    const int gl = threadIdx.x % kGroup;
-    if (k >= npairs) return;
+    const int k = blockIdx.x;             // pair k of round r
+    const int lane = threadIdx.x;
     const double tol = 2.220446049250313e-16 * sqrt((double)mp);
     int a, b;
     if (k == 0) {
@@ -393,20 +394,34 @@ jacobi_round_kernel(double* __restrict__ W, double* __restrict__ Vr, int mp, int
     double* xb = W + (int64_t)b * ld;
     double* ya = Vr + (int64_t)a * ld;
     double* yb = Vr + (int64_t)b * ld;
-    const double saa = dn[a], sbb = dn[b];
-    double t, cs, sn, sab = 0.0;
-    for (int i = gl; i < mp; i += kGroup) sab = fma(xa[i], xb[i], sab);
-    sab = group_sum(sab);
-    if (!jacobi_rotation(sab, saa, sbb, tol, t, cs, sn)) return;
-    for (int i = gl; i < mp; i += kGroup) {
-        const double x = xa[i], y = xb[i];
-        xa[i] = cs * x - sn * y;
-        xb[i] = sn * x + cs * y;
-        const double p = ya[i], q = yb[i];
-        ya[i] = cs * p - sn * q;
-        yb[i] = sn * p + cs * q;
+    double u[kMwElems], v[kMwElems], pa[kMwElems], pb[kMwElems];
+#pragma unroll
+    for (int j = 0; j < kMwElems; ++j) {
+        const int i = lane + j * kWave;
+        const bool in = i < mp;
+        u[j] = in ? xa[i] : 0.0;
+        v[j] = in ? xb[i] : 0.0;
+        pa[j] = in ? ya[i] : 0.0;
+        pb[j] = in ? yb[i] : 0.0;
     }
-    if (gl == 0) {
+    const double saa = dn[a], sbb = dn[b];
+    double sab = 0.0;
+#pragma unroll
+    for (int j = 0; j < kMwElems; ++j) sab = fma(u[j], v[j], sab);
+    sab = wave_sum(sab);
+    double t, cs, sn;
+    if (!jacobi_rotation(sab, saa, sbb, tol, t, cs, sn)) return;
+#pragma unroll
+    for (int j = 0; j < kMwElems; ++j) {
+        const int i = lane + j * kWave;
+        if (i < mp) {
+            xa[i] = cs * u[j] - sn * v[j];
+            xb[i] = sn * u[j] + cs * v[j];
+            ya[i] = cs * pa[j] - sn * pb[j];
+            yb[i] = sn * pa[j] + cs * pb[j];
+        }
+    }
+    if (lane == 0) {
         dn[a] = saa - t * sab;
         dn[b] = sbb + t * sab;
         *rotated = 1;
@@ -418,13 +433,13 @@ static void jacobi_multi_wg(double* W, double* Vr, int mp, int ld, double* dn, i
                             hipStream_t s)
 {
     const int npairs = mp / 2, ring = mp - 1;
-    const int nb = (npairs + kMwPairs - 1) / kMwPairs;
     const int nn = (int)ceil_div((int64_t)mp * kGroup, 256);
+    if (mp > kMwElems * kWave) fail(GKL_ERR_INTERNAL, "Jacobi working size beyond the register tile");
     for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
         hipLaunchKernelGGL(jacobi_norms_kernel, dim3(nn), dim3(256), 0, s, W, mp, ld, dn, flag);
         GKL_LAUNCH_CHECK("jacobi_norms_kernel");
         for (int r = 0; r < ring; ++r)
-            hipLaunchKernelGGL(jacobi_round_kernel, dim3(nb), dim3(kMwThreads), 0, s, W, Vr, mp, ld,
+            hipLaunchKernelGGL(jacobi_round_kernel, dim3(npairs), dim3(kWave), 0, s, W, Vr, mp, ld,
                                dn, r, flag);
         GKL_LAUNCH_CHECK("jacobi_round_kernel");
         int h = 0;
