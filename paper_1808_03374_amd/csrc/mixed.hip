@@ -165,8 +165,14 @@ gkl_status gkl_ctx::solve_mixed(double* sigma, double* Uo, int64_t ldu, double* 
     int svd_m = -1;
     bool converged = false;
     int since_check = 0;
-    // convergence is tested when the basis is full unless asked more often
+    // convergence is tested when the basis is full unless asked more often; with
+    // the default basis and schedule also before the first restart, from k + b
+    // columns on each time the basis has grown by a quarter -- a well separated
+    // spectrum then stops long before a 128-column basis is full, for a few
+    // small SVDs where it does not
     const int check_every = opt.check_every > 0 ? opt.check_every : 1 << 30;
+    const bool grow_checks = opt.check_every <= 0 && opt.krylov_dim <= 0;
+    int last_check_m = 0;
     while (true) {
         double* Ub = M.U + (int64_t)o * n;
         double* Vb = M.V + (int64_t)o * p;
@@ -210,8 +216,11 @@ gkl_status gkl_ctx::solve_mixed(double* sigma, double* Uo, int64_t ldu, double* 
         ++since_check;
         const bool full = o + b > M.mmax;
         const bool budget = opt.max_matvecs > 0 && info.matvecs >= opt.max_matvecs;
-        if (mcur >= k && (full || budget || since_check >= check_every)) {
+        const bool grown = grow_checks && info.restarts == 0 && mcur >= k + b &&
+                           4 * mcur >= 5 * last_check_m;
+        if (mcur >= k && (full || budget || since_check >= check_every || grown)) {
             since_check = 0;
+            last_check_m = mcur;
             launch_copy_lead(M.Bm, M.ldb, mcur, M.Bc, s);
             launch_dense_svd(M.Bc, mcur, M.ritz.P, M.ritz.S, M.ritz.Q, M.svd_scratch, s, M.svd_log,
                              M.keep);
