@@ -138,9 +138,9 @@ typedef struct gkl_options {
                                  basis is full if restarting; else every 5 steps up
                                  to a 20-vector basis, then each time it has grown
                                  by a quarter, as the projected SVD costs O(j^3);
-                                 blocked with the default basis: also before the
-                                 first restart, from k + b columns on each time the
-                                 basis has grown by a quarter) */
+                                 blocked with the default basis and n p >= 4e9:
+                                 also before the first restart, from k + b columns
+                                 on each time the basis has grown by a quarter) */
     int32_t max_steps;        /* cap on the basis size without restart; 0 = min(512,
                                  min(n, p)).  A solve without restart that fills the
                                  basis before converging returns GKL_NOT_CONVERGED. */

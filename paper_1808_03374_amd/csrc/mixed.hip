@@ -166,12 +166,15 @@ gkl_status gkl_ctx::solve_mixed(double* sigma, double* Uo, int64_t ldu, double* 
     bool converged = false;
     int since_check = 0;
     // convergence is tested when the basis is full unless asked more often; with
-    // the default basis and schedule also before the first restart, from k + b
-    // columns on each time the basis has grown by a quarter -- a well separated
-    // spectrum then stops long before a 128-column basis is full, for a few
-    // small SVDs where it does not
+    // the default basis and schedule, from 4e9 genotypes (1 GB packed) on, also
+    // before the first restart, from k + b columns on each time the basis has
+    // grown by a quarter -- a well separated spectrum then stops long before a
+    // 128-column basis is full.  Below that size a block step (two passes over
+    // at most 1 GB plus its small launches) costs less than a test (a projected
+    // SVD of up to 128 columns and a host synchronisation), so the early tests
+    // would mostly add time (10,000 x 100,000: about 6 tests, +6% per solve).
     const int check_every = opt.check_every > 0 ? opt.check_every : 1 << 30;
-    const bool grow_checks = opt.check_every <= 0 && opt.krylov_dim <= 0;
+    const bool grow_checks = opt.check_every <= 0 && opt.krylov_dim <= 0 && (double)n * p >= 4e9;
     int last_check_m = 0;
     while (true) {
         double* Ub = M.U + (int64_t)o * n;
