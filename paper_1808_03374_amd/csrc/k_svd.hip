@@ -2,22 +2,25 @@
 //
 // Section 3 of the paper: the top singular triplets of A are approximated from
 // the SVD of the small projected matrix B_j (upper bidiagonal, or after a thick
-// restart a diagonal block with one spike column followed by a bidiagonal
-// tail), and convergence is tested with the residual bound
+// restart a diagonal block -- a dense block after a harmonic restart -- with one
+// spike column followed by a bidiagonal tail), and convergence is tested with
+// the residual bound
 //     |sigma - sigma~_i| <= beta_j |P_{j,i}|
 // where P holds the left singular vectors of B_j (the Table 3 caption sums these
 // bounds into ||Delta theta||_1).
 //
-// The SVD is a one-sided (Hestenes) Jacobi method run by a single workgroup.
-// Up to 96 columns the matrix and the accumulated rotations are held in LDS;
-// up to 128 columns the matrix alone is, the rotations are logged to device
-// memory and replayed onto the identity afterwards (or, when the caller needs
-// only well-separated leading columns, those are formed from the rotated
-// matrix); larger matrices work in global scratch.  Column pairs of a
-// round-robin tournament are rotated concurrently, 16 lanes per pair, with the
-// pair's columns held in registers while they are rotated (rows zero-padded to a
-// multiple of 16, so every lane's loads are unconditional); sweeps repeat until
-// no pair needs rotating.
+// The SVD is a one-sided (Hestenes) Jacobi method.  Up to 96 columns one
+// workgroup holds the matrix and the accumulated rotations in LDS; up to 128
+// columns the matrix alone is, the rotations are logged to device memory and
+// replayed onto the identity afterwards (or, when the caller needs only
+// well-separated leading columns, those are formed from the rotated matrix).
+// Column pairs of a round-robin tournament are rotated concurrently, 16 lanes
+// per pair, with the pair's columns held in registers while they are rotated
+// (rows zero-padded to a multiple of 16, so every lane's loads are
+// unconditional); sweeps repeat until no pair needs rotating.  Larger matrices
+// work in global scratch with each round spread over workgroups (one launch
+// per round, one wave per pair).  The file also holds the small-space part of
+// the harmonic thick restart.
 #include <math.h>
 
 #include "kernels.h"
