@@ -10,7 +10,10 @@
 //   * block orthonormalisation by shifted Cholesky QR applied three times
 //     (shifted CholeskyQR3, Fukaya, Kannan, Nakatsukasa, Yamamoto & Yanagisawa,
 //     SIAM J. Sci. Comput. 2020): Gram matrix, Cholesky in one workgroup,
-//     triangular solve applied to every row, R accumulated;
+//     triangular solve applied to every row, R accumulated; a block whose
+//     R falls below a guard level (a Krylov space running out on a matrix of
+//     low rank) is re-orthogonalised column by column before R enters the
+//     projected matrix;
 //   * Ritz residuals of the block-bidiagonal projected matrix.
 //
 // v_mfma_f64_16x16x4f64 (one wave): lane l supplies A(l % 16, l / 16) and
