@@ -216,3 +216,16 @@ def test_coupling_sign_is_caught(monkeypatch):
     monkeypatch.setattr(og, "thick_restart", _variant("c_sign"))
     assert not relations_pin("ritz")
     assert not thick_solve_pin("ritz")
+
+
+@pytest.mark.parametrize("kind", ["ritz", "harmonic"])
+def test_first_cycle_is_the_plain_recurrence(kind):
+    # before its first restart the restarted run is plain GKL from the same start
+    A = _matrix(200, 500, 5)
+    v0 = synth.start_vector(500, 2)
+    thick = og.gkl_svd_thick(og.DenseOperator(A), 6, 1e-12, 20, 12, kind, v0=v0)
+    plain = og.gkl_svd(og.DenseOperator(A), 6, tol=1e-30, v0=v0, max_steps=20)
+    assert np.allclose(thick.alphas[:20], plain.alphas, rtol=1e-13, atol=0)
+    assert np.allclose(thick.betas[:20], plain.betas, rtol=1e-13, atol=0)
+    # and the run did restart (the later scalars come from the restarted basis)
+    assert thick.restarts >= 1 and len(thick.alphas) > 20
