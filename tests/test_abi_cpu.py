@@ -119,3 +119,28 @@ def test_create_batched_partial_reorth_is_unsupported():
 def test_batched_entry_points_reject_null():
     assert gk.lib.gkl_solve_batched(None, None, None, None, None, None, None) == gk.GKL_ERR_INVALID
     assert gk.lib.gkl_batched_plan(None, None, None, None, None, None, None) == gk.GKL_ERR_INVALID
+
+
+@pytest.mark.parametrize("reorth,precision,restart,status,msg", [
+    (0, 0, 7, gk.GKL_ERR_INVALID, "restart must"),
+    (0, 0, -1, gk.GKL_ERR_INVALID, "restart must"),
+    (1, 0, gk.GKL_RESTART_HARMONIC, gk.GKL_ERR_UNSUPPORTED, "harmonic"),
+    (2, 0, gk.GKL_RESTART_HARMONIC, gk.GKL_ERR_UNSUPPORTED, "harmonic"),
+    (0, 1, gk.GKL_RESTART_HARMONIC, gk.GKL_ERR_UNSUPPORTED, "harmonic"),
+    (0, 3, gk.GKL_RESTART_HARMONIC, gk.GKL_ERR_UNSUPPORTED, "harmonic"),
+])
+def test_create_ex_checks_the_restart_option(reorth, precision, restart, status, msg):
+    # the restart field sits where the binding puts it: the library reads back
+    # the values written through ctypes
+    o = gk.gkl_options_default()
+    o.krylov_dim = 20
+    o.precision = precision
+    o.restart = restart
+    ctx = ctypes.c_void_p()
+    st = gk.lib.gkl_create_ex(FAKE, 40, 50, 4, 1e-8, reorth, ctypes.byref(o), ctypes.byref(ctx))
+    assert st == status and msg in gk.gkl_last_error(None)
+
+
+def test_create_batched_rejects_harmonic_restarts():
+    st, err = _batched(1, [10], [10], restart=gk.GKL_RESTART_HARMONIC)
+    assert st == gk.GKL_ERR_UNSUPPORTED and "harmonic" in err
