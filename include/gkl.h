@@ -342,8 +342,10 @@ gkl_status gkl_get_trace(gkl_ctx* ctx, double* buf, int64_t cap, int64_t* writte
  * B (m x m, column-major, device) = P diag(S) Q^T with S descending.
  * 1 <= m <= 1024.  m <= 96: one workgroup with everything in LDS;
  * 96 < m <= 128: the matrix in LDS and the rotations logged to a device buffer
- * (5.2 MB at m = 128) and replayed; m > 128: working matrices in device memory.
- * The buffer of the last two cases is allocated and freed inside the call.
+ * (5.2 MB at m = 128) and replayed; m > 128: working matrices in device memory,
+ * each round of a sweep one launch spread over workgroups, the host reading a
+ * rotation flag after each sweep.  The buffer of the last two cases is
+ * allocated and freed inside the call.
  * P, Q: m x m column-major device; S: m device.  stream may be NULL.
  * Errors: GKL_ERR_INVALID (NULL pointer, m out of range), GKL_ERR_NOMEM /
  * GKL_ERR_DEVICE.
@@ -360,7 +362,8 @@ gkl_status gkl_dense_svd(const double* B, int32_t m, double* P, double* S, doubl
  * a fixed 5 MiB device array inside the library, one copy per GPU, held until
  * the process ends.  All calls on one GPU share that array, so calls that
  * overlap in time on one GPU (several streams or host threads) race; serialise
- * them.  The call is synchronous on `stream`.
+ * them.  The call is synchronous on `stream` (for m > 128 it also waits on
+ * the stream once per sweep), so it cannot itself be captured into a graph.
  */
 #define GKL_DENSE_SVD_NOALLOC_MAX_M 256
 gkl_status gkl_dense_svd_noalloc(const double* B, int32_t m, double* P, double* S, double* Q,
